@@ -1,0 +1,200 @@
+"""Benchmark: fast-multipole BEM matrix-vector product and solve on one MI355X.
+
+Workload (default): Laplace, unit sphere of 20480 curved 6-node triangles
+(40962 collocation nodes), point-source Neumann data, order-8 expansions,
+at most 32 elements per leaf.  A step is one application of the system
+operator A x = c.x - K x through the fast product (strengths, P2M, M2M, M2L,
+L2L, L2P, near field, corrections and free term), with the input already in
+device memory.  The headline value is the mixed-precision product
+(single-precision near field and expansions, double corrections); the plain
+FP64 product, both GMRES(50) solves to a 1e-8 residual, errors against the
+oracle, per-phase device times and the dominant kernel's roofline are
+reported beside it.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere20480] [--no-cpu]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP32_VEC_PEAK = 157.3  # TFLOP/s, MI355X vector FP32 (256 CUs, 2.4 GHz)
+FP64_VEC_PEAK = 78.6
+
+
+def algorithmic_flops(stats, P, dbl=True):
+    """Per-product algorithmic flop counts of the two heavy phases.
+
+    near field: per (target, source point) pair, Laplace double layer:
+      3 sub + 5 (r^2) + 1 (rsqrt) + 5 (r.n) + 3 (r^-3 scale) + 2 (fma) = 19
+    M2L: per (target box, source box) pair a P x P product: 2 P^2.
+    """
+    return {"p2p": 19.0 * stats["n_p2p"] if dbl else 13.0 * stats["n_p2p"],
+            "m2l": 2.0 * P * P * stats["n_m2l"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sphere20480")
+    ap.add_argument("--theta", type=float, default=0.6)
+    ap.add_argument("--B", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import bem_inputs
+    import paper_0908_0673_amd as bem
+
+    t_setup0 = time.perf_counter()
+    m = bem_inputs.workload(args.workload)
+    ctx = bem.Context(0)
+    mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
+    tree = bem.bem_tree_build(ctx, mesh, B=args.B, order=8, theta=args.theta)
+    stats = tree.stats()
+    n = mesh.n_dof
+    dof = mesh.dofs()
+    x_np = bem_inputs.random_vector(n, 1)[0]
+    x = torch.tensor(x_np, dtype=torch.float64, device="cuda:0")[None]
+    y = torch.empty_like(x)
+    # first products build the corrections and the free term (setup)
+    for prec in (bem.BEM_PREC_FP64, bem.BEM_PREC_MIXED):
+        bem.bem_matvec(ctx, tree, 0, 0.0, bem.BEM_OP_A, bem.BEM_FMM, prec, x, y)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup0
+
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            bem.bem_matvec(ctx, tree, 0, 0.0, bem.BEM_OP_A, bem.BEM_FMM, prec, x, y)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bem.bem_matvec(ctx, tree, 0, 0.0, bem.BEM_OP_A, bem.BEM_FMM, prec, x, y)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        phases = ctx.timing(False)
+        return dt, phases, y.cpu().numpy()[0].copy()
+
+    dt_mixed, ph_mixed, y_mixed = timed(bem.BEM_PREC_MIXED, args.steps, args.warmup)
+    dt_fp64, ph_fp64, y_fp64 = timed(bem.BEM_PREC_FP64, max(3, args.steps // 2), 1)
+    ms_mixed = 1e3 * dt_mixed / args.steps
+    ms_fp64 = 1e3 * dt_fp64 / max(3, args.steps // 2)
+    value = n / (ms_mixed * 1e-3)
+
+    # errors against the oracle's direct product on sampled rows
+    err = {}
+    try:
+        import oracle
+
+        om = oracle.OracleMesh(m.xyz, m.elem)
+        rows = np.sort(np.random.default_rng(2).choice(n, 64, replace=False))
+        ref = om.matvec_rows(x_np, oracle.OP_A, rows=rows).real
+        err = {"mixed": float(np.linalg.norm(y_mixed[rows] - ref) / np.linalg.norm(ref)),
+               "fp64": float(np.linalg.norm(y_fp64[rows] - ref) / np.linalg.norm(ref)),
+               "rows_sampled": int(rows.size)}
+    except Exception as e:  # noqa: BLE001
+        err = {"error": str(e)}
+
+    # solves: plain FP64 GMRES(50) vs mixed with FP64 refinement, to 1e-8
+    solve = {}
+    if not args.no_solve:
+        from oracle import analytic
+
+        phi, chi = analytic.point_source(dof["dof_xyz"], dof["dof_normal"])
+        chid = torch.tensor(chi.real, dtype=torch.float64, device="cuda:0")[None]
+        for name, prec in (("fp64", bem.BEM_PREC_FP64), ("mixed", bem.BEM_PREC_MIXED)):
+            phid = torch.zeros_like(chid)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = bem.bem_solve(ctx, tree, 0, 0.0, chid, phid, tol=1e-8, restart=50, precision=prec)[0]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            sol = phid.cpu().numpy()[0]
+            solve[name] = {"seconds": dt, "solves_per_s": 1.0 / dt, "iterations": info["iterations"],
+                           "refinements": info["refinements"], "matvecs": info["matvecs"],
+                           "residual": info["residual"],
+                           "rms_error_vs_analytic": float(np.sqrt(np.mean((sol - phi.real) ** 2)))}
+
+    # roofline of the dominant kernel of the headline product
+    P = 165
+    flops = algorithmic_flops(stats, P)
+    per_step = {k: v[0] / max(1, v[1]) for k, v in ph_mixed.items()}
+    dom = max(("p2p", "m2l"), key=lambda k: per_step[k])
+    achieved = flops[dom] / (per_step[dom] * 1e-3) / 1e12
+    roofline = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP32_VEC_PEAK, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VEC_PEAK, "traffic": None,
+                "algorithmic_flop_per_launch": flops[dom], "avg_launch_ms": per_step[dom]}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(m, x_np, args.cpu_seconds)
+
+    out = {
+        "metric": "FMM-BEM matvec unknowns/s",
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_mixed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 near field and expansions, f64 corrections",
+        "data": "synthetic",
+        "config": {"workload": f"laplace_{args.workload}_fmm_matvec", "n_elem": m.n_elem, "n_dof": n, "nrhs": 1,
+                   "order": 8, "B": args.B, "theta": args.theta, "operator": "A = c.x - K x"},
+        "fp64": {"ms_per_step": ms_fp64, "unknowns_per_s": n / (ms_fp64 * 1e-3)},
+        "error_vs_oracle": err,
+        "phases_ms_per_step": {"mixed": per_step,
+                               "fp64": {k: v[0] / max(1, v[1]) for k, v in ph_fp64.items()}},
+        "tree": stats,
+        "setup_s": t_setup,
+        "solve": solve,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(m, x_np, seconds):
+    """The oracle (plain FP64 C, OpenMP over rows) on a bounded sample: full
+    rows of the direct product of the same operator on the same mesh."""
+    import oracle
+
+    om = oracle.OracleMesh(m.xyz, m.elem)
+    rng = np.random.default_rng(3)
+    rows = rng.permutation(om.n_dof)
+    done, t0, chunk = 0, time.perf_counter(), 256
+    while time.perf_counter() - t0 < seconds and done < om.n_dof:
+        om.matvec_rows(x_np, oracle.OP_A, rows=np.sort(rows[done:done + chunk]))
+        done += chunk
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": done / dt, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} full rows of the direct product A x on the {om.n_dof}-DOF mesh "
+                      f"(plain FP64 oracle, {dt:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

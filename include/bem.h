@@ -1,0 +1,216 @@
+/*
+ * bem.h - C interface of the MI355X (gfx950) fast-multipole boundary element
+ * library for the collocation Laplace and Helmholtz integral equations over
+ * curved 6-node triangles (M. J. Carley, "BEM3D: a free adaptive fast
+ * multipole boundary element library", arXiv 0908.0673).
+ *
+ * Problem statement (Section 2.1, Eqs. 1-3).  A closed surface S with unit
+ * normal n pointing out of the body into the unbounded domain, Green's
+ * function G = 1/(4 pi R) (Laplace) or G = e^{jkR}/(4 pi R) (Helmholtz).  For
+ * every collocation point (DOF) i the library discretises
+ *
+ *     c_i phi_i - sum_j K_ij phi_j = - sum_j S_ij chi_j               (1)
+ *
+ *     S_ij = sum_{m owns j} int_{S_m} L_j G dS,
+ *     K_ij = sum_{m owns j} PV int_{S_m} L_j dG/dn_1 dS,
+ *     c_i  = 1 + sum_j K0_ij   (K0: K with the Laplace kernel, Eq. 2),
+ *
+ * with chi = dphi/dn the prescribed Neumann data.  The fast product is the
+ * adaptive Taylor-series multipole method of Sections 3.1-3.6.
+ *
+ * Conventions shared by every entry point:
+ *  - All functions return a bem_status; 0 is success.  A failing call leaves
+ *    its output handles NULL and records a message for bem_last_error().  No
+ *    function aborts the process or throws across this interface.
+ *  - "host" pointers are read (or written) during the call only.  "device"
+ *    pointers are caller-owned device memory on the context's device; the
+ *    library never frees them.
+ *  - Device vectors hold nrhs right-hand sides as [nrhs][n_dof]: float64 for
+ *    Laplace, interleaved complex128 (re, im) for Helmholtz.
+ *  - All device work is ordered on the context's stream; calls return when
+ *    their work has completed.  A context is not thread-safe.
+ */
+#ifndef BEM_H
+#define BEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BEM_OK = 0,
+    BEM_EINVAL = -1,        /* bad argument or mesh */
+    BEM_ENOMEM = -2,        /* device or host allocation failed */
+    BEM_EDEVICE = -3,       /* a HIP runtime call failed */
+    BEM_ENOCONV = -4,       /* the solver hit its iteration cap (outputs still written) */
+    BEM_ESTATE = -5,        /* handle misuse (wrong context, freed object) */
+    BEM_EUNSUPPORTED = -6   /* valid request this build does not implement */
+} bem_status;
+
+typedef enum { BEM_LAPLACE = 0, BEM_HELMHOLTZ = 1 } bem_green;
+
+/* Operators of Eq. (1): S x, K x, the system operator A x = c.x - K x, and
+ * the right-hand side b = -S chi. */
+typedef enum { BEM_OP_S = 0, BEM_OP_K = 1, BEM_OP_A = 2, BEM_OP_RHS = 3 } bem_op;
+
+/* BEM_DIRECT: every (target, element) pair summed directly with the same
+ * quadrature (the paper's baseline, Section 2.1).  BEM_FMM: Section 3.6. */
+typedef enum { BEM_DIRECT = 0, BEM_FMM = 1 } bem_method;
+
+/* BEM_PREC_FP64: every step in double precision.  BEM_PREC_MIXED: regular
+ * near-field sums and all expansion passes in single precision with single
+ * accumulation; the singular / near-singular corrections, the free term and
+ * the combination stay double. */
+typedef enum { BEM_PREC_FP64 = 0, BEM_PREC_MIXED = 1 } bem_precision;
+
+/* Device memory provider.  alloc returns device memory of at least `bytes`
+ * usable on `stream` (NULL on failure); free releases it.  Passing NULL for
+ * the allocator makes the library use hipMalloc / hipFree. */
+typedef struct {
+    void *(*alloc)(void *user, size_t bytes, void *stream);
+    void (*free)(void *user, void *ptr, void *stream);
+    void *user;
+} bem_allocator;
+
+typedef struct bem_ctx bem_ctx;
+typedef struct bem_mesh bem_mesh;
+typedef struct bem_tree bem_tree;
+
+/* Creates a context on HIP device `device` whose work goes to `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  The stream and the allocator's
+ * user data must outlive the context. */
+int bem_ctx_create(int device, void *hip_stream, const bem_allocator *alloc, bem_ctx **out);
+void bem_ctx_destroy(bem_ctx *ctx);
+/* Message of the last failing call on this context (never NULL). */
+const char *bem_last_error(const bem_ctx *ctx);
+
+/* Phase timing (profiling aid).  While enabled, every product records HIP
+ * events on the context's stream between its phases and accumulates the
+ * elapsed device time per phase:
+ *   0 strengths, 1 P2M, 2 M2M, 3 M2L, 4 L2L, 5 L2P, 6 P2P (near field),
+ *   7 corrections + combination, 8 direct sum, 9 other.
+ * enable = 1 turns timing on and zeroes the counters; 0 turns it off.
+ * ms and launches (host arrays of BEM_NPHASE, may be NULL) receive the
+ * accumulated milliseconds and the number of products timed per phase. */
+#define BEM_NPHASE 10
+int bem_ctx_timing(bem_ctx *ctx, int enable, double *ms, int64_t *launches);
+
+/* ------------------------------------------------------------------ mesh */
+typedef struct {
+    double edge_angle_deg; /* normals closer than this share a DOF (Section 2.3); 0 -> 30 */
+} bem_mesh_opts;
+
+/* Loads a mesh of 6-node triangles (Section 2.2).
+ *   node_xyz   host [n_nodes][3] float64 node coordinates
+ *   elem_nodes host [n_elem][6] int32: corners 0,1,2 counter-clockwise seen
+ *              from outside the body, then the mid-side nodes of edges 0-1,
+ *              1-2 and 2-0 (isoparametric: geometry and data share nodes)
+ * Collocation points are the nodes.  Nodes where the element normals differ
+ * by more than opts->edge_angle_deg get one DOF per group of normals (sharp
+ * edges and corners, Section 2.3); elements are visited in order and each
+ * group's reference normal is that of its first element.
+ * Errors: BEM_EINVAL for n_elem < 1, node indices out of range, or an element
+ * with a vanishing Jacobian at a node. */
+int bem_mesh_load(bem_ctx *ctx, const double *node_xyz, int64_t n_nodes, const int32_t *elem_nodes,
+                  int64_t n_elem, const bem_mesh_opts *opts, bem_mesh **out);
+
+/* Copies the DOF layout to host buffers (each may be NULL):
+ *   elem_dofs [n_elem][6] int32, dof_node [n_dof] int32 (geometric node of a
+ *   DOF), dof_xyz [n_dof][3], dof_normal [n_dof][3] (normalised mean of the
+ *   element normals of the DOF's group). */
+int bem_mesh_dofs(const bem_mesh *mesh, int64_t *n_dof, int32_t *elem_dofs, int32_t *dof_node,
+                  double *dof_xyz, double *dof_normal);
+void bem_mesh_free(bem_mesh *mesh);
+
+/* ------------------------------------------------------------------ tree */
+typedef struct {
+    int max_elems_per_leaf; /* B: a box holding more elements is split (Section 3.1); 0 -> 32 */
+    int order;              /* Taylor order p of moments and local expansions; 0 -> 8, max 8 */
+    double theta;           /* boxes are well separated iff |c1 - c2| > (r1 + r2)/theta (Eq. 14 has
+                               theta = 1); 0 -> 0.6 */
+    double kappa;           /* Helmholtz only: also require k (r1 + r2) <= kappa; 0 or inf -> none */
+    int max_depth;          /* deepest level, <= 21; 0 -> 21 */
+    double k_hint;          /* wavenumber the kappa rule uses when building the lists */
+} bem_tree_opts;
+
+/* Builds the octree over the mesh on the device (Section 3.1): element keys
+ * are the means of the corner nodes, targets are the DOF positions, both
+ * Morton-coded on 21 bits per axis inside a padded root cube and radix
+ * sorted; then convergence radii (Section 3.4, Eq. 13) and the near-field
+ * and interaction lists (Section 3.6, Eq. 14), level by level.  The tree
+ * borrows the mesh: free the tree first. */
+int bem_tree_build(bem_ctx *ctx, const bem_mesh *mesh, const bem_tree_opts *opts, bem_tree **out);
+
+/* Host view of a built tree.  Call once with the pointer fields NULL to get
+ * the sizes, then again with buffers of those sizes (any may stay NULL). */
+typedef struct {
+    int64_t n_box, n_elem, n_target, n_near, n_inter, n_leaf;
+    int32_t max_level;
+    double root[4]; /* corner x, y, z and side of the root cube */
+    int32_t *level, *leaf, *parent, *child_begin, *nchild;         /* [n_box] */
+    int64_t *elem_begin, *elem_end, *tgt_begin, *tgt_end;            /* [n_box], sorted orders */
+    uint64_t *prefix;                                                 /* [n_box] Morton prefix */
+    double *centre;                                                   /* [n_box][3] */
+    double *radius;                                                   /* [n_box] */
+    int32_t *elem_perm, *tgt_perm;                                    /* sorted position -> id */
+    int64_t *near_ptr, *inter_ptr;                                    /* [n_box + 1] */
+    int32_t *near_idx, *inter_idx;                                    /* [n_near], [n_inter] */
+} bem_tree_view;
+
+int bem_tree_export(const bem_tree *tree, bem_tree_view *view);
+void bem_tree_free(bem_tree *tree);
+
+/* Work statistics of a tree for a (Green, k): M2L pairs, near-field pair
+ * count of target DOFs x source quadrature points, correction entries.  */
+typedef struct {
+    int64_t n_m2l, n_m2l_same_level, n_p2p, n_corr_pairs, n_leaf, n_box;
+    int64_t n_quad;
+} bem_tree_stats;
+int bem_tree_stats_get(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, bem_tree_stats *st);
+
+/* ------------------------------------------------------------------ products */
+/* y = op(x) for nrhs vectors (layout above).  x_dev and y_dev are device
+ * buffers of nrhs * n_dof values and must not overlap.  The first call for a
+ * given (g, k) builds and caches the singular / near-singular corrections
+ * and the free term on the tree (Section 2.1; Section 3.6, "precomputed and
+ * stored as a sparse matrix").
+ * Errors: BEM_EINVAL for nrhs < 1, k <= 0 with Helmholtz, NULL buffers. */
+int bem_matvec(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, bem_op op, bem_method m,
+               bem_precision p, int nrhs, const void *x_dev, void *y_dev);
+
+/* ------------------------------------------------------------------ solve */
+typedef struct {
+    double tol;          /* relative residual |b - A x| / |b| to reach; 0 -> 1e-8 */
+    int restart;         /* GMRES restart length; 0 -> 50 */
+    int max_restarts;    /* cycles per inner solve; 0 -> 100 */
+    bem_precision precision; /* FP64: GMRES on the FP64 FMM operator.  MIXED: outer FP64
+                                residual refinement around GMRES on the mixed operator */
+    double inner_tol;    /* MIXED only: inner relative tolerance; 0 -> 1e-5 */
+    int max_refine;      /* MIXED only: outer refinement steps; 0 -> 10 */
+    bem_method method;   /* operator used (BEM_FMM unless set) */
+} bem_solve_opts;
+
+typedef struct {
+    int iterations;      /* total inner Krylov iterations */
+    int refinements;     /* outer refinement steps (MIXED) */
+    int matvecs;         /* operator applications, FP64 and mixed */
+    double residual;     /* final |b - A x| / |b| with the FP64 operator */
+    int status;          /* BEM_OK or BEM_ENOCONV */
+} bem_solve_info;
+
+/* Solves Eq. (1) for phi given chi, for each of nrhs right-hand sides
+ * (Section 2.1; GMRES in place of the paper's BiCGSTAB): b = -S chi with the
+ * FP64 operator, then GMRES(restart) from x0 = 0.  chi_dev and phi_dev are
+ * device buffers of nrhs * n_dof values; info is a host array of nrhs.
+ * Returns BEM_ENOCONV (with phi and info written) if a right-hand side did
+ * not converge. */
+int bem_solve(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, int nrhs,
+              const void *chi_dev, void *phi_dev, const bem_solve_opts *opts, bem_solve_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BEM_H */

@@ -200,9 +200,12 @@ class OracleTree:
         self.B, self.theta, self.kappa, self.k = B, theta, kappa, k
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().or_tree_free(self._h)
-            self._h = None
+        try:
+            if getattr(self, "_h", None) and _lib is not None:
+                _lib.or_tree_free(self._h)
+        except Exception:  # noqa: BLE001 - interpreter teardown
+            pass
+        self._h = None
 
     def fmm_matvec(self, x, op, green=LAPLACE, k=0.0, order=8):
         """The fast matrix product of Section 3.6 (plain FP64 loops)."""

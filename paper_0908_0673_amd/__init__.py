@@ -1,0 +1,330 @@
+"""MI355X fast-multipole boundary element library (arXiv 0908.0673, Carley, BEM3D).
+
+Thin Python binding of ``libbem.so`` (C interface in ``include/bem.h``):
+argument marshalling only.  Every step of the computation runs in the
+library's HIP kernels; PyTorch provides device memory (through its caching
+allocator) and the stream.  Importing works without a GPU; creating a
+:class:`Context` needs the built library and a device, and fails loudly
+otherwise.
+"""
+
+from __future__ import annotations
+
+import atexit
+import ctypes
+import os
+import weakref
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbem.so")
+
+BEM_OK, BEM_EINVAL, BEM_ENOMEM, BEM_EDEVICE, BEM_ENOCONV, BEM_ESTATE, BEM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+BEM_LAPLACE, BEM_HELMHOLTZ = 0, 1
+BEM_OP_S, BEM_OP_K, BEM_OP_A, BEM_OP_RHS = 0, 1, 2, 3
+BEM_DIRECT, BEM_FMM = 0, 1
+BEM_PREC_FP64, BEM_PREC_MIXED = 0, 1
+
+EXPORTED = [
+    "bem_ctx_create", "bem_ctx_destroy", "bem_ctx_timing", "bem_last_error", "bem_mesh_load", "bem_mesh_dofs", "bem_mesh_free",
+    "bem_tree_build", "bem_tree_export", "bem_tree_free", "bem_tree_stats_get", "bem_matvec", "bem_solve",
+]
+
+
+class BemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC), ("free", _FREE), ("user", ctypes.c_void_p)]
+
+
+class _MeshOpts(ctypes.Structure):
+    _fields_ = [("edge_angle_deg", ctypes.c_double)]
+
+
+class _TreeOpts(ctypes.Structure):
+    _fields_ = [("max_elems_per_leaf", ctypes.c_int), ("order", ctypes.c_int), ("theta", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("max_depth", ctypes.c_int), ("k_hint", ctypes.c_double)]
+
+
+class _TreeView(ctypes.Structure):
+    _fields_ = [("n_box", ctypes.c_int64), ("n_elem", ctypes.c_int64), ("n_target", ctypes.c_int64),
+                ("n_near", ctypes.c_int64), ("n_inter", ctypes.c_int64), ("n_leaf", ctypes.c_int64),
+                ("max_level", ctypes.c_int32), ("root", ctypes.c_double * 4)] + [
+        (n, ctypes.c_void_p) for n in ("level", "leaf", "parent", "child_begin", "nchild", "elem_begin", "elem_end",
+                                       "tgt_begin", "tgt_end", "prefix", "centre", "radius", "elem_perm", "tgt_perm",
+                                       "near_ptr", "inter_ptr", "near_idx", "inter_idx")]
+
+
+class _TreeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_m2l", "n_m2l_same_level", "n_p2p", "n_corr_pairs", "n_leaf",
+                                              "n_box", "n_quad")]
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_restarts", ctypes.c_int),
+                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
+                ("method", ctypes.c_int)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("refinements", ctypes.c_int), ("matvecs", ctypes.c_int),
+                ("residual", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+_lib = None
+_live = []  # handles still open, closed in reverse order before torch shuts down
+
+
+def _close_all():
+    while _live:
+        ref = _live.pop()
+        obj = ref()
+        if obj is not None:
+            try:
+                obj.close()
+            except Exception:  # noqa: BLE001
+                pass
+
+
+atexit.register(_close_all)
+
+
+def _track(obj):
+    _live.append(weakref.ref(obj))
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libbem.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_0908_0673_amd/build.py (hipcc, gfx950)")
+    L = ctypes.CDLL(path)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    L.bem_ctx_create.argtypes = [i32, vp, ctypes.POINTER(_Allocator), ctypes.POINTER(vp)]
+    L.bem_ctx_destroy.argtypes = [vp]
+    L.bem_ctx_destroy.restype = None
+    L.bem_ctx_timing.argtypes = [vp, i32, vp, vp]
+    L.bem_last_error.argtypes = [vp]
+    L.bem_last_error.restype = ctypes.c_char_p
+    L.bem_mesh_load.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(_MeshOpts), ctypes.POINTER(vp)]
+    L.bem_mesh_dofs.argtypes = [vp, ctypes.POINTER(i64), vp, vp, vp, vp]
+    L.bem_mesh_free.argtypes = [vp]
+    L.bem_mesh_free.restype = None
+    L.bem_tree_build.argtypes = [vp, vp, ctypes.POINTER(_TreeOpts), ctypes.POINTER(vp)]
+    L.bem_tree_export.argtypes = [vp, ctypes.POINTER(_TreeView)]
+    L.bem_tree_free.argtypes = [vp]
+    L.bem_tree_free.restype = None
+    L.bem_tree_stats_get.argtypes = [vp, vp, i32, dbl, ctypes.POINTER(_TreeStats)]
+    L.bem_matvec.argtypes = [vp, vp, i32, dbl, i32, i32, i32, i32, vp, vp]
+    L.bem_solve.argtypes = [vp, vp, i32, dbl, i32, vp, vp, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo)]
+    _lib = L
+    return L
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """A device, a stream (torch's current stream unless given) and torch's caching allocator."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        self.torch = torch
+        L = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the library runs on gfx950 only")
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        dev = device
+
+        def _a(user, nbytes, stream_):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream_ or 0)
+            except Exception:  # noqa: BLE001 - reported to the library as NULL (BEM_ENOMEM)
+                return None
+
+        def _f(user, ptr, stream_):
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:  # noqa: BLE001 - only at interpreter teardown
+                pass
+
+        self._cb = (_ALLOC(_a), _FREE(_f))
+        self._alloc = _Allocator(self._cb[0], self._cb[1], None)
+        h = ctypes.c_void_p()
+        rc = L.bem_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._alloc), ctypes.byref(h))
+        if rc != 0:
+            raise BemError(rc, "bem_ctx_create failed: " + L.bem_last_error(None).decode())
+        self.h = h
+        self.L = L
+        _track(self)
+
+    def check(self, rc, what):
+        if rc != 0:
+            raise BemError(rc, f"{what}: {self.L.bem_last_error(self.h).decode()}")
+        return rc
+
+    PHASES = ("strength", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "combine", "direct", "other")
+
+    def timing(self, enable: bool):
+        """Turns per-phase event timing on (zeroing it) or off; returns the
+        accumulated {phase: (ms, products)} before the switch."""
+        ms = np.zeros(10)
+        n = np.zeros(10, np.int64)
+        self.check(self.L.bem_ctx_timing(self.h, int(enable), _np_ptr(ms), _np_ptr(n)), "bem_ctx_timing")
+        return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(self.PHASES)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.bem_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+class Mesh:
+    def __init__(self, ctx: Context, xyz, elem, edge_angle_deg: float = 30.0):
+        self.ctx = ctx
+        xyz = np.ascontiguousarray(xyz, np.float64)
+        elem = np.ascontiguousarray(elem, np.int32)
+        h = ctypes.c_void_p()
+        opts = _MeshOpts(edge_angle_deg)
+        ctx.check(ctx.L.bem_mesh_load(ctx.h, _np_ptr(xyz), xyz.shape[0], _np_ptr(elem), elem.shape[0],
+                                      ctypes.byref(opts), ctypes.byref(h)), "bem_mesh_load")
+        self.h = h
+        _track(self)
+        n = ctypes.c_int64()
+        ctx.check(ctx.L.bem_mesh_dofs(h, ctypes.byref(n), None, None, None, None), "bem_mesh_dofs")
+        self.n_dof = int(n.value)
+        self.n_elem = int(elem.shape[0])
+
+    def dofs(self):
+        n = self.n_dof
+        ed = np.zeros((self.n_elem, 6), np.int32)
+        dn = np.zeros(n, np.int32)
+        dx = np.zeros((n, 3))
+        nr = np.zeros((n, 3))
+        self.ctx.check(self.ctx.L.bem_mesh_dofs(self.h, None, _np_ptr(ed), _np_ptr(dn), _np_ptr(dx), _np_ptr(nr)),
+                       "bem_mesh_dofs")
+        return {"elem_dofs": ed, "dof_node": dn, "dof_xyz": dx, "dof_normal": nr}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.L.bem_mesh_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+class Tree:
+    def __init__(self, ctx: Context, mesh: Mesh, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21, k_hint=0.0):
+        self.ctx, self.mesh = ctx, mesh
+        opts = _TreeOpts(B, order, theta, kappa, max_depth, k_hint)
+        h = ctypes.c_void_p()
+        ctx.check(ctx.L.bem_tree_build(ctx.h, mesh.h, ctypes.byref(opts), ctypes.byref(h)), "bem_tree_build")
+        self.h = h
+        self.n_dof = mesh.n_dof
+        _track(self)
+
+    def export(self):
+        v = _TreeView()
+        self.ctx.check(self.ctx.L.bem_tree_export(self.h, ctypes.byref(v)), "bem_tree_export")
+        nb, ne, nt, nn, ni = v.n_box, v.n_elem, v.n_target, v.n_near, v.n_inter
+        out = {
+            "level": np.zeros(nb, np.int32), "leaf": np.zeros(nb, np.int32), "parent": np.zeros(nb, np.int32),
+            "child_begin": np.zeros(nb, np.int32), "nchild": np.zeros(nb, np.int32),
+            "elem_begin": np.zeros(nb, np.int64), "elem_end": np.zeros(nb, np.int64),
+            "tgt_begin": np.zeros(nb, np.int64), "tgt_end": np.zeros(nb, np.int64),
+            "prefix": np.zeros(nb, np.uint64), "centre": np.zeros((nb, 3)), "radius": np.zeros(nb),
+            "elem_perm": np.zeros(ne, np.int32), "tgt_perm": np.zeros(nt, np.int32),
+            "near_ptr": np.zeros(nb + 1, np.int64), "inter_ptr": np.zeros(nb + 1, np.int64),
+            "near_idx": np.zeros(max(nn, 1), np.int32), "inter_idx": np.zeros(max(ni, 1), np.int32),
+        }
+        for k, a in out.items():
+            setattr(v, k, _np_ptr(a))
+        self.ctx.check(self.ctx.L.bem_tree_export(self.h, ctypes.byref(v)), "bem_tree_export")
+        out["near_idx"] = out["near_idx"][:nn]
+        out["inter_idx"] = out["inter_idx"][:ni]
+        out["root"] = np.array(list(v.root))
+        out["max_level"] = int(v.max_level)
+        out["n_leaf"] = int(v.n_leaf)
+        return out
+
+    def stats(self, green=BEM_LAPLACE, k=0.0):
+        st = _TreeStats()
+        self.ctx.check(self.ctx.L.bem_tree_stats_get(self.ctx.h, self.h, green, k, ctypes.byref(st)),
+                       "bem_tree_stats_get")
+        return {n: int(getattr(st, n)) for n, _ in _TreeStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.L.bem_tree_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+def _check_vec(t, n, green):
+    import torch
+
+    want = torch.complex128 if green == BEM_HELMHOLTZ else torch.float64
+    if not t.is_cuda or t.dtype != want or not t.is_contiguous() or t.numel() % n != 0:
+        raise ValueError(f"expected a contiguous {want} device tensor of nrhs x {n} values")
+    return t.numel() // n
+
+
+def bem_mesh_load(ctx: Context, xyz, elem, edge_angle_deg: float = 30.0) -> Mesh:
+    return Mesh(ctx, xyz, elem, edge_angle_deg)
+
+
+def bem_tree_build(ctx: Context, mesh: Mesh, **opts) -> Tree:
+    return Tree(ctx, mesh, **opts)
+
+
+def bem_matvec(ctx: Context, tree: Tree, green: int, k: float, op: int, method: int, precision: int, x, y) -> None:
+    """y = op(x) on the device; x, y are torch tensors [nrhs, n_dof]."""
+    nrhs = _check_vec(x, tree.n_dof, green)
+    if _check_vec(y, tree.n_dof, green) != nrhs:
+        raise ValueError("x and y differ in shape")
+    ctx.check(ctx.L.bem_matvec(ctx.h, tree.h, green, float(k), op, method, precision, nrhs,
+                               ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())), "bem_matvec")
+
+
+def bem_solve(ctx: Context, tree: Tree, green: int, k: float, chi, phi, tol=1e-8, restart=50, max_restarts=100,
+              precision=BEM_PREC_FP64, inner_tol=1e-5, max_refine=10, method=BEM_FMM, raise_on_noconv=False):
+    """Solves c.phi - K phi = -S chi; returns a list of per-rhs info dicts."""
+    nrhs = _check_vec(chi, tree.n_dof, green)
+    if _check_vec(phi, tree.n_dof, green) != nrhs:
+        raise ValueError("chi and phi differ in shape")
+    opts = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method)
+    info = (_SolveInfo * nrhs)()
+    rc = ctx.L.bem_solve(ctx.h, tree.h, green, float(k), nrhs, ctypes.c_void_p(chi.data_ptr()),
+                         ctypes.c_void_p(phi.data_ptr()), ctypes.byref(opts), info)
+    if rc != 0 and (rc != BEM_ENOCONV or raise_on_noconv):
+        ctx.check(rc, "bem_solve")
+    return [{n: getattr(i, n) for n, _ in _SolveInfo._fields_} for i in info]

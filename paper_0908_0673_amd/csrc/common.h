@@ -1,0 +1,243 @@
+// Internal helpers of the HIP library: errors, device buffers, complex values,
+// launch checks.  Included by every translation unit of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/bem.h"
+
+namespace bem {
+
+// Errors travel as exceptions inside the library and become status codes at
+// the C interface (api.hip); nothing is thrown across it.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(int code, const std::string &msg) { throw Error(code, msg); }
+
+#define BEM_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            ::bem::fail(BEM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_) + " (" + \
+                                         __FILE__ + ":" + std::to_string(__LINE__) + ")");      \
+    } while (0)
+
+#define BEM_LAUNCH_CHECK() BEM_HIP(hipGetLastError())
+
+#define BEM_REQUIRE(cond, code, msg)              \
+    do {                                          \
+        if (!(cond)) ::bem::fail((code), (msg));  \
+    } while (0)
+
+// ---------------------------------------------------------------- context
+struct Ctx {
+    // phase timing with events on the context's stream
+    bool timing = false;
+    double phase_ms[BEM_NPHASE] = {0};
+    int64_t phase_n[BEM_NPHASE] = {0};
+    std::vector<hipEvent_t> events;
+    std::vector<int> ev_phase;  // phase closed by each recorded event (-1 for the opening one)
+    int ev_used = 0;
+
+    void mark(int phase) {
+        if (!timing) return;
+        if (ev_used == (int)events.size()) {
+            hipEvent_t e;
+            BEM_HIP(hipEventCreate(&e));
+            events.push_back(e);
+            ev_phase.push_back(-1);
+        }
+        BEM_HIP(hipEventRecord(events[ev_used], stream));
+        ev_phase[ev_used] = phase;
+        ev_used++;
+    }
+    // after the stream has been synchronised: fold the recorded intervals into the counters
+    void collect() {
+        if (!timing) return;
+        bool seen[BEM_NPHASE] = {false};
+        for (int i = 1; i < ev_used; i++) {
+            float ms = 0.f;
+            BEM_HIP(hipEventElapsedTime(&ms, events[i - 1], events[i]));
+            int ph = ev_phase[i];
+            if (ph >= 0 && ph < BEM_NPHASE) {
+                phase_ms[ph] += ms;
+                if (!seen[ph]) { phase_n[ph]++; seen[ph] = true; }
+            }
+        }
+        ev_used = 0;
+    }
+    ~Ctx() {
+        for (auto e : events) (void)hipEventDestroy(e);
+    }
+
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bem_allocator alloc{};
+    bool has_alloc = false;
+    std::string err;
+
+    void *dmalloc(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        void *p = nullptr;
+        if (has_alloc) {
+            p = alloc.alloc(alloc.user, bytes, (void *)stream);
+            if (!p) fail(BEM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        } else {
+            hipError_t e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) fail(BEM_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        }
+        return p;
+    }
+    void dfree(void *p) {
+        if (!p) return;
+        if (has_alloc) alloc.free(alloc.user, p, (void *)stream);
+        else (void)hipFree(p);
+    }
+    void sync() { BEM_HIP(hipStreamSynchronize(stream)); }
+};
+
+// Device array owned by the library, released through the context's allocator.
+template <class T>
+struct DBuf {
+    Ctx *ctx = nullptr;
+    T *p = nullptr;
+    size_t n = 0;
+
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : ctx(o.ctx), p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); ctx = o.ctx; p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+
+    void alloc(Ctx *c, size_t count) {
+        release();
+        ctx = c;
+        n = count;
+        p = static_cast<T *>(c->dmalloc(sizeof(T) * (count ? count : 1)));
+    }
+    void zero() {
+        if (n) BEM_HIP(hipMemsetAsync(p, 0, sizeof(T) * n, ctx->stream));
+    }
+    void release() {
+        if (p && ctx) ctx->dfree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // copies from host memory the caller may free on return, so it waits for the copy
+    void upload(const T *h, size_t count) {
+        BEM_REQUIRE(count <= n, BEM_EINVAL, "upload overflow");
+        if (count) {
+            BEM_HIP(hipMemcpyAsync(p, h, sizeof(T) * count, hipMemcpyHostToDevice, ctx->stream));
+            BEM_HIP(hipStreamSynchronize(ctx->stream));
+        }
+    }
+    std::vector<T> download(size_t count) const {
+        std::vector<T> h(count);
+        if (count) {
+            BEM_HIP(hipMemcpyAsync(h.data(), p, sizeof(T) * count, hipMemcpyDeviceToHost, ctx->stream));
+            BEM_HIP(hipStreamSynchronize(ctx->stream));
+        }
+        return h;
+    }
+    // makes room for at least `count` elements (contents not kept)
+    void ensure(Ctx *c, size_t count) {
+        if (p && count <= n) return;
+        alloc(c, count);
+    }
+    // grows to at least `count`, keeping the first `keep` elements
+    void grow(size_t count, size_t keep) {
+        if (count <= n) return;
+        DBuf<T> nb;
+        nb.alloc(ctx, count);
+        if (keep) BEM_HIP(hipMemcpyAsync(nb.p, p, sizeof(T) * keep, hipMemcpyDeviceToDevice, ctx->stream));
+        *this = std::move(nb);
+    }
+};
+
+template <class T>
+inline T read_scalar(Ctx &c, const T *dptr) {
+    T v;
+    BEM_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, c.stream));
+    BEM_HIP(hipStreamSynchronize(c.stream));
+    return v;
+}
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------- complex
+template <class R>
+struct cx {
+    R re, im;
+    cx() = default;
+    __host__ __device__ cx(R r) : re(r), im(0) {}
+    __host__ __device__ cx(R r, R i) : re(r), im(i) {}
+    __host__ __device__ cx &operator+=(const cx &o) { re += o.re; im += o.im; return *this; }
+    __host__ __device__ cx &operator-=(const cx &o) { re -= o.re; im -= o.im; return *this; }
+    __host__ __device__ cx &operator*=(R s) { re *= s; im *= s; return *this; }
+};
+template <class R> __host__ __device__ inline cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R> __host__ __device__ inline cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R> __host__ __device__ inline cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+template <class R> __host__ __device__ inline cx<R> operator*(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R> __host__ __device__ inline cx<R> operator*(cx<R> a, R s) { return {a.re * s, a.im * s}; }
+template <class R> __host__ __device__ inline cx<R> operator*(R s, cx<R> a) { return {a.re * s, a.im * s}; }
+template <class R> __host__ __device__ inline cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+
+// Value traits: Laplace values are real, Helmholtz values complex.
+template <class V> struct real_of { using type = V; };
+template <class R> struct real_of<cx<R>> { using type = R; };
+
+template <class V> __host__ __device__ inline V vzero() { return V(0); }
+
+__host__ __device__ inline double re_part(double v) { return v; }
+__host__ __device__ inline float re_part(float v) { return v; }
+template <class R> __host__ __device__ inline R re_part(cx<R> v) { return v.re; }
+
+template <class To, class From> __host__ __device__ inline To vcast(From v) { return To(v); }
+template <> __host__ __device__ inline cx<float> vcast<cx<float>, cx<double>>(cx<double> v) {
+    return cx<float>((float)v.re, (float)v.im);
+}
+template <> __host__ __device__ inline cx<double> vcast<cx<double>, cx<float>>(cx<float> v) {
+    return cx<double>((double)v.re, (double)v.im);
+}
+template <> __host__ __device__ inline cx<double> vcast<cx<double>, cx<double>>(cx<double> v) { return v; }
+template <> __host__ __device__ inline cx<float> vcast<cx<float>, cx<float>>(cx<float> v) { return v; }
+
+__device__ inline void vsincos(float x, float *s, float *c) { sincosf(x, s, c); }
+__device__ inline void vsincos(double x, double *s, double *c) { sincos(x, s, c); }
+
+// Wave-wide (64 lanes) sums by butterfly shuffles: every lane ends with the
+// same total, accumulated in a fixed order (deterministic).
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline float wave_sum(float v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <class R> __device__ inline cx<R> wave_sum(cx<R> v) { return {wave_sum(v.re), wave_sum(v.im)}; }
+__device__ inline double wave_max(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+constexpr int MAXLEV = 21;
+constexpr int MAX_ORDER = 10;
+
+}  // namespace bem

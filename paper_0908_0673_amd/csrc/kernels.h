@@ -1,0 +1,155 @@
+// Library-internal objects (mesh, tree, per-Green caches) and the host-side
+// launchers each translation unit provides.
+#pragma once
+
+#include <memory>
+
+#include "common.h"
+
+// Opaque handles of the C interface.
+struct bem_ctx {
+    bem::Ctx c;
+};
+
+struct bem_mesh {
+    bem::Ctx *ctx = nullptr;
+    int64_t n_nodes = 0, n_el = 0, n_dof = 0;
+    std::vector<double> h_xyz, h_dof_normal;
+    std::vector<int32_t> h_elem, h_elem_dofs, h_dof_node;
+    bem::DBuf<double> xyz;        // [n_nodes][3]
+    bem::DBuf<int32_t> elem;      // [n_el][6]
+    bem::DBuf<int32_t> elem_dofs; // [n_el][6]
+    bem::DBuf<int32_t> dof_node;  // [n_dof]
+    bem::DBuf<double> dof_xyz;    // [n_dof][3]
+};
+
+namespace bem {
+
+// Singular / near-singular corrections for one (Green, k), on the tree's pair list.
+struct Corr {
+    int green = -1;
+    double k = 0.0;
+    DBuf<double> S, K;  // [n_pairs][6] (x2 interleaved when complex): accurate - 7-point
+};
+
+// Expansion operator tables for one order p.
+struct FmmTables {
+    int p = -1, P = 0, P2 = 0;
+    DBuf<int8_t> exps;        // [P2][3]
+    DBuf<int32_t> m2m_ptr;    // [P+1] terms of each target coefficient
+    DBuf<int16_t> m2m_src;    // [nnz] source coefficient
+    DBuf<double> m2m_c64;     // [8][nnz] per child octant
+    DBuf<float> m2m_c32;
+    DBuf<int32_t> l2l_ptr;
+    DBuf<int16_t> l2l_src;
+    DBuf<double> l2l_c64;
+    DBuf<float> l2l_c32;
+    DBuf<double> inv_fact64;  // [P2] 1 / alpha!
+    DBuf<float> inv_fact32;
+    int nnz_m2m = 0, nnz_l2l = 0;
+};
+
+// Per-matvec work buffers, grown on demand and kept on the tree.
+struct Work {
+    DBuf<char> strength, mom, loc, yacc;
+    DBuf<double> y64;
+};
+
+}  // namespace bem
+
+struct bem_tree {
+    bem::Ctx *ctx = nullptr;
+    const bem_mesh *mesh = nullptr;
+    int B = 32, order = 8, max_depth = 21;
+    double theta = 0.6, kappa = 0.0, k_hint = 0.0;
+    int64_t n_box = 0, n_leaf = 0, n_near = 0, n_inter = 0, n_el = 0, n_tgt = 0, n_q = 0;
+    int max_level = 0;
+    double corner[3] = {0, 0, 0}, side = 0;
+    std::vector<int64_t> level_off;  // [max_level + 2]
+
+    // boxes, canonical (level, prefix) order
+    bem::DBuf<int32_t> level, leaf, parent, child_begin, nchild;
+    bem::DBuf<int64_t> eb, ee, tb, te;
+    bem::DBuf<uint64_t> prefix;
+    bem::DBuf<double> centre, radius;  // [n_box][3], [n_box]
+    bem::DBuf<int32_t> eperm, tperm;   // sorted position -> element / DOF
+    bem::DBuf<int64_t> near_ptr, inter_ptr;
+    bem::DBuf<int32_t> near_idx, inter_idx;
+
+    // geometry in sorted element order (Section 2.2 with the 7-point rule)
+    bem::DBuf<int32_t> se_dofs;  // [n_el][6]
+    bem::DBuf<int32_t> se_nodes; // [n_el][6]
+    bem::DBuf<double> q64;       // SoA [7][n_q]: x y z wJ nx ny nz
+    bem::DBuf<float> q32;
+    bem::DBuf<double> t64;       // SoA [3][n_tgt] sorted targets
+    bem::DBuf<float> t32;
+    bem::DBuf<double> L7;        // [7][6] shape functions at the rule points
+
+    // host copies for planning
+    std::vector<int32_t> h_level, h_leaf, h_parent, h_nchild;
+    std::vector<int64_t> h_tb, h_te, h_eb, h_ee, h_near_ptr, h_inter_ptr;
+    std::vector<int32_t> h_near_idx, h_inter_idx;
+
+    // P2P work items: (target leaf, first sorted target, count <= 64)
+    bem::DBuf<int32_t> p2p_box, p2p_t0, p2p_nt;
+    int64_t n_p2p_items = 0, n_p2p_pairs = 0;
+    bem::DBuf<int32_t> leaf_ids;       // leaf boxes with elements (P2M)
+    int64_t n_leaf_src = 0;
+    bem::DBuf<int32_t> tleaf_ids;      // leaf boxes with targets (L2P)
+    int64_t n_leaf_tgt = 0;
+    bem::DBuf<int32_t> m2l_boxes;      // boxes with a non-empty interaction list and targets below
+    int64_t n_m2l_boxes = 0;
+    std::vector<std::vector<int32_t>> m2m_level_boxes;  // non-leaf boxes per level
+    std::vector<bem::DBuf<int32_t>> d_m2m_level_boxes;
+    std::vector<bem::DBuf<int32_t>> d_level_boxes;      // all boxes per level (L2L)
+
+    // (target, element) pairs needing the singular / near-singular rules: CSR by sorted target
+    bool has_pairs = false;
+    int64_t n_pairs = 0;
+    bem::DBuf<int64_t> pair_ptr;   // [n_tgt + 1]
+    bem::DBuf<int32_t> pair_elem;  // sorted element index
+    bem::DBuf<int32_t> pair_info;  // class (1 near, 2 singular) | param << 4
+    bem::DBuf<int32_t> pair_row;   // sorted target index
+    bool planned = false;
+    std::vector<int64_t> h_level_down;
+
+    std::vector<std::unique_ptr<bem::Corr>> corr;
+    bem::DBuf<double> free_term;  // [n_dof], DOF order
+    bool has_free_term = false;
+    std::unique_ptr<bem::FmmTables> tables;
+    bem::Work work;
+};
+
+namespace bem {
+
+// scan_sort.hip
+template <class T>
+void scan_exclusive(Ctx &c, const T *in, T *out, int64_t n);  // out has n + 1 entries
+void radix_sort_pairs(Ctx &c, uint64_t *keys, int32_t *vals, int64_t n, int key_bits);
+
+// mesh.cpp (host)
+void index_dofs(bem_mesh &m, double tol_deg);
+
+// tree.hip
+void build_tree(bem_tree &t);
+
+// geom.hip
+void build_geometry(bem_tree &t);
+void rule7(double s[7], double t[7], double w[7]);
+
+// quad.hip
+void build_pairs(bem_tree &t);
+Corr &get_corr(bem_tree &t, int green, double k);
+void build_free_term(bem_tree &t);
+
+// fmm.hip
+void direct_regular_unit_double_layer(bem_tree &t, double *out);
+void fmm_tables(bem_tree &t);
+void plan_fmm(bem_tree &t);
+void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int nrhs, const void *x, void *y);
+
+// solve.hip
+int solve(bem_tree &t, int green, double k, int nrhs, const void *chi, void *phi, const bem_solve_opts &o,
+          bem_solve_info *info);
+
+}  // namespace bem
