@@ -60,8 +60,8 @@ __global__ void k_strength(const XV *x, int64_t n_dof, const int32_t *se_dofs, c
 // one 64-thread block per source leaf; lanes own coefficients, points in batches of 64
 template <class V, class R, bool DBL>
 __global__ void k_p2m(const int32_t *boxes, const int64_t *eb, const int64_t *ee, const int32_t *level,
-                      const double *centre, double side, const R *q, int64_t n_q, const V *s, int p,
-                      const int8_t *exps, V *mom, int64_t n_box) {
+                      const double *centre, double side, const double *q64, const R *q, int64_t n_q, const V *s,
+                      int p, const int8_t *exps, V *mom, int64_t n_box) {
     extern __shared__ unsigned char smem[];
     const int np1 = p + 1, P = ncoef(p);
     R *pw = (R *)smem;                       // [64][3][np1]  u^k / k!
@@ -70,7 +70,8 @@ __global__ void k_p2m(const int32_t *boxes, const int64_t *eb, const int64_t *ee
     const int b = boxes[blockIdx.x], rhs = blockIdx.y, lane = threadIdx.x;
     const double rho = ldexp(side, -level[b]);
     const R irho = (R)(1.0 / rho);
-    const R cx0 = (R)centre[3 * b], cx1 = (R)centre[3 * b + 1], cx2 = (R)centre[3 * b + 2];
+    const double irho64 = 1.0 / rho;
+    const double cx0 = centre[3 * b], cx1 = centre[3 * b + 1], cx2 = centre[3 * b + 2];
     constexpr int MAXC = 5;  // up to ncoef(10) = 286 coefficients per 64 lanes
     V acc[MAXC];
     int ea[MAXC][3];
@@ -84,7 +85,8 @@ __global__ void k_p2m(const int32_t *boxes, const int64_t *eb, const int64_t *ee
     for (int64_t base = q0; base < q1; base += 64) {
         int64_t qi = base + lane;
         if (qi < q1) {
-            R u[3] = {(q[qi] - cx0) * irho, (q[n_q + qi] - cx1) * irho, (q[2 * n_q + qi] - cx2) * irho};
+            R u[3] = {(R)((q64[qi] - cx0) * irho64), (R)((q64[n_q + qi] - cx1) * irho64),
+                      (R)((q64[2 * n_q + qi] - cx2) * irho64)};
             for (int d = 0; d < 3; d++) {
                 R v = 1;
                 pw[(lane * 3 + d) * np1] = v;
@@ -169,132 +171,20 @@ __global__ void k_shift(const int32_t *boxes, const int32_t *parent, const int32
     }
 }
 
-// ---------------------------------------------------------------- M2L
-constexpr int M2L_BS = 256;
-constexpr int M2L_NR = 4;  // right-hand sides per block
-
-template <class V, class R, bool HELM>
-__device__ void radial_seq(R R2, R kk, int H, V *g) {
-    R Rr = sqrt(R2);
-    if constexpr (!HELM) {
-        g[0] = V((R)kInv4Pi / Rr);
-        for (int h = 0; h < H; h++) g[h + 1] = g[h] * (-(R)(2 * h + 1) / R2);
-    } else {
-        R sn, cs;
-        vsincos(kk * Rr, &sn, &cs);
-        R f = (R)kInv4Pi / Rr;
-        g[0] = V(f * cs, f * sn);
-        if (H >= 1) {
-            // (jkR - 1) e^{jkR} / (4 pi R^3)
-            R kr = kk * Rr, f3 = f / R2;
-            g[1] = V(f3 * (-cs - kr * sn), f3 * (kr * cs - sn));
-        }
-        for (int h = 1; h < H; h++) g[h + 1] = (g[h] * (R)(2 * h + 1) + g[h - 1] * (kk * kk)) * (-(R)1 / R2);
-    }
-}
-
-template <class V, class R, bool HELM>
-__global__ void __launch_bounds__(M2L_BS) k_m2l(const int32_t *boxes, const int64_t *iptr, const int32_t *iidx,
-                                                const int32_t *level, const double *centre, double side, double k,
-                                                int p, const int8_t *exps, const R *inv_fact, const V *mom, V *loc,
-                                                int64_t n_box, int nrhs) {
-    extern __shared__ unsigned char smem[];
-    const int P = ncoef(p), H = 2 * p, P2 = ncoef(H);
-    V *bufA = (V *)smem;
-    V *bufB = bufA + P2;
-    V *g = bufB + P2;               // [H + 1]
-    V *ms = g + (H + 1);            // [M2L_NR][P] signed, scaled source moments
-    int8_t *ex = (int8_t *)(ms + M2L_NR * P);  // [P2][3]
-    const int tid = threadIdx.x;
-    for (int j = tid; j < 3 * P2; j += M2L_BS) ex[j] = exps[j];
-    const int b = boxes[blockIdx.x];
-    const int r0 = blockIdx.y * M2L_NR, nr = min(M2L_NR, nrhs - r0);
-    const int lb = level[b];
-    const double rho_t = ldexp(side, -lb);
-    int eb0 = 0, eb1 = 0, eb2 = 0, nbeta = 0;
-    __syncthreads();
-    if (tid < P) { eb0 = ex[3 * tid]; eb1 = ex[3 * tid + 1]; eb2 = ex[3 * tid + 2]; nbeta = eb0 + eb1 + eb2; }
-    V acc[M2L_NR];
-    for (int r = 0; r < M2L_NR; r++) acc[r] = V(0.0);
-    for (int64_t j = iptr[b]; j < iptr[b + 1]; j++) {
-        const int s = iidx[j];
-        const int ls = level[s];
-        const double rho_s = ldexp(side, -ls);
-        const double rho_m = fmax(rho_s, rho_t);
-        const R rs = (R)(rho_s / rho_m), rt = (R)(rho_t / rho_m);
-        const R rx = (R)((centre[3 * b] - centre[3 * s]) / rho_m);
-        const R ry = (R)((centre[3 * b + 1] - centre[3 * s + 1]) / rho_m);
-        const R rz = (R)((centre[3 * b + 2] - centre[3 * s + 2]) / rho_m);
-        if (tid == 0) radial_seq<V, R, HELM>(rx * rx + ry * ry + rz * rz, (R)(k * rho_m), H, g);
-        // signed, scaled moments (-1)^|a| (rho_s / rho_m)^|a| Mh_a
-        for (int idx = tid; idx < nr * P; idx += M2L_BS) {
-            int r = idx / P, a = idx % P;
-            int na = ex[3 * a] + ex[3 * a + 1] + ex[3 * a + 2];
-            R f = (na & 1) ? -1 : 1;
-            for (int i = 0; i < na; i++) f *= rs;
-            ms[r * P + a] = mom[((int64_t)(r0 + r) * n_box + s) * P + a] * f;
-        }
-        __syncthreads();
-        if (tid == 0) bufA[0] = g[H];
-        __syncthreads();
-        V *prev = bufA, *cur = bufB;
-        const R rr[3] = {rx, ry, rz};
-        for (int h = H - 1; h >= 0; h--) {
-            const int m = ncoef(H - h);
-            for (int i = tid; i < m; i += M2L_BS) {
-                V v;
-                if (i == 0) {
-                    v = g[h];
-                } else {
-                    int al[3] = {ex[3 * i], ex[3 * i + 1], ex[3 * i + 2]};
-                    int d = al[0] > 0 ? 0 : (al[1] > 0 ? 1 : 2);
-                    al[d]--;
-                    v = prev[midx(al[0], al[1], al[2])] * rr[d];
-                    if (al[d] > 0) {
-                        int ad = al[d];
-                        al[d]--;
-                        v += prev[midx(al[0], al[1], al[2])] * (R)ad;
-                    }
-                }
-                cur[i] = v;
-            }
-            __syncthreads();
-            V *t = prev; prev = cur; cur = t;
-        }
-        // contraction for this thread's beta
-        if (tid < P) {
-            V part[M2L_NR];
-            for (int r = 0; r < M2L_NR; r++) part[r] = V(0.0);
-            for (int a = 0; a < P; a++) {
-                V d = prev[midx(eb0 + ex[3 * a], eb1 + ex[3 * a + 1], eb2 + ex[3 * a + 2])];
-                for (int r = 0; r < M2L_NR; r++)
-                    if (r < nr) part[r] += d * ms[r * P + a];
-            }
-            R f = (R)1;
-            for (int i = 0; i < nbeta; i++) f *= rt;
-            f = f / (R)rho_m;
-            for (int r = 0; r < M2L_NR; r++) acc[r] += part[r] * f;
-        }
-        __syncthreads();
-    }
-    if (tid < P)
-        for (int r = 0; r < nr; r++) loc[((int64_t)(r0 + r) * n_box + b) * P + tid] += acc[r] * inv_fact[tid];
-}
-
 // ---------------------------------------------------------------- L2P
 template <class V, class R>
 __global__ void k_l2p(const int32_t *boxes, const int64_t *tb, const int64_t *te, const int32_t *level,
-                      const double *centre, double side, const R *t, int64_t n_tgt, int p, const V *loc,
+                      const double *centre, double side, const double *t, int64_t n_tgt, int p, const V *loc,
                       int64_t n_box, V *y) {
     extern __shared__ unsigned char smem[];
     V *F = (V *)smem;
     const int b = boxes[blockIdx.x], rhs = blockIdx.y, P = ncoef(p);
     for (int j = threadIdx.x; j < P; j += blockDim.x) F[j] = loc[((int64_t)rhs * n_box + b) * P + j];
     __syncthreads();
-    const R irho = (R)(1.0 / ldexp(side, -level[b]));
+    const double irho = 1.0 / ldexp(side, -level[b]);
     for (int64_t i = tb[b] + threadIdx.x; i < te[b]; i += blockDim.x) {
-        R u0 = (t[i] - (R)centre[3 * b]) * irho, u1 = (t[n_tgt + i] - (R)centre[3 * b + 1]) * irho,
-          u2 = (t[2 * n_tgt + i] - (R)centre[3 * b + 2]) * irho;
+        R u0 = (R)((t[i] - centre[3 * b]) * irho), u1 = (R)((t[n_tgt + i] - centre[3 * b + 1]) * irho),
+          u2 = (R)((t[2 * n_tgt + i] - centre[3 * b + 2]) * irho);
         V acc = V(0.0);
         R xa = 1;
         for (int a = 0; a <= p; a++) {
@@ -318,32 +208,40 @@ constexpr int P2P_BS = 256;
 constexpr int P2P_TILE = 256;
 constexpr int P2P_CH = 256;  // near-list entries per chunk
 
+__device__ inline float inv_sqrt(float v) { return rsqrtf(v); }
+__device__ inline double inv_sqrt(double v) { return 1.0 / sqrt(v); }
+
+// One block per work item (a target leaf and up to 64 of its targets).  The
+// near-list boxes' points are streamed through LDS tiles; each wave takes a
+// quarter of a tile, its lanes split into (target, sub-stream) pairs.  The
+// target-source difference is formed in FP64 (the coordinates are FP64) and
+// only then rounded to R, so that close pairs keep their relative accuracy in
+// the mixed path; per-tile partial sums in R are added into an FP64 total.
 template <class V, class R, bool DBL, bool HELM>
 __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *wi_box, const int32_t *wi_t0, const int32_t *wi_nt,
                                                 const int64_t *nptr, const int32_t *nidx, const int64_t *eb,
-                                                const int64_t *ee, const R *q, int64_t n_q, const V *s, const R *t,
-                                                int64_t n_tgt, R k, V *y, bool accumulate) {
+                                                const int64_t *ee, const double *q64, const R *q, int64_t n_q,
+                                                const V *s, const double *t64, int64_t n_tgt, R k, V *y) {
+    using VD = typename std::conditional<HELM, cx<double>, double>::type;
     __shared__ int64_t pref[P2P_CH + 1];
     __shared__ int64_t qbeg[P2P_CH];
-    __shared__ R sx[P2P_TILE], sy[P2P_TILE], sz[P2P_TILE], snx[DBL ? P2P_TILE : 1], sny[DBL ? P2P_TILE : 1],
-        snz[DBL ? P2P_TILE : 1];
+    __shared__ double sx[P2P_TILE], sy[P2P_TILE], sz[P2P_TILE];
+    __shared__ R snx[DBL ? P2P_TILE : 1], sny[DBL ? P2P_TILE : 1], snz[DBL ? P2P_TILE : 1];
     __shared__ V ss[P2P_TILE];
-    __shared__ V red[P2P_BS / 64][64];
+    __shared__ VD red[P2P_BS / 64][64];
     const int w = blockIdx.x, rhs = blockIdx.y;
     const int b = wi_box[w], t0 = wi_t0[w], nt = wi_nt[w];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int tpw = 1;
     while (tpw < nt) tpw <<= 1;
     const int nsub = 64 / tpw, tl = lane % tpw, sub = lane / tpw;
-    const bool tvalid = tl < nt;
-    const int64_t ti = t0 + (tvalid ? tl : 0);
-    const R x0 = t[ti], x1 = t[n_tgt + ti], x2 = t[2 * n_tgt + ti];
+    const int64_t ti = t0 + (tl < nt ? tl : 0);
+    const double x0 = t64[ti], x1 = t64[n_tgt + ti], x2 = t64[2 * n_tgt + ti];
     const V *sr = s + (int64_t)rhs * n_q;
-    V acc = V(0.0);
+    VD total = VD(0.0);
     const int64_t j0 = nptr[b], j1 = nptr[b + 1];
     for (int64_t cb = j0; cb < j1; cb += P2P_CH) {
         const int nc = (int)min<int64_t>(P2P_CH, j1 - cb);
-        // prefix sums of the chunk's point counts
         if (tid < nc) {
             int32_t nb_ = nidx[cb + tid];
             qbeg[tid] = 7 * eb[nb_];
@@ -354,19 +252,19 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *wi_box, const int
         if (tid == 0)
             for (int i = 1; i <= nc; i++) pref[i] += pref[i - 1];
         __syncthreads();
-        const int64_t total = pref[nc];
-        for (int64_t tb0 = 0; tb0 < total; tb0 += P2P_TILE) {
+        const int64_t total_pts = pref[nc];
+        for (int64_t tb0 = 0; tb0 < total_pts; tb0 += P2P_TILE) {
             const int64_t f = tb0 + tid;
-            if (f < total) {
+            if (f < total_pts) {
                 int lo = 0, hi = nc - 1;
                 while (lo < hi) {
                     int mid = (lo + hi + 1) >> 1;
                     if (pref[mid] <= f) lo = mid; else hi = mid - 1;
                 }
                 const int64_t qi = qbeg[lo] + (f - pref[lo]);
-                sx[tid] = q[qi];
-                sy[tid] = q[n_q + qi];
-                sz[tid] = q[2 * n_q + qi];
+                sx[tid] = q64[qi];
+                sy[tid] = q64[n_q + qi];
+                sz[tid] = q64[2 * n_q + qi];
                 if (DBL) {
                     snx[tid] = q[4 * n_q + qi];
                     sny[tid] = q[5 * n_q + qi];
@@ -375,42 +273,51 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *wi_box, const int
                 ss[tid] = sr[qi];
             }
             __syncthreads();
-            const int nin = (int)min<int64_t>(P2P_TILE, total - tb0);
+            const int nin = (int)min<int64_t>(P2P_TILE, total_pts - tb0);
             const int kb = wave * 64, ke = min(nin, kb + 64);
+            V acc = V(0.0);
             for (int kk = kb + sub; kk < ke; kk += nsub) {
-                R d0 = x0 - sx[kk], d1 = x1 - sy[kk], d2 = x2 - sz[kk];
-                R r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                R rn = DBL ? d0 * snx[kk] + d1 * sny[kk] + d2 * snz[kk] : (R)0;
+                const R d0 = (R)(x0 - sx[kk]), d1 = (R)(x1 - sy[kk]), d2 = (R)(x2 - sz[kk]);
+                const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                const R ir = inv_sqrt(r2);
+                const R g = (R)kInv4Pi * ir;
                 if constexpr (HELM) {
-                    cx<R> G, dG;
-                    green_helmholtz<R>(r2, rn, k, &G, &dG);
-                    acc += (DBL ? dG : G) * ss[kk];
+                    const R kr = k * r2 * ir;
+                    R sn, cs;
+                    vsincos(kr, &sn, &cs);
+                    cx<R> kv;
+                    if (DBL) {
+                        const R f = g * (d0 * snx[kk] + d1 * sny[kk] + d2 * snz[kk]) * ir * ir;
+                        kv = cx<R>(f * (cs + kr * sn), f * (sn - kr * cs));
+                    } else {
+                        kv = cx<R>(g * cs, g * sn);
+                    }
+                    acc += kv * ss[kk];
                 } else {
-                    R G, dG;
-                    green_laplace<R>(r2, rn, &G, &dG);
-                    acc += ss[kk] * (DBL ? dG : G);
+                    if (DBL) acc += ss[kk] * (g * (d0 * snx[kk] + d1 * sny[kk] + d2 * snz[kk]) * ir * ir);
+                    else acc += ss[kk] * g;
                 }
             }
+            total += vcast<VD>(acc);
             __syncthreads();
         }
     }
     // reduce over sub-streams of the wave (lanes tl, tl + tpw, ...)
     for (int o = 32; o >= tpw; o >>= 1) {
         if constexpr (HELM) {
-            acc.re += __shfl_xor(acc.re, o, 64);
-            acc.im += __shfl_xor(acc.im, o, 64);
+            total.re += __shfl_xor(total.re, o, 64);
+            total.im += __shfl_xor(total.im, o, 64);
         } else {
-            acc += __shfl_xor(acc, o, 64);
+            total += __shfl_xor(total, o, 64);
         }
     }
-    if (sub == 0) red[wave][tl] = acc;
+    if (sub == 0) red[wave][tl] = total;
     __syncthreads();
     if (tid < nt) {
-        V v = red[0][tid];
+        VD v = red[0][tid];
         for (int wv = 1; wv < P2P_BS / 64; wv++) v += red[wv][tid];
         V *dst = y + (int64_t)rhs * n_tgt + t0 + tid;
-        if (accumulate) *dst += v;
-        else *dst = v;
+        *dst = vcast<V>(vcast<VD>(*dst) + v);
     }
 }
 
@@ -551,6 +458,7 @@ void fmm_tables(bem_tree &t) {
     auto m32 = to32(m64), l32 = to32(l64);
     auto if32 = to32(invf);
     T->exps.alloc(&c, ex.size()); T->exps.upload(ex.data(), ex.size());
+    T->h_exps = ex;
     T->inv_fact64.alloc(&c, P2); T->inv_fact64.upload(invf.data(), P2);
     T->inv_fact32.alloc(&c, P2); T->inv_fact32.upload(if32.data(), P2);
     T->m2m_ptr.alloc(&c, P + 1); T->m2m_ptr.upload(mptr.data(), P + 1);
@@ -647,6 +555,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
     const int64_t nq = t.n_q, nt = t.n_tgt;
     Corr &cr = get_corr(t, HELM ? BEM_HELMHOLTZ : BEM_LAPLACE, k);
     if (op == BEM_OP_A) build_free_term(t);
+    M2lPlan *pl = method == BEM_FMM ? &get_m2l_plan(t, HELM ? BEM_HELMHOLTZ : BEM_LAPLACE, k) : nullptr;
     const R *q = std::is_same<R, float>::value ? (const R *)t.q32.p : (const R *)t.q64.p;
     const R *tg = std::is_same<R, float>::value ? (const R *)t.t32.p : (const R *)t.t64.p;
     // work buffers
@@ -694,16 +603,16 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         V *mom = (V *)t.work.mom.p, *loc = (V *)t.work.loc.p;
         const R *mc = std::is_same<R, float>::value ? (const R *)T.m2m_c32.p : (const R *)T.m2m_c64.p;
         const R *lc = std::is_same<R, float>::value ? (const R *)T.l2l_c32.p : (const R *)T.l2l_c64.p;
-        const R *invf = std::is_same<R, float>::value ? (const R *)T.inv_fact32.p : (const R *)T.inv_fact64.p;
         // upward pass (boxes without elements keep zero moments)
         BEM_HIP(hipMemsetAsync(mom, 0, sizeof(V) * nexp, c.stream));
         if (t.n_leaf_src) {
             dim3 g((unsigned)t.n_leaf_src, nrhs);
             size_t sh = sizeof(R) * 64 * 3 * (p + 1) + sizeof(V) * 64 + sizeof(R) * 64 * 3;
             if (dbl) k_p2m<V, R, true><<<g, 64, sh, c.stream>>>(t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p,
-                                                                 t.side, q, nq, s, p, T.exps.p, mom, t.n_box);
+                                                                 t.side, t.q64.p, q, nq, s, p, T.exps.p, mom,
+                                                                 t.n_box);
             else k_p2m<V, R, false><<<g, 64, sh, c.stream>>>(t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p,
-                                                              t.side, q, nq, s, p, T.exps.p, mom, t.n_box);
+                                                              t.side, t.q64.p, q, nq, s, p, T.exps.p, mom, t.n_box);
             BEM_LAUNCH_CHECK();
         }
         c.mark(1);
@@ -722,14 +631,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         // interactions
         BEM_HIP(hipMemsetAsync(loc, 0, sizeof(V) * nexp, c.stream));
         c.mark(9);
-        if (t.n_m2l_boxes) {
-            dim3 g((unsigned)t.n_m2l_boxes, (nrhs + M2L_NR - 1) / M2L_NR);
-            size_t sh = sizeof(V) * (2 * P2 + 2 * p + 1 + M2L_NR * P) + 3 * P2 + 16;
-            k_m2l<V, R, HELM><<<g, M2L_BS, sh, c.stream>>>(t.m2l_boxes.p, t.inter_ptr.p, t.inter_idx.p, t.level.p,
-                                                           t.centre.p, t.side, k, p, T.exps.p, invf, mom, loc,
-                                                           t.n_box, nrhs);
-            BEM_LAUNCH_CHECK();
-        }
+        m2l_apply<V, R>(t, *pl, nrhs, mom, loc);
         c.mark(3);
         // downward pass
         for (int l = 1; l <= t.max_level; l++) {
@@ -746,7 +648,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         if (t.n_leaf_tgt) {
             dim3 g((unsigned)t.n_leaf_tgt, nrhs);
             k_l2p<V, R><<<g, 64, sizeof(V) * P, c.stream>>>(t.tleaf_ids.p, t.tb.p, t.te.p, t.level.p, t.centre.p,
-                                                             t.side, tg, nt, p, loc, t.n_box, yacc);
+                                                             t.side, t.t64.p, nt, p, loc, t.n_box, yacc);
             BEM_LAUNCH_CHECK();
         }
         c.mark(5);
@@ -754,12 +656,12 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
             dim3 g((unsigned)t.n_p2p_items, nrhs);
             if (dbl)
                 k_p2p<V, R, true, HELM><<<g, P2P_BS, 0, c.stream>>>(t.p2p_box.p, t.p2p_t0.p, t.p2p_nt.p,
-                                                                    t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, q, nq,
-                                                                    s, tg, nt, (R)k, yacc, true);
+                                                                    t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p,
+                                                                    t.q64.p, q, nq, s, t.t64.p, nt, (R)k, yacc);
             else
                 k_p2p<V, R, false, HELM><<<g, P2P_BS, 0, c.stream>>>(t.p2p_box.p, t.p2p_t0.p, t.p2p_nt.p,
-                                                                     t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, q,
-                                                                     nq, s, tg, nt, (R)k, yacc, true);
+                                                                     t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p,
+                                                                     t.q64.p, q, nq, s, t.t64.p, nt, (R)k, yacc);
             BEM_LAUNCH_CHECK();
         }
         c.mark(6);

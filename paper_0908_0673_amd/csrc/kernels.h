@@ -44,15 +44,30 @@ struct FmmTables {
     DBuf<int16_t> l2l_src;
     DBuf<double> l2l_c64;
     DBuf<float> l2l_c32;
+    std::vector<int8_t> h_exps;
     DBuf<double> inv_fact64;  // [P2] 1 / alpha!
     DBuf<float> inv_fact32;
     int nnz_m2m = 0, nnz_l2l = 0;
 };
 
+// Displacement classes of the interaction pairs for one (Green, k) and their
+// derivative tables (multipole-to-local translation on the matrix cores).
+struct M2lPlan {
+    int green = -1;
+    double k = 0.0;
+    int64_t n_class = 0, n_task = 0, n_pairs = 0;
+    DBuf<double> D64;                 // [n_class][P2] (x2 interleaved when complex)
+    DBuf<float> D32;
+    DBuf<int32_t> cls_delta;          // level difference of the class
+    DBuf<int32_t> pair_list;          // interaction-list slots grouped by class
+    DBuf<int32_t> task_class, task_first, task_count;  // one wave each
+    DBuf<int16_t> key_of;
+    DBuf<int32_t> kbeta, kalpha;
+};
+
 // Per-matvec work buffers, grown on demand and kept on the tree.
 struct Work {
-    DBuf<char> strength, mom, loc, yacc;
-    DBuf<double> y64;
+    DBuf<char> strength, mom, loc, yacc, m2l_out;
 };
 
 }  // namespace bem
@@ -114,6 +129,8 @@ struct bem_tree {
     std::vector<int64_t> h_level_down;
 
     std::vector<std::unique_ptr<bem::Corr>> corr;
+    std::vector<std::unique_ptr<bem::M2lPlan>> m2l;
+    std::vector<uint64_t> h_prefix;
     bem::DBuf<double> free_term;  // [n_dof], DOF order
     bool has_free_term = false;
     std::unique_ptr<bem::FmmTables> tables;
@@ -147,6 +164,11 @@ void direct_regular_unit_double_layer(bem_tree &t, double *out);
 void fmm_tables(bem_tree &t);
 void plan_fmm(bem_tree &t);
 void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int nrhs, const void *x, void *y);
+
+// m2l.hip
+M2lPlan &get_m2l_plan(bem_tree &t, int green, double k);
+template <class V, class R>
+void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc);
 
 // solve.hip
 int solve(bem_tree &t, int green, double k, int nrhs, const void *chi, void *phi, const bem_solve_opts &o,
