@@ -56,153 +56,6 @@ __global__ void k_strength(const XV *x, int64_t n_dof, const int32_t *se_dofs, c
     s[(int64_t)rhs * n_q + i] = vcast<V>(acc) * wj[i];
 }
 
-// ---------------------------------------------------------------- P2M
-// one 64-thread block per source leaf; lanes own coefficients, points in batches of 64
-template <class V, class R, bool DBL>
-__global__ void k_p2m(const int32_t *boxes, const int64_t *eb, const int64_t *ee, const int32_t *level,
-                      const double *centre, double side, const double *q64, const R *q, int64_t n_q, const V *s,
-                      int p, const int8_t *exps, V *mom, int64_t n_box) {
-    extern __shared__ unsigned char smem[];
-    const int np1 = p + 1, P = ncoef(p);
-    R *pw = (R *)smem;                       // [64][3][np1]  u^k / k!
-    V *sv = (V *)(pw + 64 * 3 * np1);        // [64] strength (/rho for the double layer)
-    R *nv = (R *)(sv + 64);                  // [64][3] normals
-    const int b = boxes[blockIdx.x], rhs = blockIdx.y, lane = threadIdx.x;
-    const double rho = ldexp(side, -level[b]);
-    const R irho = (R)(1.0 / rho);
-    const double irho64 = 1.0 / rho;
-    const double cx0 = centre[3 * b], cx1 = centre[3 * b + 1], cx2 = centre[3 * b + 2];
-    constexpr int MAXC = 5;  // up to ncoef(10) = 286 coefficients per 64 lanes
-    V acc[MAXC];
-    int ea[MAXC][3];
-    for (int j = 0; j < MAXC; j++) {
-        acc[j] = V(0.0);
-        int a = lane + 64 * j;
-        if (a < P) { ea[j][0] = exps[3 * a]; ea[j][1] = exps[3 * a + 1]; ea[j][2] = exps[3 * a + 2]; }
-    }
-    const int64_t q0 = 7 * eb[b], q1 = 7 * ee[b];
-    const V *sr = s + (int64_t)rhs * n_q;
-    for (int64_t base = q0; base < q1; base += 64) {
-        int64_t qi = base + lane;
-        if (qi < q1) {
-            R u[3] = {(R)((q64[qi] - cx0) * irho64), (R)((q64[n_q + qi] - cx1) * irho64),
-                      (R)((q64[2 * n_q + qi] - cx2) * irho64)};
-            for (int d = 0; d < 3; d++) {
-                R v = 1;
-                pw[(lane * 3 + d) * np1] = v;
-                for (int k = 1; k <= p; k++) {
-                    v = v * u[d] / (R)k;
-                    pw[(lane * 3 + d) * np1 + k] = v;
-                }
-            }
-            V sq = sr[qi];
-            if (DBL) {
-                sq = sq * irho;
-                for (int d = 0; d < 3; d++) nv[3 * lane + d] = q[(4 + d) * n_q + qi];
-            }
-            sv[lane] = sq;
-        } else {
-            sv[lane] = V(0.0);
-            for (int d = 0; d < 3; d++) {
-                for (int k = 0; k <= p; k++) pw[(lane * 3 + d) * np1 + k] = 0;
-                nv[3 * lane + d] = 0;
-            }
-        }
-        __syncthreads();
-        int nb = (int)min<int64_t>(64, q1 - base);
-        for (int j = 0; j < MAXC; j++) {
-            int a = lane + 64 * j;
-            if (a >= P) break;
-            const int e0 = ea[j][0], e1 = ea[j][1], e2 = ea[j][2];
-            V m = acc[j];
-            for (int i = 0; i < nb; i++) {
-                const R *px = pw + (i * 3) * np1, *py = px + np1, *pz = py + np1;
-                R mono;
-                if (!DBL) {
-                    mono = px[e0] * py[e1] * pz[e2];
-                } else {
-                    mono = 0;
-                    if (e0) mono += nv[3 * i] * px[e0 - 1] * py[e1] * pz[e2];
-                    if (e1) mono += nv[3 * i + 1] * px[e0] * py[e1 - 1] * pz[e2];
-                    if (e2) mono += nv[3 * i + 2] * px[e0] * py[e1] * pz[e2 - 1];
-                }
-                m += sv[i] * mono;
-            }
-            acc[j] = m;
-        }
-        __syncthreads();
-    }
-    V *out = mom + ((int64_t)rhs * n_box + b) * P;
-    for (int j = 0; j < MAXC; j++) {
-        int a = lane + 64 * j;
-        if (a < P) out[a] = acc[j];
-    }
-}
-
-// ---------------------------------------------------------------- M2M / L2L
-// out[box] (+)= sum over inputs of table(octant) . in ; threads own target coefficients.
-// M2M: boxes are parents, inputs their children (octant = child prefix & 7).
-// L2L: boxes are children, the input is the parent (octant = own prefix & 7).
-template <class V, class R, bool UP>
-__global__ void k_shift(const int32_t *boxes, const int32_t *parent, const int32_t *child_begin, const int32_t *nchild,
-                        const uint64_t *prefix, int P, const int32_t *ptr, const int16_t *src, const R *coef, int nnz,
-                        V *buf, int64_t n_box) {
-    extern __shared__ unsigned char smem[];
-    V *in = (V *)smem;
-    const int b = boxes[blockIdx.x], rhs = blockIdx.y;
-    V *base = buf + (int64_t)rhs * n_box * P;
-    V acc = V(0.0);
-    const int a = threadIdx.x;
-    int ninp = UP ? nchild[b] : 1;
-    for (int c = 0; c < ninp; c++) {
-        int from = UP ? child_begin[b] + c : parent[b];
-        int oct = (int)((UP ? prefix[from] : prefix[b]) & 7u);
-        for (int j = threadIdx.x; j < P; j += blockDim.x) in[j] = base[(int64_t)from * P + j];
-        __syncthreads();
-        if (a < P) {
-            const R *cf = coef + (int64_t)oct * nnz;
-            for (int t = ptr[a]; t < ptr[a + 1]; t++) acc += in[src[t]] * cf[t];
-        }
-        __syncthreads();
-    }
-    if (a < P) {
-        if (UP) base[(int64_t)b * P + a] = acc;
-        else base[(int64_t)b * P + a] += acc;
-    }
-}
-
-// ---------------------------------------------------------------- L2P
-template <class V, class R>
-__global__ void k_l2p(const int32_t *boxes, const int64_t *tb, const int64_t *te, const int32_t *level,
-                      const double *centre, double side, const double *t, int64_t n_tgt, int p, const V *loc,
-                      int64_t n_box, V *y) {
-    extern __shared__ unsigned char smem[];
-    V *F = (V *)smem;
-    const int b = boxes[blockIdx.x], rhs = blockIdx.y, P = ncoef(p);
-    for (int j = threadIdx.x; j < P; j += blockDim.x) F[j] = loc[((int64_t)rhs * n_box + b) * P + j];
-    __syncthreads();
-    const double irho = 1.0 / ldexp(side, -level[b]);
-    for (int64_t i = tb[b] + threadIdx.x; i < te[b]; i += blockDim.x) {
-        R u0 = (R)((t[i] - centre[3 * b]) * irho), u1 = (R)((t[n_tgt + i] - centre[3 * b + 1]) * irho),
-          u2 = (R)((t[2 * n_tgt + i] - centre[3 * b + 2]) * irho);
-        V acc = V(0.0);
-        R xa = 1;
-        for (int a = 0; a <= p; a++) {
-            R xab = xa;
-            for (int bb = 0; bb <= p - a; bb++) {
-                R xabc = xab;
-                for (int c = 0; c <= p - a - bb; c++) {
-                    acc += F[midx(a, bb, c)] * xabc;
-                    xabc *= u2;
-                }
-                xab *= u1;
-            }
-            xa *= u0;
-        }
-        y[(int64_t)rhs * n_tgt + i] = acc;
-    }
-}
-
 // ---------------------------------------------------------------- P2P
 constexpr int P2P_BS = 256;
 constexpr int P2P_TILE = 256;
@@ -211,111 +64,167 @@ constexpr int P2P_CH = 256;  // near-list entries per chunk
 __device__ inline float inv_sqrt(float v) { return rsqrtf(v); }
 __device__ inline double inv_sqrt(double v) { return 1.0 / sqrt(v); }
 
+template <class R> struct r4;
+template <> struct r4<float> { using type = float4; };
+template <> struct r4<double> { using type = double4; };
+
+// Kernel value times strength for one (target, source point) pair.  For
+// Laplace the source record holds (s n, s) and the 1/(4 pi) factor is applied
+// once per target by the caller; for Helmholtz it holds (n, Re s) plus Im s.
+template <class V, class R, bool DBL, bool HELM>
+__device__ inline V p2p_term(double x0, double x1, double x2, double2 sxy, double sz, typename r4<R>::type ns, R si,
+                             R k) {
+    const R d0 = (R)(x0 - sxy.x), d1 = (R)(x1 - sxy.y), d2 = (R)(x2 - sz);
+    const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const R ir = inv_sqrt(r2);
+    if constexpr (HELM) {
+        R g = (R)kInv4Pi * ir;
+        if (DBL) g = g * (d0 * ns.x + d1 * ns.y + d2 * ns.z) * ir * ir;
+        const R kr = k * r2 * ir;
+        R sn, cs;
+        vsincos(kr, &sn, &cs);
+        cx<R> kv = DBL ? cx<R>(g * (cs + kr * sn), g * (sn - kr * cs)) : cx<R>(g * cs, g * sn);
+        return kv * cx<R>(ns.w, si);
+    } else {
+        if (DBL) return V((d0 * ns.x + d1 * ns.y + d2 * ns.z) * (ir * ir * ir));
+        return V(ns.w * ir);
+    }
+}
+
 // One block per work item (a target leaf and up to 64 of its targets).  The
-// near-list boxes' points are streamed through LDS tiles; each wave takes a
-// quarter of a tile, its lanes split into (target, sub-stream) pairs.  The
-// target-source difference is formed in FP64 (the coordinates are FP64) and
-// only then rounded to R, so that close pairs keep their relative accuracy in
-// the mixed path; per-tile partial sums in R are added into an FP64 total.
+// near-list boxes' points (contiguous runs in tree order) are split into four
+// equal shares, one per wave; each wave streams its share in batches of 64
+// points, one per lane, through its own LDS slot as packed records (FP64
+// position, normal and strength in R), loading the next batch into registers
+// while it computes the current one, so no block barrier sits inside the
+// loop.  Each lane holds two targets, so every LDS read serves two
+// interactions; lanes not needed for targets split a batch into sub-streams.
+// The target-source difference is formed in FP64 and only then rounded to R,
+// so close pairs keep their relative accuracy in the mixed path; per-batch
+// partial sums in R are added into an FP64 total.
 template <class V, class R, bool DBL, bool HELM>
 __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *wi_box, const int32_t *wi_t0, const int32_t *wi_nt,
                                                 const int64_t *nptr, const int32_t *nidx, const int64_t *eb,
                                                 const int64_t *ee, const double *q64, const R *q, int64_t n_q,
                                                 const V *s, const double *t64, int64_t n_tgt, R k, V *y) {
     using VD = typename std::conditional<HELM, cx<double>, double>::type;
+    using R4 = typename r4<R>::type;
+    constexpr int NW = P2P_BS / 64;
     __shared__ int64_t pref[P2P_CH + 1];
     __shared__ int64_t qbeg[P2P_CH];
-    __shared__ double sx[P2P_TILE], sy[P2P_TILE], sz[P2P_TILE];
-    __shared__ R snx[DBL ? P2P_TILE : 1], sny[DBL ? P2P_TILE : 1], snz[DBL ? P2P_TILE : 1];
-    __shared__ V ss[P2P_TILE];
-    __shared__ VD red[P2P_BS / 64][64];
+    __shared__ double2 sxy[NW][2][64];
+    __shared__ double szz[NW][2][64];
+    __shared__ R4 sns[NW][2][64];
+    __shared__ R ssi[NW][2][HELM ? 64 : 1];
+    __shared__ VD red[NW][64];
     const int w = blockIdx.x, rhs = blockIdx.y;
     const int b = wi_box[w], t0 = wi_t0[w], nt = wi_nt[w];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int npair = (nt + 1) >> 1;  // lanes needed, two targets each
     int tpw = 1;
-    while (tpw < nt) tpw <<= 1;
+    while (tpw < npair) tpw <<= 1;
     const int nsub = 64 / tpw, tl = lane % tpw, sub = lane / tpw;
-    const int64_t ti = t0 + (tl < nt ? tl : 0);
-    const double x0 = t64[ti], x1 = t64[n_tgt + ti], x2 = t64[2 * n_tgt + ti];
+    const int ta = min(2 * tl, nt - 1), tb2 = min(2 * tl + 1, nt - 1);
+    const double xa0 = t64[t0 + ta], xa1 = t64[n_tgt + t0 + ta], xa2 = t64[2 * n_tgt + t0 + ta];
+    const double xb0 = t64[t0 + tb2], xb1 = t64[n_tgt + t0 + tb2], xb2 = t64[2 * n_tgt + t0 + tb2];
     const V *sr = s + (int64_t)rhs * n_q;
-    VD total = VD(0.0);
+    VD tot_a = VD(0.0), tot_b = VD(0.0);
     const int64_t j0 = nptr[b], j1 = nptr[b + 1];
     for (int64_t cb = j0; cb < j1; cb += P2P_CH) {
         const int nc = (int)min<int64_t>(P2P_CH, j1 - cb);
-        if (tid < nc) {
-            int32_t nb_ = nidx[cb + tid];
-            qbeg[tid] = 7 * eb[nb_];
-            pref[tid + 1] = 7 * (ee[nb_] - eb[nb_]);
-        }
-        if (tid == 0) pref[0] = 0;
-        __syncthreads();
-        if (tid == 0)
-            for (int i = 1; i <= nc; i++) pref[i] += pref[i - 1];
-        __syncthreads();
-        const int64_t total_pts = pref[nc];
-        for (int64_t tb0 = 0; tb0 < total_pts; tb0 += P2P_TILE) {
-            const int64_t f = tb0 + tid;
-            if (f < total_pts) {
-                int lo = 0, hi = nc - 1;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (pref[mid] <= f) lo = mid; else hi = mid - 1;
+        // run lengths of the chunk's near-list boxes, scanned by the first wave
+        if (tid < 64) {
+            int64_t carry = 0;
+            for (int base = 0; base < nc; base += 64) {
+                const int i = base + lane;
+                int64_t len = 0;
+                if (i < nc) {
+                    const int32_t nb_ = nidx[cb + i];
+                    qbeg[i] = 7 * eb[nb_];
+                    len = 7 * (ee[nb_] - eb[nb_]);
                 }
-                const int64_t qi = qbeg[lo] + (f - pref[lo]);
-                sx[tid] = q64[qi];
-                sy[tid] = q64[n_q + qi];
-                sz[tid] = q64[2 * n_q + qi];
-                if (DBL) {
-                    snx[tid] = q[4 * n_q + qi];
-                    sny[tid] = q[5 * n_q + qi];
-                    snz[tid] = q[6 * n_q + qi];
+                int64_t incl = len;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int64_t u = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += u;
                 }
-                ss[tid] = sr[qi];
+                if (i < nc) pref[i + 1] = carry + incl;
+                carry += __shfl(incl, 63, 64);
             }
-            __syncthreads();
-            const int nin = (int)min<int64_t>(P2P_TILE, total_pts - tb0);
-            const int kb = wave * 64, ke = min(nin, kb + 64);
-            V acc = V(0.0);
-            for (int kk = kb + sub; kk < ke; kk += nsub) {
-                const R d0 = (R)(x0 - sx[kk]), d1 = (R)(x1 - sy[kk]), d2 = (R)(x2 - sz[kk]);
-                const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                const R ir = inv_sqrt(r2);
-                const R g = (R)kInv4Pi * ir;
-                if constexpr (HELM) {
-                    const R kr = k * r2 * ir;
-                    R sn, cs;
-                    vsincos(kr, &sn, &cs);
-                    cx<R> kv;
-                    if (DBL) {
-                        const R f = g * (d0 * snx[kk] + d1 * sny[kk] + d2 * snz[kk]) * ir * ir;
-                        kv = cx<R>(f * (cs + kr * sn), f * (sn - kr * cs));
-                    } else {
-                        kv = cx<R>(g * cs, g * sn);
-                    }
-                    acc += kv * ss[kk];
-                } else {
-                    if (DBL) acc += ss[kk] * (g * (d0 * snx[kk] + d1 * sny[kk] + d2 * snz[kk]) * ir * ir);
-                    else acc += ss[kk] * g;
-                }
-            }
-            total += vcast<VD>(acc);
-            __syncthreads();
+            if (lane == 0) pref[0] = 0;
         }
+        __syncthreads();
+        const int64_t total = pref[nc];
+        // this wave's share of the chunk's points
+        const int64_t per = (total + NW - 1) / NW;
+        const int64_t f0 = min(total, per * wave), f1 = min(total, f0 + per);
+        int e = 0;  // run holding this lane's current point
+        auto fetch = [&](int64_t f, double2 &pxy, double &pz, R4 &ns, R &si) {
+            if (f < f1) {
+                while (pref[e + 1] <= f) e++;
+                const int64_t qi = qbeg[e] + (f - pref[e]);
+                pxy = make_double2(q64[qi], q64[n_q + qi]);
+                pz = q64[2 * n_q + qi];
+                const V sv = sr[qi];
+                ns.w = re_part(sv);
+                const R sc = HELM ? (R)1 : ns.w;  // Laplace: strength folded into the normal
+                ns.x = DBL ? q[4 * n_q + qi] * sc : (R)0;
+                ns.y = DBL ? q[5 * n_q + qi] * sc : (R)0;
+                ns.z = DBL ? q[6 * n_q + qi] * sc : (R)0;
+                if constexpr (HELM) si = sv.im;
+            }
+        };
+        double2 pxy = make_double2(0.0, 0.0);
+        double pz = 0.0;
+        R4 ns = {0, 0, 0, 0};
+        R si = 0;
+        fetch(f0 + lane, pxy, pz, ns, si);
+        int buf = 0;
+        for (int64_t fb = f0; fb < f1; fb += 64) {
+            sxy[wave][buf][lane] = pxy;
+            szz[wave][buf][lane] = pz;
+            sns[wave][buf][lane] = ns;
+            if constexpr (HELM) ssi[wave][buf][lane] = si;
+            __builtin_amdgcn_wave_barrier();
+            fetch(fb + 64 + lane, pxy, pz, ns, si);  // next batch in flight while this one is computed
+            const int nin = (int)min<int64_t>(64, f1 - fb);
+            V acc_a = V(0.0), acc_b = V(0.0);
+#pragma unroll 4
+            for (int kk = sub; kk < nin; kk += nsub) {
+                const double2 cxy = sxy[wave][buf][kk];
+                const double cz = szz[wave][buf][kk];
+                const R4 cns = sns[wave][buf][kk];
+                const R csi = HELM ? ssi[wave][buf][kk] : (R)0;
+                acc_a += p2p_term<V, R, DBL, HELM>(xa0, xa1, xa2, cxy, cz, cns, csi, k);
+                acc_b += p2p_term<V, R, DBL, HELM>(xb0, xb1, xb2, cxy, cz, cns, csi, k);
+            }
+            tot_a += vcast<VD>(acc_a);
+            tot_b += vcast<VD>(acc_b);
+            buf ^= 1;
+        }
+        __syncthreads();  // pref / qbeg are rewritten by the next chunk
     }
     // reduce over sub-streams of the wave (lanes tl, tl + tpw, ...)
     for (int o = 32; o >= tpw; o >>= 1) {
         if constexpr (HELM) {
-            total.re += __shfl_xor(total.re, o, 64);
-            total.im += __shfl_xor(total.im, o, 64);
+            tot_a.re += __shfl_xor(tot_a.re, o, 64);
+            tot_a.im += __shfl_xor(tot_a.im, o, 64);
+            tot_b.re += __shfl_xor(tot_b.re, o, 64);
+            tot_b.im += __shfl_xor(tot_b.im, o, 64);
         } else {
-            total += __shfl_xor(total, o, 64);
+            tot_a += __shfl_xor(tot_a, o, 64);
+            tot_b += __shfl_xor(tot_b, o, 64);
         }
     }
-    if (sub == 0) red[wave][tl] = total;
+    if (sub == 0) {
+        red[wave][2 * tl] = tot_a;
+        if (2 * tl + 1 < 64) red[wave][2 * tl + 1] = tot_b;
+    }
     __syncthreads();
     if (tid < nt) {
         VD v = red[0][tid];
-        for (int wv = 1; wv < P2P_BS / 64; wv++) v += red[wv][tid];
+        for (int wv = 1; wv < NW; wv++) v += red[wv][tid];
+        if constexpr (!HELM) v = v * kInv4Pi;
         V *dst = y + (int64_t)rhs * n_tgt + t0 + tid;
         *dst = vcast<V>(vcast<VD>(*dst) + v);
     }
@@ -520,18 +429,35 @@ void plan_fmm(bem_tree &t) {
         t.n_p2p_pairs += ns * (t.h_te[b] - t.h_tb[b]);
     }
     t.m2m_level_boxes.assign(t.max_level + 1, {});
+    t.l2l_level_boxes.assign(t.max_level + 1, {});
     t.d_m2m_level_boxes.clear();
+    t.d_l2l_level_boxes.clear();
     t.d_level_boxes.clear();
     for (int l = 0; l <= t.max_level; l++) {
-        std::vector<int32_t> up, down;
+        std::vector<int32_t> up, down, par;
         for (int64_t b = t.level_off[l]; b < t.level_off[l + 1]; b++) {
             if (!t.h_leaf[b]) up.push_back((int32_t)b);
             if (l > 0 && t.h_te[b] > t.h_tb[b]) down.push_back((int32_t)b);
+            if (!t.h_leaf[b] && t.h_te[b] > t.h_tb[b]) par.push_back((int32_t)b);
         }
         t.m2m_level_boxes[l] = up;
+        t.l2l_level_boxes[l] = par;
         t.d_m2m_level_boxes.push_back(upload_i32(c, up));
+        t.d_l2l_level_boxes.push_back(upload_i32(c, par));
         t.d_level_boxes.push_back(upload_i32(c, down));
         t.h_level_down.push_back((int64_t)down.size());
+    }
+    // levels the upward and downward passes can skip
+    {
+        int src_min = t.max_level + 1, tgt_min = t.max_level + 1;
+        for (int64_t b = 0; b < t.n_box; b++) {
+            if (t.h_te[b] == t.h_tb[b]) continue;
+            if (t.h_inter_ptr[b + 1] > t.h_inter_ptr[b]) tgt_min = std::min(tgt_min, (int)t.h_level[b]);
+            for (int64_t j = t.h_inter_ptr[b]; j < t.h_inter_ptr[b + 1]; j++)
+                src_min = std::min(src_min, (int)t.h_level[t.h_inter_idx[j]]);
+        }
+        t.m2m_top = std::min(src_min, t.max_level);
+        t.l2l_top = std::min(tgt_min, t.max_level);
     }
     c.sync();
     t.planned = true;
@@ -576,6 +502,11 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         t.L7.alloc(&c, 42);
         t.L7.upload(L7.data(), 42);
     }
+    if (method == BEM_FMM) {
+        fmm_tables(t);
+        plan_fmm(t);
+        build_pass_tables(t);
+    }
     c.mark(9);
     dim3 gs(nblocks(nq, 256), nrhs);
     k_strength<V, R, XV><<<gs, 256, 0, c.stream>>>(x, nt, t.se_dofs.p, q + 3 * nq, nq, t.L7.p, s);
@@ -593,40 +524,17 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
             fail(BEM_EUNSUPPORTED, "the direct product runs in FP64 only");
         }
     } else {
-        fmm_tables(t);
-        plan_fmm(t);
         FmmTables &T = *t.tables;
-        const int p = t.order, P = T.P, P2 = T.P2;
+        const int P = T.P;
         const size_t nexp = (size_t)t.n_box * P * nrhs;
         t.work.mom.ensure(&c, sizeof(V) * nexp);
         t.work.loc.ensure(&c, sizeof(V) * nexp);
         V *mom = (V *)t.work.mom.p, *loc = (V *)t.work.loc.p;
-        const R *mc = std::is_same<R, float>::value ? (const R *)T.m2m_c32.p : (const R *)T.m2m_c64.p;
-        const R *lc = std::is_same<R, float>::value ? (const R *)T.l2l_c32.p : (const R *)T.l2l_c64.p;
         // upward pass (boxes without elements keep zero moments)
         BEM_HIP(hipMemsetAsync(mom, 0, sizeof(V) * nexp, c.stream));
-        if (t.n_leaf_src) {
-            dim3 g((unsigned)t.n_leaf_src, nrhs);
-            size_t sh = sizeof(R) * 64 * 3 * (p + 1) + sizeof(V) * 64 + sizeof(R) * 64 * 3;
-            if (dbl) k_p2m<V, R, true><<<g, 64, sh, c.stream>>>(t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p,
-                                                                 t.side, t.q64.p, q, nq, s, p, T.exps.p, mom,
-                                                                 t.n_box);
-            else k_p2m<V, R, false><<<g, 64, sh, c.stream>>>(t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p,
-                                                              t.side, t.q64.p, q, nq, s, p, T.exps.p, mom, t.n_box);
-            BEM_LAUNCH_CHECK();
-        }
+        p2m_apply<V, R, XV>(t, dbl, nrhs, x, mom);
         c.mark(1);
-        const int sbs = P <= 64 ? 64 : (P <= 128 ? 128 : (P <= 192 ? 192 : 320));
-        for (int l = t.max_level - 1; l >= 0; l--) {
-            int64_t nb = (int64_t)t.m2m_level_boxes[l].size();
-            if (!nb) continue;
-            dim3 g((unsigned)nb, nrhs);
-            k_shift<V, R, true><<<g, sbs, sizeof(V) * P, c.stream>>>(t.d_m2m_level_boxes[l].p, t.parent.p,
-                                                                       t.child_begin.p, t.nchild.p, t.prefix.p, P,
-                                                                       T.m2m_ptr.p, T.m2m_src.p, mc, T.nnz_m2m, mom,
-                                                                       t.n_box);
-            BEM_LAUNCH_CHECK();
-        }
+        m2m_apply<V, R>(t, nrhs, mom);
         c.mark(2);
         // interactions
         BEM_HIP(hipMemsetAsync(loc, 0, sizeof(V) * nexp, c.stream));
@@ -634,23 +542,9 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         m2l_apply<V, R>(t, *pl, nrhs, mom, loc);
         c.mark(3);
         // downward pass
-        for (int l = 1; l <= t.max_level; l++) {
-            int64_t nb = t.h_level_down[l];
-            if (!nb) continue;
-            dim3 g((unsigned)nb, nrhs);
-            k_shift<V, R, false><<<g, sbs, sizeof(V) * P, c.stream>>>(t.d_level_boxes[l].p, t.parent.p,
-                                                                        t.child_begin.p, t.nchild.p, t.prefix.p, P,
-                                                                        T.l2l_ptr.p, T.l2l_src.p, lc, T.nnz_l2l, loc,
-                                                                        t.n_box);
-            BEM_LAUNCH_CHECK();
-        }
+        l2l_apply<V, R>(t, nrhs, loc);
         c.mark(4);
-        if (t.n_leaf_tgt) {
-            dim3 g((unsigned)t.n_leaf_tgt, nrhs);
-            k_l2p<V, R><<<g, 64, sizeof(V) * P, c.stream>>>(t.tleaf_ids.p, t.tb.p, t.te.p, t.level.p, t.centre.p,
-                                                             t.side, t.t64.p, nt, p, loc, t.n_box, yacc);
-            BEM_LAUNCH_CHECK();
-        }
+        l2p_apply<V, R>(t, nrhs, loc, yacc);
         c.mark(5);
         if (t.n_p2p_items) {
             dim3 g((unsigned)t.n_p2p_items, nrhs);

@@ -61,8 +61,20 @@ struct M2lPlan {
     DBuf<int32_t> cls_delta;          // level difference of the class
     DBuf<int32_t> pair_list;          // interaction-list slots grouped by class
     DBuf<int32_t> task_class, task_first, task_count;  // one wave each
-    DBuf<int16_t> key_of;
-    DBuf<int32_t> kbeta, kalpha;
+    DBuf<int32_t> pk;  // packed multi-indices of the contraction rows
+};
+
+// Stored P2M weights (per source leaf and DOF, single and double layer) and
+// L2P target monomials; geometry only, built once per tree.
+struct PassTables {
+    bool built = false;
+    int64_t n_w = 0;
+    DBuf<int64_t> woff;   // [n_leaf_src + 1]
+    DBuf<int32_t> wdof;   // [n_w] DOF of each weight row
+    DBuf<double> W64[2];  // [n_w][P], index 0 single layer, 1 double layer
+    DBuf<float> W32[2];
+    DBuf<double> U64;     // per target leaf [P][nt] blocks
+    DBuf<float> U32;
 };
 
 // Per-matvec work buffers, grown on demand and kept on the tree.
@@ -116,7 +128,14 @@ struct bem_tree {
     int64_t n_m2l_boxes = 0;
     std::vector<std::vector<int32_t>> m2m_level_boxes;  // non-leaf boxes per level
     std::vector<bem::DBuf<int32_t>> d_m2m_level_boxes;
-    std::vector<bem::DBuf<int32_t>> d_level_boxes;      // all boxes per level (L2L)
+    std::vector<bem::DBuf<int32_t>> d_level_boxes;      // boxes with targets per level
+    std::vector<std::vector<int32_t>> l2l_level_boxes;  // non-leaf boxes with targets per level
+    std::vector<bem::DBuf<int32_t>> d_l2l_level_boxes;
+    bem::PassTables pass;
+    // coarsest level whose moments are read (as an interaction source, directly
+    // or through a coarser source) and coarsest level holding a non-zero local
+    // expansion: M2M stops at the first, L2L starts at the second
+    int m2m_top = 0, l2l_top = 0;
 
     // (target, element) pairs needing the singular / near-singular rules: CSR by sorted target
     bool has_pairs = false;
@@ -164,6 +183,17 @@ void direct_regular_unit_double_layer(bem_tree &t, double *out);
 void fmm_tables(bem_tree &t);
 void plan_fmm(bem_tree &t);
 void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int nrhs, const void *x, void *y);
+
+// passes.hip
+void build_pass_tables(bem_tree &t);
+template <class V, class R, class XV>
+void p2m_apply(bem_tree &t, bool dbl, int nrhs, const XV *x, V *mom);
+template <class V, class R>
+void m2m_apply(bem_tree &t, int nrhs, V *mom);
+template <class V, class R>
+void l2l_apply(bem_tree &t, int nrhs, V *loc);
+template <class V, class R>
+void l2p_apply(bem_tree &t, int nrhs, const V *loc, V *y);
 
 // m2l.hip
 M2lPlan &get_m2l_plan(bem_tree &t, int green, double k);

@@ -37,7 +37,6 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-constexpr int KEYS = 17 * 17 * 17;  // packed keys a*289 + b*17 + c for components <= 16
 constexpr int MT = 11;              // 176 / 16 output row tiles (P = 165 at order 8)
 constexpr int KT = 42;              // 168 / 4 contraction steps
 
@@ -127,115 +126,156 @@ __global__ void k_class_derivs(const double *rbar, const double *kbar, int H, co
 
 struct M2lArgs {
     const int32_t *task_class, *task_first, *task_count, *pair_list, *inter_idx, *level, *cls_delta;
-    const int16_t *key_of;       // [P2] packed key of each multi-index
-    const int32_t *kbeta;        // [MT*16] packed key of each output row (0 for padding)
-    const int32_t *kalpha;       // [KT*4] packed key of each contraction index (0 for padding)
-    const int8_t *exps;
+    const int32_t *pk;           // [KT*4] packed multi-index a | b << 5 | c << 10 (0 for padding)
     double side;
     int P, P2;
     int64_t n_box, n_inter;
 };
 
-// Real values: one wave per task of up to 16 pairs of one class.
+constexpr int M2L_WAVES = 4;
+constexpr int OUT_LD = MT * 16;  // row stride of the per-pair outputs (176)
+
+// index of the multi-index sum of two packed multi-indices (graded order)
+__device__ inline int sum_index(int packed) {
+    const int a = packed & 31, b = (packed >> 5) & 31, c = packed >> 10;
+    const int n = a + b + c, m = n - a;
+    return (n * (n + 1) * (n + 2)) / 6 + ((m * (m + 1)) >> 1) + (m - b);
+}
+
+// Real values: a block of four waves takes one class and up to 64 of its
+// pairs, 16 per wave; the class table is shared by the waves.
 template <class R>
-__global__ void __launch_bounds__(64) k_m2l_mfma(M2lArgs a, const R *D, const R *inv_fact, const R *mom, R *out) {
+__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_mfma(M2lArgs a, const R *D, const R *inv_fact, const R *mom,
+                                                             R *out) {
     using V4 = typename vec4<R>::type;
-    __shared__ R Dk[KEYS];
-    __shared__ R Ms[KT * 4 * 16];
-    const int lane = threadIdx.x, task = blockIdx.x;
-    const int c = a.task_class[task], first = a.task_first[task], cnt = a.task_count[task];
+    extern __shared__ unsigned char smem[];
     const int P = a.P, P2 = a.P2;
-    for (int i = lane; i < P2; i += 64) Dk[a.key_of[i]] = D[(int64_t)c * P2 + i];
-    for (int col = 0; col < 16; col++) {
-        if (col < cnt) {
-            const int j = a.pair_list[first + col];
-            const int s = a.inter_idx[j];
-            const R scale = (R)ldexp(1.0 / a.side, a.level[s]);
-            const R *ms = mom + (int64_t)s * P;
-            for (int al = lane; al < KT * 4; al += 64) {
-                R v = 0;
-                if (al < P) {
-                    int na = a.exps[3 * al] + a.exps[3 * al + 1] + a.exps[3 * al + 2];
-                    v = ms[al] * ((na & 1) ? -scale : scale);
-                }
-                Ms[al * 16 + col] = v;
-            }
-        } else {
-            for (int al = lane; al < KT * 4; al += 64) Ms[al * 16 + col] = 0;
+    R *Dc = (R *)smem;                         // [P2]
+    R *rs = Dc + P2;                           // [OUT_LD] row scales of the class
+    int *pk = (int *)(rs + OUT_LD);            // [KT*4]
+    R *MsAll = (R *)(pk + KT * 4);             // [waves][KT*4][16]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, task = blockIdx.x;
+    const int c = a.task_class[task], first = a.task_first[task], cnt = a.task_count[task];
+    const int delta = a.cls_delta[c];
+    for (int i = tid; i < P2; i += blockDim.x) Dc[i] = D[(int64_t)c * P2 + i];
+    for (int i = tid; i < KT * 4; i += blockDim.x) pk[i] = a.pk[i];
+    for (int i = tid; i < OUT_LD; i += blockDim.x) {
+        R v = 0;
+        if (i < P) {
+            const int q = a.pk[i], nb = (q & 31) + ((q >> 5) & 31) + (q >> 10);
+            v = inv_fact[i] * (R)ldexp(1.0, -delta * nb);
         }
+        rs[i] = v;
     }
     __syncthreads();
+    const int wfirst = first + 16 * wave, wcnt = min(16, cnt - 16 * wave);
+    if (wcnt <= 0) return;
+    R *Ms = MsAll + wave * (KT * 4 * 16);
+    // sources and scales of the wave's columns, fetched in parallel
+    int my_s = -1;
+    R my_scale = 0;
+    if (lane < wcnt) {
+        my_s = a.inter_idx[a.pair_list[wfirst + lane]];
+        my_scale = (R)ldexp(1.0 / a.side, a.level[my_s]);
+    }
+#pragma unroll 4
+    for (int col = 0; col < 16; col++) {
+        const int s = __shfl(my_s, col, 64);
+        const R scale = __shfl(my_scale, col, 64);
+        for (int al = lane; al < KT * 4; al += 64) {
+            R v = 0;
+            if (s >= 0 && al < P) {
+                const int q = pk[al], na = (q & 31) + ((q >> 5) & 31) + (q >> 10);
+                v = mom[(int64_t)s * P + al] * ((na & 1) ? -scale : scale);
+            }
+            Ms[al * 16 + col] = v;
+        }
+    }
+    // each wave reads only the staging area it wrote: no block barrier is needed
+    __builtin_amdgcn_wave_barrier();
     const int row = lane & 15, kq = lane >> 4;
-    int kb[MT];
-    for (int mt = 0; mt < MT; mt++) kb[mt] = a.kbeta[16 * mt + row];
+    int pb[MT];
+    for (int mt = 0; mt < MT; mt++) pb[mt] = pk[min(16 * mt + row, KT * 4 - 1)] * (16 * mt + row < P ? 1 : 0);
     V4 acc[MT];
     for (int mt = 0; mt < MT; mt++) acc[mt] = V4{0, 0, 0, 0};
-#pragma unroll 2
     for (int kt = 0; kt < KT; kt++) {
         const int al = 4 * kt + kq;
-        const int ka = a.kalpha[al];
+        const int pa = pk[al];
         const R bv = Ms[al * 16 + row];
 #pragma unroll
-        for (int mt = 0; mt < MT; mt++) acc[mt] = mfma(Dk[kb[mt] + ka], bv, acc[mt]);
+        for (int mt = 0; mt < MT; mt++) acc[mt] = mfma(Dc[sum_index(pb[mt] + pa)], bv, acc[mt]);
     }
     const int col = row;
-    if (col < cnt) {
-        const int j = a.pair_list[first + col];
-        const int delta = a.cls_delta[c];
-        R *o = out + (int64_t)j * P;
+    if (col < wcnt) {
+        const int j = a.pair_list[wfirst + col];
+        R *o = out + (int64_t)j * OUT_LD;
         for (int mt = 0; mt < MT; mt++)
             for (int r = 0; r < 4; r++) {
                 const int b = 16 * mt + crow(R(0), kq, r);
-                if (b < P) {
-                    const int nb = a.exps[3 * b] + a.exps[3 * b + 1] + a.exps[3 * b + 2];
-                    o[b] = acc[mt][r] * inv_fact[b] * (R)ldexp(1.0, -delta * nb);
-                }
+                o[b] = acc[mt][r] * rs[b];
             }
     }
 }
 
-// Complex values: 8 pairs per task, real and imaginary parts as 16 real columns.
+// Complex values: 8 pairs per wave, real and imaginary parts as 16 real columns.
 template <class R>
-__global__ void __launch_bounds__(64) k_m2l_mfma_cx(M2lArgs a, const R *D /* interleaved */, const R *inv_fact,
-                                                   const cx<R> *mom, cx<R> *out) {
+__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_mfma_cx(M2lArgs a, const R *D /* interleaved */,
+                                                                const R *inv_fact, const cx<R> *mom, cx<R> *out) {
     using V4 = typename vec4<R>::type;
-    __shared__ R Dr[KEYS], Di[KEYS];
-    __shared__ R Ms[KT * 4 * 16];
-    const int lane = threadIdx.x, task = blockIdx.x;
-    const int c = a.task_class[task], first = a.task_first[task], cnt = a.task_count[task];
+    extern __shared__ unsigned char smem[];
     const int P = a.P, P2 = a.P2;
-    for (int i = lane; i < P2; i += 64) {
-        Dr[a.key_of[i]] = D[2 * ((int64_t)c * P2 + i)];
-        Di[a.key_of[i]] = D[2 * ((int64_t)c * P2 + i) + 1];
+    R *Dr = (R *)smem;
+    R *Di = Dr + P2;
+    R *rs = Di + P2;
+    int *pk = (int *)(rs + OUT_LD);
+    R *MsAll = (R *)(pk + KT * 4);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, task = blockIdx.x;
+    const int c = a.task_class[task], first = a.task_first[task], cnt = a.task_count[task];
+    const int delta = a.cls_delta[c];
+    for (int i = tid; i < P2; i += blockDim.x) {
+        Dr[i] = D[2 * ((int64_t)c * P2 + i)];
+        Di[i] = D[2 * ((int64_t)c * P2 + i) + 1];
     }
-    for (int p = 0; p < 8; p++) {
-        if (p < cnt) {
-            const int j = a.pair_list[first + p];
-            const int s = a.inter_idx[j];
-            const R scale = (R)ldexp(1.0 / a.side, a.level[s]);
-            const cx<R> *ms = mom + (int64_t)s * P;
-            for (int al = lane; al < KT * 4; al += 64) {
-                R vr = 0, vi = 0;
-                if (al < P) {
-                    int na = a.exps[3 * al] + a.exps[3 * al + 1] + a.exps[3 * al + 2];
-                    R f = (na & 1) ? -scale : scale;
-                    vr = ms[al].re * f;
-                    vi = ms[al].im * f;
-                }
-                Ms[al * 16 + p] = vr;
-                Ms[al * 16 + 8 + p] = vi;
-            }
-        } else {
-            for (int al = lane; al < KT * 4; al += 64) {
-                Ms[al * 16 + p] = 0;
-                Ms[al * 16 + 8 + p] = 0;
-            }
+    for (int i = tid; i < KT * 4; i += blockDim.x) pk[i] = a.pk[i];
+    for (int i = tid; i < OUT_LD; i += blockDim.x) {
+        R v = 0;
+        if (i < P) {
+            const int q = a.pk[i], nb = (q & 31) + ((q >> 5) & 31) + (q >> 10);
+            v = inv_fact[i] * (R)ldexp(1.0, -delta * nb);
         }
+        rs[i] = v;
     }
     __syncthreads();
+    const int wfirst = first + 8 * wave, wcnt = min(8, cnt - 8 * wave);
+    if (wcnt <= 0) return;
+    R *Ms = MsAll + wave * (KT * 4 * 16);
+    int my_s = -1;
+    R my_scale = 0;
+    if (lane < wcnt) {
+        my_s = a.inter_idx[a.pair_list[wfirst + lane]];
+        my_scale = (R)ldexp(1.0 / a.side, a.level[my_s]);
+    }
+#pragma unroll 2
+    for (int p = 0; p < 8; p++) {
+        const int s = __shfl(my_s, p, 64);
+        const R scale = __shfl(my_scale, p, 64);
+        for (int al = lane; al < KT * 4; al += 64) {
+            R vr = 0, vi = 0;
+            if (s >= 0 && al < P) {
+                const int q = pk[al], na = (q & 31) + ((q >> 5) & 31) + (q >> 10);
+                const R f = (na & 1) ? -scale : scale;
+                const cx<R> m = mom[(int64_t)s * P + al];
+                vr = m.re * f;
+                vi = m.im * f;
+            }
+            Ms[al * 16 + p] = vr;
+            Ms[al * 16 + 8 + p] = vi;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
     const int row = lane & 15, kq = lane >> 4;
-    int kb[MT];
-    for (int mt = 0; mt < MT; mt++) kb[mt] = a.kbeta[16 * mt + row];
+    int pb[MT];
+    for (int mt = 0; mt < MT; mt++) pb[mt] = pk[min(16 * mt + row, KT * 4 - 1)] * (16 * mt + row < P ? 1 : 0);
     V4 accR[MT], accI[MT];
     for (int mt = 0; mt < MT; mt++) {
         accR[mt] = V4{0, 0, 0, 0};
@@ -243,28 +283,27 @@ __global__ void __launch_bounds__(64) k_m2l_mfma_cx(M2lArgs a, const R *D /* int
     }
     for (int kt = 0; kt < KT; kt++) {
         const int al = 4 * kt + kq;
-        const int ka = a.kalpha[al];
+        const int pa = pk[al];
         const R bv = Ms[al * 16 + row];
 #pragma unroll
         for (int mt = 0; mt < MT; mt++) {
-            accR[mt] = mfma(Dr[kb[mt] + ka], bv, accR[mt]);
-            accI[mt] = mfma(Di[kb[mt] + ka], bv, accI[mt]);
+            const int ix = sum_index(pb[mt] + pa);
+            accR[mt] = mfma(Dr[ix], bv, accR[mt]);
+            accI[mt] = mfma(Di[ix], bv, accI[mt]);
         }
     }
     // lane with column p < 8 holds Tr.Mr and Ti.Mr of pair p; lane ^ 8 holds Tr.Mi and Ti.Mi
     const int p = row & 7;
     const bool lo = row < 8;
-    const int j = (lo && p < cnt) ? a.pair_list[first + p] : -1;
-    const int delta = a.cls_delta[c];
+    const int j = (lo && p < wcnt) ? a.pair_list[wfirst + p] : -1;
     for (int mt = 0; mt < MT; mt++)
         for (int r = 0; r < 4; r++) {
             R trmi = __shfl_xor(accR[mt][r], 8, 64);
             R timi = __shfl_xor(accI[mt][r], 8, 64);
             const int b = 16 * mt + crow(R(0), kq, r);
-            if (j >= 0 && b < P) {
-                const int nb = a.exps[3 * b] + a.exps[3 * b + 1] + a.exps[3 * b + 2];
-                const R f = inv_fact[b] * (R)ldexp(1.0, -delta * nb);
-                out[(int64_t)j * P + b] = cx<R>((accR[mt][r] - timi) * f, (trmi + accI[mt][r]) * f);
+            if (j >= 0) {
+                const R f = rs[b];
+                out[(int64_t)j * OUT_LD + b] = cx<R>((accR[mt][r] - timi) * f, (trmi + accI[mt][r]) * f);
             }
         }
 }
@@ -275,7 +314,17 @@ __global__ void k_m2l_reduce(const int32_t *boxes, const int64_t *iptr, int P, c
     const int b = boxes[blockIdx.x];
     for (int i = threadIdx.x; i < P; i += blockDim.x) {
         V acc = V(0.0);
-        for (int64_t j = iptr[b]; j < iptr[b + 1]; j++) acc += out[j * P + i];
+        const int64_t j0 = iptr[b], j1 = iptr[b + 1];
+        int64_t j = j0;
+        for (; j + 4 <= j1; j += 4) {
+            const V v0 = out[j * OUT_LD + i], v1 = out[(j + 1) * OUT_LD + i], v2 = out[(j + 2) * OUT_LD + i],
+                    v3 = out[(j + 3) * OUT_LD + i];
+            acc += v0;
+            acc += v1;
+            acc += v2;
+            acc += v3;
+        }
+        for (; j < j1; j++) acc += out[j * OUT_LD + i];
         loc[(int64_t)b * P + i] += acc;
     }
 }
@@ -350,7 +399,7 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
         }
     }
     pl->n_class = (int64_t)members.size();
-    const int cols = helm ? 8 : 16;
+    const int cols = (helm ? 8 : 16) * M2L_WAVES;
     std::vector<int32_t> plist, tc, tf, tn;
     for (int32_t cl = 0; cl < (int32_t)members.size(); cl++) {
         const int32_t base = (int32_t)plist.size();
@@ -372,17 +421,11 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     up(pl->task_first, tf);
     up(pl->task_count, tn);
     up(pl->cls_delta, cdelta);
-    // packed keys
-    std::vector<int16_t> key_of(P2);
+    // packed multi-indices of the contraction rows
     std::vector<int8_t> ex = T.h_exps;
-    for (int i = 0; i < P2; i++) key_of[i] = (int16_t)(ex[3 * i] * 289 + ex[3 * i + 1] * 17 + ex[3 * i + 2]);
-    std::vector<int32_t> kbeta(MT * 16, 0), kalpha(KT * 4, 0);
-    for (int i = 0; i < P; i++) kbeta[i] = key_of[i];
-    for (int i = 0; i < P; i++) kalpha[i] = key_of[i];
-    pl->key_of.alloc(&c, P2);
-    pl->key_of.upload(key_of.data(), P2);
-    up(pl->kbeta, kbeta);
-    up(pl->kalpha, kalpha);
+    std::vector<int32_t> pk(KT * 4, 0);
+    for (int i = 0; i < P; i++) pk[i] = ex[3 * i] | (ex[3 * i + 1] << 5) | (ex[3 * i + 2] << 10);
+    up(pl->pk, pk);
     // class derivative tables
     const int cw = helm ? 2 : 1;
     pl->D64.alloc(&c, (size_t)cw * P2 * std::max<int64_t>(1, pl->n_class));
@@ -413,20 +456,29 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc) {
     FmmTables &T = *t.tables;
     const int P = T.P;
     if (!pl.n_task) return;
-    t.work.m2l_out.ensure(&c, sizeof(V) * (size_t)std::max<int64_t>(1, t.n_inter) * P);
+    t.work.m2l_out.ensure(&c, sizeof(V) * (size_t)std::max<int64_t>(1, t.n_inter) * OUT_LD);
     V *out = (V *)t.work.m2l_out.p;
     M2lArgs a{pl.task_class.p, pl.task_first.p, pl.task_count.p, pl.pair_list.p, t.inter_idx.p, t.level.p,
-              pl.cls_delta.p, pl.key_of.p, pl.kbeta.p, pl.kalpha.p, T.exps.p, t.side, P, T.P2, t.n_box, t.n_inter};
+              pl.cls_delta.p, pl.pk.p, t.side, P, T.P2, t.n_box, t.n_inter};
+    const int cw = std::is_same<V, R>::value ? 1 : 2;
+    const size_t sh = sizeof(R) * (cw * T.P2 + OUT_LD) + sizeof(int) * KT * 4 + sizeof(R) * M2L_WAVES * KT * 4 * 16;
     const bool f32 = std::is_same<R, float>::value;
     const R *invf = f32 ? (const R *)T.inv_fact32.p : (const R *)T.inv_fact64.p;
     const R *D = f32 ? (const R *)pl.D32.p : (const R *)pl.D64.p;
+    if (sh > 64 * 1024) {
+        if constexpr (std::is_same<V, R>::value)
+            BEM_HIP(hipFuncSetAttribute((const void *)k_m2l_mfma<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+        else
+            BEM_HIP(hipFuncSetAttribute((const void *)k_m2l_mfma_cx<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)sh));
+    }
     for (int rhs = 0; rhs < nrhs; rhs++) {
         const V *m = mom + (int64_t)rhs * t.n_box * P;
         V *l = loc + (int64_t)rhs * t.n_box * P;
         if constexpr (std::is_same<V, R>::value)
-            k_m2l_mfma<R><<<(unsigned)pl.n_task, 64, 0, c.stream>>>(a, D, invf, m, out);
+            k_m2l_mfma<R><<<(unsigned)pl.n_task, 64 * M2L_WAVES, sh, c.stream>>>(a, D, invf, m, out);
         else
-            k_m2l_mfma_cx<R><<<(unsigned)pl.n_task, 64, 0, c.stream>>>(a, D, invf, m, out);
+            k_m2l_mfma_cx<R><<<(unsigned)pl.n_task, 64 * M2L_WAVES, sh, c.stream>>>(a, D, invf, m, out);
         BEM_LAUNCH_CHECK();
         k_m2l_reduce<V><<<(unsigned)t.n_m2l_boxes, 192, 0, c.stream>>>(t.m2l_boxes.p, t.inter_ptr.p, P, out, l);
         BEM_LAUNCH_CHECK();

@@ -1,0 +1,424 @@
+// Upward and downward passes of the fast product (Sections 3.2, 3.6) other
+// than the multipole-to-local translation.  Scaled expansions as in fmm.hip:
+// Mh_a = M_a / (a! rho^|a|), Fh_b = F_b rho^|b|, rho = side of the box's level.
+//
+// P2M uses stored weights (Eq. 8): for every leaf and every DOF u touched by
+// its elements,
+//     W[u][a] = sum over the leaf's elements e, their nodes j with DOF u and
+//               the 7 rule points q of  wJ_q L_j(q) Phi_a(y_q),
+// with Phi_a(y) = u^a / a! (single layer) or sum_d n_d u^(a - e_d)/(a - e_d)!
+// / rho (double layer), u = (y - c)/rho.  The weights depend on the geometry
+// only (not on G or k), so they are built once per tree and layer type and the
+// moments are one small product per leaf: Mh = W^T x.
+//
+// L2P uses the stored monomials u_t^b of every target in its leaf's frame.
+//
+// M2M and L2L: a child centre is offset from its parent's by s rho_parent / 4
+// with s in {-1, +1}^3 (s_d = +1 when bit d of the child octant is set), so
+// every shift coefficient is a magnitude times the sign s^g of some
+// multi-index g.  Summing the eight children (M2M) or the eight child
+// outputs (L2L) by the parity of g first (a Walsh-Hadamard combination) leaves
+// one table read per shift term:
+//   M2M  Mh'_a = sum_{g <= a} (4^-|g| / g!) 2^-(|a| - |g|) S_{g mod 2}[a - g],
+//        S_pi[d] = sum_children (-1)^{|pi & ~oct|} Mh_child[d]        (Eq. 10)
+//   L2L  Fh_child[b] += sum_pi (-1)^{|pi & ~oct|} T_pi[b],
+//        T_pi[b] = sum_{a >= b, (a - b) mod 2 = pi} C(a, b) 4^-|a - b| 2^-|b| Fh[a]   (Eq. 11)
+#include <cmath>
+
+#include "kernels.h"
+
+namespace bem {
+
+namespace {
+
+__host__ __device__ inline int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+__host__ __device__ inline int midx(int a, int b, int c) {
+    int n = a + b + c;
+    return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
+}
+
+// ---------------------------------------------------------------- P2M weights (setup, FP64)
+template <bool DBL>
+__global__ void k_p2m_weights(const int32_t *leaves, const int64_t *eb, const int64_t *ee, const int32_t *level,
+                              const double *centre, double side, const double *q64, int64_t n_q, const double *L7,
+                              const int32_t *slot, const int64_t *woff, int p, const int8_t *exps, double *W) {
+    const int P = ncoef(p);
+    const int b = leaves[blockIdx.x];
+    const double rho = ldexp(side, -level[b]), irho = 1.0 / rho;
+    const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
+    const int64_t off = woff[blockIdx.x];
+    for (int a = threadIdx.x; a < P; a += blockDim.x) {
+        const int e0 = exps[3 * a], e1 = exps[3 * a + 1], e2 = exps[3 * a + 2];
+        for (int64_t e = eb[b]; e < ee[b]; e++) {
+            double phi[7];
+            for (int q = 0; q < 7; q++) {
+                const int64_t qi = 7 * e + q;
+                const double u[3] = {(q64[qi] - c0) * irho, (q64[n_q + qi] - c1) * irho, (q64[2 * n_q + qi] - c2) * irho};
+                // powers u_d^k / k!
+                double pw[3][MAX_ORDER + 1];
+                for (int d = 0; d < 3; d++) {
+                    pw[d][0] = 1.0;
+                    for (int k = 1; k <= p; k++) pw[d][k] = pw[d][k - 1] * u[d] / k;
+                }
+                double v;
+                if (!DBL) {
+                    v = pw[0][e0] * pw[1][e1] * pw[2][e2];
+                } else {
+                    v = 0.0;
+                    if (e0) v += q64[4 * n_q + qi] * pw[0][e0 - 1] * pw[1][e1] * pw[2][e2];
+                    if (e1) v += q64[5 * n_q + qi] * pw[0][e0] * pw[1][e1 - 1] * pw[2][e2];
+                    if (e2) v += q64[6 * n_q + qi] * pw[0][e0] * pw[1][e1] * pw[2][e2 - 1];
+                    v *= irho;
+                }
+                phi[q] = v * q64[3 * n_q + qi];
+            }
+            for (int j = 0; j < 6; j++) {
+                double w = 0.0;
+                for (int q = 0; q < 7; q++) w += L7[6 * q + j] * phi[q];
+                W[(off + slot[6 * e + j]) * P + a] += w;
+            }
+        }
+    }
+}
+
+template <class R>
+__global__ void k_to_r(const double *in, int64_t n, R *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (R)in[i];
+}
+
+// ---------------------------------------------------------------- P2M apply
+template <class V, class R, class XV>
+__global__ void k_p2m_apply(const int32_t *leaves, const int64_t *woff, const int32_t *wdof, const R *W, int P,
+                            const XV *x, int64_t n_dof, V *mom, int64_t n_box) {
+    __shared__ V xs[256];
+    const int b = leaves[blockIdx.x], rhs = blockIdx.y;
+    const int64_t o0 = woff[blockIdx.x], o1 = woff[blockIdx.x + 1];
+    const XV *xr = x + (int64_t)rhs * n_dof;
+    V acc[2] = {V(0.0), V(0.0)};
+    for (int64_t ub = o0; ub < o1; ub += 256) {
+        const int nu = (int)min<int64_t>(256, o1 - ub);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nu; i += blockDim.x) xs[i] = vcast<V>(xr[wdof[ub + i]]);
+        __syncthreads();
+        for (int r = 0; r < 2; r++) {
+            const int a = threadIdx.x + r * blockDim.x;
+            if (a >= P) break;
+            V sacc = acc[r];
+#pragma unroll 4
+            for (int i = 0; i < nu; i++) sacc += xs[i] * W[(ub + i) * P + a];
+            acc[r] = sacc;
+        }
+    }
+    for (int r = 0; r < 2; r++) {
+        const int a = threadIdx.x + r * blockDim.x;
+        if (a < P) mom[((int64_t)rhs * n_box + b) * P + a] = acc[r];
+    }
+}
+
+// ---------------------------------------------------------------- M2M
+// grid (parents, coefficient groups of 32, rhs); block 256 = 32 coefficients x
+// 8 parity classes; each lane sums the shift terms of one parity and the eight
+// lanes of a coefficient are added by shuffles.
+template <class V, class R>
+__global__ void __launch_bounds__(256) k_m2m(const int32_t *boxes, const int32_t *child_begin, const int32_t *nchild,
+                                             const uint64_t *prefix, int p, const int8_t *exps, V *mom,
+                                             int64_t n_box) {
+    extern __shared__ unsigned char smem[];
+    const int P = ncoef(p);
+    V *S = (V *)smem;                // [8][P] parity sums of the children
+    R *c4 = (R *)(S + 8 * P);        // 4^-k / k!
+    R *p2 = c4 + (MAX_ORDER + 1);    // 2^-k
+    __shared__ int cid[8], cmask[8], ncs;
+    const int b = boxes[blockIdx.x], rhs = blockIdx.z;
+    V *base = mom + (int64_t)rhs * n_box * P;
+    if (threadIdx.x == 0) ncs = nchild[b];
+    if (threadIdx.x < 8) {
+        const int nc = nchild[b];
+        const int c = child_begin[b] + (int)threadIdx.x;
+        cid[threadIdx.x] = (int)threadIdx.x < nc ? c : 0;
+        cmask[threadIdx.x] = (int)threadIdx.x < nc ? ((~(int)(prefix[c] & 7u)) & 7) : 0;
+    }
+    if (threadIdx.x <= (unsigned)p) {
+        double f = 1.0;
+        for (int k = 2; k <= (int)threadIdx.x; k++) f *= k;
+        c4[threadIdx.x] = (R)(ldexp(1.0, -2 * (int)threadIdx.x) / f);
+        p2[threadIdx.x] = (R)ldexp(1.0, -(int)threadIdx.x);
+    }
+    __syncthreads();
+    const int nch = ncs;
+    for (int i = threadIdx.x; i < 8 * P; i += blockDim.x) {
+        const int pi = i / P, d = i % P;
+        V acc = V(0.0);
+        for (int ch = 0; ch < nch; ch++) {
+            const V m = base[(int64_t)cid[ch] * P + d];
+            if (__popc(pi & cmask[ch]) & 1) acc -= m;
+            else acc += m;
+        }
+        S[pi * P + d] = acc;
+    }
+    __syncthreads();
+    const int a = blockIdx.y * 32 + (threadIdx.x >> 3), pi = threadIdx.x & 7;
+    const int p0 = (pi >> 2) & 1, p1 = (pi >> 1) & 1, p2b = pi & 1;
+    V acc = V(0.0);
+    if (a < P) {
+        const int a0 = exps[3 * a], a1 = exps[3 * a + 1], a2 = exps[3 * a + 2], na = a0 + a1 + a2;
+        for (int g0 = p0; g0 <= a0; g0 += 2)
+            for (int g1 = p1; g1 <= a1; g1 += 2)
+                for (int g2 = p2b; g2 <= a2; g2 += 2) {
+                    const R mag = c4[g0] * c4[g1] * c4[g2] * p2[na - g0 - g1 - g2];
+                    acc += S[pi * P + midx(a0 - g0, a1 - g1, a2 - g2)] * mag;
+                }
+    }
+    for (int o = 1; o < 8; o <<= 1) {
+        if constexpr (std::is_same<V, R>::value) {
+            acc += __shfl_xor(acc, o, 64);
+        } else {
+            acc.re += __shfl_xor(acc.re, o, 64);
+            acc.im += __shfl_xor(acc.im, o, 64);
+        }
+    }
+    if (a < P && pi == 0) base[(int64_t)b * P + a] = acc;
+}
+
+// ---------------------------------------------------------------- L2L
+// grid (parents, coefficient groups of 32, rhs); block 256 = 32 coefficients x
+// 8 parity classes; the eight lanes of a coefficient form each child's value
+// by signed shuffle sums.
+template <class V, class R>
+__global__ void __launch_bounds__(256) k_l2l(const int32_t *boxes, const int32_t *child_begin, const int32_t *nchild,
+                                             const uint64_t *prefix, const int64_t *tb, const int64_t *te, int p,
+                                             const int8_t *exps, V *loc, int64_t n_box) {
+    extern __shared__ unsigned char smem[];
+    const int P = ncoef(p);
+    V *F = (V *)smem;
+    R *q4 = (R *)(F + P);            // 4^-k
+    R *bn = q4 + (MAX_ORDER + 1);    // binomials [p+1][p+1]
+    __shared__ int cmask[8], cwant[8];
+    const int b = boxes[blockIdx.x], rhs = blockIdx.z;
+    V *base = loc + (int64_t)rhs * n_box * P;
+    const int nc = nchild[b], cb = child_begin[b];
+    for (int i = threadIdx.x; i < P; i += blockDim.x) F[i] = base[(int64_t)b * P + i];
+    if (threadIdx.x <= (unsigned)p) q4[threadIdx.x] = (R)ldexp(1.0, -2 * (int)threadIdx.x);
+    for (int i = threadIdx.x; i < (p + 1) * (p + 1); i += blockDim.x) {
+        const int n = i / (p + 1), k = i % (p + 1);
+        double v = 0.0;
+        if (k <= n) {
+            v = 1.0;
+            for (int j = 1; j <= k; j++) v = v * (n - k + j) / j;
+        }
+        bn[i] = (R)v;
+    }
+    if (threadIdx.x < 8) {
+        const int c = cb + (int)threadIdx.x;
+        const bool ok = (int)threadIdx.x < nc;
+        cmask[threadIdx.x] = ok ? ((~(int)(prefix[c] & 7u)) & 7) : 0;
+        cwant[threadIdx.x] = ok && te[c] > tb[c];
+    }
+    __syncthreads();
+    const int bi = blockIdx.y * 32 + (threadIdx.x >> 3), pi = threadIdx.x & 7;
+    V T = V(0.0);
+    if (bi < P) {
+        const int b0 = exps[3 * bi], b1 = exps[3 * bi + 1], b2 = exps[3 * bi + 2];
+        const int p0 = (pi >> 2) & 1, p1 = (pi >> 1) & 1, p2 = pi & 1;
+        for (int a0 = b0 + p0; a0 <= p; a0 += 2)
+            for (int a1 = b1 + p1; a0 + a1 <= p; a1 += 2)
+                for (int a2 = b2 + p2; a0 + a1 + a2 <= p; a2 += 2) {
+                    const R mag = bn[a0 * (p + 1) + b0] * bn[a1 * (p + 1) + b1] * bn[a2 * (p + 1) + b2] *
+                                  q4[a0 - b0] * q4[a1 - b1] * q4[a2 - b2];
+                    T += F[midx(a0, a1, a2)] * mag;
+                }
+        T = T * (R)ldexp(1.0, -(b0 + b1 + b2));
+    }
+    for (int ch = 0; ch < 8; ch++) {
+        if (!cwant[ch]) continue;  // uniform across the block
+        V v = (__popc(pi & cmask[ch]) & 1) ? -T : T;
+        for (int o = 1; o < 8; o <<= 1) {
+            if constexpr (std::is_same<V, R>::value) {
+                v += __shfl_xor(v, o, 64);
+            } else {
+                v.re += __shfl_xor(v.re, o, 64);
+                v.im += __shfl_xor(v.im, o, 64);
+            }
+        }
+        if (bi < P && pi == 0) base[(int64_t)(cb + ch) * P + bi] += v;
+    }
+}
+
+// ---------------------------------------------------------------- L2P monomials
+template <class R>
+__global__ void k_l2p_monomials(const int32_t *leaves, const int64_t *tb, const int64_t *te, const int32_t *level,
+                                const double *centre, double side, const double *t64, int64_t n_tgt, int p,
+                                const int8_t *exps, R *U) {
+    const int P = ncoef(p);
+    const int b = leaves[blockIdx.x];
+    const int64_t t0 = tb[b], nt = te[b] - tb[b];
+    const double irho = 1.0 / ldexp(side, -level[b]);
+    for (int64_t i = threadIdx.x; i < nt * P; i += blockDim.x) {
+        const int64_t tl = i % nt;
+        const int bi = (int)(i / nt);
+        const int64_t t = t0 + tl;
+        const double u0 = (t64[t] - centre[3 * b]) * irho, u1 = (t64[n_tgt + t] - centre[3 * b + 1]) * irho,
+                     u2 = (t64[2 * n_tgt + t] - centre[3 * b + 2]) * irho;
+        double v = 1.0;
+        for (int k = 0; k < exps[3 * bi]; k++) v *= u0;
+        for (int k = 0; k < exps[3 * bi + 1]; k++) v *= u1;
+        for (int k = 0; k < exps[3 * bi + 2]; k++) v *= u2;
+        U[t0 * P + (int64_t)bi * nt + tl] = (R)v;
+    }
+}
+
+template <class V, class R>
+__global__ void k_l2p_apply(const int32_t *leaves, const int64_t *tb, const int64_t *te, int P, const R *U,
+                            const V *loc, int64_t n_box, int64_t n_tgt, V *y) {
+    extern __shared__ unsigned char smem[];
+    V *F = (V *)smem;
+    const int b = leaves[blockIdx.x], rhs = blockIdx.y;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) F[i] = loc[((int64_t)rhs * n_box + b) * P + i];
+    __syncthreads();
+    const int64_t t0 = tb[b], nt = te[b] - tb[b];
+    const R *Ub = U + t0 * P;
+    for (int64_t tl = threadIdx.x; tl < nt; tl += blockDim.x) {
+        V acc = V(0.0);
+        for (int bi = 0; bi < P; bi++) acc += F[bi] * Ub[(int64_t)bi * nt + tl];
+        y[(int64_t)rhs * n_tgt + t0 + tl] = acc;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- setup
+void build_pass_tables(bem_tree &t) {
+    if (t.pass.built) return;
+    Ctx &c = *t.ctx;
+    fmm_tables(t);
+    plan_fmm(t);
+    FmmTables &T = *t.tables;
+    const int p = t.order, P = T.P;
+    // DOF slots of each source leaf
+    std::vector<int32_t> sed = t.se_dofs.download(6 * t.n_el);
+    std::vector<int32_t> leaves = t.leaf_ids.download(t.n_leaf_src);
+    std::vector<int64_t> woff(leaves.size() + 1, 0);
+    std::vector<int32_t> wdof, slot(6 * t.n_el, 0);
+    for (size_t i = 0; i < leaves.size(); i++) {
+        const int b = leaves[i];
+        std::vector<int32_t> u;
+        for (int64_t e = t.h_eb[b]; e < t.h_ee[b]; e++)
+            for (int j = 0; j < 6; j++) u.push_back(sed[6 * e + j]);
+        std::sort(u.begin(), u.end());
+        u.erase(std::unique(u.begin(), u.end()), u.end());
+        for (int64_t e = t.h_eb[b]; e < t.h_ee[b]; e++)
+            for (int j = 0; j < 6; j++)
+                slot[6 * e + j] = (int32_t)(std::lower_bound(u.begin(), u.end(), sed[6 * e + j]) - u.begin());
+        wdof.insert(wdof.end(), u.begin(), u.end());
+        woff[i + 1] = (int64_t)wdof.size();
+    }
+    PassTables &pt = t.pass;
+    pt.n_w = (int64_t)wdof.size();
+    pt.woff.alloc(&c, woff.size());
+    pt.woff.upload(woff.data(), woff.size());
+    pt.wdof.alloc(&c, wdof.size());
+    pt.wdof.upload(wdof.data(), wdof.size());
+    DBuf<int32_t> dslot;
+    dslot.alloc(&c, slot.size());
+    dslot.upload(slot.data(), slot.size());
+    const size_t nw = (size_t)pt.n_w * P;
+    for (int dbl = 0; dbl < 2; dbl++) {
+        pt.W64[dbl].alloc(&c, nw);
+        pt.W64[dbl].zero();
+        pt.W32[dbl].alloc(&c, nw);
+        if (t.n_leaf_src) {
+            if (dbl)
+                k_p2m_weights<true><<<(unsigned)t.n_leaf_src, 192, 0, c.stream>>>(
+                    t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p, t.side, t.q64.p, t.n_q, t.L7.p, dslot.p,
+                    pt.woff.p, p, T.exps.p, pt.W64[dbl].p);
+            else
+                k_p2m_weights<false><<<(unsigned)t.n_leaf_src, 192, 0, c.stream>>>(
+                    t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p, t.side, t.q64.p, t.n_q, t.L7.p, dslot.p,
+                    pt.woff.p, p, T.exps.p, pt.W64[dbl].p);
+            BEM_LAUNCH_CHECK();
+        }
+        k_to_r<float><<<nblocks(nw, 256), 256, 0, c.stream>>>(pt.W64[dbl].p, nw, pt.W32[dbl].p);
+        BEM_LAUNCH_CHECK();
+    }
+    // target monomials
+    const size_t nu = (size_t)t.n_tgt * P;
+    pt.U64.alloc(&c, nu);
+    pt.U32.alloc(&c, nu);
+    if (t.n_leaf_tgt) {
+        k_l2p_monomials<double><<<(unsigned)t.n_leaf_tgt, 256, 0, c.stream>>>(
+            t.tleaf_ids.p, t.tb.p, t.te.p, t.level.p, t.centre.p, t.side, t.t64.p, t.n_tgt, p, T.exps.p, pt.U64.p);
+        BEM_LAUNCH_CHECK();
+        k_to_r<float><<<nblocks(nu, 256), 256, 0, c.stream>>>(pt.U64.p, nu, pt.U32.p);
+        BEM_LAUNCH_CHECK();
+    }
+    c.sync();
+    pt.built = true;
+}
+
+// ---------------------------------------------------------------- launchers
+template <class V, class R, class XV>
+void p2m_apply(bem_tree &t, bool dbl, int nrhs, const XV *x, V *mom) {
+    if (!t.n_leaf_src) return;
+    Ctx &c = *t.ctx;
+    const int P = t.tables->P;
+    const R *W = std::is_same<R, float>::value ? (const R *)t.pass.W32[dbl].p : (const R *)t.pass.W64[dbl].p;
+    dim3 g((unsigned)t.n_leaf_src, nrhs);
+    k_p2m_apply<V, R, XV><<<g, 192, 0, c.stream>>>(t.leaf_ids.p, t.pass.woff.p, t.pass.wdof.p, W, P, x, t.n_tgt,
+                                                   mom, t.n_box);
+    BEM_LAUNCH_CHECK();
+}
+
+template <class V, class R>
+void m2m_apply(bem_tree &t, int nrhs, V *mom) {
+    Ctx &c = *t.ctx;
+    const int p = t.order, P = t.tables->P;
+    const size_t sh = sizeof(V) * 8 * P + sizeof(R) * 2 * (MAX_ORDER + 1);
+    for (int l = t.max_level - 1; l >= t.m2m_top; l--) {
+        int64_t nb = (int64_t)t.m2m_level_boxes[l].size();
+        if (!nb) continue;
+        dim3 g((unsigned)nb, (P + 31) / 32, nrhs);
+        k_m2m<V, R><<<g, 256, sh, c.stream>>>(t.d_m2m_level_boxes[l].p, t.child_begin.p, t.nchild.p, t.prefix.p, p,
+                                              t.tables->exps.p, mom, t.n_box);
+        BEM_LAUNCH_CHECK();
+    }
+}
+
+template <class V, class R>
+void l2l_apply(bem_tree &t, int nrhs, V *loc) {
+    Ctx &c = *t.ctx;
+    const int p = t.order, P = t.tables->P;
+    const size_t sh = sizeof(V) * P + sizeof(R) * ((MAX_ORDER + 1) + (p + 1) * (p + 1));
+    for (int l = t.l2l_top; l < t.max_level; l++) {
+        int64_t nb = (int64_t)t.l2l_level_boxes[l].size();
+        if (!nb) continue;
+        dim3 g((unsigned)nb, (P + 31) / 32, nrhs);
+        k_l2l<V, R><<<g, 256, sh, c.stream>>>(t.d_l2l_level_boxes[l].p, t.child_begin.p, t.nchild.p, t.prefix.p,
+                                              t.tb.p, t.te.p, p, t.tables->exps.p, loc, t.n_box);
+        BEM_LAUNCH_CHECK();
+    }
+}
+
+template <class V, class R>
+void l2p_apply(bem_tree &t, int nrhs, const V *loc, V *y) {
+    if (!t.n_leaf_tgt) return;
+    Ctx &c = *t.ctx;
+    const int P = t.tables->P;
+    const R *U = std::is_same<R, float>::value ? (const R *)t.pass.U32.p : (const R *)t.pass.U64.p;
+    dim3 g((unsigned)t.n_leaf_tgt, nrhs);
+    k_l2p_apply<V, R><<<g, 64, sizeof(V) * P, c.stream>>>(t.tleaf_ids.p, t.tb.p, t.te.p, P, U, loc, t.n_box,
+                                                           t.n_tgt, y);
+    BEM_LAUNCH_CHECK();
+}
+
+#define BEM_PASSES(V, R, XV)                                                   \
+    template void p2m_apply<V, R, XV>(bem_tree &, bool, int, const XV *, V *); \
+    template void m2m_apply<V, R>(bem_tree &, int, V *);                       \
+    template void l2l_apply<V, R>(bem_tree &, int, V *);                       \
+    template void l2p_apply<V, R>(bem_tree &, int, const V *, V *);
+BEM_PASSES(double, double, double)
+BEM_PASSES(float, float, double)
+BEM_PASSES(cx<double>, double, cx<double>)
+BEM_PASSES(cx<float>, float, cx<double>)
+
+}  // namespace bem
