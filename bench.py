@@ -28,8 +28,48 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-FP32_VEC_PEAK = 157.3  # TFLOP/s, MI355X vector FP32 (256 CUs, 2.4 GHz)
+FP32_VEC_PEAK = 157.3  # TFLOP/s, MI355X vector FP32 (256 CUs, 2.4 GHz, packed)
+FP32_MFMA_PEAK = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 FP64_VEC_PEAK = 78.6
+KERNEL_PEAKS = {"m2l": ("mfma", FP32_MFMA_PEAK), "p2p": ("alu", FP32_VEC_PEAK)}
+# source file of each timed kernel (the HBM traffic figures hold for one version of it)
+KERNEL_SOURCES = {"m2l": "m2l.hip", "p2p": "fmm.hip"}
+
+
+def hbm_traffic(kernel, workload):
+    """HBM bytes per launch of the mixed-precision kernel, from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload, scaled by the
+    copy-kernel calibration; None when there is none or the kernel's source
+    has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_0908_0673_amd", "csrc", KERNEL_SOURCES[kernel])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != sha or "hbm_bytes_per_launch" not in kv:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def copy_calibration():
+    """A plain 1 GiB device copy: its FETCH_SIZE / WRITE_SIZE readings give the
+    factor that turns those counters into bytes."""
+    import torch
+
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": 4 * n, "launches": 3}))
 
 
 def algorithmic_flops(stats, P, dbl=True):
@@ -54,11 +94,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
 
@@ -135,14 +181,16 @@ def main():
                            "residual": info["residual"],
                            "rms_error_vs_analytic": float(np.sqrt(np.mean((sol - phi.real) ** 2)))}
 
-    # roofline of the dominant kernel of the headline product
+    # roofline of the dominant kernel of the headline product: the M2L
+    # products run on the FP32 matrix cores, the near field on the FP32 VALU
     P = 165
     flops = algorithmic_flops(stats, P)
     per_step = {k: v[0] / max(1, v[1]) for k, v in ph_mixed.items()}
     dom = max(("p2p", "m2l"), key=lambda k: per_step[k])
     achieved = flops[dom] / (per_step[dom] * 1e-3) / 1e12
-    roofline = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP32_VEC_PEAK, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VEC_PEAK, "traffic": None,
+    bound, peak = KERNEL_PEAKS[dom]
+    roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": hbm_traffic(dom, args.workload),
                 "algorithmic_flop_per_launch": flops[dom], "avg_launch_ms": per_step[dom]}
 
     cpu = None

@@ -90,12 +90,13 @@ const char *bem_last_error(const bem_ctx *ctx);
 /* Phase timing (profiling aid).  While enabled, every product records HIP
  * events on the context's stream between its phases and accumulates the
  * elapsed device time per phase:
- *   0 strengths, 1 P2M, 2 M2M, 3 M2L, 4 L2L, 5 L2P, 6 P2P (near field),
- *   7 corrections + combination, 8 direct sum, 9 other.
+ *   0 strengths, 1 P2M, 2 M2M, 3 M2L products, 4 L2L, 5 L2P, 6 P2P (near
+ *   field), 7 corrections + combination, 8 direct sum, 9 other, 10 sums of
+ *   the M2L results into the local expansions.
  * enable = 1 turns timing on and zeroes the counters; 0 turns it off.
  * ms and launches (host arrays of BEM_NPHASE, may be NULL) receive the
  * accumulated milliseconds and the number of products timed per phase. */
-#define BEM_NPHASE 10
+#define BEM_NPHASE 11
 int bem_ctx_timing(bem_ctx *ctx, int enable, double *ms, int64_t *launches);
 
 /* ------------------------------------------------------------------ mesh */

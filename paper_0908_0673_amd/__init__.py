@@ -177,13 +177,13 @@ class Context:
             raise BemError(rc, f"{what}: {self.L.bem_last_error(self.h).decode()}")
         return rc
 
-    PHASES = ("strength", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "combine", "direct", "other")
+    PHASES = ("strength", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "combine", "direct", "other", "m2l_sum")
 
     def timing(self, enable: bool):
         """Turns per-phase event timing on (zeroing it) or off; returns the
         accumulated {phase: (ms, products)} before the switch."""
-        ms = np.zeros(10)
-        n = np.zeros(10, np.int64)
+        ms = np.zeros(len(self.PHASES))
+        n = np.zeros(len(self.PHASES), np.int64)
         self.check(self.L.bem_ctx_timing(self.h, int(enable), _np_ptr(ms), _np_ptr(n)), "bem_ctx_timing")
         return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(self.PHASES)}
 

@@ -506,6 +506,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         fmm_tables(t);
         plan_fmm(t);
         build_pass_tables(t);
+        m2l_prepare<V, R>(t, *pl);
     }
     c.mark(9);
     dim3 gs(nblocks(nq, 256), nrhs);
@@ -540,7 +541,6 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         BEM_HIP(hipMemsetAsync(loc, 0, sizeof(V) * nexp, c.stream));
         c.mark(9);
         m2l_apply<V, R>(t, *pl, nrhs, mom, loc);
-        c.mark(3);
         // downward pass
         l2l_apply<V, R>(t, nrhs, loc);
         c.mark(4);

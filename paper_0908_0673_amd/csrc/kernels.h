@@ -50,19 +50,40 @@ struct FmmTables {
     int nnz_m2m = 0, nnz_l2l = 0;
 };
 
-// Displacement classes of the interaction pairs for one (Green, k) and their
-// derivative tables (multipole-to-local translation on the matrix cores).
+// Tasks of one wave each over the pairs of an M2L plan, for one column width.
+struct M2lTasks {
+    int cols = 0;
+    int64_t n_task = 0;
+    DBuf<int32_t> task_class, task_first, task_count;
+};
+
+// Canonical displacement classes of the interaction pairs for one (Green, k),
+// their derivative tables and expanded operators (multipole-to-local
+// translation on the matrix cores).
 struct M2lPlan {
     int green = -1;
     double k = 0.0;
-    int64_t n_class = 0, n_task = 0, n_pairs = 0;
-    DBuf<double> D64;                 // [n_class][P2] (x2 interleaved when complex)
-    DBuf<float> D32;
+    int64_t n_class = 0, n_pairs = 0;
+    DBuf<double> D64;                 // [n_class][P2] (x2 interleaved when complex), canonical separations
     DBuf<int32_t> cls_delta;          // level difference of the class
-    DBuf<int32_t> pair_list;          // interaction-list slots grouped by class
-    DBuf<int32_t> task_class, task_first, task_count;  // one wave each
-    DBuf<int32_t> pk;  // packed multi-indices of the contraction rows
+    DBuf<int32_t> pair_slot;          // interaction-list slot of each pair, grouped by class
+    DBuf<int32_t> pair_src;           // source box of each pair
+    DBuf<int32_t> pair_sym;           // symmetry taking the pair to its class's canonical frame
+    std::vector<int32_t> h_class_order, h_class_first, h_class_count;  // classes, largest first
+    std::vector<std::unique_ptr<M2lTasks>> tasks;
+    DBuf<int32_t> pk;                 // packed multi-indices of the contraction rows
+    DBuf<int32_t> sym_in;             // symmetry tables: moments into the canonical frame,
+    DBuf<int16_t> sym_red;            // results back to the pair's frame
+    DBuf<int32_t> slot_sym;           // symmetry of each interaction-list slot
+    DBuf<float> T32;                  // expanded operators, built on first use per precision
+    DBuf<double> T64;
+    template <class R>
+    DBuf<R> &expanded_buf();
 };
+template <>
+inline DBuf<float> &M2lPlan::expanded_buf<float>() { return T32; }
+template <>
+inline DBuf<double> &M2lPlan::expanded_buf<double>() { return T64; }
 
 // Stored P2M weights (per source leaf and DOF, single and double layer) and
 // L2P target monomials; geometry only, built once per tree.
@@ -197,6 +218,8 @@ void l2p_apply(bem_tree &t, int nrhs, const V *loc, V *y);
 
 // m2l.hip
 M2lPlan &get_m2l_plan(bem_tree &t, int green, double k);
+template <class V, class R>
+void m2l_prepare(bem_tree &t, M2lPlan &pl);
 template <class V, class R>
 void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc);
 

@@ -7,24 +7,39 @@
 //
 // where D are the derivatives of G at r = (c_t - c_s)/rho_s with wavenumber
 // k rho_s (the source side is never smaller than the target side: interaction
-// lists hold same-level boxes and coarser leaves).  Because box centres sit
-// on the lattice of their level, 2^(dl+1) r is an integer vector (dl = level
-// difference), so pairs fall into a small number of exact displacement
-// classes: (dl, 2^(dl+1) r) for Laplace, whose scaled operator does not
-// depend on the level, plus the source level for Helmholtz.  Each class's
-// derivative table is computed once per tree (FP64, Section 3.3 recursion)
-// and the pairs of a class form one dense product
+// lists hold same-level boxes and coarser leaves).  Box centres sit on the
+// lattice of their level, so q = 2^(dl+1) r is an integer vector (dl = level
+// difference).  G depends on |r| only, so for any signed permutation of the
+// axes, r_e = s_e r'_{pi(e)}, the derivatives obey
 //
-//     OUT[b, j] = sum_a T_c[b, a] M'[a, j],    T_c[b, a] = D_c[a + b]
+//   D_g(r) = s^g D'_{g'}(r'),   g'_{pi(e)} = g_e,   s^g = prod_e s_e^(g_e),
 //
-// run on the matrix cores (v_mfma 16x16x4, FP32 or FP64): one wave takes a
-// class and up to 16 pair columns (8 complex pairs as 16 real columns), the
-// class table lives in LDS indexed by packed multi-index keys so that the
-// A operand T_c[b, a] is a single LDS read, and the M' columns (signed,
-// divided by rho_s) are staged in LDS.  Each pair's result goes to its slot
-// in the interaction list; a second kernel sums every target box's slots in
-// list order, so the result does not depend on scheduling (no float atomics).
+// and every pair reduces to a canonical displacement r' = sorted |r|: the
+// translation is the canonical operator applied to the moments permuted and
+// signed into the canonical frame, its result permuted and signed back.
+// Pairs therefore fall into few exact canonical classes, (dl, sorted |q|)
+// for Laplace, whose scaled operator does not depend on the level, plus the
+// source level for Helmholtz.  Each class's derivative table is computed once
+// per tree (FP64, Section 3.3 recursion) and its pairs form one dense product
+//
+//     OUT[b', j] = sum_a' T_c[b', a'] M'[a', j],
+//     T_c[b', a'] = rs_c[b'] (-1)^|a'| D'_c[a' + b'],  rs_c[b'] = 2^(-dl |b'|) / b'!
+//
+// run on the matrix cores (v_mfma 16x16x4, FP32 or FP64).  T_c is expanded
+// once per tree into the A-operand order of the instruction, so a wave
+// streams it with one coalesced 256-byte load per product; the canonical
+// operators of a tree take a few MB and stay resident in the L2 caches.  One
+// wave takes a class and up to 16 NCG pair columns (8 complex pairs as 16
+// real columns); its B operands are the pairs' moments gathered through the
+// symmetry tables, and it stores each pair's canonical result whole (the
+// stores are contiguous).  Tasks are ordered so that every wave of a class is dispatched
+// to the same XCD (blocks go round-robin over the 8 XCDs), whose L2 then
+// holds that class's operator.  Each pair's result goes to its slot in the
+// interaction list; a second kernel sums every target box's slots in list
+// order, so the result does not depend on scheduling (no float atomics).
+#include <algorithm>
 #include <cmath>
+#include <map>
 #include <unordered_map>
 
 #include "greens.h"
@@ -63,8 +78,7 @@ template <> struct vec4<double> { using type = doublex4; };
 // One block per class: G^(h)(R), h = 0..H, then d^g G^(h) for |g| <= H - h,
 // h descending (Section 3.3, Eq. 12), at the normalised separation.
 template <bool HELM>
-__global__ void k_class_derivs(const double *rbar, const double *kbar, int H, const int8_t *exps, double *D64,
-                               float *D32) {
+__global__ void k_class_derivs(const double *rbar, const double *kbar, int H, const int8_t *exps, double *D64) {
     using V = typename std::conditional<HELM, cx<double>, double>::type;
     extern __shared__ unsigned char smem[];
     const int P2 = ncoef(H);
@@ -115,25 +129,17 @@ __global__ void k_class_derivs(const double *rbar, const double *kbar, int H, co
         if constexpr (HELM) {
             D64[2 * ((int64_t)c * P2 + i)] = prev[i].re;
             D64[2 * ((int64_t)c * P2 + i) + 1] = prev[i].im;
-            D32[2 * ((int64_t)c * P2 + i)] = (float)prev[i].re;
-            D32[2 * ((int64_t)c * P2 + i) + 1] = (float)prev[i].im;
         } else {
             D64[(int64_t)c * P2 + i] = prev[i];
-            D32[(int64_t)c * P2 + i] = (float)prev[i];
         }
     }
 }
 
-struct M2lArgs {
-    const int32_t *task_class, *task_first, *task_count, *pair_list, *inter_idx, *level, *cls_delta;
-    const int32_t *pk;           // [KT*4] packed multi-index a | b << 5 | c << 10 (0 for padding)
-    double side;
-    int P, P2;
-    int64_t n_box, n_inter;
-};
-
-constexpr int M2L_WAVES = 4;
-constexpr int OUT_LD = MT * 16;  // row stride of the per-pair outputs (176)
+constexpr int OUT_LD = MT * 16;                // row stride of the per-pair outputs (176)
+constexpr int KIN = KT * 4;                    // contraction length (168)
+constexpr int TSZ = MT * KT * 64;              // expanded operator, A-operand order
+constexpr int NSYM = 48;                       // signed permutations of the axes
+constexpr int32_t SYM_NEG = 1 << 30;           // symmetry-table flag: negate the value
 
 // index of the multi-index sum of two packed multi-indices (graded order)
 __device__ inline int sum_index(int packed) {
@@ -142,189 +148,214 @@ __device__ inline int sum_index(int packed) {
     return (n * (n + 1) * (n + 2)) / 6 + ((m * (m + 1)) >> 1) + (m - b);
 }
 
-// Real values: a block of four waves takes one class and up to 64 of its
-// pairs, 16 per wave; the class table is shared by the waves.
-template <class R>
-__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_mfma(M2lArgs a, const R *D, const R *inv_fact, const R *mom,
-                                                             R *out) {
-    using V4 = typename vec4<R>::type;
-    extern __shared__ unsigned char smem[];
-    const int P = a.P, P2 = a.P2;
-    R *Dc = (R *)smem;                         // [P2]
-    R *rs = Dc + P2;                           // [OUT_LD] row scales of the class
-    int *pk = (int *)(rs + OUT_LD);            // [KT*4]
-    R *MsAll = (R *)(pk + KT * 4);             // [waves][KT*4][16]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, task = blockIdx.x;
-    const int c = a.task_class[task], first = a.task_first[task], cnt = a.task_count[task];
-    const int delta = a.cls_delta[c];
-    for (int i = tid; i < P2; i += blockDim.x) Dc[i] = D[(int64_t)c * P2 + i];
-    for (int i = tid; i < KT * 4; i += blockDim.x) pk[i] = a.pk[i];
-    for (int i = tid; i < OUT_LD; i += blockDim.x) {
-        R v = 0;
-        if (i < P) {
-            const int q = a.pk[i], nb = (q & 31) + ((q >> 5) & 31) + (q >> 10);
-            v = inv_fact[i] * (R)ldexp(1.0, -delta * nb);
-        }
-        rs[i] = v;
-    }
-    __syncthreads();
-    const int wfirst = first + 16 * wave, wcnt = min(16, cnt - 16 * wave);
-    if (wcnt <= 0) return;
-    R *Ms = MsAll + wave * (KT * 4 * 16);
-    // sources and scales of the wave's columns, fetched in parallel
-    int my_s = -1;
-    R my_scale = 0;
-    if (lane < wcnt) {
-        my_s = a.inter_idx[a.pair_list[wfirst + lane]];
-        my_scale = (R)ldexp(1.0 / a.side, a.level[my_s]);
-    }
-#pragma unroll 4
-    for (int col = 0; col < 16; col++) {
-        const int s = __shfl(my_s, col, 64);
-        const R scale = __shfl(my_scale, col, 64);
-        for (int al = lane; al < KT * 4; al += 64) {
-            R v = 0;
-            if (s >= 0 && al < P) {
-                const int q = pk[al], na = (q & 31) + ((q >> 5) & 31) + (q >> 10);
-                v = mom[(int64_t)s * P + al] * ((na & 1) ? -scale : scale);
-            }
-            Ms[al * 16 + col] = v;
+// T_c[b][a] = rs_c[b] (-1)^|a| D_c[a + b], laid out as [kt][mt][lane] with
+// b = 16 mt + lane % 16, a = 4 kt + lane / 16; complex tables hold the real
+// plane then the imaginary plane.
+template <class R, bool HELM>
+__global__ void k_expand_T(const double *D64, const int32_t *pk, const int32_t *cls_delta, const double *inv_fact,
+                           int P, int P2, R *T) {
+    const int c = blockIdx.x, mk = blockIdx.y, lane = threadIdx.x;
+    const int kt = mk / MT, mt = mk % MT;
+    const int b = 16 * mt + (lane & 15), al = 4 * kt + (lane >> 4);
+    double vr = 0.0, vi = 0.0;
+    if (b < P && al < P) {
+        const int qa = pk[al], qb = pk[b];
+        const int na = (qa & 31) + ((qa >> 5) & 31) + (qa >> 10);
+        const int nb = (qb & 31) + ((qb >> 5) & 31) + (qb >> 10);
+        const double f = inv_fact[b] * ldexp(1.0, -cls_delta[c] * nb) * ((na & 1) ? -1.0 : 1.0);
+        const int ix = sum_index(qa + qb);
+        if (HELM) {
+            vr = f * D64[2 * ((int64_t)c * P2 + ix)];
+            vi = f * D64[2 * ((int64_t)c * P2 + ix) + 1];
+        } else {
+            vr = f * D64[(int64_t)c * P2 + ix];
         }
     }
-    // each wave reads only the staging area it wrote: no block barrier is needed
-    __builtin_amdgcn_wave_barrier();
-    const int row = lane & 15, kq = lane >> 4;
-    int pb[MT];
-    for (int mt = 0; mt < MT; mt++) pb[mt] = pk[min(16 * mt + row, KT * 4 - 1)] * (16 * mt + row < P ? 1 : 0);
-    V4 acc[MT];
-    for (int mt = 0; mt < MT; mt++) acc[mt] = V4{0, 0, 0, 0};
-    for (int kt = 0; kt < KT; kt++) {
-        const int al = 4 * kt + kq;
-        const int pa = pk[al];
-        const R bv = Ms[al * 16 + row];
+    const int64_t o = (int64_t)(HELM ? 2 * c : c) * TSZ + (int64_t)mk * 64 + lane;
+    T[o] = (R)vr;
+    if (HELM) T[o + TSZ] = (R)vi;
+}
+
+struct M2lArgs {
+    const int32_t *task_class, *task_first, *task_count;
+    const int32_t *pair_slot, *pair_src, *pair_sym, *level;
+    const int32_t *sym_in;   // [NSYM][KIN]: source moment index (| SYM_NEG) of canonical index a'
+
+    double side;
+    int P;
+};
+
+// Number of register stages: loads run NS contraction steps ahead of their
+// use (symmetry indices 2 NS ahead), so the wave's own products cover their
+// latency; fewer stages where the accumulators take more registers.
+template <class R, int NA, int NCG>
+struct Pipe {
+    static constexpr int NS = sizeof(R) == 4 ? (NA * NCG == 1 ? 4 : 3) : (NA * NCG == 1 ? 3 : 2);
+};
+
+__device__ inline float flip_sign(float v, uint32_t s) { return __uint_as_float(__float_as_uint(v) ^ s); }
+__device__ inline double flip_sign(double v, uint32_t s) {
+    return __longlong_as_double(__double_as_longlong(v) ^ ((long long)s << 32));
+}
+
+// acc[q][g] += T_q (canonical operator plane q) x B_g over all contraction
+// steps, for a lane's share of the 16 x 16 tiles.  B_g is the column's
+// moment vector taken into the canonical frame: its entry a' is
+// ms_g[mstride * index] signed, (index, sign) = si_g[a'].
+template <class R, int NA, int NCG>
+__device__ inline void m2l_contract(const R *const (&Tp)[NA], const int32_t *const (&si)[NCG],
+                                    const R *const (&ms)[NCG], int mstride,
+                                    typename vec4<R>::type (&acc)[NA][NCG][MT]) {
+    constexpr int NS = Pipe<R, NA, NCG>::NS;
+    R A[NS][NA][MT], B[NS][NCG];
+    uint32_t sg[NS][NCG];
+    int32_t ix[NS][NCG];
 #pragma unroll
-        for (int mt = 0; mt < MT; mt++) acc[mt] = mfma(Dc[sum_index(pb[mt] + pa)], bv, acc[mt]);
-    }
-    const int col = row;
-    if (col < wcnt) {
-        const int j = a.pair_list[wfirst + col];
-        R *o = out + (int64_t)j * OUT_LD;
+    for (int q = 0; q < NA; q++)
+#pragma unroll
+        for (int g = 0; g < NCG; g++)
+#pragma unroll
+            for (int mt = 0; mt < MT; mt++) acc[q][g][mt] = typename vec4<R>::type{0, 0, 0, 0};
+    // ring set-up: indices of steps 0..NS-1, their moments, indices of NS..2NS-1, operator of 0..NS-1
+#pragma unroll
+    for (int i = 0; i < NS; i++)
+#pragma unroll
+        for (int g = 0; g < NCG; g++) ix[i][g] = si[g][4 * i];
+#pragma unroll
+    for (int i = 0; i < NS; i++)
+#pragma unroll
+        for (int g = 0; g < NCG; g++) {
+            B[i][g] = ms[g][mstride * (ix[i][g] & 0xffff)];
+            sg[i][g] = ((uint32_t)ix[i][g] & (uint32_t)SYM_NEG) << 1;
+            ix[i][g] = NS + i < KT ? si[g][4 * (NS + i)] : 0;
+        }
+#pragma unroll
+    for (int i = 0; i < NS; i++)
+#pragma unroll
+        for (int q = 0; q < NA; q++)
+#pragma unroll
+            for (int mt = 0; mt < MT; mt++) A[i][q][mt] = Tp[q][(i * MT + mt) * 64];
+#pragma unroll
+    for (int kt = 0; kt < KT; kt++) {
+        const int s = kt % NS;
+        R bv[NCG];
+#pragma unroll
+        for (int g = 0; g < NCG; g++) bv[g] = flip_sign(B[s][g], sg[s][g]);
+#pragma unroll
         for (int mt = 0; mt < MT; mt++)
-            for (int r = 0; r < 4; r++) {
-                const int b = 16 * mt + crow(R(0), kq, r);
-                o[b] = acc[mt][r] * rs[b];
+#pragma unroll
+            for (int q = 0; q < NA; q++)
+#pragma unroll
+                for (int g = 0; g < NCG; g++) acc[q][g][mt] = mfma(A[s][q][mt], bv[g], acc[q][g][mt]);
+        if (kt + NS < KT) {
+#pragma unroll
+            for (int q = 0; q < NA; q++)
+#pragma unroll
+                for (int mt = 0; mt < MT; mt++) A[s][q][mt] = Tp[q][((kt + NS) * MT + mt) * 64];
+#pragma unroll
+            for (int g = 0; g < NCG; g++) {
+                B[s][g] = ms[g][mstride * (ix[s][g] & 0xffff)];
+                sg[s][g] = ((uint32_t)ix[s][g] & (uint32_t)SYM_NEG) << 1;
+                if (kt + 2 * NS < KT) ix[s][g] = si[g][4 * (kt + 2 * NS)];
             }
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads where they are issued
+    }
+}
+
+// Real values: one wave per task of up to 16 NCG pairs of one class.  Columns
+// without a pair compute on the moments of box 0 and are not stored.
+template <class R, int NCG>
+__global__ void __launch_bounds__(64) k_m2l_mfma(M2lArgs a, const R *T, const R *mom, R *out) {
+    using V4 = typename vec4<R>::type;
+    const int lane = threadIdx.x, task = blockIdx.x;
+    const int cnt = a.task_count[task];
+    if (cnt == 0) return;
+    const int c = a.task_class[task], first = a.task_first[task], P = a.P;
+    const int col = lane & 15, kq = lane >> 4;
+    int src[NCG];
+    const int32_t *si[NCG];
+    const R *ms[NCG];
+#pragma unroll
+    for (int g = 0; g < NCG; g++) {
+        const int p = 16 * g + col;
+        src[g] = p < cnt ? a.pair_src[first + p] : 0;
+        si[g] = a.sym_in + (p < cnt ? a.pair_sym[first + p] : 0) * KIN + kq;
+        ms[g] = mom + (int64_t)src[g] * P;
+    }
+    const R *const Tp[1] = {T + (int64_t)c * TSZ + lane};
+    V4 acc[1][NCG][MT];
+    m2l_contract<R, 1, NCG>(Tp, si, ms, 1, acc);
+#pragma unroll
+    for (int g = 0; g < NCG; g++) {
+        const int p = 16 * g + col;
+        if (p < cnt) {
+            R *o = out + (int64_t)a.pair_slot[first + p] * OUT_LD;
+            const R scale = (R)ldexp(1.0 / a.side, a.level[src[g]]);  // 1 / rho_s
+#pragma unroll
+            for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) o[16 * mt + crow(R(0), kq, r)] = acc[0][g][mt][r] * scale;
+        }
     }
 }
 
 // Complex values: 8 pairs per wave, real and imaginary parts as 16 real columns.
 template <class R>
-__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_mfma_cx(M2lArgs a, const R *D /* interleaved */,
-                                                                const R *inv_fact, const cx<R> *mom, cx<R> *out) {
+__global__ void __launch_bounds__(64) k_m2l_mfma_cx(M2lArgs a, const R *T, const cx<R> *mom, cx<R> *out) {
     using V4 = typename vec4<R>::type;
-    extern __shared__ unsigned char smem[];
-    const int P = a.P, P2 = a.P2;
-    R *Dr = (R *)smem;
-    R *Di = Dr + P2;
-    R *rs = Di + P2;
-    int *pk = (int *)(rs + OUT_LD);
-    R *MsAll = (R *)(pk + KT * 4);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, task = blockIdx.x;
-    const int c = a.task_class[task], first = a.task_first[task], cnt = a.task_count[task];
-    const int delta = a.cls_delta[c];
-    for (int i = tid; i < P2; i += blockDim.x) {
-        Dr[i] = D[2 * ((int64_t)c * P2 + i)];
-        Di[i] = D[2 * ((int64_t)c * P2 + i) + 1];
-    }
-    for (int i = tid; i < KT * 4; i += blockDim.x) pk[i] = a.pk[i];
-    for (int i = tid; i < OUT_LD; i += blockDim.x) {
-        R v = 0;
-        if (i < P) {
-            const int q = a.pk[i], nb = (q & 31) + ((q >> 5) & 31) + (q >> 10);
-            v = inv_fact[i] * (R)ldexp(1.0, -delta * nb);
-        }
-        rs[i] = v;
-    }
-    __syncthreads();
-    const int wfirst = first + 8 * wave, wcnt = min(8, cnt - 8 * wave);
-    if (wcnt <= 0) return;
-    R *Ms = MsAll + wave * (KT * 4 * 16);
-    int my_s = -1;
-    R my_scale = 0;
-    if (lane < wcnt) {
-        my_s = a.inter_idx[a.pair_list[wfirst + lane]];
-        my_scale = (R)ldexp(1.0 / a.side, a.level[my_s]);
-    }
-#pragma unroll 2
-    for (int p = 0; p < 8; p++) {
-        const int s = __shfl(my_s, p, 64);
-        const R scale = __shfl(my_scale, p, 64);
-        for (int al = lane; al < KT * 4; al += 64) {
-            R vr = 0, vi = 0;
-            if (s >= 0 && al < P) {
-                const int q = pk[al], na = (q & 31) + ((q >> 5) & 31) + (q >> 10);
-                const R f = (na & 1) ? -scale : scale;
-                const cx<R> m = mom[(int64_t)s * P + al];
-                vr = m.re * f;
-                vi = m.im * f;
-            }
-            Ms[al * 16 + p] = vr;
-            Ms[al * 16 + 8 + p] = vi;
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-    const int row = lane & 15, kq = lane >> 4;
-    int pb[MT];
-    for (int mt = 0; mt < MT; mt++) pb[mt] = pk[min(16 * mt + row, KT * 4 - 1)] * (16 * mt + row < P ? 1 : 0);
-    V4 accR[MT], accI[MT];
-    for (int mt = 0; mt < MT; mt++) {
-        accR[mt] = V4{0, 0, 0, 0};
-        accI[mt] = V4{0, 0, 0, 0};
-    }
-    for (int kt = 0; kt < KT; kt++) {
-        const int al = 4 * kt + kq;
-        const int pa = pk[al];
-        const R bv = Ms[al * 16 + row];
-#pragma unroll
-        for (int mt = 0; mt < MT; mt++) {
-            const int ix = sum_index(pb[mt] + pa);
-            accR[mt] = mfma(Dr[ix], bv, accR[mt]);
-            accI[mt] = mfma(Di[ix], bv, accI[mt]);
-        }
-    }
+    const int lane = threadIdx.x, task = blockIdx.x;
+    const int cnt = a.task_count[task];
+    if (cnt == 0) return;
+    const int c = a.task_class[task], first = a.task_first[task], P = a.P;
+    const int col = lane & 15, kq = lane >> 4, p = col & 7;
+    const bool im_col = col >= 8;
+    const int src = p < cnt ? a.pair_src[first + p] : 0;
+    const int32_t *const si[1] = {a.sym_in + (p < cnt ? a.pair_sym[first + p] : 0) * KIN + kq};
+    const R *const ms[1] = {(const R *)(mom + (int64_t)src * P) + (im_col ? 1 : 0)};
+    const R *const Tp[2] = {T + (int64_t)(2 * c) * TSZ + lane, T + (int64_t)(2 * c + 1) * TSZ + lane};
+    V4 acc[2][1][MT];
+    m2l_contract<R, 2, 1>(Tp, si, ms, 2, acc);
     // lane with column p < 8 holds Tr.Mr and Ti.Mr of pair p; lane ^ 8 holds Tr.Mi and Ti.Mi
-    const int p = row & 7;
-    const bool lo = row < 8;
-    const int j = (lo && p < wcnt) ? a.pair_list[wfirst + p] : -1;
+    const bool store = !im_col && p < cnt;
+    cx<R> *o = out + (int64_t)(store ? a.pair_slot[first + p] : 0) * OUT_LD;
+    const R scale = (R)ldexp(1.0 / a.side, a.level[src]);
+#pragma unroll
     for (int mt = 0; mt < MT; mt++)
+#pragma unroll
         for (int r = 0; r < 4; r++) {
-            R trmi = __shfl_xor(accR[mt][r], 8, 64);
-            R timi = __shfl_xor(accI[mt][r], 8, 64);
-            const int b = 16 * mt + crow(R(0), kq, r);
-            if (j >= 0) {
-                const R f = rs[b];
-                out[(int64_t)j * OUT_LD + b] = cx<R>((accR[mt][r] - timi) * f, (trmi + accI[mt][r]) * f);
-            }
+            const R trmi = __shfl_xor(acc[0][0][mt][r], 8, 64);
+            const R timi = __shfl_xor(acc[1][0][mt][r], 8, 64);
+            if (store)
+                o[16 * mt + crow(R(0), kq, r)] =
+                    cx<R>((acc[0][0][mt][r] - timi) * scale, (trmi + acc[1][0][mt][r]) * scale);
         }
 }
 
-// Fh(b) += sum of the b's interaction-list slots, in list order.
+// Fh(b) += sum of the b's interaction-list slots, in list order, each slot's
+// canonical result taken back to the pair's frame: row i of slot j is the
+// canonical row sym_red[sym_j][i], signed.
 template <class V>
-__global__ void k_m2l_reduce(const int32_t *boxes, const int64_t *iptr, int P, const V *out, V *loc) {
+__global__ void k_m2l_reduce(const int32_t *boxes, const int64_t *iptr, const int32_t *slot_sym,
+                             const int16_t *sym_red, int P, const V *out, V *loc) {
     const int b = boxes[blockIdx.x];
+    const int64_t j0 = iptr[b], j1 = iptr[b + 1];
     for (int i = threadIdx.x; i < P; i += blockDim.x) {
         V acc = V(0.0);
-        const int64_t j0 = iptr[b], j1 = iptr[b + 1];
         int64_t j = j0;
+        auto term = [&](int64_t jj) {
+            const int e = sym_red[slot_sym[jj] * OUT_LD + i];
+            const V v = out[jj * OUT_LD + (e & 0xff)];
+            return (e & 0x100) ? V(0.0) - v : v;
+        };
         for (; j + 4 <= j1; j += 4) {
-            const V v0 = out[j * OUT_LD + i], v1 = out[(j + 1) * OUT_LD + i], v2 = out[(j + 2) * OUT_LD + i],
-                    v3 = out[(j + 3) * OUT_LD + i];
+            const V v0 = term(j), v1 = term(j + 1), v2 = term(j + 2), v3 = term(j + 3);
             acc += v0;
             acc += v1;
             acc += v2;
             acc += v3;
         }
-        for (; j < j1; j++) acc += out[j * OUT_LD + i];
+        for (; j < j1; j++) acc += term(j);
         loc[(int64_t)b * P + i] += acc;
     }
 }
@@ -349,6 +380,35 @@ uint64_t compact3h(uint64_t v) {
     return r;
 }
 
+// the six orderings of the axes; symmetry g = 8 * ordering + sign flips
+constexpr int PERMS[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+// Symmetry tables.  For symmetry g (canonical component i = actual axis
+// sigma(i), flipped axes f), canonical multi-index a' stands for the actual
+// multi-index a with a_{sigma(i)} = a'_i, with sign prod over flipped axes of
+// (-1)^(a_e).  in[g][a'] = index of a | SYM_NEG if negative (moments into the
+// canonical frame); red[g][index of a] = a' | 0x100 if negative (results
+// back to the pair's frame).
+void symmetry_tables(const std::vector<int8_t> &ex, int P, std::vector<int32_t> &in, std::vector<int16_t> &red) {
+    std::map<int, int> index;
+    for (int i = 0; i < P; i++) index[ex[3 * i] | (ex[3 * i + 1] << 5) | (ex[3 * i + 2] << 10)] = i;
+    in.assign((size_t)NSYM * KIN, 0);
+    red.assign((size_t)NSYM * OUT_LD, 0);
+    for (int g = 0; g < NSYM; g++) {
+        const int *sg = PERMS[g / 8], flips = g % 8;
+        for (int i = 0; i < P; i++) {
+            int act[3];
+            for (int k = 0; k < 3; k++) act[sg[k]] = ex[3 * i + k];
+            int par = 0;
+            for (int e = 0; e < 3; e++)
+                if (flips & (1 << e)) par += act[e];
+            const int ai = index.at(act[0] | (act[1] << 5) | (act[2] << 10));
+            in[(size_t)g * KIN + i] = ai | ((par & 1) ? SYM_NEG : 0);
+            red[(size_t)g * OUT_LD + ai] = (int16_t)(i | ((par & 1) ? 0x100 : 0));
+        }
+    }
+}
+
 }  // namespace
 
 M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
@@ -360,15 +420,16 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     plan_fmm(t);
     FmmTables &T = *t.tables;
     const int p = t.order, P = T.P, P2 = T.P2, H = 2 * p;
-    BEM_REQUIRE(P <= MT * 16 && P <= KT * 4, BEM_EUNSUPPORTED, "expansion order too high for the M2L tiles");
+    BEM_REQUIRE(P <= MT * 16 && P <= KIN, BEM_EUNSUPPORTED, "expansion order too high for the M2L tiles");
     const bool helm = green == BEM_HELMHOLTZ;
     auto pl = std::make_unique<M2lPlan>();
     pl->green = green;
     pl->k = k;
     if (t.h_prefix.empty()) t.h_prefix = t.prefix.download(t.n_box);
-    // classes of the interaction pairs of boxes with targets
+    // canonical classes of the interaction pairs of boxes with targets
     std::unordered_map<ClassKey, int32_t, ClassKeyHash> id;
-    std::vector<std::vector<int32_t>> members;
+    std::vector<std::vector<int32_t>> members;  // slots
+    std::vector<std::vector<int32_t>> msym;
     std::vector<int32_t> cdelta;
     std::vector<double> rbar, kbar;
     for (int64_t b = 0; b < t.n_box; b++) {
@@ -380,56 +441,81 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
             const int d = t.h_level[b] - t.h_level[s];
             const uint64_t ps = t.h_prefix[s];
             const int64_t is[3] = {(int64_t)compact3h(ps >> 2), (int64_t)compact3h(ps >> 1), (int64_t)compact3h(ps)};
-            int64_t q[3];
-            for (int e = 0; e < 3; e++) q[e] = (2 * ib[e] + 1) - ((2 * is[e] + 1) << d);
-            ClassKey key{d, (int32_t)q[0], (int32_t)q[1], (int32_t)q[2], helm ? t.h_level[s] : -1};
+            int64_t q[3], u[3];
+            int flips = 0;
+            for (int e = 0; e < 3; e++) {
+                q[e] = (2 * ib[e] + 1) - ((2 * is[e] + 1) << d);
+                u[e] = q[e] < 0 ? -q[e] : q[e];
+                if (q[e] < 0) flips |= 1 << e;
+            }
+            // canonical order: |q| ascending (ties by axis)
+            int perm = 0;
+            for (; perm < 6; perm++) {
+                const int *sg = PERMS[perm];
+                if (u[sg[0]] <= u[sg[1]] && u[sg[1]] <= u[sg[2]]) break;
+            }
+            const int *sg = PERMS[perm];
+            ClassKey key{d, (int32_t)u[sg[0]], (int32_t)u[sg[1]], (int32_t)u[sg[2]], helm ? t.h_level[s] : -1};
             auto it = id.find(key);
             int32_t cid;
             if (it == id.end()) {
                 cid = (int32_t)members.size();
                 id.emplace(key, cid);
                 members.emplace_back();
+                msym.emplace_back();
                 cdelta.push_back(d);
-                for (int e = 0; e < 3; e++) rbar.push_back(std::ldexp((double)q[e], -(d + 1)));
+                for (int e = 0; e < 3; e++) rbar.push_back(std::ldexp((double)u[sg[e]], -(d + 1)));
                 kbar.push_back(k * std::ldexp(t.side, -t.h_level[s]));
             } else {
                 cid = it->second;
             }
             members[cid].push_back((int32_t)j);
+            msym[cid].push_back(8 * perm + flips);
         }
     }
     pl->n_class = (int64_t)members.size();
-    const int cols = (helm ? 8 : 16) * M2L_WAVES;
-    std::vector<int32_t> plist, tc, tf, tn;
-    for (int32_t cl = 0; cl < (int32_t)members.size(); cl++) {
-        const int32_t base = (int32_t)plist.size();
-        plist.insert(plist.end(), members[cl].begin(), members[cl].end());
-        for (size_t o = 0; o < members[cl].size(); o += cols) {
-            tc.push_back(cl);
-            tf.push_back(base + (int32_t)o);
-            tn.push_back((int32_t)std::min<size_t>(cols, members[cl].size() - o));
+    // pairs grouped by class, largest class first
+    std::vector<int32_t> order(members.size());
+    for (size_t i = 0; i < order.size(); i++) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return members[x].size() > members[y].size(); });
+    std::vector<int32_t> slot, src, sym;
+    for (int32_t cl : order) {
+        pl->h_class_order.push_back(cl);
+        pl->h_class_first.push_back((int32_t)slot.size());
+        pl->h_class_count.push_back((int32_t)members[cl].size());
+        for (size_t i = 0; i < members[cl].size(); i++) {
+            slot.push_back(members[cl][i]);
+            src.push_back(t.h_inter_idx[members[cl][i]]);
+            sym.push_back(msym[cl][i]);
         }
     }
-    pl->n_pairs = (int64_t)plist.size();
-    pl->n_task = (int64_t)tc.size();
+    pl->n_pairs = (int64_t)slot.size();
     auto up = [&](DBuf<int32_t> &d, const std::vector<int32_t> &v) {
-        d.alloc(&c, v.size());
-        d.upload(v.data(), v.size());
+        d.alloc(&c, std::max<size_t>(1, v.size()));
+        if (!v.empty()) d.upload(v.data(), v.size());
     };
-    up(pl->pair_list, plist);
-    up(pl->task_class, tc);
-    up(pl->task_first, tf);
-    up(pl->task_count, tn);
+    up(pl->pair_slot, slot);
+    up(pl->pair_src, src);
+    up(pl->pair_sym, sym);
     up(pl->cls_delta, cdelta);
-    // packed multi-indices of the contraction rows
-    std::vector<int8_t> ex = T.h_exps;
-    std::vector<int32_t> pk(KT * 4, 0);
-    for (int i = 0; i < P; i++) pk[i] = ex[3 * i] | (ex[3 * i + 1] << 5) | (ex[3 * i + 2] << 10);
+    // packed multi-indices of the rows and contraction indices
+    std::vector<int32_t> pk(KIN, 0);
+    for (int i = 0; i < P; i++) pk[i] = T.h_exps[3 * i] | (T.h_exps[3 * i + 1] << 5) | (T.h_exps[3 * i + 2] << 10);
     up(pl->pk, pk);
-    // class derivative tables
+    std::vector<int32_t> sin;
+    std::vector<int16_t> sred;
+    symmetry_tables(T.h_exps, P, sin, sred);
+    up(pl->sym_in, sin);
+    pl->sym_red.alloc(&c, sred.size());
+    pl->sym_red.upload(sred.data(), sred.size());
+    // symmetry of every interaction-list slot (slots outside the plan stay 0)
+    std::vector<int32_t> ssym(std::max<int64_t>(1, t.n_inter), 0);
+    for (size_t i = 0; i < slot.size(); i++) ssym[slot[i]] = sym[i];
+    up(pl->slot_sym, ssym);
+    // class derivative tables at the canonical separations
     const int cw = helm ? 2 : 1;
     pl->D64.alloc(&c, (size_t)cw * P2 * std::max<int64_t>(1, pl->n_class));
-    pl->D32.alloc(&c, (size_t)cw * P2 * std::max<int64_t>(1, pl->n_class));
     if (pl->n_class) {
         DBuf<double> drb, dkb;
         drb.alloc(&c, rbar.size());
@@ -438,11 +524,9 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
         dkb.upload(kbar.data(), kbar.size());
         size_t sh = (size_t)cw * sizeof(double) * (2 * P2 + H + 2);
         if (helm)
-            k_class_derivs<true><<<(unsigned)pl->n_class, 256, sh, c.stream>>>(drb.p, dkb.p, H, T.exps.p, pl->D64.p,
-                                                                               pl->D32.p);
+            k_class_derivs<true><<<(unsigned)pl->n_class, 256, sh, c.stream>>>(drb.p, dkb.p, H, T.exps.p, pl->D64.p);
         else
-            k_class_derivs<false><<<(unsigned)pl->n_class, 256, sh, c.stream>>>(drb.p, dkb.p, H, T.exps.p, pl->D64.p,
-                                                                                pl->D32.p);
+            k_class_derivs<false><<<(unsigned)pl->n_class, 256, sh, c.stream>>>(drb.p, dkb.p, H, T.exps.p, pl->D64.p);
         BEM_LAUNCH_CHECK();
         c.sync();
     }
@@ -450,41 +534,125 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     return *t.m2l.back();
 }
 
+namespace {
+
+// Tasks of `cols` pairs: each class, largest first, goes to the least-loaded
+// of the 8 XCD queues, and the queues are interleaved so that block i runs
+// on XCD i mod 8.  Padding tasks have no pairs.
+M2lTasks &get_tasks(Ctx &c, M2lPlan &pl, int cols) {
+    for (auto &tk : pl.tasks)
+        if (tk->cols == cols) return *tk;
+    constexpr int NXCD = 8;
+    std::vector<std::vector<int32_t>> qc(NXCD), qf(NXCD), qn(NXCD);
+    std::vector<int64_t> load(NXCD, 0);
+    for (size_t i = 0; i < pl.h_class_order.size(); i++) {
+        const int32_t cl = pl.h_class_order[i], f0 = pl.h_class_first[i], n = pl.h_class_count[i];
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        for (int32_t o = 0; o < n; o += cols) {
+            qc[x].push_back(cl);
+            qf[x].push_back(f0 + o);
+            qn[x].push_back(std::min(cols, n - o));
+            load[x]++;
+        }
+    }
+    size_t qmax = 0;
+    for (int x = 0; x < NXCD; x++) qmax = std::max(qmax, qc[x].size());
+    std::vector<int32_t> tc(qmax * NXCD, 0), tf(qmax * NXCD, 0), tn(qmax * NXCD, 0);
+    for (int x = 0; x < NXCD; x++)
+        for (size_t i = 0; i < qc[x].size(); i++) {
+            tc[i * NXCD + x] = qc[x][i];
+            tf[i * NXCD + x] = qf[x][i];
+            tn[i * NXCD + x] = qn[x][i];
+        }
+    auto tk = std::make_unique<M2lTasks>();
+    tk->cols = cols;
+    tk->n_task = (int64_t)tc.size();
+    auto up = [&](DBuf<int32_t> &d, const std::vector<int32_t> &v) {
+        d.alloc(&c, std::max<size_t>(1, v.size()));
+        if (!v.empty()) d.upload(v.data(), v.size());
+    };
+    up(tk->task_class, tc);
+    up(tk->task_first, tf);
+    up(tk->task_count, tn);
+    pl.tasks.push_back(std::move(tk));
+    return *pl.tasks.back();
+}
+
+// expanded operators of the plan in precision R (built on first use)
+template <class R>
+const R *expanded(bem_tree &t, M2lPlan &pl) {
+    Ctx &c = *t.ctx;
+    FmmTables &T = *t.tables;
+    DBuf<R> &buf = pl.expanded_buf<R>();
+    if (!buf.p && pl.n_class) {
+        const bool helm = pl.green == BEM_HELMHOLTZ;
+        buf.alloc(&c, (size_t)(helm ? 2 : 1) * TSZ * pl.n_class);
+        dim3 g((unsigned)pl.n_class, MT * KT);
+        if (helm)
+            k_expand_T<R, true><<<g, 64, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p, T.inv_fact64.p, T.P, T.P2,
+                                                        buf.p);
+        else
+            k_expand_T<R, false><<<g, 64, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p, T.inv_fact64.p, T.P,
+                                                         T.P2, buf.p);
+        BEM_LAUNCH_CHECK();
+        c.sync();
+    }
+    return buf.p;
+}
+
+// pair columns per wave: two column groups for real FP32, one otherwise
+template <class V, class R>
+constexpr int m2l_ncg() {
+    return std::is_same<V, float>::value ? 2 : 1;
+}
+template <class V, class R>
+constexpr int m2l_cols() {
+    return std::is_same<V, R>::value ? 16 * m2l_ncg<V, R>() : 8;
+}
+
+}  // namespace
+
+template <class V, class R>
+void m2l_prepare(bem_tree &t, M2lPlan &pl) {
+    expanded<R>(t, pl);
+    get_tasks(*t.ctx, pl, m2l_cols<V, R>());
+}
+
 template <class V, class R>
 void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc) {
     Ctx &c = *t.ctx;
     FmmTables &T = *t.tables;
     const int P = T.P;
-    if (!pl.n_task) return;
+    M2lTasks &tk = get_tasks(c, pl, m2l_cols<V, R>());
+    if (!tk.n_task || !pl.n_pairs) {
+        c.mark(3);
+        return;
+    }
     t.work.m2l_out.ensure(&c, sizeof(V) * (size_t)std::max<int64_t>(1, t.n_inter) * OUT_LD);
     V *out = (V *)t.work.m2l_out.p;
-    M2lArgs a{pl.task_class.p, pl.task_first.p, pl.task_count.p, pl.pair_list.p, t.inter_idx.p, t.level.p,
-              pl.cls_delta.p, pl.pk.p, t.side, P, T.P2, t.n_box, t.n_inter};
-    const int cw = std::is_same<V, R>::value ? 1 : 2;
-    const size_t sh = sizeof(R) * (cw * T.P2 + OUT_LD) + sizeof(int) * KT * 4 + sizeof(R) * M2L_WAVES * KT * 4 * 16;
-    const bool f32 = std::is_same<R, float>::value;
-    const R *invf = f32 ? (const R *)T.inv_fact32.p : (const R *)T.inv_fact64.p;
-    const R *D = f32 ? (const R *)pl.D32.p : (const R *)pl.D64.p;
-    if (sh > 64 * 1024) {
-        if constexpr (std::is_same<V, R>::value)
-            BEM_HIP(hipFuncSetAttribute((const void *)k_m2l_mfma<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
-        else
-            BEM_HIP(hipFuncSetAttribute((const void *)k_m2l_mfma_cx<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)sh));
-    }
+    M2lArgs a{tk.task_class.p, tk.task_first.p, tk.task_count.p, pl.pair_slot.p, pl.pair_src.p, pl.pair_sym.p,
+              t.level.p, pl.sym_in.p, t.side, P};
+    const R *Tx = expanded<R>(t, pl);
     for (int rhs = 0; rhs < nrhs; rhs++) {
         const V *m = mom + (int64_t)rhs * t.n_box * P;
         V *l = loc + (int64_t)rhs * t.n_box * P;
         if constexpr (std::is_same<V, R>::value)
-            k_m2l_mfma<R><<<(unsigned)pl.n_task, 64 * M2L_WAVES, sh, c.stream>>>(a, D, invf, m, out);
+            k_m2l_mfma<R, m2l_ncg<V, R>()><<<(unsigned)tk.n_task, 64, 0, c.stream>>>(a, Tx, m, out);
         else
-            k_m2l_mfma_cx<R><<<(unsigned)pl.n_task, 64 * M2L_WAVES, sh, c.stream>>>(a, D, invf, m, out);
+            k_m2l_mfma_cx<R><<<(unsigned)tk.n_task, 64, 0, c.stream>>>(a, Tx, m, out);
         BEM_LAUNCH_CHECK();
-        k_m2l_reduce<V><<<(unsigned)t.n_m2l_boxes, 192, 0, c.stream>>>(t.m2l_boxes.p, t.inter_ptr.p, P, out, l);
+        c.mark(3);
+        k_m2l_reduce<V><<<(unsigned)t.n_m2l_boxes, 192, 0, c.stream>>>(t.m2l_boxes.p, t.inter_ptr.p, pl.slot_sym.p,
+                                                                       pl.sym_red.p, P, out, l);
         BEM_LAUNCH_CHECK();
+        c.mark(10);
     }
 }
 
+template void m2l_prepare<double, double>(bem_tree &, M2lPlan &);
+template void m2l_prepare<float, float>(bem_tree &, M2lPlan &);
+template void m2l_prepare<cx<double>, double>(bem_tree &, M2lPlan &);
+template void m2l_prepare<cx<float>, float>(bem_tree &, M2lPlan &);
 template void m2l_apply<double, double>(bem_tree &, M2lPlan &, int, const double *, double *);
 template void m2l_apply<float, float>(bem_tree &, M2lPlan &, int, const float *, float *);
 template void m2l_apply<cx<double>, double>(bem_tree &, M2lPlan &, int, const cx<double> *, cx<double> *);
