@@ -61,8 +61,17 @@ constexpr int P2P_BS = 256;
 constexpr int P2P_TILE = 256;
 constexpr int P2P_CH = 256;  // near-list entries per chunk
 
-__device__ inline float inv_sqrt(float v) { return rsqrtf(v); }
-__device__ inline double inv_sqrt(double v) { return 1.0 / sqrt(v); }
+// 1/sqrt(v) for v > 0 far from the denormal range (squared distances of
+// distinct points): the hardware estimate, which is within 1 ulp in single
+// precision; in double precision it is refined by two Newton steps
+// y <- y + y (1/2 - (v/2) y^2), each of which squares the relative error.
+__device__ inline float inv_sqrt(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ inline double inv_sqrt(double v) {
+    double y = __builtin_amdgcn_rsq(v);
+    const double h = 0.5 * v;
+    for (int i = 0; i < 2; i++) y = fma(y, fma(-h * y, y, 0.5), y);
+    return y;
+}
 
 template <class R> struct r4;
 template <> struct r4<float> { using type = float4; };
@@ -103,10 +112,13 @@ __device__ inline V p2p_term(double x0, double x1, double x2, double2 sxy, doubl
 // so close pairs keep their relative accuracy in the mixed path; per-batch
 // partial sums in R are added into an FP64 total.
 template <class V, class R, bool DBL, bool HELM>
-__global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *wi_box, const int32_t *wi_t0, const int32_t *wi_nt,
-                                                const int64_t *nptr, const int32_t *nidx, const int64_t *eb,
-                                                const int64_t *ee, const double *q64, const R *q, int64_t n_q,
-                                                const V *s, const double *t64, int64_t n_tgt, R k, V *y) {
+__global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const int32_t *unit_item,
+                                                const int64_t *unit_f, int64_t n_unit, const int32_t *wi_box,
+                                                const int32_t *wi_t0, const int32_t *wi_nt, const int64_t *nptr,
+                                                const int32_t *nidx, const int64_t *eb, const int64_t *ee,
+                                                const double *q64, const R *q, int64_t n_q, const V *s,
+                                                const double *t64, int64_t n_tgt, R k,
+                                                typename std::conditional<HELM, cx<double>, double>::type *part) {
     using VD = typename std::conditional<HELM, cx<double>, double>::type;
     using R4 = typename r4<R>::type;
     constexpr int NW = P2P_BS / 64;
@@ -117,7 +129,9 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *wi_box, const int
     __shared__ R4 sns[NW][2][64];
     __shared__ R ssi[NW][2][HELM ? 64 : 1];
     __shared__ VD red[NW][64];
-    const int w = blockIdx.x, rhs = blockIdx.y;
+    const int u = unit_order[blockIdx.x], rhs = blockIdx.y;
+    const int w = unit_item[u];
+    const int64_t u0 = unit_f[2 * u], u1 = unit_f[2 * u + 1];  // the unit's share of the item's near points
     const int b = wi_box[w], t0 = wi_t0[w], nt = wi_nt[w];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int npair = (nt + 1) >> 1;  // lanes needed, two targets each
@@ -130,7 +144,8 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *wi_box, const int
     const V *sr = s + (int64_t)rhs * n_q;
     VD tot_a = VD(0.0), tot_b = VD(0.0);
     const int64_t j0 = nptr[b], j1 = nptr[b + 1];
-    for (int64_t cb = j0; cb < j1; cb += P2P_CH) {
+    int64_t base = 0;  // position of the chunk's first point in the item's near-point sequence
+    for (int64_t cb = j0; cb < j1 && base < u1; cb += P2P_CH) {
         const int nc = (int)min<int64_t>(P2P_CH, j1 - cb);
         // run lengths of the chunk's near-list boxes, scanned by the first wave
         if (tid < 64) {
@@ -155,9 +170,11 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *wi_box, const int
         }
         __syncthreads();
         const int64_t total = pref[nc];
-        // this wave's share of the chunk's points
-        const int64_t per = (total + NW - 1) / NW;
-        const int64_t f0 = min(total, per * wave), f1 = min(total, f0 + per);
+        // this wave's share of the unit's points in the chunk
+        const int64_t g0 = max<int64_t>(0, u0 - base), g1 = min<int64_t>(total, u1 - base);
+        const int64_t gn = max<int64_t>(0, g1 - g0), per = (gn + NW - 1) / NW;
+        const int64_t f0 = g0 + min(gn, per * wave), f1 = g0 + min(gn, per * wave + per);
+        base += total;
         int e = 0;  // run holding this lane's current point
         auto fetch = [&](int64_t f, double2 &pxy, double &pz, R4 &ns, R &si) {
             if (f < f1) {
@@ -224,10 +241,25 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *wi_box, const int
     if (tid < nt) {
         VD v = red[0][tid];
         for (int wv = 1; wv < NW; wv++) v += red[wv][tid];
-        if constexpr (!HELM) v = v * kInv4Pi;
-        V *dst = y + (int64_t)rhs * n_tgt + t0 + tid;
-        *dst = vcast<V>(vcast<VD>(*dst) + v);
+        part[((int64_t)rhs * n_unit + u) * 64 + tid] = v;
     }
+}
+
+// y(targets of item w) += the item's unit partial sums, in unit order (1/4pi
+// applied here for Laplace).
+template <class V, bool HELM>
+__global__ void k_p2p_finish(int64_t n_items, const int32_t *item_unit, const int32_t *wi_t0, const int32_t *wi_nt,
+                             const typename std::conditional<HELM, cx<double>, double>::type *part, int64_t n_unit,
+                             int64_t n_tgt, V *y) {
+    using VD = typename std::conditional<HELM, cx<double>, double>::type;
+    const int64_t w = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const int tid = threadIdx.x & 63, rhs = blockIdx.y;
+    if (w >= n_items || tid >= wi_nt[w]) return;
+    VD v = VD(0.0);
+    for (int32_t u = item_unit[w]; u < item_unit[w + 1]; u++) v += part[((int64_t)rhs * n_unit + u) * 64 + tid];
+    if constexpr (!HELM) v = v * kInv4Pi;
+    V *dst = y + (int64_t)rhs * n_tgt + wi_t0[w] + tid;
+    *dst = vcast<V>(vcast<VD>(*dst) + v);
 }
 
 // ---------------------------------------------------------------- direct (FP64)
@@ -417,6 +449,56 @@ void plan_fmm(bem_tree &t) {
     t.p2p_t0 = upload_i32(c, wt0);
     t.p2p_nt = upload_i32(c, wnt);
     t.n_p2p_items = (int64_t)wb.size();
+    // work units: each item's near points split into shares of about equal
+    // cost (points x lanes per point), so that blocks balance over the CUs;
+    // dispatched most expensive first
+    {
+        const size_t ni = wb.size();
+        std::vector<int64_t> npts(ni);
+        std::vector<double> cpp(ni);  // cost per point: a wave covers 64 / tpw points per step
+        double total = 0.0;
+        for (size_t i = 0; i < ni; i++) {
+            const int32_t b = wb[i];
+            int64_t n = 0;
+            for (int64_t j = t.h_near_ptr[b]; j < t.h_near_ptr[b + 1]; j++) {
+                const int32_t s = t.h_near_idx[j];
+                n += 7 * (t.h_ee[s] - t.h_eb[s]);
+            }
+            int tpw = 1;
+            while (tpw < (wnt[i] + 1) / 2) tpw <<= 1;
+            npts[i] = n;
+            cpp[i] = tpw / 64.0;
+            total += n * cpp[i];
+        }
+        int n_cu = 256;
+        (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c.device);
+        const double target = std::max(total / (16.0 * std::max(1, n_cu)), 1.0);
+        std::vector<int32_t> uitem, iunit(ni + 1, 0);
+        std::vector<int64_t> uf;
+        std::vector<double> ucost;
+        for (size_t i = 0; i < ni; i++) {
+            iunit[i] = (int32_t)uitem.size();
+            int64_t parts = (int64_t)std::ceil(npts[i] * cpp[i] / target);
+            // at least one batch of 64 points per wave in a unit
+            parts = std::max<int64_t>(1, std::min<int64_t>(parts, npts[i] / (64 * (P2P_BS / 64))));
+            for (int64_t k = 0; k < parts; k++) {
+                uitem.push_back((int32_t)i);
+                uf.push_back(npts[i] * k / parts);
+                uf.push_back(npts[i] * (k + 1) / parts);
+                ucost.push_back((double)(npts[i] * (k + 1) / parts - npts[i] * k / parts) * cpp[i]);
+            }
+        }
+        iunit[ni] = (int32_t)uitem.size();
+        std::vector<int32_t> order(uitem.size());
+        for (size_t i = 0; i < order.size(); i++) order[i] = (int32_t)i;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ucost[a] > ucost[b]; });
+        t.n_p2p_units = (int64_t)uitem.size();
+        t.p2p_unit_order = upload_i32(c, order);
+        t.p2p_unit_item = upload_i32(c, uitem);
+        t.p2p_item_unit = upload_i32(c, iunit);
+        t.p2p_unit_f.alloc(&c, uf.size());
+        t.p2p_unit_f.upload(uf.data(), uf.size());
+    }
     // near-field pair count: targets x source points
     t.n_p2p_pairs = 0;
     for (int64_t b = 0; b < t.n_box; b++) {
@@ -547,15 +629,22 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         l2p_apply<V, R>(t, nrhs, loc, yacc);
         c.mark(5);
         if (t.n_p2p_items) {
-            dim3 g((unsigned)t.n_p2p_items, nrhs);
+            using VD = typename std::conditional<HELM, cx<double>, double>::type;
+            t.work.p2p_part.ensure(&c, sizeof(VD) * 64 * (size_t)t.n_p2p_units * nrhs);
+            VD *part = (VD *)t.work.p2p_part.p;
+            dim3 g((unsigned)t.n_p2p_units, nrhs);
             if (dbl)
-                k_p2p<V, R, true, HELM><<<g, P2P_BS, 0, c.stream>>>(t.p2p_box.p, t.p2p_t0.p, t.p2p_nt.p,
-                                                                    t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p,
-                                                                    t.q64.p, q, nq, s, t.t64.p, nt, (R)k, yacc);
+                k_p2p<V, R, true, HELM><<<g, P2P_BS, 0, c.stream>>>(
+                    t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
+                    t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
             else
-                k_p2p<V, R, false, HELM><<<g, P2P_BS, 0, c.stream>>>(t.p2p_box.p, t.p2p_t0.p, t.p2p_nt.p,
-                                                                     t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p,
-                                                                     t.q64.p, q, nq, s, t.t64.p, nt, (R)k, yacc);
+                k_p2p<V, R, false, HELM><<<g, P2P_BS, 0, c.stream>>>(
+                    t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
+                    t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
+            BEM_LAUNCH_CHECK();
+            dim3 gf((unsigned)((t.n_p2p_items + 3) / 4), nrhs);
+            k_p2p_finish<V, HELM><<<gf, 256, 0, c.stream>>>(t.n_p2p_items, t.p2p_item_unit.p, t.p2p_t0.p, t.p2p_nt.p,
+                                                           part, t.n_p2p_units, nt, yacc);
             BEM_LAUNCH_CHECK();
         }
         c.mark(6);

@@ -68,7 +68,9 @@ struct M2lPlan {
     DBuf<int32_t> cls_delta;          // level difference of the class
     DBuf<int32_t> pair_slot;          // interaction-list slot of each pair, grouped by class
     DBuf<int32_t> pair_src;           // source box of each pair
-    DBuf<int32_t> pair_sym;           // symmetry taking the pair to its class's canonical frame
+    DBuf<int32_t> pair_mom;           // canonical moment vector (source box, symmetry) of each pair
+    int64_t n_u = 0;                  // used (source box, symmetry) combinations
+    DBuf<int32_t> u_src, u_sym;
     std::vector<int32_t> h_class_order, h_class_first, h_class_count;  // classes, largest first
     std::vector<std::unique_ptr<M2lTasks>> tasks;
     DBuf<int32_t> pk;                 // packed multi-indices of the contraction rows
@@ -100,7 +102,7 @@ struct PassTables {
 
 // Per-matvec work buffers, grown on demand and kept on the tree.
 struct Work {
-    DBuf<char> strength, mom, loc, yacc, m2l_out;
+    DBuf<char> strength, mom, loc, yacc, m2l_out, m2l_mom, p2p_part;
 };
 
 }  // namespace bem
@@ -141,6 +143,11 @@ struct bem_tree {
     // P2P work items: (target leaf, first sorted target, count <= 64)
     bem::DBuf<int32_t> p2p_box, p2p_t0, p2p_nt;
     int64_t n_p2p_items = 0, n_p2p_pairs = 0;
+    // P2P work units: shares of an item's near points (item, [f0, f1)), and
+    // the units of each item ([item_unit[i], item_unit[i + 1]))
+    int64_t n_p2p_units = 0;
+    bem::DBuf<int32_t> p2p_unit_order, p2p_unit_item, p2p_item_unit;
+    bem::DBuf<int64_t> p2p_unit_f;
     bem::DBuf<int32_t> leaf_ids;       // leaf boxes with elements (P2M)
     int64_t n_leaf_src = 0;
     bem::DBuf<int32_t> tleaf_ids;      // leaf boxes with targets (L2P)

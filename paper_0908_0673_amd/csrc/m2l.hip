@@ -30,9 +30,10 @@
 // streams it with one coalesced 256-byte load per product; the canonical
 // operators of a tree take a few MB and stay resident in the L2 caches.  One
 // wave takes a class and up to 16 NCG pair columns (8 complex pairs as 16
-// real columns); its B operands are the pairs' moments gathered through the
-// symmetry tables, and it stores each pair's canonical result whole (the
-// stores are contiguous).  Tasks are ordered so that every wave of a class is dispatched
+// real columns); its B operands are the pairs' moments in the canonical
+// frame, which a small kernel first writes once per used (source box,
+// symmetry) combination so that the product reads them contiguously, and it
+// stores each pair's canonical result whole (the stores are contiguous).  Tasks are ordered so that every wave of a class is dispatched
 // to the same XCD (blocks go round-robin over the 8 XCDs), whose L2 then
 // holds that class's operator.  Each pair's result goes to its slot in the
 // interaction list; a second kernel sums every target box's slots in list
@@ -178,57 +179,68 @@ __global__ void k_expand_T(const double *D64, const int32_t *pk, const int32_t *
 
 struct M2lArgs {
     const int32_t *task_class, *task_first, *task_count;
-    const int32_t *pair_slot, *pair_src, *pair_sym, *level;
-    const int32_t *sym_in;   // [NSYM][KIN]: source moment index (| SYM_NEG) of canonical index a'
+    const int32_t *pair_slot, *pair_src, *pair_mom, *level;
 
     double side;
     int P;
 };
 
-// Number of register stages: loads run NS contraction steps ahead of their
-// use (symmetry indices 2 NS ahead), so the wave's own products cover their
-// latency; fewer stages where the accumulators take more registers.
+// Moments in the canonical frame of each used (source box, symmetry)
+// combination u: Mc[u][a'] = sign * M_src[index], (index, sign) = sym_in[sym][a'],
+// zero past P.  One wave per combination.
+template <class V>
+__global__ void k_m2l_canonical_moments(int64_t n_u, const int32_t *u_src, const int32_t *u_sym,
+                                        const int32_t *sym_in, int P, const V *mom, V *Mc) {
+    const int64_t u = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    if (u >= n_u) return;
+    const int lane = threadIdx.x & 63;
+    const V *ms = mom + (int64_t)u_src[u] * P;
+    const int32_t *si = sym_in + u_sym[u] * KIN;
+    constexpr int NIT = (KIN + 63) / 64;
+    int32_t e[NIT];
+    V v[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int a = lane + 64 * it;
+        e[it] = a < P ? si[a] : -1;
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; it++) v[it] = e[it] >= 0 ? ms[e[it] & 0xffff] : V(0.0);
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int a = lane + 64 * it;
+        if (a < KIN) Mc[u * KIN + a] = (e[it] >= 0 && (e[it] & SYM_NEG)) ? V(0.0) - v[it] : v[it];
+    }
+}
+
+// Number of register stages: operator loads run NS contraction steps ahead
+// of their use and moment loads NB steps (they come from further away), so
+// the wave's own products cover their latency; fewer stages where the
+// accumulators take more registers.
 template <class R, int NA, int NCG>
 struct Pipe {
     static constexpr int NS = sizeof(R) == 4 ? (NA * NCG == 1 ? 4 : 3) : (NA * NCG == 1 ? 3 : 2);
+    static constexpr int NB = 2 * NS + 2;
 };
 
-__device__ inline float flip_sign(float v, uint32_t s) { return __uint_as_float(__float_as_uint(v) ^ s); }
-__device__ inline double flip_sign(double v, uint32_t s) {
-    return __longlong_as_double(__double_as_longlong(v) ^ ((long long)s << 32));
-}
-
 // acc[q][g] += T_q (canonical operator plane q) x B_g over all contraction
-// steps, for a lane's share of the 16 x 16 tiles.  B_g is the column's
-// moment vector taken into the canonical frame: its entry a' is
-// ms_g[mstride * index] signed, (index, sign) = si_g[a'].
+// steps, for a lane's share of the 16 x 16 tiles; B_g step kt is
+// ms_g[mstride * 4 kt] (the lane's row of the column's canonical moments).
 template <class R, int NA, int NCG>
-__device__ inline void m2l_contract(const R *const (&Tp)[NA], const int32_t *const (&si)[NCG],
-                                    const R *const (&ms)[NCG], int mstride,
+__device__ inline void m2l_contract(const R *const (&Tp)[NA], const R *const (&ms)[NCG], int mstride,
                                     typename vec4<R>::type (&acc)[NA][NCG][MT]) {
-    constexpr int NS = Pipe<R, NA, NCG>::NS;
-    R A[NS][NA][MT], B[NS][NCG];
-    uint32_t sg[NS][NCG];
-    int32_t ix[NS][NCG];
+    constexpr int NS = Pipe<R, NA, NCG>::NS, NB = Pipe<R, NA, NCG>::NB;
+    R A[NS][NA][MT], B[NB][NCG];
 #pragma unroll
     for (int q = 0; q < NA; q++)
 #pragma unroll
         for (int g = 0; g < NCG; g++)
 #pragma unroll
             for (int mt = 0; mt < MT; mt++) acc[q][g][mt] = typename vec4<R>::type{0, 0, 0, 0};
-    // ring set-up: indices of steps 0..NS-1, their moments, indices of NS..2NS-1, operator of 0..NS-1
 #pragma unroll
-    for (int i = 0; i < NS; i++)
+    for (int i = 0; i < NB; i++)
 #pragma unroll
-        for (int g = 0; g < NCG; g++) ix[i][g] = si[g][4 * i];
-#pragma unroll
-    for (int i = 0; i < NS; i++)
-#pragma unroll
-        for (int g = 0; g < NCG; g++) {
-            B[i][g] = ms[g][mstride * (ix[i][g] & 0xffff)];
-            sg[i][g] = ((uint32_t)ix[i][g] & (uint32_t)SYM_NEG) << 1;
-            ix[i][g] = NS + i < KT ? si[g][4 * (NS + i)] : 0;
-        }
+        for (int g = 0; g < NCG; g++) B[i][g] = ms[g][mstride * 4 * i];
 #pragma unroll
     for (int i = 0; i < NS; i++)
 #pragma unroll
@@ -237,61 +249,50 @@ __device__ inline void m2l_contract(const R *const (&Tp)[NA], const int32_t *con
             for (int mt = 0; mt < MT; mt++) A[i][q][mt] = Tp[q][(i * MT + mt) * 64];
 #pragma unroll
     for (int kt = 0; kt < KT; kt++) {
-        const int s = kt % NS;
-        R bv[NCG];
-#pragma unroll
-        for (int g = 0; g < NCG; g++) bv[g] = flip_sign(B[s][g], sg[s][g]);
+        const int s = kt % NS, sb = kt % NB;
 #pragma unroll
         for (int mt = 0; mt < MT; mt++)
 #pragma unroll
             for (int q = 0; q < NA; q++)
 #pragma unroll
-                for (int g = 0; g < NCG; g++) acc[q][g][mt] = mfma(A[s][q][mt], bv[g], acc[q][g][mt]);
-        if (kt + NS < KT) {
+                for (int g = 0; g < NCG; g++) acc[q][g][mt] = mfma(A[s][q][mt], B[sb][g], acc[q][g][mt]);
+        if (kt + NB < KT)
+#pragma unroll
+            for (int g = 0; g < NCG; g++) B[sb][g] = ms[g][mstride * 4 * (kt + NB)];
+        if (kt + NS < KT)
 #pragma unroll
             for (int q = 0; q < NA; q++)
 #pragma unroll
                 for (int mt = 0; mt < MT; mt++) A[s][q][mt] = Tp[q][((kt + NS) * MT + mt) * 64];
-#pragma unroll
-            for (int g = 0; g < NCG; g++) {
-                B[s][g] = ms[g][mstride * (ix[s][g] & 0xffff)];
-                sg[s][g] = ((uint32_t)ix[s][g] & (uint32_t)SYM_NEG) << 1;
-                if (kt + 2 * NS < KT) ix[s][g] = si[g][4 * (kt + 2 * NS)];
-            }
-        }
         __builtin_amdgcn_sched_barrier(0);  // keep the loads where they are issued
     }
 }
 
 // Real values: one wave per task of up to 16 NCG pairs of one class.  Columns
-// without a pair compute on the moments of box 0 and are not stored.
+// without a pair compute on the first canonical moments and are not stored.
 template <class R, int NCG>
-__global__ void __launch_bounds__(64) k_m2l_mfma(M2lArgs a, const R *T, const R *mom, R *out) {
+__global__ void __launch_bounds__(64) k_m2l_mfma(M2lArgs a, const R *T, const R *Mc, R *out) {
     using V4 = typename vec4<R>::type;
     const int lane = threadIdx.x, task = blockIdx.x;
     const int cnt = a.task_count[task];
     if (cnt == 0) return;
-    const int c = a.task_class[task], first = a.task_first[task], P = a.P;
+    const int c = a.task_class[task], first = a.task_first[task];
     const int col = lane & 15, kq = lane >> 4;
-    int src[NCG];
-    const int32_t *si[NCG];
     const R *ms[NCG];
 #pragma unroll
     for (int g = 0; g < NCG; g++) {
         const int p = 16 * g + col;
-        src[g] = p < cnt ? a.pair_src[first + p] : 0;
-        si[g] = a.sym_in + (p < cnt ? a.pair_sym[first + p] : 0) * KIN + kq;
-        ms[g] = mom + (int64_t)src[g] * P;
+        ms[g] = Mc + (int64_t)(p < cnt ? a.pair_mom[first + p] : 0) * KIN + kq;
     }
     const R *const Tp[1] = {T + (int64_t)c * TSZ + lane};
     V4 acc[1][NCG][MT];
-    m2l_contract<R, 1, NCG>(Tp, si, ms, 1, acc);
+    m2l_contract<R, 1, NCG>(Tp, ms, 1, acc);
 #pragma unroll
     for (int g = 0; g < NCG; g++) {
         const int p = 16 * g + col;
         if (p < cnt) {
             R *o = out + (int64_t)a.pair_slot[first + p] * OUT_LD;
-            const R scale = (R)ldexp(1.0 / a.side, a.level[src[g]]);  // 1 / rho_s
+            const R scale = (R)ldexp(1.0 / a.side, a.level[a.pair_src[first + p]]);  // 1 / rho_s
 #pragma unroll
             for (int mt = 0; mt < MT; mt++)
 #pragma unroll
@@ -302,24 +303,23 @@ __global__ void __launch_bounds__(64) k_m2l_mfma(M2lArgs a, const R *T, const R 
 
 // Complex values: 8 pairs per wave, real and imaginary parts as 16 real columns.
 template <class R>
-__global__ void __launch_bounds__(64) k_m2l_mfma_cx(M2lArgs a, const R *T, const cx<R> *mom, cx<R> *out) {
+__global__ void __launch_bounds__(64) k_m2l_mfma_cx(M2lArgs a, const R *T, const cx<R> *Mc, cx<R> *out) {
     using V4 = typename vec4<R>::type;
     const int lane = threadIdx.x, task = blockIdx.x;
     const int cnt = a.task_count[task];
     if (cnt == 0) return;
-    const int c = a.task_class[task], first = a.task_first[task], P = a.P;
+    const int c = a.task_class[task], first = a.task_first[task];
     const int col = lane & 15, kq = lane >> 4, p = col & 7;
     const bool im_col = col >= 8;
-    const int src = p < cnt ? a.pair_src[first + p] : 0;
-    const int32_t *const si[1] = {a.sym_in + (p < cnt ? a.pair_sym[first + p] : 0) * KIN + kq};
-    const R *const ms[1] = {(const R *)(mom + (int64_t)src * P) + (im_col ? 1 : 0)};
+    const R *const ms[1] = {(const R *)(Mc + (int64_t)(p < cnt ? a.pair_mom[first + p] : 0) * KIN + kq) +
+                            (im_col ? 1 : 0)};
     const R *const Tp[2] = {T + (int64_t)(2 * c) * TSZ + lane, T + (int64_t)(2 * c + 1) * TSZ + lane};
     V4 acc[2][1][MT];
-    m2l_contract<R, 2, 1>(Tp, si, ms, 2, acc);
+    m2l_contract<R, 2, 1>(Tp, ms, 2, acc);
     // lane with column p < 8 holds Tr.Mr and Ti.Mr of pair p; lane ^ 8 holds Tr.Mi and Ti.Mi
     const bool store = !im_col && p < cnt;
     cx<R> *o = out + (int64_t)(store ? a.pair_slot[first + p] : 0) * OUT_LD;
-    const R scale = (R)ldexp(1.0 / a.side, a.level[src]);
+    const R scale = (R)ldexp(1.0 / a.side, a.level[p < cnt ? a.pair_src[first + p] : 0]);
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
 #pragma unroll
@@ -497,7 +497,25 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     };
     up(pl->pair_slot, slot);
     up(pl->pair_src, src);
-    up(pl->pair_sym, sym);
+    // used (source box, symmetry) combinations: one canonical moment vector each
+    {
+        std::unordered_map<int64_t, int32_t> uid;
+        std::vector<int32_t> pmom(slot.size()), usrc, usym;
+        for (size_t i = 0; i < slot.size(); i++) {
+            const int64_t key = (int64_t)src[i] * NSYM + sym[i];
+            auto it = uid.find(key);
+            if (it == uid.end()) {
+                it = uid.emplace(key, (int32_t)usrc.size()).first;
+                usrc.push_back(src[i]);
+                usym.push_back(sym[i]);
+            }
+            pmom[i] = it->second;
+        }
+        pl->n_u = (int64_t)usrc.size();
+        up(pl->pair_mom, pmom);
+        up(pl->u_src, usrc);
+        up(pl->u_sym, usym);
+    }
     up(pl->cls_delta, cdelta);
     // packed multi-indices of the rows and contraction indices
     std::vector<int32_t> pk(KIN, 0);
@@ -630,16 +648,21 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc) {
     }
     t.work.m2l_out.ensure(&c, sizeof(V) * (size_t)std::max<int64_t>(1, t.n_inter) * OUT_LD);
     V *out = (V *)t.work.m2l_out.p;
-    M2lArgs a{tk.task_class.p, tk.task_first.p, tk.task_count.p, pl.pair_slot.p, pl.pair_src.p, pl.pair_sym.p,
-              t.level.p, pl.sym_in.p, t.side, P};
+    M2lArgs a{tk.task_class.p, tk.task_first.p, tk.task_count.p, pl.pair_slot.p, pl.pair_src.p, pl.pair_mom.p,
+              t.level.p, t.side, P};
+    t.work.m2l_mom.ensure(&c, sizeof(V) * (size_t)std::max<int64_t>(1, pl.n_u) * KIN);
+    V *Mc = (V *)t.work.m2l_mom.p;
     const R *Tx = expanded<R>(t, pl);
     for (int rhs = 0; rhs < nrhs; rhs++) {
         const V *m = mom + (int64_t)rhs * t.n_box * P;
         V *l = loc + (int64_t)rhs * t.n_box * P;
+        k_m2l_canonical_moments<V><<<(unsigned)((pl.n_u + 3) / 4), 256, 0, c.stream>>>(pl.n_u, pl.u_src.p, pl.u_sym.p,
+                                                                                     pl.sym_in.p, P, m, Mc);
+        BEM_LAUNCH_CHECK();
         if constexpr (std::is_same<V, R>::value)
-            k_m2l_mfma<R, m2l_ncg<V, R>()><<<(unsigned)tk.n_task, 64, 0, c.stream>>>(a, Tx, m, out);
+            k_m2l_mfma<R, m2l_ncg<V, R>()><<<(unsigned)tk.n_task, 64, 0, c.stream>>>(a, Tx, Mc, out);
         else
-            k_m2l_mfma_cx<R><<<(unsigned)tk.n_task, 64, 0, c.stream>>>(a, Tx, m, out);
+            k_m2l_mfma_cx<R><<<(unsigned)tk.n_task, 64, 0, c.stream>>>(a, Tx, Mc, out);
         BEM_LAUNCH_CHECK();
         c.mark(3);
         k_m2l_reduce<V><<<(unsigned)t.n_m2l_boxes, 192, 0, c.stream>>>(t.m2l_boxes.p, t.inter_ptr.p, pl.slot_sym.p,
