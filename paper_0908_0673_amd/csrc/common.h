@@ -77,6 +77,7 @@ struct Ctx {
     }
     ~Ctx() {
         for (auto e : events) (void)hipEventDestroy(e);
+        release_streams();
     }
 
     int device = 0;
@@ -103,7 +104,41 @@ struct Ctx {
         else (void)hipFree(p);
     }
     void sync() { BEM_HIP(hipStreamSynchronize(stream)); }
+
+    // second stream (default priority) for work that runs concurrently with
+    // the main stream inside one call, with its fork / join events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t side_stream() {
+        if (!side) {
+            BEM_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+            BEM_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+            BEM_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+        }
+        return side;
+    }
+    // side stream waits for everything issued so far on the main stream
+    void fork() {
+        BEM_HIP(hipEventRecord(ev_fork, stream));
+        BEM_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+    }
+    // main stream waits for everything issued so far on the side stream
+    void join() {
+        BEM_HIP(hipEventRecord(ev_join, side));
+        BEM_HIP(hipStreamWaitEvent(stream, ev_join, 0));
+    }
+    void release_streams() {
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
+        side = nullptr;
+        ev_fork = ev_join = nullptr;
+    }
 };
+
+// Zeroes `bytes` bytes at device address p on the context's stream with a
+// fill kernel (no memset node, so the call can sit in a captured graph).
+void zero_fill(Ctx &c, void *p, size_t bytes);
 
 // Device array owned by the library, released through the context's allocator.
 template <class T>
@@ -129,7 +164,7 @@ struct DBuf {
         p = static_cast<T *>(c->dmalloc(sizeof(T) * (count ? count : 1)));
     }
     void zero() {
-        if (n) BEM_HIP(hipMemsetAsync(p, 0, sizeof(T) * n, ctx->stream));
+        if (n) zero_fill(*ctx, p, sizeof(T) * n);
     }
     void release() {
         if (p && ctx) ctx->dfree(p);

@@ -613,14 +613,42 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         t.work.mom.ensure(&c, sizeof(V) * nexp);
         t.work.loc.ensure(&c, sizeof(V) * nexp);
         V *mom = (V *)t.work.mom.p, *loc = (V *)t.work.loc.p;
+        using VD = typename std::conditional<HELM, cx<double>, double>::type;
+        VD *part = nullptr;
+        if (t.n_p2p_items) {
+            t.work.p2p_part.ensure(&c, sizeof(VD) * 64 * (size_t)t.n_p2p_units * nrhs);
+            part = (VD *)t.work.p2p_part.p;
+        }
+        auto near_field = [&](hipStream_t st) {
+            dim3 g((unsigned)t.n_p2p_units, nrhs);
+            if (dbl)
+                k_p2p<V, R, true, HELM><<<g, P2P_BS, 0, st>>>(
+                    t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
+                    t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
+            else
+                k_p2p<V, R, false, HELM><<<g, P2P_BS, 0, st>>>(
+                    t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
+                    t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
+            BEM_LAUNCH_CHECK();
+        };
+        // The near field depends only on the strengths and writes only its
+        // own partial sums: it runs on the second stream, concurrently with
+        // the far-field passes, and is joined before its sums are added.
+        // While phases are being timed everything stays on one stream.
+        const bool overlap = t.n_p2p_items && !c.timing;
+        if (overlap) {
+            hipStream_t side = c.side_stream();
+            c.fork();
+            near_field(side);
+        }
         // upward pass (boxes without elements keep zero moments)
-        BEM_HIP(hipMemsetAsync(mom, 0, sizeof(V) * nexp, c.stream));
+        zero_fill(c, mom, sizeof(V) * nexp);
         p2m_apply<V, R, XV>(t, dbl, nrhs, x, mom);
         c.mark(1);
         m2m_apply<V, R>(t, nrhs, mom);
         c.mark(2);
         // interactions
-        BEM_HIP(hipMemsetAsync(loc, 0, sizeof(V) * nexp, c.stream));
+        zero_fill(c, loc, sizeof(V) * nexp);
         c.mark(9);
         m2l_apply<V, R>(t, *pl, nrhs, mom, loc);
         // downward pass
@@ -629,19 +657,8 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         l2p_apply<V, R>(t, nrhs, loc, yacc);
         c.mark(5);
         if (t.n_p2p_items) {
-            using VD = typename std::conditional<HELM, cx<double>, double>::type;
-            t.work.p2p_part.ensure(&c, sizeof(VD) * 64 * (size_t)t.n_p2p_units * nrhs);
-            VD *part = (VD *)t.work.p2p_part.p;
-            dim3 g((unsigned)t.n_p2p_units, nrhs);
-            if (dbl)
-                k_p2p<V, R, true, HELM><<<g, P2P_BS, 0, c.stream>>>(
-                    t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
-                    t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
-            else
-                k_p2p<V, R, false, HELM><<<g, P2P_BS, 0, c.stream>>>(
-                    t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
-                    t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
-            BEM_LAUNCH_CHECK();
+            if (overlap) c.join();
+            else near_field(c.stream);
             dim3 gf((unsigned)((t.n_p2p_items + 3) / 4), nrhs);
             k_p2p_finish<V, HELM><<<gf, 256, 0, c.stream>>>(t.n_p2p_items, t.p2p_item_unit.p, t.p2p_t0.p, t.p2p_nt.p,
                                                            part, t.n_p2p_units, nt, yacc);

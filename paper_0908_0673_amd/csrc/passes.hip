@@ -31,7 +31,7 @@ namespace bem {
 
 namespace {
 
-__host__ __device__ inline int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+__host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 __host__ __device__ inline int midx(int a, int b, int c) {
     int n = a + b + c;
     return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
@@ -116,75 +116,116 @@ __global__ void k_p2m_apply(const int32_t *leaves, const int64_t *woff, const in
     }
 }
 
-// ---------------------------------------------------------------- M2M
-// grid (parents, coefficient groups of 32, rhs); block 256 = 32 coefficients x
-// 8 parity classes; each lane sums the shift terms of one parity and the eight
-// lanes of a coefficient are added by shuffles.
+// ---------------------------------------------------------------- M2M / L2L
+// Children sit at c_parent + (rho/4) s with s in {-1, 1}^3.  With parity
+// class pi (the parities of the shift multi-index g), the sign of a child's
+// term is (-1)^popc(pi & m), m = the child's complemented octant bits, so the
+// eight parity sums of the children are the Walsh-Hadamard transform over m
+// of the children's values, and a parent's eight per-parity terms go back to
+// the children by the same transform.  An 8-lane group computes it with three
+// butterfly shuffles: lane j ends holding the transform at index j.
+template <class V>
+__device__ inline V wht8(V v, int j) {
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+        V u;
+        if constexpr (std::is_same<V, float>::value || std::is_same<V, double>::value) {
+            u = __shfl_xor(v, o, 64);
+        } else {
+            u.re = __shfl_xor(v.re, o, 64);
+            u.im = __shfl_xor(v.im, o, 64);
+        }
+        v = (j & o) ? u - v : v + u;
+    }
+    return v;
+}
+
+template <class V>
+__device__ inline V sum8(V v) {
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+        if constexpr (std::is_same<V, float>::value || std::is_same<V, double>::value) {
+            v += __shfl_xor(v, o, 64);
+        } else {
+            v.re += __shfl_xor(v.re, o, 64);
+            v.im += __shfl_xor(v.im, o, 64);
+        }
+    }
+    return v;
+}
+
+// grid (parents, coefficient groups of 32, rhs); block 256 = 32 coefficient
+// slots x 8 lanes.  The children's moments are all loaded at once and
+// transformed into the eight parity sums S[pi] (LDS); then each lane sums the
+// shift terms of one parity class for a coefficient of the block's group and
+// the eight lanes are added by shuffles.
 template <class V, class R>
 __global__ void __launch_bounds__(256) k_m2m(const int32_t *boxes, const int32_t *child_begin, const int32_t *nchild,
                                              const uint64_t *prefix, int p, const int8_t *exps, V *mom,
                                              int64_t n_box) {
+    constexpr int NIT = (ncoef(MAX_ORDER) + 31) / 32;
     extern __shared__ unsigned char smem[];
     const int P = ncoef(p);
     V *S = (V *)smem;                // [8][P] parity sums of the children
     R *c4 = (R *)(S + 8 * P);        // 4^-k / k!
     R *p2 = c4 + (MAX_ORDER + 1);    // 2^-k
-    __shared__ int cid[8], cmask[8], ncs;
+    __shared__ int cof[8];           // child by complemented octant bits, -1 if absent
     const int b = boxes[blockIdx.x], rhs = blockIdx.z;
+    const int tid = threadIdx.x, j = tid & 7, grp = tid >> 3;
     V *base = mom + (int64_t)rhs * n_box * P;
-    if (threadIdx.x == 0) ncs = nchild[b];
-    if (threadIdx.x < 8) {
-        const int nc = nchild[b];
-        const int c = child_begin[b] + (int)threadIdx.x;
-        cid[threadIdx.x] = (int)threadIdx.x < nc ? c : 0;
-        cmask[threadIdx.x] = (int)threadIdx.x < nc ? ((~(int)(prefix[c] & 7u)) & 7) : 0;
+    if (tid < 8) {
+        const int nc = nchild[b], cb = child_begin[b];
+        // each octant holds at most one child: gather the child whose bits complement to tid
+        int who = -1;
+        for (int ch = 0; ch < nc; ch++)
+            if (((~(int)(prefix[cb + ch] & 7u)) & 7) == tid) who = cb + ch;
+        cof[tid] = who;
     }
-    if (threadIdx.x <= (unsigned)p) {
-        double f = 1.0;
-        for (int k = 2; k <= (int)threadIdx.x; k++) f *= k;
-        c4[threadIdx.x] = (R)(ldexp(1.0, -2 * (int)threadIdx.x) / f);
-        p2[threadIdx.x] = (R)ldexp(1.0, -(int)threadIdx.x);
+    if (tid <= p) {
+        double fct = 1.0;
+        for (int k = 2; k <= tid; k++) fct *= k;
+        c4[tid] = (R)(ldexp(1.0, -2 * tid) / fct);
+        p2[tid] = (R)ldexp(1.0, -tid);
     }
     __syncthreads();
-    const int nch = ncs;
-    for (int i = threadIdx.x; i < 8 * P; i += blockDim.x) {
-        const int pi = i / P, d = i % P;
+    const int cj = cof[j];
+    V x[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int d = grp + 32 * it;
+        x[it] = (cj >= 0 && d < P) ? base[(int64_t)cj * P + d] : V(0.0);
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int d = grp + 32 * it;
+        if (32 * it < P) {  // uniform: the whole group takes part in the shuffles
+            const V s = wht8(x[it], j);
+            if (d < P) S[j * P + d] = s;
+        }
+    }
+    __syncthreads();
+    const int pi = j, p0 = (pi >> 2) & 1, p1 = (pi >> 1) & 1, p2b = pi & 1;
+    {
+        const int a = blockIdx.y * 32 + grp;
         V acc = V(0.0);
-        for (int ch = 0; ch < nch; ch++) {
-            const V m = base[(int64_t)cid[ch] * P + d];
-            if (__popc(pi & cmask[ch]) & 1) acc -= m;
-            else acc += m;
+        if (a < P) {
+            const int a0 = exps[3 * a], a1 = exps[3 * a + 1], a2 = exps[3 * a + 2], na = a0 + a1 + a2;
+            for (int g0 = p0; g0 <= a0; g0 += 2)
+                for (int g1 = p1; g1 <= a1; g1 += 2)
+                    for (int g2 = p2b; g2 <= a2; g2 += 2) {
+                        const R mag = c4[g0] * c4[g1] * c4[g2] * p2[na - g0 - g1 - g2];
+                        acc += S[pi * P + midx(a0 - g0, a1 - g1, a2 - g2)] * mag;
+                    }
         }
-        S[pi * P + d] = acc;
+        acc = sum8(acc);
+        if (a < P && pi == 0) base[(int64_t)b * P + a] = acc;
     }
-    __syncthreads();
-    const int a = blockIdx.y * 32 + (threadIdx.x >> 3), pi = threadIdx.x & 7;
-    const int p0 = (pi >> 2) & 1, p1 = (pi >> 1) & 1, p2b = pi & 1;
-    V acc = V(0.0);
-    if (a < P) {
-        const int a0 = exps[3 * a], a1 = exps[3 * a + 1], a2 = exps[3 * a + 2], na = a0 + a1 + a2;
-        for (int g0 = p0; g0 <= a0; g0 += 2)
-            for (int g1 = p1; g1 <= a1; g1 += 2)
-                for (int g2 = p2b; g2 <= a2; g2 += 2) {
-                    const R mag = c4[g0] * c4[g1] * c4[g2] * p2[na - g0 - g1 - g2];
-                    acc += S[pi * P + midx(a0 - g0, a1 - g1, a2 - g2)] * mag;
-                }
-    }
-    for (int o = 1; o < 8; o <<= 1) {
-        if constexpr (std::is_same<V, R>::value) {
-            acc += __shfl_xor(acc, o, 64);
-        } else {
-            acc.re += __shfl_xor(acc.re, o, 64);
-            acc.im += __shfl_xor(acc.im, o, 64);
-        }
-    }
-    if (a < P && pi == 0) base[(int64_t)b * P + a] = acc;
 }
 
-// ---------------------------------------------------------------- L2L
 // grid (parents, coefficient groups of 32, rhs); block 256 = 32 coefficients x
-// 8 parity classes; the eight lanes of a coefficient form each child's value
-// by signed shuffle sums.
+// 8 parity classes; each lane sums the parent's terms of one parity class,
+// the group's transform gives lane j the value of the child with
+// complemented octant bits j, and every lane updates its child at once.
 template <class V, class R>
 __global__ void __launch_bounds__(256) k_l2l(const int32_t *boxes, const int32_t *child_begin, const int32_t *nchild,
                                              const uint64_t *prefix, const int64_t *tb, const int64_t *te, int p,
@@ -194,13 +235,13 @@ __global__ void __launch_bounds__(256) k_l2l(const int32_t *boxes, const int32_t
     V *F = (V *)smem;
     R *q4 = (R *)(F + P);            // 4^-k
     R *bn = q4 + (MAX_ORDER + 1);    // binomials [p+1][p+1]
-    __shared__ int cmask[8], cwant[8];
+    __shared__ int cof[8];           // wanted child by complemented octant bits, -1 if none
     const int b = boxes[blockIdx.x], rhs = blockIdx.z;
+    const int tid = threadIdx.x;
     V *base = loc + (int64_t)rhs * n_box * P;
-    const int nc = nchild[b], cb = child_begin[b];
-    for (int i = threadIdx.x; i < P; i += blockDim.x) F[i] = base[(int64_t)b * P + i];
-    if (threadIdx.x <= (unsigned)p) q4[threadIdx.x] = (R)ldexp(1.0, -2 * (int)threadIdx.x);
-    for (int i = threadIdx.x; i < (p + 1) * (p + 1); i += blockDim.x) {
+    for (int i = tid; i < P; i += blockDim.x) F[i] = base[(int64_t)b * P + i];
+    if (tid <= p) q4[tid] = (R)ldexp(1.0, -2 * tid);
+    for (int i = tid; i < (p + 1) * (p + 1); i += blockDim.x) {
         const int n = i / (p + 1), k = i % (p + 1);
         double v = 0.0;
         if (k <= n) {
@@ -209,14 +250,20 @@ __global__ void __launch_bounds__(256) k_l2l(const int32_t *boxes, const int32_t
         }
         bn[i] = (R)v;
     }
-    if (threadIdx.x < 8) {
-        const int c = cb + (int)threadIdx.x;
-        const bool ok = (int)threadIdx.x < nc;
-        cmask[threadIdx.x] = ok ? ((~(int)(prefix[c] & 7u)) & 7) : 0;
-        cwant[threadIdx.x] = ok && te[c] > tb[c];
+    if (tid < 8) {
+        const int nc = nchild[b], cb = child_begin[b];
+        int who = -1;
+        for (int ch = 0; ch < nc; ch++) {
+            const int c = cb + ch;
+            if (((~(int)(prefix[c] & 7u)) & 7) == tid && te[c] > tb[c]) who = c;
+        }
+        cof[tid] = who;
     }
     __syncthreads();
-    const int bi = blockIdx.y * 32 + (threadIdx.x >> 3), pi = threadIdx.x & 7;
+    const int bi = blockIdx.y * 32 + (tid >> 3), pi = tid & 7;
+    const int cj = cof[pi];
+    V old = V(0.0);
+    if (bi < P && cj >= 0) old = base[(int64_t)cj * P + bi];  // in flight while the terms are summed
     V T = V(0.0);
     if (bi < P) {
         const int b0 = exps[3 * bi], b1 = exps[3 * bi + 1], b2 = exps[3 * bi + 2];
@@ -230,19 +277,8 @@ __global__ void __launch_bounds__(256) k_l2l(const int32_t *boxes, const int32_t
                 }
         T = T * (R)ldexp(1.0, -(b0 + b1 + b2));
     }
-    for (int ch = 0; ch < 8; ch++) {
-        if (!cwant[ch]) continue;  // uniform across the block
-        V v = (__popc(pi & cmask[ch]) & 1) ? -T : T;
-        for (int o = 1; o < 8; o <<= 1) {
-            if constexpr (std::is_same<V, R>::value) {
-                v += __shfl_xor(v, o, 64);
-            } else {
-                v.re += __shfl_xor(v.re, o, 64);
-                v.im += __shfl_xor(v.im, o, 64);
-            }
-        }
-        if (bi < P && pi == 0) base[(int64_t)(cb + ch) * P + bi] += v;
-    }
+    const V v = wht8(T, pi);
+    if (bi < P && cj >= 0) base[(int64_t)cj * P + bi] = old + v;
 }
 
 // ---------------------------------------------------------------- L2P monomials

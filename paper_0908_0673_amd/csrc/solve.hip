@@ -216,7 +216,7 @@ int gmres(Krylov<V> &K, F &&apply, const V *b, V *x, double tol, int max_cycles,
     const unsigned nb = nblocks(n, RBS);
     double bnorm = K.norm(b);
     if (bnorm == 0.0) {
-        BEM_HIP(hipMemsetAsync(x, 0, sizeof(V) * n, c.stream));
+        zero_fill(c, x, sizeof(V) * n);
         *relres = 0.0;
         return BEM_OK;
     }
@@ -235,7 +235,7 @@ int gmres(Krylov<V> &K, F &&apply, const V *b, V *x, double tol, int max_cycles,
         if (beta / bnorm <= tol) return BEM_OK;
         {
             double inv = 1.0 / beta;
-            BEM_HIP(hipMemsetAsync(K.tmp.p, 0, sizeof(V) * n, c.stream));
+            zero_fill(c, K.tmp.p, sizeof(V) * n);
             k_axpy<V><<<nb, RBS, 0, c.stream>>>(V(0.0), K.vec(0), K.tmp.p, n, inv);
             BEM_LAUNCH_CHECK();
             BEM_HIP(hipMemcpyAsync(K.vec(0), K.tmp.p, sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
@@ -317,15 +317,15 @@ int solve_t(bem_tree &t, int green, double k, int nrhs, const V *chi, V *phi, co
         int st;
         double res = 0.0;
         if (o.precision == BEM_PREC_FP64 || method == BEM_DIRECT) {
-            BEM_HIP(hipMemsetAsync(x, 0, sizeof(V) * n, c.stream));
+            zero_fill(c, x, sizeof(V) * n);
             st = gmres(K, A64, b.p, x, o.tol, o.max_restarts, &inf.iterations, &inf.matvecs, &res, true);
         } else {
-            BEM_HIP(hipMemsetAsync(x, 0, sizeof(V) * n, c.stream));
+            zero_fill(c, x, sizeof(V) * n);
             BEM_HIP(hipMemcpyAsync(r.p, b.p, sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
             double bnorm = K.norm(b.p);
             st = BEM_ENOCONV;
             for (int it = 0; it < o.max_refine; it++) {
-                BEM_HIP(hipMemsetAsync(d.p, 0, sizeof(V) * n, c.stream));
+                zero_fill(c, d.p, sizeof(V) * n);
                 double inner = 0.0;
                 gmres(K, A32, r.p, d.p, o.inner_tol, o.max_restarts, &inf.iterations, &inf.matvecs, &inner, true);
                 k_axpy<V><<<nblocks(n, RBS), RBS, 0, c.stream>>>(V(0.0), d.p, x, n, 1.0);
