@@ -60,6 +60,7 @@ __global__ void k_strength(const XV *x, int64_t n_dof, const int32_t *se_dofs, c
 constexpr int P2P_BS = 256;
 constexpr int P2P_TILE = 256;
 constexpr int P2P_CH = 256;  // near-list entries per chunk
+constexpr int P2P_PER_CU = 3;  // near-field blocks per CU while the far field runs beside it
 
 // 1/sqrt(v) for v > 0 far from the denormal range (squared distances of
 // distinct points): the hardware estimate, which is within 1 ulp in single
@@ -129,15 +130,15 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
     __shared__ R4 sns[NW][2][64];
     __shared__ R ssi[NW][2][HELM ? 64 : 1];
     __shared__ VD red[NW][64];
+    __shared__ VD sub_a[NW][64], sub_b[NW][64];
     const int u = unit_order[blockIdx.x], rhs = blockIdx.y;
     const int w = unit_item[u];
     const int64_t u0 = unit_f[2 * u], u1 = unit_f[2 * u + 1];  // the unit's share of the item's near points
     const int b = wi_box[w], t0 = wi_t0[w], nt = wi_nt[w];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int npair = (nt + 1) >> 1;  // lanes needed, two targets each
-    int tpw = 1;
-    while (tpw < npair) tpw <<= 1;
-    const int nsub = 64 / tpw, tl = lane % tpw, sub = lane / tpw;
+    // tpw lanes hold the item's targets, two each; the wave's lanes form nsub
+    // such groups, each streaming every nsub-th point (leftover lanes idle)
+    const int tpw = (nt + 1) >> 1, nsub = 64 / tpw, tl = lane % tpw, sub = lane / tpw;
     const int ta = min(2 * tl, nt - 1), tb2 = min(2 * tl + 1, nt - 1);
     const double xa0 = t64[t0 + ta], xa1 = t64[n_tgt + t0 + ta], xa2 = t64[2 * n_tgt + t0 + ta];
     const double xb0 = t64[t0 + tb2], xb1 = t64[n_tgt + t0 + tb2], xb2 = t64[2 * n_tgt + t0 + tb2];
@@ -176,38 +177,47 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
         const int64_t f0 = g0 + min(gn, per * wave), f1 = g0 + min(gn, per * wave + per);
         base += total;
         int e = 0;  // run holding this lane's current point
-        auto fetch = [&](int64_t f, double2 &pxy, double &pz, R4 &ns, R &si) {
+        // raw point records are loaded a batch ahead and only combined (strength
+        // into the normal) when stored, so the loads stay in flight meanwhile
+        double rx = 0.0, ry = 0.0, rz = 0.0;
+        R rnx = 0, rny = 0, rnz = 0;
+        V rs = V(0.0);
+        auto fetch = [&](int64_t f) {
             if (f < f1) {
                 while (pref[e + 1] <= f) e++;
                 const int64_t qi = qbeg[e] + (f - pref[e]);
-                pxy = make_double2(q64[qi], q64[n_q + qi]);
-                pz = q64[2 * n_q + qi];
-                const V sv = sr[qi];
-                ns.w = re_part(sv);
-                const R sc = HELM ? (R)1 : ns.w;  // Laplace: strength folded into the normal
-                ns.x = DBL ? q[4 * n_q + qi] * sc : (R)0;
-                ns.y = DBL ? q[5 * n_q + qi] * sc : (R)0;
-                ns.z = DBL ? q[6 * n_q + qi] * sc : (R)0;
-                if constexpr (HELM) si = sv.im;
+                rx = q64[qi];
+                ry = q64[n_q + qi];
+                rz = q64[2 * n_q + qi];
+                rs = sr[qi];
+                if (DBL) {
+                    rnx = q[4 * n_q + qi];
+                    rny = q[5 * n_q + qi];
+                    rnz = q[6 * n_q + qi];
+                }
             }
         };
-        double2 pxy = make_double2(0.0, 0.0);
-        double pz = 0.0;
-        R4 ns = {0, 0, 0, 0};
-        R si = 0;
-        fetch(f0 + lane, pxy, pz, ns, si);
+        fetch(f0 + lane);
         int buf = 0;
         for (int64_t fb = f0; fb < f1; fb += 64) {
-            sxy[wave][buf][lane] = pxy;
-            szz[wave][buf][lane] = pz;
-            sns[wave][buf][lane] = ns;
-            if constexpr (HELM) ssi[wave][buf][lane] = si;
+            {
+                R4 ns;
+                ns.w = re_part(rs);
+                const R sc = HELM ? (R)1 : ns.w;  // Laplace: strength folded into the normal
+                ns.x = rnx * sc;
+                ns.y = rny * sc;
+                ns.z = rnz * sc;
+                sxy[wave][buf][lane] = make_double2(rx, ry);
+                szz[wave][buf][lane] = rz;
+                sns[wave][buf][lane] = ns;
+                if constexpr (HELM) ssi[wave][buf][lane] = rs.im;
+            }
             __builtin_amdgcn_wave_barrier();
-            fetch(fb + 64 + lane, pxy, pz, ns, si);  // next batch in flight while this one is computed
+            fetch(fb + 64 + lane);  // next batch in flight while this one is computed
             const int nin = (int)min<int64_t>(64, f1 - fb);
             V acc_a = V(0.0), acc_b = V(0.0);
 #pragma unroll 4
-            for (int kk = sub; kk < nin; kk += nsub) {
+            for (int kk = sub < nsub ? sub : nin; kk < nin; kk += nsub) {
                 const double2 cxy = sxy[wave][buf][kk];
                 const double cz = szz[wave][buf][kk];
                 const R4 cns = sns[wave][buf][kk];
@@ -221,19 +231,15 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
         }
         __syncthreads();  // pref / qbeg are rewritten by the next chunk
     }
-    // reduce over sub-streams of the wave (lanes tl, tl + tpw, ...)
-    for (int o = 32; o >= tpw; o >>= 1) {
-        if constexpr (HELM) {
-            tot_a.re += __shfl_xor(tot_a.re, o, 64);
-            tot_a.im += __shfl_xor(tot_a.im, o, 64);
-            tot_b.re += __shfl_xor(tot_b.re, o, 64);
-            tot_b.im += __shfl_xor(tot_b.im, o, 64);
-        } else {
-            tot_a += __shfl_xor(tot_a, o, 64);
-            tot_b += __shfl_xor(tot_b, o, 64);
-        }
-    }
+    // reduce over the wave's groups (lanes tl, tl + tpw, ...), in group order
+    sub_a[wave][lane] = tot_a;
+    sub_b[wave][lane] = tot_b;
+    __builtin_amdgcn_wave_barrier();
     if (sub == 0) {
+        for (int k = 1; k < nsub; k++) {
+            tot_a += sub_a[wave][tl + k * tpw];
+            tot_b += sub_b[wave][tl + k * tpw];
+        }
         red[wave][2 * tl] = tot_a;
         if (2 * tl + 1 < 64) red[wave][2 * tl + 1] = tot_b;
     }
@@ -245,22 +251,6 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
     }
 }
 
-// y(targets of item w) += the item's unit partial sums, in unit order (1/4pi
-// applied here for Laplace).
-template <class V, bool HELM>
-__global__ void k_p2p_finish(int64_t n_items, const int32_t *item_unit, const int32_t *wi_t0, const int32_t *wi_nt,
-                             const typename std::conditional<HELM, cx<double>, double>::type *part, int64_t n_unit,
-                             int64_t n_tgt, V *y) {
-    using VD = typename std::conditional<HELM, cx<double>, double>::type;
-    const int64_t w = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-    const int tid = threadIdx.x & 63, rhs = blockIdx.y;
-    if (w >= n_items || tid >= wi_nt[w]) return;
-    VD v = VD(0.0);
-    for (int32_t u = item_unit[w]; u < item_unit[w + 1]; u++) v += part[((int64_t)rhs * n_unit + u) * 64 + tid];
-    if constexpr (!HELM) v = v * kInv4Pi;
-    V *dst = y + (int64_t)rhs * n_tgt + wi_t0[w] + tid;
-    *dst = vcast<V>(vcast<VD>(*dst) + v);
-}
 
 // ---------------------------------------------------------------- direct (FP64)
 template <class V, bool DBL, bool HELM>
@@ -303,20 +293,49 @@ __global__ void __launch_bounds__(256) k_direct(const double *q, int64_t n_q, co
 }
 
 // ---------------------------------------------------------------- correction + combine (FP64)
-template <class XV, class AV>
-__global__ void k_combine(int64_t n_tgt, const int32_t *tperm, const AV *yacc, const int64_t *row_ptr,
-                          const int32_t *pair_elem, const int32_t *se_dofs, const XV *corr, const double *cfree,
-                          const XV *x, int op, XV *y) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int rhs = blockIdx.y;
-    if (t >= n_tgt) return;
+// y(DOF of sorted target t) = the operator's combination of the far field
+// (yacc), the near-field partial sums of t's item (1/4pi applied for
+// Laplace), the singular / near-singular corrections and, for A, the free
+// term.  Eight lanes per target share its correction pairs and meet by
+// shuffles.
+template <class XV, class AV, class VD, bool LAP>
+__global__ void __launch_bounds__(256) k_combine(int64_t n_tgt, const int32_t *tperm, const AV *yacc,
+                                                 const int32_t *tgt_item, const int32_t *item_unit,
+                                                 const int32_t *wi_t0, const VD *part, int64_t n_unit,
+                                                 const int64_t *row_ptr, const int32_t *pair_elem,
+                                                 const int32_t *se_dofs, const XV *corr, const double *cfree,
+                                                 const XV *x, int op, XV *y) {
+    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int l8 = threadIdx.x & 7, rhs = blockIdx.y;
+    const bool ok = t < n_tgt;
     const XV *xr = x + (int64_t)rhs * n_tgt;
-    XV acc = vcast<XV>(yacc[(int64_t)rhs * n_tgt + t]);
-    for (int64_t p = row_ptr[t]; p < row_ptr[t + 1]; p++) {
-        const int32_t *dof = se_dofs + 6 * (int64_t)pair_elem[p];
-        const XV *cp = corr + 6 * p;
-        for (int a = 0; a < 6; a++) acc += cp[a] * xr[dof[a]];
+    XV acc = XV(0.0);
+    if (ok) {
+        for (int64_t p = row_ptr[t] + l8; p < row_ptr[t + 1]; p += 8) {
+            const int32_t *dof = se_dofs + 6 * (int64_t)pair_elem[p];
+            const XV *cp = corr + 6 * p;
+            for (int a = 0; a < 6; a++) acc += cp[a] * xr[dof[a]];
+        }
+        if (part && l8 == 1) {
+            const int32_t w = tgt_item[t];
+            const int64_t o = t - wi_t0[w];
+            VD v = VD(0.0);
+            for (int32_t u = item_unit[w]; u < item_unit[w + 1]; u++) v += part[((int64_t)rhs * n_unit + u) * 64 + o];
+            if (LAP) v = v * kInv4Pi;
+            acc += vcast<XV>(v);
+        }
+        if (l8 == 0) acc += vcast<XV>(yacc[(int64_t)rhs * n_tgt + t]);
     }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+        if constexpr (std::is_same<XV, double>::value) {
+            acc += __shfl_xor(acc, o, 64);
+        } else {
+            acc.re += __shfl_xor(acc.re, o, 64);
+            acc.im += __shfl_xor(acc.im, o, 64);
+        }
+    }
+    if (!ok || l8) return;
     const int64_t i = tperm[t];
     XV out;
     if (op == BEM_OP_A) out = xr[i] * cfree[i] - acc;
@@ -455,7 +474,7 @@ void plan_fmm(bem_tree &t) {
     {
         const size_t ni = wb.size();
         std::vector<int64_t> npts(ni);
-        std::vector<double> cpp(ni);  // cost per point: a wave covers 64 / tpw points per step
+        std::vector<double> cpp(ni);  // cost per point: a wave covers 64 / ceil(nt / 2) points per step
         double total = 0.0;
         for (size_t i = 0; i < ni; i++) {
             const int32_t b = wb[i];
@@ -464,10 +483,9 @@ void plan_fmm(bem_tree &t) {
                 const int32_t s = t.h_near_idx[j];
                 n += 7 * (t.h_ee[s] - t.h_eb[s]);
             }
-            int tpw = 1;
-            while (tpw < (wnt[i] + 1) / 2) tpw <<= 1;
+            const int nsub = 64 / ((wnt[i] + 1) / 2);
             npts[i] = n;
-            cpp[i] = tpw / 64.0;
+            cpp[i] = 1.0 / nsub;
             total += n * cpp[i];
         }
         int n_cu = 256;
@@ -498,6 +516,10 @@ void plan_fmm(bem_tree &t) {
         t.p2p_item_unit = upload_i32(c, iunit);
         t.p2p_unit_f.alloc(&c, uf.size());
         t.p2p_unit_f.upload(uf.data(), uf.size());
+        std::vector<int32_t> titem(std::max<int64_t>(1, t.n_tgt), 0);
+        for (size_t i = 0; i < ni; i++)
+            for (int32_t k = 0; k < wnt[i]; k++) titem[wt0[i] + k] = (int32_t)i;
+        t.p2p_tgt_item = upload_i32(c, titem);
     }
     // near-field pair count: targets x source points
     t.n_p2p_pairs = 0;
@@ -610,46 +632,62 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         FmmTables &T = *t.tables;
         const int P = T.P;
         const size_t nexp = (size_t)t.n_box * P * nrhs;
-        t.work.mom.ensure(&c, sizeof(V) * nexp);
-        t.work.loc.ensure(&c, sizeof(V) * nexp);
-        V *mom = (V *)t.work.mom.p, *loc = (V *)t.work.loc.p;
-        using VD = typename std::conditional<HELM, cx<double>, double>::type;
-        VD *part = nullptr;
+        // moments and locals in one buffer, cleared by one fill
+        t.work.mom.ensure(&c, 2 * sizeof(V) * nexp);
+        V *mom = (V *)t.work.mom.p, *loc = mom + nexp;
+        using PD = typename std::conditional<HELM, cx<double>, double>::type;
+        PD *part = nullptr;
         if (t.n_p2p_items) {
-            t.work.p2p_part.ensure(&c, sizeof(VD) * 64 * (size_t)t.n_p2p_units * nrhs);
-            part = (VD *)t.work.p2p_part.p;
+            t.work.p2p_part.ensure(&c, sizeof(PD) * 64 * (size_t)t.n_p2p_units * nrhs);
+            part = (PD *)t.work.p2p_part.p;
         }
+        // While it runs beside the far field, the near-field kernel asks for
+        // enough LDS that at most P2P_PER_CU of its blocks share a CU, which
+        // leaves registers and wave slots for the far-field kernels (their
+        // matrix-core and latency-bound work then overlaps its VALU work).
+        auto near_lds = [&](const void *fn) -> unsigned {
+            hipFuncAttributes fa;
+            BEM_HIP(hipFuncGetAttributes(&fa, fn));
+            int lds = 0;
+            BEM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c.device));
+            const long pad = (long)lds / P2P_PER_CU - (long)fa.sharedSizeBytes - 256;
+            return pad > 0 ? (unsigned)pad : 0u;
+        };
         auto near_field = [&](hipStream_t st) {
             dim3 g((unsigned)t.n_p2p_units, nrhs);
+            const bool beside = st != c.stream;
             if (dbl)
-                k_p2p<V, R, true, HELM><<<g, P2P_BS, 0, st>>>(
+                k_p2p<V, R, true, HELM><<<g, P2P_BS, beside ? near_lds((const void *)k_p2p<V, R, true, HELM>) : 0,
+                                          st>>>(
                     t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
                     t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
             else
-                k_p2p<V, R, false, HELM><<<g, P2P_BS, 0, st>>>(
+                k_p2p<V, R, false, HELM><<<g, P2P_BS, beside ? near_lds((const void *)k_p2p<V, R, false, HELM>) : 0,
+                                           st>>>(
                     t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
                     t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
             BEM_LAUNCH_CHECK();
         };
         // The near field depends only on the strengths and writes only its
         // own partial sums: it runs on the second stream, concurrently with
-        // the far-field passes, and is joined before its sums are added.
-        // While phases are being timed everything stays on one stream.
+        // the far-field passes from M2L on (started after the short upward
+        // pass, which it would otherwise crowd out), and is joined before its
+        // sums are added.  While phases are being timed everything stays on
+        // one stream.
         const bool overlap = t.n_p2p_items && !c.timing;
-        if (overlap) {
-            hipStream_t side = c.side_stream();
-            c.fork();
-            near_field(side);
-        }
         // upward pass (boxes without elements keep zero moments)
-        zero_fill(c, mom, sizeof(V) * nexp);
+        zero_fill(c, mom, 2 * sizeof(V) * nexp);
         p2m_apply<V, R, XV>(t, dbl, nrhs, x, mom);
         c.mark(1);
         m2m_apply<V, R>(t, nrhs, mom);
         c.mark(2);
         // interactions
-        zero_fill(c, loc, sizeof(V) * nexp);
         c.mark(9);
+        if (overlap) {
+            hipStream_t side = c.side_stream();
+            c.fork();
+            near_field(side);
+        }
         m2l_apply<V, R>(t, *pl, nrhs, mom, loc);
         // downward pass
         l2l_apply<V, R>(t, nrhs, loc);
@@ -659,18 +697,17 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         if (t.n_p2p_items) {
             if (overlap) c.join();
             else near_field(c.stream);
-            dim3 gf((unsigned)((t.n_p2p_items + 3) / 4), nrhs);
-            k_p2p_finish<V, HELM><<<gf, 256, 0, c.stream>>>(t.n_p2p_items, t.p2p_item_unit.p, t.p2p_t0.p, t.p2p_nt.p,
-                                                           part, t.n_p2p_units, nt, yacc);
-            BEM_LAUNCH_CHECK();
         }
         c.mark(6);
     }
-    // corrections and combination in FP64
+    // near-field sums, corrections and combination in FP64
+    using VD = typename std::conditional<HELM, cx<double>, double>::type;
     const XV *corr = (const XV *)(dbl ? cr.K.p : cr.S.p);
-    dim3 g(nblocks(nt, 256), nrhs);
-    k_combine<XV, V><<<g, 256, 0, c.stream>>>(nt, t.tperm.p, yacc, t.pair_ptr.p, t.pair_elem.p, t.se_dofs.p, corr,
-                                             op == BEM_OP_A ? t.free_term.p : nullptr, x, op, y);
+    const VD *part = method == BEM_FMM && t.n_p2p_items ? (const VD *)t.work.p2p_part.p : nullptr;
+    dim3 g(nblocks(8 * nt, 256), nrhs);
+    k_combine<XV, V, VD, !HELM><<<g, 256, 0, c.stream>>>(
+        nt, t.tperm.p, yacc, t.p2p_tgt_item.p, t.p2p_item_unit.p, t.p2p_t0.p, part, t.n_p2p_units, t.pair_ptr.p,
+        t.pair_elem.p, t.se_dofs.p, corr, op == BEM_OP_A ? t.free_term.p : nullptr, x, op, y);
     BEM_LAUNCH_CHECK();
     c.mark(7);
 }

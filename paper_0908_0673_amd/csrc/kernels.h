@@ -147,6 +147,7 @@ struct bem_tree {
     // the units of each item ([item_unit[i], item_unit[i + 1]))
     int64_t n_p2p_units = 0;
     bem::DBuf<int32_t> p2p_unit_order, p2p_unit_item, p2p_item_unit;
+    bem::DBuf<int32_t> p2p_tgt_item;  // item of each sorted target
     bem::DBuf<int64_t> p2p_unit_f;
     bem::DBuf<int32_t> leaf_ids;       // leaf boxes with elements (P2M)
     int64_t n_leaf_src = 0;

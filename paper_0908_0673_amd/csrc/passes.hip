@@ -105,8 +105,15 @@ __global__ void k_p2m_apply(const int32_t *leaves, const int64_t *woff, const in
             const int a = threadIdx.x + r * blockDim.x;
             if (a >= P) break;
             V sacc = acc[r];
-#pragma unroll 4
-            for (int i = 0; i < nu; i++) sacc += xs[i] * W[(ub + i) * P + a];
+            // batches of 16 weight rows, all loads of a batch in flight together
+            for (int i0 = 0; i0 < nu; i0 += 16) {
+                R wv[16];
+#pragma unroll
+                for (int i = 0; i < 16; i++) wv[i] = i0 + i < nu ? W[(ub + i0 + i) * P + a] : R(0);
+#pragma unroll
+                for (int i = 0; i < 16; i++)
+                    if (i0 + i < nu) sacc += xs[i0 + i] * wv[i];
+            }
             acc[r] = sacc;
         }
     }
@@ -304,20 +311,38 @@ __global__ void k_l2p_monomials(const int32_t *leaves, const int64_t *tb, const 
     }
 }
 
+// grid (target leaves, rhs); block 256: wave w sums the coefficients of its
+// quarter of the expansion for up to 64 targets at a time, with all of its
+// monomial loads in flight together; the four partial sums meet in LDS.
 template <class V, class R>
-__global__ void k_l2p_apply(const int32_t *leaves, const int64_t *tb, const int64_t *te, int P, const R *U,
-                            const V *loc, int64_t n_box, int64_t n_tgt, V *y) {
+__global__ void __launch_bounds__(256) k_l2p_apply(const int32_t *leaves, const int64_t *tb, const int64_t *te,
+                                                   int P, const R *U, const V *loc, int64_t n_box, int64_t n_tgt,
+                                                   V *y) {
+    constexpr int QMAX = (ncoef(MAX_ORDER) + 3) / 4;
     extern __shared__ unsigned char smem[];
-    V *F = (V *)smem;
+    V *F = (V *)smem;           // [P]
+    __shared__ V red[4][64];
     const int b = leaves[blockIdx.x], rhs = blockIdx.y;
-    for (int i = threadIdx.x; i < P; i += blockDim.x) F[i] = loc[((int64_t)rhs * n_box + b) * P + i];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int i = tid; i < P; i += blockDim.x) F[i] = loc[((int64_t)rhs * n_box + b) * P + i];
     __syncthreads();
     const int64_t t0 = tb[b], nt = te[b] - tb[b];
     const R *Ub = U + t0 * P;
-    for (int64_t tl = threadIdx.x; tl < nt; tl += blockDim.x) {
+    const int q = (P + 3) / 4, c0 = w * q, c1 = min(P, c0 + q);
+    for (int64_t tbase = 0; tbase < nt; tbase += 64) {
+        const int64_t tl = tbase + lane;
+        const bool ok = tl < nt;
+        R u[QMAX];
+#pragma unroll
+        for (int i = 0; i < QMAX; i++) u[i] = (ok && c0 + i < c1) ? Ub[(int64_t)(c0 + i) * nt + tl] : R(0);
         V acc = V(0.0);
-        for (int bi = 0; bi < P; bi++) acc += F[bi] * Ub[(int64_t)bi * nt + tl];
-        y[(int64_t)rhs * n_tgt + t0 + tl] = acc;
+#pragma unroll
+        for (int i = 0; i < QMAX; i++)
+            if (c0 + i < c1) acc += F[c0 + i] * u[i];
+        red[w][lane] = acc;
+        __syncthreads();
+        if (w == 0 && ok) y[(int64_t)rhs * n_tgt + t0 + tl] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        __syncthreads();
     }
 }
 
@@ -442,8 +467,8 @@ void l2p_apply(bem_tree &t, int nrhs, const V *loc, V *y) {
     const int P = t.tables->P;
     const R *U = std::is_same<R, float>::value ? (const R *)t.pass.U32.p : (const R *)t.pass.U64.p;
     dim3 g((unsigned)t.n_leaf_tgt, nrhs);
-    k_l2p_apply<V, R><<<g, 64, sizeof(V) * P, c.stream>>>(t.tleaf_ids.p, t.tb.p, t.te.p, P, U, loc, t.n_box,
-                                                           t.n_tgt, y);
+    k_l2p_apply<V, R><<<g, 256, sizeof(V) * P, c.stream>>>(t.tleaf_ids.p, t.tb.p, t.te.p, P, U, loc, t.n_box,
+                                                            t.n_tgt, y);
     BEM_LAUNCH_CHECK();
 }
 

@@ -68,14 +68,14 @@ __global__ void k_tile_scan(const T *in, T *out, int64_t n, const T *offsets) {
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BS - 1) out[n] = ex;
 }
 
-__global__ void k_zero16(uint4 *p, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = make_uint4(0u, 0u, 0u, 0u);
-}
-
-__global__ void k_zero1(unsigned char *p, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0;
+// Zeroes [p, p + bytes): 16-byte stores over the aligned middle, byte stores
+// for the unaligned head and tail (taken by the first threads).
+__global__ void k_zero(unsigned char *p, size_t head, size_t n16, size_t tail) {
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    uint4 *m = (uint4 *)(p + head);
+    for (size_t i = i0; i < n16; i += stride) m[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (i0 < head) p[i0] = 0;
+    if (i0 < tail) p[head + 16 * n16 + i0] = 0;
 }
 
 }  // namespace
@@ -83,22 +83,12 @@ __global__ void k_zero1(unsigned char *p, size_t n) {
 void zero_fill(Ctx &c, void *p, size_t bytes) {
     if (!bytes) return;
     unsigned char *b = (unsigned char *)p;
-    size_t head = 0;
-    if ((uintptr_t)b % 16) head = std::min(bytes, 16 - (size_t)((uintptr_t)b % 16));
+    size_t head = (16 - (size_t)((uintptr_t)b % 16)) % 16;
+    if (head > bytes) head = bytes;
     const size_t n16 = (bytes - head) / 16, tail = bytes - head - 16 * n16;
-    if (head) {
-        k_zero1<<<1, 64, 0, c.stream>>>(b, head);
-        BEM_LAUNCH_CHECK();
-    }
-    if (n16) {
-        const unsigned nb = (unsigned)std::min<size_t>((n16 + 255) / 256, 4096);
-        k_zero16<<<nb, 256, 0, c.stream>>>((uint4 *)(b + head), n16);
-        BEM_LAUNCH_CHECK();
-    }
-    if (tail) {
-        k_zero1<<<1, 64, 0, c.stream>>>(b + head + 16 * n16, tail);
-        BEM_LAUNCH_CHECK();
-    }
+    const unsigned nb = (unsigned)std::max<size_t>(1, std::min<size_t>((n16 + 255) / 256, 4096));
+    k_zero<<<nb, 256, 0, c.stream>>>(b, head, n16, tail);
+    BEM_LAUNCH_CHECK();
 }
 
 template <class T>
