@@ -91,8 +91,12 @@ const char *bem_last_error(const bem_ctx *ctx);
  * events on the context's stream between its phases and accumulates the
  * elapsed device time per phase:
  *   0 strengths, 1 P2M, 2 M2M, 3 M2L products, 4 L2L, 5 L2P, 6 P2P (near
- *   field), 7 corrections + combination, 8 direct sum, 9 other, 10 sums of
- *   the M2L results into the local expansions.
+ *   field), 7 corrections + combination, 8 direct sum, 9 other, 10 the M2L
+ *   gathers around the products (moments into the canonical frames, results
+ *   summed into the local expansions).
+ * While timing is enabled every phase runs on the context's stream; without
+ * it the near field runs concurrently with the far field on a second
+ * stream, so the per-phase times are those of the serialized product.
  * enable = 1 turns timing on and zeroes the counters; 0 turns it off.
  * ms and launches (host arrays of BEM_NPHASE, may be NULL) receive the
  * accumulated milliseconds and the number of products timed per phase. */

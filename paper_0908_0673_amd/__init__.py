@@ -177,7 +177,7 @@ class Context:
             raise BemError(rc, f"{what}: {self.L.bem_last_error(self.h).decode()}")
         return rc
 
-    PHASES = ("strength", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "combine", "direct", "other", "m2l_sum")
+    PHASES = ("strength", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "combine", "direct", "other", "m2l_aux")
 
     def timing(self, enable: bool):
         """Turns per-phase event timing on (zeroing it) or off; returns the

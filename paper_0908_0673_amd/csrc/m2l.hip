@@ -213,123 +213,129 @@ __global__ void k_m2l_canonical_moments(int64_t n_u, const int32_t *u_src, const
     }
 }
 
-// Number of register stages: operator loads run NS contraction steps ahead
-// of their use and moment loads NB steps (they come from further away), so
-// the wave's own products cover their latency; fewer stages where the
-// accumulators take more registers.
-template <class R, int NA, int NCG>
-struct Pipe {
-    static constexpr int NS = sizeof(R) == 4 ? (NA * NCG == 1 ? 4 : 3) : (NA * NCG == 1 ? 3 : 2);
-    static constexpr int NB = 2 * NS + 2;
+// Blocks of M2L_WAVES waves share one class: the class's expanded operator
+// streams through a double-buffered LDS ring in chunks of KC contraction
+// steps (coalesced 16-byte loads, one chunk ahead, one barrier per chunk), and
+// every wave reads its A operands from there for its own 16 pair columns, so
+// each operator byte is fetched once per block rather than once per wave.
+// The B operands (the columns' canonical moments) stream per wave through a
+// register ring NB steps ahead.
+constexpr int M2L_WAVES = 4;
+constexpr int M2L_NB = 8;
+
+// Row split: with MS = 2 the block's waves pair up, each computing half of
+// the output row tiles of the same 16 columns, which halves the accumulators
+// per wave (used where they would otherwise limit the waves per SIMD).
+template <class R, int NA>
+constexpr int m2l_ms() {
+    return sizeof(R) * NA >= 8 ? 2 : 1;
+}
+
+template <class R, int NA>
+struct M2lChunk {
+    static constexpr int KC = sizeof(R) * NA == 4 ? 6 : (sizeof(R) * NA == 8 ? 3 : 2);
+    static constexpr int NCH = KT / KC;
+    static constexpr int CE = KC * MT * 64;                     // values per chunk and plane
+    static constexpr int U4 = CE * NA * (int)sizeof(R) / 16;    // 16-byte pieces per chunk
+    static constexpr int PER = (U4 + 64 * M2L_WAVES - 1) / (64 * M2L_WAVES);
+    static_assert(KT % KC == 0, "chunks must tile the contraction");
 };
 
-// acc[q][g] += T_q (canonical operator plane q) x B_g over all contraction
-// steps, for a lane's share of the 16 x 16 tiles; B_g step kt is
-// ms_g[mstride * 4 kt] (the lane's row of the column's canonical moments).
-template <class R, int NA, int NCG>
-__device__ inline void m2l_contract(const R *const (&Tp)[NA], const R *const (&ms)[NCG], int mstride,
-                                    typename vec4<R>::type (&acc)[NA][NCG][MT]) {
-    constexpr int NS = Pipe<R, NA, NCG>::NS, NB = Pipe<R, NA, NCG>::NB;
-    R A[NS][NA][MT], B[NB][NCG];
+// NA = 1: real values, 16 pair columns per wave.  NA = 2: complex values, 8
+// pairs per wave as 16 real columns (real parts, then imaginary parts) against
+// the operator's real and imaginary planes.  Columns without a pair compute
+// on the first canonical moments and are not stored.
+template <class R, int NA>
+__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, const R *Mc, R *out) {
+    using V4 = typename vec4<R>::type;
+    using CK = M2lChunk<R, NA>;
+    constexpr int KC = CK::KC, NCH = CK::NCH, CE = CK::CE, U4 = CK::U4, PER = CK::PER, NB = M2L_NB;
+    constexpr int MS = m2l_ms<R, NA>(), MTH = (MT + MS - 1) / MS;
+    __shared__ __align__(16) R As[2][NA * CE];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, task = blockIdx.x;
+    const int cnt = a.task_count[task];
+    if (cnt == 0) return;  // the same for the whole block
+    const int c = a.task_class[task], first = a.task_first[task];
+    const int col = lane & 15, kq = lane >> 4;
+    const int cg = w / MS, mt0 = (w % MS) * MTH;  // column group and first row tile of this wave
+    const int p = NA == 1 ? 16 * cg + col : 8 * cg + (col & 7);
+    const int64_t u = p < cnt ? a.pair_mom[first + p] : 0;
+    // lane's entries of its column: real values, or the real / imaginary part
+    const R *ms = Mc + (u * KIN + kq) * NA + (NA == 2 && col >= 8 ? 1 : 0);
+    const uint4 *Tg = (const uint4 *)(T + (int64_t)c * NA * TSZ);
+    // pieces past the chunk are clamped to its last one: those threads load
+    // and store the same value as its owner, so no branch is needed
+    auto fetch = [&](int ch, uint4 (&r)[PER]) {
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            const int x = min(tid + 64 * M2L_WAVES * i, U4 - 1);
+            const int q = x / (U4 / NA), off = x % (U4 / NA);
+            r[i] = Tg[(int64_t)q * (TSZ * (int)sizeof(R) / 16) + (int64_t)ch * (U4 / NA) + off];
+        }
+    };
+    auto stash = [&](int buf, const uint4 (&r)[PER]) {
+#pragma unroll
+        for (int i = 0; i < PER; i++) ((uint4 *)As[buf])[min(tid + 64 * M2L_WAVES * i, U4 - 1)] = r[i];
+    };
+    uint4 r[PER];
+    fetch(0, r);
+    R B[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) B[i] = ms[NA * 4 * i];
+    V4 acc[NA][MTH];
 #pragma unroll
     for (int q = 0; q < NA; q++)
 #pragma unroll
-        for (int g = 0; g < NCG; g++)
+        for (int j = 0; j < MTH; j++) acc[q][j] = V4{0, 0, 0, 0};
+    stash(0, r);
+    __syncthreads();
+    if (NCH > 1) fetch(1, r);
 #pragma unroll
-            for (int mt = 0; mt < MT; mt++) acc[q][g][mt] = typename vec4<R>::type{0, 0, 0, 0};
+    for (int ch = 0; ch < NCH; ch++) {
+        const R *Ab = As[ch & 1] + lane;
 #pragma unroll
-    for (int i = 0; i < NB; i++)
+        for (int kk = 0; kk < KC; kk++) {
+            const int kt = ch * KC + kk, sb = kt % NB;
 #pragma unroll
-        for (int g = 0; g < NCG; g++) B[i][g] = ms[g][mstride * 4 * i];
+            for (int j = 0; j < MTH; j++)
+                if (MS == 1 || mt0 + j < MT)  // the same for the whole wave
 #pragma unroll
-    for (int i = 0; i < NS; i++)
-#pragma unroll
-        for (int q = 0; q < NA; q++)
-#pragma unroll
-            for (int mt = 0; mt < MT; mt++) A[i][q][mt] = Tp[q][(i * MT + mt) * 64];
-#pragma unroll
-    for (int kt = 0; kt < KT; kt++) {
-        const int s = kt % NS, sb = kt % NB;
-#pragma unroll
-        for (int mt = 0; mt < MT; mt++)
-#pragma unroll
-            for (int q = 0; q < NA; q++)
-#pragma unroll
-                for (int g = 0; g < NCG; g++) acc[q][g][mt] = mfma(A[s][q][mt], B[sb][g], acc[q][g][mt]);
-        if (kt + NB < KT)
-#pragma unroll
-            for (int g = 0; g < NCG; g++) B[sb][g] = ms[g][mstride * 4 * (kt + NB)];
-        if (kt + NS < KT)
-#pragma unroll
-            for (int q = 0; q < NA; q++)
-#pragma unroll
-                for (int mt = 0; mt < MT; mt++) A[s][q][mt] = Tp[q][((kt + NS) * MT + mt) * 64];
-        __builtin_amdgcn_sched_barrier(0);  // keep the loads where they are issued
+                    for (int q = 0; q < NA; q++)
+                        acc[q][j] = mfma(Ab[q * CE + (kk * MT + mt0 + j) * 64], B[sb], acc[q][j]);
+            if (kt + NB < KT) B[sb] = ms[NA * 4 * (kt + NB)];
+        }
+        if (ch + 1 < NCH) {
+            stash((ch + 1) & 1, r);  // that buffer's last readers passed the previous barrier
+            __syncthreads();
+            if (ch + 2 < NCH) fetch(ch + 2, r);
+        }
     }
-}
-
-// Real values: one wave per task of up to 16 NCG pairs of one class.  Columns
-// without a pair compute on the first canonical moments and are not stored.
-template <class R, int NCG>
-__global__ void __launch_bounds__(64) k_m2l_mfma(M2lArgs a, const R *T, const R *Mc, R *out) {
-    using V4 = typename vec4<R>::type;
-    const int lane = threadIdx.x, task = blockIdx.x;
-    const int cnt = a.task_count[task];
-    if (cnt == 0) return;
-    const int c = a.task_class[task], first = a.task_first[task];
-    const int col = lane & 15, kq = lane >> 4;
-    const R *ms[NCG];
-#pragma unroll
-    for (int g = 0; g < NCG; g++) {
-        const int p = 16 * g + col;
-        ms[g] = Mc + (int64_t)(p < cnt ? a.pair_mom[first + p] : 0) * KIN + kq;
-    }
-    const R *const Tp[1] = {T + (int64_t)c * TSZ + lane};
-    V4 acc[1][NCG][MT];
-    m2l_contract<R, 1, NCG>(Tp, ms, 1, acc);
-#pragma unroll
-    for (int g = 0; g < NCG; g++) {
-        const int p = 16 * g + col;
+    const R scale = (R)ldexp(1.0 / a.side, a.level[p < cnt ? a.pair_src[first + p] : 0]);  // 1 / rho_s
+    if constexpr (NA == 1) {
         if (p < cnt) {
             R *o = out + (int64_t)a.pair_slot[first + p] * OUT_LD;
-            const R scale = (R)ldexp(1.0 / a.side, a.level[a.pair_src[first + p]]);  // 1 / rho_s
 #pragma unroll
-            for (int mt = 0; mt < MT; mt++)
+            for (int j = 0; j < MTH; j++)
+                if (MS == 1 || mt0 + j < MT)
 #pragma unroll
-                for (int r = 0; r < 4; r++) o[16 * mt + crow(R(0), kq, r)] = acc[0][g][mt][r] * scale;
+                    for (int r4 = 0; r4 < 4; r4++) o[16 * (mt0 + j) + crow(R(0), kq, r4)] = acc[0][j][r4] * scale;
         }
+    } else {
+        // lane with column < 8 holds Tr.Mr and Ti.Mr of its pair; lane ^ 8 holds Tr.Mi and Ti.Mi
+        const bool store = col < 8 && p < cnt;
+        cx<R> *o = (cx<R> *)out + (int64_t)(store ? a.pair_slot[first + p] : 0) * OUT_LD;
+#pragma unroll
+        for (int j = 0; j < MTH; j++)
+            if (MS == 1 || mt0 + j < MT)
+#pragma unroll
+                for (int r4 = 0; r4 < 4; r4++) {
+                    const R trmi = __shfl_xor(acc[0][j][r4], 8, 64);
+                    const R timi = __shfl_xor(acc[1][j][r4], 8, 64);
+                    if (store)
+                        o[16 * (mt0 + j) + crow(R(0), kq, r4)] =
+                            cx<R>((acc[0][j][r4] - timi) * scale, (trmi + acc[1][j][r4]) * scale);
+                }
     }
-}
-
-// Complex values: 8 pairs per wave, real and imaginary parts as 16 real columns.
-template <class R>
-__global__ void __launch_bounds__(64) k_m2l_mfma_cx(M2lArgs a, const R *T, const cx<R> *Mc, cx<R> *out) {
-    using V4 = typename vec4<R>::type;
-    const int lane = threadIdx.x, task = blockIdx.x;
-    const int cnt = a.task_count[task];
-    if (cnt == 0) return;
-    const int c = a.task_class[task], first = a.task_first[task];
-    const int col = lane & 15, kq = lane >> 4, p = col & 7;
-    const bool im_col = col >= 8;
-    const R *const ms[1] = {(const R *)(Mc + (int64_t)(p < cnt ? a.pair_mom[first + p] : 0) * KIN + kq) +
-                            (im_col ? 1 : 0)};
-    const R *const Tp[2] = {T + (int64_t)(2 * c) * TSZ + lane, T + (int64_t)(2 * c + 1) * TSZ + lane};
-    V4 acc[2][1][MT];
-    m2l_contract<R, 2, 1>(Tp, ms, 2, acc);
-    // lane with column p < 8 holds Tr.Mr and Ti.Mr of pair p; lane ^ 8 holds Tr.Mi and Ti.Mi
-    const bool store = !im_col && p < cnt;
-    cx<R> *o = out + (int64_t)(store ? a.pair_slot[first + p] : 0) * OUT_LD;
-    const R scale = (R)ldexp(1.0 / a.side, a.level[p < cnt ? a.pair_src[first + p] : 0]);
-#pragma unroll
-    for (int mt = 0; mt < MT; mt++)
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const R trmi = __shfl_xor(acc[0][0][mt][r], 8, 64);
-            const R timi = __shfl_xor(acc[1][0][mt][r], 8, 64);
-            if (store)
-                o[16 * mt + crow(R(0), kq, r)] =
-                    cx<R>((acc[0][0][mt][r] - timi) * scale, (trmi + acc[1][0][mt][r]) * scale);
-        }
 }
 
 // Fh(b) += sum of the b's interaction-list slots, in list order, each slot's
@@ -618,14 +624,11 @@ const R *expanded(bem_tree &t, M2lPlan &pl) {
     return buf.p;
 }
 
-// pair columns per wave: two column groups for real FP32, one otherwise
-template <class V, class R>
-constexpr int m2l_ncg() {
-    return std::is_same<V, float>::value ? 2 : 1;
-}
+// pairs per block: 16 real or 8 complex per column group
 template <class V, class R>
 constexpr int m2l_cols() {
-    return std::is_same<V, R>::value ? 16 * m2l_ncg<V, R>() : 8;
+    constexpr int NA = std::is_same<V, R>::value ? 1 : 2;
+    return (NA == 1 ? 16 : 8) * (M2L_WAVES / m2l_ms<R, NA>());
 }
 
 }  // namespace
@@ -659,10 +662,9 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc) {
         k_m2l_canonical_moments<V><<<(unsigned)((pl.n_u + 3) / 4), 256, 0, c.stream>>>(pl.n_u, pl.u_src.p, pl.u_sym.p,
                                                                                      pl.sym_in.p, P, m, Mc);
         BEM_LAUNCH_CHECK();
-        if constexpr (std::is_same<V, R>::value)
-            k_m2l_mfma<R, m2l_ncg<V, R>()><<<(unsigned)tk.n_task, 64, 0, c.stream>>>(a, Tx, Mc, out);
-        else
-            k_m2l_mfma_cx<R><<<(unsigned)tk.n_task, 64, 0, c.stream>>>(a, Tx, Mc, out);
+        c.mark(10);
+        constexpr int NA = std::is_same<V, R>::value ? 1 : 2;
+        k_m2l<R, NA><<<(unsigned)tk.n_task, 64 * M2L_WAVES, 0, c.stream>>>(a, Tx, (const R *)Mc, (R *)out);
         BEM_LAUNCH_CHECK();
         c.mark(3);
         k_m2l_reduce<V><<<(unsigned)t.n_m2l_boxes, 192, 0, c.stream>>>(t.m2l_boxes.p, t.inter_ptr.p, pl.slot_sym.p,
