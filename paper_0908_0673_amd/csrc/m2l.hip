@@ -338,32 +338,61 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, c
     }
 }
 
-// Fh(b) += sum of the b's interaction-list slots, in list order, each slot's
-// canonical result taken back to the pair's frame: row i of slot j is the
-// canonical row sym_red[sym_j][i], signed.
+// Fh(b) = sum of the b's interaction-list slots, each slot's canonical result
+// taken back to the pair's frame: row i of slot j is the canonical row
+// red[sym_j][i], signed.  One block per target box: the symmetry table and
+// the slots' symmetries are staged in LDS, wave w sums the slots j = w mod 4
+// (in order) with the loads of RU slots in flight together, and the four
+// partial sums are added in wave order (the result does not depend on
+// scheduling).  The box's locals have no other contribution yet: they are
+// written, not accumulated.
+constexpr int RED_CH = 512;  // slots staged per pass
+constexpr int RED_RU = 6;    // slots per wave in flight
+
 template <class V>
-__global__ void k_m2l_reduce(const int32_t *boxes, const int64_t *iptr, const int32_t *slot_sym,
-                             const int16_t *sym_red, int P, const V *out, V *loc) {
+__global__ void __launch_bounds__(256) k_m2l_reduce(const int32_t *boxes, const int64_t *iptr, const int32_t *slot_sym,
+                                                    const int16_t *sym_red, int P, const V *out, V *loc) {
+    __shared__ __align__(16) int16_t tab[NSYM * OUT_LD];
+    __shared__ int32_t ssym[RED_CH];
+    __shared__ V part[4][3 * 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int b = boxes[blockIdx.x];
     const int64_t j0 = iptr[b], j1 = iptr[b + 1];
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        V acc = V(0.0);
-        int64_t j = j0;
-        auto term = [&](int64_t jj) {
-            const int e = sym_red[slot_sym[jj] * OUT_LD + i];
-            const V v = out[jj * OUT_LD + (e & 0xff)];
-            return (e & 0x100) ? V(0.0) - v : v;
-        };
-        for (; j + 4 <= j1; j += 4) {
-            const V v0 = term(j), v1 = term(j + 1), v2 = term(j + 2), v3 = term(j + 3);
-            acc += v0;
-            acc += v1;
-            acc += v2;
-            acc += v3;
+    for (int x = tid; x < NSYM * OUT_LD / 8; x += 256) ((int4 *)tab)[x] = ((const int4 *)sym_red)[x];
+    V acc[3] = {V(0.0), V(0.0), V(0.0)};
+    for (int64_t cb = j0; cb < j1; cb += RED_CH) {
+        const int ns = (int)min<int64_t>(RED_CH, j1 - cb);
+        __syncthreads();
+        for (int x = tid; x < ns; x += 256) ssym[x] = slot_sym[cb + x];
+        __syncthreads();
+        for (int jb = w; jb < ns; jb += 4 * RED_RU) {
+            V v[RED_RU][3];
+            int sg[RED_RU][3];
+#pragma unroll
+            for (int k = 0; k < RED_RU; k++) {
+                const int j = jb + 4 * k;
+                const int g = j < ns ? ssym[j] : 0;
+#pragma unroll
+                for (int r = 0; r < 3; r++) {
+                    const int i = lane + 64 * r;
+                    const int e = (j < ns && i < P) ? tab[g * OUT_LD + i] : 0;
+                    sg[k][r] = (j < ns && i < P) ? ((e & 0x100) ? -1 : 1) : 0;
+                    v[k][r] = out[(cb + min(j, ns - 1)) * OUT_LD + (e & 0xff)];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < RED_RU; k++)
+#pragma unroll
+                for (int r = 0; r < 3; r++) {
+                    if (sg[k][r] > 0) acc[r] += v[k][r];
+                    else if (sg[k][r] < 0) acc[r] -= v[k][r];
+                }
         }
-        for (; j < j1; j++) acc += term(j);
-        loc[(int64_t)b * P + i] += acc;
     }
+#pragma unroll
+    for (int r = 0; r < 3; r++) part[w][lane + 64 * r] = acc[r];
+    __syncthreads();
+    for (int i = tid; i < P; i += 256) loc[(int64_t)b * P + i] = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
 }
 
 struct ClassKey {
@@ -426,7 +455,7 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     plan_fmm(t);
     FmmTables &T = *t.tables;
     const int p = t.order, P = T.P, P2 = T.P2, H = 2 * p;
-    BEM_REQUIRE(P <= MT * 16 && P <= KIN, BEM_EUNSUPPORTED, "expansion order too high for the M2L tiles");
+    BEM_REQUIRE(P <= MT * 16 && P <= KIN && P <= 3 * 64, BEM_EUNSUPPORTED, "expansion order too high for the M2L tiles");
     const bool helm = green == BEM_HELMHOLTZ;
     auto pl = std::make_unique<M2lPlan>();
     pl->green = green;
@@ -667,7 +696,7 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc) {
         k_m2l<R, NA><<<(unsigned)tk.n_task, 64 * M2L_WAVES, 0, c.stream>>>(a, Tx, (const R *)Mc, (R *)out);
         BEM_LAUNCH_CHECK();
         c.mark(3);
-        k_m2l_reduce<V><<<(unsigned)t.n_m2l_boxes, 192, 0, c.stream>>>(t.m2l_boxes.p, t.inter_ptr.p, pl.slot_sym.p,
+        k_m2l_reduce<V><<<(unsigned)t.n_m2l_boxes, 256, 0, c.stream>>>(t.m2l_boxes.p, t.inter_ptr.p, pl.slot_sym.p,
                                                                        pl.sym_red.p, P, out, l);
         BEM_LAUNCH_CHECK();
         c.mark(10);
