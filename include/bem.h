@@ -27,8 +27,12 @@
  *    library never frees them.
  *  - Device vectors hold nrhs right-hand sides as [nrhs][n_dof]: float64 for
  *    Laplace, interleaved complex128 (re, im) for Helmholtz.
- *  - All device work is ordered on the context's stream; calls return when
- *    their work has completed.  A context is not thread-safe.
+ *  - All device work is ordered on the context's stream (bem_matvec may
+ *    also use a second internal stream of the context, joined back into the
+ *    context's stream before it returns).  bem_matvec returns once its work
+ *    is enqueued (stream-ordered, like a kernel launch; the first call for a
+ *    (g, k) also waits for its set-up); every other call returns when its
+ *    work has completed.  A context is not thread-safe.
  */
 #ifndef BEM_H
 #define BEM_H
@@ -97,7 +101,11 @@ const char *bem_last_error(const bem_ctx *ctx);
  * While timing is enabled every phase runs on the context's stream; without
  * it the near field runs concurrently with the far field on a second
  * stream, so the per-phase times are those of the serialized product.
- * enable = 1 turns timing on and zeroes the counters; 0 turns it off.
+ * enable = 1 turns phase timing on and zeroes the counters; 2 instead times
+ * only the two heavy kernels (the M2L products as phase 3 and the near field
+ * as phase 6, each with events on the stream it runs on) and leaves the
+ * scheduling of the product unchanged; 0 turns timing off.  Other values
+ * give BEM_EINVAL.
  * ms and launches (host arrays of BEM_NPHASE, may be NULL) receive the
  * accumulated milliseconds and the number of products timed per phase. */
 #define BEM_NPHASE 11

@@ -179,12 +179,14 @@ class Context:
 
     PHASES = ("strength", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "combine", "direct", "other", "m2l_aux")
 
-    def timing(self, enable: bool):
-        """Turns per-phase event timing on (zeroing it) or off; returns the
+    def timing(self, mode):
+        """Sets the event timing mode (0 / False off, 1 / True per phase with
+        every phase on one stream, 2 the two heavy kernels only with the usual
+        scheduling), zeroing the counters when it changes; returns the
         accumulated {phase: (ms, products)} before the switch."""
         ms = np.zeros(len(self.PHASES))
         n = np.zeros(len(self.PHASES), np.int64)
-        self.check(self.L.bem_ctx_timing(self.h, int(enable), _np_ptr(ms), _np_ptr(n)), "bem_ctx_timing")
+        self.check(self.L.bem_ctx_timing(self.h, int(mode), _np_ptr(ms), _np_ptr(n)), "bem_ctx_timing")
         return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(self.PHASES)}
 
     def close(self):

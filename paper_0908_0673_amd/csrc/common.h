@@ -40,8 +40,11 @@ struct Error : std::runtime_error {
 
 // ---------------------------------------------------------------- context
 struct Ctx {
-    // phase timing with events on the context's stream
-    bool timing = false;
+    // Timing with HIP events.  Mode 1 (phases): events between the phases on
+    // the context's stream, with every phase on that stream.  Mode 2 (heavy
+    // kernels): event pairs around the M2L product and near-field kernels
+    // only, each on the stream it runs on, with the usual scheduling.
+    int timing = 0;
     double phase_ms[BEM_NPHASE] = {0};
     int64_t phase_n[BEM_NPHASE] = {0};
     std::vector<hipEvent_t> events;
@@ -49,7 +52,7 @@ struct Ctx {
     int ev_used = 0;
 
     void mark(int phase) {
-        if (!timing) return;
+        if (timing != 1) return;
         if (ev_used == (int)events.size()) {
             hipEvent_t e;
             BEM_HIP(hipEventCreate(&e));
@@ -60,9 +63,43 @@ struct Ctx {
         ev_phase[ev_used] = phase;
         ev_used++;
     }
-    // after the stream has been synchronised: fold the recorded intervals into the counters
+    // mode 2: an event pair around one kernel on stream st
+    std::vector<hipEvent_t> kev;
+    std::vector<int> kev_phase;  // phase of each pair
+    int kev_used = 0;            // events used (two per pair)
+    hipEvent_t kernel_event() {
+        if (kev_used == (int)kev.size()) {
+            hipEvent_t e;
+            BEM_HIP(hipEventCreate(&e));
+            kev.push_back(e);
+        }
+        return kev[kev_used++];
+    }
+    void kbegin(hipStream_t st, int phase) {
+        if (timing != 2) return;
+        BEM_HIP(hipEventRecord(kernel_event(), st));
+        kev_phase.resize(kev_used / 2 + 1);
+        kev_phase[kev_used / 2] = phase;
+    }
+    void kend(hipStream_t st) {
+        if (timing != 2) return;
+        BEM_HIP(hipEventRecord(kernel_event(), st));
+    }
+    // after the streams have been synchronised: fold the recorded intervals into the counters
     void collect() {
-        if (!timing) return;
+        if (timing == 2) {
+            bool seen[BEM_NPHASE] = {false};
+            for (int i = 0; i + 1 < kev_used; i += 2) {
+                float ms = 0.f;
+                BEM_HIP(hipEventElapsedTime(&ms, kev[i], kev[i + 1]));
+                const int ph = kev_phase[i / 2];
+                phase_ms[ph] += ms;
+                if (!seen[ph]) { phase_n[ph]++; seen[ph] = true; }
+            }
+            kev_used = 0;
+            return;
+        }
+        if (timing != 1) return;
         bool seen[BEM_NPHASE] = {false};
         for (int i = 1; i < ev_used; i++) {
             float ms = 0.f;
@@ -77,6 +114,7 @@ struct Ctx {
     }
     ~Ctx() {
         for (auto e : events) (void)hipEventDestroy(e);
+        for (auto e : kev) (void)hipEventDestroy(e);
         release_streams();
     }
 

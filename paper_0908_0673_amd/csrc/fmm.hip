@@ -656,6 +656,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         auto near_field = [&](hipStream_t st) {
             dim3 g((unsigned)t.n_p2p_units, nrhs);
             const bool beside = st != c.stream;
+            c.kbegin(st, 6);
             if (dbl)
                 k_p2p<V, R, true, HELM><<<g, P2P_BS, beside ? near_lds((const void *)k_p2p<V, R, true, HELM>) : 0,
                                           st>>>(
@@ -667,6 +668,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
                     t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
                     t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
             BEM_LAUNCH_CHECK();
+            c.kend(st);
         };
         // The near field depends only on the strengths and writes only its
         // own partial sums: it runs on the second stream, concurrently with
@@ -674,7 +676,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         // pass, which it would otherwise crowd out), and is joined before its
         // sums are added.  While phases are being timed everything stays on
         // one stream.
-        const bool overlap = t.n_p2p_items && !c.timing;
+        const bool overlap = t.n_p2p_items && c.timing != 1;
         // upward pass (boxes without elements keep zero moments)
         zero_fill(c, mom, 2 * sizeof(V) * nexp);
         p2m_apply<V, R, XV>(t, dbl, nrhs, x, mom);

@@ -693,8 +693,10 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc) {
         BEM_LAUNCH_CHECK();
         c.mark(10);
         constexpr int NA = std::is_same<V, R>::value ? 1 : 2;
+        c.kbegin(c.stream, 3);
         k_m2l<R, NA><<<(unsigned)tk.n_task, 64 * M2L_WAVES, 0, c.stream>>>(a, Tx, (const R *)Mc, (R *)out);
         BEM_LAUNCH_CHECK();
+        c.kend(c.stream);
         c.mark(3);
         k_m2l_reduce<V><<<(unsigned)t.n_m2l_boxes, 256, 0, c.stream>>>(t.m2l_boxes.p, t.inter_ptr.p, pl.slot_sym.p,
                                                                        pl.sym_red.p, P, out, l);
