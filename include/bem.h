@@ -51,7 +51,8 @@ typedef enum {
     BEM_EDEVICE = -3,       /* a HIP runtime call failed */
     BEM_ENOCONV = -4,       /* the solver hit its iteration cap (outputs still written) */
     BEM_ESTATE = -5,        /* handle misuse (wrong context, freed object) */
-    BEM_EUNSUPPORTED = -6   /* valid request this build does not implement */
+    BEM_EUNSUPPORTED = -6,  /* valid request this build does not implement */
+    BEM_EAGAIN = -7         /* (serving) the request has not completed yet */
 } bem_status;
 
 typedef enum { BEM_LAPLACE = 0, BEM_HELMHOLTZ = 1 } bem_green;
@@ -222,6 +223,64 @@ typedef struct {
  * not converge. */
 int bem_solve(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, int nrhs,
               const void *chi_dev, void *phi_dev, const bem_solve_opts *opts, bem_solve_info *info);
+
+/* ------------------------------------------------------------------ serving
+ * Batched / concurrent solves for many independent problems on one GPU (no
+ * counterpart in the paper: a production layer around the solve above).
+ * A server runs `lanes` workers, each with its own context (HIP stream of
+ * its own, default priority) and host thread.  Meshes are registered once and
+ * stay with one lane, which builds their mesh and tree on first use and
+ * keeps them while they fit: before building, a lane evicts its least
+ * recently used meshes until its resident bytes plus the estimate for the
+ * new tree fit its share (hbm_budget / lanes) of the budget (a mesh larger
+ * than the share is still served, alone).  Requests queue per lane in
+ * arrival order; a worker takes the oldest request and merges the waiting
+ * requests with the same (mesh, Green, k) into one solve, up to
+ * max_batch_rhs right-hand sides (continuous batching).  Every right-hand
+ * side is solved exactly as bem_solve solves it with the same options, so
+ * results do not depend on batching, lanes or arrival order.
+ * Host buffers passed to the server are copied at the call; results are
+ * copied out by bem_server_poll.  The server calls are thread-safe. */
+typedef struct bem_server bem_server;
+
+typedef struct {
+    int device;              /* HIP device */
+    int lanes;               /* concurrent workers; 0 -> 4 */
+    int64_t hbm_budget;      /* device bytes for resident meshes, trees and solves; 0 -> 32 GiB */
+    int max_batch_rhs;       /* most right-hand sides merged into one solve; 0 -> 32 */
+    bem_tree_opts tree;      /* tree options of every mesh (zero fields -> defaults) */
+    bem_solve_opts solve;    /* solve options of every request (zero fields -> defaults) */
+} bem_server_opts;
+
+typedef struct {
+    int64_t submitted, completed, batches, rhs_solved, evictions, trees_built;
+    int64_t resident_bytes;  /* device bytes held by the lanes now */
+} bem_server_stats;
+
+/* Starts the workers.  Errors: BEM_EINVAL for bad options, BEM_EDEVICE. */
+int bem_server_create(const bem_server_opts *opts, bem_server **out);
+/* Registers a mesh (arguments as bem_mesh_load, host arrays copied) and
+ * returns its id and DOF count (the layout of chi / phi below).  The DOF
+ * indexing runs here on the host; device work waits for the first request. */
+int bem_server_add_mesh(bem_server *s, const double *node_xyz, int64_t n_nodes, const int32_t *elem_nodes,
+                        int64_t n_elem, const bem_mesh_opts *opts, int32_t *mesh_id, int64_t *n_dof);
+/* Queues a solve of c.phi - K phi = -S chi for nrhs right-hand sides; chi_host
+ * is [nrhs][n_dof] float64 (Laplace) or interleaved complex128 (Helmholtz),
+ * copied here.  Returns a ticket.  Errors: BEM_EINVAL (unknown mesh, nrhs < 1,
+ * k <= 0 for Helmholtz). */
+int bem_server_submit(bem_server *s, int32_t mesh_id, bem_green g, double k, int nrhs, const void *chi_host,
+                      int64_t *ticket);
+/* Result of a ticket: with wait != 0 blocks until it completes.  When done,
+ * copies phi ([nrhs][n_dof], may be NULL) and info ([nrhs], may be NULL),
+ * sets *latency_s (may be NULL) to the time from submission to completion,
+ * releases the ticket and returns the solve's status (BEM_OK or
+ * BEM_ENOCONV, or the error that stopped it).  Returns BEM_EAGAIN if not
+ * done and wait == 0, BEM_EINVAL for an unknown ticket. */
+int bem_server_poll(bem_server *s, int64_t ticket, int wait, void *phi_host, bem_solve_info *info,
+                    double *latency_s);
+int bem_server_stats_get(bem_server *s, bem_server_stats *st);
+/* Finishes the queued work, stops the workers and frees everything. */
+void bem_server_destroy(bem_server *s);
 
 #ifdef __cplusplus
 }

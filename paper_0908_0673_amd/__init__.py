@@ -21,6 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbem.so")
 
 BEM_OK, BEM_EINVAL, BEM_ENOMEM, BEM_EDEVICE, BEM_ENOCONV, BEM_ESTATE, BEM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+BEM_EAGAIN = -7
 BEM_LAPLACE, BEM_HELMHOLTZ = 0, 1
 BEM_OP_S, BEM_OP_K, BEM_OP_A, BEM_OP_RHS = 0, 1, 2, 3
 BEM_DIRECT, BEM_FMM = 0, 1
@@ -29,6 +30,8 @@ BEM_PREC_FP64, BEM_PREC_MIXED = 0, 1
 EXPORTED = [
     "bem_ctx_create", "bem_ctx_destroy", "bem_ctx_timing", "bem_last_error", "bem_mesh_load", "bem_mesh_dofs", "bem_mesh_free",
     "bem_tree_build", "bem_tree_export", "bem_tree_free", "bem_tree_stats_get", "bem_matvec", "bem_solve",
+    "bem_server_create", "bem_server_add_mesh", "bem_server_submit", "bem_server_poll", "bem_server_stats_get",
+    "bem_server_destroy",
 ]
 
 
@@ -73,6 +76,16 @@ class _SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_restarts", ctypes.c_int),
                 ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
                 ("method", ctypes.c_int)]
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("lanes", ctypes.c_int), ("hbm_budget", ctypes.c_int64),
+                ("max_batch_rhs", ctypes.c_int), ("tree", _TreeOpts), ("solve", _SolveOpts)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "batches", "rhs_solved", "evictions",
+                                              "trees_built", "resident_bytes")]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -128,6 +141,14 @@ def load_library(path: str = LIB_PATH):
     L.bem_tree_stats_get.argtypes = [vp, vp, i32, dbl, ctypes.POINTER(_TreeStats)]
     L.bem_matvec.argtypes = [vp, vp, i32, dbl, i32, i32, i32, i32, vp, vp]
     L.bem_solve.argtypes = [vp, vp, i32, dbl, i32, vp, vp, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo)]
+    L.bem_server_create.argtypes = [ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]
+    L.bem_server_add_mesh.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(_MeshOpts), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(i64)]
+    L.bem_server_submit.argtypes = [vp, ctypes.c_int32, i32, dbl, i32, vp, ctypes.POINTER(i64)]
+    L.bem_server_poll.argtypes = [vp, i64, i32, vp, ctypes.POINTER(_SolveInfo), ctypes.POINTER(dbl)]
+    L.bem_server_stats_get.argtypes = [vp, ctypes.POINTER(_ServerStats)]
+    L.bem_server_destroy.argtypes = [vp]
+    L.bem_server_destroy.restype = None
     _lib = L
     return L
 
@@ -330,3 +351,87 @@ def bem_solve(ctx: Context, tree: Tree, green: int, k: float, chi, phi, tol=1e-8
     if rc != 0 and (rc != BEM_ENOCONV or raise_on_noconv):
         ctx.check(rc, "bem_solve")
     return [{n: getattr(i, n) for n, _ in _SolveInfo._fields_} for i in info]
+
+
+class Server:
+    """Batched / concurrent solves of many problems on one GPU (bem_server_*).
+
+    Host arrays in, host arrays out: meshes are registered once
+    (add_mesh -> (id, n_dof)); submit() queues a solve of nrhs right-hand
+    sides ([nrhs, n_dof] float64, or complex128 for Helmholtz) and returns a
+    ticket; poll() returns (status, phi, infos, latency_s), or None while the
+    request is pending and wait is False."""
+
+    def __init__(self, device=0, lanes=4, hbm_budget=32 << 30, max_batch_rhs=32, tol=1e-8, restart=50,
+                 max_restarts=100, precision=BEM_PREC_FP64, inner_tol=1e-5, max_refine=10, method=BEM_FMM,
+                 B=32, order=8, theta=0.6, kappa=0.0, max_depth=21):
+        self.L = load_library()
+        o = _ServerOpts()
+        o.device, o.lanes, o.hbm_budget, o.max_batch_rhs = device, lanes, int(hbm_budget), max_batch_rhs
+        o.tree = _TreeOpts(B, order, theta, kappa, max_depth, 0.0)
+        o.solve = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method)
+        h = ctypes.c_void_p()
+        rc = self.L.bem_server_create(ctypes.byref(o), ctypes.byref(h))
+        if rc != 0:
+            raise BemError(rc, "bem_server_create failed")
+        self.h = h.value
+        self._meta = {}  # ticket -> (nrhs, n_dof, complex)
+        self._ndof = {}
+        _track(self)
+
+    def add_mesh(self, xyz, elem, edge_angle_deg: float = 30.0):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        elem = np.ascontiguousarray(elem, dtype=np.int32)
+        mid, nd = ctypes.c_int32(), ctypes.c_int64()
+        rc = self.L.bem_server_add_mesh(self.h, _np_ptr(xyz), xyz.shape[0], _np_ptr(elem), elem.shape[0],
+                                        ctypes.byref(_MeshOpts(edge_angle_deg)), ctypes.byref(mid), ctypes.byref(nd))
+        if rc != 0:
+            raise BemError(rc, "bem_server_add_mesh failed")
+        self._ndof[mid.value] = nd.value
+        return mid.value, nd.value
+
+    def submit(self, mesh_id: int, green: int, k: float, chi) -> int:
+        cplx = green == BEM_HELMHOLTZ
+        chi = np.ascontiguousarray(np.atleast_2d(chi), dtype=np.complex128 if cplx else np.float64)
+        nrhs, nd = chi.shape
+        if nd != self._ndof.get(mesh_id, -1):
+            raise ValueError("chi does not match the mesh's DOF count")
+        t = ctypes.c_int64()
+        rc = self.L.bem_server_submit(self.h, mesh_id, green, float(k), nrhs, _np_ptr(chi), ctypes.byref(t))
+        if rc != 0:
+            raise BemError(rc, "bem_server_submit failed")
+        self._meta[t.value] = (nrhs, nd, cplx)
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        if ticket not in self._meta:
+            raise BemError(BEM_EINVAL, "unknown ticket")
+        nrhs, nd, cplx = self._meta[ticket]
+        phi = np.empty((nrhs, nd), dtype=np.complex128 if cplx else np.float64)
+        info = (_SolveInfo * nrhs)()
+        lat = ctypes.c_double()
+        rc = self.L.bem_server_poll(self.h, ticket, int(wait), _np_ptr(phi), info, ctypes.byref(lat))
+        if rc == BEM_EAGAIN:
+            return None
+        if rc == BEM_EINVAL:
+            raise BemError(rc, "unknown ticket")
+        del self._meta[ticket]
+        return rc, phi, [{n: getattr(i, n) for n, _ in _SolveInfo._fields_} for i in info], lat.value
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        rc = self.L.bem_server_stats_get(self.h, ctypes.byref(st))
+        if rc != 0:
+            raise BemError(rc, "bem_server_stats_get failed")
+        return {n: getattr(st, n) for n, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.bem_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass

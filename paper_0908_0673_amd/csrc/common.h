@@ -4,10 +4,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/bem.h"
@@ -124,6 +126,9 @@ struct Ctx {
     bool has_alloc = false;
     std::string err;
 
+    // device bytes currently held by the library through this context
+    std::atomic<size_t> bytes_live{0};
+    std::unordered_map<void *, size_t> sizes;
     void *dmalloc(size_t bytes) {
         if (bytes == 0) bytes = 256;
         void *p = nullptr;
@@ -134,10 +139,17 @@ struct Ctx {
             hipError_t e = hipMalloc(&p, bytes);
             if (e != hipSuccess) fail(BEM_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
         }
+        sizes[p] = bytes;
+        bytes_live += bytes;
         return p;
     }
     void dfree(void *p) {
         if (!p) return;
+        auto it = sizes.find(p);
+        if (it != sizes.end()) {
+            bytes_live -= it->second;
+            sizes.erase(it);
+        }
         if (has_alloc) alloc.free(alloc.user, p, (void *)stream);
         else (void)hipFree(p);
     }

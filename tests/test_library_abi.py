@@ -55,3 +55,21 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt and "bem_oracle" not in txt, f
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbem.so not built")
+def test_server_options_are_checked_before_any_device_work():
+    """Bad serving options are refused with BEM_EINVAL, and with no usable
+    device the server reports BEM_EDEVICE (no host fallback)."""
+    import paper_0908_0673_amd as bem
+
+    L = bem.load_library()
+    h = ctypes.c_void_p()
+    o = bem._ServerOpts()
+    o.lanes = -1
+    assert L.bem_server_create(ctypes.byref(o), ctypes.byref(h)) == bem.BEM_EINVAL
+    o.lanes, o.max_batch_rhs = 1, -3
+    assert L.bem_server_create(ctypes.byref(o), ctypes.byref(h)) == bem.BEM_EINVAL
+    o.max_batch_rhs, o.device = 1, 1 << 20  # no such device
+    assert L.bem_server_create(ctypes.byref(o), ctypes.byref(h)) == bem.BEM_EDEVICE
+    assert not h.value
