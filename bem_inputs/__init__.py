@@ -1,7 +1,8 @@
 """Seeded synthetic inputs shared by the GPU path's tests and by the oracle.
 
-This package holds geometry generators (meshes of curved 6-node triangles)
-and seeded random vectors only.  It contains none of the boundary element
+This package holds geometry generators (meshes of curved 6-node triangles),
+seeded random vectors and seeded request streams (sizes, shapes, draws)
+only.  It contains none of the boundary element
 method's arithmetic: no shape-function evaluation, no quadrature, no Green's
 function, no tree.  Both sides of every parity test take their meshes and
 input vectors from here and compute everything else on their own.
@@ -17,3 +18,4 @@ from .meshes import (  # noqa: F401
     WORKLOADS,
 )
 from .vectors import random_vector, random_directions  # noqa: F401
+from .requests import request_stream, mesh_of  # noqa: F401

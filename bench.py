@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-phases", action="store_true", help="skip the serialized per-phase timing pass")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving measurement on the longer stream (200 requests, 2000-40000 triangles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -211,6 +214,13 @@ def main():
                 "other_kernel": {"name": [k for k in kern if k != dom][0],
                                  "avg_launch_ms": min(per_launch.values())}}
 
+    serve = None
+    if not args.no_serve:
+        if args.serve_full:
+            serve = serving(200, 20090908, (2000, 40000), (1.0, 25.0), 32, 4, 96 << 30)
+        else:
+            serve = serving(24, 20090908, (1000, 6000), (1.0, 5.0), 8, 4, 32 << 30)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(m, x_np, args.cpu_seconds)
@@ -240,9 +250,107 @@ def main():
         "setup_s": t_setup,
         "solve": solve,
         "roofline": roofline,
+        "serving": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def _boundary_data(dofs, req):
+    """Neumann data of a request: for Helmholtz the sound-hard scattered-field
+    data of unit plane waves along the request's directions; for Laplace the
+    flux of a unit point source at 0.1 d inside the body, per direction d."""
+    x, nrm = dofs["dof_xyz"], dofs["dof_normal"]
+    rows = []
+    for d in req["dirs"]:
+        if req["green"]:
+            k = req["k"]
+            rows.append(-1j * k * (nrm @ d) * np.exp(1j * k * (x @ d)))
+        else:
+            r = x - 0.1 * d[None, :]
+            R = np.linalg.norm(r, axis=1)
+            rows.append(-np.einsum("ij,ij->i", r, nrm) / (4 * np.pi * R ** 3))
+    return np.array(rows)
+
+
+def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5):
+    """Served, mixed-precision solves (bem_server_*: concurrent lanes, request
+    merging) against plain FP64 one-at-a-time solves on one context, on the
+    same seeded request stream; trees are cached per mesh on both sides.
+    Throughput: all requests offered at once.  Latency: a second pass with
+    Poisson arrivals at rate_frac times the measured request throughput
+    (warm caches), submission to completion."""
+    import torch
+
+    import paper_0908_0673_amd as bem
+    from bem_inputs.requests import mesh_of, request_stream
+
+    reqs = request_stream(count, seed, n_tri=n_tri, ka=ka, nrhs_max=nrhs_max)
+    meshes = {}
+    for r in reqs:
+        if r["key"] not in meshes:
+            meshes[r["key"]] = mesh_of(r)
+    total_rhs = sum(r["nrhs"] for r in reqs)
+    out = {"requests": count, "rhs": total_rhs, "distinct_meshes": len(meshes),
+           "elements": [int(min(m.n_elem for m in meshes.values())), int(max(m.n_elem for m in meshes.values()))],
+           "lanes": lanes, "hbm_budget_gb": budget / 2 ** 30, "seed": seed,
+           "stream": f"n_tri log-uniform {list(n_tri)}, sphere/cube/ellipsoid, Laplace/Helmholtz 50/50, "
+                     f"ka U{list(ka)}, nrhs U[1,{nrhs_max}]"}
+    # served
+    srv = bem.Server(lanes=lanes, hbm_budget=budget, max_batch_rhs=32, precision=bem.BEM_PREC_MIXED)
+    try:
+        ids = {key: srv.add_mesh(m.xyz, m.elem)[0] for key, m in meshes.items()}
+        chis = [_boundary_data(srv.mesh_dofs(ids[r["key"]]), r) for r in reqs]
+        t0 = time.perf_counter()
+        tickets = [srv.submit(ids[r["key"]], r["green"], r["k"], c) for r, c in zip(reqs, chis)]
+        res = [srv.poll(t) for t in tickets]
+        dt = time.perf_counter() - t0
+        out["served_solves_per_s"] = total_rhs / dt
+        out["served_requests_per_s"] = count / dt
+        out["served_not_converged"] = sum(1 for r in res for i in r[2] if i["status"] != 0)
+        rate = rate_frac * count / dt
+        t0 = time.perf_counter()
+        tickets = []
+        for r, c in zip(reqs, chis):
+            wait = r["t"] / rate - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            tickets.append(srv.submit(ids[r["key"]], r["green"], r["k"], c))
+        lat = np.array([srv.poll(t)[3] for t in tickets])
+        out["open_loop_rate_requests_per_s"] = rate
+        out["latency_ms"] = {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)}
+        out["server_stats"] = srv.stats()
+    finally:
+        srv.close()
+    # plain FP64, one request at a time
+    ctx = bem.Context(0)
+    trees = {}
+    t0 = time.perf_counter()
+    lat_base = []
+    nconv = 0
+    for r, c in zip(reqs, chis):
+        t1 = time.perf_counter()
+        if r["key"] not in trees:
+            m = meshes[r["key"]]
+            mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
+            trees[r["key"]] = (mesh, bem.bem_tree_build(ctx, mesh, B=32, order=8, theta=0.6))
+        cplx = r["green"] == 1
+        chid = torch.tensor(c if cplx else c.real, dtype=torch.complex128 if cplx else torch.float64, device="cuda:0")
+        phid = torch.empty_like(chid)
+        info = bem.bem_solve(ctx, trees[r["key"]][1], r["green"], r["k"], chid, phid, precision=bem.BEM_PREC_FP64)
+        torch.cuda.synchronize()
+        nconv += sum(1 for i in info if i["status"] != 0)
+        lat_base.append(time.perf_counter() - t1)
+    dtb = time.perf_counter() - t0
+    out["baseline_fp64_solves_per_s"] = total_rhs / dtb
+    out["baseline_not_converged"] = nconv
+    out["baseline_latency_ms"] = {"p50": float(np.percentile(lat_base, 50) * 1e3),
+                                  "p99": float(np.percentile(lat_base, 99) * 1e3)}
+    out["speedup_solves_per_s"] = out["served_solves_per_s"] / out["baseline_fp64_solves_per_s"]
+    for tr in trees.values():
+        tr[1].close()
+        tr[0].close()
+    return out
 
 
 def cpu_baseline(m, x_np, seconds):

@@ -264,6 +264,8 @@ int bem_server_create(const bem_server_opts *opts, bem_server **out);
  * indexing runs here on the host; device work waits for the first request. */
 int bem_server_add_mesh(bem_server *s, const double *node_xyz, int64_t n_nodes, const int32_t *elem_nodes,
                         int64_t n_elem, const bem_mesh_opts *opts, int32_t *mesh_id, int64_t *n_dof);
+/* DOF layout of a registered mesh (as bem_mesh_dofs; each buffer may be NULL). */
+int bem_server_mesh_dofs(bem_server *s, int32_t mesh_id, int32_t *elem_dofs, double *dof_xyz, double *dof_normal);
 /* Queues a solve of c.phi - K phi = -S chi for nrhs right-hand sides; chi_host
  * is [nrhs][n_dof] float64 (Laplace) or interleaved complex128 (Helmholtz),
  * copied here.  Returns a ticket.  Errors: BEM_EINVAL (unknown mesh, nrhs < 1,

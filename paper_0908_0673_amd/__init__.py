@@ -30,7 +30,8 @@ BEM_PREC_FP64, BEM_PREC_MIXED = 0, 1
 EXPORTED = [
     "bem_ctx_create", "bem_ctx_destroy", "bem_ctx_timing", "bem_last_error", "bem_mesh_load", "bem_mesh_dofs", "bem_mesh_free",
     "bem_tree_build", "bem_tree_export", "bem_tree_free", "bem_tree_stats_get", "bem_matvec", "bem_solve",
-    "bem_server_create", "bem_server_add_mesh", "bem_server_submit", "bem_server_poll", "bem_server_stats_get",
+    "bem_server_create", "bem_server_add_mesh", "bem_server_mesh_dofs", "bem_server_submit", "bem_server_poll",
+    "bem_server_stats_get",
     "bem_server_destroy",
 ]
 
@@ -122,6 +123,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with paper_0908_0673_amd/build.py (hipcc, gfx950)")
+    # torch first: the library then binds to the HIP runtime torch has loaded
+    # (one runtime per process), whichever of the two a caller touches first
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(path)
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     L.bem_ctx_create.argtypes = [i32, vp, ctypes.POINTER(_Allocator), ctypes.POINTER(vp)]
@@ -144,6 +149,7 @@ def load_library(path: str = LIB_PATH):
     L.bem_server_create.argtypes = [ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]
     L.bem_server_add_mesh.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(_MeshOpts), ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(i64)]
+    L.bem_server_mesh_dofs.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
     L.bem_server_submit.argtypes = [vp, ctypes.c_int32, i32, dbl, i32, vp, ctypes.POINTER(i64)]
     L.bem_server_poll.argtypes = [vp, i64, i32, vp, ctypes.POINTER(_SolveInfo), ctypes.POINTER(dbl)]
     L.bem_server_stats_get.argtypes = [vp, ctypes.POINTER(_ServerStats)]
@@ -366,6 +372,10 @@ class Server:
                  max_restarts=100, precision=BEM_PREC_FP64, inner_tol=1e-5, max_refine=10, method=BEM_FMM,
                  B=32, order=8, theta=0.6, kappa=0.0, max_depth=21):
         self.L = load_library()
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the library runs on gfx950 only")
         o = _ServerOpts()
         o.device, o.lanes, o.hbm_budget, o.max_batch_rhs = device, lanes, int(hbm_budget), max_batch_rhs
         o.tree = _TreeOpts(B, order, theta, kappa, max_depth, 0.0)
@@ -389,6 +399,15 @@ class Server:
             raise BemError(rc, "bem_server_add_mesh failed")
         self._ndof[mid.value] = nd.value
         return mid.value, nd.value
+
+    def mesh_dofs(self, mesh_id: int) -> dict:
+        """DOF layout of a registered mesh: dof_xyz, dof_normal [n_dof, 3]."""
+        nd = self._ndof[mesh_id]
+        xyz, nrm = np.empty((nd, 3)), np.empty((nd, 3))
+        rc = self.L.bem_server_mesh_dofs(self.h, mesh_id, None, _np_ptr(xyz), _np_ptr(nrm))
+        if rc != 0:
+            raise BemError(rc, "bem_server_mesh_dofs failed")
+        return {"dof_xyz": xyz, "dof_normal": nrm}
 
     def submit(self, mesh_id: int, green: int, k: float, chi) -> int:
         cplx = green == BEM_HELMHOLTZ

@@ -39,6 +39,8 @@ struct Request {
 struct MeshEntry {
     std::vector<double> xyz;
     std::vector<int32_t> elem;
+    std::vector<int32_t> elem_dofs, dof_node;
+    std::vector<double> dof_normal;
     bem_mesh_opts mopts{};
     int64_t n_nodes = 0, n_elem = 0, n_dof = 0;
     int lane = 0;
@@ -288,6 +290,9 @@ int bem_server_add_mesh(bem_server *s, const double *node_xyz, int64_t n_nodes, 
             if (!std::isfinite(v)) return BEM_EINVAL;
         bem::index_dofs(tmp, me->mopts.edge_angle_deg > 0.0 ? me->mopts.edge_angle_deg : 30.0);
         me->n_dof = tmp.n_dof;
+        me->elem_dofs = tmp.h_elem_dofs;
+        me->dof_node = tmp.h_dof_node;
+        me->dof_normal = tmp.h_dof_normal;
     } catch (const bem::Error &e) {
         return e.code;
     } catch (...) {
@@ -298,6 +303,19 @@ int bem_server_add_mesh(bem_server *s, const double *node_xyz, int64_t n_nodes, 
     *mesh_id = (int32_t)s->meshes.size();
     if (n_dof) *n_dof = me->n_dof;
     s->meshes.push_back(std::move(me));
+    return BEM_OK;
+}
+
+int bem_server_mesh_dofs(bem_server *s, int32_t mesh_id, int32_t *elem_dofs, double *dof_xyz, double *dof_normal) {
+    if (!s) return BEM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (mesh_id < 0 || mesh_id >= (int32_t)s->meshes.size()) return BEM_EINVAL;
+    const MeshEntry &m = *s->meshes[mesh_id];
+    if (elem_dofs) std::memcpy(elem_dofs, m.elem_dofs.data(), sizeof(int32_t) * m.elem_dofs.size());
+    if (dof_xyz)
+        for (int64_t i = 0; i < m.n_dof; i++)
+            for (int d = 0; d < 3; d++) dof_xyz[3 * i + d] = m.xyz[3 * (int64_t)m.dof_node[i] + d];
+    if (dof_normal) std::memcpy(dof_normal, m.dof_normal.data(), sizeof(double) * m.dof_normal.size());
     return BEM_OK;
 }
 
