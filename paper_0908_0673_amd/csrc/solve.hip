@@ -14,6 +14,7 @@
 //   MIXED  outer refinement in FP64: d = GMRES(A_mixed, r, inner_tol);
 //          x += d; r = b - A_64 x; until |r| / |b| <= tol.
 #include <cmath>
+#include <memory>
 
 #include "kernels.h"
 
@@ -166,7 +167,7 @@ struct Krylov {
     int nblk;
     DBuf<V> basis, w, hcol, hc2, H, cs, sn, g, y, partial, tmp;
     DBuf<double> est;  // [0] residual estimate, [1] scratch
-    double *h_est = nullptr;
+    double *h_est = nullptr;  // pinned host copies of est[0], est[1]
 
     Krylov(Ctx &c_, int64_t n_, int m_) : c(c_), n(n_), m(m_) {
         nblk = (int)std::min<int64_t>(256, nblocks(n, RBS));
@@ -182,7 +183,7 @@ struct Krylov {
         y.alloc(&c, m);
         partial.alloc(&c, (size_t)(m + 2) * nblk);
         est.alloc(&c, 2);
-        BEM_HIP(hipHostMalloc((void **)&h_est, sizeof(double), hipHostMallocDefault));
+        BEM_HIP(hipHostMalloc((void **)&h_est, 2 * sizeof(double), hipHostMallocDefault));
     }
     ~Krylov() {
         if (h_est) (void)hipHostFree(h_est);
@@ -197,100 +198,212 @@ struct Krylov {
         k_dots_finish<V><<<nblocks(cnt, 64), 64, 0, c.stream>>>(partial.p, nblk, cnt, out, acc ? 1 : 0);
         BEM_LAUNCH_CHECK();
     }
-    double norm(const V *v) {
+    // |v|^2 into est[1] and its host copy (read after a stream sync)
+    void norm_async(const V *v) {
         dots(v, 1, v, hc2.p, false);
         k_norm2_to<V><<<1, 1, 0, c.stream>>>(hc2.p, est.p + 1);
         BEM_LAUNCH_CHECK();
-        double v2 = read_scalar(c, est.p + 1);
-        return std::sqrt(v2);
+        BEM_HIP(hipMemcpyAsync(h_est + 1, est.p + 1, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    }
+    double norm(const V *v) {
+        norm_async(v);
+        c.sync();
+        return std::sqrt(h_est[1]);
     }
 };
 
-// GMRES(m) on apply(); x holds the initial guess and receives the result.
+// |v_i| of each (K_i, v_i), with one stream sync for all of them.
+template <class V>
+std::vector<double> norms(std::vector<Krylov<V> *> &K, const std::vector<const V *> &v) {
+    for (size_t i = 0; i < K.size(); i++) K[i]->norm_async(v[i]);
+    if (!K.empty()) K[0]->c.sync();
+    std::vector<double> out(K.size());
+    for (size_t i = 0; i < K.size(); i++) out[i] = std::sqrt(K[i]->h_est[1]);
+    return out;
+}
+
+// Lock-step GMRES(m) for several right-hand sides.  Each right-hand side r
+// runs exactly the iteration a solve of r alone runs (its own Krylov space,
+// rotations, decisions and kernels, in the same order); only the operator
+// products of the right-hand sides that need one at a step are applied
+// together, as one multi-vector product (whose columns equal single
+// products bit for bit), and the host reads every residual estimate of a
+// step after one synchronisation.  x_r holds the initial guess (zero when
+// zero_x0) and receives the result.
 template <class V, class F>
-int gmres(Krylov<V> &K, F &&apply, const V *b, V *x, double tol, int max_cycles, int *iters, int *matvecs,
-          double *relres, bool zero_x0) {
-    Ctx &c = K.c;
-    const int64_t n = K.n;
-    const int m = K.m;
+void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, const std::vector<const V *> &b,
+           const std::vector<V *> &x, double tol, int max_cycles, int *iters, int *matvecs, double *relres,
+           int *status, bool zero_x0) {
+    const size_t nr = K.size();
+    if (!nr) return;
+    Ctx &c = K[0]->c;
+    const int64_t n = K[0]->n;
+    const int m = K[0]->m;
     const unsigned nb = nblocks(n, RBS);
-    double bnorm = K.norm(b);
-    if (bnorm == 0.0) {
-        zero_fill(c, x, sizeof(V) * n);
-        *relres = 0.0;
-        return BEM_OK;
+    // A x_r for the right-hand sides in `set`, through the staging buffers
+    auto apply_set = [&](const std::vector<size_t> &set, const std::vector<const V *> &in,
+                         const std::vector<V *> &out) {
+        for (size_t i = 0; i < set.size(); i++)
+            BEM_HIP(hipMemcpyAsync(stage_in + (int64_t)i * n, in[i], sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
+        apply(stage_in, stage_out, (int)set.size());
+        for (size_t i = 0; i < set.size(); i++) {
+            BEM_HIP(hipMemcpyAsync(out[i], stage_out + (int64_t)i * n, sizeof(V) * n, hipMemcpyDeviceToDevice,
+                                   c.stream));
+            matvecs[set[i]]++;
+        }
+    };
+    std::vector<double> bnorm;
+    {
+        std::vector<Krylov<V> *> Ks(K.begin(), K.end());
+        bnorm = norms(Ks, std::vector<const V *>(b.begin(), b.end()));
     }
-    for (int cycle = 0; cycle < max_cycles; cycle++) {
-        // r = b - A x, into V0
-        if (zero_x0 && cycle == 0) {
-            BEM_HIP(hipMemcpyAsync(K.vec(0), b, sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
+    std::vector<size_t> act;  // right-hand sides still iterating
+    for (size_t r = 0; r < nr; r++) {
+        status[r] = BEM_ENOCONV;
+        if (bnorm[r] == 0.0) {
+            zero_fill(c, x[r], sizeof(V) * n);
+            relres[r] = 0.0;
+            status[r] = BEM_OK;
         } else {
-            apply(x, K.tmp.p);
-            (*matvecs)++;
-            k_sub<V><<<nb, RBS, 0, c.stream>>>(b, K.tmp.p, K.vec(0), n);
-            BEM_LAUNCH_CHECK();
+            act.push_back(r);
         }
-        double beta = K.norm(K.vec(0));
-        *relres = beta / bnorm;
-        if (beta / bnorm <= tol) return BEM_OK;
-        {
-            double inv = 1.0 / beta;
-            zero_fill(c, K.tmp.p, sizeof(V) * n);
-            k_axpy<V><<<nb, RBS, 0, c.stream>>>(V(0.0), K.vec(0), K.tmp.p, n, inv);
-            BEM_LAUNCH_CHECK();
-            BEM_HIP(hipMemcpyAsync(K.vec(0), K.tmp.p, sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
-        }
-        std::vector<V> g0(m + 1, V(0.0));
-        g0[0] = V(beta);
-        K.g.upload(g0.data(), m + 1);
-        int jdone = 0;
-        bool converged = false;
-        for (int j = 0; j < m; j++) {
-            apply(K.vec(j), K.w.p);
-            (*matvecs)++;
-            double wnorm = K.norm(K.w.p);
-            // CGS2
-            K.dots(K.basis.p, j + 1, K.w.p, K.hcol.p, false);
-            k_subtract<V><<<nb, RBS, 0, c.stream>>>(K.basis.p, n, K.hcol.p, j + 1, K.w.p, n);
-            BEM_LAUNCH_CHECK();
-            K.dots(K.basis.p, j + 1, K.w.p, K.hc2.p, false);
-            k_subtract<V><<<nb, RBS, 0, c.stream>>>(K.basis.p, n, K.hc2.p, j + 1, K.w.p, n);
-            BEM_LAUNCH_CHECK();
-            k_add<V><<<1, 64, 0, c.stream>>>(K.hcol.p, K.hc2.p, j + 1);  // h = h1 + h2
-            BEM_LAUNCH_CHECK();
-            double hn = K.norm(K.w.p);  // leaves |w|^2 in est[1]
-            k_set_real<V><<<1, 1, 0, c.stream>>>(K.hcol.p, j + 1, K.est.p + 1);
-            BEM_LAUNCH_CHECK();
-            bool breakdown = hn <= 1e-14 * wnorm;
-            if (!breakdown) {
-                k_scale_into<V><<<nb, RBS, 0, c.stream>>>(K.w.p, K.hcol.p, j, K.vec(j + 1), n);
+    }
+    for (int cycle = 0; cycle < max_cycles && !act.empty(); cycle++) {
+        // r0 = b - A x into V0
+        if (zero_x0 && cycle == 0) {
+            for (size_t r : act)
+                BEM_HIP(hipMemcpyAsync(K[r]->vec(0), b[r], sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
+        } else {
+            std::vector<const V *> in;
+            std::vector<V *> out;
+            for (size_t r : act) {
+                in.push_back(x[r]);
+                out.push_back(K[r]->tmp.p);
+            }
+            apply_set(act, in, out);
+            for (size_t r : act) {
+                k_sub<V><<<nb, RBS, 0, c.stream>>>(b[r], K[r]->tmp.p, K[r]->vec(0), n);
                 BEM_LAUNCH_CHECK();
             }
-            k_givens<V><<<1, 1, 0, c.stream>>>(K.H.p, m, K.hcol.p, K.cs.p, K.sn.p, K.g.p, j, K.est.p);
-            BEM_LAUNCH_CHECK();
-            BEM_HIP(hipMemcpyAsync(K.h_est, K.est.p, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-            c.sync();
-            (*iters)++;
-            jdone = j + 1;
-            *relres = *K.h_est / bnorm;
-            if (*relres <= tol || breakdown) {
-                converged = true;
-                break;
+        }
+        std::vector<Krylov<V> *> Ka;
+        std::vector<const V *> v0;
+        for (size_t r : act) {
+            Ka.push_back(K[r]);
+            v0.push_back(K[r]->vec(0));
+        }
+        const std::vector<double> beta = norms(Ka, v0);
+        std::vector<size_t> run;  // right-hand sides running this cycle's Arnoldi process
+        std::vector<double> beta_run;
+        for (size_t i = 0; i < act.size(); i++) {
+            const size_t r = act[i];
+            relres[r] = beta[i] / bnorm[r];
+            if (relres[r] <= tol) status[r] = BEM_OK;
+            else {
+                run.push_back(r);
+                beta_run.push_back(beta[i]);
             }
         }
-        k_backsolve<V><<<1, 1, 0, c.stream>>>(K.H.p, m, K.g.p, jdone, K.y.p);
-        BEM_LAUNCH_CHECK();
-        k_lincomb<V><<<nb, RBS, 0, c.stream>>>(K.basis.p, n, K.y.p, jdone, x, n);
-        BEM_LAUNCH_CHECK();
-        (void)converged;
+        act = run;
+        for (size_t i = 0; i < run.size(); i++) {
+            Krylov<V> &Kr = *K[run[i]];
+            const double inv = 1.0 / beta_run[i];
+            zero_fill(c, Kr.tmp.p, sizeof(V) * n);
+            k_axpy<V><<<nb, RBS, 0, c.stream>>>(V(0.0), Kr.vec(0), Kr.tmp.p, n, inv);
+            BEM_LAUNCH_CHECK();
+            BEM_HIP(hipMemcpyAsync(Kr.vec(0), Kr.tmp.p, sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
+            std::vector<V> g0(m + 1, V(0.0));
+            g0[0] = V(beta_run[i]);
+            Kr.g.upload(g0.data(), m + 1);
+        }
+        std::vector<int> jdone(nr, 0);
+        std::vector<size_t> live = run;  // still in this cycle's Arnoldi process
+        for (int j = 0; j < m && !live.empty(); j++) {
+            {
+                std::vector<const V *> in;
+                std::vector<V *> out;
+                for (size_t r : live) {
+                    in.push_back(K[r]->vec(j));
+                    out.push_back(K[r]->w.p);
+                }
+                apply_set(live, in, out);
+            }
+            std::vector<Krylov<V> *> Kl;
+            std::vector<const V *> wl;
+            for (size_t r : live) {
+                Kl.push_back(K[r]);
+                wl.push_back(K[r]->w.p);
+            }
+            const std::vector<double> wnorm = norms(Kl, wl);
+            // CGS2
+            for (size_t r : live) {
+                Krylov<V> &Kr = *K[r];
+                Kr.dots(Kr.basis.p, j + 1, Kr.w.p, Kr.hcol.p, false);
+                k_subtract<V><<<nb, RBS, 0, c.stream>>>(Kr.basis.p, n, Kr.hcol.p, j + 1, Kr.w.p, n);
+                BEM_LAUNCH_CHECK();
+                Kr.dots(Kr.basis.p, j + 1, Kr.w.p, Kr.hc2.p, false);
+                k_subtract<V><<<nb, RBS, 0, c.stream>>>(Kr.basis.p, n, Kr.hc2.p, j + 1, Kr.w.p, n);
+                BEM_LAUNCH_CHECK();
+                k_add<V><<<1, 64, 0, c.stream>>>(Kr.hcol.p, Kr.hc2.p, j + 1);  // h = h1 + h2
+                BEM_LAUNCH_CHECK();
+            }
+            const std::vector<double> hn = norms(Kl, wl);  // leaves |w|^2 in est[1]
+            for (size_t i = 0; i < live.size(); i++) {
+                Krylov<V> &Kr = *K[live[i]];
+                k_set_real<V><<<1, 1, 0, c.stream>>>(Kr.hcol.p, j + 1, Kr.est.p + 1);
+                BEM_LAUNCH_CHECK();
+                if (!(hn[i] <= 1e-14 * wnorm[i])) {
+                    k_scale_into<V><<<nb, RBS, 0, c.stream>>>(Kr.w.p, Kr.hcol.p, j, Kr.vec(j + 1), n);
+                    BEM_LAUNCH_CHECK();
+                }
+                k_givens<V><<<1, 1, 0, c.stream>>>(Kr.H.p, m, Kr.hcol.p, Kr.cs.p, Kr.sn.p, Kr.g.p, j, Kr.est.p);
+                BEM_LAUNCH_CHECK();
+                BEM_HIP(hipMemcpyAsync(Kr.h_est, Kr.est.p, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            }
+            c.sync();
+            std::vector<size_t> next;
+            for (size_t i = 0; i < live.size(); i++) {
+                const size_t r = live[i];
+                iters[r]++;
+                jdone[r] = j + 1;
+                relres[r] = K[r]->h_est[0] / bnorm[r];
+                const bool breakdown = hn[i] <= 1e-14 * wnorm[i];
+                if (!(relres[r] <= tol || breakdown)) next.push_back(r);
+            }
+            live = next;
+        }
+        for (size_t r : run) {
+            Krylov<V> &Kr = *K[r];
+            k_backsolve<V><<<1, 1, 0, c.stream>>>(Kr.H.p, m, Kr.g.p, jdone[r], Kr.y.p);
+            BEM_LAUNCH_CHECK();
+            k_lincomb<V><<<nb, RBS, 0, c.stream>>>(Kr.basis.p, n, Kr.y.p, jdone[r], x[r], n);
+            BEM_LAUNCH_CHECK();
+        }
     }
-    // final explicit residual
-    apply(x, K.tmp.p);
-    (*matvecs)++;
-    k_sub<V><<<nb, RBS, 0, c.stream>>>(b, K.tmp.p, K.w.p, n);
-    BEM_LAUNCH_CHECK();
-    *relres = K.norm(K.w.p) / bnorm;
-    return *relres <= tol ? BEM_OK : BEM_ENOCONV;
+    // final explicit residual of those that did not stop at a cycle start
+    if (!act.empty()) {
+        std::vector<const V *> in;
+        std::vector<V *> out;
+        for (size_t r : act) {
+            in.push_back(x[r]);
+            out.push_back(K[r]->tmp.p);
+        }
+        apply_set(act, in, out);
+        std::vector<Krylov<V> *> Ka;
+        std::vector<const V *> wa;
+        for (size_t r : act) {
+            k_sub<V><<<nb, RBS, 0, c.stream>>>(b[r], K[r]->tmp.p, K[r]->w.p, n);
+            BEM_LAUNCH_CHECK();
+            Ka.push_back(K[r]);
+            wa.push_back(K[r]->w.p);
+        }
+        const std::vector<double> rn = norms(Ka, wa);
+        for (size_t i = 0; i < act.size(); i++) {
+            const size_t r = act[i];
+            relres[r] = rn[i] / bnorm[r];
+            status[r] = relres[r] <= tol ? BEM_OK : BEM_ENOCONV;
+        }
+    }
 }
 
 template <class V>
@@ -300,51 +413,110 @@ int solve_t(bem_tree &t, int green, double k, int nrhs, const V *chi, V *phi, co
     const int64_t n = t.mesh->n_dof;
     const int m = o.restart;
     const int method = o.method;
-    Krylov<V> K(c, n, m);
-    DBuf<V> b, r, d;
-    b.alloc(&c, n);
-    r.alloc(&c, n);
-    d.alloc(&c, n);
-    int status = BEM_OK;
-    for (int rhs = 0; rhs < nrhs; rhs++) {
-        bem_solve_info inf{};
-        const V *ch = chi + (int64_t)rhs * n;
-        V *x = phi + (int64_t)rhs * n;
-        matvec(t, green, k, BEM_OP_RHS, method, BEM_PREC_FP64, 1, ch, b.p);
-        inf.matvecs++;
-        auto A64 = [&](const V *in, V *out) { matvec(t, green, k, BEM_OP_A, method, BEM_PREC_FP64, 1, in, out); };
-        auto A32 = [&](const V *in, V *out) { matvec(t, green, k, BEM_OP_A, method, BEM_PREC_MIXED, 1, in, out); };
-        int st;
-        double res = 0.0;
-        if (o.precision == BEM_PREC_FP64 || method == BEM_DIRECT) {
-            zero_fill(c, x, sizeof(V) * n);
-            st = gmres(K, A64, b.p, x, o.tol, o.max_restarts, &inf.iterations, &inf.matvecs, &res, true);
-        } else {
-            zero_fill(c, x, sizeof(V) * n);
-            BEM_HIP(hipMemcpyAsync(r.p, b.p, sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
-            double bnorm = K.norm(b.p);
-            st = BEM_ENOCONV;
-            for (int it = 0; it < o.max_refine; it++) {
-                zero_fill(c, d.p, sizeof(V) * n);
-                double inner = 0.0;
-                gmres(K, A32, r.p, d.p, o.inner_tol, o.max_restarts, &inf.iterations, &inf.matvecs, &inner, true);
-                k_axpy<V><<<nblocks(n, RBS), RBS, 0, c.stream>>>(V(0.0), d.p, x, n, 1.0);
-                BEM_LAUNCH_CHECK();
-                A64(x, K.tmp.p);
-                inf.matvecs++;
-                k_sub<V><<<nblocks(n, RBS), RBS, 0, c.stream>>>(b.p, K.tmp.p, r.p, n);
-                BEM_LAUNCH_CHECK();
-                inf.refinements++;
-                res = bnorm > 0 ? K.norm(r.p) / bnorm : 0.0;
-                if (res <= o.tol) { st = BEM_OK; break; }
-            }
+    std::vector<std::unique_ptr<Krylov<V>>> Kown;
+    std::vector<Krylov<V> *> K;
+    for (int r = 0; r < nrhs; r++) {
+        Kown.push_back(std::make_unique<Krylov<V>>(c, n, m));
+        K.push_back(Kown.back().get());
+    }
+    DBuf<V> b, rr, d, sin, sout;
+    b.alloc(&c, (size_t)nrhs * n);
+    rr.alloc(&c, (size_t)nrhs * n);
+    d.alloc(&c, (size_t)nrhs * n);
+    sin.alloc(&c, (size_t)nrhs * n);
+    sout.alloc(&c, (size_t)nrhs * n);
+    std::vector<bem_solve_info> inf(nrhs);
+    for (auto &i : inf) i = bem_solve_info{};
+    std::vector<int> iters(nrhs, 0), mv(nrhs, 0), st(nrhs, BEM_ENOCONV);
+    std::vector<double> res(nrhs, 0.0);
+    // right-hand sides b = -S chi, all at once (columns equal single products)
+    matvec(t, green, k, BEM_OP_RHS, method, BEM_PREC_FP64, nrhs, chi, b.p);
+    for (auto &i : inf) i.matvecs++;
+    auto A64 = [&](const V *in, V *out, int cnt) {
+        matvec(t, green, k, BEM_OP_A, method, BEM_PREC_FP64, cnt, in, out);
+    };
+    auto A32 = [&](const V *in, V *out, int cnt) {
+        matvec(t, green, k, BEM_OP_A, method, BEM_PREC_MIXED, cnt, in, out);
+    };
+    auto col = [&](V *base, int r) { return base + (int64_t)r * n; };
+    std::vector<const V *> bv;
+    std::vector<V *> xv;
+    for (int r = 0; r < nrhs; r++) {
+        bv.push_back(col(b.p, r));
+        xv.push_back(col(phi, r));
+        zero_fill(c, xv[r], sizeof(V) * n);
+    }
+    if (o.precision == BEM_PREC_FP64 || method == BEM_DIRECT) {
+        gmres(K, A64, sin.p, sout.p, bv, xv, o.tol, o.max_restarts, iters.data(), mv.data(), res.data(), st.data(),
+              true);
+        for (int r = 0; r < nrhs; r++) {
+            inf[r].iterations += iters[r];
+            inf[r].matvecs += mv[r];
+            inf[r].residual = res[r];
+            inf[r].status = st[r];
         }
-        inf.residual = res;
-        inf.status = st;
-        if (st != BEM_OK) status = st;
-        if (info) info[rhs] = inf;
+    } else {
+        // outer FP64 refinement around GMRES on the mixed operator, in lock step
+        BEM_HIP(hipMemcpyAsync(rr.p, b.p, sizeof(V) * n * nrhs, hipMemcpyDeviceToDevice, c.stream));
+        const std::vector<double> bnorm = norms(K, std::vector<const V *>(bv.begin(), bv.end()));
+        std::vector<int> act;
+        for (int r = 0; r < nrhs; r++) {
+            inf[r].status = BEM_ENOCONV;
+            act.push_back(r);
+        }
+        for (int it = 0; it < o.max_refine && !act.empty(); it++) {
+            std::vector<Krylov<V> *> Ka;
+            std::vector<const V *> ra;
+            std::vector<V *> da;
+            for (int r : act) {
+                zero_fill(c, col(d.p, r), sizeof(V) * n);
+                Ka.push_back(K[r]);
+                ra.push_back(col(rr.p, r));
+                da.push_back(col(d.p, r));
+            }
+            std::vector<int> ii(act.size(), 0), mm(act.size(), 0), ss(act.size(), 0);
+            std::vector<double> inner(act.size(), 0.0);
+            gmres(Ka, A32, sin.p, sout.p, ra, da, o.inner_tol, o.max_restarts, ii.data(), mm.data(), inner.data(),
+                  ss.data(), true);
+            for (size_t i = 0; i < act.size(); i++) {
+                inf[act[i]].iterations += ii[i];
+                inf[act[i]].matvecs += mm[i];
+                k_axpy<V><<<nblocks(n, RBS), RBS, 0, c.stream>>>(V(0.0), da[i], xv[act[i]], n, 1.0);
+                BEM_LAUNCH_CHECK();
+            }
+            // r = b - A_64 x for the active right-hand sides, one product
+            for (size_t i = 0; i < act.size(); i++)
+                BEM_HIP(hipMemcpyAsync(sin.p + (int64_t)i * n, xv[act[i]], sizeof(V) * n, hipMemcpyDeviceToDevice,
+                                       c.stream));
+            A64(sin.p, sout.p, (int)act.size());
+            std::vector<const V *> rv;
+            for (size_t i = 0; i < act.size(); i++) {
+                const int r = act[i];
+                inf[r].matvecs++;
+                BEM_HIP(hipMemcpyAsync(K[r]->tmp.p, sout.p + (int64_t)i * n, sizeof(V) * n, hipMemcpyDeviceToDevice,
+                                       c.stream));
+                k_sub<V><<<nblocks(n, RBS), RBS, 0, c.stream>>>(bv[r], K[r]->tmp.p, col(rr.p, r), n);
+                BEM_LAUNCH_CHECK();
+                inf[r].refinements++;
+                rv.push_back(col(rr.p, r));
+            }
+            const std::vector<double> rn = norms(Ka, rv);
+            std::vector<int> next;
+            for (size_t i = 0; i < act.size(); i++) {
+                const int r = act[i];
+                inf[r].residual = bnorm[r] > 0 ? rn[i] / bnorm[r] : 0.0;
+                if (inf[r].residual <= o.tol) inf[r].status = BEM_OK;
+                else next.push_back(r);
+            }
+            act = next;
+        }
     }
     c.sync();
+    int status = BEM_OK;
+    for (int r = 0; r < nrhs; r++) {
+        if (inf[r].status != BEM_OK) status = inf[r].status;
+        if (info) info[r] = inf[r];
+    }
     return status;
 }
 

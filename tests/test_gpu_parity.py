@@ -290,6 +290,31 @@ def test_solve_point_source_sphere(prec):
     assert np.sqrt(np.mean((x - phi.real) ** 2)) < 1e-5
 
 
+@pytest.mark.parametrize("green, prec", [(0, 0), (0, 1), (1, 1)])
+def test_multi_rhs_solve_equals_single_solves(green, prec):
+    """Right-hand sides solved together run in lock step (shared products,
+    one host synchronisation per step) and must reproduce the single solves
+    bit for bit, iteration counts included."""
+    bem = _bem()
+    k = 2.0 if green else 0.0
+    m, ctx, mesh, tree, om, ot = setup("sphere320")
+    rng = np.random.default_rng(41)
+    chi = rng.standard_normal((3, om.n_dof))
+    if green:
+        chi = chi + 1j * rng.standard_normal((3, om.n_dof))
+    chi[1] *= 1e-3  # different scales converge at different steps
+    chid = to_dev(chi, bool(green))
+    phid = chid.clone()
+    infos = bem.bem_solve(ctx, tree, green, k, chid, phid, tol=1e-8, precision=prec)
+    together = phid.cpu().numpy()
+    for r in range(3):
+        c1 = chid[r:r + 1].clone()
+        p1 = c1.clone()
+        i1 = bem.bem_solve(ctx, tree, green, k, c1, p1, tol=1e-8, precision=prec)[0]
+        assert i1 == infos[r], (r, i1, infos[r])
+        assert np.array_equal(p1.cpu().numpy()[0], together[r]), r
+
+
 def test_solve_helmholtz_rigid_sphere():
     bem = _bem()
     ka = 2.0
