@@ -275,8 +275,9 @@ def _boundary_data(dofs, req):
 
 def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5):
     """Served, mixed-precision solves (bem_server_*: concurrent lanes, request
-    merging) against plain FP64 one-at-a-time solves on one context, on the
-    same seeded request stream; trees are cached per mesh on both sides.
+    merging, right-hand sides in lock step) against plain FP64 solves of one
+    right-hand side at a time on one context, on the same seeded request
+    stream; trees are cached per mesh on both sides.
     Throughput: all requests offered at once.  Latency: a second pass with
     Poisson arrivals at rate_frac times the measured request throughput
     (warm caches), submission to completion."""
@@ -337,9 +338,11 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5):
         cplx = r["green"] == 1
         chid = torch.tensor(c if cplx else c.real, dtype=torch.complex128 if cplx else torch.float64, device="cuda:0")
         phid = torch.empty_like(chid)
-        info = bem.bem_solve(ctx, trees[r["key"]][1], r["green"], r["k"], chid, phid, precision=bem.BEM_PREC_FP64)
+        for j in range(chid.shape[0]):  # one right-hand side at a time
+            info = bem.bem_solve(ctx, trees[r["key"]][1], r["green"], r["k"], chid[j:j + 1], phid[j:j + 1],
+                                 precision=bem.BEM_PREC_FP64)
+            nconv += sum(1 for i in info if i["status"] != 0)
         torch.cuda.synchronize()
-        nconv += sum(1 for i in info if i["status"] != 0)
         lat_base.append(time.perf_counter() - t1)
     dtb = time.perf_counter() - t0
     out["baseline_fp64_solves_per_s"] = total_rhs / dtb
