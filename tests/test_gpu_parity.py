@@ -194,10 +194,13 @@ def test_repeat_is_bitwise_identical():
 
 
 # ---------------------------------------------------------------- full-size workloads, sampled rows
-@pytest.mark.parametrize("name", ["sphere20480", "cube24300"])
-def test_full_size_fmm_sampled_rows(name):
+@pytest.mark.parametrize("name, B, theta", [("sphere20480", 32, THETA), ("cube24300", 32, THETA),
+                                           ("sphere20480", 48, 0.62)])
+def test_full_size_fmm_sampled_rows(name, B, theta):
+    """Full-size meshes, sampled rows against the oracle's direct product;
+    the last case is the leaf size and separation bench.py times."""
     bem = _bem()
-    m, ctx, mesh, tree, om, ot = setup(name)
+    m, ctx, mesh, tree, om, ot = setup(name, B=B, theta=theta)
     x = bem_inputs.random_vector(om.n_dof, 27)[0]
     xd = to_dev(x, False)
     yd = xd.clone()
