@@ -60,7 +60,7 @@ __global__ void k_strength(const XV *x, int64_t n_dof, const int32_t *se_dofs, c
 constexpr int P2P_BS = 256;
 constexpr int P2P_TILE = 256;
 constexpr int P2P_CH = 256;  // near-list entries per chunk
-constexpr int P2P_PER_CU = 3;  // near-field blocks per CU while the far field runs beside it
+constexpr int P2P_PER_CU = 4;  // near-field blocks per CU while the far field runs beside it
 
 // 1/sqrt(v) for v > 0 far from the denormal range (squared distances of
 // distinct points): the hardware estimate, which is within 1 ulp in single
