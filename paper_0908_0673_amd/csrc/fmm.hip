@@ -44,9 +44,12 @@ template <bool C, class R> using val_t = typename std::conditional<C, cx<R>, R>:
 // ---------------------------------------------------------------- strengths
 template <class V, class R, class XV>
 __global__ void k_strength(const XV *x, int64_t n_dof, const int32_t *se_dofs, const R *wj, int64_t n_q,
-                           const double *L7 /* [7][6] */, V *s) {
+                           const double *L7 /* [7][6] */, V *s, uint32_t *zero, int64_t n_zero) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int rhs = blockIdx.y;
+    // the same launch clears n_zero words (the expansions of the fast product)
+    if (zero && rhs == 0)
+        for (int64_t z = i; z < n_zero; z += (int64_t)gridDim.x * blockDim.x) zero[z] = 0u;
     if (i >= n_q) return;
     int64_t se = i / 7;
     int q = (int)(i % 7);
@@ -293,14 +296,19 @@ __global__ void __launch_bounds__(256) k_direct(const double *q, int64_t n_q, co
 }
 
 // ---------------------------------------------------------------- correction + combine (FP64)
-// y(DOF of sorted target t) = the operator's combination of the far field
-// (yacc), the near-field partial sums of t's item (1/4pi applied for
-// Laplace), the singular / near-singular corrections and, for A, the free
-// term.  Eight lanes per target share its correction pairs and meet by
-// shuffles.
-template <class XV, class AV, class VD, bool LAP>
+// y(DOF of sorted target t) = the operator's combination of the far field,
+// the near-field partial sums of t's item (1/4pi applied for Laplace), the
+// singular / near-singular corrections and, for A, the free term.  Eight
+// lanes per target share its correction pairs and meet by shuffles.  The far
+// field is either a finished value per target (yacc, direct product) or, for
+// the fast product, the local expansion evaluated at the target (Section 3.2,
+// the stored monomials U of its leaf), folded in here: the lanes take every
+// eighth coefficient, in the expansion's precision, and the sum over lanes
+// runs in FP64.
+template <class XV, class AV, class R, class VD, bool LAP>
 __global__ void __launch_bounds__(256) k_combine(int64_t n_tgt, const int32_t *tperm, const AV *yacc,
-                                                 const int32_t *tgt_item, const int32_t *item_unit,
+                                                 const int32_t *tgt_leaf, const R *U, const AV *loc, int P,
+                                                 int64_t n_box, const int32_t *tgt_item, const int32_t *item_unit,
                                                  const int32_t *wi_t0, const VD *part, int64_t n_unit,
                                                  const int64_t *row_ptr, const int32_t *pair_elem,
                                                  const int32_t *se_dofs, const XV *corr, const double *cfree,
@@ -310,6 +318,15 @@ __global__ void __launch_bounds__(256) k_combine(int64_t n_tgt, const int32_t *t
     const bool ok = t < n_tgt;
     const XV *xr = x + (int64_t)rhs * n_tgt;
     XV acc = XV(0.0);
+    if (ok && loc) {
+        const int4 m = *(const int4 *)(tgt_leaf + 4 * t);  // leaf, first target, target count
+        const R *Ut = U + (int64_t)m.y * P + (t - m.y);
+        const AV *F = loc + ((int64_t)rhs * n_box + m.x) * P;
+        AV a = AV(0.0);
+#pragma unroll 4
+        for (int i = l8; i < P; i += 8) a += F[i] * Ut[(int64_t)i * m.z];
+        acc = vcast<XV>(a);
+    }
     if (ok) {
         for (int64_t p = row_ptr[t] + l8; p < row_ptr[t + 1]; p += 8) {
             const int32_t *dof = se_dofs + 6 * (int64_t)pair_elem[p];
@@ -324,7 +341,7 @@ __global__ void __launch_bounds__(256) k_combine(int64_t n_tgt, const int32_t *t
             if (LAP) v = v * kInv4Pi;
             acc += vcast<XV>(v);
         }
-        if (l8 == 0) acc += vcast<XV>(yacc[(int64_t)rhs * n_tgt + t]);
+        if (yacc && l8 == 0) acc += vcast<XV>(yacc[(int64_t)rhs * n_tgt + t]);
     }
 #pragma unroll
     for (int o = 1; o < 8; o <<= 1) {
@@ -462,6 +479,16 @@ void plan_fmm(bem_tree &t) {
     t.n_leaf_src = (int64_t)src_leaves.size();
     t.tleaf_ids = upload_i32(c, tgt_leaves);
     t.n_leaf_tgt = (int64_t)tgt_leaves.size();
+    {
+        std::vector<int32_t> tl(4 * std::max<int64_t>(1, t.n_tgt), 0);
+        for (int32_t b : tgt_leaves)
+            for (int64_t i = t.h_tb[b]; i < t.h_te[b]; i++) {
+                tl[4 * i] = b;
+                tl[4 * i + 1] = (int32_t)t.h_tb[b];
+                tl[4 * i + 2] = (int32_t)(t.h_te[b] - t.h_tb[b]);
+            }
+        t.tgt_leaf = upload_i32(c, tl);
+    }
     t.m2l_boxes = upload_i32(c, m2l);
     t.n_m2l_boxes = (int64_t)m2l.size();
     t.p2p_box = upload_i32(c, wb);
@@ -590,7 +617,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
     const R *tg = std::is_same<R, float>::value ? (const R *)t.t32.p : (const R *)t.t64.p;
     // work buffers
     t.work.strength.ensure(&c, sizeof(V) * nq * nrhs);
-    t.work.yacc.ensure(&c, sizeof(V) * nt * nrhs);
+    if (method == BEM_DIRECT) t.work.yacc.ensure(&c, sizeof(V) * nt * nrhs);
     V *s = (V *)t.work.strength.p;
     V *yacc = (V *)t.work.yacc.p;
     if (!t.L7.p) {
@@ -612,9 +639,19 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         build_pass_tables(t);
         m2l_prepare<V, R>(t, *pl);
     }
+    // moments and locals of the fast product in one buffer, cleared by the strength launch
+    V *mom = nullptr, *loc = nullptr;
+    size_t nexp = 0;
+    if (method == BEM_FMM) {
+        nexp = (size_t)t.n_box * t.tables->P * nrhs;
+        t.work.mom.ensure(&c, 2 * sizeof(V) * nexp);
+        mom = (V *)t.work.mom.p;
+        loc = mom + nexp;
+    }
     c.mark(9);
     dim3 gs(nblocks(nq, 256), nrhs);
-    k_strength<V, R, XV><<<gs, 256, 0, c.stream>>>(x, nt, t.se_dofs.p, q + 3 * nq, nq, t.L7.p, s);
+    k_strength<V, R, XV><<<gs, 256, 0, c.stream>>>(x, nt, t.se_dofs.p, q + 3 * nq, nq, t.L7.p, s, (uint32_t *)mom,
+                                                   (int64_t)(2 * sizeof(V) * nexp / 4));
     BEM_LAUNCH_CHECK();
     c.mark(0);
 
@@ -629,12 +666,6 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
             fail(BEM_EUNSUPPORTED, "the direct product runs in FP64 only");
         }
     } else {
-        FmmTables &T = *t.tables;
-        const int P = T.P;
-        const size_t nexp = (size_t)t.n_box * P * nrhs;
-        // moments and locals in one buffer, cleared by one fill
-        t.work.mom.ensure(&c, 2 * sizeof(V) * nexp);
-        V *mom = (V *)t.work.mom.p, *loc = mom + nexp;
         using PD = typename std::conditional<HELM, cx<double>, double>::type;
         PD *part = nullptr;
         if (t.n_p2p_items) {
@@ -678,7 +709,6 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         // one stream.
         const bool overlap = t.n_p2p_items && c.timing != 1;
         // upward pass (boxes without elements keep zero moments)
-        zero_fill(c, mom, 2 * sizeof(V) * nexp);
         p2m_apply<V, R, XV>(t, dbl, nrhs, x, mom);
         c.mark(1);
         m2m_apply<V, R>(t, nrhs, mom);
@@ -694,8 +724,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         // downward pass
         l2l_apply<V, R>(t, nrhs, loc);
         c.mark(4);
-        l2p_apply<V, R>(t, nrhs, loc, yacc);
-        c.mark(5);
+        c.mark(5);  // the local expansions are evaluated at the targets in the combination
         if (t.n_p2p_items) {
             if (overlap) c.join();
             else near_field(c.stream);
@@ -707,8 +736,12 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
     const XV *corr = (const XV *)(dbl ? cr.K.p : cr.S.p);
     const VD *part = method == BEM_FMM && t.n_p2p_items ? (const VD *)t.work.p2p_part.p : nullptr;
     dim3 g(nblocks(8 * nt, 256), nrhs);
-    k_combine<XV, V, VD, !HELM><<<g, 256, 0, c.stream>>>(
-        nt, t.tperm.p, yacc, t.p2p_tgt_item.p, t.p2p_item_unit.p, t.p2p_t0.p, part, t.n_p2p_units, t.pair_ptr.p,
+    const bool fmm = method == BEM_FMM;
+    const R *U = nullptr;
+    if (fmm) U = std::is_same<R, float>::value ? (const R *)t.pass.U32.p : (const R *)t.pass.U64.p;
+    k_combine<XV, V, R, VD, !HELM><<<g, 256, 0, c.stream>>>(
+        nt, t.tperm.p, fmm ? nullptr : yacc, t.tgt_leaf.p, U, fmm ? loc : nullptr, fmm ? t.tables->P : 0, t.n_box,
+        t.p2p_tgt_item.p, t.p2p_item_unit.p, t.p2p_t0.p, part, t.n_p2p_units, t.pair_ptr.p,
         t.pair_elem.p, t.se_dofs.p, corr, op == BEM_OP_A ? t.free_term.p : nullptr, x, op, y);
     BEM_LAUNCH_CHECK();
     c.mark(7);

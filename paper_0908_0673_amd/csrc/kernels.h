@@ -153,6 +153,7 @@ struct bem_tree {
     int64_t n_leaf_src = 0;
     bem::DBuf<int32_t> tleaf_ids;      // leaf boxes with targets (L2P)
     int64_t n_leaf_tgt = 0;
+    bem::DBuf<int32_t> tgt_leaf;       // [n_tgt][4]: leaf box, its first target, its target count, 0
     bem::DBuf<int32_t> m2l_boxes;      // boxes with a non-empty interaction list and targets below
     int64_t n_m2l_boxes = 0;
     std::vector<std::vector<int32_t>> m2m_level_boxes;  // non-leaf boxes per level
