@@ -29,74 +29,93 @@ __device__ inline cx<double> cj(cx<double> v) { return conj(v); }
 __device__ inline double abs2(double v) { return v * v; }
 __device__ inline double abs2(cx<double> v) { return v.re * v.re + v.im * v.im; }
 
-// partial[i][blk] = sum over the block's chunk of conj(Vi) w
+constexpr int DOT_BLK = 64;  // blocks of a reduction over a vector
+
+// Partial sums cross blocks (and the XCDs' separate L2 caches) through
+// device-scope atomic stores and loads.
+__device__ inline void st_dev(double *p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline double ld_dev(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_dev(cx<double> *p, cx<double> v) {
+    st_dev(&p->re, v.re);
+    st_dev(&p->im, v.im);
+}
+__device__ inline cx<double> ld_dev(const cx<double> *p) { return cx<double>(ld_dev(&p->re), ld_dev(&p->im)); }
+
+// Sum over the block's threads by a fixed tree; the result is returned to
+// every thread.
 template <class V>
-__global__ void k_dots(const V *basis, int64_t ld, const V *w, int64_t n, V *partial, int nblk) {
-    __shared__ V red[RBS];
-    const int i = blockIdx.y;
-    const V *vi = basis + (int64_t)i * ld;
-    V acc = V(0.0);
-    for (int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x; e < n; e += (int64_t)nblk * RBS)
-        acc += cj(vi[e]) * w[e];
-    red[threadIdx.x] = acc;
+__device__ V block_sum(V v, V *red) {
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int o = RBS / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[(int64_t)i * nblk + blockIdx.x] = red[0];
+    const V s = red[0];
+    __syncthreads();
+    return s;
 }
 
-// out[i] (+)= sum of partial[i][:] in order
+// Row `row` of a reduction has gridDim.x blocks, each of which has stored its
+// partial sum at part[row * gridDim.x + blockIdx.x].  Returns, in every
+// thread, the row's total (partial sums added in block order, so the result
+// does not depend on which block finishes last) to the block that finishes
+// the row last, and false to the others.  The row's counter is left at zero.
 template <class V>
-__global__ void k_dots_finish(const V *partial, int nblk, int m, V *out, int accumulate) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    V acc = V(0.0);
-    for (int b = 0; b < nblk; b++) acc += partial[(int64_t)i * nblk + b];
-    if (accumulate) out[i] += acc;
-    else out[i] = acc;
+__device__ bool row_total(V *part, unsigned *count, int row, V *red, V *total) {
+    __shared__ int last;
+    const int nblk = gridDim.x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(count + row, 1u) == (unsigned)nblk - 1;
+        if (last) {
+            atomicExch(count + row, 0u);
+            __threadfence();
+        }
+    }
+    __syncthreads();
+    if (!last) return false;
+    if ((int)threadIdx.x < nblk) red[threadIdx.x] = ld_dev(part + (int64_t)row * nblk + threadIdx.x);
+    __syncthreads();
+    V t = V(0.0);
+    for (int b = 0; b < nblk; b++) t += red[b];
+    *total = t;
+    return true;
 }
 
-// w -= sum_{i < m} h[i] Vi
+// Grid (nblk, rows + 1): row r < rows reduces conj(V_r) . w (V_r at basis +
+// r ld), row `rows` reduces conj(w) . w.  Totals go to out[r] (the last row
+// to out[rows]); with acc, acc[r] += total as well for r < rows; with
+// host_self, the real part of the last row's total also goes to that
+// host-mapped word.
 template <class V>
-__global__ void k_subtract(const V *basis, int64_t ld, const V *h, int m, V *w, int64_t n) {
-    int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
-    if (e >= n) return;
-    V acc = w[e];
-    for (int i = 0; i < m; i++) acc -= h[i] * basis[(int64_t)i * ld + e];
-    w[e] = acc;
+__global__ void __launch_bounds__(RBS) k_rows(const V *basis, int64_t ld, const V *w, int64_t n, int rows, V *part,
+                                              unsigned *count, V *out, V *acc, double *host_self) {
+    __shared__ V red[RBS];
+    const int r = blockIdx.y, nblk = gridDim.x;
+    const V *v = r < rows ? basis + (int64_t)r * ld : w;
+    V s = V(0.0);
+    for (int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x; e < n; e += (int64_t)nblk * RBS) s += cj(v[e]) * w[e];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) st_dev(part + (int64_t)r * nblk + blockIdx.x, s);
+    V t;
+    if (!row_total(part, count, r, red, &t)) return;
+    if (threadIdx.x == 0) {
+        out[r] = t;
+        if (r < rows && acc) acc[r] += t;
+        if (r == rows && host_self) *host_self = re_part(t);
+    }
 }
 
+// Givens update of the Hessenberg least-squares problem at step j: hcol
+// holds column j (j + 2 entries, hcol[j+1] = |w| real).  Applies the
+// previous rotations, forms the new one, stores the rotated column into H,
+// updates g and returns |g[j+1]|, the residual estimate.
 template <class V>
-__global__ void k_scale_into(const V *w, const V *hcol, int j, V *out, int64_t n) {
-    int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
-    if (e >= n) return;
-    double inv = 1.0 / re_part(hcol[j + 1]);
-    out[e] = w[e] * inv;
-}
-
-template <class V>
-__global__ void k_axpy(V a_dummy, const V *x, V *y, int64_t n, double alpha) {
-    int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
-    if (e < n) y[e] += x[e] * alpha;
-}
-
-template <class V>
-__global__ void k_lincomb(const V *basis, int64_t ld, const V *yv, int m, V *x, int64_t n) {
-    int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
-    if (e >= n) return;
-    V acc = x[e];
-    for (int i = 0; i < m; i++) acc += yv[i] * basis[(int64_t)i * ld + e];
-    x[e] = acc;
-}
-
-// hcol holds column j of the Hessenberg matrix (j + 2 entries) with
-// hcol[j+1] = |w| real.  Applies the previous rotations, forms the new one,
-// stores the rotated column into H and updates g.  est[0] = |g[j+1]|.
-template <class V>
-__global__ void k_givens(V *H, int ldh, const V *hcol, V *cs, V *sn, V *g, int j, double *est) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ double givens_step(V *H, int ldh, const V *hcol, V *cs, V *sn, V *g, int j) {
     V col[96];
     for (int i = 0; i <= j + 1; i++) col[i] = hcol[i];
     for (int i = 0; i < j; i++) {
@@ -122,7 +141,77 @@ __global__ void k_givens(V *H, int ldh, const V *hcol, V *cs, V *sn, V *g, int j
     V gj = g[j];
     g[j + 1] = -(cj(s) * gj);
     g[j] = c * gj;
-    est[0] = sqrt(abs2(g[j + 1]));
+    return sqrt(abs2(g[j + 1]));
+}
+
+// Second half of Arnoldi step j (after the first Gram-Schmidt pass and the
+// second pass's coefficients h2 = hc2[0..j]): w -= sum_{i <= j} h2[i] V_i,
+// then |w|^2 reduced over the grid.  The block that completes the sum ends
+// the step: hcol[j+1] = |w|, the breakdown test (|w| <= 1e-14 |w before the
+// orthogonalisation|, from wn2), the Givens update, and for the host (the
+// host-mapped words hout[0] = residual estimate, hout[1] = breakdown) and the
+// device (*flag = breakdown).
+template <class V>
+__global__ void __launch_bounds__(RBS) k_arnoldi_end(const V *basis, int64_t ld, const V *h2, V *w, int64_t n,
+                                                     V *part, unsigned *count, V *hcol, const V *wn2, V *H, int ldh,
+                                                     V *cs, V *sn, V *g, int j, int *flag, double *hout) {
+    __shared__ V red[RBS];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x; e < n; e += (int64_t)gridDim.x * RBS) {
+        V acc = w[e];
+        for (int i = 0; i <= j; i++) acc -= h2[i] * basis[(int64_t)i * ld + e];
+        w[e] = acc;
+        s += abs2(acc);
+    }
+    V t;
+    {
+        const V bs = block_sum(V(s), red);
+        if (threadIdx.x == 0) st_dev(part + blockIdx.x, bs);
+    }
+    if (!row_total(part, count, 0, red, &t)) return;
+    if (threadIdx.x != 0) return;
+    const double hn = sqrt(re_part(t)), wn = sqrt(re_part(wn2[0]));
+    const int breakdown = hn <= 1e-14 * wn;
+    hcol[j + 1] = V(hn);
+    const double est = givens_step(H, ldh, hcol, cs, sn, g, j);
+    *flag = breakdown;
+    hout[0] = est;
+    hout[1] = breakdown;
+}
+
+// w -= sum_{i < m} h[i] Vi
+template <class V>
+__global__ void k_subtract(const V *basis, int64_t ld, const V *h, int m, V *w, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x; e < n; e += (int64_t)gridDim.x * RBS) {
+        V acc = w[e];
+        for (int i = 0; i < m; i++) acc -= h[i] * basis[(int64_t)i * ld + e];
+        w[e] = acc;
+    }
+}
+
+// V_{j+1} = w / hcol[j+1] unless step j broke down
+template <class V>
+__global__ void k_scale_into(const V *w, const V *hcol, int j, const int *flag, V *out, int64_t n) {
+    if (*flag) return;
+    int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
+    if (e >= n) return;
+    double inv = 1.0 / re_part(hcol[j + 1]);
+    out[e] = w[e] * inv;
+}
+
+template <class V>
+__global__ void k_axpy(V a_dummy, const V *x, V *y, int64_t n, double alpha) {
+    int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
+    if (e < n) y[e] += x[e] * alpha;
+}
+
+template <class V>
+__global__ void k_lincomb(const V *basis, int64_t ld, const V *yv, int m, V *x, int64_t n) {
+    int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
+    if (e >= n) return;
+    V acc = x[e];
+    for (int i = 0; i < m; i++) acc += yv[i] * basis[(int64_t)i * ld + e];
+    x[e] = acc;
 }
 
 // y = R^{-1} g for the leading m x m upper triangle of H
@@ -139,24 +228,9 @@ __global__ void k_backsolve(const V *H, int ldh, const V *g, int m, V *y) {
 }
 
 template <class V>
-__global__ void k_add(V *a, const V *b, int m) {
-    for (int i = threadIdx.x; i < m; i += blockDim.x) a[i] += b[i];
-}
-
-template <class V>
 __global__ void k_sub(const V *a, const V *b, V *out, int64_t n) {
     int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
     if (e < n) out[e] = a[e] - b[e];
-}
-
-template <class V>
-__global__ void k_set_real(V *h, int i, const double *v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) h[i] = V(sqrt(*v));
-}
-
-template <class V>
-__global__ void k_norm2_to(const V *hv, double *out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = re_part(hv[0]);
 }
 
 template <class V>
@@ -165,12 +239,15 @@ struct Krylov {
     int64_t n;
     int m;
     int nblk;
-    DBuf<V> basis, w, hcol, hc2, H, cs, sn, g, y, partial, tmp;
-    DBuf<double> est;  // [0] residual estimate, [1] scratch
-    double *h_est = nullptr;  // pinned host copies of est[0], est[1]
+    DBuf<V> basis, w, hcol, hc2, H, cs, sn, g, y, part, tmp;
+    DBuf<unsigned> count;  // completed blocks per reduction row, zero between launches
+    DBuf<int> flag;        // breakdown of the last Arnoldi step
+    // pinned, host-mapped words written by the kernels and read after a
+    // stream sync: [0] residual estimate, [1] breakdown, [2] |v|^2 of norm_async
+    double *h_out = nullptr, *d_out = nullptr;
 
     Krylov(Ctx &c_, int64_t n_, int m_) : c(c_), n(n_), m(m_) {
-        nblk = (int)std::min<int64_t>(256, nblocks(n, RBS));
+        nblk = (int)std::min<int64_t>(DOT_BLK, nblocks(n, RBS));
         basis.alloc(&c, (size_t)(m + 1) * n);
         w.alloc(&c, n);
         tmp.alloc(&c, n);
@@ -181,35 +258,28 @@ struct Krylov {
         sn.alloc(&c, m);
         g.alloc(&c, m + 1);
         y.alloc(&c, m);
-        partial.alloc(&c, (size_t)(m + 2) * nblk);
-        est.alloc(&c, 2);
-        BEM_HIP(hipHostMalloc((void **)&h_est, 2 * sizeof(double), hipHostMallocDefault));
+        part.alloc(&c, (size_t)(m + 2) * nblk);
+        count.alloc(&c, m + 2);
+        count.zero();
+        flag.alloc(&c, 1);
+        BEM_HIP(hipHostMalloc((void **)&h_out, 4 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+        BEM_HIP(hipHostGetDevicePointer((void **)&d_out, h_out, 0));
     }
     ~Krylov() {
-        if (h_est) (void)hipHostFree(h_est);
+        if (h_out) (void)hipHostFree(h_out);
     }
     V *vec(int i) { return basis.p + (int64_t)i * n; }
 
-    // out[0..cnt) (= or +=) conj(V_i) . v
-    void dots(const V *base, int cnt, const V *v, V *out, bool acc) {
-        dim3 g2(nblk, cnt);
-        k_dots<V><<<g2, RBS, 0, c.stream>>>(base, n, v, n, partial.p, nblk);
-        BEM_LAUNCH_CHECK();
-        k_dots_finish<V><<<nblocks(cnt, 64), 64, 0, c.stream>>>(partial.p, nblk, cnt, out, acc ? 1 : 0);
+    // out[i] = conj(V_i) . v for i < cnt (V_i at base + i n) and out[cnt] =
+    // |v|^2; with acc, acc[i] += out[i] for i < cnt; with host_self, |v|^2
+    // also goes to that host-mapped word.  One launch.
+    void rows(const V *base, int cnt, const V *v, V *out, V *acc, double *host_self) {
+        dim3 g2(nblk, cnt + 1);
+        k_rows<V><<<g2, RBS, 0, c.stream>>>(base, n, v, n, cnt, part.p, count.p, out, acc, host_self);
         BEM_LAUNCH_CHECK();
     }
-    // |v|^2 into est[1] and its host copy (read after a stream sync)
-    void norm_async(const V *v) {
-        dots(v, 1, v, hc2.p, false);
-        k_norm2_to<V><<<1, 1, 0, c.stream>>>(hc2.p, est.p + 1);
-        BEM_LAUNCH_CHECK();
-        BEM_HIP(hipMemcpyAsync(h_est + 1, est.p + 1, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    }
-    double norm(const V *v) {
-        norm_async(v);
-        c.sync();
-        return std::sqrt(h_est[1]);
-    }
+    // |v|^2 into h_out[2] (read after a stream sync)
+    void norm_async(const V *v) { rows(nullptr, 0, v, hc2.p, nullptr, d_out + 2); }
 };
 
 // |v_i| of each (K_i, v_i), with one stream sync for all of them.
@@ -218,7 +288,7 @@ std::vector<double> norms(std::vector<Krylov<V> *> &K, const std::vector<const V
     for (size_t i = 0; i < K.size(); i++) K[i]->norm_async(v[i]);
     if (!K.empty()) K[0]->c.sync();
     std::vector<double> out(K.size());
-    for (size_t i = 0; i < K.size(); i++) out[i] = std::sqrt(K[i]->h_est[1]);
+    for (size_t i = 0; i < K.size(); i++) out[i] = std::sqrt(K[i]->h_out[2]);
     return out;
 }
 
@@ -243,6 +313,11 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
     // A x_r for the right-hand sides in `set`, through the staging buffers
     auto apply_set = [&](const std::vector<size_t> &set, const std::vector<const V *> &in,
                          const std::vector<V *> &out) {
+        if (set.size() == 1) {  // a single product needs no staging
+            apply(in[0], out[0], 1);
+            matvecs[set[0]]++;
+            return;
+        }
         for (size_t i = 0; i < set.size(); i++)
             BEM_HIP(hipMemcpyAsync(stage_in + (int64_t)i * n, in[i], sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
         apply(stage_in, stage_out, (int)set.size());
@@ -328,37 +403,21 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
                 }
                 apply_set(live, in, out);
             }
-            std::vector<Krylov<V> *> Kl;
-            std::vector<const V *> wl;
-            for (size_t r : live) {
-                Kl.push_back(K[r]);
-                wl.push_back(K[r]->w.p);
-            }
-            const std::vector<double> wnorm = norms(Kl, wl);
-            // CGS2
+            // CGS2: h1 and |w|^2 in one launch, w -= V h1, h2 (added into h),
+            // then w -= V h2 with |w|, the breakdown test, the Givens update and
+            // the residual estimate in one launch, and V_{j+1} = w / |w|
             for (size_t r : live) {
                 Krylov<V> &Kr = *K[r];
-                Kr.dots(Kr.basis.p, j + 1, Kr.w.p, Kr.hcol.p, false);
+                Kr.rows(Kr.basis.p, j + 1, Kr.w.p, Kr.hcol.p, nullptr, nullptr);
                 k_subtract<V><<<nb, RBS, 0, c.stream>>>(Kr.basis.p, n, Kr.hcol.p, j + 1, Kr.w.p, n);
                 BEM_LAUNCH_CHECK();
-                Kr.dots(Kr.basis.p, j + 1, Kr.w.p, Kr.hc2.p, false);
-                k_subtract<V><<<nb, RBS, 0, c.stream>>>(Kr.basis.p, n, Kr.hc2.p, j + 1, Kr.w.p, n);
+                Kr.rows(Kr.basis.p, j + 1, Kr.w.p, Kr.hc2.p, Kr.hcol.p, nullptr);
+                k_arnoldi_end<V><<<Kr.nblk, RBS, 0, c.stream>>>(Kr.basis.p, n, Kr.hc2.p, Kr.w.p, n, Kr.part.p,
+                                                                 Kr.count.p, Kr.hcol.p, Kr.hcol.p + j + 1, Kr.H.p, m,
+                                                                 Kr.cs.p, Kr.sn.p, Kr.g.p, j, Kr.flag.p, Kr.d_out);
                 BEM_LAUNCH_CHECK();
-                k_add<V><<<1, 64, 0, c.stream>>>(Kr.hcol.p, Kr.hc2.p, j + 1);  // h = h1 + h2
+                k_scale_into<V><<<nb, RBS, 0, c.stream>>>(Kr.w.p, Kr.hcol.p, j, Kr.flag.p, Kr.vec(j + 1), n);
                 BEM_LAUNCH_CHECK();
-            }
-            const std::vector<double> hn = norms(Kl, wl);  // leaves |w|^2 in est[1]
-            for (size_t i = 0; i < live.size(); i++) {
-                Krylov<V> &Kr = *K[live[i]];
-                k_set_real<V><<<1, 1, 0, c.stream>>>(Kr.hcol.p, j + 1, Kr.est.p + 1);
-                BEM_LAUNCH_CHECK();
-                if (!(hn[i] <= 1e-14 * wnorm[i])) {
-                    k_scale_into<V><<<nb, RBS, 0, c.stream>>>(Kr.w.p, Kr.hcol.p, j, Kr.vec(j + 1), n);
-                    BEM_LAUNCH_CHECK();
-                }
-                k_givens<V><<<1, 1, 0, c.stream>>>(Kr.H.p, m, Kr.hcol.p, Kr.cs.p, Kr.sn.p, Kr.g.p, j, Kr.est.p);
-                BEM_LAUNCH_CHECK();
-                BEM_HIP(hipMemcpyAsync(Kr.h_est, Kr.est.p, sizeof(double), hipMemcpyDeviceToHost, c.stream));
             }
             c.sync();
             std::vector<size_t> next;
@@ -366,8 +425,8 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
                 const size_t r = live[i];
                 iters[r]++;
                 jdone[r] = j + 1;
-                relres[r] = K[r]->h_est[0] / bnorm[r];
-                const bool breakdown = hn[i] <= 1e-14 * wnorm[i];
+                relres[r] = K[r]->h_out[0] / bnorm[r];
+                const bool breakdown = K[r]->h_out[1] != 0.0;
                 if (!(relres[r] <= tol || breakdown)) next.push_back(r);
             }
             live = next;
@@ -485,16 +544,19 @@ int solve_t(bem_tree &t, int green, double k, int nrhs, const V *chi, V *phi, co
                 BEM_LAUNCH_CHECK();
             }
             // r = b - A_64 x for the active right-hand sides, one product
-            for (size_t i = 0; i < act.size(); i++)
+            const bool one = act.size() == 1;  // a single product needs no staging
+            for (size_t i = 0; i < act.size() && !one; i++)
                 BEM_HIP(hipMemcpyAsync(sin.p + (int64_t)i * n, xv[act[i]], sizeof(V) * n, hipMemcpyDeviceToDevice,
                                        c.stream));
-            A64(sin.p, sout.p, (int)act.size());
+            if (one) A64(xv[act[0]], K[act[0]]->tmp.p, 1);
+            else A64(sin.p, sout.p, (int)act.size());
             std::vector<const V *> rv;
             for (size_t i = 0; i < act.size(); i++) {
                 const int r = act[i];
                 inf[r].matvecs++;
-                BEM_HIP(hipMemcpyAsync(K[r]->tmp.p, sout.p + (int64_t)i * n, sizeof(V) * n, hipMemcpyDeviceToDevice,
-                                       c.stream));
+                if (!one)
+                    BEM_HIP(hipMemcpyAsync(K[r]->tmp.p, sout.p + (int64_t)i * n, sizeof(V) * n,
+                                           hipMemcpyDeviceToDevice, c.stream));
                 k_sub<V><<<nblocks(n, RBS), RBS, 0, c.stream>>>(bv[r], K[r]->tmp.p, col(rr.p, r), n);
                 BEM_LAUNCH_CHECK();
                 inf[r].refinements++;
