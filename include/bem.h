@@ -200,16 +200,20 @@ typedef struct {
     double tol;          /* relative residual |b - A x| / |b| to reach; 0 -> 1e-8 */
     int restart;         /* GMRES restart length; 0 -> 50 */
     int max_restarts;    /* cycles per inner solve; 0 -> 100 */
-    bem_precision precision; /* FP64: GMRES on the FP64 FMM operator.  MIXED: outer FP64
-                                residual refinement around GMRES on the mixed operator */
-    double inner_tol;    /* MIXED only: inner relative tolerance; 0 -> 1e-5 */
-    int max_refine;      /* MIXED only: outer refinement steps; 0 -> 10 */
+    bem_precision precision; /* FP64: GMRES on the FP64 FMM operator.  MIXED: the same
+                                GMRES, whose steps use the mixed product once the relative
+                                residual r satisfies inner_tol * r <= tol / 10 (relaxed
+                                inexact Krylov); every residual that decides convergence
+                                (each cycle start and the end) uses the FP64 product */
+    double inner_tol;    /* MIXED only: bound on the mixed product's relative deviation
+                            from the FP64 product; 0 -> 1e-6 */
+    int max_refine;      /* unused (0) */
     bem_method method;   /* operator used (BEM_FMM unless set) */
 } bem_solve_opts;
 
 typedef struct {
     int iterations;      /* total inner Krylov iterations */
-    int refinements;     /* outer refinement steps (MIXED) */
+    int refinements;     /* MIXED: GMRES cycles restarted from an FP64 residual above tol */
     int matvecs;         /* operator applications, FP64 and mixed */
     double residual;     /* final |b - A x| / |b| with the FP64 operator */
     int status;          /* BEM_OK or BEM_ENOCONV */

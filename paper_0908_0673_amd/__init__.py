@@ -345,7 +345,7 @@ def bem_matvec(ctx: Context, tree: Tree, green: int, k: float, op: int, method: 
 
 
 def bem_solve(ctx: Context, tree: Tree, green: int, k: float, chi, phi, tol=1e-8, restart=50, max_restarts=100,
-              precision=BEM_PREC_FP64, inner_tol=1e-5, max_refine=10, method=BEM_FMM, raise_on_noconv=False):
+              precision=BEM_PREC_FP64, inner_tol=0.0, max_refine=0, method=BEM_FMM, raise_on_noconv=False):
     """Solves c.phi - K phi = -S chi; returns a list of per-rhs info dicts."""
     nrhs = _check_vec(chi, tree.n_dof, green)
     if _check_vec(phi, tree.n_dof, green) != nrhs:
@@ -369,7 +369,7 @@ class Server:
     request is pending and wait is False."""
 
     def __init__(self, device=0, lanes=4, hbm_budget=32 << 30, max_batch_rhs=32, tol=1e-8, restart=50,
-                 max_restarts=100, precision=BEM_PREC_FP64, inner_tol=1e-5, max_refine=10, method=BEM_FMM,
+                 max_restarts=100, precision=BEM_PREC_FP64, inner_tol=0.0, max_refine=0, method=BEM_FMM,
                  B=32, order=8, theta=0.6, kappa=0.0, max_depth=21):
         self.L = load_library()
         import torch

@@ -278,8 +278,7 @@ int bem_solve(bem_ctx *ctx, const bem_tree *tc, bem_green g, double k, int nrhs,
         if (!(o.tol > 0.0)) o.tol = 1e-8;
         if (o.restart <= 0) o.restart = 50;
         if (o.max_restarts <= 0) o.max_restarts = 100;
-        if (!(o.inner_tol > 0.0)) o.inner_tol = 1e-5;
-        if (o.max_refine <= 0) o.max_refine = 10;
+        if (!(o.inner_tol > 0.0)) o.inner_tol = 1e-6;
         if (!opts) o.method = BEM_FMM;
         BEM_REQUIRE(o.restart <= 90, BEM_EINVAL, "restart must be <= 90");
         BEM_REQUIRE(o.method == BEM_FMM || o.method == BEM_DIRECT, BEM_EINVAL, "unknown method");

@@ -11,8 +11,10 @@
 //
 // Precision modes:
 //   FP64   GMRES on the FP64 operator to tol.
-//   MIXED  outer refinement in FP64: d = GMRES(A_mixed, r, inner_tol);
-//          x += d; r = b - A_64 x; until |r| / |b| <= tol.
+//   MIXED  the same GMRES, whose steps switch to the mixed-precision
+//          product once the residual is small enough for its error not to
+//          matter (relaxed inexact Krylov); the residual that decides
+//          convergence is always formed with the FP64 product.
 #include <cmath>
 #include <memory>
 
@@ -300,10 +302,20 @@ std::vector<double> norms(std::vector<Krylov<V> *> &K, const std::vector<const V
 // products bit for bit), and the host reads every residual estimate of a
 // step after one synchronisation.  x_r holds the initial guess (zero when
 // zero_x0) and receives the result.
+//
+// apply(in, out, cnt, prec) is the operator in precision prec.  Residuals at
+// the start of a cycle are always FP64 products.  Inside a cycle a step uses
+// the mixed product once the right-hand side's current relative residual is
+// at most mixed_below (never when negative): the relaxation of inexact
+// Krylov methods (Simoncini and Szyld 2003; Bouras and Fraysse 2005), where
+// a product error of relative size d at a step whose residual is r perturbs
+// the attained residual by about d r, so d r <= tol / 10 keeps the FP64
+// residual at the end within tol.  A cycle whose FP64 residual misses tol
+// restarts from there (counted in restarts[r]).
 template <class V, class F>
 void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, const std::vector<const V *> &b,
-           const std::vector<V *> &x, double tol, int max_cycles, int *iters, int *matvecs, double *relres,
-           int *status, bool zero_x0) {
+           const std::vector<V *> &x, double tol, int max_cycles, double mixed_below, int *iters, int *matvecs,
+           int *restarts, double *relres, int *status, bool zero_x0) {
     const size_t nr = K.size();
     if (!nr) return;
     Ctx &c = K[0]->c;
@@ -312,15 +324,16 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
     const unsigned nb = nblocks(n, RBS);
     // A x_r for the right-hand sides in `set`, through the staging buffers
     auto apply_set = [&](const std::vector<size_t> &set, const std::vector<const V *> &in,
-                         const std::vector<V *> &out) {
+                         const std::vector<V *> &out, int prec) {
+        if (set.empty()) return;
         if (set.size() == 1) {  // a single product needs no staging
-            apply(in[0], out[0], 1);
+            apply(in[0], out[0], 1, prec);
             matvecs[set[0]]++;
             return;
         }
         for (size_t i = 0; i < set.size(); i++)
             BEM_HIP(hipMemcpyAsync(stage_in + (int64_t)i * n, in[i], sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
-        apply(stage_in, stage_out, (int)set.size());
+        apply(stage_in, stage_out, (int)set.size(), prec);
         for (size_t i = 0; i < set.size(); i++) {
             BEM_HIP(hipMemcpyAsync(out[i], stage_out + (int64_t)i * n, sizeof(V) * n, hipMemcpyDeviceToDevice,
                                    c.stream));
@@ -355,7 +368,7 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
                 in.push_back(x[r]);
                 out.push_back(K[r]->tmp.p);
             }
-            apply_set(act, in, out);
+            apply_set(act, in, out, BEM_PREC_FP64);
             for (size_t r : act) {
                 k_sub<V><<<nb, RBS, 0, c.stream>>>(b[r], K[r]->tmp.p, K[r]->vec(0), n);
                 BEM_LAUNCH_CHECK();
@@ -375,6 +388,7 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
             relres[r] = beta[i] / bnorm[r];
             if (relres[r] <= tol) status[r] = BEM_OK;
             else {
+                if (cycle > 0) restarts[r]++;
                 run.push_back(r);
                 beta_run.push_back(beta[i]);
             }
@@ -394,14 +408,18 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
         std::vector<int> jdone(nr, 0);
         std::vector<size_t> live = run;  // still in this cycle's Arnoldi process
         for (int j = 0; j < m && !live.empty(); j++) {
-            {
+            for (int prec : {BEM_PREC_FP64, BEM_PREC_MIXED}) {
+                std::vector<size_t> set;
                 std::vector<const V *> in;
                 std::vector<V *> out;
                 for (size_t r : live) {
+                    const bool mixed = relres[r] <= mixed_below;
+                    if (mixed != (prec == BEM_PREC_MIXED)) continue;
+                    set.push_back(r);
                     in.push_back(K[r]->vec(j));
                     out.push_back(K[r]->w.p);
                 }
-                apply_set(live, in, out);
+                apply_set(set, in, out, prec);
             }
             // CGS2: h1 and |w|^2 in one launch, w -= V h1, h2 (added into h),
             // then w -= V h2 with |w|, the breakdown test, the Givens update and
@@ -447,7 +465,7 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
             in.push_back(x[r]);
             out.push_back(K[r]->tmp.p);
         }
-        apply_set(act, in, out);
+        apply_set(act, in, out, BEM_PREC_FP64);
         std::vector<Krylov<V> *> Ka;
         std::vector<const V *> wa;
         for (size_t r : act) {
@@ -478,24 +496,19 @@ int solve_t(bem_tree &t, int green, double k, int nrhs, const V *chi, V *phi, co
         Kown.push_back(std::make_unique<Krylov<V>>(c, n, m));
         K.push_back(Kown.back().get());
     }
-    DBuf<V> b, rr, d, sin, sout;
+    DBuf<V> b, sin, sout;
     b.alloc(&c, (size_t)nrhs * n);
-    rr.alloc(&c, (size_t)nrhs * n);
-    d.alloc(&c, (size_t)nrhs * n);
     sin.alloc(&c, (size_t)nrhs * n);
     sout.alloc(&c, (size_t)nrhs * n);
     std::vector<bem_solve_info> inf(nrhs);
     for (auto &i : inf) i = bem_solve_info{};
-    std::vector<int> iters(nrhs, 0), mv(nrhs, 0), st(nrhs, BEM_ENOCONV);
+    std::vector<int> iters(nrhs, 0), mv(nrhs, 0), rs(nrhs, 0), st(nrhs, BEM_ENOCONV);
     std::vector<double> res(nrhs, 0.0);
     // right-hand sides b = -S chi, all at once (columns equal single products)
     matvec(t, green, k, BEM_OP_RHS, method, BEM_PREC_FP64, nrhs, chi, b.p);
     for (auto &i : inf) i.matvecs++;
-    auto A64 = [&](const V *in, V *out, int cnt) {
-        matvec(t, green, k, BEM_OP_A, method, BEM_PREC_FP64, cnt, in, out);
-    };
-    auto A32 = [&](const V *in, V *out, int cnt) {
-        matvec(t, green, k, BEM_OP_A, method, BEM_PREC_MIXED, cnt, in, out);
+    auto A = [&](const V *in, V *out, int cnt, int prec) {
+        matvec(t, green, k, BEM_OP_A, method, prec, cnt, in, out);
     };
     auto col = [&](V *base, int r) { return base + (int64_t)r * n; };
     std::vector<const V *> bv;
@@ -505,73 +518,18 @@ int solve_t(bem_tree &t, int green, double k, int nrhs, const V *chi, V *phi, co
         xv.push_back(col(phi, r));
         zero_fill(c, xv[r], sizeof(V) * n);
     }
-    if (o.precision == BEM_PREC_FP64 || method == BEM_DIRECT) {
-        gmres(K, A64, sin.p, sout.p, bv, xv, o.tol, o.max_restarts, iters.data(), mv.data(), res.data(), st.data(),
-              true);
-        for (int r = 0; r < nrhs; r++) {
-            inf[r].iterations += iters[r];
-            inf[r].matvecs += mv[r];
-            inf[r].residual = res[r];
-            inf[r].status = st[r];
-        }
-    } else {
-        // outer FP64 refinement around GMRES on the mixed operator, in lock step
-        BEM_HIP(hipMemcpyAsync(rr.p, b.p, sizeof(V) * n * nrhs, hipMemcpyDeviceToDevice, c.stream));
-        const std::vector<double> bnorm = norms(K, std::vector<const V *>(bv.begin(), bv.end()));
-        std::vector<int> act;
-        for (int r = 0; r < nrhs; r++) {
-            inf[r].status = BEM_ENOCONV;
-            act.push_back(r);
-        }
-        for (int it = 0; it < o.max_refine && !act.empty(); it++) {
-            std::vector<Krylov<V> *> Ka;
-            std::vector<const V *> ra;
-            std::vector<V *> da;
-            for (int r : act) {
-                zero_fill(c, col(d.p, r), sizeof(V) * n);
-                Ka.push_back(K[r]);
-                ra.push_back(col(rr.p, r));
-                da.push_back(col(d.p, r));
-            }
-            std::vector<int> ii(act.size(), 0), mm(act.size(), 0), ss(act.size(), 0);
-            std::vector<double> inner(act.size(), 0.0);
-            gmres(Ka, A32, sin.p, sout.p, ra, da, o.inner_tol, o.max_restarts, ii.data(), mm.data(), inner.data(),
-                  ss.data(), true);
-            for (size_t i = 0; i < act.size(); i++) {
-                inf[act[i]].iterations += ii[i];
-                inf[act[i]].matvecs += mm[i];
-                k_axpy<V><<<nblocks(n, RBS), RBS, 0, c.stream>>>(V(0.0), da[i], xv[act[i]], n, 1.0);
-                BEM_LAUNCH_CHECK();
-            }
-            // r = b - A_64 x for the active right-hand sides, one product
-            const bool one = act.size() == 1;  // a single product needs no staging
-            for (size_t i = 0; i < act.size() && !one; i++)
-                BEM_HIP(hipMemcpyAsync(sin.p + (int64_t)i * n, xv[act[i]], sizeof(V) * n, hipMemcpyDeviceToDevice,
-                                       c.stream));
-            if (one) A64(xv[act[0]], K[act[0]]->tmp.p, 1);
-            else A64(sin.p, sout.p, (int)act.size());
-            std::vector<const V *> rv;
-            for (size_t i = 0; i < act.size(); i++) {
-                const int r = act[i];
-                inf[r].matvecs++;
-                if (!one)
-                    BEM_HIP(hipMemcpyAsync(K[r]->tmp.p, sout.p + (int64_t)i * n, sizeof(V) * n,
-                                           hipMemcpyDeviceToDevice, c.stream));
-                k_sub<V><<<nblocks(n, RBS), RBS, 0, c.stream>>>(bv[r], K[r]->tmp.p, col(rr.p, r), n);
-                BEM_LAUNCH_CHECK();
-                inf[r].refinements++;
-                rv.push_back(col(rr.p, r));
-            }
-            const std::vector<double> rn = norms(Ka, rv);
-            std::vector<int> next;
-            for (size_t i = 0; i < act.size(); i++) {
-                const int r = act[i];
-                inf[r].residual = bnorm[r] > 0 ? rn[i] / bnorm[r] : 0.0;
-                if (inf[r].residual <= o.tol) inf[r].status = BEM_OK;
-                else next.push_back(r);
-            }
-            act = next;
-        }
+    // MIXED: steps whose residual r satisfies inner_tol * r <= tol / 10 use the
+    // mixed product (inner_tol bounds its relative deviation from the FP64 one)
+    const bool mixed = o.precision == BEM_PREC_MIXED && method == BEM_FMM;
+    const double mixed_below = mixed ? 0.1 * o.tol / o.inner_tol : -1.0;
+    gmres(K, A, sin.p, sout.p, bv, xv, o.tol, o.max_restarts, mixed_below, iters.data(), mv.data(), rs.data(),
+          res.data(), st.data(), true);
+    for (int r = 0; r < nrhs; r++) {
+        inf[r].iterations += iters[r];
+        inf[r].matvecs += mv[r];
+        inf[r].refinements = mixed ? rs[r] : 0;
+        inf[r].residual = res[r];
+        inf[r].status = st[r];
     }
     c.sync();
     int status = BEM_OK;

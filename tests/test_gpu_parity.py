@@ -238,7 +238,7 @@ def test_full_size_helmholtz_geodesic_ka10_sampled_rows(kappa, tol):
 
 def test_solve_helmholtz_rigid_sphere_ka10():
     """C3: rigid unit sphere at ka = 10 (geodesic, 30420 elements, ~20 per
-    wavelength), plane wave along +z, mixed precision refined to 1e-8;
+    wavelength), plane wave along +z, mixed-precision GMRES to an FP64 residual of 1e-8;
     the total surface field against the series solution (measured 5.8e-6 rms,
     2.3e-5 max relative)."""
     bem = _bem()
@@ -259,7 +259,7 @@ def test_solve_helmholtz_rigid_sphere_ka10():
 @pytest.mark.parametrize("prec", [0, 1])
 def test_solve_point_source_cube24300(prec):
     """C2 cube: sharp edges and corners, 24300 elements (49686 DOFs), point
-    source inside; FP64 and mixed-with-refinement solves to 1e-8 against the
+    source inside; FP64 and mixed-precision solves to 1e-8 against the
     analytic surface potential (measured 4.6e-7 relative)."""
     bem = _bem()
     m, ctx, mesh, tree, om, ot = setup("cube24300")

@@ -15,7 +15,7 @@ from gpu_common import context, perturbed_sphere, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
-SOLVE = dict(tol=1e-8, restart=50, precision=1)  # mixed precision with FP64 refinement
+SOLVE = dict(tol=1e-8, restart=50, precision=1)  # mixed-precision steps, FP64 residuals
 TREE = dict(B=32, order=8, theta=0.6)
 
 
