@@ -95,8 +95,10 @@ const char *bem_last_error(const bem_ctx *ctx);
 /* Phase timing (profiling aid).  While enabled, every product records HIP
  * events on the context's stream between its phases and accumulates the
  * elapsed device time per phase:
- *   0 strengths, 1 P2M, 2 M2M, 3 M2L products, 4 L2L, 5 L2P, 6 P2P (near
- *   field), 7 corrections + combination, 8 direct sum, 9 other, 10 the M2L
+ *   0 strengths, 1 P2M, 2 M2M, 3 M2L products, 4 L2L, 5 L2P (no longer a
+ *   kernel of its own: the local expansions are evaluated inside phase 7),
+ *   6 P2P (near field), 7 corrections, L2P + combination, 8 direct sum,
+ *   9 other, 10 the M2L
  *   gathers around the products (moments into the canonical frames, results
  *   summed into the local expansions).
  * While timing is enabled every phase runs on the context's stream; without
@@ -105,10 +107,14 @@ const char *bem_last_error(const bem_ctx *ctx);
  * enable = 1 turns phase timing on and zeroes the counters; 2 instead times
  * only the two heavy kernels (the M2L products as phase 3 and the near field
  * as phase 6, each with events on the stream it runs on) and leaves the
- * scheduling of the product unchanged; 0 turns timing off.  Other values
- * give BEM_EINVAL.
- * ms and launches (host arrays of BEM_NPHASE, may be NULL) receive the
- * accumulated milliseconds and the number of products timed per phase. */
+ * scheduling of the product unchanged; 3 and 4 do the same for the near
+ * field only and for the M2L products only (one event pair per product);
+ * 0 turns timing off.  Other values give BEM_EINVAL.
+ * Products do not wait for their events: each call of bem_ctx_timing first
+ * synchronises the context's stream and reads back the events recorded
+ * since the previous call.  ms and launches (host arrays of BEM_NPHASE, may
+ * be NULL) then receive the accumulated milliseconds and the number of
+ * products timed per phase. */
 #define BEM_NPHASE 11
 int bem_ctx_timing(bem_ctx *ctx, int enable, double *ms, int64_t *launches);
 

@@ -68,17 +68,23 @@ void bem_ctx_destroy(bem_ctx *ctx) { delete ctx; }
 int bem_ctx_timing(bem_ctx *ctx, int enable, double *ms, int64_t *launches) {
     if (!ctx) return BEM_EINVAL;
     Ctx &c = ctx->c;
+    // the events recorded since the last call are read back now
+    const int rc = guard(&c, [&] {
+        if (c.ev_used || c.kev_used) {
+            c.sync();
+            c.collect();
+        }
+    });
+    if (rc != BEM_OK) return rc;
     if (ms)
         for (int i = 0; i < BEM_NPHASE; i++) ms[i] = c.phase_ms[i];
     if (launches)
         for (int i = 0; i < BEM_NPHASE; i++) launches[i] = c.phase_n[i];
-    if (enable < 0 || enable > 2) return BEM_EINVAL;
+    if (enable < 0 || enable > 4) return BEM_EINVAL;
     if (enable && c.timing != enable) {
         for (int i = 0; i < BEM_NPHASE; i++) { c.phase_ms[i] = 0.0; c.phase_n[i] = 0; }
     }
     c.timing = enable;
-    c.ev_used = 0;
-    c.kev_used = 0;
     return BEM_OK;
 }
 
@@ -254,11 +260,6 @@ int bem_matvec(bem_ctx *ctx, const bem_tree *tc, bem_green g, double k, bem_op o
         BEM_REQUIRE(m == BEM_DIRECT || m == BEM_FMM, BEM_EINVAL, "unknown method");
         BEM_REQUIRE(p == BEM_PREC_FP64 || p == BEM_PREC_MIXED, BEM_EINVAL, "unknown precision");
         bem::matvec(*t, g, g == BEM_HELMHOLTZ ? k : 0.0, op, m, p, nrhs, x_dev, y_dev);
-        // the product is stream-ordered; only timing reads its events back here
-        if (ctx->c.timing) {
-            ctx->c.sync();
-            ctx->c.collect();
-        }
     });
 }
 

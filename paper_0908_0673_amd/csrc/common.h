@@ -9,6 +9,7 @@
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <map>
 #include <unordered_map>
 #include <vector>
 
@@ -43,14 +44,20 @@ struct Error : std::runtime_error {
 // ---------------------------------------------------------------- context
 struct Ctx {
     // Timing with HIP events.  Mode 1 (phases): events between the phases on
-    // the context's stream, with every phase on that stream.  Mode 2 (heavy
-    // kernels): event pairs around the M2L product and near-field kernels
-    // only, each on the stream it runs on, with the usual scheduling.
+    // the context's stream, with every phase on that stream.  Modes 2-4
+    // (heavy kernels): event pairs around the M2L product and / or
+    // near-field kernels only, each on the stream it runs on, with the usual
+    // scheduling.  Events pile up without any synchronisation and are read
+    // back when the counters are (collect, after a stream sync), so timing
+    // does not stall the host between products; each event carries the
+    // sequence number of its product.
     int timing = 0;
+    int64_t prod_seq = 0;  // products started on this context
     double phase_ms[BEM_NPHASE] = {0};
     int64_t phase_n[BEM_NPHASE] = {0};
     std::vector<hipEvent_t> events;
-    std::vector<int> ev_phase;  // phase closed by each recorded event (-1 for the opening one)
+    std::vector<int> ev_phase;      // phase closed by each recorded event
+    std::vector<int64_t> ev_prod;   // product of each recorded event
     int ev_used = 0;
 
     void mark(int phase) {
@@ -60,15 +67,18 @@ struct Ctx {
             BEM_HIP(hipEventCreate(&e));
             events.push_back(e);
             ev_phase.push_back(-1);
+            ev_prod.push_back(-1);
         }
         BEM_HIP(hipEventRecord(events[ev_used], stream));
         ev_phase[ev_used] = phase;
+        ev_prod[ev_used] = prod_seq;
         ev_used++;
     }
-    // mode 2: an event pair around one kernel on stream st
+    // modes 2-4: an event pair around one kernel on stream st
     std::vector<hipEvent_t> kev;
-    std::vector<int> kev_phase;  // phase of each pair
-    int kev_used = 0;            // events used (two per pair)
+    std::vector<int> kev_phase;      // phase of each pair
+    std::vector<int64_t> kev_prod;   // product of each pair
+    int kev_used = 0;                // events used (two per pair)
     hipEvent_t kernel_event() {
         if (kev_used == (int)kev.size()) {
             hipEvent_t e;
@@ -77,36 +87,55 @@ struct Ctx {
         }
         return kev[kev_used++];
     }
+    // modes 2 (both heavy kernels), 3 (near field only), 4 (M2L products only)
+    bool times_kernel(int phase) const {
+        return timing == 2 || (timing == 3 && phase == 6) || (timing == 4 && phase == 3);
+    }
+    int open_phase = -1;
     void kbegin(hipStream_t st, int phase) {
-        if (timing != 2) return;
+        open_phase = times_kernel(phase) ? phase : -1;
+        if (open_phase < 0) return;
         BEM_HIP(hipEventRecord(kernel_event(), st));
         kev_phase.resize(kev_used / 2 + 1);
+        kev_prod.resize(kev_used / 2 + 1);
         kev_phase[kev_used / 2] = phase;
+        kev_prod[kev_used / 2] = prod_seq;
     }
     void kend(hipStream_t st) {
-        if (timing != 2) return;
-        BEM_HIP(hipEventRecord(kernel_event(), st));
+        if (open_phase < 0) return;
+        open_phase = -1;
+        hipEvent_t e = kernel_event();
+        BEM_HIP(hipEventRecord(e, st));
+        if (st == side) side_tail = e;
     }
-    // after the streams have been synchronised: fold the recorded intervals into the counters
+    // After the streams have been synchronised: folds the recorded intervals
+    // into the counters (launches = products in which the phase was timed)
+    // and frees the events for reuse.
     void collect() {
-        if (timing == 2) {
-            bool seen[BEM_NPHASE] = {false};
-            for (int i = 0; i + 1 < kev_used; i += 2) {
-                float ms = 0.f;
-                BEM_HIP(hipEventElapsedTime(&ms, kev[i], kev[i + 1]));
-                const int ph = kev_phase[i / 2];
-                phase_ms[ph] += ms;
-                if (!seen[ph]) { phase_n[ph]++; seen[ph] = true; }
-            }
-            kev_used = 0;
-            return;
-        }
-        if (timing != 1) return;
         bool seen[BEM_NPHASE] = {false};
+        int64_t cur = -1;
+        for (int i = 0; i + 1 < kev_used; i += 2) {
+            float ms = 0.f;
+            BEM_HIP(hipEventElapsedTime(&ms, kev[i], kev[i + 1]));
+            const int ph = kev_phase[i / 2];
+            if (kev_prod[i / 2] != cur) {
+                cur = kev_prod[i / 2];
+                for (bool &b : seen) b = false;
+            }
+            phase_ms[ph] += ms;
+            if (!seen[ph]) { phase_n[ph]++; seen[ph] = true; }
+        }
+        kev_used = 0;
+        cur = -1;
         for (int i = 1; i < ev_used; i++) {
+            if (ev_prod[i] != ev_prod[i - 1]) continue;  // no interval across products
+            if (ev_prod[i] != cur) {
+                cur = ev_prod[i];
+                for (bool &b : seen) b = false;
+            }
             float ms = 0.f;
             BEM_HIP(hipEventElapsedTime(&ms, events[i - 1], events[i]));
-            int ph = ev_phase[i];
+            const int ph = ev_phase[i];
             if (ph >= 0 && ph < BEM_NPHASE) {
                 phase_ms[ph] += ms;
                 if (!seen[ph]) { phase_n[ph]++; seen[ph] = true; }
@@ -115,6 +144,7 @@ struct Ctx {
         ev_used = 0;
     }
     ~Ctx() {
+        trim_cache();
         for (auto e : events) (void)hipEventDestroy(e);
         for (auto e : kev) (void)hipEventDestroy(e);
         release_streams();
@@ -126,9 +156,24 @@ struct Ctx {
     bool has_alloc = false;
     std::string err;
 
-    // device bytes currently held by the library through this context
+    // Device bytes in use by the library through this context (bytes_live)
+    // and freed blocks kept for reuse (cached).  Without a caller allocator,
+    // freed blocks up to cache_limit bytes in total are kept by size class
+    // (four classes per power of two) instead of being returned with
+    // hipFree, which waits for the whole device: repeated solves allocate
+    // the same work buffers, and a context serving requests beside others
+    // must not stall them.
     std::atomic<size_t> bytes_live{0};
+    std::atomic<size_t> cached{0};
+    size_t cache_limit = (size_t)1 << 30;
     std::unordered_map<void *, size_t> sizes;
+    std::multimap<size_t, void *> cache;
+    static size_t size_class(size_t bytes) {
+        if (bytes <= 4096) return 4096;
+        int top = 63 - __builtin_clzll((unsigned long long)bytes);
+        const size_t step = (size_t)1 << (top - 2);
+        return (bytes + step - 1) / step * step;
+    }
     void *dmalloc(size_t bytes) {
         if (bytes == 0) bytes = 256;
         void *p = nullptr;
@@ -136,8 +181,22 @@ struct Ctx {
             p = alloc.alloc(alloc.user, bytes, (void *)stream);
             if (!p) fail(BEM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
         } else {
-            hipError_t e = hipMalloc(&p, bytes);
-            if (e != hipSuccess) fail(BEM_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+            bytes = size_class(bytes);
+            auto it = cache.find(bytes);
+            if (it != cache.end()) {
+                p = it->second;
+                cache.erase(it);
+                cached -= bytes;
+            } else {
+                hipError_t e = hipMalloc(&p, bytes);
+                if (e != hipSuccess && cached) {  // give the cache back and try once more
+                    (void)hipGetLastError();
+                    trim_cache();
+                    e = hipMalloc(&p, bytes);
+                }
+                if (e != hipSuccess)
+                    fail(BEM_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+            }
         }
         sizes[p] = bytes;
         bytes_live += bytes;
@@ -145,13 +204,26 @@ struct Ctx {
     }
     void dfree(void *p) {
         if (!p) return;
+        size_t bytes = 0;
         auto it = sizes.find(p);
         if (it != sizes.end()) {
-            bytes_live -= it->second;
+            bytes = it->second;
+            bytes_live -= bytes;
             sizes.erase(it);
         }
         if (has_alloc) alloc.free(alloc.user, p, (void *)stream);
-        else (void)hipFree(p);
+        else if (bytes && cached + bytes <= cache_limit) {
+            cache.emplace(bytes, p);
+            cached += bytes;
+        } else {
+            (void)hipFree(p);
+        }
+    }
+    // returns every cached block to the device
+    void trim_cache() {
+        for (auto &kv : cache) (void)hipFree(kv.second);
+        cache.clear();
+        cached = 0;
     }
     void sync() { BEM_HIP(hipStreamSynchronize(stream)); }
 
@@ -159,6 +231,7 @@ struct Ctx {
     // the main stream inside one call, with its fork / join events
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t side_tail = nullptr;  // event recorded last on the side stream, if any (timing)
     hipStream_t side_stream() {
         if (!side) {
             BEM_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
@@ -171,11 +244,19 @@ struct Ctx {
     void fork() {
         BEM_HIP(hipEventRecord(ev_fork, stream));
         BEM_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+        side_tail = nullptr;
     }
-    // main stream waits for everything issued so far on the side stream
+    // main stream waits for everything issued so far on the side stream (on
+    // the timing event that closed the side stream's last kernel, when there
+    // is one, rather than on one more event)
     void join() {
-        BEM_HIP(hipEventRecord(ev_join, side));
-        BEM_HIP(hipStreamWaitEvent(stream, ev_join, 0));
+        hipEvent_t e = side_tail;
+        if (!e) {
+            BEM_HIP(hipEventRecord(ev_join, side));
+            e = ev_join;
+        }
+        BEM_HIP(hipStreamWaitEvent(stream, e, 0));
+        side_tail = nullptr;
     }
     void release_streams() {
         if (ev_fork) (void)hipEventDestroy(ev_fork);

@@ -724,7 +724,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         // downward pass
         l2l_apply<V, R>(t, nrhs, loc);
         c.mark(4);
-        c.mark(5);  // the local expansions are evaluated at the targets in the combination
+        // (the local expansions are evaluated at the targets in the combination)
         if (t.n_p2p_items) {
             if (overlap) c.join();
             else near_field(c.stream);
@@ -750,6 +750,12 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
 }  // namespace
 
 void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int nrhs, const void *x, void *y) {
+    Ctx &c = *t.ctx;
+    c.prod_seq++;
+    if (c.timing && (c.ev_used > 4096 || c.kev_used > 4096)) {  // bound the pool of pending events
+        c.sync();
+        c.collect();
+    }
     if (green == BEM_HELMHOLTZ) {
         using XV = cx<double>;
         if (prec == BEM_PREC_FP64 || method == BEM_DIRECT)

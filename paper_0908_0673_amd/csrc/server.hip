@@ -85,6 +85,7 @@ size_t value_bytes(int green) { return green == BEM_HELMHOLTZ ? 16 : 8; }
 void make_room(bem_server *s, int lane, size_t need, int32_t keep) {
     Lane &L = *s->lanes[lane];
     const size_t share = (size_t)(s->o.hbm_budget / s->o.lanes);
+    if (L.ctx->c.bytes_live + L.ctx->c.cached + need > share) L.ctx->c.trim_cache();
     while (L.ctx->c.bytes_live + need > share) {
         MeshEntry *victim = nullptr;
         int32_t vid = -1;
@@ -372,7 +373,7 @@ int bem_server_stats_get(bem_server *s, bem_server_stats *st) {
     std::lock_guard<std::mutex> lk(s->mu);
     *st = s->st;
     int64_t b = 0;
-    for (auto &l : s->lanes) b += (int64_t)l->ctx->c.bytes_live + (int64_t)l->dbytes;
+    for (auto &l : s->lanes) b += (int64_t)(l->ctx->c.bytes_live + l->ctx->c.cached) + (int64_t)l->dbytes;
     st->resident_bytes = b;
     return BEM_OK;
 }

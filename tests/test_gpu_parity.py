@@ -361,3 +361,31 @@ def test_invalid_arguments():
     with pytest.raises(bem.BemError) as e:
         bem.bem_tree_build(ctx, mesh, order=12)
     assert e.value.code == bem.BEM_EUNSUPPORTED
+
+
+def test_kernel_event_timing_modes():
+    """bem_ctx_timing modes 2-4 bracket the heavy kernels with events without
+    changing the product: 2 times both, 3 the near field only, 4 the M2L
+    products only, one pair per product; other modes are rejected."""
+    import torch
+
+    bem = _bem()
+    m, ctx, mesh, tree, om, ot = setup("sphere320")
+    x = to_dev(bem_inputs.random_vector(om.n_dof, 1)[0], False)
+    ref = torch.empty_like(x)
+    bem.bem_matvec(ctx, tree, 0, 0.0, bem.BEM_OP_A, bem.BEM_FMM, bem.BEM_PREC_MIXED, x, ref)
+    try:
+        for mode, timed in ((2, {"m2l", "p2p"}), (3, {"p2p"}), (4, {"m2l"})):
+            ctx.timing(mode)
+            y = torch.empty_like(x)
+            for _ in range(3):
+                bem.bem_matvec(ctx, tree, 0, 0.0, bem.BEM_OP_A, bem.BEM_FMM, bem.BEM_PREC_MIXED, x, y)
+            got = ctx.timing(0)
+            assert torch.equal(y, ref)
+            assert {k for k, (ms, n) in got.items() if n} == timed, (mode, got)
+            assert all(got[k][1] == 3 and got[k][0] > 0.0 for k in timed)
+        with pytest.raises(bem.BemError) as e:
+            ctx.timing(5)
+        assert e.value.code == bem.BEM_EINVAL
+    finally:
+        ctx.timing(0)
