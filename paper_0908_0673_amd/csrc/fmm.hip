@@ -77,6 +77,61 @@ __device__ inline double inv_sqrt(double v) {
     return y;
 }
 
+// sin and cos of x for the near field's phases k r: Cody-Waite reduction by
+// the nearest multiple q of pi/2 (pi/2 split in three parts, each product
+// q * part formed exactly inside an fma), Taylor polynomials of sin and cos
+// on the reduced argument |r| <= pi/4 (the first omitted term is below half
+// an ulp there) and the quadrant q mod 4.  No range branch; the reduction
+// stays accurate while |x| < 2^20 in single and 2^40 in double precision,
+// far beyond k times any near-field distance.
+__device__ inline void sincos_near(float x, float *s, float *c) {
+    const float q = rintf(x * 0.63661977f);
+    float r = fmaf(-q, 1.5707963705062866f, x);
+    r = fmaf(-q, -4.371138828673793e-08f, r);
+    r = fmaf(-q, -1.7151245100058819e-15f, r);
+    const float r2 = r * r;
+    float ps = fmaf(r2, 2.7557319e-6f, -1.9841270e-4f);  // 1/9!, -1/7!
+    ps = fmaf(r2, ps, 8.3333333e-3f);                    // 1/5!
+    ps = fmaf(r2, ps, -1.6666667e-1f);                   // -1/3!
+    const float sr = fmaf(r * r2, ps, r);
+    float pc = fmaf(r2, -2.7557319e-7f, 2.4801587e-5f);  // -1/10!, 1/8!
+    pc = fmaf(r2, pc, -1.3888889e-3f);                   // -1/6!
+    pc = fmaf(r2, pc, 4.1666667e-2f);                    // 1/4!
+    pc = fmaf(r2, pc, -0.5f);
+    const float cr = fmaf(r2, pc, 1.0f);
+    const int n = (int)q;  // two's complement: n & 3 is q mod 4 for negative q too
+    const float u = (n & 1) ? cr : sr, v = (n & 1) ? sr : cr;
+    *s = (n & 2) ? -u : u;
+    *c = ((n + 1) & 2) ? -v : v;
+}
+__device__ inline void sincos_near(double x, double *s, double *c) {
+    const double q = rint(x * 0.6366197723675814);
+    double r = fma(-q, 1.5707963267948966, x);
+    r = fma(-q, 6.123233995736766e-17, r);
+    r = fma(-q, -1.4973849048591698e-33, r);
+    const double r2 = r * r;
+    double ps = fma(r2, 2.8114572543455206e-15, -7.647163731819816e-13);  // 1/17!, -1/15!
+    ps = fma(r2, ps, 1.6059043836821613e-10);                          // 1/13!
+    ps = fma(r2, ps, -2.505210838544172e-08);                          // -1/11!
+    ps = fma(r2, ps, 2.7557319223985893e-06);                          // 1/9!
+    ps = fma(r2, ps, -1.984126984126984e-04);                          // -1/7!
+    ps = fma(r2, ps, 8.333333333333333e-03);                           // 1/5!
+    ps = fma(r2, ps, -1.6666666666666666e-01);                         // -1/3!
+    const double sr = fma(r * r2, ps, r);
+    double pc = fma(r2, 4.779477332387385e-14, -1.1470745597729725e-11);  // 1/16!, -1/14!
+    pc = fma(r2, pc, 2.08767569878681e-09);                            // 1/12!
+    pc = fma(r2, pc, -2.755731922398589e-07);                          // -1/10!
+    pc = fma(r2, pc, 2.48015873015873e-05);                            // 1/8!
+    pc = fma(r2, pc, -1.388888888888889e-03);                          // -1/6!
+    pc = fma(r2, pc, 4.1666666666666664e-02);                          // 1/4!
+    pc = fma(r2, pc, -0.5);
+    const double cr = fma(r2, pc, 1.0);
+    const int n = (int)q;
+    const double u = (n & 1) ? cr : sr, v = (n & 1) ? sr : cr;
+    *s = (n & 2) ? -u : u;
+    *c = ((n + 1) & 2) ? -v : v;
+}
+
 template <class R> struct r4;
 template <> struct r4<float> { using type = float4; };
 template <> struct r4<double> { using type = double4; };
@@ -95,7 +150,7 @@ __device__ inline V p2p_term(double x0, double x1, double x2, double2 sxy, doubl
         if (DBL) g = g * (d0 * ns.x + d1 * ns.y + d2 * ns.z) * ir * ir;
         const R kr = k * r2 * ir;
         R sn, cs;
-        vsincos(kr, &sn, &cs);
+        sincos_near(kr, &sn, &cs);
         cx<R> kv = DBL ? cx<R>(g * (cs + kr * sn), g * (sn - kr * cs)) : cx<R>(g * cs, g * sn);
         return kv * cx<R>(ns.w, si);
     } else {
