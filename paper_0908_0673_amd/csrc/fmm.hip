@@ -25,6 +25,7 @@
 //   correction sparse (accurate - 7-point) terms, free term, combination (FP64)
 #include <cmath>
 #include <type_traits>
+#include <unordered_map>
 
 #include "greens.h"
 #include "kernels.h"
@@ -732,12 +733,15 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         // leaves registers and wave slots for the far-field kernels (their
         // matrix-core and latency-bound work then overlaps its VALU work).
         auto near_lds = [&](const void *fn) -> unsigned {
+            static thread_local std::unordered_map<const void *, unsigned> memo;  // per kernel (one device model)
+            auto it = memo.find(fn);
+            if (it != memo.end()) return it->second;
             hipFuncAttributes fa;
             BEM_HIP(hipFuncGetAttributes(&fa, fn));
             int lds = 0;
             BEM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c.device));
             const long pad = (long)lds / P2P_PER_CU - (long)fa.sharedSizeBytes - 256;
-            return pad > 0 ? (unsigned)pad : 0u;
+            return memo[fn] = pad > 0 ? (unsigned)pad : 0u;
         };
         auto near_field = [&](hipStream_t st) {
             dim3 g((unsigned)t.n_p2p_units, nrhs);
