@@ -34,7 +34,7 @@ namespace bem {
 
 namespace {
 
-__host__ __device__ inline int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+__host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 __host__ __device__ inline int midx(int a, int b, int c) {
     int n = a + b + c;
     return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
@@ -357,31 +357,52 @@ __global__ void __launch_bounds__(256) k_direct(const double *q, int64_t n_q, co
 // singular / near-singular corrections and, for A, the free term.  Eight
 // lanes per target share its correction pairs and meet by shuffles.  The far
 // field is either a finished value per target (yacc, direct product) or, for
-// the fast product, the local expansion evaluated at the target (Section 3.2,
-// the stored monomials U of its leaf), folded in here: the lanes take every
-// eighth coefficient, in the expansion's precision, and the sum over lanes
-// runs in FP64.
+// the fast product, the local expansion evaluated at the target (Section 3.2),
+// folded in here: the monomials u^b of the target's position u in its leaf's
+// frame (scaled by the leaf's side) are products of powers of u's three
+// components, which three lanes of the target form in FP64 and leave in LDS
+// in the expansion's precision; the target's eight lanes then take every
+// eighth coefficient, and the sum over lanes runs in FP64.
 template <class XV, class AV, class R, class VD, bool LAP>
 __global__ void __launch_bounds__(256) k_combine(int64_t n_tgt, const int32_t *tperm, const AV *yacc,
-                                                 const int32_t *tgt_leaf, const R *U, const AV *loc, int P,
-                                                 int64_t n_box, const int32_t *tgt_item, const int32_t *item_unit,
-                                                 const int32_t *wi_t0, const VD *part, int64_t n_unit,
-                                                 const int64_t *row_ptr, const int32_t *pair_elem,
+                                                 const int32_t *tgt_leaf, const double *t64, const double *centre,
+                                                 const int32_t *level, double side, const int8_t *exps, int order,
+                                                 const AV *loc, int P, int64_t n_box, const int32_t *tgt_item,
+                                                 const int32_t *item_unit, const int32_t *wi_t0, const VD *part,
+                                                 int64_t n_unit, const int64_t *row_ptr, const int32_t *pair_elem,
                                                  const int32_t *se_dofs, const XV *corr, const double *cfree,
                                                  const XV *x, int op, XV *y) {
+    __shared__ R pw[32][3][MAX_ORDER + 1];      // powers of the block's targets' coordinates
+    __shared__ int32_t ex[ncoef(MAX_ORDER)];    // exponents a | b << 8 | c << 16 of each coefficient
     const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-    const int l8 = threadIdx.x & 7, rhs = blockIdx.y;
+    const int l8 = threadIdx.x & 7, slot = threadIdx.x >> 3, rhs = blockIdx.y;
     const bool ok = t < n_tgt;
     const XV *xr = x + (int64_t)rhs * n_tgt;
     XV acc = XV(0.0);
-    if (ok && loc) {
-        const int4 m = *(const int4 *)(tgt_leaf + 4 * t);  // leaf, first target, target count
-        const R *Ut = U + (int64_t)m.y * P + (t - m.y);
-        const AV *F = loc + ((int64_t)rhs * n_box + m.x) * P;
-        AV a = AV(0.0);
+    if (loc) {  // the same for the whole block
+        for (int i = threadIdx.x; i < P; i += blockDim.x)
+            ex[i] = exps[3 * i] | (exps[3 * i + 1] << 8) | (exps[3 * i + 2] << 16);
+        const int b = ok ? tgt_leaf[4 * t] : 0;
+        if (ok && l8 < 3) {
+            const double u = (t64[l8 * n_tgt + t] - centre[3 * b + l8]) * ldexp(1.0 / side, level[b]);
+            double v = 1.0;
+            for (int k = 0; k <= order; k++) {
+                pw[slot][l8][k] = (R)v;
+                v *= u;
+            }
+        }
+        __syncthreads();
+        if (ok) {
+            const AV *F = loc + ((int64_t)rhs * n_box + b) * P;
+            const R *p0 = pw[slot][0], *p1 = pw[slot][1], *p2 = pw[slot][2];
+            AV a = AV(0.0);
 #pragma unroll 4
-        for (int i = l8; i < P; i += 8) a += F[i] * Ut[(int64_t)i * m.z];
-        acc = vcast<XV>(a);
+            for (int i = l8; i < P; i += 8) {
+                const int e = ex[i];
+                a += F[i] * (p0[e & 255] * p1[(e >> 8) & 255] * p2[e >> 16]);
+            }
+            acc = vcast<XV>(a);
+        }
     }
     if (ok) {
         for (int64_t p = row_ptr[t] + l8; p < row_ptr[t + 1]; p += 8) {
@@ -796,10 +817,9 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
     const VD *part = method == BEM_FMM && t.n_p2p_items ? (const VD *)t.work.p2p_part.p : nullptr;
     dim3 g(nblocks(8 * nt, 256), nrhs);
     const bool fmm = method == BEM_FMM;
-    const R *U = nullptr;
-    if (fmm) U = std::is_same<R, float>::value ? (const R *)t.pass.U32.p : (const R *)t.pass.U64.p;
     k_combine<XV, V, R, VD, !HELM><<<g, 256, 0, c.stream>>>(
-        nt, t.tperm.p, fmm ? nullptr : yacc, t.tgt_leaf.p, U, fmm ? loc : nullptr, fmm ? t.tables->P : 0, t.n_box,
+        nt, t.tperm.p, fmm ? nullptr : yacc, t.tgt_leaf.p, t.t64.p, t.centre.p, t.level.p, t.side,
+        fmm ? t.tables->exps.p : nullptr, t.order, fmm ? loc : nullptr, fmm ? t.tables->P : 0, t.n_box,
         t.p2p_tgt_item.p, t.p2p_item_unit.p, t.p2p_t0.p, part, t.n_p2p_units, t.pair_ptr.p,
         t.pair_elem.p, t.se_dofs.p, corr, op == BEM_OP_A ? t.free_term.p : nullptr, x, op, y);
     BEM_LAUNCH_CHECK();

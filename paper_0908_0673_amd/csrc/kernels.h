@@ -87,8 +87,8 @@ inline DBuf<float> &M2lPlan::expanded_buf<float>() { return T32; }
 template <>
 inline DBuf<double> &M2lPlan::expanded_buf<double>() { return T64; }
 
-// Stored P2M weights (per source leaf and DOF, single and double layer) and
-// L2P target monomials; geometry only, built once per tree.
+// Stored P2M weights (per source leaf and DOF, single and double layer);
+// geometry only, built once per tree.
 struct PassTables {
     bool built = false;
     int64_t n_w = 0;
@@ -96,8 +96,6 @@ struct PassTables {
     DBuf<int32_t> wdof;   // [n_w] DOF of each weight row
     DBuf<double> W64[2];  // [n_w][P], index 0 single layer, 1 double layer
     DBuf<float> W32[2];
-    DBuf<double> U64;     // per target leaf [P][nt] blocks
-    DBuf<float> U32;
 };
 
 // Per-matvec work buffers, grown on demand and kept on the tree.
@@ -222,8 +220,6 @@ template <class V, class R>
 void m2m_apply(bem_tree &t, int nrhs, V *mom);
 template <class V, class R>
 void l2l_apply(bem_tree &t, int nrhs, V *loc);
-template <class V, class R>
-void l2p_apply(bem_tree &t, int nrhs, const V *loc, V *y);
 
 // m2l.hip
 M2lPlan &get_m2l_plan(bem_tree &t, int green, double k);

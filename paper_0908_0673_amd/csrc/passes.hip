@@ -11,7 +11,8 @@
 // only (not on G or k), so they are built once per tree and layer type and the
 // moments are one small product per leaf: Mh = W^T x.
 //
-// L2P uses the stored monomials u_t^b of every target in its leaf's frame.
+// (L2P, the evaluation of the local expansions at the targets, runs inside
+// the combination kernel of fmm.hip.)
 //
 // M2M and L2L: a child centre is offset from its parent's by s rho_parent / 4
 // with s in {-1, +1}^3 (s_d = +1 when bit d of the child octant is set), so
@@ -288,64 +289,6 @@ __global__ void __launch_bounds__(256) k_l2l(const int32_t *boxes, const int32_t
     if (bi < P && cj >= 0) base[(int64_t)cj * P + bi] = old + v;
 }
 
-// ---------------------------------------------------------------- L2P monomials
-template <class R>
-__global__ void k_l2p_monomials(const int32_t *leaves, const int64_t *tb, const int64_t *te, const int32_t *level,
-                                const double *centre, double side, const double *t64, int64_t n_tgt, int p,
-                                const int8_t *exps, R *U) {
-    const int P = ncoef(p);
-    const int b = leaves[blockIdx.x];
-    const int64_t t0 = tb[b], nt = te[b] - tb[b];
-    const double irho = 1.0 / ldexp(side, -level[b]);
-    for (int64_t i = threadIdx.x; i < nt * P; i += blockDim.x) {
-        const int64_t tl = i % nt;
-        const int bi = (int)(i / nt);
-        const int64_t t = t0 + tl;
-        const double u0 = (t64[t] - centre[3 * b]) * irho, u1 = (t64[n_tgt + t] - centre[3 * b + 1]) * irho,
-                     u2 = (t64[2 * n_tgt + t] - centre[3 * b + 2]) * irho;
-        double v = 1.0;
-        for (int k = 0; k < exps[3 * bi]; k++) v *= u0;
-        for (int k = 0; k < exps[3 * bi + 1]; k++) v *= u1;
-        for (int k = 0; k < exps[3 * bi + 2]; k++) v *= u2;
-        U[t0 * P + (int64_t)bi * nt + tl] = (R)v;
-    }
-}
-
-// grid (target leaves, rhs); block 256: wave w sums the coefficients of its
-// quarter of the expansion for up to 64 targets at a time, with all of its
-// monomial loads in flight together; the four partial sums meet in LDS.
-template <class V, class R>
-__global__ void __launch_bounds__(256) k_l2p_apply(const int32_t *leaves, const int64_t *tb, const int64_t *te,
-                                                   int P, const R *U, const V *loc, int64_t n_box, int64_t n_tgt,
-                                                   V *y) {
-    constexpr int QMAX = (ncoef(MAX_ORDER) + 3) / 4;
-    extern __shared__ unsigned char smem[];
-    V *F = (V *)smem;           // [P]
-    __shared__ V red[4][64];
-    const int b = leaves[blockIdx.x], rhs = blockIdx.y;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int i = tid; i < P; i += blockDim.x) F[i] = loc[((int64_t)rhs * n_box + b) * P + i];
-    __syncthreads();
-    const int64_t t0 = tb[b], nt = te[b] - tb[b];
-    const R *Ub = U + t0 * P;
-    const int q = (P + 3) / 4, c0 = w * q, c1 = min(P, c0 + q);
-    for (int64_t tbase = 0; tbase < nt; tbase += 64) {
-        const int64_t tl = tbase + lane;
-        const bool ok = tl < nt;
-        R u[QMAX];
-#pragma unroll
-        for (int i = 0; i < QMAX; i++) u[i] = (ok && c0 + i < c1) ? Ub[(int64_t)(c0 + i) * nt + tl] : R(0);
-        V acc = V(0.0);
-#pragma unroll
-        for (int i = 0; i < QMAX; i++)
-            if (c0 + i < c1) acc += F[c0 + i] * u[i];
-        red[w][lane] = acc;
-        __syncthreads();
-        if (w == 0 && ok) y[(int64_t)rhs * n_tgt + t0 + tl] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-        __syncthreads();
-    }
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------- setup
@@ -402,17 +345,6 @@ void build_pass_tables(bem_tree &t) {
         k_to_r<float><<<nblocks(nw, 256), 256, 0, c.stream>>>(pt.W64[dbl].p, nw, pt.W32[dbl].p);
         BEM_LAUNCH_CHECK();
     }
-    // target monomials
-    const size_t nu = (size_t)t.n_tgt * P;
-    pt.U64.alloc(&c, nu);
-    pt.U32.alloc(&c, nu);
-    if (t.n_leaf_tgt) {
-        k_l2p_monomials<double><<<(unsigned)t.n_leaf_tgt, 256, 0, c.stream>>>(
-            t.tleaf_ids.p, t.tb.p, t.te.p, t.level.p, t.centre.p, t.side, t.t64.p, t.n_tgt, p, T.exps.p, pt.U64.p);
-        BEM_LAUNCH_CHECK();
-        k_to_r<float><<<nblocks(nu, 256), 256, 0, c.stream>>>(pt.U64.p, nu, pt.U32.p);
-        BEM_LAUNCH_CHECK();
-    }
     c.sync();
     pt.built = true;
 }
@@ -460,23 +392,10 @@ void l2l_apply(bem_tree &t, int nrhs, V *loc) {
     }
 }
 
-template <class V, class R>
-void l2p_apply(bem_tree &t, int nrhs, const V *loc, V *y) {
-    if (!t.n_leaf_tgt) return;
-    Ctx &c = *t.ctx;
-    const int P = t.tables->P;
-    const R *U = std::is_same<R, float>::value ? (const R *)t.pass.U32.p : (const R *)t.pass.U64.p;
-    dim3 g((unsigned)t.n_leaf_tgt, nrhs);
-    k_l2p_apply<V, R><<<g, 256, sizeof(V) * P, c.stream>>>(t.tleaf_ids.p, t.tb.p, t.te.p, P, U, loc, t.n_box,
-                                                            t.n_tgt, y);
-    BEM_LAUNCH_CHECK();
-}
-
 #define BEM_PASSES(V, R, XV)                                                   \
     template void p2m_apply<V, R, XV>(bem_tree &, bool, int, const XV *, V *); \
     template void m2m_apply<V, R>(bem_tree &, int, V *);                       \
-    template void l2l_apply<V, R>(bem_tree &, int, V *);                       \
-    template void l2p_apply<V, R>(bem_tree &, int, const V *, V *);
+    template void l2l_apply<V, R>(bem_tree &, int, V *);
 BEM_PASSES(double, double, double)
 BEM_PASSES(float, float, double)
 BEM_PASSES(cx<double>, double, cx<double>)
