@@ -65,6 +65,9 @@ constexpr int P2P_BS = 256;
 constexpr int P2P_TILE = 256;
 constexpr int P2P_CH = 256;  // near-list entries per chunk
 constexpr int P2P_PER_CU = 4;  // near-field blocks per CU while the far field runs beside it
+#ifndef P2P_TPL
+#define P2P_TPL 4  // targets per lane
+#endif
 
 // 1/sqrt(v) for v > 0 far from the denormal range (squared distances of
 // distinct points): the hardware estimate, which is within 1 ulp in single
@@ -166,12 +169,12 @@ __device__ inline V p2p_term(double x0, double x1, double x2, double2 sxy, doubl
 // points, one per lane, through its own LDS slot as packed records (FP64
 // position, normal and strength in R), loading the next batch into registers
 // while it computes the current one, so no block barrier sits inside the
-// loop.  Each lane holds two targets, so every LDS read serves two
+// loop.  Each lane holds TPL targets, so every LDS read serves TPL
 // interactions; lanes not needed for targets split a batch into sub-streams.
 // The target-source difference is formed in FP64 and only then rounded to R,
 // so close pairs keep their relative accuracy in the mixed path; per-batch
 // partial sums in R are added into an FP64 total.
-template <class V, class R, bool DBL, bool HELM>
+template <class V, class R, bool DBL, bool HELM, int TPL>
 __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const int32_t *unit_item,
                                                 const int64_t *unit_f, int64_t n_unit, const int32_t *wi_box,
                                                 const int32_t *wi_t0, const int32_t *wi_nt, const int64_t *nptr,
@@ -189,20 +192,28 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
     __shared__ R4 sns[NW][2][64];
     __shared__ R ssi[NW][2][HELM ? 64 : 1];
     __shared__ VD red[NW][64];
-    __shared__ VD sub_a[NW][64], sub_b[NW][64];
+    __shared__ VD subs[NW][64];
     const int u = unit_order[blockIdx.x], rhs = blockIdx.y;
     const int w = unit_item[u];
     const int64_t u0 = unit_f[2 * u], u1 = unit_f[2 * u + 1];  // the unit's share of the item's near points
     const int b = wi_box[w], t0 = wi_t0[w], nt = wi_nt[w];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // tpw lanes hold the item's targets, two each; the wave's lanes form nsub
-    // such groups, each streaming every nsub-th point (leftover lanes idle)
-    const int tpw = (nt + 1) >> 1, nsub = 64 / tpw, tl = lane % tpw, sub = lane / tpw;
-    const int ta = min(2 * tl, nt - 1), tb2 = min(2 * tl + 1, nt - 1);
-    const double xa0 = t64[t0 + ta], xa1 = t64[n_tgt + t0 + ta], xa2 = t64[2 * n_tgt + t0 + ta];
-    const double xb0 = t64[t0 + tb2], xb1 = t64[n_tgt + t0 + tb2], xb2 = t64[2 * n_tgt + t0 + tb2];
+    // tpw lanes hold the item's targets, TPL each (the last one repeated to
+    // fill a lane); the wave's lanes form nsub such groups, each streaming
+    // every nsub-th point (leftover lanes idle)
+    const int tpw = (nt + TPL - 1) / TPL, nsub = 64 / tpw, tl = lane % tpw, sub = lane / tpw;
+    double xt[TPL][3];
+#pragma unroll
+    for (int q = 0; q < TPL; q++) {
+        const int ti = t0 + min(TPL * tl + q, nt - 1);
+        xt[q][0] = t64[ti];
+        xt[q][1] = t64[n_tgt + ti];
+        xt[q][2] = t64[2 * n_tgt + ti];
+    }
     const V *sr = s + (int64_t)rhs * n_q;
-    VD tot_a = VD(0.0), tot_b = VD(0.0);
+    VD tot[TPL];
+#pragma unroll
+    for (int q = 0; q < TPL; q++) tot[q] = VD(0.0);
     const int64_t j0 = nptr[b], j1 = nptr[b + 1];
     int64_t base = 0;  // position of the chunk's first point in the item's near-point sequence
     for (int64_t cb = j0; cb < j1 && base < u1; cb += P2P_CH) {
@@ -274,33 +285,36 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
             __builtin_amdgcn_wave_barrier();
             fetch(fb + 64 + lane);  // next batch in flight while this one is computed
             const int nin = (int)min<int64_t>(64, f1 - fb);
-            V acc_a = V(0.0), acc_b = V(0.0);
-#pragma unroll 4
+            V acc[TPL];
+#pragma unroll
+            for (int q = 0; q < TPL; q++) acc[q] = V(0.0);
+#pragma unroll(8 / TPL)
             for (int kk = sub < nsub ? sub : nin; kk < nin; kk += nsub) {
                 const double2 cxy = sxy[wave][buf][kk];
                 const double cz = szz[wave][buf][kk];
                 const R4 cns = sns[wave][buf][kk];
                 const R csi = HELM ? ssi[wave][buf][kk] : (R)0;
-                acc_a += p2p_term<V, R, DBL, HELM>(xa0, xa1, xa2, cxy, cz, cns, csi, k);
-                acc_b += p2p_term<V, R, DBL, HELM>(xb0, xb1, xb2, cxy, cz, cns, csi, k);
+#pragma unroll
+                for (int q = 0; q < TPL; q++)
+                    acc[q] += p2p_term<V, R, DBL, HELM>(xt[q][0], xt[q][1], xt[q][2], cxy, cz, cns, csi, k);
             }
-            tot_a += vcast<VD>(acc_a);
-            tot_b += vcast<VD>(acc_b);
+#pragma unroll
+            for (int q = 0; q < TPL; q++) tot[q] += vcast<VD>(acc[q]);
             buf ^= 1;
         }
         __syncthreads();  // pref / qbeg are rewritten by the next chunk
     }
     // reduce over the wave's groups (lanes tl, tl + tpw, ...), in group order
-    sub_a[wave][lane] = tot_a;
-    sub_b[wave][lane] = tot_b;
-    __builtin_amdgcn_wave_barrier();
-    if (sub == 0) {
-        for (int k = 1; k < nsub; k++) {
-            tot_a += sub_a[wave][tl + k * tpw];
-            tot_b += sub_b[wave][tl + k * tpw];
+#pragma unroll
+    for (int q = 0; q < TPL; q++) {
+        subs[wave][lane] = tot[q];
+        __builtin_amdgcn_wave_barrier();
+        if (sub == 0) {
+            VD v = tot[q];
+            for (int k = 1; k < nsub; k++) v += subs[wave][tl + k * tpw];
+            if (TPL * tl + q < 64) red[wave][TPL * tl + q] = v;
         }
-        red[wave][2 * tl] = tot_a;
-        if (2 * tl + 1 < 64) red[wave][2 * tl + 1] = tot_b;
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     if (tid < nt) {
@@ -768,14 +782,15 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
             dim3 g((unsigned)t.n_p2p_units, nrhs);
             const bool beside = st != c.stream;
             c.kbegin(st, 6);
+            constexpr int TPL = P2P_TPL;
             if (dbl)
-                k_p2p<V, R, true, HELM><<<g, P2P_BS, beside ? near_lds((const void *)k_p2p<V, R, true, HELM>) : 0,
-                                          st>>>(
+                k_p2p<V, R, true, HELM, TPL><<<g, P2P_BS,
+                                               beside ? near_lds((const void *)k_p2p<V, R, true, HELM, TPL>) : 0, st>>>(
                     t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
                     t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
             else
-                k_p2p<V, R, false, HELM><<<g, P2P_BS, beside ? near_lds((const void *)k_p2p<V, R, false, HELM>) : 0,
-                                           st>>>(
+                k_p2p<V, R, false, HELM, TPL><<<g, P2P_BS,
+                                                beside ? near_lds((const void *)k_p2p<V, R, false, HELM, TPL>) : 0, st>>>(
                     t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
                     t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
             BEM_LAUNCH_CHECK();
