@@ -686,11 +686,63 @@ void plan_fmm(bem_tree &t) {
 }
 
 // ---------------------------------------------------------------- drivers
+// The regular 7-point double layer of a unit density at every target (the
+// regular part of the free term, Eq. 2): sum over all rule points y of
+// wJ n1.(x - y) / (4 pi |x - y|^3), FP64.  Grid (target tiles of 256, point
+// splits): each block sums its share of the points for its targets into a
+// partial sum per split, and the splits are added in order afterwards (so
+// that even small meshes fill the GPU); 1/|x - y| is the hardware estimate
+// refined twice by Newton (a few ulp, like the division and square root it
+// replaces).
+__global__ void __launch_bounds__(256) k_unit_double_layer(const double *q, int64_t n_q, int64_t per_split,
+                                                           const double *t, int64_t n_tgt, double *part) {
+    __shared__ double sx[256], sy[256], sz[256], sn0[256], sn1[256], sn2[256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x, ii = min(i, n_tgt - 1);
+    const double x0 = t[ii], x1 = t[n_tgt + ii], x2 = t[2 * n_tgt + ii];
+    const int64_t j0 = (int64_t)blockIdx.y * per_split, j1 = min(n_q, j0 + per_split);
+    double acc = 0.0;
+    for (int64_t base = j0; base < j1; base += 256) {
+        const int64_t j = base + threadIdx.x;
+        if (j < j1) {
+            const double wj = q[3 * n_q + j];
+            sx[threadIdx.x] = q[j];
+            sy[threadIdx.x] = q[n_q + j];
+            sz[threadIdx.x] = q[2 * n_q + j];
+            sn0[threadIdx.x] = wj * q[4 * n_q + j];
+            sn1[threadIdx.x] = wj * q[5 * n_q + j];
+            sn2[threadIdx.x] = wj * q[6 * n_q + j];
+        }
+        __syncthreads();
+        const int m = (int)min<int64_t>(256, j1 - base);
+        for (int kk = 0; kk < m; kk++) {
+            const double d0 = x0 - sx[kk], d1 = x1 - sy[kk], d2 = x2 - sz[kk];
+            const double ir = inv_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            acc += (d0 * sn0[kk] + d1 * sn1[kk] + d2 * sn2[kk]) * (ir * ir * ir);
+        }
+        __syncthreads();
+    }
+    if (i < n_tgt) part[(int64_t)blockIdx.y * n_tgt + i] = acc;
+}
+
+__global__ void k_sum_splits(const double *part, int splits, int64_t n, double *y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int s = 0; s < splits; s++) acc += part[(int64_t)s * n + i];
+    y[i] = acc * kInv4Pi;
+}
+
 void direct_regular_unit_double_layer(bem_tree &t, double *out) {
     Ctx &c = *t.ctx;
-    dim3 g(nblocks(t.n_tgt, 256), 1);
-    k_direct<double, true, false><<<g, 256, 0, c.stream>>>(t.q64.p, t.n_q, t.q64.p + 3 * t.n_q, t.t64.p, t.n_tgt,
-                                                           0.0, out);
+    const int64_t tiles = nblocks(t.n_tgt, 256);
+    const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(nblocks(t.n_q, 256), 2048 / std::max<int64_t>(1, tiles)));
+    const int64_t per = (t.n_q + splits - 1) / splits;
+    DBuf<double> part;
+    part.alloc(&c, (size_t)splits * t.n_tgt);
+    k_unit_double_layer<<<dim3((unsigned)tiles, (unsigned)splits), 256, 0, c.stream>>>(t.q64.p, t.n_q, per, t.t64.p,
+                                                                                      t.n_tgt, part.p);
+    BEM_LAUNCH_CHECK();
+    k_sum_splits<<<nblocks(t.n_tgt, 256), 256, 0, c.stream>>>(part.p, splits, t.n_tgt, out);
     BEM_LAUNCH_CHECK();
 }
 

@@ -74,11 +74,13 @@ struct R7 {
 __device__ inline double dsq(double a0, double a1, double a2) { return (a0 * a0 + a1 * a1) + a2 * a2; }
 
 // classification of (target at x with geometric node g, sorted element se)
-__device__ inline int classify(const int32_t *se_nodes, const double *xyz, int64_t se, int32_t g, const double x[3],
-                               int *param) {
+// Per sorted element: the centroid of its corner nodes and h^2, the largest
+// squared distance from it to the element's six nodes (the element's extent
+// as the classification below uses it), [n_el][4].
+__global__ void k_elem_extent(int64_t n_el, const int32_t *se_nodes, const double *xyz, double *ext) {
+    const int64_t se = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (se >= n_el) return;
     const int32_t *en = se_nodes + 6 * se;
-    for (int a = 0; a < 6; a++)
-        if (en[a] == g) { *param = a; return 2; }
     double cm[3];
     for (int d = 0; d < 3; d++)
         cm[d] = ((xyz[3 * (int64_t)en[0] + d] + xyz[3 * (int64_t)en[1] + d]) + xyz[3 * (int64_t)en[2] + d]) / 3.0;
@@ -88,6 +90,30 @@ __device__ inline int classify(const int32_t *se_nodes, const double *xyz, int64
         double v = dsq(p[0] - cm[0], p[1] - cm[1], p[2] - cm[2]);
         if (v > h2) h2 = v;
     }
+    ext[4 * se] = cm[0];
+    ext[4 * se + 1] = cm[1];
+    ext[4 * se + 2] = cm[2];
+    ext[4 * se + 3] = h2;
+}
+
+// Per box: the largest element extent h (square root of h^2 above) over the
+// box's elements, one wave per box.
+__global__ void k_box_extent(int64_t n_box, const int64_t *eb, const int64_t *ee, const double *ext, double *hbox) {
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    double m = 0.0;
+    for (int64_t e = eb[b] + lane; e < ee[b]; e += 64) m = fmax(m, ext[4 * e + 3]);
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) hbox[b] = sqrt(m);
+}
+
+__device__ inline int classify(const int32_t *se_nodes, const double *ext, int64_t se, int32_t g, const double x[3],
+                               int *param) {
+    const int32_t *en = se_nodes + 6 * se;
+    for (int a = 0; a < 6; a++)
+        if (en[a] == g) { *param = a; return 2; }
+    const double4 e4 = *(const double4 *)(ext + 4 * se);
+    const double cm[3] = {e4.x, e4.y, e4.z}, h2 = e4.w;
     double d2 = dsq(x[0] - cm[0], x[1] - cm[1], x[2] - cm[2]);
     if (!(d2 < 4.0 * h2)) return 0;
     int d = 1;
@@ -97,12 +123,18 @@ __device__ inline int classify(const int32_t *se_nodes, const double *xyz, int64
     return 1;
 }
 
-// PASS 0: count pairs per sorted target; PASS 1: write them.
+// PASS 0: count pairs per sorted target; PASS 1: write them.  A depth-first
+// walk from the root visits the boxes in tree order; a box is skipped when the
+// target is farther from its centre than its radius plus twice its largest
+// element extent (with a relative margin), since every element the
+// classification accepts lies within twice its extent of the target and
+// within the box's radius of its centre.
 template <int PASS>
 __global__ void k_pairs(int64_t n_tgt, const double *t64, const int32_t *tperm, const int32_t *dof_node,
-                        const double *xyz, const int32_t *se_nodes, const int32_t *leaf, const int32_t *child_begin,
+                        const double *ext, const int32_t *se_nodes, const int32_t *leaf, const int32_t *child_begin,
                         const int32_t *nchild, const int64_t *eb, const int64_t *ee, const double *centre,
-                        const double *radius, int64_t *count, const int64_t *row_ptr, int32_t *pair_elem,
+                        const double *radius, const double *hbox, int64_t *count, const int64_t *row_ptr,
+                        int32_t *pair_elem,
                         int32_t *pair_info, int32_t *pair_row) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tgt) return;
@@ -116,12 +148,12 @@ __global__ void k_pairs(int64_t n_tgt, const double *t64, const int32_t *tperm, 
         int32_t X = stack[--sp];
         const double *c = centre + 3 * (int64_t)X;
         double dd = sqrt(dsq(x[0] - c[0], x[1] - c[1], x[2] - c[2]));
-        if (dd > 5.0 * radius[X] * (1.0 + 1e-9) + 1e-300) continue;
+        if (dd > (radius[X] + 2.0 * hbox[X]) * (1.0 + 1e-9) + 1e-300) continue;
         if (ee[X] == eb[X]) continue;
         if (leaf[X]) {
             for (int64_t se = eb[X]; se < ee[X]; se++) {
                 int param = 0;
-                int cls = classify(se_nodes, xyz, se, g, x, &param);
+                int cls = classify(se_nodes, ext, se, g, x, &param);
                 if (cls == 0) continue;
                 if (PASS == 1) {
                     pair_elem[w + cnt] = (int32_t)se;
@@ -254,19 +286,27 @@ void build_pairs(bem_tree &t) {
     DBuf<int64_t> cnt;
     cnt.alloc(&c, t.n_tgt);
     t.pair_ptr.alloc(&c, t.n_tgt + 1);
-    unsigned nb = nblocks(t.n_tgt, 128);
-    k_pairs<0><<<nb, 128, 0, c.stream>>>(t.n_tgt, t.t64.p, t.tperm.p, m.dof_node.p, m.xyz.p, t.se_nodes.p, t.leaf.p,
-                                         t.child_begin.p, t.nchild.p, t.eb.p, t.ee.p, t.centre.p, t.radius.p, cnt.p,
-                                         nullptr, nullptr, nullptr, nullptr);
+    DBuf<double> ext;  // element extents, as the classification uses them
+    ext.alloc(&c, 4 * (size_t)std::max<int64_t>(1, t.n_el));
+    k_elem_extent<<<nblocks(t.n_el, 256), 256, 0, c.stream>>>(t.n_el, t.se_nodes.p, m.xyz.p, ext.p);
+    BEM_LAUNCH_CHECK();
+    DBuf<double> hbox;
+    hbox.alloc(&c, (size_t)std::max<int64_t>(1, t.n_box));
+    k_box_extent<<<(unsigned)t.n_box, 64, 0, c.stream>>>(t.n_box, t.eb.p, t.ee.p, ext.p, hbox.p);
+    BEM_LAUNCH_CHECK();
+    unsigned nb = nblocks(t.n_tgt, 64);
+    k_pairs<0><<<nb, 64, 0, c.stream>>>(t.n_tgt, t.t64.p, t.tperm.p, m.dof_node.p, ext.p, t.se_nodes.p, t.leaf.p,
+                                        t.child_begin.p, t.nchild.p, t.eb.p, t.ee.p, t.centre.p, t.radius.p, hbox.p,
+                                        cnt.p, nullptr, nullptr, nullptr, nullptr);
     BEM_LAUNCH_CHECK();
     scan_exclusive<int64_t>(c, cnt.p, t.pair_ptr.p, t.n_tgt);
     t.n_pairs = read_scalar(c, t.pair_ptr.p + t.n_tgt);
     t.pair_elem.alloc(&c, t.n_pairs);
     t.pair_info.alloc(&c, t.n_pairs);
     t.pair_row.alloc(&c, t.n_pairs);
-    k_pairs<1><<<nb, 128, 0, c.stream>>>(t.n_tgt, t.t64.p, t.tperm.p, m.dof_node.p, m.xyz.p, t.se_nodes.p, t.leaf.p,
-                                         t.child_begin.p, t.nchild.p, t.eb.p, t.ee.p, t.centre.p, t.radius.p, nullptr,
-                                         t.pair_ptr.p, t.pair_elem.p, t.pair_info.p, t.pair_row.p);
+    k_pairs<1><<<nb, 64, 0, c.stream>>>(t.n_tgt, t.t64.p, t.tperm.p, m.dof_node.p, ext.p, t.se_nodes.p, t.leaf.p,
+                                        t.child_begin.p, t.nchild.p, t.eb.p, t.ee.p, t.centre.p, t.radius.p, hbox.p,
+                                        nullptr, t.pair_ptr.p, t.pair_elem.p, t.pair_info.p, t.pair_row.p);
     BEM_LAUNCH_CHECK();
     c.sync();
     t.has_pairs = true;
