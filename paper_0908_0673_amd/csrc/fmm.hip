@@ -850,11 +850,19 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         };
         // The near field depends only on the strengths and writes only its
         // own partial sums: it runs on the second stream, concurrently with
-        // the far-field passes from M2L on (started after the short upward
-        // pass, which it would otherwise crowd out), and is joined before its
-        // sums are added.  While phases are being timed everything stays on
-        // one stream.
+        // the far-field passes, and is joined before its sums are added.
+        // While phases are being timed everything stays on one stream.
         const bool overlap = t.n_p2p_items && c.timing != 1;
+        // In single precision the near field starts as soon as the strengths
+        // are in (beside the upward pass); in double precision after the
+        // upward pass, whose latency-bound kernels it would otherwise slow
+        // more than it gains (measured both ways on the 40962-DOF sphere).
+        constexpr bool early = std::is_same<R, float>::value;
+        if (overlap && early) {
+            hipStream_t side = c.side_stream();
+            c.fork();
+            near_field(side);
+        }
         // upward pass (boxes without elements keep zero moments)
         p2m_apply<V, R, XV>(t, dbl, nrhs, x, mom);
         c.mark(1);
@@ -862,7 +870,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         c.mark(2);
         // interactions
         c.mark(9);
-        if (overlap) {
+        if (overlap && !early) {
             hipStream_t side = c.side_stream();
             c.fork();
             near_field(side);
