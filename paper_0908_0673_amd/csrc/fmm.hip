@@ -827,7 +827,9 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
             BEM_HIP(hipFuncGetAttributes(&fa, fn));
             int lds = 0;
             BEM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c.device));
-            const long pad = (long)lds / P2P_PER_CU - (long)fa.sharedSizeBytes - 256;
+            // (three for the complex FP64 kernel, whose blocks are heaviest: measured)
+            const long per_cu = HELM && std::is_same<R, double>::value ? P2P_PER_CU - 1 : P2P_PER_CU;
+            const long pad = (long)lds / per_cu - (long)fa.sharedSizeBytes - 256;
             return memo[fn] = pad > 0 ? (unsigned)pad : 0u;
         };
         auto near_field = [&](hipStream_t st) {
