@@ -387,6 +387,13 @@ template <> __host__ __device__ inline cx<float> vcast<cx<float>, cx<float>>(cx<
 __device__ inline void vsincos(float x, float *s, float *c) { sincosf(x, s, c); }
 __device__ inline void vsincos(double x, double *s, double *c) { sincos(x, s, c); }
 
+// The far-field kernels (P2M, M2M, the M2L steps, L2L) raise their waves'
+// issue priority: they run beside the near-field kernel, whose VALU-bound
+// waves would otherwise take most of a CU's issue slots from their
+// latency-bound ones.  (Wave priority within a CU; the streams keep the
+// default priority.)
+__device__ inline void far_field_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // Wave-wide (64 lanes) sums by butterfly shuffles: every lane ends with the
 // same total, accumulated in a fixed order (deterministic).
 __device__ inline double wave_sum(double v) {

@@ -191,6 +191,7 @@ struct M2lArgs {
 template <class V>
 __global__ void k_m2l_canonical_moments(int64_t n_u, const int32_t *u_src, const int32_t *u_sym,
                                         const int32_t *sym_in, int P, const V *mom, V *Mc) {
+    far_field_priority();
     const int64_t u = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     if (u >= n_u) return;
     const int lane = threadIdx.x & 63;
@@ -247,6 +248,7 @@ struct M2lChunk {
 // on the first canonical moments and are not stored.
 template <class R, int NA>
 __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, const R *Mc, R *out) {
+    far_field_priority();
     using V4 = typename vec4<R>::type;
     using CK = M2lChunk<R, NA>;
     constexpr int KC = CK::KC, NCH = CK::NCH, CE = CK::CE, U4 = CK::U4, PER = CK::PER, NB = M2L_NB;
@@ -352,6 +354,7 @@ constexpr int RED_RU = 6;    // slots per wave in flight
 template <class V>
 __global__ void __launch_bounds__(256) k_m2l_reduce(const int32_t *boxes, const int64_t *iptr, const int32_t *slot_sym,
                                                     const int16_t *sym_red, int P, const V *out, V *loc) {
+    far_field_priority();
     __shared__ __align__(16) int16_t tab[NSYM * OUT_LD];
     __shared__ int32_t ssym[RED_CH];
     __shared__ V part[4][3 * 64];

@@ -92,6 +92,7 @@ __global__ void k_to_r(const double *in, int64_t n, R *out) {
 template <class V, class R, class XV>
 __global__ void k_p2m_apply(const int32_t *leaves, const int64_t *woff, const int32_t *wdof, const R *W, int P,
                             const XV *x, int64_t n_dof, V *mom, int64_t n_box) {
+    far_field_priority();
     __shared__ V xs[256];
     const int b = leaves[blockIdx.x], rhs = blockIdx.y;
     const int64_t o0 = woff[blockIdx.x], o1 = woff[blockIdx.x + 1];
@@ -171,6 +172,7 @@ template <class V, class R>
 __global__ void __launch_bounds__(256) k_m2m(const int32_t *boxes, const int32_t *child_begin, const int32_t *nchild,
                                              const uint64_t *prefix, int p, const int8_t *exps, V *mom,
                                              int64_t n_box) {
+    far_field_priority();
     constexpr int NIT = (ncoef(MAX_ORDER) + 31) / 32;
     extern __shared__ unsigned char smem[];
     const int P = ncoef(p);
@@ -238,6 +240,7 @@ template <class V, class R>
 __global__ void __launch_bounds__(256) k_l2l(const int32_t *boxes, const int32_t *child_begin, const int32_t *nchild,
                                              const uint64_t *prefix, const int64_t *tb, const int64_t *te, int p,
                                              const int8_t *exps, V *loc, int64_t n_box) {
+    far_field_priority();
     extern __shared__ unsigned char smem[];
     const int P = ncoef(p);
     V *F = (V *)smem;
