@@ -827,8 +827,8 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
             BEM_HIP(hipFuncGetAttributes(&fa, fn));
             int lds = 0;
             BEM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c.device));
-            // (three for the complex FP64 kernel, whose blocks are heaviest: measured)
-            const long per_cu = HELM && std::is_same<R, double>::value ? P2P_PER_CU - 1 : P2P_PER_CU;
+            // (three for the complex kernels, whose blocks are heavier: measured)
+            const long per_cu = HELM ? P2P_PER_CU - 1 : P2P_PER_CU;
             const long pad = (long)lds / per_cu - (long)fa.sharedSizeBytes - 256;
             return memo[fn] = pad > 0 ? (unsigned)pad : 0u;
         };
@@ -855,11 +855,11 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         // the far-field passes, and is joined before its sums are added.
         // While phases are being timed everything stays on one stream.
         const bool overlap = t.n_p2p_items && c.timing != 1;
-        // In single precision the near field starts as soon as the strengths
-        // are in (beside the upward pass); in double precision after the
-        // upward pass, whose latency-bound kernels it would otherwise slow
-        // more than it gains (measured both ways on the 40962-DOF sphere).
-        constexpr bool early = std::is_same<R, float>::value;
+        // The near field starts as soon as the strengths are in (beside the
+        // upward pass), except for the complex FP64 kernel, which starts after
+        // M2M: it slows the latency-bound upward pass more than it gains
+        // (measured both ways for all four variants on the 40962-DOF sphere).
+        constexpr bool early = !(HELM && std::is_same<R, double>::value);
         if (overlap && early) {
             hipStream_t side = c.side_stream();
             c.fork();
