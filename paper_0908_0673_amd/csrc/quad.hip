@@ -171,9 +171,33 @@ __global__ void k_pairs(int64_t n_tgt, const double *t64, const int32_t *tperm, 
 
 // One wave per pair: (accurate rule - 7-point rule) integrals of L_a G and L_a dG/dn1.
 template <bool HELM>
-__global__ void k_corr_values(int64_t n_pairs, const int32_t *pair_elem, const int32_t *pair_info,
-                              const int32_t *pair_row, const double *t64, int64_t n_tgt, const int32_t *se_nodes,
-                              const double *xyz, double k, Gauss gq, R7 r7, double *Sout, double *Kout) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HELM ? 1 : 4, HELM ? 2 : 4)))
+k_corr_values(int64_t n_pairs, const int32_t *pair_elem, const int32_t *pair_info, const int32_t *pair_row,
+              const double *t64, int64_t n_tgt, const int32_t *se_nodes, const double *xyz, double k, Gauss gq_arg,
+              R7 r7_arg, double *Sout, double *Kout) {
+    // the rules are indexed per point: kept in LDS (a by-value kernel
+    // argument indexed at run time would be copied to scratch per thread)
+    __shared__ Gauss gq;
+    __shared__ R7 r7;
+    __shared__ double V3[3][2], MID[3][2];
+    if (threadIdx.x < NG) {
+        gq.x[threadIdx.x] = gq_arg.x[threadIdx.x];
+        gq.w[threadIdx.x] = gq_arg.w[threadIdx.x];
+    }
+    if (threadIdx.x < 7) {
+        r7.s[threadIdx.x] = r7_arg.s[threadIdx.x];
+        r7.t[threadIdx.x] = r7_arg.t[threadIdx.x];
+        r7.w[threadIdx.x] = r7_arg.w[threadIdx.x];
+    }
+    if (threadIdx.x < 3) {
+        const double v3[3][2] = {{0, 0}, {1, 0}, {0, 1}};
+        const double mid[3][2] = {{0.5, 0.0}, {0.5, 0.5}, {0.0, 0.5}};
+        for (int d = 0; d < 2; d++) {
+            V3[threadIdx.x][d] = v3[threadIdx.x][d];
+            MID[threadIdx.x][d] = mid[threadIdx.x][d];
+        }
+    }
+    __syncthreads();
     int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
     if (p >= n_pairs) return;
@@ -191,8 +215,6 @@ __global__ void k_corr_values(int64_t n_pairs, const int32_t *pair_elem, const i
     int npts;
     if (cls == 2) npts = (param < 3 ? 1 : 2) * NG * NG;
     else npts = 7 << (2 * param);
-    const double V3[3][2] = {{0, 0}, {1, 0}, {0, 1}};
-    const double MID[3][2] = {{0.5, 0.0}, {0.5, 0.5}, {0.0, 0.5}};
     for (int j = lane; j < npts + 7; j += 64) {
         double s, t, w;
         if (j >= npts) {  // minus the regular rule
