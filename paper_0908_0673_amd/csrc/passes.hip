@@ -43,41 +43,53 @@ template <bool DBL>
 __global__ void k_p2m_weights(const int32_t *leaves, const int64_t *eb, const int64_t *ee, const int32_t *level,
                               const double *centre, double side, const double *q64, int64_t n_q, const double *L7,
                               const int32_t *slot, const int64_t *woff, int p, const int8_t *exps, double *W) {
+    // per element of the leaf: the powers u_d^k / k! of its 7 rule points
+    // (formed once, in LDS) and their normals and weights
+    __shared__ double pw[7][3][MAX_ORDER + 1];
+    __shared__ double qn[7][4];  // n1, n2, n3, wJ
     const int P = ncoef(p);
     const int b = leaves[blockIdx.x];
     const double rho = ldexp(side, -level[b]), irho = 1.0 / rho;
-    const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
+    const double cc[3] = {centre[3 * b], centre[3 * b + 1], centre[3 * b + 2]};
     const int64_t off = woff[blockIdx.x];
-    for (int a = threadIdx.x; a < P; a += blockDim.x) {
-        const int e0 = exps[3 * a], e1 = exps[3 * a + 1], e2 = exps[3 * a + 2];
-        for (int64_t e = eb[b]; e < ee[b]; e++) {
-            double phi[7];
-            for (int q = 0; q < 7; q++) {
-                const int64_t qi = 7 * e + q;
-                const double u[3] = {(q64[qi] - c0) * irho, (q64[n_q + qi] - c1) * irho, (q64[2 * n_q + qi] - c2) * irho};
-                // powers u_d^k / k!
-                double pw[3][MAX_ORDER + 1];
-                for (int d = 0; d < 3; d++) {
-                    pw[d][0] = 1.0;
-                    for (int k = 1; k <= p; k++) pw[d][k] = pw[d][k - 1] * u[d] / k;
-                }
-                double v;
-                if (!DBL) {
-                    v = pw[0][e0] * pw[1][e1] * pw[2][e2];
-                } else {
-                    v = 0.0;
-                    if (e0) v += q64[4 * n_q + qi] * pw[0][e0 - 1] * pw[1][e1] * pw[2][e2];
-                    if (e1) v += q64[5 * n_q + qi] * pw[0][e0] * pw[1][e1 - 1] * pw[2][e2];
-                    if (e2) v += q64[6 * n_q + qi] * pw[0][e0] * pw[1][e1] * pw[2][e2 - 1];
-                    v *= irho;
-                }
-                phi[q] = v * q64[3 * n_q + qi];
+    const int a = threadIdx.x;  // one coefficient per thread (blockDim >= P)
+    const int e0 = a < P ? exps[3 * a] : 0, e1 = a < P ? exps[3 * a + 1] : 0, e2 = a < P ? exps[3 * a + 2] : 0;
+    for (int64_t e = eb[b]; e < ee[b]; e++) {
+        __syncthreads();  // the previous element's tables have been read
+        if (threadIdx.x < 21) {
+            const int q = threadIdx.x / 3, d = threadIdx.x % 3;
+            const double u = (q64[d * n_q + 7 * e + q] - cc[d]) * irho;
+            pw[q][d][0] = 1.0;
+            for (int k = 1; k <= p; k++) pw[q][d][k] = pw[q][d][k - 1] * u / k;
+        } else if (threadIdx.x < 28) {
+            const int q = threadIdx.x - 21;
+            const int64_t qi = 7 * e + q;
+            qn[q][0] = q64[4 * n_q + qi];
+            qn[q][1] = q64[5 * n_q + qi];
+            qn[q][2] = q64[6 * n_q + qi];
+            qn[q][3] = q64[3 * n_q + qi];
+        }
+        __syncthreads();
+        if (a >= P) continue;
+        double phi[7];
+        for (int q = 0; q < 7; q++) {
+            const double *p0 = pw[q][0], *p1 = pw[q][1], *p2 = pw[q][2];
+            double v;
+            if (!DBL) {
+                v = p0[e0] * p1[e1] * p2[e2];
+            } else {
+                v = 0.0;
+                if (e0) v += qn[q][0] * p0[e0 - 1] * p1[e1] * p2[e2];
+                if (e1) v += qn[q][1] * p0[e0] * p1[e1 - 1] * p2[e2];
+                if (e2) v += qn[q][2] * p0[e0] * p1[e1] * p2[e2 - 1];
+                v *= irho;
             }
-            for (int j = 0; j < 6; j++) {
-                double w = 0.0;
-                for (int q = 0; q < 7; q++) w += L7[6 * q + j] * phi[q];
-                W[(off + slot[6 * e + j]) * P + a] += w;
-            }
+            phi[q] = v * qn[q][3];
+        }
+        for (int j = 0; j < 6; j++) {
+            double w = 0.0;
+            for (int q = 0; q < 7; q++) w += L7[6 * q + j] * phi[q];
+            W[(off + slot[6 * e + j]) * P + a] += w;
         }
     }
 }
@@ -330,17 +342,18 @@ void build_pass_tables(bem_tree &t) {
     dslot.alloc(&c, slot.size());
     dslot.upload(slot.data(), slot.size());
     const size_t nw = (size_t)pt.n_w * P;
+    const unsigned wbs = (unsigned)std::max(192, (P + 63) / 64 * 64);  // one thread per coefficient
     for (int dbl = 0; dbl < 2; dbl++) {
         pt.W64[dbl].alloc(&c, nw);
         pt.W64[dbl].zero();
         pt.W32[dbl].alloc(&c, nw);
         if (t.n_leaf_src) {
             if (dbl)
-                k_p2m_weights<true><<<(unsigned)t.n_leaf_src, 192, 0, c.stream>>>(
+                k_p2m_weights<true><<<(unsigned)t.n_leaf_src, wbs, 0, c.stream>>>(
                     t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p, t.side, t.q64.p, t.n_q, t.L7.p, dslot.p,
                     pt.woff.p, p, T.exps.p, pt.W64[dbl].p);
             else
-                k_p2m_weights<false><<<(unsigned)t.n_leaf_src, 192, 0, c.stream>>>(
+                k_p2m_weights<false><<<(unsigned)t.n_leaf_src, wbs, 0, c.stream>>>(
                     t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p, t.side, t.q64.p, t.n_q, t.L7.p, dslot.p,
                     pt.woff.p, p, T.exps.p, pt.W64[dbl].p);
             BEM_LAUNCH_CHECK();
