@@ -234,6 +234,31 @@ typedef struct {
 int bem_solve(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, int nrhs,
               const void *chi_dev, void *phi_dev, const bem_solve_opts *opts, bem_solve_info *info);
 
+/* ------------------------------------------------------------------ field
+ * Potential at points off the surface from the surface solution
+ * (Section 3.5, accelerated field evaluation; Eq. 1 with C = 1 outside the
+ * body and 0 inside):
+ *     u(x) = sum over the 7 rule points y of every element of
+ *            wJ(y) [phi(y) dG/dn1(x, y) - chi(y) G(x, y)],
+ * phi and chi interpolated from their DOF values.  The tree's moments (double
+ * layer of phi minus single layer of chi) are shifted to the root and each
+ * point descends the tree: a box far from it (|x - c| > r_C / theta, the
+ * paper's test at theta = 1, and for Helmholtz k r_C <= 0.75) contributes
+ * its order-p multipole expansion, a leaf that is not far its direct
+ * 7-point sum.  theta <= 0 selects 0.25 (about 1e-6 of the direct sum
+ * at order 8); theta > 1 gives BEM_EINVAL.  FP64 throughout; the 7-point
+ * rule is accurate for points a few element sizes away from the surface
+ * (points on it are not allowed).
+ *   phi_dev, chi_dev: [nrhs][n_dof] device, f64 (Laplace) or c128 interleaved
+ *                     (Helmholtz), DOF order of bem_mesh_dofs
+ *   pts_dev:          [n_pts][3] f64 device
+ *   u_dev:            [nrhs][n_pts] device, same value type as phi
+ * Buffers are caller-owned and read / written on the context's stream;
+ * returns after the work is complete.  BEM_EINVAL for nrhs < 1, missing or
+ * aliased buffers, k <= 0 for Helmholtz. */
+int bem_field(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, double theta, int nrhs,
+              const void *phi_dev, const void *chi_dev, int64_t n_pts, const double *pts_dev, void *u_dev);
+
 /* ------------------------------------------------------------------ serving
  * Batched / concurrent solves for many independent problems on one GPU (no
  * counterpart in the paper: a production layer around the solve above).

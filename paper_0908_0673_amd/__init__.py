@@ -29,7 +29,7 @@ BEM_PREC_FP64, BEM_PREC_MIXED = 0, 1
 
 EXPORTED = [
     "bem_ctx_create", "bem_ctx_destroy", "bem_ctx_timing", "bem_last_error", "bem_mesh_load", "bem_mesh_dofs", "bem_mesh_free",
-    "bem_tree_build", "bem_tree_export", "bem_tree_free", "bem_tree_stats_get", "bem_matvec", "bem_solve",
+    "bem_tree_build", "bem_tree_export", "bem_tree_free", "bem_tree_stats_get", "bem_matvec", "bem_solve", "bem_field",
     "bem_server_create", "bem_server_add_mesh", "bem_server_mesh_dofs", "bem_server_submit", "bem_server_poll",
     "bem_server_stats_get",
     "bem_server_destroy",
@@ -146,6 +146,7 @@ def load_library(path: str = LIB_PATH):
     L.bem_tree_stats_get.argtypes = [vp, vp, i32, dbl, ctypes.POINTER(_TreeStats)]
     L.bem_matvec.argtypes = [vp, vp, i32, dbl, i32, i32, i32, i32, vp, vp]
     L.bem_solve.argtypes = [vp, vp, i32, dbl, i32, vp, vp, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo)]
+    L.bem_field.argtypes = [vp, vp, i32, dbl, dbl, i32, vp, vp, i64, vp, vp]
     L.bem_server_create.argtypes = [ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]
     L.bem_server_add_mesh.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(_MeshOpts), ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(i64)]
@@ -357,6 +358,26 @@ def bem_solve(ctx: Context, tree: Tree, green: int, k: float, chi, phi, tol=1e-8
     if rc != 0 and (rc != BEM_ENOCONV or raise_on_noconv):
         ctx.check(rc, "bem_solve")
     return [{n: getattr(i, n) for n, _ in _SolveInfo._fields_} for i in info]
+
+
+def bem_field(ctx: Context, tree: Tree, green: int, k: float, phi, chi, pts, theta: float = 0.0):
+    """Potential at points off the surface from the surface solution:
+    u(x) = D[phi](x) - S[chi](x) (tree-accelerated, FP64; theta <= 0: 0.25).
+    phi, chi are device tensors [nrhs, n_dof]; pts a float64 device tensor
+    [n_pts, 3].  Returns u, a device tensor [nrhs, n_pts] of phi's dtype."""
+    import torch
+
+    nrhs = _check_vec(phi, tree.n_dof, green)
+    if _check_vec(chi, tree.n_dof, green) != nrhs:
+        raise ValueError("phi and chi differ in shape")
+    if not pts.is_cuda or pts.dtype != torch.float64 or not pts.is_contiguous() or pts.dim() != 2 or pts.shape[1] != 3:
+        raise ValueError("pts must be a contiguous float64 device tensor [n_pts, 3]")
+    n_pts = pts.shape[0]
+    u = torch.empty((nrhs, max(1, n_pts)), dtype=phi.dtype, device=phi.device)
+    ctx.check(ctx.L.bem_field(ctx.h, tree.h, green, float(k), float(theta), nrhs, ctypes.c_void_p(phi.data_ptr()),
+                              ctypes.c_void_p(chi.data_ptr()), n_pts, ctypes.c_void_p(pts.data_ptr()),
+                              ctypes.c_void_p(u.data_ptr())), "bem_field")
+    return u[:, :n_pts]
 
 
 class Server:

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libbem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.hip", "mesh.hip", "scan_sort.hip", "tree.hip", "geom.hip", "quad.hip", "fmm.hip", "passes.hip", "m2l.hip", "solve.hip",
-           "server.hip"]
+           "server.hip", "field.hip"]
 NO_CONTRACT = {"tree.hip", "quad.hip"}
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]

@@ -290,4 +290,21 @@ int bem_solve(bem_ctx *ctx, const bem_tree *tc, bem_green g, double k, int nrhs,
     return status;
 }
 
+int bem_field(bem_ctx *ctx, const bem_tree *tc, bem_green g, double k, double theta, int nrhs, const void *phi_dev,
+              const void *chi_dev, int64_t n_pts, const double *pts_dev, void *u_dev) {
+    if (!ctx || !tc) return BEM_EINVAL;
+    bem_tree *t = const_cast<bem_tree *>(tc);
+    return guard(&ctx->c, [&] {
+        BEM_REQUIRE(t->ctx == &ctx->c, BEM_ESTATE, "tree belongs to another context");
+        BEM_REQUIRE(nrhs >= 1 && nrhs <= 65535, BEM_EINVAL, "nrhs must be in 1..65535");
+        BEM_REQUIRE(n_pts >= 0 && n_pts <= 0x7fffffff, BEM_EINVAL, "n_pts must be in 0..2^31-1");
+        BEM_REQUIRE(phi_dev && chi_dev && (n_pts == 0 || (pts_dev && u_dev)), BEM_EINVAL, "missing buffer");
+        BEM_REQUIRE(u_dev != phi_dev && u_dev != chi_dev, BEM_EINVAL, "u must not alias phi or chi");
+        BEM_REQUIRE(g == BEM_LAPLACE || g == BEM_HELMHOLTZ, BEM_EINVAL, "unknown Green's function");
+        BEM_REQUIRE(g != BEM_HELMHOLTZ || (k > 0.0 && std::isfinite(k)), BEM_EINVAL, "Helmholtz needs k > 0");
+        BEM_REQUIRE(!(theta > 1.0) && !std::isnan(theta), BEM_EINVAL, "theta must be at most 1");
+        bem::field(*t, g, g == BEM_HELMHOLTZ ? k : 0.0, theta, nrhs, phi_dev, chi_dev, n_pts, pts_dev, u_dev);
+    });
+}
+
 }  // extern "C"

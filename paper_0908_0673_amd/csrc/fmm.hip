@@ -686,6 +686,21 @@ void plan_fmm(bem_tree &t) {
 }
 
 // ---------------------------------------------------------------- drivers
+void rule_shapes(bem_tree &t) {
+    if (t.L7.p) return;
+    // shape functions at the 7 rule points
+    std::vector<double> L7(42);
+    double rs[7], rt[7], rw[7];
+    rule7(rs, rt, rw);
+    for (int qq = 0; qq < 7; qq++) {
+        double S_ = rs[qq], T_ = rt[qq], Z = 1.0 - S_ - T_;
+        double L[6] = {Z * (2 * Z - 1), S_ * (2 * S_ - 1), T_ * (2 * T_ - 1), 4 * Z * S_, 4 * S_ * T_, 4 * T_ * Z};
+        for (int a = 0; a < 6; a++) L7[6 * qq + a] = L[a];
+    }
+    t.L7.alloc(t.ctx, 42);
+    t.L7.upload(L7.data(), 42);
+}
+
 // The regular 7-point double layer of a unit density at every target (the
 // regular part of the free term, Eq. 2): sum over all rule points y of
 // wJ n1.(x - y) / (4 pi |x - y|^3), FP64.  Grid (target tiles of 256, point
@@ -763,19 +778,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
     if (method == BEM_DIRECT) t.work.yacc.ensure(&c, sizeof(V) * nt * nrhs);
     V *s = (V *)t.work.strength.p;
     V *yacc = (V *)t.work.yacc.p;
-    if (!t.L7.p) {
-        // shape functions at the 7 rule points
-        std::vector<double> L7(42);
-        double rs[7], rt[7], rw[7];
-        rule7(rs, rt, rw);
-        for (int qq = 0; qq < 7; qq++) {
-            double S_ = rs[qq], T_ = rt[qq], Z = 1.0 - S_ - T_;
-            double L[6] = {Z * (2 * Z - 1), S_ * (2 * S_ - 1), T_ * (2 * T_ - 1), 4 * Z * S_, 4 * S_ * T_, 4 * T_ * Z};
-            for (int a = 0; a < 6; a++) L7[6 * qq + a] = L[a];
-        }
-        t.L7.alloc(&c, 42);
-        t.L7.upload(L7.data(), 42);
-    }
+    rule_shapes(t);
     if (method == BEM_FMM) {
         fmm_tables(t);
         plan_fmm(t);

@@ -1,6 +1,8 @@
 // Green's functions of Eqs. (1a/b) and the element map, as device functions.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace bem {
@@ -30,6 +32,66 @@ __device__ inline void green_helmholtz(R r2, R rn, R k, cx<R> *G, cx<R> *dG) {
     R kr = k * Rr;
     R f = g * rn * inv * inv;
     *dG = cx<R>(f * (cs + kr * sn), f * (sn - kr * cs));
+}
+
+// Derivatives d^g G(r) for |g| <= H (graded multi-index order, exps[3 * i]
+// the exponents of index i), Laplace or Helmholtz with wavenumber kk: the
+// radial functions G^(h)(R), h = 0..H, then d^g G^(h) for |g| <= H - h with h
+// descending, each level from the previous one (Section 3.3, Eq. 12).  All
+// threads of the block take part; A and B (ncoef(H) values each) and g (H +
+// 1 values) are LDS scratch; returns the buffer holding the result.
+__host__ __device__ constexpr int deriv_count(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+__device__ inline int deriv_index(int a, int b, int c) {
+    const int n = a + b + c;
+    return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
+}
+template <bool HELM>
+__device__ typename std::conditional<HELM, cx<double>, double>::type *derivs_block(
+    const double r[3], double kk, int H, const int8_t *exps, typename std::conditional<HELM, cx<double>, double>::type *A,
+    typename std::conditional<HELM, cx<double>, double>::type *B,
+    typename std::conditional<HELM, cx<double>, double>::type *g) {
+    using V = typename std::conditional<HELM, cx<double>, double>::type;
+    const int tid = threadIdx.x;
+    const double R2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2], Rr = sqrt(R2);
+    if (tid == 0) {
+        if constexpr (!HELM) {
+            g[0] = kInv4Pi / Rr;
+            for (int h = 0; h < H; h++) g[h + 1] = g[h] * (-(double)(2 * h + 1) / R2);
+        } else {
+            double sn, cs;
+            sincos(kk * Rr, &sn, &cs);
+            const double f = kInv4Pi / Rr, kr = kk * Rr, f3 = f / R2;
+            g[0] = V(f * cs, f * sn);
+            if (H >= 1) g[1] = V(f3 * (-cs - kr * sn), f3 * (kr * cs - sn));
+            for (int h = 1; h < H; h++) g[h + 1] = (g[h] * (double)(2 * h + 1) + g[h - 1] * (kk * kk)) * (-1.0 / R2);
+        }
+        A[0] = g[H];
+    }
+    __syncthreads();
+    V *prev = A, *cur = B;
+    for (int h = H - 1; h >= 0; h--) {
+        const int m = deriv_count(H - h);
+        for (int i = tid; i < m; i += blockDim.x) {
+            V v;
+            if (i == 0) {
+                v = g[h];
+            } else {
+                int al[3] = {exps[3 * i], exps[3 * i + 1], exps[3 * i + 2]};
+                int d = al[0] > 0 ? 0 : (al[1] > 0 ? 1 : 2);
+                al[d]--;
+                v = prev[deriv_index(al[0], al[1], al[2])] * r[d];
+                if (al[d] > 0) {
+                    int ad = al[d];
+                    al[d]--;
+                    v += prev[deriv_index(al[0], al[1], al[2])] * (double)ad;
+                }
+            }
+            cur[i] = v;
+        }
+        __syncthreads();
+        V *t = prev; prev = cur; cur = t;
+    }
+    return prev;
 }
 
 // Quadratic 6-node triangle: shape functions and their s, t derivatives.

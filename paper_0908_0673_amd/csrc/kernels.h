@@ -208,6 +208,7 @@ void build_free_term(bem_tree &t);
 
 // fmm.hip
 void direct_regular_unit_double_layer(bem_tree &t, double *out);
+void rule_shapes(bem_tree &t);  // t.L7: the six shape functions at the 7 rule points
 void fmm_tables(bem_tree &t);
 void plan_fmm(bem_tree &t);
 void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int nrhs, const void *x, void *y);
@@ -217,7 +218,7 @@ void build_pass_tables(bem_tree &t);
 template <class V, class R, class XV>
 void p2m_apply(bem_tree &t, bool dbl, int nrhs, const XV *x, V *mom);
 template <class V, class R>
-void m2m_apply(bem_tree &t, int nrhs, V *mom);
+void m2m_apply(bem_tree &t, int nrhs, V *mom, int top = -1);  // levels down to top (default: m2m_top)
 template <class V, class R>
 void l2l_apply(bem_tree &t, int nrhs, V *loc);
 
@@ -227,6 +228,10 @@ template <class V, class R>
 void m2l_prepare(bem_tree &t, M2lPlan &pl);
 template <class V, class R>
 void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc);
+
+// field.hip
+void field(bem_tree &t, int green, double k, double theta, int nrhs, const void *phi, const void *chi, int64_t n_pts,
+           const double *pts, void *u);
 
 // solve.hip
 int solve(bem_tree &t, int green, double k, int nrhs, const void *chi, void *phi, const bem_solve_opts &o,

@@ -76,8 +76,8 @@ template <> struct vec4<float> { using type = floatx4; };
 template <> struct vec4<double> { using type = doublex4; };
 
 // ---------------------------------------------------------------- class tables (FP64)
-// One block per class: G^(h)(R), h = 0..H, then d^g G^(h) for |g| <= H - h,
-// h descending (Section 3.3, Eq. 12), at the normalised separation.
+// One block per class: the derivatives of G up to order H at the class's
+// normalised separation (greens.h, Section 3.3, Eq. 12).
 template <bool HELM>
 __global__ void k_class_derivs(const double *rbar, const double *kbar, int H, const int8_t *exps, double *D64) {
     using V = typename std::conditional<HELM, cx<double>, double>::type;
@@ -86,52 +86,13 @@ __global__ void k_class_derivs(const double *rbar, const double *kbar, int H, co
     V *A = (V *)smem, *B = A + P2, *g = B + P2;
     const int c = blockIdx.x, tid = threadIdx.x;
     const double r[3] = {rbar[3 * c], rbar[3 * c + 1], rbar[3 * c + 2]};
-    const double R2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2], Rr = sqrt(R2);
-    if (tid == 0) {
-        if constexpr (!HELM) {
-            g[0] = kInv4Pi / Rr;
-            for (int h = 0; h < H; h++) g[h + 1] = g[h] * (-(double)(2 * h + 1) / R2);
-        } else {
-            const double kk = kbar[c];
-            double sn, cs;
-            sincos(kk * Rr, &sn, &cs);
-            const double f = kInv4Pi / Rr, kr = kk * Rr, f3 = f / R2;
-            g[0] = V(f * cs, f * sn);
-            if (H >= 1) g[1] = V(f3 * (-cs - kr * sn), f3 * (kr * cs - sn));
-            for (int h = 1; h < H; h++) g[h + 1] = (g[h] * (double)(2 * h + 1) + g[h - 1] * (kk * kk)) * (-1.0 / R2);
-        }
-        A[0] = g[H];
-    }
-    __syncthreads();
-    V *prev = A, *cur = B;
-    for (int h = H - 1; h >= 0; h--) {
-        const int m = ncoef(H - h);
-        for (int i = tid; i < m; i += blockDim.x) {
-            V v;
-            if (i == 0) {
-                v = g[h];
-            } else {
-                int al[3] = {exps[3 * i], exps[3 * i + 1], exps[3 * i + 2]};
-                int d = al[0] > 0 ? 0 : (al[1] > 0 ? 1 : 2);
-                al[d]--;
-                v = prev[midx(al[0], al[1], al[2])] * r[d];
-                if (al[d] > 0) {
-                    int ad = al[d];
-                    al[d]--;
-                    v += prev[midx(al[0], al[1], al[2])] * (double)ad;
-                }
-            }
-            cur[i] = v;
-        }
-        __syncthreads();
-        V *t = prev; prev = cur; cur = t;
-    }
+    const V *D = derivs_block<HELM>(r, HELM ? kbar[c] : 0.0, H, exps, A, B, g);
     for (int i = tid; i < P2; i += blockDim.x) {
         if constexpr (HELM) {
-            D64[2 * ((int64_t)c * P2 + i)] = prev[i].re;
-            D64[2 * ((int64_t)c * P2 + i) + 1] = prev[i].im;
+            D64[2 * ((int64_t)c * P2 + i)] = D[i].re;
+            D64[2 * ((int64_t)c * P2 + i) + 1] = D[i].im;
         } else {
-            D64[(int64_t)c * P2 + i] = prev[i];
+            D64[(int64_t)c * P2 + i] = D[i];
         }
     }
 }

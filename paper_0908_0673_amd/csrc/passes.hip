@@ -379,11 +379,11 @@ void p2m_apply(bem_tree &t, bool dbl, int nrhs, const XV *x, V *mom) {
 }
 
 template <class V, class R>
-void m2m_apply(bem_tree &t, int nrhs, V *mom) {
+void m2m_apply(bem_tree &t, int nrhs, V *mom, int top) {
     Ctx &c = *t.ctx;
     const int p = t.order, P = t.tables->P;
     const size_t sh = sizeof(V) * 8 * P + sizeof(R) * 2 * (MAX_ORDER + 1);
-    for (int l = t.max_level - 1; l >= t.m2m_top; l--) {
+    for (int l = t.max_level - 1; l >= (top < 0 ? t.m2m_top : top); l--) {
         int64_t nb = (int64_t)t.m2m_level_boxes[l].size();
         if (!nb) continue;
         dim3 g((unsigned)nb, (P + 31) / 32, nrhs);
@@ -410,7 +410,7 @@ void l2l_apply(bem_tree &t, int nrhs, V *loc) {
 
 #define BEM_PASSES(V, R, XV)                                                   \
     template void p2m_apply<V, R, XV>(bem_tree &, bool, int, const XV *, V *); \
-    template void m2m_apply<V, R>(bem_tree &, int, V *);                       \
+    template void m2m_apply<V, R>(bem_tree &, int, V *, int);                  \
     template void l2l_apply<V, R>(bem_tree &, int, V *);
 BEM_PASSES(double, double, double)
 BEM_PASSES(float, float, double)

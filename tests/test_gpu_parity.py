@@ -389,3 +389,92 @@ def test_kernel_event_timing_modes():
         assert e.value.code == bem.BEM_EINVAL
     finally:
         ctx.timing(0)
+
+
+# ---------------------------------------------------------------- field evaluation
+def _field_points(rng, n_out, n_in):
+    d = rng.standard_normal((n_out + n_in, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    r = np.concatenate([rng.uniform(1.4, 4.0, n_out), rng.uniform(0.0, 0.6, n_in)])
+    far = np.array([[40.0, -30.0, 20.0]])  # beyond the root: its expansion alone
+    return np.concatenate([d * r[:, None], far])
+
+
+@pytest.mark.parametrize("green,k", [(0, 0.0), (1, 2.0)])
+def test_field_matches_oracle_layer_potentials(green, k):
+    """bem_field (Section 3.5, tree-accelerated) against the oracle's direct
+    layer potentials D[phi] - S[chi] at points outside and inside the body and
+    one far beyond the root, for seeded phi and chi: within the expansion
+    tolerance (1e-6 of the largest value), two right-hand sides at once equal
+    to one at a time, bit for bit."""
+    import torch
+
+    bem = _bem()
+    m, ctx, mesh, tree, om, ot = setup("perturbed")
+    rng = np.random.default_rng(35 + green)
+    pts = _field_points(rng, 48, 16)
+    phi = rng.standard_normal((2, om.n_dof))
+    chi = rng.standard_normal((2, om.n_dof))
+    if green:
+        phi = phi + 1j * rng.standard_normal((2, om.n_dof))
+        chi = chi + 1j * rng.standard_normal((2, om.n_dof))
+    pd = torch.tensor(pts, dtype=torch.float64, device="cuda:0")
+    u2 = bem.bem_field(ctx, tree, green, k, to_dev(phi, green == 1), to_dev(chi, green == 1), pd).cpu().numpy()
+    for r in range(2):
+        u1 = bem.bem_field(ctx, tree, green, k, to_dev(phi[r:r + 1], green == 1), to_dev(chi[r:r + 1], green == 1),
+                           pd).cpu().numpy()[0]
+        assert np.array_equal(u1, u2[r])
+        ref = om.layer_potential(pts, green, k, sigma_d=phi[r]) - om.layer_potential(pts, green, k, sigma_s=chi[r])
+        if not green:
+            ref = ref.real
+        err = np.abs(u1 - ref).max() / np.abs(ref).max()
+        say(f"  field green={green} rhs {r}: max error {err:.2e} (largest |u| {np.abs(ref).max():.3e})")
+        assert err < 1e-6
+    # the truncation error falls with theta as the order-8 expansion predicts
+    errs = []
+    for th in (0.6, 0.4, 0.25, 0.15):
+        u = bem.bem_field(ctx, tree, green, k, to_dev(phi[:1], green == 1), to_dev(chi[:1], green == 1), pd,
+                          theta=th).cpu().numpy()[0]
+        ref = om.layer_potential(pts, green, k, sigma_d=phi[0]) - om.layer_potential(pts, green, k, sigma_s=chi[0])
+        errs.append(np.abs(u - (ref if green else ref.real)).max() / np.abs(ref).max())
+    say(f"  field green={green}: error at theta 0.6 / 0.4 / 0.25 / 0.15: {errs}")
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+
+
+def test_field_of_solved_point_source_problem():
+    """End to end: solve the exterior Neumann problem for a point source
+    inside the sphere, then evaluate the field outside: it is the source's
+    own field 1/(4 pi |x - xs|) (analytic), up to the discretisation."""
+    import torch
+
+    bem = _bem()
+    m, ctx, mesh, tree, om, ot = setup("sphere5120")
+    xs = np.array([0.1, 0.2, 0.3])
+    phi_a, chi = analytic.point_source(om.dof_xyz, om.dof_normal, xs=xs)
+    chid = to_dev(chi.real, False)
+    phid = torch.zeros_like(chid)
+    info = bem.bem_solve(ctx, tree, 0, 0.0, chid, phid, tol=1e-10)
+    assert info[0]["status"] == 0
+    pts = _field_points(np.random.default_rng(5), 32, 0)
+    u = bem.bem_field(ctx, tree, 0, 0.0, phid, chid, torch.tensor(pts, dtype=torch.float64, device="cuda:0"))
+    u = u.cpu().numpy()[0]
+    want = 1.0 / (4 * np.pi * np.linalg.norm(pts - xs, axis=1))
+    err = np.abs(u - want).max() / np.abs(want).max()
+    say(f"  solved field vs analytic: {err:.2e}")
+    assert err < 2e-5
+
+
+def test_field_rejects_bad_arguments():
+    import torch
+
+    bem = _bem()
+    m, ctx, mesh, tree, om, ot = setup("sphere320")
+    x = to_dev(np.zeros(om.n_dof), False)
+    pts = torch.zeros((4, 3), dtype=torch.float64, device="cuda:0") + 2.0
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_field(ctx, tree, 1, 0.0, to_dev(np.zeros(om.n_dof, complex), True), to_dev(np.zeros(om.n_dof, complex), True), pts)
+    assert e.value.code == bem.BEM_EINVAL
+    with pytest.raises(ValueError):
+        bem.bem_field(ctx, tree, 0, 0.0, x, x, pts.float())
+    u = bem.bem_field(ctx, tree, 0, 0.0, x, x, pts)  # zero densities: zero field
+    assert torch.count_nonzero(u) == 0
