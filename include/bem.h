@@ -71,6 +71,11 @@ typedef enum { BEM_DIRECT = 0, BEM_FMM = 1 } bem_method;
  * the combination stay double. */
 typedef enum { BEM_PREC_FP64 = 0, BEM_PREC_MIXED = 1 } bem_precision;
 
+/* Krylov method of bem_solve.  BEM_KRYLOV_GMRES: restarted GMRES with
+ * classical Gram-Schmidt applied twice.  BEM_KRYLOV_BICGSTAB: BiCGSTAB, the
+ * paper's solver (Section 2.1), two products per step. */
+typedef enum { BEM_KRYLOV_GMRES = 0, BEM_KRYLOV_BICGSTAB = 1 } bem_krylov;
+
 /* Device memory provider.  alloc returns device memory of at least `bytes`
  * usable on `stream` (NULL on failure); free releases it.  Passing NULL for
  * the allocator makes the library use hipMalloc / hipFree. */
@@ -204,10 +209,13 @@ int bem_matvec(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, bem_op
 /* ------------------------------------------------------------------ solve */
 typedef struct {
     double tol;          /* relative residual |b - A x| / |b| to reach; 0 -> 1e-8 */
-    int restart;         /* GMRES restart length; 0 -> 50 */
-    int max_restarts;    /* cycles per inner solve; 0 -> 100 */
-    bem_precision precision; /* FP64: GMRES on the FP64 FMM operator.  MIXED: the same
-                                GMRES, whose steps use the mixed product once the relative
+    int restart;         /* GMRES: restart length, 0 -> 50, at most 90.  BiCGSTAB: steps
+                            per cycle, 0 -> 50; a cycle ends early once the updated
+                            residual meets tol, and every cycle starts from the FP64
+                            residual b - A x */
+    int max_restarts;    /* cycles per solve; 0 -> 100 */
+    bem_precision precision; /* FP64: the Krylov method on the FP64 FMM operator.  MIXED: the
+                                same method, whose steps use the mixed product once the relative
                                 residual r satisfies inner_tol * r <= tol / 10 (relaxed
                                 inexact Krylov); every residual that decides convergence
                                 (each cycle start and the end) uses the FP64 product */
@@ -215,19 +223,22 @@ typedef struct {
                             from the FP64 product; 0 -> 1e-6 */
     int max_refine;      /* unused (0) */
     bem_method method;   /* operator used (BEM_FMM unless set) */
+    bem_krylov krylov;   /* BEM_KRYLOV_GMRES (0) or BEM_KRYLOV_BICGSTAB */
 } bem_solve_opts;
 
 typedef struct {
     int iterations;      /* total inner Krylov iterations */
-    int refinements;     /* MIXED: GMRES cycles restarted from an FP64 residual above tol */
+    int refinements;     /* MIXED: cycles restarted from an FP64 residual above tol */
     int matvecs;         /* operator applications, FP64 and mixed */
     double residual;     /* final |b - A x| / |b| with the FP64 operator */
     int status;          /* BEM_OK or BEM_ENOCONV */
 } bem_solve_info;
 
 /* Solves Eq. (1) for phi given chi, for each of nrhs right-hand sides
- * (Section 2.1; GMRES in place of the paper's BiCGSTAB): b = -S chi with the
- * FP64 operator, then GMRES(restart) from x0 = 0.  chi_dev and phi_dev are
+ * (Section 2.1): b = -S chi with the FP64 operator, then GMRES(restart)
+ * (default) or BiCGSTAB, the paper's solver, from x0 = 0.  GMRES advances the
+ * right-hand sides in lock step with one batched product per step; BiCGSTAB
+ * solves them one after the other.  chi_dev and phi_dev are
  * device buffers of nrhs * n_dof values; info is a host array of nrhs.
  * Returns BEM_ENOCONV (with phi and info written) if a right-hand side did
  * not converge. */

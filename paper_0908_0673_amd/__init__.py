@@ -26,6 +26,7 @@ BEM_LAPLACE, BEM_HELMHOLTZ = 0, 1
 BEM_OP_S, BEM_OP_K, BEM_OP_A, BEM_OP_RHS = 0, 1, 2, 3
 BEM_DIRECT, BEM_FMM = 0, 1
 BEM_PREC_FP64, BEM_PREC_MIXED = 0, 1
+BEM_KRYLOV_GMRES, BEM_KRYLOV_BICGSTAB = 0, 1
 
 EXPORTED = [
     "bem_ctx_create", "bem_ctx_destroy", "bem_ctx_timing", "bem_last_error", "bem_mesh_load", "bem_mesh_dofs", "bem_mesh_free",
@@ -76,7 +77,7 @@ class _TreeStats(ctypes.Structure):
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_restarts", ctypes.c_int),
                 ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
-                ("method", ctypes.c_int)]
+                ("method", ctypes.c_int), ("krylov", ctypes.c_int)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -346,12 +347,13 @@ def bem_matvec(ctx: Context, tree: Tree, green: int, k: float, op: int, method: 
 
 
 def bem_solve(ctx: Context, tree: Tree, green: int, k: float, chi, phi, tol=1e-8, restart=50, max_restarts=100,
-              precision=BEM_PREC_FP64, inner_tol=0.0, max_refine=0, method=BEM_FMM, raise_on_noconv=False):
+              precision=BEM_PREC_FP64, inner_tol=0.0, max_refine=0, method=BEM_FMM, raise_on_noconv=False,
+              krylov=BEM_KRYLOV_GMRES):
     """Solves c.phi - K phi = -S chi; returns a list of per-rhs info dicts."""
     nrhs = _check_vec(chi, tree.n_dof, green)
     if _check_vec(phi, tree.n_dof, green) != nrhs:
         raise ValueError("chi and phi differ in shape")
-    opts = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method)
+    opts = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method, krylov)
     info = (_SolveInfo * nrhs)()
     rc = ctx.L.bem_solve(ctx.h, tree.h, green, float(k), nrhs, ctypes.c_void_p(chi.data_ptr()),
                          ctypes.c_void_p(phi.data_ptr()), ctypes.byref(opts), info)
@@ -391,7 +393,7 @@ class Server:
 
     def __init__(self, device=0, lanes=4, hbm_budget=32 << 30, max_batch_rhs=32, tol=1e-8, restart=50,
                  max_restarts=100, precision=BEM_PREC_FP64, inner_tol=0.0, max_refine=0, method=BEM_FMM,
-                 B=32, order=8, theta=0.6, kappa=0.0, max_depth=21):
+                 krylov=BEM_KRYLOV_GMRES, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21):
         self.L = load_library()
         import torch
 
@@ -400,7 +402,7 @@ class Server:
         o = _ServerOpts()
         o.device, o.lanes, o.hbm_budget, o.max_batch_rhs = device, lanes, int(hbm_budget), max_batch_rhs
         o.tree = _TreeOpts(B, order, theta, kappa, max_depth, 0.0)
-        o.solve = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method)
+        o.solve = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method, krylov)
         h = ctypes.c_void_p()
         rc = self.L.bem_server_create(ctypes.byref(o), ctypes.byref(h))
         if rc != 0:

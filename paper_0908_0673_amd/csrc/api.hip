@@ -281,7 +281,9 @@ int bem_solve(bem_ctx *ctx, const bem_tree *tc, bem_green g, double k, int nrhs,
         if (o.max_restarts <= 0) o.max_restarts = 100;
         if (!(o.inner_tol > 0.0)) o.inner_tol = 1e-6;
         if (!opts) o.method = BEM_FMM;
-        BEM_REQUIRE(o.restart <= 90, BEM_EINVAL, "restart must be <= 90");
+        BEM_REQUIRE(o.krylov == BEM_KRYLOV_GMRES || o.krylov == BEM_KRYLOV_BICGSTAB, BEM_EINVAL,
+                    "unknown Krylov method");
+        BEM_REQUIRE(o.krylov != BEM_KRYLOV_GMRES || o.restart <= 90, BEM_EINVAL, "GMRES restart must be <= 90");
         BEM_REQUIRE(o.method == BEM_FMM || o.method == BEM_DIRECT, BEM_EINVAL, "unknown method");
         status = bem::solve(*t, g, g == BEM_HELMHOLTZ ? k : 0.0, nrhs, chi_dev, phi_dev, o, info);
     });

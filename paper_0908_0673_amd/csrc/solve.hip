@@ -235,6 +235,61 @@ __global__ void k_sub(const V *a, const V *b, V *out, int64_t n) {
     if (e < n) out[e] = a[e] - b[e];
 }
 
+// ---------------------------------------------------------------- BiCGSTAB
+// Scalars on the device, in the slots written by the reductions:
+//   [0] rho = (rh, r)  [1] |r|^2   [2] (rh, v)   [3] |v|^2 (unused)
+//   [4] (t, s)         [5] |s|^2   [6] |t|^2     [8] rho of the previous step
+//   [9] alpha          [10] omega
+// (inner products conjugate their first argument).  Each vector kernel forms
+// the scalars it needs itself, so no host round trip sits inside a step.
+enum { BI_RHO = 0, BI_V = 2, BI_TS = 4, BI_TT = 6, BI_RHO0 = 8, BI_ALPHA = 9, BI_OMEGA = 10, BI_NS = 12 };
+
+__device__ inline double vdiv(double a, double b) { return a / b; }
+__device__ inline cx<double> vdiv(cx<double> a, cx<double> b) { return a * conj(b) * (1.0 / abs2(b)); }
+
+// p = r + beta (p - omega v), beta = (rho / rho0) (alpha / omega)
+template <class V>
+__global__ void k_bicg_p(const V *sc, const V *r, const V *v, V *p, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
+    if (e >= n) return;
+    const V beta = vdiv(sc[BI_RHO], sc[BI_RHO0]) * vdiv(sc[BI_ALPHA], sc[BI_OMEGA]);
+    p[e] = r[e] + beta * (p[e] - sc[BI_OMEGA] * v[e]);
+}
+
+// alpha = rho / (rh, v); s = r - alpha v; the step's rho becomes rho0
+template <class V>
+__global__ void k_bicg_s(V *sc, const V *r, const V *v, V *s, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
+    const V alpha = vdiv(sc[BI_RHO], sc[BI_V]);
+    if (e < n) s[e] = r[e] - alpha * v[e];
+    if (e == 0) {
+        sc[BI_ALPHA] = alpha;
+        sc[BI_RHO0] = sc[BI_RHO];
+    }
+}
+
+// omega = (t, s) / |t|^2; x += alpha p + omega s; r = s - omega t
+template <class V>
+__global__ void k_bicg_x(V *sc, const V *p, const V *s, const V *t, V *x, V *r, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
+    const V omega = sc[BI_TS] * (1.0 / re_part(sc[BI_TT]));
+    if (e < n) {
+        x[e] = x[e] + sc[BI_ALPHA] * p[e] + omega * s[e];
+        r[e] = s[e] - omega * t[e];
+    }
+    if (e == 0) sc[BI_OMEGA] = omega;
+}
+
+template <class V>
+__global__ void k_bicg_reset(V *sc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int i = 0; i < BI_NS; i++) sc[i] = V(0.0);
+        sc[BI_RHO0] = V(1.0);
+        sc[BI_ALPHA] = V(1.0);
+        sc[BI_OMEGA] = V(1.0);
+    }
+}
+
 template <class V>
 struct Krylov {
     Ctx &c;
@@ -483,6 +538,80 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
     }
 }
 
+// BiCGSTAB (van der Vorst 1992; the paper's Krylov solver, Section 2.1) for
+// one right-hand side from x = 0.  Each cycle starts from the FP64 residual
+// r = b - A x (r itself at the first), runs up to `steps` steps of two
+// products each and ends early once the recursively updated residual meets
+// tol; a cycle whose FP64 residual then misses tol restarts from x (counted
+// in restarts).  Products switch to the mixed precision below mixed_below
+// as in gmres().  Inner products reduce in a fixed order; the host reads |r|
+// once per step.
+template <class V, class F>
+void bicgstab(Krylov<V> &K, F &&apply, const V *b, V *x, double tol, int max_cycles, int steps, double mixed_below,
+              int *iters, int *matvecs, int *restarts, double *relres, int *status) {
+    Ctx &c = K.c;
+    const int64_t n = K.n;
+    const unsigned nb = nblocks(n, RBS);
+    V *r = K.vec(0), *rh = K.vec(1), *p = K.vec(2), *v = K.vec(3), *s = K.vec(4), *tv = K.vec(5), *tmp = K.tmp.p;
+    DBuf<V> sc;
+    sc.alloc(&c, BI_NS);
+    std::vector<Krylov<V> *> Kv{&K};
+    const double bnorm = norms(Kv, std::vector<const V *>{b})[0];
+    *status = BEM_ENOCONV;
+    if (bnorm == 0.0) {
+        zero_fill(c, x, sizeof(V) * n);
+        *relres = 0.0;
+        *status = BEM_OK;
+        return;
+    }
+    for (int cycle = 0;; cycle++) {
+        // r = b - A x in FP64 (b itself while x = 0)
+        if (cycle == 0) {
+            BEM_HIP(hipMemcpyAsync(r, b, sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
+        } else {
+            apply(x, tmp, 1, BEM_PREC_FP64);
+            (*matvecs)++;
+            k_sub<V><<<nb, RBS, 0, c.stream>>>(b, tmp, r, n);
+            BEM_LAUNCH_CHECK();
+        }
+        BEM_HIP(hipMemcpyAsync(rh, r, sizeof(V) * n, hipMemcpyDeviceToDevice, c.stream));
+        k_bicg_reset<V><<<1, 1, 0, c.stream>>>(sc.p);
+        BEM_LAUNCH_CHECK();
+        zero_fill(c, p, sizeof(V) * n);
+        zero_fill(c, v, sizeof(V) * n);
+        K.rows(rh, 1, r, sc.p + BI_RHO, nullptr, K.d_out + 2);  // rho and |r|^2
+        c.sync();
+        double rel = std::sqrt(K.h_out[2]) / bnorm;
+        *relres = rel;
+        if (rel <= tol) {
+            *status = BEM_OK;
+            return;
+        }
+        if (cycle >= max_cycles || !(rel == rel)) return;  // out of cycles, or the iterate is not finite
+        if (cycle > 0) (*restarts)++;
+        for (int it = 0; it < steps; it++) {
+            const int prec = rel <= mixed_below ? BEM_PREC_MIXED : BEM_PREC_FP64;
+            k_bicg_p<V><<<nb, RBS, 0, c.stream>>>(sc.p, r, v, p, n);
+            BEM_LAUNCH_CHECK();
+            apply(p, v, 1, prec);
+            K.rows(rh, 1, v, sc.p + BI_V, nullptr, nullptr);
+            k_bicg_s<V><<<nb, RBS, 0, c.stream>>>(sc.p, r, v, s, n);
+            BEM_LAUNCH_CHECK();
+            apply(s, tv, 1, prec);
+            *matvecs += 2;
+            K.rows(tv, 1, s, sc.p + BI_TS, nullptr, nullptr);
+            K.rows(nullptr, 0, tv, sc.p + BI_TT, nullptr, nullptr);
+            k_bicg_x<V><<<nb, RBS, 0, c.stream>>>(sc.p, p, s, tv, x, r, n);
+            BEM_LAUNCH_CHECK();
+            K.rows(rh, 1, r, sc.p + BI_RHO, nullptr, K.d_out + 2);
+            c.sync();
+            (*iters)++;
+            rel = std::sqrt(K.h_out[2]) / bnorm;
+            if (!(rel == rel) || rel <= tol) break;  // converged, or broke down (NaN): check the FP64 residual
+        }
+    }
+}
+
 template <class V>
 int solve_t(bem_tree &t, int green, double k, int nrhs, const V *chi, V *phi, const bem_solve_opts &o,
             bem_solve_info *info) {
@@ -522,8 +651,17 @@ int solve_t(bem_tree &t, int green, double k, int nrhs, const V *chi, V *phi, co
     // mixed product (inner_tol bounds its relative deviation from the FP64 one)
     const bool mixed = o.precision == BEM_PREC_MIXED && method == BEM_FMM;
     const double mixed_below = mixed ? 0.1 * o.tol / o.inner_tol : -1.0;
-    gmres(K, A, sin.p, sout.p, bv, xv, o.tol, o.max_restarts, mixed_below, iters.data(), mv.data(), rs.data(),
-          res.data(), st.data(), true);
+    if (o.krylov == BEM_KRYLOV_BICGSTAB) {
+        // one right-hand side after the other, each with its own vectors
+        for (int r = 0; r < nrhs; r++) {
+            Krylov<V> Kb(c, n, 6);
+            bicgstab(Kb, A, bv[r], xv[r], o.tol, o.max_restarts, o.restart, mixed_below, &iters[r], &mv[r], &rs[r],
+                     &res[r], &st[r]);
+        }
+    } else {
+        gmres(K, A, sin.p, sout.p, bv, xv, o.tol, o.max_restarts, mixed_below, iters.data(), mv.data(), rs.data(),
+              res.data(), st.data(), true);
+    }
     for (int r = 0; r < nrhs; r++) {
         inf[r].iterations += iters[r];
         inf[r].matvecs += mv[r];

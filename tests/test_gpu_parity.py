@@ -343,6 +343,97 @@ def test_solve_reports_noconv():
     assert info[0]["status"] == bem.BEM_ENOCONV and info[0]["residual"] > 1e-14
 
 
+# ---------------------------------------------------------------- BiCGSTAB (the paper's solver)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_bicgstab_point_source_sphere(prec):
+    """BiCGSTAB to an FP64 residual of 1e-8 reaches the dense oracle's
+    solution and the analytic one as GMRES does, and agrees with the GMRES
+    solution to the tolerance (the system is of the second kind, so a
+    residual of 1e-8 bounds the error to about that)."""
+    bem = _bem()
+    m, ctx, mesh, tree, om, ot = setup("sphere320")
+    phi, chi = analytic.point_source(om.dof_xyz, om.dof_normal)
+    S, K, c = om.assemble()
+    x_or = np.linalg.solve(np.diag(c) - K, -S @ chi).real
+    chid = to_dev(chi, False)
+    phid = chid.clone()
+    info = bem.bem_solve(ctx, tree, 0, 0.0, chid, phid, tol=1e-8, precision=prec, krylov=bem.BEM_KRYLOV_BICGSTAB)
+    say(f"  bicgstab prec={prec} info={info}")
+    assert info[0]["status"] == 0 and info[0]["residual"] <= 1e-8
+    x = phid.cpu().numpy()[0]
+    assert rel(x, x_or) < 2e-6
+    assert np.sqrt(np.mean((x - phi.real) ** 2)) < 1e-5
+    pg = chid.clone()
+    bem.bem_solve(ctx, tree, 0, 0.0, chid, pg, tol=1e-8, precision=prec)
+    say(f"    vs GMRES {rel(x, pg.cpu().numpy()[0]):.2e}")
+    assert rel(x, pg.cpu().numpy()[0]) < 1e-7
+
+
+def test_bicgstab_helmholtz_rigid_sphere():
+    """Complex BiCGSTAB (inner products conjugate the first argument) on the
+    rigid sphere at ka = 2, mixed precision: the series solution as for
+    GMRES, and the GMRES solution to the tolerance."""
+    bem = _bem()
+    ka = 2.0
+    m, ctx, mesh, tree, om, ot = setup("sphere1280", kappa=3.0, k_hint=ka)
+    inc, chi = analytic.plane_wave(om.dof_xyz, om.dof_normal, ka)
+    chid = to_dev(chi, True)
+    phid = chid.clone()
+    info = bem.bem_solve(ctx, tree, 1, ka, chid, phid, tol=1e-8, precision=bem.BEM_PREC_MIXED,
+                         krylov=bem.BEM_KRYLOV_BICGSTAB)
+    say(f"  helmholtz bicgstab info={info}")
+    assert info[0]["status"] == 0 and info[0]["residual"] <= 1e-8
+    x = phid.cpu().numpy()[0]
+    ref = analytic.rigid_sphere_total(ka, om.dof_xyz[:, 2] / np.linalg.norm(om.dof_xyz, axis=1))
+    assert relmax(x + inc, ref) < 2e-3
+    pg = chid.clone()
+    bem.bem_solve(ctx, tree, 1, ka, chid, pg, tol=1e-8, precision=bem.BEM_PREC_MIXED)
+    say(f"    vs GMRES {rel(x, pg.cpu().numpy()[0]):.2e}")
+    assert rel(x, pg.cpu().numpy()[0]) < 1e-7
+
+
+@pytest.mark.parametrize("green", [0, 1])
+def test_bicgstab_multi_rhs_equals_single_solves(green):
+    """Right-hand sides given together are solved one after the other with
+    the same kernels, so each equals its solve alone bit for bit."""
+    bem = _bem()
+    k = 2.0 if green else 0.0
+    m, ctx, mesh, tree, om, ot = setup("sphere320")
+    rng = np.random.default_rng(43)
+    chi = rng.standard_normal((2, om.n_dof))
+    if green:
+        chi = chi + 1j * rng.standard_normal((2, om.n_dof))
+    chi[1] *= 1e-3
+    chid = to_dev(chi, bool(green))
+    phid = chid.clone()
+    kw = dict(tol=1e-8, precision=bem.BEM_PREC_MIXED, krylov=bem.BEM_KRYLOV_BICGSTAB)
+    infos = bem.bem_solve(ctx, tree, green, k, chid, phid, **kw)
+    together = phid.cpu().numpy()
+    for r in range(2):
+        c1 = chid[r:r + 1].clone()
+        p1 = c1.clone()
+        i1 = bem.bem_solve(ctx, tree, green, k, c1, p1, **kw)[0]
+        assert i1 == infos[r], (r, i1, infos[r])
+        assert np.array_equal(p1.cpu().numpy()[0], together[r]), r
+
+
+def test_bicgstab_reports_noconv_and_rejects_bad_method():
+    bem = _bem()
+    m, ctx, mesh, tree, om, ot = setup("sphere320")
+    _, chi = analytic.point_source(om.dof_xyz, om.dof_normal)
+    chid = to_dev(chi, False)
+    phid = chid.clone()
+    info = bem.bem_solve(ctx, tree, 0, 0.0, chid, phid, tol=1e-14, restart=2, max_restarts=1,
+                         krylov=bem.BEM_KRYLOV_BICGSTAB)
+    say(f"  bicgstab noconv info={info}")
+    assert info[0]["status"] == bem.BEM_ENOCONV and info[0]["residual"] > 1e-14
+    # one cycle of two steps; the right-hand side and the closing FP64 residual
+    assert info[0]["iterations"] == 2 and info[0]["matvecs"] == 1 + 2 * 2 + 1
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_solve(ctx, tree, 0, 0.0, chid, phid, krylov=7, raise_on_noconv=True)
+    assert e.value.code == bem.BEM_EINVAL
+
+
 # ---------------------------------------------------------------- errors
 def test_invalid_arguments():
     bem = _bem()
