@@ -12,6 +12,8 @@ Parity status per function (pins live in ``tests/test_oracle_*.py``):
   S, K, free term                                        pinned (solid angles, Green's identity, sphere potentials)
   tree, radii, lists                                     pinned (invariants, brute-force coverage)
   derivatives, shifts, local expansions, FMM product     pinned (harmonicity, closed forms, exact |r|^2 kernel, direct sum)
+  level-dependent order of the FMM product               pinned (one interaction level equals the uniform
+                                                         leaf order; error ordering in L_min)
   GMRES                                                  pinned (numpy.linalg.solve)
 """
 
@@ -58,7 +60,7 @@ def lib():
         L.or_tree_export.argtypes = [vp] + [vp] * 9
         L.or_tree_free.argtypes = [vp]
         L.or_fmm_matvec.argtypes = [vp, vp, vp, vp, vp, i64, i64, ctypes.c_int, ctypes.c_double,
-                                    ctypes.c_int, ctypes.c_int, vp, vp]
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
         L.or_index_dofs.argtypes = [vp, i64, vp, i64, ctypes.c_double, vp, vp, vp, vp]
         L.or_assemble.argtypes = [vp, vp, vp, vp, i64, i64, ctypes.c_int, ctypes.c_double, vp, vp, vp]
         L.or_matvec_rows.argtypes = [vp, vp, vp, vp, i64, i64, ctypes.c_int, ctypes.c_double,
@@ -207,12 +209,14 @@ class OracleTree:
             pass
         self._h = None
 
-    def fmm_matvec(self, x, op, green=LAPLACE, k=0.0, order=8):
-        """The fast matrix product of Section 3.6 (plain FP64 loops)."""
+    def fmm_matvec(self, x, op, green=LAPLACE, k=0.0, order=8, order_min=0):
+        """The fast matrix product of Section 3.6 (plain FP64 loops).  With
+        order_min > 0 the order depends on the level as in Section 3.6:
+        L_l = min(order, order_min + max_level - l)."""
         m = self.mesh
         x = _c(x, np.complex128)
         y = np.zeros(m.n_dof, np.complex128)
-        lib().or_fmm_matvec(self._h, *m._args(), green, float(k), int(order), op, _p(x), _p(y))
+        lib().or_fmm_matvec(self._h, *m._args(), green, float(k), int(order), int(order_min), op, _p(x), _p(y))
         return y
 
 

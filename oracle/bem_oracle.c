@@ -1023,9 +1023,16 @@ static double binom(int n, int k) { return fact(n) / (fact(k) * fact(n - k)); }
 
 static double ipow(double x, int n) { double r = 1.0; for (int i = 0; i < n; i++) r *= x; return r; }
 
+/* Section 3.6: the expansion order may depend on the level, L_l =          */
+/* min(L_max, L_min + l_max - l) with l_max the deepest level of the tree;  */
+/* order_min <= 0 keeps L_max everywhere.  Every expansion of a box at      */
+/* level l has order L_l: moments and locals past it are never formed, so   */
+/* a parent's moments come from its children's truncated moments (Eq. 10)   */
+/* and a child's locals are the parent's truncated to the child's order     */
+/* (Eq. 11); a translation (Eq. 9) maps order L_source to order L_target.   */
 int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const int32_t *elem_dofs,
                   const int32_t *dof_node, int64_t n_el, int64_t n_dof, int green, double k,
-                  int order, int op, const double *x_in, double *y_out)
+                  int order, int order_min, int op, const double *x_in, double *y_out)
 {
     const otree_t *T = h;
     const cplx *x = (const cplx *)x_in;
@@ -1056,13 +1063,23 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
         }
     }
     cplx *M = calloc(T->n_box * P, sizeof(cplx)), *F = calloc(T->n_box * P, sizeof(cplx));
+    /* number of coefficients of each box's expansions */
+    int lmax = 0;
+    for (int64_t b = 0; b < T->n_box; b++)
+        if (T->box[b].level > lmax) lmax = T->box[b].level;
+    int *nc = malloc(T->n_box * sizeof *nc);
+    for (int64_t b = 0; b < T->n_box; b++) {
+        int Lb = p;
+        if (order_min > 0 && order_min + lmax - T->box[b].level < p) Lb = order_min + lmax - T->box[b].level;
+        nc[b] = ncoef(Lb);
+    }
     /* P2M at leaves */
     for (int64_t b = 0; b < T->n_box; b++) {
         const obox_t *B_ = &T->box[b];
         if (!B_->leaf) continue;
         for (int64_t q = 7 * B_->eb; q < 7 * B_->ee; q++) {
             double d[3] = {qy[q][0] - B_->c[0], qy[q][1] - B_->c[1], qy[q][2] - B_->c[2]};
-            for (int i = 0; i < P; i++) {
+            for (int i = 0; i < nc[b]; i++) {
                 int a = ex[i][0], bb = ex[i][1], c = ex[i][2];
                 if (!dbl) {
                     M[b * P + i] += qs[q] * ipow(d[0], a) * ipow(d[1], bb) * ipow(d[2], c);
@@ -1082,7 +1099,7 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
         int64_t pb = C->parent;
         const obox_t *Pa = &T->box[pb];
         double d[3] = {C->c[0] - Pa->c[0], C->c[1] - Pa->c[1], C->c[2] - Pa->c[2]};
-        for (int i = 0; i < P; i++) {
+        for (int i = 0; i < nc[pb]; i++) {
             int a = ex[i][0], bb = ex[i][1], c = ex[i][2];
             cplx acc = 0.0;
             for (int q = 0; q <= a; q++)
@@ -1101,10 +1118,10 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
         if (b > 0) {
             const obox_t *Pa = &T->box[B_->parent];
             double d[3] = {B_->c[0] - Pa->c[0], B_->c[1] - Pa->c[1], B_->c[2] - Pa->c[2]};
-            for (int i = 0; i < P; i++) {
+            for (int i = 0; i < nc[b]; i++) {
                 int a = ex[i][0], bb = ex[i][1], c = ex[i][2];
                 cplx acc = 0.0;
-                for (int j = 0; j < P; j++) {
+                for (int j = 0; j < nc[B_->parent]; j++) {
                     int a2 = ex[j][0], b2 = ex[j][1], c2 = ex[j][2];
                     if (a2 < a || b2 < bb || c2 < c) continue;
                     acc += binom(a2, a) * binom(b2, bb) * binom(c2, c) * ipow(d[0], a2 - a) *
@@ -1118,9 +1135,9 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
             const obox_t *S_ = &T->box[T->inter_idx[j]];
             double r[3] = {B_->c[0] - S_->c[0], B_->c[1] - S_->c[1], B_->c[2] - S_->c[2]};
             derivs(green, k, r, 2 * p, D);
-            for (int i = 0; i < P; i++) {
+            for (int i = 0; i < nc[b]; i++) {
                 cplx acc = 0.0;
-                for (int a = 0; a < P; a++) {
+                for (int a = 0; a < nc[T->inter_idx[j]]; a++) {
                     int g0 = ex[i][0] + ex[a][0], g1 = ex[i][1] + ex[a][1], g2 = ex[i][2] + ex[a][2];
                     double sg = ((ex[a][0] + ex[a][1] + ex[a][2]) & 1) ? -1.0 : 1.0;
                     acc += sg * D[midx(g0, g1, g2)] * M[T->inter_idx[j] * P + a] / fa[a];
@@ -1141,7 +1158,7 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
             const double *xi = xyz + 3 * (int64_t)dof_node[i];
             double d[3] = {xi[0] - B_->c[0], xi[1] - B_->c[1], xi[2] - B_->c[2]};
             cplx acc = 0.0;
-            for (int j = 0; j < P; j++)
+            for (int j = 0; j < nc[b]; j++)
                 acc += F[b * P + j] * ipow(d[0], ex[j][0]) * ipow(d[1], ex[j][1]) * ipow(d[2], ex[j][2]);
             for (int64_t j = T->near_ptr[b]; j < T->near_ptr[b + 1]; j++) {
                 const obox_t *S_ = &T->box[T->near_idx[j]];
@@ -1186,7 +1203,7 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
         else y[i] = yo[i];
     }
     (void)m;
-    free(c); free(yo); free(fa); free(M); free(F); free(qy); free(qn); free(qs); free(ex);
+    free(c); free(yo); free(fa); free(M); free(F); free(nc); free(qy); free(qn); free(qs); free(ex);
     return 0;
 }
 

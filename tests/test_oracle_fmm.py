@@ -297,3 +297,85 @@ def test_fmm_helmholtz_to_direct(fmm_case):
         yd = om.matvec_rows(x, op, oracle.HELMHOLTZ, k)
         yf = T.fmm_matvec(x, op, oracle.HELMHOLTZ, k, order=8)
         assert np.linalg.norm(yf - yd) / np.linalg.norm(yd) < 1e-5
+
+
+# ---------------------------------------------------------------- level-dependent order (Section 3.6)
+def _quadrature_sources(om, x):
+    """Points, normals and strengths wJ sum_a L_a x_a of the 7-point rule on
+    every element (element id order)."""
+    s, t, w = oracle.rule(0)
+    ys, ns, qs = [], [], []
+    for e in range(om.n_el):
+        X6 = om.xyz[om.elem[e]]
+        for q in range(len(w)):
+            y, n, J = oracle.elem_point(X6, s[q], t[q])
+            L, _, _ = oracle.shape(s[q], t[q])
+            ys.append(y)
+            ns.append(n)
+            qs.append(w[q] * J * np.dot(L, x[om.elem_dofs[e]]))
+    return np.array(ys), np.array(ns), np.array(qs)
+
+
+@pytest.mark.parametrize("op", [oracle.OP_S_REG, oracle.OP_K_REG])
+def test_level_order_drops_exactly_the_truncated_terms(fmm_case, op):
+    """G = |r|^2 with L_min = 1: only the deepest level has order 1, every
+    coarser level order >= 2, which the kernel needs.  Then the fast product
+    differs from the direct sum by exactly the terms the order-1 expansions
+    drop.  A source in a deepest-level leaf S keeps its charge and dipole
+    about c_S but loses its second moment, whose field is the constant
+    sigma |y - c_S|^2 (single layer) or 2 sigma n . (y - c_S) (double layer);
+    a target in a deepest-level leaf T loses the quadratic part of its far
+    field about c_T, Q_far |x - c_T|^2, where Q_far is the total far strength
+    (single layer; the double layer's far field is linear in x).  With
+    L_min = 2 every order is >= 2 and the product equals the direct sum."""
+    om, x = fmm_case
+    T = oracle.OracleTree(om, B=16, theta=0.7)
+    lmax = int(T.level.max())
+    dbl = op == oracle.OP_K_REG
+    y, n, qs = _quadrature_sources(om, x)
+    leaf_of_q = np.zeros(len(qs), np.int64)
+    for b in np.nonzero(T.leaf)[0]:
+        for se in range(T.eb[b], T.ee[b]):
+            leaf_of_q[7 * T.eperm[se]:7 * T.eperm[se] + 7] = b
+    c_q = T.centre[leaf_of_q]
+    drop_src = 2.0 * qs * np.einsum("ij,ij->i", n, y - c_q) if dbl else qs * np.sum((y - c_q) ** 2, 1)
+    deep_src = T.level[leaf_of_q] == lmax
+    expect = om.matvec_rows(x, op, green=oracle.R2)
+    n_deep_targets = 0
+    for b in np.nonzero(T.leaf)[0]:
+        if T.te[b] == T.tb[b]:
+            continue
+        # near boxes (leaves, or larger boxes beside a coarse leaf) are summed directly
+        far = np.ones(len(qs), bool)
+        for s in T.near_idx[T.near_ptr[b]:T.near_ptr[b + 1]]:
+            for se in range(T.eb[s], T.ee[s]):
+                far[7 * T.eperm[se]:7 * T.eperm[se] + 7] = False
+        for tpos in range(T.tb[b], T.te[b]):
+            i = T.tperm[tpos]
+            xi = om.xyz[om.dof_node[i]]
+            expect[i] -= np.sum(drop_src[far & deep_src])
+            if T.level[b] == lmax and not dbl:
+                expect[i] -= np.sum(qs[far]) * np.sum((xi - T.centre[b]) ** 2)
+                n_deep_targets += 1
+    assert T.inter_idx.size and (dbl or n_deep_targets)
+    yf = T.fmm_matvec(x, op, green=oracle.R2, order=5, order_min=1)
+    yd = om.matvec_rows(x, op, green=oracle.R2)
+    assert np.linalg.norm(yf - yd) / np.linalg.norm(yd) > 1e-6  # the truncation is visible
+    assert np.linalg.norm(yf - expect) / np.linalg.norm(yd) < 1e-13
+    y2 = T.fmm_matvec(x, op, green=oracle.R2, order=5, order_min=2)
+    assert np.linalg.norm(y2 - yd) / np.linalg.norm(yd) < 1e-13
+
+
+def test_level_order_error_ordering(fmm_case):
+    """Laplace: order_min >= order is the uniform product bit for bit, and
+    the error against the direct product falls as L_min rises (Section 4's
+    reference runs use L_min = 3 and 4 with L_max = 8)."""
+    om, x = fmm_case
+    T = oracle.OracleTree(om, B=16, theta=0.7)
+    yd = om.matvec_rows(x, oracle.OP_A)
+    y8 = T.fmm_matvec(x, oracle.OP_A, order=8)
+    assert np.array_equal(T.fmm_matvec(x, oracle.OP_A, order=8, order_min=8), y8)
+    errs = [np.linalg.norm(T.fmm_matvec(x, oracle.OP_A, order=8, order_min=m) - yd) / np.linalg.norm(yd)
+            for m in (2, 3, 4)]
+    e8 = np.linalg.norm(y8 - yd) / np.linalg.norm(yd)
+    assert errs[0] > errs[1] > errs[2] > e8
