@@ -106,6 +106,8 @@ def main():
                     help="serving measurement on the longer stream (200 requests, 2000-40000 triangles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--protocol", action="store_true",
+                    help="run only the paper's own test protocol (sphere series, level-dependent order, BiCGSTAB)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -114,6 +116,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.protocol:
+        paper_protocol()
         return
 
     import torch
@@ -289,6 +294,78 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def paper_protocol():
+    """Section 4's test run the paper's way: a unit point source at
+    (0.1, 0.2, 0.3) inside spheres of 162 ... 40962 nodes (second-order
+    elements), the Neumann data given and the surface potential recovered by
+    BiCGSTAB; FMM with the level-dependent order L_l = min(8, L_min + l_max -
+    l) at L_min = 3 and 4, the leaf size growing with N as in the tables
+    (B = 8 ... 128 nodes, here B/2 elements: a quadratic mesh has two nodes
+    per element) and the paper's separation test (theta = 1).  Laplace as in
+    Table 2, Helmholtz k = 2 as in Table 6.  One JSON line per row: N, B,
+    the rms error against the exact potential (absolute and relative), setup
+    and solve times, the peak device bytes of the context and the FP64
+    product time.  Rows with L_min = 8 are the uniform order-8 product on the
+    same tree, for comparison."""
+    import torch
+
+    import bem_inputs
+    import paper_0908_0673_amd as bem
+
+    xs = np.array([0.1, 0.2, 0.3])
+    for green, k, table in ((0, 0.0, "table2_laplace"), (1, 2.0, "table6_helmholtz_k2")):
+        for s, Bp in zip(range(1, 6), (8, 16, 32, 64, 128)):
+            m = bem_inputs.icosphere(s)
+            for omin in (3, 4, 0):
+                t0 = time.perf_counter()
+                ctx = bem.Context(0)
+                mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
+                tree = bem.bem_tree_build(ctx, mesh, B=max(4, Bp // 2), order=8, theta=1.0, order_min=omin,
+                                          k_hint=k)
+                d = mesh.dofs()
+                r = d["dof_xyz"] - xs[None, :]
+                R = np.linalg.norm(r, axis=1)
+                e = np.exp(1j * k * R)
+                phi = e / (4 * np.pi * R)
+                chi = (1j * k * R - 1.0) * e / (4 * np.pi * R ** 2) * np.einsum("ij,ij->i", r, d["dof_normal"]) / R
+                dt = torch.complex128 if green else torch.float64
+                chid = torch.tensor(chi if green else chi.real, dtype=dt, device="cuda:0")[None].contiguous()
+                y = torch.empty_like(chid)
+                bem.bem_matvec(ctx, tree, green, k, bem.BEM_OP_A, bem.BEM_FMM, bem.BEM_PREC_FP64, chid, y)
+                torch.cuda.synchronize()
+                t_setup = time.perf_counter() - t0
+                phid = torch.empty_like(chid)
+                best, info = 1e9, None
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    info = bem.bem_solve(ctx, tree, green, k, chid, phid, tol=1e-8,
+                                         krylov=bem.BEM_KRYLOV_BICGSTAB)[0]
+                    torch.cuda.synchronize()
+                    best = min(best, time.perf_counter() - t1)
+                x = phid.cpu().numpy()[0]
+                ref = phi if green else phi.real
+                err = float(np.sqrt(np.mean(np.abs(x - ref) ** 2)))
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for _ in range(20):
+                    bem.bem_matvec(ctx, tree, green, k, bem.BEM_OP_A, bem.BEM_FMM, bem.BEM_PREC_FP64, chid, y)
+                torch.cuda.synchronize()
+                ms_prod = (time.perf_counter() - t1) / 20 * 1e3
+                row = {"protocol": table, "N": int(mesh.n_dof), "n_elem": int(m.n_elem), "B_nodes": Bp,
+                       "B_elems": max(4, Bp // 2), "L_min": omin if omin else 8, "L_max": 8, "theta": 1.0,
+                       "max_level": int(tree.export()["level"].max()),
+                       "eps_rms": err, "eps_rms_rel": err / float(np.sqrt(np.mean(np.abs(ref) ** 2))),
+                       "t_setup_s": t_setup, "t_solve_s": best, "iterations": info["iterations"],
+                       "matvecs": info["matvecs"], "residual": info["residual"], "status": info["status"],
+                       "device_mib_peak": ctx.device_bytes()[1] / 2 ** 20, "ms_per_fp64_product": ms_prod}
+                print(json.dumps(row), flush=True)
+                tree.close()
+                mesh.close()
+                ctx.close()
+                del chid, phid, y
 
 
 def _boundary_data(dofs, req):

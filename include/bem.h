@@ -123,6 +123,13 @@ const char *bem_last_error(const bem_ctx *ctx);
 #define BEM_NPHASE 11
 int bem_ctx_timing(bem_ctx *ctx, int enable, double *ms, int64_t *launches);
 
+/* Device bytes the library holds through this context for meshes, trees and
+ * work buffers (live), and the largest such figure since the context was
+ * created or since the last call with reset_peak = 1 (peak: the memory a
+ * setup and solve needed, the counterpart of the paper's memory columns).
+ * Freed blocks kept for reuse are not counted.  Either pointer may be NULL. */
+int bem_ctx_device_bytes(bem_ctx *ctx, int reset_peak, int64_t *live, int64_t *peak);
+
 /* ------------------------------------------------------------------ mesh */
 typedef struct {
     double edge_angle_deg; /* normals closer than this share a DOF (Section 2.3); 0 -> 30 */
@@ -159,6 +166,9 @@ typedef struct {
     double kappa;           /* Helmholtz only: also require k (r1 + r2) <= kappa; 0 or inf -> none */
     int max_depth;          /* deepest level, <= 21; 0 -> 21 */
     double k_hint;          /* wavenumber the kappa rule uses when building the lists */
+    int order_min;          /* L_min of the level-dependent order (Section 3.6): boxes at level l
+                               use order min(order, order_min + l_max - l), l_max the deepest
+                               level; 0 (or >= order) -> `order` at every level */
 } bem_tree_opts;
 
 /* Builds the octree over the mesh on the device (Section 3.1): element keys

@@ -29,7 +29,7 @@ BEM_PREC_FP64, BEM_PREC_MIXED = 0, 1
 BEM_KRYLOV_GMRES, BEM_KRYLOV_BICGSTAB = 0, 1
 
 EXPORTED = [
-    "bem_ctx_create", "bem_ctx_destroy", "bem_ctx_timing", "bem_last_error", "bem_mesh_load", "bem_mesh_dofs", "bem_mesh_free",
+    "bem_ctx_create", "bem_ctx_destroy", "bem_ctx_timing", "bem_ctx_device_bytes", "bem_last_error", "bem_mesh_load", "bem_mesh_dofs", "bem_mesh_free",
     "bem_tree_build", "bem_tree_export", "bem_tree_free", "bem_tree_stats_get", "bem_matvec", "bem_solve", "bem_field",
     "bem_server_create", "bem_server_add_mesh", "bem_server_mesh_dofs", "bem_server_submit", "bem_server_poll",
     "bem_server_stats_get",
@@ -57,7 +57,8 @@ class _MeshOpts(ctypes.Structure):
 
 class _TreeOpts(ctypes.Structure):
     _fields_ = [("max_elems_per_leaf", ctypes.c_int), ("order", ctypes.c_int), ("theta", ctypes.c_double),
-                ("kappa", ctypes.c_double), ("max_depth", ctypes.c_int), ("k_hint", ctypes.c_double)]
+                ("kappa", ctypes.c_double), ("max_depth", ctypes.c_int), ("k_hint", ctypes.c_double),
+                ("order_min", ctypes.c_int)]
 
 
 class _TreeView(ctypes.Structure):
@@ -134,6 +135,7 @@ def load_library(path: str = LIB_PATH):
     L.bem_ctx_destroy.argtypes = [vp]
     L.bem_ctx_destroy.restype = None
     L.bem_ctx_timing.argtypes = [vp, i32, vp, vp]
+    L.bem_ctx_device_bytes.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.bem_last_error.argtypes = [vp]
     L.bem_last_error.restype = ctypes.c_char_p
     L.bem_mesh_load.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(_MeshOpts), ctypes.POINTER(vp)]
@@ -218,6 +220,13 @@ class Context:
         self.check(self.L.bem_ctx_timing(self.h, int(mode), _np_ptr(ms), _np_ptr(n)), "bem_ctx_timing")
         return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(self.PHASES)}
 
+    def device_bytes(self, reset_peak=False):
+        """(live, peak) device bytes held by the library through this context."""
+        live, peak = ctypes.c_int64(), ctypes.c_int64()
+        self.check(self.L.bem_ctx_device_bytes(self.h, int(reset_peak), ctypes.byref(live), ctypes.byref(peak)),
+                   "bem_ctx_device_bytes")
+        return live.value, peak.value
+
     def close(self):
         if getattr(self, "h", None):
             self.L.bem_ctx_destroy(self.h)
@@ -269,9 +278,10 @@ class Mesh:
 
 
 class Tree:
-    def __init__(self, ctx: Context, mesh: Mesh, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21, k_hint=0.0):
+    def __init__(self, ctx: Context, mesh: Mesh, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21, k_hint=0.0,
+                 order_min=0):
         self.ctx, self.mesh = ctx, mesh
-        opts = _TreeOpts(B, order, theta, kappa, max_depth, k_hint)
+        opts = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min)
         h = ctypes.c_void_p()
         ctx.check(ctx.L.bem_tree_build(ctx.h, mesh.h, ctypes.byref(opts), ctypes.byref(h)), "bem_tree_build")
         self.h = h
@@ -393,7 +403,7 @@ class Server:
 
     def __init__(self, device=0, lanes=4, hbm_budget=32 << 30, max_batch_rhs=32, tol=1e-8, restart=50,
                  max_restarts=100, precision=BEM_PREC_FP64, inner_tol=0.0, max_refine=0, method=BEM_FMM,
-                 krylov=BEM_KRYLOV_GMRES, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21):
+                 krylov=BEM_KRYLOV_GMRES, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21, order_min=0):
         self.L = load_library()
         import torch
 
@@ -401,7 +411,7 @@ class Server:
             raise RuntimeError("no GPU visible: the library runs on gfx950 only")
         o = _ServerOpts()
         o.device, o.lanes, o.hbm_budget, o.max_batch_rhs = device, lanes, int(hbm_budget), max_batch_rhs
-        o.tree = _TreeOpts(B, order, theta, kappa, max_depth, 0.0)
+        o.tree = _TreeOpts(B, order, theta, kappa, max_depth, 0.0, order_min)
         o.solve = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method, krylov)
         h = ctypes.c_void_p()
         rc = self.L.bem_server_create(ctypes.byref(o), ctypes.byref(h))

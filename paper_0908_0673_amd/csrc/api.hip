@@ -88,6 +88,15 @@ int bem_ctx_timing(bem_ctx *ctx, int enable, double *ms, int64_t *launches) {
     return BEM_OK;
 }
 
+int bem_ctx_device_bytes(bem_ctx *ctx, int reset_peak, int64_t *live, int64_t *peak) {
+    if (!ctx) return BEM_EINVAL;
+    Ctx &c = ctx->c;
+    if (live) *live = (int64_t)c.bytes_live.load();
+    if (peak) *peak = (int64_t)c.bytes_peak.load();
+    if (reset_peak) c.bytes_peak = c.bytes_live.load();
+    return BEM_OK;
+}
+
 const char *bem_last_error(const bem_ctx *ctx) { return ctx ? ctx->c.err.c_str() : g_err.c_str(); }
 
 int bem_mesh_load(bem_ctx *ctx, const double *node_xyz, int64_t n_nodes, const int32_t *elem_nodes, int64_t n_elem,
@@ -163,7 +172,10 @@ int bem_tree_build(bem_ctx *ctx, const bem_mesh *mesh, const bem_tree_opts *opts
             t->kappa = opts->kappa;
             if (opts->max_depth > 0) t->max_depth = opts->max_depth;
             t->k_hint = opts->k_hint;
+            t->order_min = opts->order_min;
         }
+        BEM_REQUIRE(t->order_min >= 0, BEM_EINVAL, "order_min must be >= 0");
+        if (t->order_min >= t->order) t->order_min = 0;
         BEM_REQUIRE(t->order >= 1 && t->order <= 8, BEM_EUNSUPPORTED, "expansion order must be 1..8");
         BEM_REQUIRE(t->max_depth <= bem::MAXLEV, BEM_EINVAL, "max_depth must be <= 21");
         BEM_REQUIRE(t->theta > 0.0 && t->theta <= 1.0, BEM_EINVAL, "theta must be in (0, 1]");

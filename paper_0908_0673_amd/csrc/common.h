@@ -164,6 +164,7 @@ struct Ctx {
     // the same work buffers, and a context serving requests beside others
     // must not stall them.
     std::atomic<size_t> bytes_live{0};
+    std::atomic<size_t> bytes_peak{0};  // largest bytes_live since creation or the last reset
     std::atomic<size_t> cached{0};
     size_t cache_limit = (size_t)1 << 30;
     std::unordered_map<void *, size_t> sizes;
@@ -199,7 +200,8 @@ struct Ctx {
             }
         }
         sizes[p] = bytes;
-        bytes_live += bytes;
+        const size_t live = bytes_live += bytes;
+        if (live > bytes_peak) bytes_peak = live;
         return p;
     }
     void dfree(void *p) {

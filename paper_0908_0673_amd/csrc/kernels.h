@@ -55,6 +55,9 @@ struct M2lTasks {
     int cols = 0;
     int64_t n_task = 0;
     DBuf<int32_t> task_class, task_first, task_count;
+    // level-dependent order only: contraction steps of 4 and row tiles of 16
+    // that cover the largest source and target orders of each task's pairs
+    DBuf<int32_t> task_kt, task_mt;
 };
 
 // Canonical displacement classes of the interaction pairs for one (Green, k),
@@ -72,6 +75,8 @@ struct M2lPlan {
     int64_t n_u = 0;                  // used (source box, symmetry) combinations
     DBuf<int32_t> u_src, u_sym;
     std::vector<int32_t> h_class_order, h_class_first, h_class_count;  // classes, largest first
+    bool var = false;                 // level-dependent order: per-pair steps and row tiles below
+    std::vector<int32_t> h_pair_kt, h_pair_mt;
     std::vector<std::unique_ptr<M2lTasks>> tasks;
     DBuf<int32_t> pk;                 // packed multi-indices of the contraction rows
     DBuf<int32_t> sym_in;             // symmetry tables: moments into the canonical frame,
@@ -98,6 +103,12 @@ struct PassTables {
     DBuf<float> W32[2];
 };
 
+// Number of expansion coefficients of the boxes of each level (Section 3.6:
+// the order may fall towards the leaves); passed to kernels by value.
+struct LevelP {
+    int32_t P[MAXLEV + 1];
+};
+
 // Per-matvec work buffers, grown on demand and kept on the tree.
 struct Work {
     DBuf<char> strength, mom, loc, yacc, m2l_out, m2l_mom, p2p_part;
@@ -109,6 +120,7 @@ struct bem_tree {
     bem::Ctx *ctx = nullptr;
     const bem_mesh *mesh = nullptr;
     int B = 32, order = 8, max_depth = 21;
+    int order_min = 0;  // level-dependent order when > 0 (see level_p)
     double theta = 0.6, kappa = 0.0, k_hint = 0.0;
     int64_t n_box = 0, n_leaf = 0, n_near = 0, n_inter = 0, n_el = 0, n_tgt = 0, n_q = 0;
     int max_level = 0;
@@ -211,6 +223,7 @@ void direct_regular_unit_double_layer(bem_tree &t, double *out);
 void rule_shapes(bem_tree &t);  // t.L7: the six shape functions at the 7 rule points
 void fmm_tables(bem_tree &t);
 void plan_fmm(bem_tree &t);
+LevelP level_p(const bem_tree &t);  // coefficients per level: min(order, order_min + max_level - l)
 void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int nrhs, const void *x, void *y);
 
 // passes.hip

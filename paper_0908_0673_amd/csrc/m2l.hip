@@ -141,6 +141,7 @@ __global__ void k_expand_T(const double *D64, const int32_t *pk, const int32_t *
 struct M2lArgs {
     const int32_t *task_class, *task_first, *task_count;
     const int32_t *pair_slot, *pair_src, *pair_mom, *level;
+    const int32_t *task_kt, *task_mt;  // level-dependent order: steps and row tiles each task needs
 
     double side;
     int P;
@@ -207,7 +208,11 @@ struct M2lChunk {
 // pairs per wave as 16 real columns (real parts, then imaginary parts) against
 // the operator's real and imaginary planes.  Columns without a pair compute
 // on the first canonical moments and are not stored.
-template <class R, int NA>
+// VAR (level-dependent order): a task stops after the chunks that cover its
+// sources' coefficients (the moments past them are zero, so the skipped
+// products add nothing) and computes and stores only the row tiles that
+// cover its targets' coefficients (the reduction reads no other row).
+template <class R, int NA, bool VAR>
 __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, const R *Mc, R *out) {
     far_field_priority();
     using V4 = typename vec4<R>::type;
@@ -219,6 +224,8 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, c
     const int cnt = a.task_count[task];
     if (cnt == 0) return;  // the same for the whole block
     const int c = a.task_class[task], first = a.task_first[task];
+    const int nch = VAR ? (a.task_kt[task] + KC - 1) / KC : NCH;  // the same for the whole block
+    const int mtn = VAR ? a.task_mt[task] : MT;
     const int col = lane & 15, kq = lane >> 4;
     const int cg = w / MS, mt0 = (w % MS) * MTH;  // column group and first row tile of this wave
     const int p = NA == 1 ? 16 * cg + col : 8 * cg + (col & 7);
@@ -255,13 +262,14 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, c
     if (NCH > 1) fetch(1, r);
 #pragma unroll
     for (int ch = 0; ch < NCH; ch++) {
+        if (VAR && ch >= nch) break;  // uniform over the block: no barrier is skipped by part of it
         const R *Ab = As[ch & 1] + lane;
 #pragma unroll
         for (int kk = 0; kk < KC; kk++) {
             const int kt = ch * KC + kk, sb = kt % NB;
 #pragma unroll
             for (int j = 0; j < MTH; j++)
-                if (MS == 1 || mt0 + j < MT)  // the same for the whole wave
+                if ((MS == 1 || mt0 + j < MT) && (!VAR || mt0 + j < mtn))  // the same for the whole wave
 #pragma unroll
                     for (int q = 0; q < NA; q++)
                         acc[q][j] = mfma(Ab[q * CE + (kk * MT + mt0 + j) * 64], B[sb], acc[q][j]);
@@ -279,7 +287,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, c
             R *o = out + (int64_t)a.pair_slot[first + p] * OUT_LD;
 #pragma unroll
             for (int j = 0; j < MTH; j++)
-                if (MS == 1 || mt0 + j < MT)
+                if ((MS == 1 || mt0 + j < MT) && (!VAR || mt0 + j < mtn))
 #pragma unroll
                     for (int r4 = 0; r4 < 4; r4++) o[16 * (mt0 + j) + crow(R(0), kq, r4)] = acc[0][j][r4] * scale;
         }
@@ -289,7 +297,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, c
         cx<R> *o = (cx<R> *)out + (int64_t)(store ? a.pair_slot[first + p] : 0) * OUT_LD;
 #pragma unroll
         for (int j = 0; j < MTH; j++)
-            if (MS == 1 || mt0 + j < MT)
+            if ((MS == 1 || mt0 + j < MT) && (!VAR || mt0 + j < mtn))
 #pragma unroll
                 for (int r4 = 0; r4 < 4; r4++) {
                     const R trmi = __shfl_xor(acc[0][j][r4], 8, 64);
@@ -314,13 +322,15 @@ constexpr int RED_RU = 6;    // slots per wave in flight
 
 template <class V>
 __global__ void __launch_bounds__(256) k_m2l_reduce(const int32_t *boxes, const int64_t *iptr, const int32_t *slot_sym,
-                                                    const int16_t *sym_red, int P, const V *out, V *loc) {
+                                                    const int16_t *sym_red, int P, const int32_t *level, LevelP lp,
+                                                    const V *out, V *loc) {
     far_field_priority();
     __shared__ __align__(16) int16_t tab[NSYM * OUT_LD];
     __shared__ int32_t ssym[RED_CH];
     __shared__ V part[4][3 * 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int b = boxes[blockIdx.x];
+    const int Pt = lp.P[level[b]];  // the box's own order: rows past it are not formed
     const int64_t j0 = iptr[b], j1 = iptr[b + 1];
     for (int x = tid; x < NSYM * OUT_LD / 8; x += 256) ((int4 *)tab)[x] = ((const int4 *)sym_red)[x];
     V acc[3] = {V(0.0), V(0.0), V(0.0)};
@@ -339,8 +349,8 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int32_t *boxes, const 
 #pragma unroll
                 for (int r = 0; r < 3; r++) {
                     const int i = lane + 64 * r;
-                    const int e = (j < ns && i < P) ? tab[g * OUT_LD + i] : 0;
-                    sg[k][r] = (j < ns && i < P) ? ((e & 0x100) ? -1 : 1) : 0;
+                    const int e = (j < ns && i < Pt) ? tab[g * OUT_LD + i] : 0;
+                    sg[k][r] = (j < ns && i < Pt) ? ((e & 0x100) ? -1 : 1) : 0;
                     v[k][r] = out[(cb + min(j, ns - 1)) * OUT_LD + (e & 0xff)];
                 }
             }
@@ -356,7 +366,8 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int32_t *boxes, const 
 #pragma unroll
     for (int r = 0; r < 3; r++) part[w][lane + 64 * r] = acc[r];
     __syncthreads();
-    for (int i = tid; i < P; i += 256) loc[(int64_t)b * P + i] = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
+    for (int i = tid; i < P; i += 256)
+        loc[(int64_t)b * P + i] = i < Pt ? ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i] : V(0.0);
 }
 
 struct ClassKey {
@@ -428,7 +439,7 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     // canonical classes of the interaction pairs of boxes with targets
     std::unordered_map<ClassKey, int32_t, ClassKeyHash> id;
     std::vector<std::vector<int32_t>> members;  // slots
-    std::vector<std::vector<int32_t>> msym;
+    std::vector<std::vector<int32_t>> msym, mlev;  // symmetry and target level of each member
     std::vector<int32_t> cdelta;
     std::vector<double> rbar, kbar;
     for (int64_t b = 0; b < t.n_box; b++) {
@@ -462,6 +473,7 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
                 id.emplace(key, cid);
                 members.emplace_back();
                 msym.emplace_back();
+                mlev.emplace_back();
                 cdelta.push_back(d);
                 for (int e = 0; e < 3; e++) rbar.push_back(std::ldexp((double)u[sg[e]], -(d + 1)));
                 kbar.push_back(k * std::ldexp(t.side, -t.h_level[s]));
@@ -470,9 +482,29 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
             }
             members[cid].push_back((int32_t)j);
             msym[cid].push_back(8 * perm + flips);
+            mlev[cid].push_back(t.h_level[b]);
         }
     }
     pl->n_class = (int64_t)members.size();
+    // level-dependent order: a class's pairs in target-level order, so that
+    // the pairs of a task mostly share their orders
+    const LevelP lp = level_p(t);
+    pl->var = t.order_min > 0 && t.order_min < t.order;
+    if (pl->var)
+        for (size_t cl = 0; cl < members.size(); cl++) {
+            std::vector<size_t> ix(members[cl].size());
+            for (size_t i = 0; i < ix.size(); i++) ix[i] = i;
+            std::stable_sort(ix.begin(), ix.end(), [&](size_t x, size_t y) { return mlev[cl][x] < mlev[cl][y]; });
+            std::vector<int32_t> m2(ix.size()), s2(ix.size()), l2(ix.size());
+            for (size_t i = 0; i < ix.size(); i++) {
+                m2[i] = members[cl][ix[i]];
+                s2[i] = msym[cl][ix[i]];
+                l2[i] = mlev[cl][ix[i]];
+            }
+            members[cl].swap(m2);
+            msym[cl].swap(s2);
+            mlev[cl].swap(l2);
+        }
     // pairs grouped by class, largest class first
     std::vector<int32_t> order(members.size());
     for (size_t i = 0; i < order.size(); i++) order[i] = (int32_t)i;
@@ -487,6 +519,10 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
             slot.push_back(members[cl][i]);
             src.push_back(t.h_inter_idx[members[cl][i]]);
             sym.push_back(msym[cl][i]);
+            if (pl->var) {
+                pl->h_pair_kt.push_back((lp.P[t.h_level[src.back()]] + 3) / 4);
+                pl->h_pair_mt.push_back((lp.P[mlev[cl][i]] + 15) / 16);
+            }
         }
     }
     pl->n_pairs = (int64_t)slot.size();
@@ -560,7 +596,7 @@ M2lTasks &get_tasks(Ctx &c, M2lPlan &pl, int cols) {
     for (auto &tk : pl.tasks)
         if (tk->cols == cols) return *tk;
     constexpr int NXCD = 8;
-    std::vector<std::vector<int32_t>> qc(NXCD), qf(NXCD), qn(NXCD);
+    std::vector<std::vector<int32_t>> qc(NXCD), qf(NXCD), qn(NXCD), qk(NXCD), qm(NXCD);
     std::vector<int64_t> load(NXCD, 0);
     for (size_t i = 0; i < pl.h_class_order.size(); i++) {
         const int32_t cl = pl.h_class_order[i], f0 = pl.h_class_first[i], n = pl.h_class_count[i];
@@ -569,17 +605,34 @@ M2lTasks &get_tasks(Ctx &c, M2lPlan &pl, int cols) {
             qc[x].push_back(cl);
             qf[x].push_back(f0 + o);
             qn[x].push_back(std::min(cols, n - o));
+            if (pl.var) {
+                int32_t kt = 0, mt = 0;
+                for (int32_t i = f0 + o; i < f0 + o + qn[x].back(); i++) {
+                    kt = std::max(kt, pl.h_pair_kt[i]);
+                    mt = std::max(mt, pl.h_pair_mt[i]);
+                }
+                qk[x].push_back(kt);
+                qm[x].push_back(mt);
+            }
             load[x]++;
         }
     }
     size_t qmax = 0;
     for (int x = 0; x < NXCD; x++) qmax = std::max(qmax, qc[x].size());
-    std::vector<int32_t> tc(qmax * NXCD, 0), tf(qmax * NXCD, 0), tn(qmax * NXCD, 0);
+    std::vector<int32_t> tc(qmax * NXCD, 0), tf(qmax * NXCD, 0), tn(qmax * NXCD, 0), tkt, tmt;
+    if (pl.var) {
+        tkt.assign(qmax * NXCD, 0);
+        tmt.assign(qmax * NXCD, 0);
+    }
     for (int x = 0; x < NXCD; x++)
         for (size_t i = 0; i < qc[x].size(); i++) {
             tc[i * NXCD + x] = qc[x][i];
             tf[i * NXCD + x] = qf[x][i];
             tn[i * NXCD + x] = qn[x][i];
+            if (pl.var) {
+                tkt[i * NXCD + x] = qk[x][i];
+                tmt[i * NXCD + x] = qm[x][i];
+            }
         }
     auto tk = std::make_unique<M2lTasks>();
     tk->cols = cols;
@@ -591,6 +644,10 @@ M2lTasks &get_tasks(Ctx &c, M2lPlan &pl, int cols) {
     up(tk->task_class, tc);
     up(tk->task_first, tf);
     up(tk->task_count, tn);
+    if (pl.var) {
+        up(tk->task_kt, tkt);
+        up(tk->task_mt, tmt);
+    }
     pl.tasks.push_back(std::move(tk));
     return *pl.tasks.back();
 }
@@ -645,7 +702,8 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc) {
     t.work.m2l_out.ensure(&c, sizeof(V) * (size_t)std::max<int64_t>(1, t.n_inter) * OUT_LD);
     V *out = (V *)t.work.m2l_out.p;
     M2lArgs a{tk.task_class.p, tk.task_first.p, tk.task_count.p, pl.pair_slot.p, pl.pair_src.p, pl.pair_mom.p,
-              t.level.p, t.side, P};
+              t.level.p, tk.task_kt.p, tk.task_mt.p, t.side, P};
+    const LevelP lp = level_p(t);
     t.work.m2l_mom.ensure(&c, sizeof(V) * (size_t)std::max<int64_t>(1, pl.n_u) * KIN);
     V *Mc = (V *)t.work.m2l_mom.p;
     const R *Tx = expanded<R>(t, pl);
@@ -658,12 +716,15 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc) {
         c.mark(10);
         constexpr int NA = std::is_same<V, R>::value ? 1 : 2;
         c.kbegin(c.stream, 3);
-        k_m2l<R, NA><<<(unsigned)tk.n_task, 64 * M2L_WAVES, 0, c.stream>>>(a, Tx, (const R *)Mc, (R *)out);
+        if (pl.var)
+            k_m2l<R, NA, true><<<(unsigned)tk.n_task, 64 * M2L_WAVES, 0, c.stream>>>(a, Tx, (const R *)Mc, (R *)out);
+        else
+            k_m2l<R, NA, false><<<(unsigned)tk.n_task, 64 * M2L_WAVES, 0, c.stream>>>(a, Tx, (const R *)Mc, (R *)out);
         BEM_LAUNCH_CHECK();
         c.kend(c.stream);
         c.mark(3);
         k_m2l_reduce<V><<<(unsigned)t.n_m2l_boxes, 256, 0, c.stream>>>(t.m2l_boxes.p, t.inter_ptr.p, pl.slot_sym.p,
-                                                                       pl.sym_red.p, P, out, l);
+                                                                       pl.sym_red.p, P, t.level.p, lp, out, l);
         BEM_LAUNCH_CHECK();
         c.mark(10);
     }

@@ -42,13 +42,15 @@ __host__ __device__ inline int midx(int a, int b, int c) {
 template <bool DBL>
 __global__ void k_p2m_weights(const int32_t *leaves, const int64_t *eb, const int64_t *ee, const int32_t *level,
                               const double *centre, double side, const double *q64, int64_t n_q, const double *L7,
-                              const int32_t *slot, const int64_t *woff, int p, const int8_t *exps, double *W) {
+                              const int32_t *slot, const int64_t *woff, int p, const int8_t *exps, LevelP lp,
+                              double *W) {
     // per element of the leaf: the powers u_d^k / k! of its 7 rule points
     // (formed once, in LDS) and their normals and weights
     __shared__ double pw[7][3][MAX_ORDER + 1];
     __shared__ double qn[7][4];  // n1, n2, n3, wJ
     const int P = ncoef(p);
     const int b = leaves[blockIdx.x];
+    const int Pb = lp.P[level[b]];  // rows past the leaf's order stay zero
     const double rho = ldexp(side, -level[b]), irho = 1.0 / rho;
     const double cc[3] = {centre[3 * b], centre[3 * b + 1], centre[3 * b + 2]};
     const int64_t off = woff[blockIdx.x];
@@ -70,7 +72,7 @@ __global__ void k_p2m_weights(const int32_t *leaves, const int64_t *eb, const in
             qn[q][3] = q64[3 * n_q + qi];
         }
         __syncthreads();
-        if (a >= P) continue;
+        if (a >= Pb) continue;
         double phi[7];
         for (int q = 0; q < 7; q++) {
             const double *p0 = pw[q][0], *p1 = pw[q][1], *p2 = pw[q][2];
@@ -182,7 +184,7 @@ __device__ inline V sum8(V v) {
 // the eight lanes are added by shuffles.
 template <class V, class R>
 __global__ void __launch_bounds__(256) k_m2m(const int32_t *boxes, const int32_t *child_begin, const int32_t *nchild,
-                                             const uint64_t *prefix, int p, const int8_t *exps, V *mom,
+                                             const uint64_t *prefix, int p, int Pout, const int8_t *exps, V *mom,
                                              int64_t n_box) {
     far_field_priority();
     constexpr int NIT = (ncoef(MAX_ORDER) + 31) / 32;
@@ -240,7 +242,8 @@ __global__ void __launch_bounds__(256) k_m2m(const int32_t *boxes, const int32_t
                     }
         }
         acc = sum8(acc);
-        if (a < P && pi == 0) base[(int64_t)b * P + a] = acc;
+        // terms past the parent's order (Pout coefficients) are not kept
+        if (a < P && pi == 0) base[(int64_t)b * P + a] = a < Pout ? acc : V(0.0);
     }
 }
 
@@ -251,7 +254,7 @@ __global__ void __launch_bounds__(256) k_m2m(const int32_t *boxes, const int32_t
 template <class V, class R>
 __global__ void __launch_bounds__(256) k_l2l(const int32_t *boxes, const int32_t *child_begin, const int32_t *nchild,
                                              const uint64_t *prefix, const int64_t *tb, const int64_t *te, int p,
-                                             const int8_t *exps, V *loc, int64_t n_box) {
+                                             int Pc, const int8_t *exps, V *loc, int64_t n_box) {
     far_field_priority();
     extern __shared__ unsigned char smem[];
     const int P = ncoef(p);
@@ -301,12 +304,23 @@ __global__ void __launch_bounds__(256) k_l2l(const int32_t *boxes, const int32_t
         T = T * (R)ldexp(1.0, -(b0 + b1 + b2));
     }
     const V v = wht8(T, pi);
-    if (bi < P && cj >= 0) base[(int64_t)cj * P + bi] = old + v;
+    // the children keep the terms of their own order (Pc coefficients)
+    if (bi < Pc && cj >= 0) base[(int64_t)cj * P + bi] = old + v;
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------- setup
+LevelP level_p(const bem_tree &t) {
+    LevelP lp{};
+    for (int l = 0; l <= MAXLEV; l++) {
+        int L = t.order;
+        if (t.order_min > 0) L = std::min(t.order, t.order_min + std::max(0, t.max_level - l));
+        lp.P[l] = ncoef(L);
+    }
+    return lp;
+}
+
 void build_pass_tables(bem_tree &t) {
     if (t.pass.built) return;
     Ctx &c = *t.ctx;
@@ -343,6 +357,7 @@ void build_pass_tables(bem_tree &t) {
     dslot.upload(slot.data(), slot.size());
     const size_t nw = (size_t)pt.n_w * P;
     const unsigned wbs = (unsigned)std::max(192, (P + 63) / 64 * 64);  // one thread per coefficient
+    const LevelP lp = level_p(t);
     for (int dbl = 0; dbl < 2; dbl++) {
         pt.W64[dbl].alloc(&c, nw);
         pt.W64[dbl].zero();
@@ -351,11 +366,11 @@ void build_pass_tables(bem_tree &t) {
             if (dbl)
                 k_p2m_weights<true><<<(unsigned)t.n_leaf_src, wbs, 0, c.stream>>>(
                     t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p, t.side, t.q64.p, t.n_q, t.L7.p, dslot.p,
-                    pt.woff.p, p, T.exps.p, pt.W64[dbl].p);
+                    pt.woff.p, p, T.exps.p, lp, pt.W64[dbl].p);
             else
                 k_p2m_weights<false><<<(unsigned)t.n_leaf_src, wbs, 0, c.stream>>>(
                     t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p, t.side, t.q64.p, t.n_q, t.L7.p, dslot.p,
-                    pt.woff.p, p, T.exps.p, pt.W64[dbl].p);
+                    pt.woff.p, p, T.exps.p, lp, pt.W64[dbl].p);
             BEM_LAUNCH_CHECK();
         }
         k_to_r<float><<<nblocks(nw, 256), 256, 0, c.stream>>>(pt.W64[dbl].p, nw, pt.W32[dbl].p);
@@ -383,12 +398,13 @@ void m2m_apply(bem_tree &t, int nrhs, V *mom, int top) {
     Ctx &c = *t.ctx;
     const int p = t.order, P = t.tables->P;
     const size_t sh = sizeof(V) * 8 * P + sizeof(R) * 2 * (MAX_ORDER + 1);
+    const LevelP lp = level_p(t);
     for (int l = t.max_level - 1; l >= (top < 0 ? t.m2m_top : top); l--) {
         int64_t nb = (int64_t)t.m2m_level_boxes[l].size();
         if (!nb) continue;
         dim3 g((unsigned)nb, (P + 31) / 32, nrhs);
         k_m2m<V, R><<<g, 256, sh, c.stream>>>(t.d_m2m_level_boxes[l].p, t.child_begin.p, t.nchild.p, t.prefix.p, p,
-                                              t.tables->exps.p, mom, t.n_box);
+                                              lp.P[l], t.tables->exps.p, mom, t.n_box);
         BEM_LAUNCH_CHECK();
     }
 }
@@ -398,12 +414,13 @@ void l2l_apply(bem_tree &t, int nrhs, V *loc) {
     Ctx &c = *t.ctx;
     const int p = t.order, P = t.tables->P;
     const size_t sh = sizeof(V) * P + sizeof(R) * ((MAX_ORDER + 1) + (p + 1) * (p + 1));
+    const LevelP lp = level_p(t);
     for (int l = t.l2l_top; l < t.max_level; l++) {
         int64_t nb = (int64_t)t.l2l_level_boxes[l].size();
         if (!nb) continue;
         dim3 g((unsigned)nb, (P + 31) / 32, nrhs);
         k_l2l<V, R><<<g, 256, sh, c.stream>>>(t.d_l2l_level_boxes[l].p, t.child_begin.p, t.nchild.p, t.prefix.p,
-                                              t.tb.p, t.te.p, p, t.tables->exps.p, loc, t.n_box);
+                                              t.tb.p, t.te.p, p, lp.P[l + 1], t.tables->exps.p, loc, t.n_box);
         BEM_LAUNCH_CHECK();
     }
 }

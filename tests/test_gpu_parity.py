@@ -31,15 +31,16 @@ def _bem():
 _cache = {}
 
 
-def setup(name, B=32, theta=THETA, kappa=0.0, k_hint=0.0):
-    key = (name, B, theta, kappa, k_hint)
+def setup(name, B=32, theta=THETA, kappa=0.0, k_hint=0.0, order_min=0):
+    key = (name, B, theta, kappa, k_hint, order_min)
     if key not in _cache:
         bem = _bem()
-        say(f"[setup] mesh={name} B={B} theta={theta} kappa={kappa}")
+        say(f"[setup] mesh={name} B={B} theta={theta} kappa={kappa} order_min={order_min}")
         m = mesh_by_name(name)
         ctx = context()
         mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
-        tree = bem.bem_tree_build(ctx, mesh, B=B, order=8, theta=theta, kappa=kappa, k_hint=k_hint)
+        tree = bem.bem_tree_build(ctx, mesh, B=B, order=8, theta=theta, kappa=kappa, k_hint=k_hint,
+                                  order_min=order_min)
         om = oracle.OracleMesh(m.xyz, m.elem)
         ot = oracle.OracleTree(om, B=B, theta=theta, kappa=kappa if kappa > 0 else float("inf"), k=k_hint)
         _cache[key] = (m, ctx, mesh, tree, om, ot)
@@ -146,6 +147,32 @@ def test_fmm_fp64_matches_oracle_fmm(name, green, k):
         # double layer K (only used inside A) has a smaller norm: within 1e-5
         bound = 1e-6 if op in (2, 3) else 1e-5
         assert rel(y, dref) < bound, ("truncation", op, rel(y, dref))
+
+
+@pytest.mark.parametrize("name,B", [("sphere1280", 16), ("sphere1280", 4), ("cube4", 8)])
+@pytest.mark.parametrize("green,k", [(0, 0.0), (1, 2.0)])
+def test_fmm_level_dependent_order_matches_oracle(name, B, green, k):
+    """Section 3.6's level-dependent order, L_l = min(8, L_min + l_max - l),
+    at the paper's L_min = 3 and 4: the FP64 product against the oracle's
+    fast product with the same orders (1e-11), the mixed one within its
+    stated tolerance of it."""
+    bem = _bem()
+    cplx = green == 1
+    for m_ in (3, 4):
+        m, ctx, mesh, tree, om, ot = setup(name, B=B, order_min=m_)
+        x = bem_inputs.random_vector(om.n_dof, 26, complex_=cplx)[0]
+        xd = to_dev(x, cplx)
+        yd = xd.clone()
+        levels = ot.level.max()
+        for op in (bem.BEM_OP_A, bem.BEM_OP_RHS):
+            ref = ot.fmm_matvec(x, op, green, k, order=8, order_min=m_)
+            ref = ref if cplx else ref.real
+            bem.bem_matvec(ctx, tree, green, k, op, bem.BEM_FMM, bem.BEM_PREC_FP64, xd, yd)
+            e64 = rel(yd.cpu().numpy()[0], ref)
+            bem.bem_matvec(ctx, tree, green, k, op, bem.BEM_FMM, bem.BEM_PREC_MIXED, xd, yd)
+            e32 = rel(yd.cpu().numpy()[0], ref)
+            say(f"  {name} L_min={m_} l_max={levels} green={green} op={op}: fp64 {e64:.2e} mixed {e32:.2e}")
+            assert e64 < 1e-11 and e32 < MIXED_TOL, (op, e64, e32)
 
 
 @pytest.mark.parametrize("green,k", [(0, 0.0), (1, 2.0)])
