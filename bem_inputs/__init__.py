@@ -1,6 +1,6 @@
 """Seeded synthetic inputs shared by the GPU path's tests and by the oracle.
 
-This package holds geometry generators (meshes of curved 6-node triangles),
+This package holds geometry generators (meshes of curved 6-node or flat 3-node triangles),
 seeded random vectors and seeded request streams (sizes, shapes, draws)
 only.  It contains none of the boundary element
 method's arithmetic: no shape-function evaluation, no quadrature, no Green's
@@ -14,6 +14,7 @@ from .meshes import (  # noqa: F401
     geodesic_sphere,
     cube,
     ellipsoid,
+    linear,
     workload,
     WORKLOADS,
 )

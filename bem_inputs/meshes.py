@@ -1,8 +1,8 @@
-"""Synthetic surface meshes of 6-node quadratic triangles.
+"""Synthetic surface meshes of 6-node quadratic or 3-node flat triangles.
 
 Element node order (both the oracle and the GPU library assume it): the
-three corners counter-clockwise seen from outside the body, then the
-mid-side nodes of edges 0-1, 1-2 and 2-0.  The paper's test surfaces are a
+three corners counter-clockwise seen from outside the body, then (6-node
+elements) the mid-side nodes of edges 0-1, 1-2 and 2-0.  The paper's test surfaces are a
 unit sphere refined from an initial surface and a cube of edge 2 centred on
 the origin (Section 4); its cube meshes came from an external mesher that is
 not available here, so structured cube meshes stand in for them.
@@ -18,7 +18,7 @@ import numpy as np
 
 @dataclasses.dataclass
 class Mesh:
-    """Nodes ``xyz`` [n_nodes, 3] float64 and elements ``elem`` [n_el, 6] int32."""
+    """Nodes ``xyz`` [n_nodes, 3] float64 and elements ``elem`` [n_el, 6] (or [n_el, 3]) int32."""
 
     name: str
     xyz: np.ndarray
@@ -191,6 +191,17 @@ def ellipsoid(freq: int, axes) -> Mesh:
     return Mesh(f"ellipsoid{freq}", s.xyz * np.asarray(axes, dtype=np.float64)[None, :], s.elem)
 
 
+def linear(m: Mesh) -> Mesh:
+    """The flat 3-node triangulation on the corners of a 6-node mesh (the
+    surface's first-order mesh of the same refinement); nodes renumbered in
+    order of first use by the corners."""
+    corners = m.elem[:, :3]
+    used = np.unique(corners)
+    remap = np.full(m.n_nodes, -1, np.int64)
+    remap[used] = np.arange(used.size)
+    return Mesh(m.name + "_p1", m.xyz[used].copy(), remap[corners].astype(np.int32))
+
+
 # Named workloads with the sizes of the paper's test surfaces.
 WORKLOADS = {
     "sphere320": lambda: icosphere(2),       # 320 elements, 642 nodes
@@ -203,6 +214,11 @@ WORKLOADS = {
 
 
 def workload(name: str) -> Mesh:
+    """A named mesh; the suffix ``_p1`` gives the first-order mesh on the
+    corners of the named one (e.g. ``sphere20480_p1``: 20480 flat triangles,
+    10242 nodes)."""
+    if name.endswith("_p1"):
+        return linear(workload(name[:-3]))
     if name in WORKLOADS:
         return WORKLOADS[name]()
     if name.startswith("cube"):

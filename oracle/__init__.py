@@ -8,6 +8,8 @@ fast-math); this module marshals numpy arrays into it.  ``gmres`` and
 
 Parity status per function (pins live in ``tests/test_oracle_*.py``):
   shape functions, quadrature rules, element geometry   pinned (exactness, areas, closed forms)
+  first-order (3-node) elements                          pinned (closed forms, solid angles, the direct
+                                                         errors printed in Tables 1 and 5)
   DOF indexing                                           pinned (cube DOF counts, corner/edge multiplicity)
   S, K, free term                                        pinned (solid angles, Green's identity, sphere potentials)
   tree, radii, lists                                     pinned (invariants, brute-force coverage)
@@ -54,25 +56,26 @@ def lib():
         vp = ctypes.c_void_p
         i64 = ctypes.c_int64
         L.or_tree_build.restype = vp
-        L.or_tree_build.argtypes = [vp, i64, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int,
+        L.or_tree_build.argtypes = [vp, i64, vp, i64, ctypes.c_int, vp, i64, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.or_tree_sizes.argtypes = [vp, vp]
         L.or_tree_export.argtypes = [vp] + [vp] * 9
         L.or_tree_free.argtypes = [vp]
-        L.or_fmm_matvec.argtypes = [vp, vp, vp, vp, vp, i64, i64, ctypes.c_int, ctypes.c_double,
-                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
-        L.or_index_dofs.argtypes = [vp, i64, vp, i64, ctypes.c_double, vp, vp, vp, vp]
-        L.or_assemble.argtypes = [vp, vp, vp, vp, i64, i64, ctypes.c_int, ctypes.c_double, vp, vp, vp]
-        L.or_matvec_rows.argtypes = [vp, vp, vp, vp, i64, i64, ctypes.c_int, ctypes.c_double,
-                                     ctypes.c_int, vp, vp, i64, vp]
-        L.or_free_term.argtypes = [vp, vp, vp, vp, i64, i64, vp, i64, vp]
-        L.or_layer_potential.argtypes = [vp, vp, vp, i64, ctypes.c_int, ctypes.c_double, vp, vp,
+        ci = ctypes.c_int
+        L.or_fmm_matvec.argtypes = [vp, vp, vp, vp, vp, i64, i64, ci, ci, ctypes.c_double,
+                                    ci, ci, ci, vp, vp]
+        L.or_index_dofs.argtypes = [vp, i64, vp, i64, ci, ctypes.c_double, vp, vp, vp, vp]
+        L.or_assemble.argtypes = [vp, vp, vp, vp, i64, i64, ci, ci, ctypes.c_double, vp, vp, vp]
+        L.or_matvec_rows.argtypes = [vp, vp, vp, vp, i64, i64, ci, ci, ctypes.c_double,
+                                     ci, vp, vp, i64, vp]
+        L.or_free_term.argtypes = [vp, vp, vp, vp, i64, i64, ci, vp, i64, vp]
+        L.or_layer_potential.argtypes = [vp, vp, vp, i64, ci, ci, ctypes.c_double, vp, vp,
                                          vp, i64, vp]
-        L.or_pair.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int, ctypes.c_double, vp, vp]
-        L.or_classify.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
-        L.or_rule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
-        L.or_shape.argtypes = [ctypes.c_double, ctypes.c_double, vp, vp, vp]
-        L.or_elem_point.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+        L.or_pair.argtypes = [ci, vp, vp, ctypes.c_int32, vp, ci, ctypes.c_double, vp, vp]
+        L.or_classify.argtypes = [ci, vp, vp, ctypes.c_int32, vp, vp]
+        L.or_rule.argtypes = [ci, ci, ci, vp, vp, vp]
+        L.or_shape.argtypes = [ci, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+        L.or_elem_point.argtypes = [ci, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
         L.or_derivs.argtypes = [ctypes.c_int, ctypes.c_double, vp, ctypes.c_int, vp]
         L.or_mono_moments.argtypes = [ctypes.c_int, vp, vp, vp, i64, vp]
         L.or_m2m.argtypes = [ctypes.c_int, vp, vp, vp]
@@ -96,17 +99,20 @@ def ncoef(p: int) -> int:
 
 # ---------------------------------------------------------------- mesh
 class OracleMesh:
-    """A mesh with the oracle's own DOF indexing (Section 2.3)."""
+    """A mesh with the oracle's own DOF indexing (Section 2.3).  elem is
+    [n_el][6] (second-order triangles) or [n_el][3] (first-order, flat)."""
 
     def __init__(self, xyz, elem, edge_angle_deg: float = 30.0):
         self.xyz = _c(xyz, np.float64)
         self.elem = _c(elem, np.int32)
-        n_el = self.elem.shape[0]
-        ed = np.empty((n_el, 6), np.int32)
-        dn = np.empty(6 * n_el, np.int32)
-        dnorm = np.empty((6 * n_el, 3), np.float64)
+        n_el, self.nn = self.elem.shape
+        if self.nn not in (3, 6):
+            raise ValueError("elements need 3 or 6 nodes")
+        ed = np.empty((n_el, self.nn), np.int32)
+        dn = np.empty(self.nn * n_el, np.int32)
+        dnorm = np.empty((self.nn * n_el, 3), np.float64)
         nd = np.zeros(1, np.int64)
-        rc = lib().or_index_dofs(_p(self.xyz), self.xyz.shape[0], _p(self.elem), n_el,
+        rc = lib().or_index_dofs(_p(self.xyz), self.xyz.shape[0], _p(self.elem), n_el, self.nn,
                                  edge_angle_deg, _p(ed), _p(dn), _p(dnorm), _p(nd))
         if rc != 0:
             raise ValueError("invalid mesh")
@@ -122,7 +128,7 @@ class OracleMesh:
         return self.xyz[self.dof_node]
 
     def _args(self):
-        return (_p(self.xyz), _p(self.elem), _p(self.elem_dofs), _p(self.dof_node), self.n_el, self.n_dof)
+        return (_p(self.xyz), _p(self.elem), _p(self.elem_dofs), _p(self.dof_node), self.n_el, self.n_dof, self.nn)
 
     def assemble(self, green=LAPLACE, k=0.0):
         """Dense S, K (complex, n x n) and the free term c (Eq. 3)."""
@@ -153,7 +159,7 @@ class OracleMesh:
         ss = None if sigma_s is None else _c(sigma_s, np.complex128)
         sd = None if sigma_d is None else _c(sigma_d, np.complex128)
         out = np.zeros(pts.shape[0], np.complex128)
-        lib().or_layer_potential(_p(self.xyz), _p(self.elem), _p(self.elem_dofs), self.n_el, green,
+        lib().or_layer_potential(_p(self.xyz), _p(self.elem), _p(self.elem_dofs), self.n_el, self.nn, green,
                                  float(k), None if ss is None else _p(ss), None if sd is None else _p(sd),
                                  _p(pts), pts.shape[0], _p(out))
         return out
@@ -162,7 +168,8 @@ class OracleMesh:
         S = np.zeros(12)
         K = np.zeros(12)
         x = _c(x, np.float64)
-        cls = lib().or_pair(_p(self.xyz), _p(self.elem[e]), int(tgt_node), _p(x), green, float(k), _p(S), _p(K))
+        cls = lib().or_pair(self.nn, _p(self.xyz), _p(self.elem[e]), int(tgt_node), _p(x), green, float(k), _p(S),
+                            _p(K))
         return cls, S.view(np.complex128), K.view(np.complex128)
 
 
@@ -173,7 +180,7 @@ class OracleTree:
     def __init__(self, mesh: OracleMesh, B=32, max_depth=21, theta=1.0, kappa=float("inf"), k=0.0):
         self.mesh = mesh
         tgt = _c(mesh.dof_xyz, np.float64)
-        self._h = lib().or_tree_build(_p(mesh.xyz), mesh.xyz.shape[0], _p(mesh.elem), mesh.n_el,
+        self._h = lib().or_tree_build(_p(mesh.xyz), mesh.xyz.shape[0], _p(mesh.elem), mesh.n_el, mesh.nn,
                                       _p(tgt), tgt.shape[0], int(B), int(max_depth), float(theta),
                                       float(kappa), float(k))
         sz = np.zeros(4, np.int64)
@@ -229,16 +236,20 @@ def rule(kind: int, param: int = 0, ng: int = 8):
     return s[:n], t[:n], w[:n]
 
 
-def shape(s, t):
+def shape(s, t, nn=6):
+    """Shape functions of the 6-node (nn = 6) or 3-node triangle and their
+    s, t derivatives (six entries, unused ones zero)."""
     L, Ls, Lt = np.zeros(6), np.zeros(6), np.zeros(6)
-    lib().or_shape(float(s), float(t), _p(L), _p(Ls), _p(Lt))
+    lib().or_shape(int(nn), float(s), float(t), _p(L), _p(Ls), _p(Lt))
     return L, Ls, Lt
 
 
-def elem_point(X6, s, t):
-    X = _c(X6, np.float64)
+def elem_point(X, s, t):
+    """Position, unit normal and Jacobian of the element with node
+    coordinates X ([6][3] or [3][3]) at (s, t)."""
+    X = _c(X, np.float64).reshape(-1, 3)
     y, n, J = np.zeros(3), np.zeros(3), np.zeros(1)
-    lib().or_elem_point(_p(X), float(s), float(t), _p(y), _p(n), _p(J))
+    lib().or_elem_point(X.shape[0], _p(X), float(s), float(t), _p(y), _p(n), _p(J))
     return y, n, float(J[0])
 
 

@@ -14,7 +14,8 @@
  * definitions state.  Build with -O2 -ffp-contract=off, no fast-math.
  *
  * Contents, each with the passage it follows:
- *   - 6-node isoparametric triangle                          (Section 2.2)
+ *   - 6-node isoparametric triangle and the 3-node flat
+ *     triangle (every element routine takes nn = 6 or 3)     (Section 2.2)
  *   - sharp-edge DOF indexing                                 (Section 2.3)
  *   - quadrature: 7-point degree-5 rule, Duffy singular rule,
  *     uniform-subdivision near-singular rule                  (Section 2.1)
@@ -22,7 +23,8 @@
  *   - octree, convergence radii, near/interaction lists      (Sections 3.1, 3.4, 3.6; Eqs. 13, 14)
  *   - Taylor moments, shifts, local expansions               (Section 3.2; Eqs. 6-11)
  *   - derivatives of the Green's functions                   (Section 3.3; Eq. 12)
- *   - the fast matrix product                                 (Section 3.6)
+ *   - the fast matrix product, uniform or level-dependent
+ *     expansion order                                         (Section 3.6)
  */
 #include <complex.h>
 #include <math.h>
@@ -68,18 +70,43 @@ static void shape6(double s, double t, double L[6], double Ls[6], double Lt[6])
     }
 }
 
+/* The first-order (3-node) triangle of Section 2.2: a flat triangle with   */
+/* the linear shape functions 1 - s - t, s, t on the corners.               */
+static void shape3(double s, double t, double L[6], double Ls[6], double Lt[6])
+{
+    for (int a = 0; a < 6; a++) L[a] = 0.0;
+    L[0] = 1.0 - s - t;
+    L[1] = s;
+    L[2] = t;
+    if (Ls) {
+        for (int a = 0; a < 6; a++) Ls[a] = Lt[a] = 0.0;
+        Ls[0] = -1.0; Lt[0] = -1.0;
+        Ls[1] = 1.0;
+        Lt[2] = 1.0;
+    }
+}
+
+/* Shape functions of an element of nn nodes (3 or 6); unused entries 0. */
+static void shape(int nn, double s, double t, double L[6], double Ls[6], double Lt[6])
+{
+    if (nn == 3) shape3(s, t, L, Ls, Lt);
+    else shape6(s, t, L, Ls, Lt);
+}
+
 static const double NODE_ST[6][2] = {
     {0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}, {0.5, 0.0}, {0.5, 0.5}, {0.0, 0.5}};
 
-/* Position, unit normal and area Jacobian of the element at (s,t). */
-static void elem_point(const double X[6][3], double s, double t, double y[3],
+/* Position, unit normal and area Jacobian of an element of nn nodes at   */
+/* (s,t); L receives the shape functions (which also interpolate the     */
+/* unknowns: the elements are isoparametric).                             */
+static void elem_point(int nn, const double X[6][3], double s, double t, double y[3],
                        double n[3], double *J, double L[6])
 {
     double Ls[6], Lt[6], ys[3] = {0, 0, 0}, yt[3] = {0, 0, 0};
-    shape6(s, t, L, Ls, Lt);
+    shape(nn, s, t, L, Ls, Lt);
     for (int d = 0; d < 3; d++) {
         y[d] = 0.0;
-        for (int a = 0; a < 6; a++) {
+        for (int a = 0; a < nn; a++) {
             y[d] += L[a] * X[a][d];
             ys[d] += Ls[a] * X[a][d];
             yt[d] += Lt[a] * X[a][d];
@@ -92,20 +119,21 @@ static void elem_point(const double X[6][3], double s, double t, double y[3],
     for (int d = 0; d < 3; d++) n[d] = N[d] / j;
 }
 
-static void load_elem(const double *xyz, const int32_t *en, double X[6][3])
+static void load_elem(int nn, const double *xyz, const int32_t *en, double X[6][3])
 {
     for (int a = 0; a < 6; a++)
-        for (int d = 0; d < 3; d++) X[a][d] = xyz[3 * (int64_t)en[a] + d];
+        for (int d = 0; d < 3; d++) X[a][d] = a < nn ? xyz[3 * (int64_t)en[a] + d] : 0.0;
 }
 
 /* Exported for tests: shape functions and the element map at (s,t). */
-void or_shape(double s, double t, double *L, double *Ls, double *Lt) { shape6(s, t, L, Ls, Lt); }
+void or_shape(int nn, double s, double t, double *L, double *Ls, double *Lt) { shape(nn, s, t, L, Ls, Lt); }
 
-void or_elem_point(const double *X18, double s, double t, double *y, double *n, double *J)
+void or_elem_point(int nn, const double *X, double s, double t, double *y, double *n, double *J)
 {
-    double X[6][3], L[6];
-    memcpy(X, X18, sizeof X);
-    elem_point(X, s, t, y, n, J, L);
+    double Xe[6][3], L[6];
+    for (int a = 0; a < 6; a++)
+        for (int d = 0; d < 3; d++) Xe[a][d] = a < nn ? X[3 * a + d] : 0.0;
+    elem_point(nn, Xe, s, t, y, n, J, L);
 }
 
 /* ------------------------------------------------------------------ */
@@ -117,40 +145,40 @@ void or_elem_point(const double *X18, double s, double t, double *y, double *n, 
 /* reference being its first member's normal; a DOF's normal is the    */
 /* normalised sum of its cluster's element normals.                    */
 /* ------------------------------------------------------------------ */
-int or_index_dofs(const double *xyz, int64_t n_nodes, const int32_t *elem, int64_t n_el,
+int or_index_dofs(const double *xyz, int64_t n_nodes, const int32_t *elem, int64_t n_el, int nn,
                   double tol_deg, int32_t *elem_dofs, int32_t *dof_node, double *dof_normal,
                   int64_t *n_dof_out)
 {
     int64_t *cnt = calloc(n_nodes + 1, sizeof *cnt);
     for (int64_t e = 0; e < n_el; e++)
-        for (int a = 0; a < 6; a++) {
-            int32_t g = elem[6 * e + a];
+        for (int a = 0; a < nn; a++) {
+            int32_t g = elem[nn * e + a];
             if (g < 0 || g >= n_nodes) { free(cnt); return -1; }
             cnt[g + 1]++;
         }
     for (int64_t g = 0; g < n_nodes; g++) cnt[g + 1] += cnt[g];
     int64_t *fill = malloc((n_nodes + 1) * sizeof *fill);
     memcpy(fill, cnt, (n_nodes + 1) * sizeof *fill);
-    int64_t *inc = malloc(6 * n_el * sizeof *inc); /* incidence = 6*e + a, in element order */
+    int64_t *inc = malloc(nn * n_el * sizeof *inc); /* incidence = nn*e + a, in element order */
     for (int64_t e = 0; e < n_el; e++)
-        for (int a = 0; a < 6; a++) inc[fill[elem[6 * e + a]]++] = 6 * e + a;
-    for (int64_t i = 0; i < 6 * n_el; i++) elem_dofs[i] = -1;
+        for (int a = 0; a < nn; a++) inc[fill[elem[nn * e + a]]++] = nn * e + a;
+    for (int64_t i = 0; i < nn * n_el; i++) elem_dofs[i] = -1;
 
     double cos_tol = cos(tol_deg * PI / 180.0);
     int64_t n_dof = 0;
-    double (*nrm)[3] = malloc(6 * n_el * sizeof *nrm);
-    int64_t *ref = malloc(6 * n_el * sizeof *ref);
+    double (*nrm)[3] = malloc(nn * n_el * sizeof *nrm);
+    int64_t *ref = malloc(nn * n_el * sizeof *ref);
     for (int64_t e = 0; e < n_el; e++) {
-        for (int a = 0; a < 6; a++) {
-            if (elem_dofs[6 * e + a] >= 0) continue;
-            int32_t g = elem[6 * e + a];
+        for (int a = 0; a < nn; a++) {
+            if (elem_dofs[nn * e + a] >= 0) continue;
+            int32_t g = elem[nn * e + a];
             int64_t first_dof = n_dof;
             for (int64_t p = cnt[g]; p < cnt[g + 1]; p++) {
-                int64_t e2 = inc[p] / 6;
-                int a2 = (int)(inc[p] % 6);
+                int64_t e2 = inc[p] / nn;
+                int a2 = (int)(inc[p] % nn);
                 double X[6][3], y[3], n[3], J, L[6];
-                load_elem(xyz, elem + 6 * e2, X);
-                elem_point(X, NODE_ST[a2][0], NODE_ST[a2][1], y, n, &J, L);
+                load_elem(nn, xyz, elem + nn * e2, X);
+                elem_point(nn, X, NODE_ST[a2][0], NODE_ST[a2][1], y, n, &J, L);
                 int64_t hit = -1;
                 for (int64_t c = first_dof; c < n_dof; c++) {
                     const double *r = nrm[ref[c]];
@@ -163,7 +191,7 @@ int or_index_dofs(const double *xyz, int64_t n_nodes, const int32_t *elem, int64
                     dof_node[hit] = g;
                     dof_normal[3 * hit] = dof_normal[3 * hit + 1] = dof_normal[3 * hit + 2] = 0.0;
                 }
-                elem_dofs[6 * e2 + a2] = (int32_t)hit;
+                elem_dofs[nn * e2 + a2] = (int32_t)hit;
                 for (int d = 0; d < 3; d++) dof_normal[3 * hit + d] += n[d];
             }
         }
@@ -342,17 +370,17 @@ static void kernel(int green, double k, const double x[3], const double y[3], co
 }
 
 /* Integrals over one element of L_a G and L_a dG/dn1 for target x. */
-static void elem_integrals(const double X[6][3], const double x[3], int green, double k,
+static void elem_integrals(int nn, const double X[6][3], const double x[3], int green, double k,
                            const rule_t *r, cplx S[6], cplx K[6])
 {
     for (int a = 0; a < 6; a++) S[a] = K[a] = 0.0;
     for (int q = 0; q < r->n; q++) {
         double y[3], n[3], J, L[6];
         cplx G, dG;
-        elem_point(X, r->s[q], r->t[q], y, n, &J, L);
+        elem_point(nn, X, r->s[q], r->t[q], y, n, &J, L);
         kernel(green, k, x, y, n, &G, &dG);
         double wj = r->w[q] * J;
-        for (int a = 0; a < 6; a++) {
+        for (int a = 0; a < nn; a++) {
             S[a] += wj * L[a] * G;
             K[a] += wj * L[a] * dG;
         }
@@ -371,16 +399,16 @@ static void elem_integrals(const double X[6][3], const double x[3], int green, d
 #define CL_NEAR 1
 #define CL_SINGULAR 2
 
-static int classify(const double *xyz, const int32_t *en, int32_t tgt_node, const double x[3],
+static int classify(int nn, const double *xyz, const int32_t *en, int32_t tgt_node, const double x[3],
                     int *param)
 {
-    for (int a = 0; a < 6; a++)
+    for (int a = 0; a < nn; a++)
         if (en[a] == tgt_node) { *param = a; return CL_SINGULAR; }
     double cm[3];
     for (int d = 0; d < 3; d++)
         cm[d] = ((xyz[3 * (int64_t)en[0] + d] + xyz[3 * (int64_t)en[1] + d]) + xyz[3 * (int64_t)en[2] + d]) / 3.0;
     double h2 = 0.0;
-    for (int a = 0; a < 6; a++) {
+    for (int a = 0; a < nn; a++) {
         const double *p = xyz + 3 * (int64_t)en[a];
         double dx = p[0] - cm[0], dy = p[1] - cm[1], dz = p[2] - cm[2];
         double v = (dx * dx + dy * dy) + dz * dz;
@@ -396,25 +424,25 @@ static int classify(const double *xyz, const int32_t *en, int32_t tgt_node, cons
     return CL_NEAR;
 }
 
-int or_classify(const double *xyz, const int32_t *en, int32_t tgt_node, const double *x, int *param)
+int or_classify(int nn, const double *xyz, const int32_t *en, int32_t tgt_node, const double *x, int *param)
 {
     *param = 0;
-    return classify(xyz, en, tgt_node, x, param);
+    return classify(nn, xyz, en, tgt_node, x, param);
 }
 
 #define NGAUSS 12
 
 /* Accurate (S, K) integrals of one (target, element) pair, and the same
  * with the 7-point rule; kind is the classification.                     */
-static int pair_integrals(const double *xyz, const int32_t *en, int32_t tgt_node, const double x[3],
+static int pair_integrals(int nn, const double *xyz, const int32_t *en, int32_t tgt_node, const double x[3],
                           int green, double k, cplx S[6], cplx K[6], cplx Sr[6], cplx Kr[6])
 {
     double X[6][3];
-    load_elem(xyz, en, X);
+    load_elem(nn, xyz, en, X);
     static __thread rule_t reg, acc;
     rule_regular(&reg);
-    elem_integrals(X, x, green, k, &reg, Sr, Kr);
-    int param = 0, cls = green == OR_R2 ? CL_REGULAR : classify(xyz, en, tgt_node, x, &param);
+    elem_integrals(nn, X, x, green, k, &reg, Sr, Kr);
+    int param = 0, cls = green == OR_R2 ? CL_REGULAR : classify(nn, xyz, en, tgt_node, x, &param);
     if (cls == CL_REGULAR) {
         memcpy(S, Sr, 6 * sizeof(cplx));
         memcpy(K, Kr, 6 * sizeof(cplx));
@@ -422,16 +450,16 @@ static int pair_integrals(const double *xyz, const int32_t *en, int32_t tgt_node
     }
     if (cls == CL_SINGULAR) rule_singular(&acc, param, NGAUSS);
     else rule_subdiv(&acc, param);
-    elem_integrals(X, x, green, k, &acc, S, K);
+    elem_integrals(nn, X, x, green, k, &acc, S, K);
     return cls;
 }
 
 /* Exported for tests: accurate integrals of one pair (interleaved complex). */
-int or_pair(const double *xyz, const int32_t *en, int32_t tgt_node, const double *x, int green,
+int or_pair(int nn, const double *xyz, const int32_t *en, int32_t tgt_node, const double *x, int green,
             double k, double *S12, double *K12)
 {
     cplx S[6], K[6], Sr[6], Kr[6];
-    int c = pair_integrals(xyz, en, tgt_node, x, green, k, S, K, Sr, Kr);
+    int c = pair_integrals(nn, xyz, en, tgt_node, x, green, k, S, K, Sr, Kr);
     for (int a = 0; a < 6; a++) {
         S12[2 * a] = creal(S[a]); S12[2 * a + 1] = cimag(S[a]);
         K12[2 * a] = creal(K[a]); K12[2 * a + 1] = cimag(K[a]);
@@ -446,8 +474,9 @@ int or_pair(const double *xyz, const int32_t *en, int32_t tgt_node, const double
 /* ------------------------------------------------------------------ */
 typedef struct {
     const double *xyz;
-    const int32_t *elem, *elem_dofs, *dof_node;
+    const int32_t *elem, *elem_dofs, *dof_node; /* elem, elem_dofs: [n_el][nn] */
     int64_t n_el, n_dof;
+    int nn; /* nodes per element: 3 (first order) or 6 (second order) */
 } mesh_t;
 
 /* One row: S_i., K_i. (dense, length n_dof) and the free term c_i. */
@@ -457,12 +486,12 @@ static void assemble_row(const mesh_t *m, int64_t i, int green, double k, int re
     const double *x = m->xyz + 3 * (int64_t)m->dof_node[i];
     double k0sum = 0.0;
     for (int64_t e = 0; e < m->n_el; e++) {
-        const int32_t *en = m->elem + 6 * e;
+        const int32_t *en = m->elem + m->nn * e;
         cplx S[6], K[6], Sr[6], Kr[6];
-        int cls = pair_integrals(m->xyz, en, m->dof_node[i], x, green, k, S, K, Sr, Kr);
+        int cls = pair_integrals(m->nn, m->xyz, en, m->dof_node[i], x, green, k, S, K, Sr, Kr);
         if (regular_only) { memcpy(S, Sr, sizeof S); memcpy(K, Kr, sizeof K); }
-        for (int a = 0; a < 6; a++) {
-            int32_t j = m->elem_dofs[6 * e + a];
+        for (int a = 0; a < m->nn; a++) {
+            int32_t j = m->elem_dofs[m->nn * e + a];
             if (Srow) Srow[j] += S[a];
             if (Krow) Krow[j] += K[a];
         }
@@ -472,14 +501,14 @@ static void assemble_row(const mesh_t *m, int64_t i, int green, double k, int re
             else if (cls == CL_REGULAR) {
                 double X[6][3];
                 rule_t reg;
-                load_elem(m->xyz, en, X);
+                load_elem(m->nn, m->xyz, en, X);
                 rule_regular(&reg);
-                elem_integrals(X, x, OR_LAPLACE, 0.0, &reg, S0, K0);
+                elem_integrals(m->nn, X, x, OR_LAPLACE, 0.0, &reg, S0, K0);
             } else {
                 cplx a1[6], a2[6];
-                pair_integrals(m->xyz, en, m->dof_node[i], x, OR_LAPLACE, 0.0, S0, K0, a1, a2);
+                pair_integrals(m->nn, m->xyz, en, m->dof_node[i], x, OR_LAPLACE, 0.0, S0, K0, a1, a2);
             }
-            for (int a = 0; a < 6; a++) k0sum += creal(K0[a]);
+            for (int a = 0; a < m->nn; a++) k0sum += creal(K0[a]);
         }
     }
     if (c) *c = 1.0 + k0sum;
@@ -487,10 +516,10 @@ static void assemble_row(const mesh_t *m, int64_t i, int green, double k, int re
 
 /* Dense S, K (row-major n x n, interleaved complex) and free term c. */
 int or_assemble(const double *xyz, const int32_t *elem, const int32_t *elem_dofs,
-                const int32_t *dof_node, int64_t n_el, int64_t n_dof, int green, double k,
+                const int32_t *dof_node, int64_t n_el, int64_t n_dof, int nn, int green, double k,
                 double *S, double *K, double *c)
 {
-    mesh_t m = {xyz, elem, elem_dofs, dof_node, n_el, n_dof};
+    mesh_t m = {xyz, elem, elem_dofs, dof_node, n_el, n_dof, nn};
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < n_dof; i++) {
         cplx *Sr = (cplx *)S + i * n_dof, *Kr = (cplx *)K + i * n_dof;
@@ -502,10 +531,10 @@ int or_assemble(const double *xyz, const int32_t *elem, const int32_t *elem_dofs
 
 /* Direct matrix-vector product on selected rows.  x, y interleaved complex. */
 int or_matvec_rows(const double *xyz, const int32_t *elem, const int32_t *elem_dofs,
-                   const int32_t *dof_node, int64_t n_el, int64_t n_dof, int green, double k,
+                   const int32_t *dof_node, int64_t n_el, int64_t n_dof, int nn, int green, double k,
                    int op, const double *x, const int64_t *rows, int64_t nrows, double *y)
 {
-    mesh_t m = {xyz, elem, elem_dofs, dof_node, n_el, n_dof};
+    mesh_t m = {xyz, elem, elem_dofs, dof_node, n_el, n_dof, nn};
     const cplx *xc = (const cplx *)x;
     cplx *yc = (cplx *)y;
     int regular = (op == OP_S_REG || op == OP_K_REG);
@@ -533,10 +562,10 @@ int or_matvec_rows(const double *xyz, const int32_t *elem, const int32_t *elem_d
 
 /* Free term alone on selected rows. */
 int or_free_term(const double *xyz, const int32_t *elem, const int32_t *elem_dofs,
-                 const int32_t *dof_node, int64_t n_el, int64_t n_dof, const int64_t *rows,
+                 const int32_t *dof_node, int64_t n_el, int64_t n_dof, int nn, const int64_t *rows,
                  int64_t nrows, double *c)
 {
-    mesh_t m = {xyz, elem, elem_dofs, dof_node, n_el, n_dof};
+    mesh_t m = {xyz, elem, elem_dofs, dof_node, n_el, n_dof, nn};
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t r = 0; r < nrows; r++) assemble_row(&m, rows[r], OR_LAPLACE, 0.0, 0, NULL, NULL, c + r);
     return 0;
@@ -545,7 +574,7 @@ int or_free_term(const double *xyz, const int32_t *elem, const int32_t *elem_dof
 /* Potential of single/double layer densities at arbitrary points (regular
  * and near-singular rules only: the points must not lie on the surface). */
 int or_layer_potential(const double *xyz, const int32_t *elem, const int32_t *elem_dofs,
-                       int64_t n_el, int green, double k, const double *sig_s,
+                       int64_t n_el, int nn, int green, double k, const double *sig_s,
                        const double *sig_d, const double *pts, int64_t npts, double *out)
 {
     const cplx *ss = (const cplx *)sig_s, *sd = (const cplx *)sig_d;
@@ -555,9 +584,9 @@ int or_layer_potential(const double *xyz, const int32_t *elem, const int32_t *el
         cplx acc = 0.0;
         for (int64_t e = 0; e < n_el; e++) {
             cplx S[6], K[6], Sr[6], Kr[6];
-            pair_integrals(xyz, elem + 6 * e, -1, pts + 3 * p, green, k, S, K, Sr, Kr);
-            for (int a = 0; a < 6; a++) {
-                int32_t j = elem_dofs[6 * e + a];
+            pair_integrals(nn, xyz, elem + nn * e, -1, pts + 3 * p, green, k, S, K, Sr, Kr);
+            for (int a = 0; a < nn; a++) {
+                int32_t j = elem_dofs[nn * e + a];
                 if (ss) acc += S[a] * ss[j];
                 if (sd) acc += K[a] * sd[j];
             }
@@ -725,7 +754,7 @@ static int cmp_i64(const void *a, const void *b)
     return x < y ? -1 : (x > y);
 }
 
-void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int64_t n_el,
+void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int64_t n_el, int nn,
                     const double *tgt_xyz, int64_t n_tgt, int B, int max_depth, double theta,
                     double kappa, double k)
 {
@@ -751,7 +780,7 @@ void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int
     kv_t *ek = malloc((n_el > 0 ? n_el : 1) * sizeof *ek), *tk = malloc((n_tgt > 0 ? n_tgt : 1) * sizeof *tk);
     for (int64_t e = 0; e < n_el; e++) {
         double p[3];
-        const int32_t *en = elem + 6 * e;
+        const int32_t *en = elem + nn * e;
         for (int d = 0; d < 3; d++)
             p[d] = ((xyz[3 * (int64_t)en[0] + d] + xyz[3 * (int64_t)en[1] + d]) + xyz[3 * (int64_t)en[2] + d]) / 3.0;
         ek[e].key = morton(p, T->corner, scale);
@@ -808,8 +837,8 @@ void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int
         double r = 0.0;
         if (x->leaf) {
             for (int64_t e = x->eb; e < x->ee; e++)
-                for (int a = 0; a < 6; a++) {
-                    double v = dist3(xyz + 3 * (int64_t)elem[6 * T->eperm[e] + a], x->c);
+                for (int a = 0; a < nn; a++) {
+                    double v = dist3(xyz + 3 * (int64_t)elem[nn * T->eperm[e] + a], x->c);
                     if (v > r) r = v;
                 }
             for (int64_t i = x->tb; i < x->te; i++) {
@@ -1031,13 +1060,13 @@ static double ipow(double x, int n) { double r = 1.0; for (int i = 0; i < n; i++
 /* and a child's locals are the parent's truncated to the child's order     */
 /* (Eq. 11); a translation (Eq. 9) maps order L_source to order L_target.   */
 int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const int32_t *elem_dofs,
-                  const int32_t *dof_node, int64_t n_el, int64_t n_dof, int green, double k,
+                  const int32_t *dof_node, int64_t n_el, int64_t n_dof, int nn, int green, double k,
                   int order, int order_min, int op, const double *x_in, double *y_out)
 {
     const otree_t *T = h;
     const cplx *x = (const cplx *)x_in;
     cplx *y = (cplx *)y_out;
-    mesh_t m = {xyz, elem, elem_dofs, dof_node, n_el, n_dof};
+    mesh_t m = {xyz, elem, elem_dofs, dof_node, n_el, n_dof, nn};
     int p = order, P = ncoef(p), P2 = ncoef(2 * p);
     int dbl = (op == OP_K || op == OP_A || op == OP_K_REG);
     int regular_only = (op == OP_S_REG || op == OP_K_REG);
@@ -1053,12 +1082,12 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
     for (int64_t se = 0; se < n_el; se++) {
         int64_t e = T->eperm[se];
         double X[6][3];
-        load_elem(xyz, elem + 6 * e, X);
+        load_elem(nn, xyz, elem + nn * e, X);
         for (int q = 0; q < 7; q++) {
             double L[6], J;
-            elem_point(X, reg.s[q], reg.t[q], qy[7 * se + q], qn[7 * se + q], &J, L);
+            elem_point(nn, X, reg.s[q], reg.t[q], qy[7 * se + q], qn[7 * se + q], &J, L);
             cplx sig = 0.0;
-            for (int a = 0; a < 6; a++) sig += L[a] * x[elem_dofs[6 * e + a]];
+            for (int a = 0; a < nn; a++) sig += L[a] * x[elem_dofs[nn * e + a]];
             qs[7 * se + q] = sig * (reg.w[q] * J);
         }
     }
@@ -1179,11 +1208,11 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
             cplx acc = 0.0;
             for (int64_t e = 0; e < n_el; e++) {
                 int param;
-                if (classify(xyz, elem + 6 * e, dof_node[i], xi, &param) == CL_REGULAR) continue;
+                if (classify(nn, xyz, elem + nn * e, dof_node[i], xi, &param) == CL_REGULAR) continue;
                 cplx S[6], K[6], Sr[6], Kr[6];
-                pair_integrals(xyz, elem + 6 * e, dof_node[i], xi, green, k, S, K, Sr, Kr);
-                for (int a = 0; a < 6; a++)
-                    acc += (dbl ? (K[a] - Kr[a]) : (S[a] - Sr[a])) * x[elem_dofs[6 * e + a]];
+                pair_integrals(nn, xyz, elem + nn * e, dof_node[i], xi, green, k, S, K, Sr, Kr);
+                for (int a = 0; a < nn; a++)
+                    acc += (dbl ? (K[a] - Kr[a]) : (S[a] - Sr[a])) * x[elem_dofs[nn * e + a]];
             }
             yo[i] += acc;
         }
@@ -1194,7 +1223,7 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
         c = malloc(n_dof * sizeof(double));
         int64_t *rows = malloc(n_dof * sizeof(int64_t));
         for (int64_t i = 0; i < n_dof; i++) rows[i] = i;
-        or_free_term(xyz, elem, elem_dofs, dof_node, n_el, n_dof, rows, n_dof, c);
+        or_free_term(xyz, elem, elem_dofs, dof_node, n_el, n_dof, nn, rows, n_dof, c);
         free(rows);
     }
     for (int64_t i = 0; i < n_dof; i++) {
