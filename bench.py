@@ -299,12 +299,14 @@ def main():
 def paper_protocol():
     """Section 4's test run the paper's way: a unit point source at
     (0.1, 0.2, 0.3) inside spheres of 162 ... 40962 nodes (second-order
-    elements), the Neumann data given and the surface potential recovered by
-    BiCGSTAB; FMM with the level-dependent order L_l = min(8, L_min + l_max -
-    l) at L_min = 3 and 4, the leaf size growing with N as in the tables
-    (B = 8 ... 128 nodes, here B/2 elements: a quadratic mesh has two nodes
-    per element) and the paper's separation test (theta = 1).  Laplace as in
-    Table 2, Helmholtz k = 2 as in Table 6.  One JSON line per row: N, B,
+    elements) or 42 ... 10242 nodes (first-order), the Neumann data given and
+    the surface potential recovered by BiCGSTAB; FMM with the level-dependent
+    order L_l = min(8, L_min + l_max - l) at L_min = 3 and 4, the leaf size
+    growing with N as in the tables (B = 8 ... 128 nodes, here B/2 elements
+    for the quadratic meshes, which have two nodes per element, and 2B for
+    the flat ones, which have one node per two elements) and the paper's
+    separation test (theta = 1).  Laplace as in Tables 1 and 2, Helmholtz
+    k = 2 as in Tables 5 and 6.  One JSON line per row: N, B,
     the rms error against the exact potential (absolute and relative), setup
     and solve times, the peak device bytes of the context and the FP64
     product time.  Rows with L_min = 8 are the uniform order-8 product on the
@@ -315,15 +317,17 @@ def paper_protocol():
     import paper_0908_0673_amd as bem
 
     xs = np.array([0.1, 0.2, 0.3])
-    for green, k, table in ((0, 0.0, "table2_laplace"), (1, 2.0, "table6_helmholtz_k2")):
+    cases = ((0, 0.0, "table2_laplace", 6), (1, 2.0, "table6_helmholtz_k2", 6),
+             (0, 0.0, "table1_laplace_p1", 3), (1, 2.0, "table5_helmholtz_k2_p1", 3))
+    for green, k, table, nn in cases:
         for s, Bp in zip(range(1, 6), (8, 16, 32, 64, 128)):
-            m = bem_inputs.icosphere(s)
+            m = bem_inputs.icosphere(s) if nn == 6 else bem_inputs.linear(bem_inputs.icosphere(s))
+            Be = max(4, Bp // 2) if nn == 6 else 2 * Bp
             for omin in (3, 4, 0):
                 t0 = time.perf_counter()
                 ctx = bem.Context(0)
                 mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
-                tree = bem.bem_tree_build(ctx, mesh, B=max(4, Bp // 2), order=8, theta=1.0, order_min=omin,
-                                          k_hint=k)
+                tree = bem.bem_tree_build(ctx, mesh, B=Be, order=8, theta=1.0, order_min=omin, k_hint=k)
                 d = mesh.dofs()
                 r = d["dof_xyz"] - xs[None, :]
                 R = np.linalg.norm(r, axis=1)
@@ -354,8 +358,9 @@ def paper_protocol():
                     bem.bem_matvec(ctx, tree, green, k, bem.BEM_OP_A, bem.BEM_FMM, bem.BEM_PREC_FP64, chid, y)
                 torch.cuda.synchronize()
                 ms_prod = (time.perf_counter() - t1) / 20 * 1e3
-                row = {"protocol": table, "N": int(mesh.n_dof), "n_elem": int(m.n_elem), "B_nodes": Bp,
-                       "B_elems": max(4, Bp // 2), "L_min": omin if omin else 8, "L_max": 8, "theta": 1.0,
+                row = {"protocol": table, "N": int(m.n_nodes), "n_dof": int(mesh.n_dof), "n_elem": int(m.n_elem),
+                       "nodes_per_elem": nn, "B_nodes": Bp, "B_elems": Be, "L_min": omin if omin else 8, "L_max": 8,
+                       "theta": 1.0,
                        "max_level": int(tree.export()["level"].max()),
                        "eps_rms": err, "eps_rms_rel": err / float(np.sqrt(np.mean(np.abs(ref) ** 2))),
                        "t_setup_s": t_setup, "t_solve_s": best, "iterations": info["iterations"],

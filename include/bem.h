@@ -133,13 +133,17 @@ int bem_ctx_device_bytes(bem_ctx *ctx, int reset_peak, int64_t *live, int64_t *p
 /* ------------------------------------------------------------------ mesh */
 typedef struct {
     double edge_angle_deg; /* normals closer than this share a DOF (Section 2.3); 0 -> 30 */
+    int nodes_per_elem;    /* 6 (second-order curved triangles) or 3 (first-order flat
+                              triangles, unknowns linear over each); 0 -> 6 */
 } bem_mesh_opts;
 
-/* Loads a mesh of 6-node triangles (Section 2.2).
+/* Loads a mesh of 6-node or 3-node triangles (Section 2.2).
  *   node_xyz   host [n_nodes][3] float64 node coordinates
  *   elem_nodes host [n_elem][6] int32: corners 0,1,2 counter-clockwise seen
  *              from outside the body, then the mid-side nodes of edges 0-1,
- *              1-2 and 2-0 (isoparametric: geometry and data share nodes)
+ *              1-2 and 2-0 (isoparametric: geometry and data share nodes);
+ *              with opts->nodes_per_elem = 3, [n_elem][3]: the corners of
+ *              flat triangles, the data linear over each
  * Collocation points are the nodes.  Nodes where the element normals differ
  * by more than opts->edge_angle_deg get one DOF per group of normals (sharp
  * edges and corners, Section 2.3); elements are visited in order and each
@@ -150,7 +154,7 @@ int bem_mesh_load(bem_ctx *ctx, const double *node_xyz, int64_t n_nodes, const i
                   int64_t n_elem, const bem_mesh_opts *opts, bem_mesh **out);
 
 /* Copies the DOF layout to host buffers (each may be NULL):
- *   elem_dofs [n_elem][6] int32, dof_node [n_dof] int32 (geometric node of a
+ *   elem_dofs [n_elem][nodes_per_elem] int32, dof_node [n_dof] int32 (geometric node of a
  *   DOF), dof_xyz [n_dof][3], dof_normal [n_dof][3] (normalised mean of the
  *   element normals of the DOF's group). */
 int bem_mesh_dofs(const bem_mesh *mesh, int64_t *n_dof, int32_t *elem_dofs, int32_t *dof_node,

@@ -52,7 +52,7 @@ class _Allocator(ctypes.Structure):
 
 
 class _MeshOpts(ctypes.Structure):
-    _fields_ = [("edge_angle_deg", ctypes.c_double)]
+    _fields_ = [("edge_angle_deg", ctypes.c_double), ("nodes_per_elem", ctypes.c_int)]
 
 
 class _TreeOpts(ctypes.Structure):
@@ -244,8 +244,11 @@ class Mesh:
         self.ctx = ctx
         xyz = np.ascontiguousarray(xyz, np.float64)
         elem = np.ascontiguousarray(elem, np.int32)
+        if elem.ndim != 2 or elem.shape[1] not in (3, 6):
+            raise ValueError("elements need 3 or 6 nodes")
         h = ctypes.c_void_p()
-        opts = _MeshOpts(edge_angle_deg)
+        self.nodes_per_elem = int(elem.shape[1])
+        opts = _MeshOpts(edge_angle_deg, self.nodes_per_elem)
         ctx.check(ctx.L.bem_mesh_load(ctx.h, _np_ptr(xyz), xyz.shape[0], _np_ptr(elem), elem.shape[0],
                                       ctypes.byref(opts), ctypes.byref(h)), "bem_mesh_load")
         self.h = h
@@ -257,7 +260,7 @@ class Mesh:
 
     def dofs(self):
         n = self.n_dof
-        ed = np.zeros((self.n_elem, 6), np.int32)
+        ed = np.zeros((self.n_elem, self.nodes_per_elem), np.int32)
         dn = np.zeros(n, np.int32)
         dx = np.zeros((n, 3))
         nr = np.zeros((n, 3))
@@ -426,8 +429,11 @@ class Server:
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         elem = np.ascontiguousarray(elem, dtype=np.int32)
         mid, nd = ctypes.c_int32(), ctypes.c_int64()
+        if elem.ndim != 2 or elem.shape[1] not in (3, 6):
+            raise ValueError("elements need 3 or 6 nodes")
         rc = self.L.bem_server_add_mesh(self.h, _np_ptr(xyz), xyz.shape[0], _np_ptr(elem), elem.shape[0],
-                                        ctypes.byref(_MeshOpts(edge_angle_deg)), ctypes.byref(mid), ctypes.byref(nd))
+                                        ctypes.byref(_MeshOpts(edge_angle_deg, int(elem.shape[1]))),
+                                        ctypes.byref(mid), ctypes.byref(nd))
         if rc != 0:
             raise BemError(rc, "bem_server_add_mesh failed")
         self._ndof[mid.value] = nd.value

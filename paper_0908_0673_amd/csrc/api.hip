@@ -109,14 +109,11 @@ int bem_mesh_load(bem_ctx *ctx, const double *node_xyz, int64_t n_nodes, const i
         BEM_REQUIRE(n_elem >= 1 && n_nodes >= 3, BEM_EINVAL, "empty mesh");
         BEM_REQUIRE(n_elem < (int64_t)1 << 28, BEM_EINVAL, "too many elements");
         double tol = (opts && opts->edge_angle_deg > 0.0) ? opts->edge_angle_deg : 30.0;
+        const int nn = (opts && opts->nodes_per_elem) ? opts->nodes_per_elem : 6;
         m = new bem_mesh;
         m->ctx = &ctx->c;
-        m->n_nodes = n_nodes;
-        m->n_el = n_elem;
-        m->h_xyz.assign(node_xyz, node_xyz + 3 * n_nodes);
-        m->h_elem.assign(elem_nodes, elem_nodes + 6 * n_elem);
-        for (double v : m->h_xyz) BEM_REQUIRE(std::isfinite(v), BEM_EINVAL, "non-finite node coordinate");
-        bem::index_dofs(*m, tol);
+        bem::load_mesh_host(*m, node_xyz, n_nodes, elem_nodes, n_elem, nn, tol);
+        n_nodes = m->n_nodes;
         std::vector<double> dxyz(3 * m->n_dof);
         for (int64_t i = 0; i < m->n_dof; i++)
             for (int d = 0; d < 3; d++) dxyz[3 * i + d] = m->h_xyz[3 * (int64_t)m->h_dof_node[i] + d];
@@ -145,7 +142,11 @@ int bem_mesh_dofs(const bem_mesh *m, int64_t *n_dof, int32_t *elem_dofs, int32_t
                   double *dof_normal) {
     if (!m) return BEM_EINVAL;
     if (n_dof) *n_dof = m->n_dof;
-    if (elem_dofs) std::copy(m->h_elem_dofs.begin(), m->h_elem_dofs.end(), elem_dofs);
+    if (elem_dofs) {
+        const int nn = m->linear ? 3 : 6;  // the columns the mesh was given with
+        for (int64_t e = 0; e < m->n_el; e++)
+            for (int a = 0; a < nn; a++) elem_dofs[nn * e + a] = m->h_elem_dofs[6 * e + a];
+    }
     if (dof_node) std::copy(m->h_dof_node.begin(), m->h_dof_node.end(), dof_node);
     if (dof_normal) std::copy(m->h_dof_normal.begin(), m->h_dof_normal.end(), dof_normal);
     if (dof_xyz)

@@ -695,6 +695,10 @@ void rule_shapes(bem_tree &t) {
     for (int qq = 0; qq < 7; qq++) {
         double S_ = rs[qq], T_ = rt[qq], Z = 1.0 - S_ - T_;
         double L[6] = {Z * (2 * Z - 1), S_ * (2 * S_ - 1), T_ * (2 * T_ - 1), 4 * Z * S_, 4 * S_ * T_, 4 * T_ * Z};
+        if (t.mesh->linear) {  // first-order elements: linear on the corners, nothing on the mid-side slots
+            L[0] = Z; L[1] = S_; L[2] = T_;
+            L[3] = L[4] = L[5] = 0.0;
+        }
         for (int a = 0; a < 6; a++) L7[6 * qq + a] = L[a];
     }
     t.L7.alloc(t.ctx, 42);

@@ -14,6 +14,9 @@ struct bem_ctx {
 struct bem_mesh {
     bem::Ctx *ctx = nullptr;
     int64_t n_nodes = 0, n_el = 0, n_dof = 0;
+    // first-order (3-node flat) elements, carried as 6-node elements whose
+    // mid-side nodes are appended edge midpoints (see load_mesh_host)
+    bool linear = false;
     std::vector<double> h_xyz, h_dof_normal;
     std::vector<int32_t> h_elem, h_elem_dofs, h_dof_node;
     bem::DBuf<double> xyz;        // [n_nodes][3]
@@ -205,6 +208,9 @@ void radix_sort_pairs(Ctx &c, uint64_t *keys, int32_t *vals, int64_t n, int key_
 
 // mesh.cpp (host)
 void index_dofs(bem_mesh &m, double tol_deg);
+// host arrays of a mesh from nn-node elements (nn = 6 or 3) and its DOF indexing
+void load_mesh_host(bem_mesh &m, const double *xyz, int64_t n_nodes, const int32_t *elem, int64_t n_el, int nn,
+                    double tol_deg);
 
 // tree.hip
 void build_tree(bem_tree &t);

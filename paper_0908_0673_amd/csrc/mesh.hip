@@ -8,6 +8,15 @@
 // otherwise it starts a new group.  Each group is one DOF; its normal is the
 // normalised sum of its members.  On a smooth surface every node gets one DOF;
 // a cube edge node gets two and a corner three.
+//
+// First-order elements (Section 2.2: flat 3-node triangles, unknowns
+// interpolated linearly between the corners) are carried as 6-node elements
+// whose mid-side nodes are the edge midpoints, appended after the given
+// nodes (three per element).  The quadratic map through them is the flat
+// map, so geometry, tree and quadrature run unchanged; only the corners carry
+// DOFs, the unknowns use the linear shape functions 1 - s - t, s, t (rule
+// tables and correction integrals), and an element's mid-side slots refer to
+// the DOFs of its corners 0, 1, 2 with shape function zero.
 #include <cmath>
 
 #include "kernels.h"
@@ -43,15 +52,18 @@ double node_normal(const double *xyz, const int32_t *en, double s, double t, dou
 
 void index_dofs(bem_mesh &m, double tol_deg) {
     const int64_t nn = m.n_nodes, ne = m.n_el;
+    const int na = m.linear ? 3 : 6;  // slots that carry DOFs
     const int32_t *el = m.h_elem.data();
     for (int64_t i = 0; i < 6 * ne; i++)
         BEM_REQUIRE(el[i] >= 0 && el[i] < nn, BEM_EINVAL, "element node index out of range");
-    // node -> incidences (6 e + a), in element order
+    // node -> incidences (6 e + a, a < na), in element order
     std::vector<int64_t> start(nn + 1, 0);
-    for (int64_t i = 0; i < 6 * ne; i++) start[el[i] + 1]++;
+    for (int64_t i = 0; i < 6 * ne; i++)
+        if (i % 6 < na) start[el[i] + 1]++;
     for (int64_t g = 0; g < nn; g++) start[g + 1] += start[g];
-    std::vector<int64_t> inc(6 * ne), fill(start.begin(), start.end() - 1);
-    for (int64_t i = 0; i < 6 * ne; i++) inc[fill[el[i]]++] = i;
+    std::vector<int64_t> inc(start[nn]), fill(start.begin(), start.end() - 1);
+    for (int64_t i = 0; i < 6 * ne; i++)
+        if (i % 6 < na) inc[fill[el[i]]++] = i;
 
     // normals of every incidence
     std::vector<double> nrm(18 * ne);
@@ -67,7 +79,7 @@ void index_dofs(bem_mesh &m, double tol_deg) {
     m.h_dof_normal.clear();
     std::vector<int64_t> group_ref;  // incidence holding each group's reference normal
     for (int64_t e = 0; e < ne; e++) {
-        for (int a = 0; a < 6; a++) {
+        for (int a = 0; a < na; a++) {
             if (m.h_elem_dofs[6 * e + a] >= 0) continue;
             const int32_t g = el[6 * e + a];
             const int64_t first = (int64_t)m.h_dof_node.size();
@@ -96,6 +108,36 @@ void index_dofs(bem_mesh &m, double tol_deg) {
         double l = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         for (int d = 0; d < 3; d++) v[d] /= l;
     }
+    if (m.linear)  // mid-side slots: a corner's DOF, weighted by a zero shape function
+        for (int64_t e = 0; e < ne; e++)
+            for (int a = 3; a < 6; a++) m.h_elem_dofs[6 * e + a] = m.h_elem_dofs[6 * e + a - 3];
+}
+
+void load_mesh_host(bem_mesh &m, const double *xyz, int64_t n_nodes, const int32_t *elem, int64_t n_el, int nn,
+                    double tol_deg) {
+    BEM_REQUIRE(nn == 3 || nn == 6, BEM_EINVAL, "elements need 3 or 6 nodes");
+    for (int64_t i = 0; i < (int64_t)nn * n_el; i++)
+        BEM_REQUIRE(elem[i] >= 0 && elem[i] < n_nodes, BEM_EINVAL, "element node index out of range");
+    m.n_el = n_el;
+    m.linear = nn == 3;
+    m.h_xyz.assign(xyz, xyz + 3 * n_nodes);
+    for (double v : m.h_xyz) BEM_REQUIRE(std::isfinite(v), BEM_EINVAL, "non-finite node coordinate");
+    if (nn == 6) {
+        m.n_nodes = n_nodes;
+        m.h_elem.assign(elem, elem + 6 * n_el);
+    } else {
+        m.n_nodes = n_nodes + 3 * n_el;
+        m.h_xyz.resize(3 * m.n_nodes);
+        m.h_elem.resize(6 * n_el);
+        for (int64_t e = 0; e < n_el; e++)
+            for (int j = 0; j < 3; j++) {
+                const int64_t a = elem[3 * e + j], b = elem[3 * e + (j + 1) % 3], id = n_nodes + 3 * e + j;
+                for (int d = 0; d < 3; d++) m.h_xyz[3 * id + d] = 0.5 * (xyz[3 * a + d] + xyz[3 * b + d]);
+                m.h_elem[6 * e + j] = elem[3 * e + j];
+                m.h_elem[6 * e + 3 + j] = (int32_t)id;  // mid-side of edge j, j + 1
+            }
+    }
+    index_dofs(m, tol_deg);
 }
 
 }  // namespace bem

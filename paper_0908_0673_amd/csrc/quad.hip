@@ -170,11 +170,13 @@ __global__ void k_pairs(int64_t n_tgt, const double *t64, const int32_t *tperm, 
 }
 
 // One wave per pair: (accurate rule - 7-point rule) integrals of L_a G and L_a dG/dn1.
+// lin: first-order elements, L = (1 - s - t, s, t, 0, 0, 0) (the element map
+// stays the quadratic one through the edge midpoints, which is flat).
 template <bool HELM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HELM ? 1 : 4, HELM ? 2 : 4)))
 k_corr_values(int64_t n_pairs, const int32_t *pair_elem, const int32_t *pair_info, const int32_t *pair_row,
-              const double *t64, int64_t n_tgt, const int32_t *se_nodes, const double *xyz, double k, Gauss gq_arg,
-              R7 r7_arg, double *Sout, double *Kout) {
+              const double *t64, int64_t n_tgt, const int32_t *se_nodes, const double *xyz, double k, int lin,
+              Gauss gq_arg, R7 r7_arg, double *Sout, double *Kout) {
     // the rules are indexed per point: kept in LDS (a by-value kernel
     // argument indexed at run time would be copied to scratch per thread)
     __shared__ Gauss gq;
@@ -258,6 +260,10 @@ k_corr_values(int64_t n_pairs, const int32_t *pair_elem, const int32_t *pair_inf
         }
         double y[3], n[3], J, L[6];
         elem_map(X, s, t, y, n, &J, L);
+        if (lin) {
+            L[0] = 1.0 - s - t; L[1] = s; L[2] = t;
+            L[3] = L[4] = L[5] = 0.0;
+        }
         double r[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
         double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
         double rn = r[0] * n[0] + r[1] * n[1] + r[2] * n[2];
@@ -353,12 +359,12 @@ Corr &get_corr(bem_tree &t, int green, double k) {
         unsigned nb = nblocks(t.n_pairs, 4);
         if (green == BEM_HELMHOLTZ)
             k_corr_values<true><<<nb, 256, 0, c.stream>>>(t.n_pairs, t.pair_elem.p, t.pair_info.p, t.pair_row.p,
-                                                          t.t64.p, t.n_tgt, t.se_nodes.p, t.mesh->xyz.p, k, gq, r7,
-                                                          cr->S.p, cr->K.p);
+                                                          t.t64.p, t.n_tgt, t.se_nodes.p, t.mesh->xyz.p, k,
+                                                          (int)t.mesh->linear, gq, r7, cr->S.p, cr->K.p);
         else
             k_corr_values<false><<<nb, 256, 0, c.stream>>>(t.n_pairs, t.pair_elem.p, t.pair_info.p, t.pair_row.p,
-                                                           t.t64.p, t.n_tgt, t.se_nodes.p, t.mesh->xyz.p, 0.0, gq,
-                                                           r7, cr->S.p, cr->K.p);
+                                                           t.t64.p, t.n_tgt, t.se_nodes.p, t.mesh->xyz.p, 0.0,
+                                                           (int)t.mesh->linear, gq, r7, cr->S.p, cr->K.p);
         BEM_LAUNCH_CHECK();
     }
     c.sync();

@@ -275,23 +275,22 @@ int bem_server_add_mesh(bem_server *s, const double *node_xyz, int64_t n_nodes, 
                         int64_t n_elem, const bem_mesh_opts *opts, int32_t *mesh_id, int64_t *n_dof) {
     if (!s || !node_xyz || !elem_nodes || !mesh_id || n_elem < 1 || n_nodes < 3) return BEM_EINVAL;
     auto me = std::make_unique<MeshEntry>();
-    me->xyz.assign(node_xyz, node_xyz + 3 * n_nodes);
-    me->elem.assign(elem_nodes, elem_nodes + 6 * n_elem);
     if (opts) me->mopts = *opts;
+    const int nn = me->mopts.nodes_per_elem ? me->mopts.nodes_per_elem : 6;
+    if (nn != 3 && nn != 6) return BEM_EINVAL;
+    me->xyz.assign(node_xyz, node_xyz + 3 * n_nodes);
+    me->elem.assign(elem_nodes, elem_nodes + (int64_t)nn * n_elem);
     me->n_nodes = n_nodes;
     me->n_elem = n_elem;
     // DOF indexing on the host, as bem_mesh_load does it
     try {
         bem_mesh tmp;
-        tmp.n_nodes = n_nodes;
-        tmp.n_el = n_elem;
-        tmp.h_xyz = me->xyz;
-        tmp.h_elem = me->elem;
-        for (double v : tmp.h_xyz)
-            if (!std::isfinite(v)) return BEM_EINVAL;
-        bem::index_dofs(tmp, me->mopts.edge_angle_deg > 0.0 ? me->mopts.edge_angle_deg : 30.0);
+        bem::load_mesh_host(tmp, node_xyz, n_nodes, elem_nodes, n_elem, nn,
+                            me->mopts.edge_angle_deg > 0.0 ? me->mopts.edge_angle_deg : 30.0);
         me->n_dof = tmp.n_dof;
-        me->elem_dofs = tmp.h_elem_dofs;
+        me->elem_dofs.resize((size_t)nn * n_elem);  // the columns the mesh was given with
+        for (int64_t e = 0; e < n_elem; e++)
+            for (int a = 0; a < nn; a++) me->elem_dofs[nn * e + a] = tmp.h_elem_dofs[6 * e + a];
         me->dof_node = tmp.h_dof_node;
         me->dof_normal = tmp.h_dof_normal;
     } catch (const bem::Error &e) {

@@ -50,6 +50,8 @@ def perturbed_sphere(sub: int, seed: int, amp: float = 0.02):
 
 
 def mesh_by_name(name: str):
+    if name.endswith("_p1"):  # first-order mesh on the corners of the named one
+        return bem_inputs.linear(mesh_by_name(name[:-3]))
     if name.startswith("perturbed"):
         return perturbed_sphere(3, 5)
     if name.startswith("ellipsoid"):
