@@ -297,31 +297,41 @@ def main():
 
 
 def paper_protocol():
-    """Section 4's test run the paper's way: a unit point source at
-    (0.1, 0.2, 0.3) inside spheres of 162 ... 40962 nodes (second-order
-    elements) or 42 ... 10242 nodes (first-order), the Neumann data given and
-    the surface potential recovered by BiCGSTAB; FMM with the level-dependent
-    order L_l = min(8, L_min + l_max - l) at L_min = 3 and 4, the leaf size
-    growing with N as in the tables (B = 8 ... 128 nodes, here B/2 elements
-    for the quadratic meshes, which have two nodes per element, and 2B for
-    the flat ones, which have one node per two elements) and the paper's
-    separation test (theta = 1).  Laplace as in Tables 1 and 2, Helmholtz
-    k = 2 as in Tables 5 and 6.  One JSON line per row: N, B,
-    the rms error against the exact potential (absolute and relative), setup
-    and solve times, the peak device bytes of the context and the FP64
-    product time.  Rows with L_min = 8 are the uniform order-8 product on the
-    same tree, for comparison."""
+    """Section 4's test run the paper's way, on the shapes of Tables 1-8: a
+    unit point source at (0.1, 0.2, 0.3) inside the unit sphere or the cube
+    of edge 2, the Neumann data given and the surface potential recovered by
+    BiCGSTAB (to 1e-8); FMM with the level-dependent order L_l = min(8, L_min
+    + l_max - l) at L_min = 3 (the tables' plain rows) and 4 (their starred
+    rows), beside uniform order 8; the paper's separation test (theta = 1);
+    the tables' leaf sizes B (nodes per box), here B/2 elements for
+    second-order meshes (two nodes per element) and 2B for first-order ones
+    (one node per two elements).  Spheres: icosphere refinements 1-5 (42 ...
+    10242 or 162 ... 40962 nodes).  Cubes: structured meshes stand in for the
+    paper's unstructured ones, with node counts near the tables' (98 ... 27746
+    first-order, 386 ... 27746 second-order).  Laplace (Tables 1-4) and
+    Helmholtz k = 2 (Tables 5-8).  One JSON line per row: N (nodes), B, the
+    rms error against the exact potential (absolute and relative), setup and
+    solve times, BiCGSTAB steps, the peak device bytes of the context and the
+    FP64 product time."""
     import torch
 
     import bem_inputs
     import paper_0908_0673_amd as bem
 
     xs = np.array([0.1, 0.2, 0.3])
-    cases = ((0, 0.0, "table2_laplace", 6), (1, 2.0, "table6_helmholtz_k2", 6),
-             (0, 0.0, "table1_laplace_p1", 3), (1, 2.0, "table5_helmholtz_k2_p1", 3))
-    for green, k, table, nn in cases:
-        for s, Bp in zip(range(1, 6), (8, 16, 32, 64, 128)):
-            m = bem_inputs.icosphere(s) if nn == 6 else bem_inputs.linear(bem_inputs.icosphere(s))
+    sphere = ((1, 8), (2, 16), (3, 32), (4, 64), (5, 128))
+    cube_p1 = ((4, 5), (8, 10), (17, 20), (35, 40), (68, 80))
+    cube_p2 = ((4, 10), (8, 20), (17, 40), (34, 80))
+    tables = (("table1", 0, "sphere", 3, sphere), ("table2", 0, "sphere", 6, sphere),
+              ("table3", 0, "cube", 3, cube_p1), ("table4", 0, "cube", 6, cube_p2),
+              ("table5", 1, "sphere", 3, sphere), ("table6", 1, "sphere", 6, ((1, 16), (2, 32), (3, 64), (4, 128))),
+              ("table7", 1, "cube", 3, cube_p1), ("table8", 1, "cube", 6, cube_p2))
+    for table, green, shape, nn, sizes in tables:
+        k = 2.0 if green else 0.0
+        for size, Bp in sizes:
+            m = bem_inputs.icosphere(size) if shape == "sphere" else bem_inputs.cube(size)
+            if nn == 3:
+                m = bem_inputs.linear(m)
             Be = max(4, Bp // 2) if nn == 6 else 2 * Bp
             for omin in (3, 4, 0):
                 t0 = time.perf_counter()
@@ -358,9 +368,9 @@ def paper_protocol():
                     bem.bem_matvec(ctx, tree, green, k, bem.BEM_OP_A, bem.BEM_FMM, bem.BEM_PREC_FP64, chid, y)
                 torch.cuda.synchronize()
                 ms_prod = (time.perf_counter() - t1) / 20 * 1e3
-                row = {"protocol": table, "N": int(m.n_nodes), "n_dof": int(mesh.n_dof), "n_elem": int(m.n_elem),
-                       "nodes_per_elem": nn, "B_nodes": Bp, "B_elems": Be, "L_min": omin if omin else 8, "L_max": 8,
-                       "theta": 1.0,
+                row = {"protocol": f"{table}_{shape}_p{1 if nn == 3 else 2}_{'helmholtz_k2' if green else 'laplace'}",
+                       "N": int(m.n_nodes), "n_dof": int(mesh.n_dof), "n_elem": int(m.n_elem), "B_nodes": Bp,
+                       "B_elems": Be, "L_min": omin if omin else 8, "L_max": 8, "theta": 1.0,
                        "max_level": int(tree.export()["level"].max()),
                        "eps_rms": err, "eps_rms_rel": err / float(np.sqrt(np.mean(np.abs(ref) ** 2))),
                        "t_setup_s": t_setup, "t_solve_s": best, "iterations": info["iterations"],
