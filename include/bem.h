@@ -173,6 +173,11 @@ typedef struct {
     int order_min;          /* L_min of the level-dependent order (Section 3.6): boxes at level l
                                use order min(order, order_min + l_max - l), l_max the deepest
                                level; 0 (or >= order) -> `order` at every level */
+    int attach_radii;       /* 1: a leaf's convergence radius also covers every node of every
+                               element attached to the geometric nodes of its targets (the
+                               paper's r_C, Section 3.6, over the elements attached to a leaf's
+                               vertices, Section 3.1); sources stay owned by one leaf each.
+                               0: owned elements and targets only */
 } bem_tree_opts;
 
 /* Builds the octree over the mesh on the device (Section 3.1): element keys

@@ -56,8 +56,8 @@ def lib():
         vp = ctypes.c_void_p
         i64 = ctypes.c_int64
         L.or_tree_build.restype = vp
-        L.or_tree_build.argtypes = [vp, i64, vp, i64, ctypes.c_int, vp, i64, ctypes.c_int, ctypes.c_int,
-                                    ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.or_tree_build.argtypes = [vp, i64, vp, i64, ctypes.c_int, vp, vp, i64, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.or_tree_sizes.argtypes = [vp, vp]
         L.or_tree_export.argtypes = [vp] + [vp] * 9
         L.or_tree_free.argtypes = [vp]
@@ -177,12 +177,16 @@ class OracleMesh:
 class OracleTree:
     """Recursive octree with radii and lists (Sections 3.1, 3.4, 3.6)."""
 
-    def __init__(self, mesh: OracleMesh, B=32, max_depth=21, theta=1.0, kappa=float("inf"), k=0.0):
+    def __init__(self, mesh: OracleMesh, B=32, max_depth=21, theta=1.0, kappa=float("inf"), k=0.0,
+                 attach=False):
+        """attach: leaf radii also cover the elements attached to the nodes of
+        the leaf's targets (the paper's r_C); sources stay single-owner."""
         self.mesh = mesh
         tgt = _c(mesh.dof_xyz, np.float64)
+        tnode = _c(mesh.dof_node, np.int32)
         self._h = lib().or_tree_build(_p(mesh.xyz), mesh.xyz.shape[0], _p(mesh.elem), mesh.n_el, mesh.nn,
-                                      _p(tgt), tgt.shape[0], int(B), int(max_depth), float(theta),
-                                      float(kappa), float(k))
+                                      _p(tgt), _p(tnode), tgt.shape[0], int(B), int(max_depth), float(theta),
+                                      float(kappa), float(k), int(bool(attach)))
         sz = np.zeros(4, np.int64)
         lib().or_tree_sizes(self._h, _p(sz))
         nb, nn, ni, ml = (int(v) for v in sz)

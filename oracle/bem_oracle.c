@@ -754,9 +754,13 @@ static int cmp_i64(const void *a, const void *b)
     return x < y ? -1 : (x > y);
 }
 
+/* attach != 0 (with tgt_node, the geometric node of each target): a leaf's */
+/* radius also covers every node of every element attached to the nodes of */
+/* its targets, as Section 3.6 defines r_C (the elements attached to a     */
+/* leaf's vertices, Section 3.1); sources stay owned by one leaf each.     */
 void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int64_t n_el, int nn,
-                    const double *tgt_xyz, int64_t n_tgt, int B, int max_depth, double theta,
-                    double kappa, double k)
+                    const double *tgt_xyz, const int32_t *tgt_node, int64_t n_tgt, int B, int max_depth,
+                    double theta, double kappa, double k, int attach)
 {
     otree_t *T = calloc(1, sizeof *T);
     T->n_el = n_el;
@@ -829,8 +833,21 @@ void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int
             p->nchild++;
         }
     }
+    /* elements holding each node (attach mode) */
+    int64_t *ns = NULL, *ne_of = NULL;
+    if (attach) {
+        ns = calloc(n_nodes + 1, sizeof *ns);
+        for (int64_t i = 0; i < nn * n_el; i++) ns[elem[i] + 1]++;
+        for (int64_t g = 0; g < n_nodes; g++) ns[g + 1] += ns[g];
+        int64_t *fill = malloc((n_nodes + 1) * sizeof *fill);
+        memcpy(fill, ns, (n_nodes + 1) * sizeof *fill);
+        ne_of = malloc((nn * n_el + 1) * sizeof *ne_of);
+        for (int64_t i = 0; i < nn * n_el; i++) ne_of[fill[elem[i]]++] = i / nn;
+        free(fill);
+    }
     /* Section 3.4: convergence radii.  Leaf: farthest node of an owned
-     * element or owned target from the centre.  Parent: Eq. 13.          */
+     * element or owned target from the centre (and, attach mode, of an
+     * element attached to a target's node).  Parent: Eq. 13.             */
     double sqrt3 = sqrt(3.0);
     for (int64_t b = T->n_box - 1; b >= 0; b--) {
         obox_t *x = &T->box[b];
@@ -844,6 +861,13 @@ void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int
             for (int64_t i = x->tb; i < x->te; i++) {
                 double v = dist3(tgt_xyz + 3 * T->tperm[i], x->c);
                 if (v > r) r = v;
+                if (!attach) continue;
+                int32_t g = tgt_node[T->tperm[i]];
+                for (int64_t p = ns[g]; p < ns[g + 1]; p++)
+                    for (int a = 0; a < nn; a++) {
+                        double w = dist3(xyz + 3 * (int64_t)elem[nn * ne_of[p] + a], x->c);
+                        if (w > r) r = w;
+                    }
             }
         } else {
             double rc = 0.0;
@@ -854,6 +878,8 @@ void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int
         }
         x->r = r;
     }
+    free(ns);
+    free(ne_of);
     /* Section 3.6: near-field and interaction lists, descending the tree;
      * Eq. 14 with a safety factor theta (paper: theta = 1) and, for
      * Helmholtz, the extra bound k (r1 + r2) <= kappa (paper: none).

@@ -58,7 +58,7 @@ class _MeshOpts(ctypes.Structure):
 class _TreeOpts(ctypes.Structure):
     _fields_ = [("max_elems_per_leaf", ctypes.c_int), ("order", ctypes.c_int), ("theta", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("max_depth", ctypes.c_int), ("k_hint", ctypes.c_double),
-                ("order_min", ctypes.c_int)]
+                ("order_min", ctypes.c_int), ("attach_radii", ctypes.c_int)]
 
 
 class _TreeView(ctypes.Structure):
@@ -282,9 +282,9 @@ class Mesh:
 
 class Tree:
     def __init__(self, ctx: Context, mesh: Mesh, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21, k_hint=0.0,
-                 order_min=0):
+                 order_min=0, attach_radii=False):
         self.ctx, self.mesh = ctx, mesh
-        opts = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min)
+        opts = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min, int(bool(attach_radii)))
         h = ctypes.c_void_p()
         ctx.check(ctx.L.bem_tree_build(ctx.h, mesh.h, ctypes.byref(opts), ctypes.byref(h)), "bem_tree_build")
         self.h = h
@@ -414,7 +414,7 @@ class Server:
             raise RuntimeError("no GPU visible: the library runs on gfx950 only")
         o = _ServerOpts()
         o.device, o.lanes, o.hbm_budget, o.max_batch_rhs = device, lanes, int(hbm_budget), max_batch_rhs
-        o.tree = _TreeOpts(B, order, theta, kappa, max_depth, 0.0, order_min)
+        o.tree = _TreeOpts(B, order, theta, kappa, max_depth, 0.0, order_min, 0)
         o.solve = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method, krylov)
         h = ctypes.c_void_p()
         rc = self.L.bem_server_create(ctypes.byref(o), ctypes.byref(h))

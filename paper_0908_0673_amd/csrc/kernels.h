@@ -124,6 +124,7 @@ struct bem_tree {
     const bem_mesh *mesh = nullptr;
     int B = 32, order = 8, max_depth = 21;
     int order_min = 0;  // level-dependent order when > 0 (see level_p)
+    bool attach = false;  // leaf radii over the elements attached to the leaf's target nodes
     double theta = 0.6, kappa = 0.0, k_hint = 0.0;
     int64_t n_box = 0, n_leaf = 0, n_near = 0, n_inter = 0, n_el = 0, n_tgt = 0, n_q = 0;
     int max_level = 0;

@@ -214,11 +214,12 @@ __device__ inline double dist3(const double *a, const double *b) {
     return sqrt((dx * dx + dy * dy) + dz * dz);
 }
 
-// one wave per leaf box
+// one wave per leaf box; with node_ptr (attached radii) the nodes of every
+// element holding a target's geometric node count too
 __global__ void k_leaf_radius(const int32_t *leaf, const int64_t *eb, const int64_t *ee, const int64_t *tb,
                               const int64_t *te, const double *centre, const int32_t *eperm, const int32_t *tperm,
-                              const int32_t *elem, const double *xyz, const double *dof_xyz, int64_t n_box,
-                              double *radius) {
+                              const int32_t *elem, const double *xyz, const double *dof_xyz, const int32_t *dof_node,
+                              const int64_t *node_ptr, const int32_t *node_elems, int64_t n_box, double *radius) {
     int64_t b = (int64_t)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
     if (b >= n_box || !leaf[b]) return;
@@ -230,7 +231,13 @@ __global__ void k_leaf_radius(const int32_t *leaf, const int64_t *eb, const int6
         double v = dist3(xyz + 3 * (int64_t)elem[6 * (int64_t)e + j % 6], c);
         r = fmax(r, v);
     }
-    for (int64_t j = tb[b] + lane; j < te[b]; j += 64) r = fmax(r, dist3(dof_xyz + 3 * (int64_t)tperm[j], c));
+    for (int64_t j = tb[b] + lane; j < te[b]; j += 64) {
+        r = fmax(r, dist3(dof_xyz + 3 * (int64_t)tperm[j], c));
+        if (!node_ptr) continue;
+        const int32_t g = dof_node[tperm[j]];
+        for (int64_t p = node_ptr[g]; p < node_ptr[g + 1]; p++)
+            for (int a = 0; a < 6; a++) r = fmax(r, dist3(xyz + 3 * (int64_t)elem[6 * (int64_t)node_elems[p] + a], c));
+    }
     r = wave_max(r);
     if (lane == 0) radius[b] = r;
 }
@@ -422,10 +429,31 @@ void build_tree(bem_tree &t) {
     k_centres<<<nblocks(t.n_box, BS), BS, 0, c.stream>>>(t.level.p, t.prefix.p, t.n_box, root.p, t.centre.p);
     BEM_LAUNCH_CHECK();
 
-    // 5. radii: leaves, then parents bottom-up
+    // 5. radii: leaves, then parents bottom-up.  Attached radii (Section 3.6's
+    // r_C over the elements attached to a leaf's vertices) need the elements
+    // holding each node: CSR built on the host from the element slots that
+    // can be targets (corners only for first-order meshes).
+    DBuf<int64_t> node_ptr;
+    DBuf<int32_t> node_elems;
+    if (t.attach) {
+        const int na = m.linear ? 3 : 6;
+        std::vector<int64_t> np(m.n_nodes + 1, 0);
+        for (int64_t i = 0; i < 6 * m.n_el; i++)
+            if (i % 6 < na) np[m.h_elem[i] + 1]++;
+        for (int64_t g = 0; g < m.n_nodes; g++) np[g + 1] += np[g];
+        std::vector<int32_t> ne(np[m.n_nodes]);
+        std::vector<int64_t> fill(np.begin(), np.end() - 1);
+        for (int64_t i = 0; i < 6 * m.n_el; i++)
+            if (i % 6 < na) ne[fill[m.h_elem[i]]++] = (int32_t)(i / 6);
+        node_ptr.alloc(&c, np.size());
+        node_ptr.upload(np.data(), np.size());
+        node_elems.alloc(&c, std::max<size_t>(1, ne.size()));
+        if (!ne.empty()) node_elems.upload(ne.data(), ne.size());
+    }
     k_leaf_radius<<<nblocks(t.n_box, BS / 64), BS, 0, c.stream>>>(t.leaf.p, t.eb.p, t.ee.p, t.tb.p, t.te.p, t.centre.p,
                                                                   t.eperm.p, t.tperm.p, m.elem.p, m.xyz.p,
-                                                                  m.dof_xyz.p, t.n_box, t.radius.p);
+                                                                  m.dof_xyz.p, m.dof_node.p, node_ptr.p,
+                                                                  node_elems.p, t.n_box, t.radius.p);
     BEM_LAUNCH_CHECK();
     for (int l = t.max_level; l >= 0; l--) {
         int64_t lo = t.level_off[l], hi = t.level_off[l + 1];

@@ -31,8 +31,8 @@ def _bem():
 _cache = {}
 
 
-def setup(name, B=32, theta=THETA, kappa=0.0, k_hint=0.0, order_min=0):
-    key = (name, B, theta, kappa, k_hint, order_min)
+def setup(name, B=32, theta=THETA, kappa=0.0, k_hint=0.0, order_min=0, attach=False):
+    key = (name, B, theta, kappa, k_hint, order_min, attach)
     if key not in _cache:
         bem = _bem()
         say(f"[setup] mesh={name} B={B} theta={theta} kappa={kappa} order_min={order_min}")
@@ -40,9 +40,10 @@ def setup(name, B=32, theta=THETA, kappa=0.0, k_hint=0.0, order_min=0):
         ctx = context()
         mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
         tree = bem.bem_tree_build(ctx, mesh, B=B, order=8, theta=theta, kappa=kappa, k_hint=k_hint,
-                                  order_min=order_min)
+                                  order_min=order_min, attach_radii=attach)
         om = oracle.OracleMesh(m.xyz, m.elem)
-        ot = oracle.OracleTree(om, B=B, theta=theta, kappa=kappa if kappa > 0 else float("inf"), k=k_hint)
+        ot = oracle.OracleTree(om, B=B, theta=theta, kappa=kappa if kappa > 0 else float("inf"), k=k_hint,
+                               attach=attach)
         _cache[key] = (m, ctx, mesh, tree, om, ot)
     return _cache[key]
 
@@ -64,9 +65,15 @@ TREE_CASES = [("sphere320", 32, 1.0), ("sphere320", 8, 0.6), ("sphere1280", 16, 
               ("cube24300", 32, 0.6), ("sphere1280_p1", 16, 0.6), ("cube4_p1", 8, 0.6), ("sphere20480_p1", 32, 0.6)]
 
 
-@pytest.mark.parametrize("name,B,theta", TREE_CASES)
-def test_tree_and_lists_bit_exact(name, B, theta):
-    m, ctx, mesh, tree, om, ot = setup(name, B=B, theta=theta)
+ATTACH_CASES = [("sphere1280", 16, 1.0, True), ("cube4", 8, 1.0, True), ("sphere1280_p1", 16, 1.0, True),
+                ("perturbed", 10, 0.6, True)]
+
+
+@pytest.mark.parametrize("name,B,theta,attach", [c + (False,) for c in TREE_CASES] + ATTACH_CASES)
+def test_tree_and_lists_bit_exact(name, B, theta, attach):
+    """Attached radii (the paper's r_C over the elements attached to a leaf's
+    vertices) included."""
+    m, ctx, mesh, tree, om, ot = setup(name, B=B, theta=theta, attach=attach)
     ex = tree.export()
     say(f"  boxes {ex['level'].size} leaves {ex['n_leaf']} near {ex['near_idx'].size} inter {ex['inter_idx'].size}")
     assert ex["level"].size == ot.n_box
@@ -150,6 +157,30 @@ def test_fmm_fp64_matches_oracle_fmm(name, green, k):
         # double layer K (only used inside A) has a smaller norm: within 1e-5
         bound = 1e-6 if op in (2, 3) else 1e-5
         assert rel(y, dref) < bound, ("truncation", op, rel(y, dref))
+
+
+@pytest.mark.parametrize("green,k", [(0, 0.0), (1, 2.0)])
+def test_fmm_attached_radii_matches_oracle(green, k):
+    """The paper's tree settings (attached radii, theta = 1, L_min = 3): the
+    FP64 product against the oracle's on the same tree, and its error against
+    the direct product far below that of the single-owner radii."""
+    bem = _bem()
+    cplx = green == 1
+    errs = {}
+    for attach in (False, True):
+        m, ctx, mesh, tree, om, ot = setup("sphere1280", B=16, theta=1.0, order_min=3, attach=attach)
+        x = bem_inputs.random_vector(om.n_dof, 27, complex_=cplx)[0]
+        xd = to_dev(x, cplx)
+        yd = xd.clone()
+        ref = ot.fmm_matvec(x, bem.BEM_OP_A, green, k, order=8, order_min=3)
+        ref = ref if cplx else ref.real
+        bem.bem_matvec(ctx, tree, green, k, bem.BEM_OP_A, bem.BEM_FMM, bem.BEM_PREC_FP64, xd, yd)
+        y = yd.cpu().numpy()[0]
+        dref = om.matvec_rows(x, bem.BEM_OP_A, green, k)
+        errs[attach] = rel(y, dref if cplx else dref.real)
+        say(f"  attach={attach} green={green}: vs oracle fmm {rel(y, ref):.2e}, vs direct {errs[attach]:.2e}")
+        assert rel(y, ref) < 1e-11
+    assert errs[True] < 0.5 * errs[False]
 
 
 @pytest.mark.parametrize("name,B", [("sphere1280", 16), ("sphere1280", 4), ("cube4", 8)])

@@ -379,3 +379,29 @@ def test_level_order_error_ordering(fmm_case):
             for m in (2, 3, 4)]
     e8 = np.linalg.norm(y8 - yd) / np.linalg.norm(yd)
     assert errs[0] > errs[1] > errs[2] > e8
+
+
+@pytest.mark.parametrize("name,B", [("sphere1280", 16), ("cube4", 8)])
+def test_attached_radii_cover_attached_elements(oracle_lib, name, B):
+    """Attach mode: every node of every element holding a leaf target's node
+    lies within the leaf's radius (brute force over the mesh); single-owner
+    radii miss some of them, and attach radii are never smaller."""
+    m = bem_inputs.workload(name)
+    om = oracle.OracleMesh(m.xyz, m.elem)
+    Ta = oracle.OracleTree(om, B=B, theta=1.0, attach=True)
+    To = oracle.OracleTree(om, B=B, theta=1.0)
+    assert np.array_equal(Ta.level, To.level) and np.all(Ta.radius >= To.radius)
+    holders = [[] for _ in range(m.n_nodes)]
+    for e, en in enumerate(m.elem):
+        for g in en:
+            holders[g].append(e)
+    missed = 0
+    for b in np.nonzero(Ta.leaf)[0]:
+        c = Ta.centre[b]
+        for t in range(Ta.tb[b], Ta.te[b]):
+            g = om.dof_node[Ta.tperm[t]]
+            pts = m.xyz[m.elem[holders[g]].ravel()]
+            d = np.sqrt(((pts - c) ** 2).sum(1)).max()
+            assert d <= Ta.radius[b] * (1 + 1e-15)
+            missed += d > To.radius[b]
+    assert missed > 0
