@@ -1,6 +1,6 @@
 // Iterative solution of Eq. (3) (Section 2.1: the paper uses a matrix-free
-// Krylov solver around the fast product; GMRES with restart replaces its
-// BiCGSTAB here).
+// Krylov solver, BiCGSTAB, around the fast product).  GMRES with restart is
+// the default here; BiCGSTAB is the other option (bicgstab() below).
 //
 // GMRES(m) from x0 = 0: Arnoldi with classical Gram-Schmidt applied twice
 // (CGS2), the Hessenberg column rotated by complex Givens rotations on the
@@ -9,9 +9,9 @@
 // is FP64 (complex128 for Helmholtz); the inner products reduce in a fixed
 // order, so repeated solves are bitwise identical.
 //
-// Precision modes:
-//   FP64   GMRES on the FP64 operator to tol.
-//   MIXED  the same GMRES, whose steps switch to the mixed-precision
+// Precision modes (both methods):
+//   FP64   the method on the FP64 operator to tol.
+//   MIXED  the same method, whose steps switch to the mixed-precision
 //          product once the residual is small enough for its error not to
 //          matter (relaxed inexact Krylov); the residual that decides
 //          convergence is always formed with the FP64 product.
@@ -268,14 +268,25 @@ __global__ void k_bicg_s(V *sc, const V *r, const V *v, V *s, int64_t n) {
     }
 }
 
-// omega = (t, s) / |t|^2; x += alpha p + omega s; r = s - omega t
+// omega = (t, s) / |t|^2; x += alpha p + omega s; r = s - omega t.  On a
+// breakdown (alpha or omega not finite: (rh, v) = 0 or t = 0) x is kept and
+// r is set to NaN, so that the host ends the cycle and restarts from x.
+__device__ inline bool vfinite(double v) { return isfinite(v); }
+__device__ inline bool vfinite(cx<double> v) { return isfinite(v.re) && isfinite(v.im); }
+
 template <class V>
 __global__ void k_bicg_x(V *sc, const V *p, const V *s, const V *t, V *x, V *r, int64_t n) {
     const int64_t e = (int64_t)blockIdx.x * RBS + threadIdx.x;
     const V omega = sc[BI_TS] * (1.0 / re_part(sc[BI_TT]));
+    const V alpha = sc[BI_ALPHA];
+    const bool ok = vfinite(alpha) && vfinite(omega);  // the same for every thread
     if (e < n) {
-        x[e] = x[e] + sc[BI_ALPHA] * p[e] + omega * s[e];
-        r[e] = s[e] - omega * t[e];
+        if (ok) {
+            x[e] = x[e] + alpha * p[e] + omega * s[e];
+            r[e] = s[e] - omega * t[e];
+        } else {
+            r[e] = V(NAN);
+        }
     }
     if (e == 0) sc[BI_OMEGA] = omega;
 }
@@ -607,7 +618,7 @@ void bicgstab(Krylov<V> &K, F &&apply, const V *b, V *x, double tol, int max_cyc
             c.sync();
             (*iters)++;
             rel = std::sqrt(K.h_out[2]) / bnorm;
-            if (!(rel == rel) || rel <= tol) break;  // converged, or broke down (NaN): check the FP64 residual
+            if (!(rel == rel) || rel <= tol) break;  // converged, or broke down (x kept): FP64 residual, restart
         }
     }
 }

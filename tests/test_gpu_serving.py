@@ -142,3 +142,29 @@ def test_server_rejects_bad_requests():
             srv.poll(12345)
     finally:
         srv.close()
+
+
+def test_server_first_order_bicgstab_level_order():
+    """The server with first-order meshes, BiCGSTAB and the level-dependent
+    order: every served result equals bem_solve's with the same options."""
+    bem = _bem()
+    meshes = [bem_inputs.linear(bem_inputs.icosphere(3)), bem_inputs.linear(bem_inputs.cube(4))]
+    rng = np.random.default_rng(11)
+    srv = bem.Server(lanes=2, max_batch_rhs=4, precision=1, krylov=bem.BEM_KRYLOV_BICGSTAB, order_min=3, **TREE)
+    try:
+        ids, ndofs = zip(*[srv.add_mesh(m.xyz, m.elem) for m in meshes])
+        reqs = _requests(rng, ids, ndofs)
+        results = [srv.poll(t) for t in [srv.submit(ids[j], g, k, chi) for j, g, k, chi in reqs]]
+    finally:
+        srv.close()
+    ctx = context()
+    for (j, g, k, chi), (rc, phi, info, lat) in zip(reqs, results):
+        assert rc == 0 and all(i["status"] == 0 for i in info)
+        m = bem.bem_mesh_load(ctx, meshes[j].xyz, meshes[j].elem)
+        t = bem.bem_tree_build(ctx, m, order_min=3, **TREE)
+        for r, row in enumerate(np.atleast_2d(chi)):
+            d = to_dev(row[None], g == 1)
+            p = d.clone()
+            bem.bem_solve(ctx, t, g, k, d, p, krylov=bem.BEM_KRYLOV_BICGSTAB, **SOLVE)
+            ref = p.cpu().numpy()[0]
+            assert np.array_equal(phi[r], ref if g else ref.real), f"mesh {j} green {g} rhs {r}"
