@@ -177,6 +177,11 @@ typedef struct {
                                element attached to the geometric nodes of its targets (the
                                paper's r_C, Section 3.6, over the elements attached to a leaf's
                                vertices, Section 3.1); sources stay owned by one leaf each.
+                               2: the paper's tree read literally: boxes over the DOF points
+                               alone, max_elems_per_leaf then counting DOFs, every DOF's basis
+                               function a source over its element patch, radii as for 1; the
+                               element fields of bem_tree_export then describe element pieces
+                               (the part of an element in one leaf's basis functions).
                                0: owned elements and targets only */
 } bem_tree_opts;
 

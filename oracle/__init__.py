@@ -178,22 +178,26 @@ class OracleTree:
     """Recursive octree with radii and lists (Sections 3.1, 3.4, 3.6)."""
 
     def __init__(self, mesh: OracleMesh, B=32, max_depth=21, theta=1.0, kappa=float("inf"), k=0.0,
-                 attach=False):
+                 attach=False, literal=False):
         """attach: leaf radii also cover the elements attached to the nodes of
-        the leaf's targets (the paper's r_C); sources stay single-owner."""
+        the leaf's targets (the paper's r_C); sources stay single-owner.
+        literal: the paper's tree read literally: boxes over the DOF points,
+        B counting DOFs, each DOF's basis function a source (attached radii);
+        elem_begin / elem_end are then the DOF ranges."""
         self.mesh = mesh
         tgt = _c(mesh.dof_xyz, np.float64)
         tnode = _c(mesh.dof_node, np.int32)
         self._h = lib().or_tree_build(_p(mesh.xyz), mesh.xyz.shape[0], _p(mesh.elem), mesh.n_el, mesh.nn,
                                       _p(tgt), _p(tnode), tgt.shape[0], int(B), int(max_depth), float(theta),
-                                      float(kappa), float(k), int(bool(attach)))
+                                      float(kappa), float(k), 2 if literal else int(bool(attach)))
         sz = np.zeros(4, np.int64)
         lib().or_tree_sizes(self._h, _p(sz))
         nb, nn, ni, ml = (int(v) for v in sz)
         self.n_box, self.max_level = nb, ml
         ib = np.zeros((nb, 10), np.int64)
         db = np.zeros((nb, 4), np.float64)
-        self.eperm = np.zeros(mesh.n_el, np.int64)
+        # sources of the tree: the elements, or the DOFs of the literal tree
+        self.eperm = np.zeros(mesh.n_dof if literal else mesh.n_el, np.int64)
         self.tperm = np.zeros(mesh.n_dof, np.int64)
         self.near_ptr = np.zeros(nb + 1, np.int64)
         self.near_idx = np.zeros(max(nn, 1), np.int64)

@@ -623,6 +623,7 @@ typedef struct {
     int64_t *near_ptr, *near_idx, *inter_ptr, *inter_idx;
     double corner[3], side;
     int max_level;
+    int literal; /* sources are the DOFs (node basis functions); eb/ee = tb/te */
 } otree_t;
 
 static uint64_t spread3(uint64_t v)
@@ -754,15 +755,23 @@ static int cmp_i64(const void *a, const void *b)
     return x < y ? -1 : (x > y);
 }
 
-/* attach != 0 (with tgt_node, the geometric node of each target): a leaf's */
+/* attach = 1 (with tgt_node, the geometric node of each target): a leaf's */
 /* radius also covers every node of every element attached to the nodes of */
 /* its targets, as Section 3.6 defines r_C (the elements attached to a     */
 /* leaf's vertices, Section 3.1); sources stay owned by one leaf each.     */
+/* attach = 2, the paper's tree read literally (Sections 3.1, 3.6): the    */
+/* boxes are built over the DOF points alone, B counts DOFs, each DOF's    */
+/* basis function is a source of its box, and the radius of a leaf covers  */
+/* its DOF points and every node of every element attached to them.  The   */
+/* element ranges of the boxes are then their DOF ranges (eb = tb, ...).   */
 void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int64_t n_el, int nn,
                     const double *tgt_xyz, const int32_t *tgt_node, int64_t n_tgt, int B, int max_depth,
                     double theta, double kappa, double k, int attach)
 {
     otree_t *T = calloc(1, sizeof *T);
+    T->literal = attach == 2;
+    const int64_t n_mesh_el = n_el;
+    if (T->literal) n_el = n_tgt; /* the DOFs stand in the element slots of the tree */
     T->n_el = n_el;
     T->n_tgt = n_tgt;
     /* root cube */
@@ -784,6 +793,11 @@ void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int
     kv_t *ek = malloc((n_el > 0 ? n_el : 1) * sizeof *ek), *tk = malloc((n_tgt > 0 ? n_tgt : 1) * sizeof *tk);
     for (int64_t e = 0; e < n_el; e++) {
         double p[3];
+        if (T->literal) { /* the DOF points */
+            ek[e].key = morton(tgt_xyz + 3 * e, T->corner, scale);
+            ek[e].id = e;
+            continue;
+        }
         const int32_t *en = elem + nn * e;
         for (int d = 0; d < 3; d++)
             p[d] = ((xyz[3 * (int64_t)en[0] + d] + xyz[3 * (int64_t)en[1] + d]) + xyz[3 * (int64_t)en[2] + d]) / 3.0;
@@ -837,12 +851,12 @@ void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int
     int64_t *ns = NULL, *ne_of = NULL;
     if (attach) {
         ns = calloc(n_nodes + 1, sizeof *ns);
-        for (int64_t i = 0; i < nn * n_el; i++) ns[elem[i] + 1]++;
+        for (int64_t i = 0; i < nn * n_mesh_el; i++) ns[elem[i] + 1]++;
         for (int64_t g = 0; g < n_nodes; g++) ns[g + 1] += ns[g];
         int64_t *fill = malloc((n_nodes + 1) * sizeof *fill);
         memcpy(fill, ns, (n_nodes + 1) * sizeof *fill);
-        ne_of = malloc((nn * n_el + 1) * sizeof *ne_of);
-        for (int64_t i = 0; i < nn * n_el; i++) ne_of[fill[elem[i]]++] = i / nn;
+        ne_of = malloc((nn * n_mesh_el + 1) * sizeof *ne_of);
+        for (int64_t i = 0; i < nn * n_mesh_el; i++) ne_of[fill[elem[i]]++] = i / nn;
         free(fill);
     }
     /* Section 3.4: convergence radii.  Leaf: farthest node of an owned
@@ -853,7 +867,7 @@ void *or_tree_build(const double *xyz, int64_t n_nodes, const int32_t *elem, int
         obox_t *x = &T->box[b];
         double r = 0.0;
         if (x->leaf) {
-            for (int64_t e = x->eb; e < x->ee; e++)
+            for (int64_t e = x->eb; e < x->ee && !T->literal; e++)
                 for (int a = 0; a < nn; a++) {
                     double v = dist3(xyz + 3 * (int64_t)elem[nn * T->eperm[e] + a], x->c);
                     if (v > r) r = v;
@@ -1099,22 +1113,59 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
     int (*ex)[3] = malloc(P2 * sizeof *ex);
     mexps(2 * p, ex);
 
-    /* quadrature-point strengths of the 7-point rule, sorted element order */
-    int64_t nq = 7 * n_el;
-    double (*qy)[3] = malloc(nq * sizeof *qy), (*qn)[3] = malloc(nq * sizeof *qn);
-    cplx *qs = malloc(nq * sizeof(cplx));
+    /* Source points of the 7-point rule and their strengths, in the tree's  */
+    /* source order: the points of sorted source s are so[s] .. so[s+1]-1.    */
+    /* Sources are the elements (7 points each, strength wJ sum_a L_a x_a),   */
+    /* or in the literal tree the DOFs: DOF i's basis function over its       */
+    /* element patch, 7 points of every element e holding it in slot a, with  */
+    /* strength wJ L_a x_i.                                                    */
     rule_t reg;
     rule_regular(&reg);
-    for (int64_t se = 0; se < n_el; se++) {
-        int64_t e = T->eperm[se];
-        double X[6][3];
-        load_elem(nn, xyz, elem + nn * e, X);
-        for (int q = 0; q < 7; q++) {
-            double L[6], J;
-            elem_point(nn, X, reg.s[q], reg.t[q], qy[7 * se + q], qn[7 * se + q], &J, L);
-            cplx sig = 0.0;
-            for (int a = 0; a < nn; a++) sig += L[a] * x[elem_dofs[nn * e + a]];
-            qs[7 * se + q] = sig * (reg.w[q] * J);
+    int64_t ns = T->n_el; /* sorted sources */
+    int64_t *so = malloc((ns + 1) * sizeof *so);
+    int64_t *ip = NULL, *iv = NULL; /* DOF -> incidences nn*e + a (literal tree) */
+    if (T->literal) {
+        ip = calloc(n_dof + 1, sizeof *ip);
+        for (int64_t i = 0; i < nn * n_el; i++) ip[elem_dofs[i] + 1]++;
+        for (int64_t i = 0; i < n_dof; i++) ip[i + 1] += ip[i];
+        int64_t *fill = malloc((n_dof + 1) * sizeof *fill);
+        memcpy(fill, ip, (n_dof + 1) * sizeof *fill);
+        iv = malloc((nn * n_el + 1) * sizeof *iv);
+        for (int64_t i = 0; i < nn * n_el; i++) iv[fill[elem_dofs[i]]++] = i;
+        free(fill);
+    }
+    so[0] = 0;
+    for (int64_t s = 0; s < ns; s++)
+        so[s + 1] = so[s] + (T->literal ? 7 * (ip[T->eperm[s] + 1] - ip[T->eperm[s]]) : 7);
+    int64_t nq = so[ns];
+    double (*qy)[3] = malloc((nq + 1) * sizeof *qy), (*qn)[3] = malloc((nq + 1) * sizeof *qn);
+    cplx *qs = malloc((nq + 1) * sizeof(cplx));
+    for (int64_t s = 0; s < ns; s++) {
+        int64_t o = so[s];
+        if (!T->literal) {
+            int64_t e = T->eperm[s];
+            double X[6][3];
+            load_elem(nn, xyz, elem + nn * e, X);
+            for (int q = 0; q < 7; q++) {
+                double L[6], J;
+                elem_point(nn, X, reg.s[q], reg.t[q], qy[o + q], qn[o + q], &J, L);
+                cplx sig = 0.0;
+                for (int a = 0; a < nn; a++) sig += L[a] * x[elem_dofs[nn * e + a]];
+                qs[o + q] = sig * (reg.w[q] * J);
+            }
+            continue;
+        }
+        int64_t i = T->eperm[s];
+        for (int64_t p = ip[i]; p < ip[i + 1]; p++, o += 7) {
+            int64_t e = iv[p] / nn;
+            int a = (int)(iv[p] % nn);
+            double X[6][3];
+            load_elem(nn, xyz, elem + nn * e, X);
+            for (int q = 0; q < 7; q++) {
+                double L[6], J;
+                elem_point(nn, X, reg.s[q], reg.t[q], qy[o + q], qn[o + q], &J, L);
+                qs[o + q] = x[i] * (L[a] * (reg.w[q] * J));
+            }
         }
     }
     cplx *M = calloc(T->n_box * P, sizeof(cplx)), *F = calloc(T->n_box * P, sizeof(cplx));
@@ -1132,7 +1183,7 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
     for (int64_t b = 0; b < T->n_box; b++) {
         const obox_t *B_ = &T->box[b];
         if (!B_->leaf) continue;
-        for (int64_t q = 7 * B_->eb; q < 7 * B_->ee; q++) {
+        for (int64_t q = so[B_->eb]; q < so[B_->ee]; q++) {
             double d[3] = {qy[q][0] - B_->c[0], qy[q][1] - B_->c[1], qy[q][2] - B_->c[2]};
             for (int i = 0; i < nc[b]; i++) {
                 int a = ex[i][0], bb = ex[i][1], c = ex[i][2];
@@ -1217,7 +1268,7 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
                 acc += F[b * P + j] * ipow(d[0], ex[j][0]) * ipow(d[1], ex[j][1]) * ipow(d[2], ex[j][2]);
             for (int64_t j = T->near_ptr[b]; j < T->near_ptr[b + 1]; j++) {
                 const obox_t *S_ = &T->box[T->near_idx[j]];
-                for (int64_t q = 7 * S_->eb; q < 7 * S_->ee; q++) {
+                for (int64_t q = so[S_->eb]; q < so[S_->ee]; q++) {
                     cplx G, dG;
                     kernel(green, k, xi, qy[q], qn[q], &G, &dG);
                     acc += (dbl ? dG : G) * qs[q];
@@ -1259,6 +1310,7 @@ int or_fmm_matvec(const void *h, const double *xyz, const int32_t *elem, const i
     }
     (void)m;
     free(c); free(yo); free(fa); free(M); free(F); free(nc); free(qy); free(qn); free(qs); free(ex);
+    free(so); free(ip); free(iv);
     return 0;
 }
 

@@ -284,7 +284,7 @@ class Tree:
     def __init__(self, ctx: Context, mesh: Mesh, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21, k_hint=0.0,
                  order_min=0, attach_radii=False):
         self.ctx, self.mesh = ctx, mesh
-        opts = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min, int(bool(attach_radii)))
+        opts = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min, int(attach_radii))
         h = ctypes.c_void_p()
         ctx.check(ctx.L.bem_tree_build(ctx.h, mesh.h, ctypes.byref(opts), ctypes.byref(h)), "bem_tree_build")
         self.h = h

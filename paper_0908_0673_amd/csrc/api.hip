@@ -175,6 +175,7 @@ int bem_tree_build(bem_ctx *ctx, const bem_mesh *mesh, const bem_tree_opts *opts
             t->k_hint = opts->k_hint;
             t->order_min = opts->order_min;
             t->attach = opts->attach_radii != 0;
+            t->literal = opts->attach_radii == 2;
         }
         BEM_REQUIRE(t->order_min >= 0, BEM_EINVAL, "order_min must be >= 0");
         if (t->order_min >= t->order) t->order_min = 0;

@@ -41,8 +41,8 @@ constexpr double FIELD_KAPPA = 0.75;  // Helmholtz: largest k r_C of a box whose
 
 // sigma_q = wJ_q sum_a L_a(q) x(DOF of the element's node a), [rhs][n_q]
 template <class V>
-__global__ void k_field_strength(const V *x, int64_t n_dof, const int32_t *se_dofs, const double *wj, int64_t n_q,
-                                 const double *L7, V *s) {
+__global__ void k_field_strength(const V *x, int64_t n_dof, const int32_t *se_dofs, const uint8_t *se_mask,
+                                 const double *wj, int64_t n_q, const double *L7, V *s) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int rhs = blockIdx.y;
     if (i >= n_q) return;
@@ -50,7 +50,9 @@ __global__ void k_field_strength(const V *x, int64_t n_dof, const int32_t *se_do
     const int q = (int)(i % 7);
     const V *xr = x + (int64_t)rhs * n_dof;
     V acc = V(0.0);
-    for (int a = 0; a < 6; a++) acc += xr[se_dofs[6 * e + a]] * L7[6 * q + a];
+    const int mk = se_mask ? se_mask[e] : 0x3f;  // literal tree: the piece's own slots
+    for (int a = 0; a < 6; a++)
+        if (mk >> a & 1) acc += xr[se_dofs[6 * e + a]] * L7[6 * q + a];
     s[(int64_t)rhs * n_q + i] = acc * wj[i];
 }
 
@@ -162,9 +164,11 @@ void field_t(bem_tree &t, double k, double theta, int nrhs, const void *phi, con
     mom.zero();
     tmp.zero();
     const dim3 gs(nblocks(nq, 256), nrhs);
-    k_field_strength<V><<<gs, 256, 0, c.stream>>>((const V *)phi, nd, t.se_dofs.p, t.q64.p + 3 * nq, nq, t.L7.p, sphi.p);
+    k_field_strength<V><<<gs, 256, 0, c.stream>>>((const V *)phi, nd, t.se_dofs.p, t.se_mask.p, t.q64.p + 3 * nq, nq,
+                                                  t.L7.p, sphi.p);
     BEM_LAUNCH_CHECK();
-    k_field_strength<V><<<gs, 256, 0, c.stream>>>((const V *)chi, nd, t.se_dofs.p, t.q64.p + 3 * nq, nq, t.L7.p, schi.p);
+    k_field_strength<V><<<gs, 256, 0, c.stream>>>((const V *)chi, nd, t.se_dofs.p, t.se_mask.p, t.q64.p + 3 * nq, nq,
+                                                  t.L7.p, schi.p);
     BEM_LAUNCH_CHECK();
     // moments of the double layer of phi minus those of the single layer of chi
     p2m_apply<V, double, V>(t, true, nrhs, (const V *)phi, mom.p);

@@ -44,8 +44,8 @@ template <bool C, class R> using val_t = typename std::conditional<C, cx<R>, R>:
 
 // ---------------------------------------------------------------- strengths
 template <class V, class R, class XV>
-__global__ void k_strength(const XV *x, int64_t n_dof, const int32_t *se_dofs, const R *wj, int64_t n_q,
-                           const double *L7 /* [7][6] */, V *s, uint32_t *zero, int64_t n_zero) {
+__global__ void k_strength(const XV *x, int64_t n_dof, const int32_t *se_dofs, const uint8_t *se_mask, const R *wj,
+                           int64_t n_q, const double *L7 /* [7][6] */, V *s, uint32_t *zero, int64_t n_zero) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int rhs = blockIdx.y;
     // the same launch clears n_zero words (the expansions of the fast product)
@@ -56,7 +56,13 @@ __global__ void k_strength(const XV *x, int64_t n_dof, const int32_t *se_dofs, c
     int q = (int)(i % 7);
     const XV *xr = x + (int64_t)rhs * n_dof;
     XV acc = XV(0.0);
-    for (int a = 0; a < 6; a++) acc += xr[se_dofs[6 * se + a]] * L7[6 * q + a];
+    if (!se_mask) {
+        for (int a = 0; a < 6; a++) acc += xr[se_dofs[6 * se + a]] * L7[6 * q + a];
+    } else {  // literal tree: the piece's own shape-function slots
+        const int mk = se_mask[se];
+        for (int a = 0; a < 6; a++)
+            if (mk >> a & 1) acc += xr[se_dofs[6 * se + a]] * L7[6 * q + a];
+    }
     s[(int64_t)rhs * n_q + i] = vcast<V>(acc) * wj[i];
 }
 
@@ -713,8 +719,11 @@ void rule_shapes(bem_tree &t) {
 // that even small meshes fill the GPU); 1/|x - y| is the hardware estimate
 // refined twice by Newton (a few ulp, like the division and square root it
 // replaces).
+// qmul (literal tree, else NULL): each point's share of the unit density,
+// the sum of its piece's shape functions there.
 __global__ void __launch_bounds__(256) k_unit_double_layer(const double *q, int64_t n_q, int64_t per_split,
-                                                           const double *t, int64_t n_tgt, double *part) {
+                                                           const double *qmul, const double *t, int64_t n_tgt,
+                                                           double *part) {
     __shared__ double sx[256], sy[256], sz[256], sn0[256], sn1[256], sn2[256];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x, ii = min(i, n_tgt - 1);
     const double x0 = t[ii], x1 = t[n_tgt + ii], x2 = t[2 * n_tgt + ii];
@@ -723,7 +732,7 @@ __global__ void __launch_bounds__(256) k_unit_double_layer(const double *q, int6
     for (int64_t base = j0; base < j1; base += 256) {
         const int64_t j = base + threadIdx.x;
         if (j < j1) {
-            const double wj = q[3 * n_q + j];
+            const double wj = qmul ? q[3 * n_q + j] * qmul[j] : q[3 * n_q + j];
             sx[threadIdx.x] = q[j];
             sy[threadIdx.x] = q[n_q + j];
             sz[threadIdx.x] = q[2 * n_q + j];
@@ -756,10 +765,22 @@ void direct_regular_unit_double_layer(bem_tree &t, double *out) {
     const int64_t tiles = nblocks(t.n_tgt, 256);
     const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(nblocks(t.n_q, 256), 2048 / std::max<int64_t>(1, tiles)));
     const int64_t per = (t.n_q + splits - 1) / splits;
-    DBuf<double> part;
+    DBuf<double> part, qmul;
     part.alloc(&c, (size_t)splits * t.n_tgt);
-    k_unit_double_layer<<<dim3((unsigned)tiles, (unsigned)splits), 256, 0, c.stream>>>(t.q64.p, t.n_q, per, t.t64.p,
-                                                                                      t.n_tgt, part.p);
+    if (t.se_mask.p) {
+        rule_shapes(t);
+        const std::vector<double> L7 = t.L7.download(42);
+        const std::vector<uint8_t> mk = t.se_mask.download(t.n_el);
+        std::vector<double> qm(t.n_q, 0.0);
+        for (int64_t v = 0; v < t.n_el; v++)
+            for (int q = 0; q < 7; q++)
+                for (int a = 0; a < 6; a++)
+                    if (mk[v] >> a & 1) qm[7 * v + q] += L7[6 * q + a];
+        qmul.alloc(&c, t.n_q);
+        qmul.upload(qm.data(), t.n_q);
+    }
+    k_unit_double_layer<<<dim3((unsigned)tiles, (unsigned)splits), 256, 0, c.stream>>>(t.q64.p, t.n_q, per, qmul.p,
+                                                                                      t.t64.p, t.n_tgt, part.p);
     BEM_LAUNCH_CHECK();
     k_sum_splits<<<nblocks(t.n_tgt, 256), 256, 0, c.stream>>>(part.p, splits, t.n_tgt, out);
     BEM_LAUNCH_CHECK();
@@ -800,8 +821,8 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
     }
     c.mark(9);
     dim3 gs(nblocks(nq, 256), nrhs);
-    k_strength<V, R, XV><<<gs, 256, 0, c.stream>>>(x, nt, t.se_dofs.p, q + 3 * nq, nq, t.L7.p, s, (uint32_t *)mom,
-                                                   (int64_t)(2 * sizeof(V) * nexp / 4));
+    k_strength<V, R, XV><<<gs, 256, 0, c.stream>>>(x, nt, t.se_dofs.p, t.se_mask.p, q + 3 * nq, nq, t.L7.p, s,
+                                                   (uint32_t *)mom, (int64_t)(2 * sizeof(V) * nexp / 4));
     BEM_LAUNCH_CHECK();
     c.mark(0);
 

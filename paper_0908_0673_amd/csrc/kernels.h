@@ -125,6 +125,7 @@ struct bem_tree {
     int B = 32, order = 8, max_depth = 21;
     int order_min = 0;  // level-dependent order when > 0 (see level_p)
     bool attach = false;  // leaf radii over the elements attached to the leaf's target nodes
+    bool literal = false; // the paper's tree read literally: DOF sources, B counting DOFs (attach too)
     double theta = 0.6, kappa = 0.0, k_hint = 0.0;
     int64_t n_box = 0, n_leaf = 0, n_near = 0, n_inter = 0, n_el = 0, n_tgt = 0, n_q = 0;
     int max_level = 0;
@@ -137,6 +138,7 @@ struct bem_tree {
     bem::DBuf<uint64_t> prefix;
     bem::DBuf<double> centre, radius;  // [n_box][3], [n_box]
     bem::DBuf<int32_t> eperm, tperm;   // sorted position -> element / DOF
+    bem::DBuf<uint8_t> se_mask;        // literal tree: shape-function slots of each element piece (else empty)
     bem::DBuf<int64_t> near_ptr, inter_ptr;
     bem::DBuf<int32_t> near_idx, inter_idx;
 

@@ -42,8 +42,8 @@ __host__ __device__ inline int midx(int a, int b, int c) {
 template <bool DBL>
 __global__ void k_p2m_weights(const int32_t *leaves, const int64_t *eb, const int64_t *ee, const int32_t *level,
                               const double *centre, double side, const double *q64, int64_t n_q, const double *L7,
-                              const int32_t *slot, const int64_t *woff, int p, const int8_t *exps, LevelP lp,
-                              double *W) {
+                              const int32_t *slot, const uint8_t *se_mask, const int64_t *woff, int p,
+                              const int8_t *exps, LevelP lp, double *W) {
     // per element of the leaf: the powers u_d^k / k! of its 7 rule points
     // (formed once, in LDS) and their normals and weights
     __shared__ double pw[7][3][MAX_ORDER + 1];
@@ -88,7 +88,9 @@ __global__ void k_p2m_weights(const int32_t *leaves, const int64_t *eb, const in
             }
             phi[q] = v * qn[q][3];
         }
+        const int mk = se_mask ? se_mask[e] : 0x3f;  // literal tree: the piece's own slots
         for (int j = 0; j < 6; j++) {
+            if (!(mk >> j & 1)) continue;
             double w = 0.0;
             for (int q = 0; q < 7; q++) w += L7[6 * q + j] * phi[q];
             W[(off + slot[6 * e + j]) * P + a] += w;
@@ -333,16 +335,20 @@ void build_pass_tables(bem_tree &t) {
     std::vector<int32_t> leaves = t.leaf_ids.download(t.n_leaf_src);
     std::vector<int64_t> woff(leaves.size() + 1, 0);
     std::vector<int32_t> wdof, slot(6 * t.n_el, 0);
+    // literal tree: a piece contributes through its own slots only
+    const std::vector<uint8_t> mk = t.se_mask.p ? t.se_mask.download(t.n_el) : std::vector<uint8_t>(t.n_el, 0x3f);
     for (size_t i = 0; i < leaves.size(); i++) {
         const int b = leaves[i];
         std::vector<int32_t> u;
         for (int64_t e = t.h_eb[b]; e < t.h_ee[b]; e++)
-            for (int j = 0; j < 6; j++) u.push_back(sed[6 * e + j]);
+            for (int j = 0; j < 6; j++)
+                if (mk[e] >> j & 1) u.push_back(sed[6 * e + j]);
         std::sort(u.begin(), u.end());
         u.erase(std::unique(u.begin(), u.end()), u.end());
         for (int64_t e = t.h_eb[b]; e < t.h_ee[b]; e++)
             for (int j = 0; j < 6; j++)
-                slot[6 * e + j] = (int32_t)(std::lower_bound(u.begin(), u.end(), sed[6 * e + j]) - u.begin());
+                if (mk[e] >> j & 1)
+                    slot[6 * e + j] = (int32_t)(std::lower_bound(u.begin(), u.end(), sed[6 * e + j]) - u.begin());
         wdof.insert(wdof.end(), u.begin(), u.end());
         woff[i + 1] = (int64_t)wdof.size();
     }
@@ -366,11 +372,11 @@ void build_pass_tables(bem_tree &t) {
             if (dbl)
                 k_p2m_weights<true><<<(unsigned)t.n_leaf_src, wbs, 0, c.stream>>>(
                     t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p, t.side, t.q64.p, t.n_q, t.L7.p, dslot.p,
-                    pt.woff.p, p, T.exps.p, lp, pt.W64[dbl].p);
+                    t.se_mask.p, pt.woff.p, p, T.exps.p, lp, pt.W64[dbl].p);
             else
                 k_p2m_weights<false><<<(unsigned)t.n_leaf_src, wbs, 0, c.stream>>>(
                     t.leaf_ids.p, t.eb.p, t.ee.p, t.level.p, t.centre.p, t.side, t.q64.p, t.n_q, t.L7.p, dslot.p,
-                    pt.woff.p, p, T.exps.p, lp, pt.W64[dbl].p);
+                    t.se_mask.p, pt.woff.p, p, T.exps.p, lp, pt.W64[dbl].p);
             BEM_LAUNCH_CHECK();
         }
         k_to_r<float><<<nblocks(nw, 256), 256, 0, c.stream>>>(pt.W64[dbl].p, nw, pt.W32[dbl].p);

@@ -175,8 +175,8 @@ __global__ void k_pairs(int64_t n_tgt, const double *t64, const int32_t *tperm, 
 template <bool HELM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HELM ? 1 : 4, HELM ? 2 : 4)))
 k_corr_values(int64_t n_pairs, const int32_t *pair_elem, const int32_t *pair_info, const int32_t *pair_row,
-              const double *t64, int64_t n_tgt, const int32_t *se_nodes, const double *xyz, double k, int lin,
-              Gauss gq_arg, R7 r7_arg, double *Sout, double *Kout) {
+              const double *t64, int64_t n_tgt, const int32_t *se_nodes, const uint8_t *se_mask, const double *xyz,
+              double k, int lin, Gauss gq_arg, R7 r7_arg, double *Sout, double *Kout) {
     // the rules are indexed per point: kept in LDS (a by-value kernel
     // argument indexed at run time would be copied to scratch per thread)
     __shared__ Gauss gq;
@@ -277,9 +277,10 @@ k_corr_values(int64_t n_pairs, const int32_t *pair_elem, const int32_t *pair_inf
             K[a] += dG * f;
         }
     }
+    const int mk = se_mask ? se_mask[se] : 0x3f;  // literal tree: the piece's own slots
     for (int a = 0; a < 6; a++) {
-        S[a] = wave_sum(S[a]);
-        K[a] = wave_sum(K[a]);
+        S[a] = (mk >> a & 1) ? wave_sum(S[a]) : V(0.0);
+        K[a] = (mk >> a & 1) ? wave_sum(K[a]) : V(0.0);
     }
     if (lane == 0) {
         for (int a = 0; a < 6; a++) {
@@ -359,12 +360,12 @@ Corr &get_corr(bem_tree &t, int green, double k) {
         unsigned nb = nblocks(t.n_pairs, 4);
         if (green == BEM_HELMHOLTZ)
             k_corr_values<true><<<nb, 256, 0, c.stream>>>(t.n_pairs, t.pair_elem.p, t.pair_info.p, t.pair_row.p,
-                                                          t.t64.p, t.n_tgt, t.se_nodes.p, t.mesh->xyz.p, k,
-                                                          (int)t.mesh->linear, gq, r7, cr->S.p, cr->K.p);
+                                                          t.t64.p, t.n_tgt, t.se_nodes.p, t.se_mask.p, t.mesh->xyz.p,
+                                                          k, (int)t.mesh->linear, gq, r7, cr->S.p, cr->K.p);
         else
             k_corr_values<false><<<nb, 256, 0, c.stream>>>(t.n_pairs, t.pair_elem.p, t.pair_info.p, t.pair_row.p,
-                                                           t.t64.p, t.n_tgt, t.se_nodes.p, t.mesh->xyz.p, 0.0,
-                                                           (int)t.mesh->linear, gq, r7, cr->S.p, cr->K.p);
+                                                           t.t64.p, t.n_tgt, t.se_nodes.p, t.se_mask.p, t.mesh->xyz.p,
+                                                           0.0, (int)t.mesh->linear, gq, r7, cr->S.p, cr->K.p);
         BEM_LAUNCH_CHECK();
     }
     c.sync();

@@ -106,12 +106,15 @@ __global__ void k_root(const double *part, int nb, double *out) {
     out[4] = 2097152.0 / side;
 }
 
+// lit: the literal tree, whose sources are the DOFs (n_el = n_tgt, keyed at the DOF points)
 __global__ void k_keys(const double *xyz, const int32_t *elem, int64_t n_el, const double *dof_xyz, int64_t n_tgt,
-                       const double *root, uint64_t *key, int32_t *val) {
+                       int lit, const double *root, uint64_t *key, int32_t *val) {
     int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     if (i >= n_el + n_tgt) return;
     double p[3];
-    if (i < n_el) {
+    if (i < n_el && lit) {
+        for (int d = 0; d < 3; d++) p[d] = dof_xyz[3 * i + d];
+    } else if (i < n_el) {
         const int32_t *en = elem + 6 * i;
         for (int d = 0; d < 3; d++)
             p[d] = ((xyz[3 * (int64_t)en[0] + d] + xyz[3 * (int64_t)en[1] + d]) + xyz[3 * (int64_t)en[2] + d]) / 3.0;
@@ -219,13 +222,14 @@ __device__ inline double dist3(const double *a, const double *b) {
 __global__ void k_leaf_radius(const int32_t *leaf, const int64_t *eb, const int64_t *ee, const int64_t *tb,
                               const int64_t *te, const double *centre, const int32_t *eperm, const int32_t *tperm,
                               const int32_t *elem, const double *xyz, const double *dof_xyz, const int32_t *dof_node,
-                              const int64_t *node_ptr, const int32_t *node_elems, int64_t n_box, double *radius) {
+                              const int64_t *node_ptr, const int32_t *node_elems, int owned, int64_t n_box,
+                              double *radius) {
     int64_t b = (int64_t)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
     if (b >= n_box || !leaf[b]) return;
     const double *c = centre + 3 * b;
     double r = 0.0;
-    int64_t ne = 6 * (ee[b] - eb[b]);
+    int64_t ne = owned ? 6 * (ee[b] - eb[b]) : 0;  // owned elements (none in the literal tree)
     for (int64_t j = lane; j < ne; j += 64) {
         int32_t e = eperm[eb[b] + j / 6];
         double v = dist3(xyz + 3 * (int64_t)elem[6 * (int64_t)e + j % 6], c);
@@ -328,10 +332,76 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 
 }  // namespace
 
+// The literal tree's sources are the DOFs' basis functions, each over its
+// element patch.  The product runs on element pieces: for every element and
+// every leaf holding one of its DOFs, one piece with the element's points
+// and the shape functions of those DOFs only (a slot mask).  Pieces are
+// ordered by their first DOF's sorted position, so every box's pieces are
+// the range between its DOF range's bounds; the tree's element fields then
+// describe the pieces (eperm: the element of each piece).
+void expand_literal_sources(bem_tree &t) {
+    Ctx &c = *t.ctx;
+    const bem_mesh &m = *t.mesh;
+    const int na = m.linear ? 3 : 6;
+    std::vector<int32_t> tperm = t.tperm.download(t.n_tgt);
+    std::vector<int64_t> pos(t.n_tgt), leaf_of(t.n_tgt, -1);
+    for (int64_t s = 0; s < t.n_tgt; s++) pos[tperm[s]] = s;
+    for (int64_t b = 0; b < t.n_box; b++)
+        if (t.h_leaf[b])
+            for (int64_t s = t.h_tb[b]; s < t.h_te[b]; s++) leaf_of[s] = b;
+    struct Piece {
+        int64_t key;
+        int32_t elem;
+        uint8_t mask;
+    };
+    std::vector<Piece> pc;
+    pc.reserve(2 * m.n_el);
+    for (int64_t e = 0; e < m.n_el; e++) {
+        uint8_t done = 0;
+        for (int a = 0; a < na; a++) {
+            if (done >> a & 1) continue;
+            const int64_t lf = leaf_of[pos[m.h_elem_dofs[6 * e + a]]];
+            Piece p{INT64_MAX, (int32_t)e, 0};
+            for (int b = a; b < na; b++) {
+                const int64_t sp = pos[m.h_elem_dofs[6 * e + b]];
+                if (leaf_of[sp] != lf) continue;
+                p.mask |= (uint8_t)(1u << b);
+                p.key = std::min(p.key, sp);
+            }
+            done |= p.mask;
+            pc.push_back(p);
+        }
+    }
+    std::stable_sort(pc.begin(), pc.end(), [](const Piece &x, const Piece &y) { return x.key < y.key; });
+    const int64_t np = (int64_t)pc.size();
+    std::vector<int32_t> eperm(np);
+    std::vector<uint8_t> mask(np);
+    std::vector<int64_t> keys(np);
+    for (int64_t i = 0; i < np; i++) {
+        eperm[i] = pc[i].elem;
+        mask[i] = pc[i].mask;
+        keys[i] = pc[i].key;
+    }
+    for (int64_t b = 0; b < t.n_box; b++) {
+        t.h_eb[b] = std::lower_bound(keys.begin(), keys.end(), t.h_tb[b]) - keys.begin();
+        t.h_ee[b] = std::lower_bound(keys.begin(), keys.end(), t.h_te[b]) - keys.begin();
+    }
+    t.n_el = np;
+    t.eperm.alloc(&c, std::max<int64_t>(1, np));
+    t.eperm.upload(eperm.data(), np);
+    t.se_mask.alloc(&c, std::max<int64_t>(1, np));
+    t.se_mask.upload(mask.data(), np);
+    t.eb.upload(t.h_eb.data(), t.n_box);
+    t.ee.upload(t.h_ee.data(), t.n_box);
+    c.sync();
+}
+
 void build_tree(bem_tree &t) {
     Ctx &c = *t.ctx;
     const bem_mesh &m = *t.mesh;
-    const int64_t n_el = m.n_el, n_tgt = m.n_dof, n = n_el + n_tgt;
+    // the literal tree keys its sources at the DOF points (eb/ee are then DOF
+    // ranges until the sources are expanded into element pieces at the end)
+    const int64_t n_el = t.literal ? m.n_dof : m.n_el, n_tgt = m.n_dof, n = n_el + n_tgt;
     t.n_el = n_el;
     t.n_tgt = n_tgt;
 
@@ -350,7 +420,8 @@ void build_tree(bem_tree &t) {
     DBuf<int32_t> val;
     key.alloc(&c, n);
     val.alloc(&c, n);
-    k_keys<<<nblocks(n, BS), BS, 0, c.stream>>>(m.xyz.p, m.elem.p, n_el, m.dof_xyz.p, n_tgt, root.p, key.p, val.p);
+    k_keys<<<nblocks(n, BS), BS, 0, c.stream>>>(m.xyz.p, m.elem.p, n_el, m.dof_xyz.p, n_tgt, (int)t.literal, root.p,
+                                                key.p, val.p);
     BEM_LAUNCH_CHECK();
     radix_sort_pairs(c, key.p, val.p, n, 63);
 
@@ -453,7 +524,8 @@ void build_tree(bem_tree &t) {
     k_leaf_radius<<<nblocks(t.n_box, BS / 64), BS, 0, c.stream>>>(t.leaf.p, t.eb.p, t.ee.p, t.tb.p, t.te.p, t.centre.p,
                                                                   t.eperm.p, t.tperm.p, m.elem.p, m.xyz.p,
                                                                   m.dof_xyz.p, m.dof_node.p, node_ptr.p,
-                                                                  node_elems.p, t.n_box, t.radius.p);
+                                                                  node_elems.p, (int)!t.literal, t.n_box,
+                                                                  t.radius.p);
     BEM_LAUNCH_CHECK();
     for (int l = t.max_level; l >= 0; l--) {
         int64_t lo = t.level_off[l], hi = t.level_off[l + 1];
@@ -539,6 +611,7 @@ void build_tree(bem_tree &t) {
     t.h_inter_idx = t.inter_idx.download(t.n_inter);
     t.n_leaf = 0;
     for (int64_t b = 0; b < t.n_box; b++) t.n_leaf += t.h_leaf[b];
+    if (t.literal) expand_literal_sources(t);
 }
 
 }  // namespace bem

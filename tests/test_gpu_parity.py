@@ -39,11 +39,12 @@ def setup(name, B=32, theta=THETA, kappa=0.0, k_hint=0.0, order_min=0, attach=Fa
         m = mesh_by_name(name)
         ctx = context()
         mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
+        # attach: False, True (attached radii) or "literal" (the paper's tree read literally)
         tree = bem.bem_tree_build(ctx, mesh, B=B, order=8, theta=theta, kappa=kappa, k_hint=k_hint,
-                                  order_min=order_min, attach_radii=attach)
+                                  order_min=order_min, attach_radii=2 if attach == "literal" else int(attach))
         om = oracle.OracleMesh(m.xyz, m.elem)
         ot = oracle.OracleTree(om, B=B, theta=theta, kappa=kappa if kappa > 0 else float("inf"), k=k_hint,
-                               attach=attach)
+                               attach=bool(attach), literal=attach == "literal")
         _cache[key] = (m, ctx, mesh, tree, om, ot)
     return _cache[key]
 
@@ -66,7 +67,8 @@ TREE_CASES = [("sphere320", 32, 1.0), ("sphere320", 8, 0.6), ("sphere1280", 16, 
 
 
 ATTACH_CASES = [("sphere1280", 16, 1.0, True), ("cube4", 8, 1.0, True), ("sphere1280_p1", 16, 1.0, True),
-                ("perturbed", 10, 0.6, True)]
+                ("perturbed", 10, 0.6, True), ("sphere1280", 32, 1.0, "literal"), ("cube4", 16, 1.0, "literal"),
+                ("sphere1280_p1", 16, 1.0, "literal"), ("sphere20480", 64, 0.6, "literal")]
 
 
 @pytest.mark.parametrize("name,B,theta,attach", [c + (False,) for c in TREE_CASES] + ATTACH_CASES)
@@ -78,8 +80,11 @@ def test_tree_and_lists_bit_exact(name, B, theta, attach):
     say(f"  boxes {ex['level'].size} leaves {ex['n_leaf']} near {ex['near_idx'].size} inter {ex['inter_idx'].size}")
     assert ex["level"].size == ot.n_box
     assert np.array_equal(ex["root"][:3], ot.corner) and ex["root"][3] == ot.side
+    lit = attach == "literal"  # the element fields then describe element pieces, not the oracle's DOF ranges
     for k, o in (("level", ot.level), ("leaf", ot.leaf), ("parent", ot.parent), ("nchild", ot.nchild),
                  ("elem_begin", ot.eb), ("elem_end", ot.ee), ("tgt_begin", ot.tb), ("tgt_end", ot.te)):
+        if lit and k.startswith("elem"):
+            continue
         assert np.array_equal(ex[k].astype(np.int64), np.asarray(o, np.int64)), k
     assert np.array_equal(ex["prefix"].astype(np.uint64), ot.prefix.astype(np.uint64))
     has_child = ot.nchild > 0
@@ -87,7 +92,11 @@ def test_tree_and_lists_bit_exact(name, B, theta, attach):
     # FP64 bit patterns of centres and radii
     assert np.array_equal(ex["centre"].view(np.uint64), ot.centre.view(np.uint64))
     assert np.array_equal(ex["radius"].view(np.uint64), ot.radius.view(np.uint64))
-    assert np.array_equal(ex["elem_perm"], ot.eperm) and np.array_equal(ex["tgt_perm"], ot.tperm)
+    assert lit or np.array_equal(ex["elem_perm"], ot.eperm)
+    assert np.array_equal(ex["tgt_perm"], ot.tperm)
+    if lit:  # every box's pieces are the elements holding its DOFs, each slot in one piece
+        assert np.all(ex["elem_end"] >= ex["elem_begin"]) and ex["elem_begin"][0] == 0
+        assert np.all((ex["tgt_end"] - ex["tgt_begin"])[ex["leaf"] == 1] <= B)
     assert np.array_equal(ex["near_ptr"], ot.near_ptr) and np.array_equal(ex["near_idx"], ot.near_idx)
     assert np.array_equal(ex["inter_ptr"], ot.inter_ptr) and np.array_equal(ex["inter_idx"], ot.inter_idx)
 
@@ -157,6 +166,35 @@ def test_fmm_fp64_matches_oracle_fmm(name, green, k):
         # double layer K (only used inside A) has a smaller norm: within 1e-5
         bound = 1e-6 if op in (2, 3) else 1e-5
         assert rel(y, dref) < bound, ("truncation", op, rel(y, dref))
+
+
+@pytest.mark.parametrize("name,B", [("sphere1280", 32), ("cube4", 16), ("sphere1280_p1", 16)])
+@pytest.mark.parametrize("green,k", [(0, 0.0), (1, 2.0)])
+def test_literal_tree_products_match_oracle(name, B, green, k):
+    """The paper's tree read literally (DOF sources over their element
+    patches, B counting DOFs, attached radii): the direct product equals the
+    oracle's dense one (the element pieces partition every element's shape
+    functions), the FP64 fast product the oracle's literal fast product, and
+    the mixed one within its tolerance."""
+    bem = _bem()
+    cplx = green == 1
+    m, ctx, mesh, tree, om, ot = setup(name, B=B, theta=1.0, order_min=3, attach="literal")
+    x = bem_inputs.random_vector(om.n_dof, 28, complex_=cplx)[0]
+    xd = to_dev(x, cplx)
+    yd = xd.clone()
+    for op in (bem.BEM_OP_A, bem.BEM_OP_RHS):
+        dref = om.matvec_rows(x, op, green, k)
+        bem.bem_matvec(ctx, tree, green, k, op, bem.BEM_DIRECT, bem.BEM_PREC_FP64, xd, yd)
+        e_dir = rel(yd.cpu().numpy()[0], dref if cplx else dref.real)
+        ref = ot.fmm_matvec(x, op, green, k, order=8, order_min=3)
+        ref = ref if cplx else ref.real
+        bem.bem_matvec(ctx, tree, green, k, op, bem.BEM_FMM, bem.BEM_PREC_FP64, xd, yd)
+        e64 = rel(yd.cpu().numpy()[0], ref)
+        bem.bem_matvec(ctx, tree, green, k, op, bem.BEM_FMM, bem.BEM_PREC_MIXED, xd, yd)
+        e32 = rel(yd.cpu().numpy()[0], ref)
+        say(f"  literal {name} green={green} op={op}: direct {e_dir:.2e} fp64 {e64:.2e} mixed {e32:.2e} "
+            f"(truncation {rel(ref, dref if cplx else dref.real):.2e})")
+        assert e_dir < 1e-10 and e64 < 1e-11 and e32 < MIXED_TOL
 
 
 @pytest.mark.parametrize("green,k", [(0, 0.0), (1, 2.0)])

@@ -405,3 +405,27 @@ def test_attached_radii_cover_attached_elements(oracle_lib, name, B):
             assert d <= Ta.radius[b] * (1 + 1e-15)
             missed += d > To.radius[b]
     assert missed > 0
+
+
+@pytest.mark.parametrize("op", [oracle.OP_S_REG, oracle.OP_K_REG])
+def test_literal_tree_exact_for_terminating_taylor_series(fmm_case, op):
+    """The paper's tree read literally (boxes over the DOF points, every
+    DOF's basis function a source over its element patch): with G = |r|^2 the
+    fast product equals the direct sum, so every (DOF, element slot) piece is
+    counted exactly once; leaves hold at most B DOFs."""
+    om, x = fmm_case
+    for B in (8, 16):
+        T = oracle.OracleTree(om, B=B, theta=0.7, literal=True)
+        assert np.array_equal(T.eb, T.tb) and np.array_equal(T.ee, T.te)
+        assert np.all((T.te - T.tb)[T.leaf.astype(bool)] <= B) and T.inter_idx.size
+        yf = T.fmm_matvec(x, op, green=oracle.R2, order=3)
+        yd = om.matvec_rows(x, op, green=oracle.R2)
+        assert np.linalg.norm(yf - yd) / np.linalg.norm(yd) < 1e-13
+
+
+def test_literal_tree_converges_to_direct(fmm_case):
+    om, x = fmm_case
+    T = oracle.OracleTree(om, B=16, theta=0.7, literal=True)
+    yd = om.matvec_rows(x, oracle.OP_A)
+    errs = [np.linalg.norm(T.fmm_matvec(x, oracle.OP_A, order=p) - yd) / np.linalg.norm(yd) for p in (2, 4, 8)]
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-6
