@@ -302,9 +302,11 @@ def paper_protocol():
     of edge 2, the Neumann data given and the surface potential recovered by
     BiCGSTAB (to 1e-8); FMM with the level-dependent order L_l = min(8, L_min
     + l_max - l) at L_min = 3 (the tables' plain rows) and 4 (their starred
-    rows), beside uniform order 8; the paper's separation test (theta = 1)
-    with its convergence radii (over the elements attached to a leaf's
-    vertices), and with single-owner radii for comparison;
+    rows), beside uniform order 8; the paper's separation test (theta = 1);
+    three trees: the paper's read literally (boxes over the DOF points, B
+    counting them, every DOF's basis function a source, radii over the
+    attached elements), single-owner element sources with those radii, and
+    single-owner sources and radii;
     the tables' leaf sizes B (nodes per box), here B/2 elements for
     second-order meshes (two nodes per element) and 2B for first-order ones
     (one node per two elements).  Spheres: icosphere refinements 1-5 (42 ...
@@ -335,12 +337,12 @@ def paper_protocol():
             if nn == 3:
                 m = bem_inputs.linear(m)
             Be = max(4, Bp // 2) if nn == 6 else 2 * Bp
-            for attach, omin in ((True, 3), (True, 4), (True, 0), (False, 3), (False, 4), (False, 0)):
+            for attach, omin in ((2, 3), (2, 4), (2, 0), (1, 3), (1, 4), (1, 0), (0, 3), (0, 4), (0, 0)):
                 t0 = time.perf_counter()
                 ctx = bem.Context(0)
                 mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
-                tree = bem.bem_tree_build(ctx, mesh, B=Be, order=8, theta=1.0, order_min=omin, k_hint=k,
-                                          attach_radii=attach)
+                tree = bem.bem_tree_build(ctx, mesh, B=Bp if attach == 2 else Be, order=8, theta=1.0,
+                                          order_min=omin, k_hint=k, attach_radii=attach)
                 d = mesh.dofs()
                 r = d["dof_xyz"] - xs[None, :]
                 R = np.linalg.norm(r, axis=1)
@@ -373,8 +375,8 @@ def paper_protocol():
                 ms_prod = (time.perf_counter() - t1) / 20 * 1e3
                 row = {"protocol": f"{table}_{shape}_p{1 if nn == 3 else 2}_{'helmholtz_k2' if green else 'laplace'}",
                        "N": int(m.n_nodes), "n_dof": int(mesh.n_dof), "n_elem": int(m.n_elem), "B_nodes": Bp,
-                       "B_elems": Be, "L_min": omin if omin else 8, "L_max": 8, "theta": 1.0,
-                       "radii": "attached" if attach else "owned",
+                       "B_elems": None if attach == 2 else Be, "L_min": omin if omin else 8, "L_max": 8, "theta": 1.0,
+                       "tree": ("literal", "attached_radii", "owned")[2 - attach],
                        "max_level": int(tree.export()["level"].max()),
                        "eps_rms": err, "eps_rms_rel": err / float(np.sqrt(np.mean(np.abs(ref) ** 2))),
                        "t_setup_s": t_setup, "t_solve_s": best, "iterations": info["iterations"],
