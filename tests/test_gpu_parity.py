@@ -615,7 +615,7 @@ def _field_points(rng, n_out, n_in):
     return np.concatenate([d * r[:, None], far])
 
 
-@pytest.mark.parametrize("name", ["perturbed", "perturbed_p1"])
+@pytest.mark.parametrize("name", ["perturbed", "perturbed_p1", "perturbed:literal"])
 @pytest.mark.parametrize("green,k", [(0, 0.0), (1, 2.0)])
 def test_field_matches_oracle_layer_potentials(name, green, k):
     """bem_field (Section 3.5, tree-accelerated) against the oracle's direct
@@ -626,7 +626,8 @@ def test_field_matches_oracle_layer_potentials(name, green, k):
     import torch
 
     bem = _bem()
-    m, ctx, mesh, tree, om, ot = setup(name)
+    mesh_name, _, tree_kind = name.partition(":")  # ":literal": the paper's tree (element pieces as sources)
+    m, ctx, mesh, tree, om, ot = setup(mesh_name, attach="literal" if tree_kind else False)
     rng = np.random.default_rng(35 + green)
     pts = _field_points(rng, 48, 16)
     phi = rng.standard_normal((2, om.n_dof))
