@@ -174,6 +174,7 @@ int bem_tree_build(bem_ctx *ctx, const bem_mesh *mesh, const bem_tree_opts *opts
             if (opts->max_depth > 0) t->max_depth = opts->max_depth;
             t->k_hint = opts->k_hint;
             t->order_min = opts->order_min;
+            BEM_REQUIRE(opts->attach_radii >= 0 && opts->attach_radii <= 2, BEM_EINVAL, "attach_radii must be 0, 1 or 2");
             t->attach = opts->attach_radii != 0;
             t->literal = opts->attach_radii == 2;
         }

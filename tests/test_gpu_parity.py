@@ -576,6 +576,17 @@ def test_invalid_arguments():
     with pytest.raises(bem.BemError) as e:
         bem.bem_tree_build(ctx, mesh, order=12)
     assert e.value.code == bem.BEM_EUNSUPPORTED
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_tree_build(ctx, mesh, attach_radii=3)
+    assert e.value.code == bem.BEM_EINVAL
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_tree_build(ctx, mesh, order_min=-1)
+    assert e.value.code == bem.BEM_EINVAL
+    with pytest.raises(ValueError):
+        bem.bem_mesh_load(ctx, m.xyz, m.elem[:, :4])  # 4-node elements do not exist
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_mesh_load(ctx, m.xyz, m.elem[:, :3] + 100000)  # first-order node out of range
+    assert e.value.code == bem.BEM_EINVAL
 
 
 def test_kernel_event_timing_modes():
