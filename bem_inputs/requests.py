@@ -29,22 +29,27 @@ def _mesh(shape: str, n_tri: int, axes) -> Mesh:
     return ellipsoid(m, axes)
 
 
-def request_stream(count: int, seed: int, n_tri=(2000, 80000), ka=(1.0, 25.0), nrhs_max: int = 32):
+def request_stream(count: int, seed: int, n_tri=(2000, 80000), ka=(1.0, 25.0), nrhs_max: int = 32,
+                   uniform_size: bool = False, nrhs_fixed: int = 0):
     """List of dicts: key (a mesh identity), shape, n_tri, green (0 Laplace,
     1 Helmholtz), k, nrhs, dirs [nrhs, 3], t (arrival time at unit rate);
-    meshes are generated lazily by ``mesh_of(request)``."""
+    meshes are generated lazily by ``mesh_of(request)``.  uniform_size draws
+    n_tri uniformly instead of log-uniformly; nrhs_fixed > 0 gives every
+    request that many right-hand sides."""
     root = np.random.default_rng(seed)
     children = root.spawn(count)
     t = 0.0
     out = []
     for rng in children:
-        lo, hi = np.log(n_tri[0]), np.log(n_tri[1])
-        nt = int(round(np.exp(rng.uniform(lo, hi))))
+        if uniform_size:
+            nt = int(round(rng.uniform(n_tri[0], n_tri[1])))
+        else:
+            nt = int(round(np.exp(rng.uniform(np.log(n_tri[0]), np.log(n_tri[1])))))
         shape = ("sphere", "cube", "ellipsoid")[int(rng.integers(3))]
         axes = tuple(float(a) for a in rng.uniform(0.5, 2.0, 3)) if shape == "ellipsoid" else None
         green = int(rng.integers(2))
         k = float(rng.uniform(*ka)) if green else 0.0
-        nrhs = int(rng.integers(1, nrhs_max + 1))
+        nrhs = nrhs_fixed if nrhs_fixed > 0 else int(rng.integers(1, nrhs_max + 1))
         g = rng.standard_normal((nrhs, 3))
         dirs = g / np.linalg.norm(g, axis=1, keepdims=True)
         t += float(rng.exponential(1.0))

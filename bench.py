@@ -106,6 +106,9 @@ def main():
                     help="serving measurement on the longer stream (200 requests, 2000-40000 triangles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--batched", action="store_true",
+                    help="run only the batched measurement: 64 instances of 1000-40000 triangles, 16 plane-wave "
+                         "right-hand sides each, served against plain FP64 one-at-a-time solves")
     ap.add_argument("--protocol", action="store_true",
                     help="run only the paper's own test protocol (sphere series, level-dependent order, BiCGSTAB)")
     args = ap.parse_args()
@@ -119,6 +122,10 @@ def main():
         return
     if args.protocol:
         paper_protocol()
+        return
+    if args.batched:
+        print(json.dumps({"batched": serving(64, 20090909, (1000, 40000), (1.0, 20.0), 16, 4, 96 << 30,
+                                             uniform_size=True, nrhs_fixed=16)}), flush=True)
         return
 
     import torch
@@ -406,7 +413,7 @@ def _boundary_data(dofs, req):
     return np.array(rows)
 
 
-def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5):
+def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5, uniform_size=False, nrhs_fixed=0):
     """Served, mixed-precision solves (bem_server_*: concurrent lanes, request
     merging, right-hand sides in lock step) against plain FP64 solves of one
     right-hand side at a time on one context, on the same seeded request
@@ -419,17 +426,20 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5):
     import paper_0908_0673_amd as bem
     from bem_inputs.requests import mesh_of, request_stream
 
-    reqs = request_stream(count, seed, n_tri=n_tri, ka=ka, nrhs_max=nrhs_max)
+    reqs = request_stream(count, seed, n_tri=n_tri, ka=ka, nrhs_max=nrhs_max, uniform_size=uniform_size,
+                          nrhs_fixed=nrhs_fixed)
     meshes = {}
     for r in reqs:
         if r["key"] not in meshes:
             meshes[r["key"]] = mesh_of(r)
     total_rhs = sum(r["nrhs"] for r in reqs)
+    print(f"serving: {len(meshes)} meshes generated, {total_rhs} right-hand sides", file=sys.stderr, flush=True)
     out = {"requests": count, "rhs": total_rhs, "distinct_meshes": len(meshes),
            "elements": [int(min(m.n_elem for m in meshes.values())), int(max(m.n_elem for m in meshes.values()))],
            "lanes": lanes, "hbm_budget_gb": budget / 2 ** 30, "seed": seed,
-           "stream": f"n_tri log-uniform {list(n_tri)}, sphere/cube/ellipsoid, Laplace/Helmholtz 50/50, "
-                     f"ka U{list(ka)}, nrhs U[1,{nrhs_max}]"}
+           "stream": f"n_tri {'uniform' if uniform_size else 'log-uniform'} {list(n_tri)}, sphere/cube/ellipsoid, "
+                     f"Laplace/Helmholtz 50/50, ka U{list(ka)}, "
+                     + (f"nrhs {nrhs_fixed}" if nrhs_fixed else f"nrhs U[1,{nrhs_max}]")}
     # served
     srv = bem.Server(lanes=lanes, hbm_budget=budget, max_batch_rhs=32, precision=bem.BEM_PREC_MIXED)
     try:
@@ -456,6 +466,7 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5):
         out["server_stats"] = srv.stats()
     finally:
         srv.close()
+    print(f"serving: served pass done ({out.get('served_solves_per_s', 0):.1f} solves/s)", file=sys.stderr, flush=True)
     # plain FP64, one request at a time
     ctx = bem.Context(0)
     trees = {}
