@@ -318,7 +318,9 @@ typedef struct {
     int lanes;               /* concurrent workers; 0 -> 4 */
     int64_t hbm_budget;      /* device bytes for resident meshes, trees and solves; 0 -> 32 GiB */
     int max_batch_rhs;       /* most right-hand sides merged into one solve; 0 -> 32 */
-    bem_tree_opts tree;      /* tree options of every mesh (zero fields -> defaults) */
+    bem_tree_opts tree;      /* tree options of every mesh (zero fields -> defaults); one tree
+                                per mesh serves every k, so with kappa > 0 set k_hint to the
+                                largest wavenumber of the Helmholtz requests */
     bem_solve_opts solve;    /* solve options of every request (zero fields -> defaults) */
 } bem_server_opts;
 

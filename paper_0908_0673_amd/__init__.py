@@ -406,7 +406,8 @@ class Server:
 
     def __init__(self, device=0, lanes=4, hbm_budget=32 << 30, max_batch_rhs=32, tol=1e-8, restart=50,
                  max_restarts=100, precision=BEM_PREC_FP64, inner_tol=0.0, max_refine=0, method=BEM_FMM,
-                 krylov=BEM_KRYLOV_GMRES, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21, order_min=0):
+                 krylov=BEM_KRYLOV_GMRES, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21, order_min=0,
+                 k_hint=0.0, attach_radii=0):
         self.L = load_library()
         import torch
 
@@ -414,7 +415,9 @@ class Server:
             raise RuntimeError("no GPU visible: the library runs on gfx950 only")
         o = _ServerOpts()
         o.device, o.lanes, o.hbm_budget, o.max_batch_rhs = device, lanes, int(hbm_budget), max_batch_rhs
-        o.tree = _TreeOpts(B, order, theta, kappa, max_depth, 0.0, order_min, 0)
+        # one tree per mesh serves every k: with kappa > 0, k_hint should be the
+        # largest wavenumber the server will see (the lists then hold for all k below it)
+        o.tree = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min, int(attach_radii))
         o.solve = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method, krylov)
         h = ctypes.c_void_p()
         rc = self.L.bem_server_create(ctypes.byref(o), ctypes.byref(h))
