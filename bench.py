@@ -113,6 +113,8 @@ def main():
                     help="largest ka of the batched set (the set's shape names 20; the trees of a served mesh "
                          "are built once for every k, without the wavenumber bound on their lists, so order 8 "
                          "stays accurate only for moderate ka)")
+    ap.add_argument("--serve-ka-max", type=float, default=25.0,
+                    help="largest ka of the --serve-full stream (see --batched-ka-max)")
     ap.add_argument("--protocol", action="store_true",
                     help="run only the paper's own test protocol (sphere series, level-dependent order, BiCGSTAB)")
     args = ap.parse_args()
@@ -268,7 +270,7 @@ def main():
     serve = None
     if not args.no_serve:
         if args.serve_full:
-            serve = serving(200, 20090908, (2000, 40000), (1.0, 25.0), 32, 4, 96 << 30)
+            serve = serving(200, 20090908, (2000, 40000), (1.0, args.serve_ka_max), 32, 4, 96 << 30)
         else:
             serve = serving(24, 20090908, (1000, 6000), (1.0, 5.0), 8, 4, 32 << 30)
 
