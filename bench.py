@@ -109,6 +109,9 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="run only the batched measurement: 64 instances of 1000-40000 triangles, 16 plane-wave "
                          "right-hand sides each, served against plain FP64 one-at-a-time solves")
+    ap.add_argument("--batched-kappa", type=float, default=0.0,
+                    help="wavenumber bound k (r1 + r2) <= kappa on the lists of the batched set's Helmholtz "
+                         "solves (0: none); with it each Helmholtz batch gets a tree of its own k")
     ap.add_argument("--batched-ka-max", type=float, default=5.0,
                     help="largest ka of the batched set (the set's shape names 20; the trees of a served mesh "
                          "are built once for every k, without the wavenumber bound on their lists, so order 8 "
@@ -131,7 +134,8 @@ def main():
         return
     if args.batched:
         print(json.dumps({"batched": serving(64, 20090909, (1000, 40000), (1.0, args.batched_ka_max), 16, 4,
-                                             96 << 30, uniform_size=True, nrhs_fixed=16)}), flush=True)
+                                             96 << 30, uniform_size=True, nrhs_fixed=16,
+                                             kappa=args.batched_kappa)}), flush=True)
         return
 
     import torch
@@ -419,7 +423,8 @@ def _boundary_data(dofs, req):
     return np.array(rows)
 
 
-def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5, uniform_size=False, nrhs_fixed=0):
+def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5, uniform_size=False, nrhs_fixed=0,
+            kappa=0.0):
     """Served, mixed-precision solves (bem_server_*: concurrent lanes, request
     merging, right-hand sides in lock step) against plain FP64 solves of one
     right-hand side at a time on one context, on the same seeded request
@@ -440,14 +445,16 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5, unif
             meshes[r["key"]] = mesh_of(r)
     total_rhs = sum(r["nrhs"] for r in reqs)
     print(f"serving: {len(meshes)} meshes generated, {total_rhs} right-hand sides", file=sys.stderr, flush=True)
-    out = {"requests": count, "rhs": total_rhs, "distinct_meshes": len(meshes),
+    out = {"requests": count, "rhs": total_rhs, "distinct_meshes": len(meshes), "kappa": kappa,
            "elements": [int(min(m.n_elem for m in meshes.values())), int(max(m.n_elem for m in meshes.values()))],
            "lanes": lanes, "hbm_budget_gb": budget / 2 ** 30, "seed": seed,
            "stream": f"n_tri {'uniform' if uniform_size else 'log-uniform'} {list(n_tri)}, sphere/cube/ellipsoid, "
                      f"Laplace/Helmholtz 50/50, ka U{list(ka)}, "
                      + (f"nrhs {nrhs_fixed}" if nrhs_fixed else f"nrhs U[1,{nrhs_max}]")}
     # served
-    srv = bem.Server(lanes=lanes, hbm_budget=budget, max_batch_rhs=32, precision=bem.BEM_PREC_MIXED)
+    # kappa > 0: the wavenumber bound on the lists; the server then solves every
+    # Helmholtz batch on a tree of its own k, and so does the baseline below
+    srv = bem.Server(lanes=lanes, hbm_budget=budget, max_batch_rhs=32, precision=bem.BEM_PREC_MIXED, kappa=kappa)
     try:
         ids = {key: srv.add_mesh(m.xyz, m.elem)[0] for key, m in meshes.items()}
         chis = [_boundary_data(srv.mesh_dofs(ids[r["key"]]), r) for r in reqs]
@@ -492,10 +499,16 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5, unif
         cplx = r["green"] == 1
         chid = torch.tensor(c if cplx else c.real, dtype=torch.complex128 if cplx else torch.float64, device="cuda:0")
         phid = torch.empty_like(chid)
+        tree, own = trees[r["key"]][1], None
+        if cplx and kappa > 0.0:
+            own = bem.bem_tree_build(ctx, trees[r["key"]][0], B=32, order=8, theta=0.6, kappa=kappa, k_hint=r["k"])
+            tree = own
         for j in range(chid.shape[0]):  # one right-hand side at a time
-            info = bem.bem_solve(ctx, trees[r["key"]][1], r["green"], r["k"], chid[j:j + 1], phid[j:j + 1],
+            info = bem.bem_solve(ctx, tree, r["green"], r["k"], chid[j:j + 1], phid[j:j + 1],
                                  precision=bem.BEM_PREC_FP64)
             nconv += sum(1 for i in info if i["status"] != 0)
+        if own is not None:
+            own.close()
         torch.cuda.synchronize()
         lat_base.append(time.perf_counter() - t1)
         if len(lat_base) % 8 == 0:

@@ -318,9 +318,11 @@ typedef struct {
     int lanes;               /* concurrent workers; 0 -> 4 */
     int64_t hbm_budget;      /* device bytes for resident meshes, trees and solves; 0 -> 32 GiB */
     int max_batch_rhs;       /* most right-hand sides merged into one solve; 0 -> 32 */
-    bem_tree_opts tree;      /* tree options of every mesh (zero fields -> defaults); one tree
-                                per mesh serves every k, so with kappa > 0 set k_hint to the
-                                largest wavenumber of the Helmholtz requests */
+    bem_tree_opts tree;      /* tree options of every mesh (zero fields -> defaults).  With
+                                kappa > 0 and k_hint = 0, each Helmholtz batch is solved on a
+                                tree of its own k (built for the batch and freed after it);
+                                with k_hint > 0, the mesh's one tree serves every k (its lists
+                                then hold for every k <= k_hint) */
     bem_solve_opts solve;    /* solve options of every request (zero fields -> defaults) */
 } bem_server_opts;
 

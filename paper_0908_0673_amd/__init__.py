@@ -415,8 +415,8 @@ class Server:
             raise RuntimeError("no GPU visible: the library runs on gfx950 only")
         o = _ServerOpts()
         o.device, o.lanes, o.hbm_budget, o.max_batch_rhs = device, lanes, int(hbm_budget), max_batch_rhs
-        # one tree per mesh serves every k: with kappa > 0, k_hint should be the
-        # largest wavenumber the server will see (the lists then hold for all k below it)
+        # kappa > 0 with k_hint = 0: every Helmholtz batch gets a tree of its own k;
+        # with k_hint > 0 the mesh's one tree serves every k up to k_hint
         o.tree = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min, int(attach_radii))
         o.solve = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method, krylov)
         h = ctypes.c_void_p()

@@ -182,17 +182,27 @@ void worker(bem_server *s, int lane) {
         if (rc == BEM_OK && (hipMemcpyAsync(L.dchi, chi.data(), nrhs * n * vb, hipMemcpyHostToDevice, st) != hipSuccess ||
                              hipStreamSynchronize(st) != hipSuccess))
             rc = BEM_EDEVICE;
+        // Helmholtz with the wavenumber bound on the lists (tree.kappa > 0) and
+        // no fixed k_hint: the batch gets a tree of its own k, freed after it
+        bem_tree *own = nullptr;
+        if (rc == BEM_OK && green == BEM_HELMHOLTZ && s->o.tree.kappa > 0.0 && s->o.tree.k_hint == 0.0) {
+            bem_tree_opts to = s->o.tree;
+            to.k_hint = k;
+            rc = bem_tree_build(ctx, me.mesh, &to, &own);
+        }
         if (rc == BEM_OK) {
             const size_t before = ctx->c.bytes_live;
-            rc = bem_solve(ctx, me.tree, (bem_green)green, k, nrhs, L.dchi, L.dphi, &s->o.solve, info.data());
+            rc = bem_solve(ctx, own ? own : me.tree, (bem_green)green, k, nrhs, L.dchi, L.dphi, &s->o.solve,
+                           info.data());
             // the first solve of a (Green, k) caches its corrections on the tree
-            me.bytes += ctx->c.bytes_live > before ? ctx->c.bytes_live - before : 0;
+            if (!own) me.bytes += ctx->c.bytes_live > before ? ctx->c.bytes_live - before : 0;
             if (rc == BEM_OK || rc == BEM_ENOCONV) {
                 if (hipMemcpyAsync(phi.data(), L.dphi, nrhs * n * vb, hipMemcpyDeviceToHost, st) != hipSuccess ||
                     hipStreamSynchronize(st) != hipSuccess)
                     rc = BEM_EDEVICE;
             }
         }
+        if (own) bem_tree_free(own);
         lk.lock();
         if (me.bytes && me.n_elem)
             s->bytes_per_elem = std::max(s->bytes_per_elem * 0.5, (double)me.bytes / (double)me.n_elem);

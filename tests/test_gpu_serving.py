@@ -168,3 +168,30 @@ def test_server_first_order_bicgstab_level_order():
             bem.bem_solve(ctx, t, g, k, d, p, krylov=bem.BEM_KRYLOV_BICGSTAB, **SOLVE)
             ref = p.cpu().numpy()[0]
             assert np.array_equal(phi[r], ref if g else ref.real), f"mesh {j} green {g} rhs {r}"
+
+
+def test_server_helmholtz_trees_of_their_own_k():
+    """With the wavenumber bound on the lists (kappa > 0, no fixed k_hint),
+    every Helmholtz batch is solved on a tree built for its k: results equal
+    bem_solve's on such a tree, bit for bit."""
+    bem = _bem()
+    mesh = bem_inputs.icosphere(3)
+    rng = np.random.default_rng(17)
+    srv = bem.Server(lanes=2, max_batch_rhs=4, precision=1, kappa=3.0, **TREE)
+    ks = (4.0, 7.5)
+    try:
+        mid, nd = srv.add_mesh(mesh.xyz, mesh.elem)
+        chis = [rng.standard_normal((2, nd)) + 1j * rng.standard_normal((2, nd)) for _ in ks]
+        res = [srv.poll(srv.submit(mid, 1, k, c)) for k, c in zip(ks, chis)]
+    finally:
+        srv.close()
+    ctx = context()
+    m = bem.bem_mesh_load(ctx, mesh.xyz, mesh.elem)
+    for k, chi, (rc, phi, info, lat) in zip(ks, chis, res):
+        assert rc == 0 and all(i["status"] == 0 for i in info)
+        t = bem.bem_tree_build(ctx, m, kappa=3.0, k_hint=k, **TREE)
+        for r in range(2):
+            d = to_dev(chi[r][None], True)
+            p = d.clone()
+            bem.bem_solve(ctx, t, 1, k, d, p, **SOLVE)
+            assert np.array_equal(phi[r], p.cpu().numpy()[0]), (k, r)
