@@ -119,11 +119,12 @@ def main():
     ap.add_argument("--serve-ka-max", type=float, default=25.0,
                     help="largest ka of the --serve-full stream (see --batched-ka-max)")
     ap.add_argument("--protocol", action="store_true",
-                    help="run only the paper's own test protocol (sphere series, level-dependent order, BiCGSTAB)")
+                    help="run only the paper's own test protocol (Tables 1-8 shapes, level-dependent order, "
+                         "BiCGSTAB, three trees)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(--gpus 1 only).", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:
