@@ -51,7 +51,7 @@ typedef enum {
     BEM_EDEVICE = -3,       /* a HIP runtime call failed */
     BEM_ENOCONV = -4,       /* the solver hit its iteration cap (outputs still written) */
     BEM_ESTATE = -5,        /* handle misuse (wrong context, freed object) */
-    BEM_EUNSUPPORTED = -6,  /* valid request this build does not implement */
+    BEM_EUNSUPPORTED = -6,  /* valid request the library does not implement (e.g. order > 8) */
     BEM_EAGAIN = -7         /* (serving) the request has not completed yet */
 } bem_status;
 
