@@ -1,22 +1,33 @@
-"""Benchmark: fast-multipole BEM matrix-vector product and solve on one MI355X.
+"""Benchmark: fast-multipole BEM matrix-vector products and solves on one MI355X.
 
-Workload (default): Laplace, unit sphere of 20480 curved 6-node triangles
-(40962 collocation nodes), point-source Neumann data, order-8 expansions,
-at most 48 elements per leaf, separation factor 0.62.  A step is one application of the system
-operator A x = c.x - K x through the fast product (strengths, P2M, M2M, M2L,
-L2L, L2P, near field, corrections and free term), with the input already in
-device memory.  The headline value is the mixed-precision product
-(single-precision near field and expansions, double corrections); the plain
-FP64 product, both GMRES(50) solves to a 1e-8 residual, errors against the
-oracle, per-phase device times and the dominant kernel's roofline are
-reported beside it.
+Workloads (the fast product of the system operator A x = c.x - K x, order-8
+expansions, input already in device memory; each tree's leaf size, separation
+factor and wavenumber bound are the cheapest of a sweep whose largest error
+over all rows stays below 1e-6 against the FP64 direct product):
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere20480] [--no-cpu]
+  c2_sphere  Laplace, unit sphere of 20480 curved 6-node triangles (40962
+             DOFs), B = 48, theta = 0.5
+  c2_cube    Laplace, cube [-1, 1]^3 of 24300 triangles with sharp edges
+             (49686 DOFs), B = 48, theta = 0.55
+  c3         Helmholtz ka = 10, geodesic sphere of 30420 triangles (60842
+             complex DOFs), B = 64, theta = 0.5, k (r1 + r2) <= 2.2
+
+A step is one mixed-precision product (single-precision near field and
+expansions, double-precision corrections, free term and combination) on each
+of the two meshes of the C2 configuration, the one the metric is quoted on;
+the headline value is their unknowns per second.  C3, the plain FP64
+products, GMRES(50) solves to a 1e-8 FP64 residual (plain FP64 against mixed
+precision), errors against the oracle (sampled rows, 2-norm and largest row),
+per-phase device times, every workload's dominant-kernel roofline, the
+serving measurement and the CPU oracle are reported beside it.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serve] [--no-c3]
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,23 +39,29 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-FP32_VEC_PEAK = 157.3  # TFLOP/s, MI355X vector FP32 (256 CUs, 2.4 GHz, packed)
+FP32_VEC_PEAK = 157.3  # TFLOP/s, MI355X vector FP32 (256 CUs x 2.4 GHz; counts packed FP32)
+FP32_VEC_UNPACKED = 78.6  # TFLOP/s: the same without packed FP32, which this build does not emit
 FP32_MFMA_PEAK = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 FP64_VEC_PEAK = 78.6
 KERNEL_PEAKS = {"m2l": ("mfma", FP32_MFMA_PEAK), "p2p": ("alu", FP32_VEC_PEAK)}
 # source file of each timed kernel (the HBM traffic figures hold for one version of it)
 KERNEL_SOURCES = {"m2l": "m2l.hip", "p2p": "fmm.hip"}
 
+# name -> (mesh, Green's function, k, B, theta, kappa)
+WORKLOADS = {
+    "c2_sphere": ("sphere20480", 0, 0.0, 48, 0.5, 0.0),
+    "c2_cube": ("cube24300", 0, 0.0, 48, 0.55, 0.0),
+    "c3": ("geodesic30420", 1, 10.0, 64, 0.5, 2.2),
+}
+HEADLINE = ("c2_sphere", "c2_cube")
 
-def hbm_traffic(kernel, workload, B, theta):
-    """HBM bytes per launch of the mixed-precision kernel, from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload, scaled by the
+
+def hbm_traffic(kernel, mesh, B, theta, kappa):
+    """HBM bytes per launch of the mixed-precision kernel on this tree, from
+    the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, scaled by the
     copy-kernel calibration; None when there is none or the kernel's source
-    has changed since the counters were taken (or they were taken on another
-    leaf size / separation factor)."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.txt")
+    has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{mesh}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -56,9 +73,12 @@ def hbm_traffic(kernel, workload, B, theta):
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if kv.get("source_sha256") != sha or "hbm_bytes_per_launch" not in kv:
         return None
-    if kv.get("B") != str(B) or abs(float(kv.get("theta", "nan")) - theta) > 1e-12:
-        return None  # counters taken on another tree
-    return float(kv["hbm_bytes_per_launch"])
+    try:
+        same = (int(kv.get("B", -1)) == B and abs(float(kv.get("theta", "nan")) - theta) < 1e-12
+                and abs(float(kv.get("kappa", "0")) - kappa) < 1e-12)
+    except ValueError:
+        same = False
+    return float(kv["hbm_bytes_per_launch"]) if same else None
 
 
 def copy_calibration():
@@ -75,31 +95,147 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_each_way": 4 * n, "launches": 3}))
 
 
-def algorithmic_flops(stats, P, dbl=True):
-    """Per-product algorithmic flop counts of the two heavy phases.
+def algorithmic_flops(stats, P, helm):
+    """Per-product algorithmic flop counts of the two heavy phases (operator A,
+    double layer).
 
-    near field: per (target, source point) pair, Laplace double layer:
-      3 sub + 5 (r^2) + 1 (rsqrt) + 5 (r.n) + 3 (r^-3 scale) + 2 (fma) = 19
-    M2L: per (target box, source box) pair a P x P product: 2 P^2.
+    near field, per (target, source point) pair, as the kernel evaluates it:
+      Laplace:   3 (difference) + 5 (r^2) + 1 (1/r) + 5 (r.n) + 3 (r^-3) + 2 (accumulate) = 19
+      Helmholtz: 3 + 5 + 1 + 5 (r.n) + 4 (G, r.n / r^3) + 2 (k r) + 31 (sin and cos of k r by
+                 reduction and polynomials) + 6 (dG/dn) + 8 (complex strength and accumulate) = 65
+    M2L: per (target box, source box) pair a P x P product, 2 P^2 real, 8 P^2 complex.
     """
-    return {"p2p": 19.0 * stats["n_p2p"] if dbl else 13.0 * stats["n_p2p"],
-            "m2l": 2.0 * P * P * stats["n_m2l"]}
+    return {"p2p": (65.0 if helm else 19.0) * stats["n_p2p"],
+            "m2l": (8.0 if helm else 2.0) * P * P * stats["n_m2l"]}
+
+
+class Workload:
+    """One tree of one named workload on the shared context, with its input."""
+
+    def __init__(self, ctx, name):
+        import torch
+
+        import bem_inputs
+        import paper_0908_0673_amd as bem
+
+        self.bem, self.ctx, self.name = bem, ctx, name
+        self.mesh_name, self.green, self.k, self.B, self.theta, self.kappa = WORKLOADS[name]
+        t0 = time.perf_counter()
+        self.m = bem_inputs.workload(self.mesh_name)
+        self.mesh = bem.bem_mesh_load(ctx, self.m.xyz, self.m.elem)
+        self.tree = bem.bem_tree_build(ctx, self.mesh, B=self.B, order=8, theta=self.theta, kappa=self.kappa,
+                                       k_hint=self.k)
+        self.n = self.mesh.n_dof
+        self.cplx = self.green == 1
+        self.x_np = bem_inputs.random_vector(self.n, 1, complex_=self.cplx)[0]
+        dt = torch.complex128 if self.cplx else torch.float64
+        self.x = torch.tensor(self.x_np if self.cplx else self.x_np.real, dtype=dt, device="cuda:0")[None].contiguous()
+        self.y = torch.empty_like(self.x)
+        for prec in (0, 1):  # the first products build corrections, free term, plans (setup)
+            self.product(prec)
+        torch.cuda.synchronize()
+        self.setup_s = time.perf_counter() - t0
+        self.stats = self.tree.stats(self.green, self.k)
+
+    def product(self, prec, op=2):
+        self.bem.bem_matvec(self.ctx, self.tree, self.green, self.k, op, self.bem.BEM_FMM, prec, self.x, self.y)
+
+    def config(self):
+        return {"workload": f"{'helmholtz_ka10' if self.cplx else 'laplace'}_{self.mesh_name}_fmm_matvec",
+                "n_elem": self.m.n_elem, "n_dof": self.n, "value_type": "complex" if self.cplx else "real",
+                "nrhs": 1, "order": 8, "B": self.B, "theta": self.theta, "kappa": self.kappa or None,
+                "k": self.k or None, "operator": "A = c.x - K x"}
+
+
+def probe_dominant(ctx, wls, prec):
+    """Average launch time of the two heavy kernels over three untimed
+    products of each workload (events around both, the usual scheduling)."""
+    import torch
+
+    out = {}
+    for w in wls:
+        ctx.timing(2)
+        for _ in range(3):
+            w.product(prec)
+        torch.cuda.synchronize()
+        ph = ctx.timing(0)
+        out[w.name] = {k: ph[k][0] / max(1, ph[k][1]) for k in ("m2l", "p2p")}
+    return out
+
+
+def timed_products(ctx, wls, prec, steps, warmup, dom):
+    """steps x (one product of every workload in wls), with one event pair per
+    product around the kernel `dom` (on its stream); returns wall ms per step
+    and the event-timed (ms, launches) of that kernel."""
+    import torch
+
+    for _ in range(warmup):
+        for w in wls:
+            w.product(prec)
+    torch.cuda.synchronize()
+    ctx.timing(3 if dom == "p2p" else 4)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for w in wls:
+            w.product(prec)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ph = ctx.timing(0)
+    return 1e3 * dt / steps, ph[dom]
+
+
+def phase_times(ctx, w, prec, reps):
+    import torch
+
+    ctx.timing(1)
+    for _ in range(reps):
+        w.product(prec)
+    torch.cuda.synchronize()
+    ph = ctx.timing(0)
+    return {k: v[0] / max(1, v[1]) for k, v in ph.items()}
+
+
+def oracle_errors(w, yv, rows_n=64):
+    """Sampled rows of the oracle's direct product against y: 2-norm and
+    largest-row relative errors."""
+    import oracle
+
+    om = oracle.OracleMesh(w.m.xyz, w.m.elem)
+    rows = np.sort(np.random.default_rng(2).choice(w.n, rows_n, replace=False))
+    ref = om.matvec_rows(w.x_np, oracle.OP_A, green=w.green, k=w.k, rows=rows)
+    if not w.cplx:
+        ref = ref.real
+    out = {}
+    for name, y in yv.items():
+        d = np.abs(y[rows] - ref)
+        out[name] = {"rel_2norm": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+                     "rel_max_row": float(d.max() / np.abs(ref).max())}
+    out["rows_sampled"] = int(rows.size)
+    return out
+
+
+def roofline(dom, flops, ms_launch, launches, traffic):
+    bound, peak = KERNEL_PEAKS[dom]
+    achieved = flops / (ms_launch * 1e-3) / 1e12
+    r = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+         "frac": achieved / peak, "traffic": traffic, "algorithmic_flop_per_launch": flops,
+         "avg_launch_ms": ms_launch, "launches": launches}
+    if dom == "p2p":  # the attainable VALU peak of a build without packed FP32
+        r["peak_unpacked"] = FP32_VEC_UNPACKED
+        r["frac_unpacked"] = achieved / FP32_VEC_UNPACKED
+    return r
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--workload", default="sphere20480")
-    # leaf size and separation factor: the fastest pair measured with the
-    # product's error against the oracle below 1e-6 on this workload (sweep of
-    # B in 12..128 and theta in 0.6..0.7: 6.9e-7 at B = 48, theta = 0.62)
-    ap.add_argument("--theta", type=float, default=0.62)
-    ap.add_argument("--B", type=int, default=48)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the Helmholtz ka = 10 workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-fmm", action="store_true", help="skip timing the oracle's fast product")
     ap.add_argument("--no-phases", action="store_true", help="skip the serialized per-phase timing pass")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-full", action="store_true",
@@ -109,18 +245,15 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="run only the batched measurement: 64 instances of 1000-40000 triangles, 16 plane-wave "
                          "right-hand sides each, served against plain FP64 one-at-a-time solves")
-    ap.add_argument("--batched-kappa", type=float, default=0.0,
-                    help="wavenumber bound k (r1 + r2) <= kappa on the lists of the batched set's Helmholtz "
-                         "solves (0: none); with it each Helmholtz batch gets a tree of its own k")
-    ap.add_argument("--batched-ka-max", type=float, default=5.0,
-                    help="largest ka of the batched set (the set's shape names 20; the trees of a served mesh "
-                         "are built once for every k, without the wavenumber bound on their lists, so order 8 "
-                         "stays accurate only for moderate ka)")
+    ap.add_argument("--batched-kappa", type=float, default=2.2,
+                    help="wavenumber bound k (r1 + r2) <= kappa on the lists of the Helmholtz trees")
+    ap.add_argument("--batched-ka-max", type=float, default=20.0, help="largest ka of the batched set")
     ap.add_argument("--serve-ka-max", type=float, default=25.0,
                     help="largest ka of the --serve-full stream (see --batched-ka-max)")
     ap.add_argument("--protocol", action="store_true",
                     help="run only the paper's own test protocol (Tables 1-8 shapes, level-dependent order, "
                          "BiCGSTAB, three trees)")
+    ap.add_argument("--only", default="", help="comma-separated workloads to set up (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -141,177 +274,159 @@ def main():
 
     import torch
 
-    import bem_inputs
     import paper_0908_0673_amd as bem
 
-    t_setup0 = time.perf_counter()
-    m = bem_inputs.workload(args.workload)
     ctx = bem.Context(0)
-    mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
-    tree = bem.bem_tree_build(ctx, mesh, B=args.B, order=8, theta=args.theta)
-    stats = tree.stats()
-    n = mesh.n_dof
-    dof = mesh.dofs()
-    x_np = bem_inputs.random_vector(n, 1)[0]
-    x = torch.tensor(x_np, dtype=torch.float64, device="cuda:0")[None]
-    y = torch.empty_like(x)
-    # first products build the corrections and the free term (setup)
-    for prec in (bem.BEM_PREC_FP64, bem.BEM_PREC_MIXED):
-        bem.bem_matvec(ctx, tree, 0, 0.0, bem.BEM_OP_A, bem.BEM_FMM, prec, x, y)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t_setup0
+    names = [n for n in WORKLOADS if not (args.no_c3 and n == "c3")]
+    if args.only:
+        names = [n for n in names if n in args.only.split(",")]
+    wls = {}
+    for n in names:
+        wls[n] = Workload(ctx, n)
+        print(f"bench: {n} set up ({wls[n].setup_s:.2f} s)", file=sys.stderr, flush=True)
+    head = [wls[n] for n in HEADLINE if n in wls]
 
-    def timed(prec, steps, warmup):
-        for _ in range(warmup):
-            bem.bem_matvec(ctx, tree, 0, 0.0, bem.BEM_OP_A, bem.BEM_FMM, prec, x, y)
-        torch.cuda.synchronize()
-        # which heavy kernel dominates: both bracketed by events, untimed
-        ctx.timing(2)
-        for _ in range(3):
-            bem.bem_matvec(ctx, tree, 0, 0.0, bem.BEM_OP_A, bem.BEM_FMM, prec, x, y)
-        torch.cuda.synchronize()
-        probe = ctx.timing(0)
-        per = {k: probe[k][0] / max(1, probe[k][1]) for k in ("m2l", "p2p")}
-        dom = max(per, key=lambda k: per[k])
-        # timed region: one event pair per product, around the dominant kernel
-        # on the stream it runs on (the product keeps its two-stream schedule)
-        ctx.timing(3 if dom == "p2p" else 4)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            bem.bem_matvec(ctx, tree, 0, 0.0, bem.BEM_OP_A, bem.BEM_FMM, prec, x, y)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        heavy = ctx.timing(0)
-        heavy = {"dominant": dom, "timed": heavy[dom], "probe": per}
-        yv = y.cpu().numpy()[0].copy()
-        # per-phase device times from HIP events in separate products (while
-        # phases are timed, the library runs every phase on the one stream)
-        phases = None
-        if not args.no_phases:
-            ctx.timing(1)
-            for _ in range(max(3, steps // 4)):
-                bem.bem_matvec(ctx, tree, 0, 0.0, bem.BEM_OP_A, bem.BEM_FMM, prec, x, y)
+    # every workload on its own: dominant kernel, event-timed products, errors
+    per = {}
+    P = 165
+    for n, w in wls.items():
+        probe = probe_dominant(ctx, [w], bem.BEM_PREC_MIXED)[n]
+        dom = max(probe, key=lambda k: probe[k])
+        steps_w = max(5, args.steps // (5 if w.cplx else 1))
+        ms = {}
+        ys = {}
+        dom_t = None
+        for prec, pname in ((bem.BEM_PREC_MIXED, "mixed"), (bem.BEM_PREC_FP64, "fp64")):
+            ms_step, kt = timed_products(ctx, [w], prec, steps_w if prec else max(3, steps_w // 2), 3, dom)
+            ms[pname] = ms_step
+            if prec == bem.BEM_PREC_MIXED:
+                dom_t = kt
+            w.product(prec)
             torch.cuda.synchronize()
-            phases = ctx.timing(0)
-        return dt, heavy, phases, yv
+            ys[pname] = w.y.cpu().numpy()[0].copy()
+        fl = algorithmic_flops(w.stats, P, w.cplx)
+        ms_launch = dom_t[0] / max(1, dom_t[1])
+        per[n] = {"config": w.config(),
+                  "ms_per_product": ms,
+                  "unknowns_per_s": {k: w.n / (v * 1e-3) for k, v in ms.items()},
+                  "error_vs_oracle": oracle_errors(w, ys),
+                  "roofline": roofline(dom, fl[dom], ms_launch, dom_t[1],
+                                       hbm_traffic(dom, w.mesh_name, w.B, w.theta, w.kappa)),
+                  "other_kernel_ms": {k: v for k, v in probe.items() if k != dom},
+                  "tree": w.stats, "setup_s": w.setup_s}
+        if not args.no_phases:
+            per[n]["phases_ms"] = {pname: phase_times(ctx, w, prec, 5)
+                                   for prec, pname in ((bem.BEM_PREC_MIXED, "mixed"), (bem.BEM_PREC_FP64, "fp64"))}
+        print(f"bench: {n} measured ({ms['mixed']:.3f} ms mixed, {ms['fp64']:.3f} ms fp64)", file=sys.stderr,
+              flush=True)
 
-    dt_mixed, hv_mixed, ph_mixed, y_mixed = timed(bem.BEM_PREC_MIXED, args.steps, args.warmup)
-    dt_fp64, hv_fp64, ph_fp64, y_fp64 = timed(bem.BEM_PREC_FP64, max(3, args.steps // 2), 1)
-    ms_mixed = 1e3 * dt_mixed / args.steps
-    ms_fp64 = 1e3 * dt_fp64 / max(3, args.steps // 2)
-    value = n / (ms_mixed * 1e-3)
-
-    # errors against the oracle's direct product on sampled rows
-    err = {}
-    try:
-        import oracle
-
-        om = oracle.OracleMesh(m.xyz, m.elem)
-        rows = np.sort(np.random.default_rng(2).choice(n, 64, replace=False))
-        ref = om.matvec_rows(x_np, oracle.OP_A, rows=rows).real
-        err = {"mixed": float(np.linalg.norm(y_mixed[rows] - ref) / np.linalg.norm(ref)),
-               "fp64": float(np.linalg.norm(y_fp64[rows] - ref) / np.linalg.norm(ref)),
-               "rows_sampled": int(rows.size)}
-    except Exception as e:  # noqa: BLE001
-        err = {"error": str(e)}
+    # the headline step: one mixed product on each C2 mesh; events around the
+    # kernel that dominates the step
+    out = {"metric": "FMM-BEM matvec unknowns/s", "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 near field and expansions, f64 corrections", "data": "synthetic"}
+    if head:
+        tot = {k: sum(per[w.name]["other_kernel_ms"].get(k, 0.0) + (
+            per[w.name]["roofline"]["avg_launch_ms"] if per[w.name]["roofline"]["kernel"] == k else 0.0)
+            for w in head) for k in ("m2l", "p2p")}
+        dom = max(tot, key=lambda k: tot[k])
+        ms_step, kt = timed_products(ctx, head, bem.BEM_PREC_MIXED, args.steps, args.warmup, dom)
+        n_head = sum(w.n for w in head)
+        flops = sum(algorithmic_flops(w.stats, P, w.cplx)[dom] for w in head) / len(head)
+        traffic = [hbm_traffic(dom, w.mesh_name, w.B, w.theta, w.kappa) for w in head]
+        out.update({
+            "value": n_head / (ms_step * 1e-3), "ms_per_step": ms_step,
+            "config": {"workload": "laplace_c2_sphere20480_and_cube24300_fmm_matvec",
+                       "meshes": [w.config() for w in head], "n_dof_per_step": n_head,
+                       "step": "one mixed-precision product of A on each mesh"},
+            "roofline": roofline(dom, flops, kt[0] / max(1, kt[1]), kt[1],
+                                 None if None in traffic else sum(traffic) / len(traffic)),
+        })
+        out["roofline"]["note"] = ("averages over the step's launches on both meshes (flops and traffic per "
+                                   "launch averaged the same way)")
+    out["workloads"] = per
 
     # solves: plain FP64 GMRES(50) vs mixed-precision (relaxed) GMRES, to an FP64 residual of 1e-8
-    solve = {}
     if not args.no_solve:
-        from oracle import analytic
+        out["solve"] = solves(bem, ctx, wls)
 
-        phi, chi = analytic.point_source(dof["dof_xyz"], dof["dof_normal"])
-        chid = torch.tensor(chi.real, dtype=torch.float64, device="cuda:0")[None]
-        # one untimed solve first: the right-hand side's operator (single
-        # layer) builds its weights and corrections on first use
-        bem.bem_solve(ctx, tree, 0, 0.0, chid, torch.zeros_like(chid), tol=1e-8, restart=50)
+    if not args.no_serve:
+        if args.serve_full:
+            out["serving"] = serving(200, 20090908, (2000, 40000), (1.0, args.serve_ka_max), 32, 4, 96 << 30,
+                                     kappa=2.2)
+        else:
+            out["serving"] = serving(24, 20090908, (1000, 6000), (1.0, 5.0), 8, 4, 32 << 30, kappa=2.2)
+
+    if not args.no_cpu and "c2_sphere" in wls:
+        w = wls["c2_sphere"]
+        out["cpu_baseline"] = cpu_baseline(w.m, w.x_np, args.cpu_seconds, fmm=not args.no_cpu_fmm, B=w.B,
+                                           theta=w.theta)
+    print(json.dumps(out), flush=True)
+
+
+def solves(bem, ctx, wls):
+    """Plain FP64 against mixed-precision GMRES(50) to an FP64 residual of
+    1e-8: point-source data on the C2 meshes, the rigid-sphere plane wave on
+    C3 (against the series solution)."""
+    import torch
+
+    from oracle import analytic
+
+    res = {}
+    for n, w in wls.items():
+        d = w.mesh.dofs()
+        if w.cplx:
+            inc, chi = analytic.plane_wave(d["dof_xyz"], d["dof_normal"], w.k)
+            ref = analytic.rigid_sphere_total(w.k, d["dof_xyz"][:, 2] / np.linalg.norm(d["dof_xyz"], axis=1))
+            chid = torch.tensor(chi, dtype=torch.complex128, device="cuda:0")[None].contiguous()
+        else:
+            phi, chi = analytic.point_source(d["dof_xyz"], d["dof_normal"])
+            chid = torch.tensor(chi.real, dtype=torch.float64, device="cuda:0")[None].contiguous()
+        # one untimed solve first: the right-hand side's operator builds its tables on first use
+        bem.bem_solve(ctx, w.tree, w.green, w.k, chid, torch.zeros_like(chid), tol=1e-8, restart=50)
+        r = {}
         for name, prec in (("fp64", bem.BEM_PREC_FP64), ("mixed", bem.BEM_PREC_MIXED)):
             phid = torch.zeros_like(chid)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            info = bem.bem_solve(ctx, tree, 0, 0.0, chid, phid, tol=1e-8, restart=50, precision=prec)[0]
+            info = bem.bem_solve(ctx, w.tree, w.green, w.k, chid, phid, tol=1e-8, restart=50, precision=prec)[0]
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             sol = phid.cpu().numpy()[0]
-            solve[name] = {"seconds": dt, "solves_per_s": 1.0 / dt, "iterations": info["iterations"],
-                           "refinements": info["refinements"], "matvecs": info["matvecs"],
-                           "residual": info["residual"],
-                           "rms_error_vs_analytic": float(np.sqrt(np.mean((sol - phi.real) ** 2)))}
-        # field of the solved problem at points outside the body (Section 3.5),
-        # against the source's own field
+            e = {"seconds": dt, "solves_per_s": 1.0 / dt, "iterations": info["iterations"],
+                 "restarts": info["restarts"], "matvecs": info["matvecs"], "residual": info["residual"],
+                 "status": info["status"]}
+            if w.cplx:
+                tot = sol + inc
+                e["rms_rel_error_vs_series"] = float(np.linalg.norm(tot - ref) / np.linalg.norm(ref))
+            else:
+                e["rms_error_vs_analytic"] = float(np.sqrt(np.mean((sol - phi.real) ** 2)))
+            r[name] = e
+        res[n] = r
+        print(f"bench: {n} solves done", file=sys.stderr, flush=True)
+    if "c2_sphere" in wls:  # field of the solved problem at points outside the body (Section 3.5)
+        w = wls["c2_sphere"]
+        d = w.mesh.dofs()
+        phi_a, chi = analytic.point_source(d["dof_xyz"], d["dof_normal"])
+        chid = torch.tensor(chi.real, dtype=torch.float64, device="cuda:0")[None].contiguous()
+        phid = torch.zeros_like(chid)
+        bem.bem_solve(ctx, w.tree, 0, 0.0, chid, phid, tol=1e-8, precision=bem.BEM_PREC_MIXED)
         rng = np.random.default_rng(7)
         dirs = rng.standard_normal((4096, 3))
         pts = dirs / np.linalg.norm(dirs, axis=1, keepdims=True) * rng.uniform(1.4, 4.0, (4096, 1))
         pd = torch.tensor(pts, dtype=torch.float64, device="cuda:0")
-        bem.bem_field(ctx, tree, 0, 0.0, phid, chid, pd[:64])
+        bem.bem_field(ctx, w.tree, 0, 0.0, phid, chid, pd[:64])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        u = bem.bem_field(ctx, tree, 0, 0.0, phid, chid, pd)
+        u = bem.bem_field(ctx, w.tree, 0, 0.0, phid, chid, pd)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         want = 1.0 / (4 * np.pi * np.linalg.norm(pts - np.array([0.1, 0.2, 0.3]), axis=1))
-        solve["field"] = {"points": len(pts), "seconds": dt, "points_per_s": len(pts) / dt, "theta": 0.25,
-                          "max_rel_error_vs_analytic": float(np.abs(u.cpu().numpy()[0] - want).max() / want.max()),
-                          "note": "FP64, from the mixed solve's phi; includes the per-call moments and M2M"}
-
-    # roofline of the dominant kernel of the headline product: the M2L
-    # products run on the FP32 matrix cores, the near field on the FP32 VALU;
-    # its launch duration is the event pair around it in every product of the
-    # timed region (the other kernel's comes from the untimed probe products)
-    P = 165
-    flops = algorithmic_flops(stats, P)
-    dom = hv_mixed["dominant"]
-    ms_launch = hv_mixed["timed"][0] / max(1, hv_mixed["timed"][1])
-    achieved = flops[dom] / (ms_launch * 1e-3) / 1e12
-    bound, peak = KERNEL_PEAKS[dom]
-    other = [k for k in hv_mixed["probe"] if k != dom][0]
-    roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": hbm_traffic(dom, args.workload, args.B, args.theta),
-                "algorithmic_flop_per_launch": flops[dom], "avg_launch_ms": ms_launch,
-                "launches": hv_mixed["timed"][1],
-                "other_kernel": {"name": other, "avg_launch_ms": hv_mixed["probe"][other],
-                                 "note": "three untimed products with events around both kernels"}}
-
-    serve = None
-    if not args.no_serve:
-        if args.serve_full:
-            serve = serving(200, 20090908, (2000, 40000), (1.0, args.serve_ka_max), 32, 4, 96 << 30)
-        else:
-            serve = serving(24, 20090908, (1000, 6000), (1.0, 5.0), 8, 4, 32 << 30)
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(m, x_np, args.cpu_seconds)
-
-    out = {
-        "metric": "FMM-BEM matvec unknowns/s",
-        "value": value,
-        "unit": "unknowns/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_mixed,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 near field and expansions, f64 corrections",
-        "data": "synthetic",
-        "config": {"workload": f"laplace_{args.workload}_fmm_matvec", "n_elem": m.n_elem, "n_dof": n, "nrhs": 1,
-                   "order": 8, "B": args.B, "theta": args.theta, "operator": "A = c.x - K x"},
-        "fp64": {"ms_per_step": ms_fp64, "unknowns_per_s": n / (ms_fp64 * 1e-3)},
-        "error_vs_oracle": err,
-        "phases_ms_per_step": None if ph_mixed is None else {
-            "mixed": {k: v[0] / max(1, v[1]) for k, v in ph_mixed.items()},
-            "fp64": {k: v[0] / max(1, v[1]) for k, v in ph_fp64.items()},
-            "note": "serialized products (one stream), HIP events between phases"},
-        "tree": stats,
-        "setup_s": t_setup,
-        "solve": solve,
-        "roofline": roofline,
-        "serving": serve,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out))
+        res["field_c2_sphere"] = {
+            "points": len(pts), "seconds": dt, "points_per_s": len(pts) / dt, "theta": 0.25,
+            "max_rel_error_vs_analytic": float(np.abs(u.cpu().numpy()[0] - want).max() / want.max()),
+            "note": "FP64, from the mixed solve's phi; includes the per-call moments and M2M"}
+    return res
 
 
 def paper_protocol():
@@ -425,7 +540,7 @@ def _boundary_data(dofs, req):
 
 
 def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5, uniform_size=False, nrhs_fixed=0,
-            kappa=0.0):
+            kappa=2.2, max_iters=1500):
     """Served, mixed-precision solves (bem_server_*: concurrent lanes, request
     merging, right-hand sides in lock step) against plain FP64 solves of one
     right-hand side at a time on one context, on the same seeded request
@@ -455,7 +570,8 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5, unif
     # served
     # kappa > 0: the wavenumber bound on the lists; the server then solves every
     # Helmholtz batch on a tree of its own k, and so does the baseline below
-    srv = bem.Server(lanes=lanes, hbm_budget=budget, max_batch_rhs=32, precision=bem.BEM_PREC_MIXED, kappa=kappa)
+    srv = bem.Server(lanes=lanes, hbm_budget=budget, max_batch_rhs=32, precision=bem.BEM_PREC_MIXED, kappa=kappa,
+                     max_iters=max_iters)
     try:
         ids = {key: srv.add_mesh(m.xyz, m.elem)[0] for key, m in meshes.items()}
         chis = [_boundary_data(srv.mesh_dofs(ids[r["key"]]), r) for r in reqs]
@@ -485,31 +601,31 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5, unif
     finally:
         srv.close()
     print(f"serving: served pass done ({out.get('served_solves_per_s', 0):.1f} solves/s)", file=sys.stderr, flush=True)
-    # plain FP64, one request at a time
+    # plain FP64, one request at a time, one right-hand side at a time, on the
+    # trees the server uses (per mesh and, with the wavenumber bound, per
+    # wavenumber bucket), cached on first use
     ctx = bem.Context(0)
-    trees = {}
+    meshes_dev, trees = {}, {}
     t0 = time.perf_counter()
     lat_base = []
     nconv = 0
     for r, c in zip(reqs, chis):
         t1 = time.perf_counter()
-        if r["key"] not in trees:
+        if r["key"] not in meshes_dev:
             m = meshes[r["key"]]
-            mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
-            trees[r["key"]] = (mesh, bem.bem_tree_build(ctx, mesh, B=32, order=8, theta=0.6))
+            meshes_dev[r["key"]] = bem.bem_mesh_load(ctx, m.xyz, m.elem)
+        kh = _bucket_top(r["k"]) if (kappa > 0.0 and r["green"] == 1) else 0.0
+        if (r["key"], kh) not in trees:
+            trees[(r["key"], kh)] = bem.bem_tree_build(ctx, meshes_dev[r["key"]], B=32, order=8, theta=0.5,
+                                                       kappa=kappa, k_hint=kh)
+        tree = trees[(r["key"], kh)]
         cplx = r["green"] == 1
         chid = torch.tensor(c if cplx else c.real, dtype=torch.complex128 if cplx else torch.float64, device="cuda:0")
         phid = torch.empty_like(chid)
-        tree, own = trees[r["key"]][1], None
-        if cplx and kappa > 0.0:
-            own = bem.bem_tree_build(ctx, trees[r["key"]][0], B=32, order=8, theta=0.6, kappa=kappa, k_hint=r["k"])
-            tree = own
-        for j in range(chid.shape[0]):  # one right-hand side at a time
+        for j in range(chid.shape[0]):
             info = bem.bem_solve(ctx, tree, r["green"], r["k"], chid[j:j + 1], phid[j:j + 1],
-                                 precision=bem.BEM_PREC_FP64)
+                                 precision=bem.BEM_PREC_FP64, max_iters=max_iters)
             nconv += sum(1 for i in info if i["status"] != 0)
-        if own is not None:
-            own.close()
         torch.cuda.synchronize()
         lat_base.append(time.perf_counter() - t1)
         if len(lat_base) % 8 == 0:
@@ -518,17 +634,28 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5, unif
     out["baseline_fp64_solves_per_s"] = total_rhs / dtb
     out["baseline_not_converged"] = nconv
     out["baseline_latency_ms"] = {"p50": float(np.percentile(lat_base, 50) * 1e3),
-                                  "p99": float(np.percentile(lat_base, 99) * 1e3)}
+                                  "p99": float(np.percentile(lat_base, 99) * 1e3),
+                                  "note": "back to back, no queue: service time per request"}
     out["speedup_solves_per_s"] = out["served_solves_per_s"] / out["baseline_fp64_solves_per_s"]
     for tr in trees.values():
-        tr[1].close()
-        tr[0].close()
+        tr.close()
+    for m in meshes_dev.values():
+        m.close()
     return out
 
 
-def cpu_baseline(m, x_np, seconds):
-    """The oracle (plain FP64 C, OpenMP over rows) on a bounded sample: full
-    rows of the direct product of the same operator on the same mesh."""
+def _bucket_top(k):
+    """Top of the server's wavenumber bucket of k: 2^(ceil(4 log2 k) / 4)."""
+    return float(2.0 ** (np.ceil(4.0 * np.log2(k) - 1e-12) / 4.0))
+
+
+def cpu_baseline(m, x_np, seconds, fmm=True, B=48, theta=0.5):
+    """The oracle (plain FP64 C, OpenMP where it has loops over rows) on the
+    headline sphere: a bounded sample of full rows of the direct product of
+    the same operator, and (fmm) one whole fast product of the oracle on the
+    same tree parameters, timed once."""
+    import platform
+
     import oracle
 
     om = oracle.OracleMesh(m.xyz, m.elem)
@@ -540,9 +667,31 @@ def cpu_baseline(m, x_np, seconds):
         done += chunk
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": done / dt, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} full rows of the direct product A x on the {om.n_dof}-DOF mesh "
-                      f"(plain FP64 oracle, {dt:.1f} s)"}
+    cpu = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {"value": done / dt, "unit": "unknowns/s", "cores": cores, "kind": "oracle", "cpu": cpu,
+           "sample": f"{done} full rows of the direct product A x on the {om.n_dof}-DOF mesh "
+                     f"(plain FP64 oracle, {dt:.1f} s)"}
+    if fmm:
+        print("bench: timing the oracle's fast product (one whole product)", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        T = oracle.OracleTree(om, B=B, theta=theta)
+        t1 = time.perf_counter()
+        T.fmm_matvec(x_np, oracle.OP_A)
+        t2 = time.perf_counter()
+        out["fmm"] = {"value": om.n_dof / (t2 - t1), "unit": "unknowns/s", "seconds": t2 - t1,
+                      "tree_seconds": t1 - t0,
+                      "sample": f"one whole fast product A x of the oracle on the {om.n_dof}-DOF mesh "
+                                f"(B = {B}, theta = {theta}, order 8; plain loops, the free term and the "
+                                "corrections by direct sums; single-threaded far field, near field and "
+                                "corrections over targets on all cores)"}
+    return out
 
 
 if __name__ == "__main__":

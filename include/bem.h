@@ -166,7 +166,7 @@ typedef struct {
     int max_elems_per_leaf; /* B: a box holding more elements is split (Section 3.1); 0 -> 32 */
     int order;              /* Taylor order p of moments and local expansions; 0 -> 8, max 8 */
     double theta;           /* boxes are well separated iff |c1 - c2| > (r1 + r2)/theta (Eq. 14 has
-                               theta = 1); 0 -> 0.6 */
+                               theta = 1); 0 -> 0.5 */
     double kappa;           /* Helmholtz only: also require k (r1 + r2) <= kappa; 0 or inf -> none */
     int max_depth;          /* deepest level, <= 21; 0 -> 21 */
     double k_hint;          /* wavenumber the kappa rule uses when building the lists */
@@ -226,7 +226,11 @@ int bem_tree_stats_get(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k
  * given (g, k) builds and caches the singular / near-singular corrections
  * and the free term on the tree (Section 2.1; Section 3.6, "precomputed and
  * stored as a sparse matrix").
- * Errors: BEM_EINVAL for nrhs < 1, k <= 0 with Helmholtz, NULL buffers. */
+ * Errors: BEM_EINVAL for nrhs < 1, k <= 0 with Helmholtz, NULL buffers, and
+ * for a Helmholtz k that the tree's lists do not cover: a tree built with the
+ * wavenumber bound (kappa > 0) holds its error bound only for k <= k_hint, so
+ * such a tree rejects Helmholtz products with k > k_hint (and every
+ * Helmholtz product when k_hint = 0). */
 int bem_matvec(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, bem_op op, bem_method m,
                bem_precision p, int nrhs, const void *x_dev, void *y_dev);
 
@@ -245,17 +249,24 @@ typedef struct {
                                 (each cycle start and the end) uses the FP64 product */
     double inner_tol;    /* MIXED only: bound on the mixed product's relative deviation
                             from the FP64 product; 0 -> 1e-6 */
-    int max_refine;      /* unused (0) */
+    int max_iters;       /* budget of Krylov steps per right-hand side (GMRES: Arnoldi steps,
+                            BiCGSTAB: steps of two products); a right-hand side that spends it
+                            stops where it is; 0 -> none beyond restart x max_restarts */
     bem_method method;   /* operator used (BEM_FMM unless set) */
     bem_krylov krylov;   /* BEM_KRYLOV_GMRES (0) or BEM_KRYLOV_BICGSTAB */
+    double max_seconds;  /* wall-clock budget of the whole call, checked after every step;
+                            when it runs out every right-hand side stops where it is;
+                            0 -> none */
 } bem_solve_opts;
 
 typedef struct {
     int iterations;      /* total inner Krylov iterations */
-    int refinements;     /* MIXED: cycles restarted from an FP64 residual above tol */
+    int restarts;        /* cycles restarted from an FP64 residual b - A x above tol */
     int matvecs;         /* operator applications, FP64 and mixed */
     double residual;     /* final |b - A x| / |b| with the FP64 operator */
-    int status;          /* BEM_OK or BEM_ENOCONV */
+    int status;          /* BEM_OK, or BEM_ENOCONV: tol not reached within max_restarts cycles,
+                            max_iters steps or max_seconds (phi then holds the last iterate,
+                            residual its FP64 residual) */
 } bem_solve_info;
 
 /* Solves Eq. (1) for phi given chi, for each of nrhs right-hand sides
@@ -265,7 +276,10 @@ typedef struct {
  * solves them one after the other.  chi_dev and phi_dev are
  * device buffers of nrhs * n_dof values; info is a host array of nrhs.
  * Returns BEM_ENOCONV (with phi and info written) if a right-hand side did
- * not converge. */
+ * not converge within its cycle, step or time budget.
+ * Errors: BEM_EINVAL as for bem_matvec, for restart > 90 with GMRES, negative
+ * max_iters or max_seconds, and for a Helmholtz k above the wavenumber the
+ * tree's lists were built for (see bem_matvec). */
 int bem_solve(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, int nrhs,
               const void *chi_dev, void *phi_dev, const bem_solve_opts *opts, bem_solve_info *info);
 
@@ -299,16 +313,26 @@ int bem_field(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, double 
  * counterpart in the paper: a production layer around the solve above).
  * A server runs `lanes` workers, each with its own context (HIP stream of
  * its own, default priority) and host thread.  Meshes are registered once and
- * stay with one lane, which builds their mesh and tree on first use and
- * keeps them while they fit: before building, a lane evicts its least
- * recently used meshes until its resident bytes plus the estimate for the
- * new tree fit its share (hbm_budget / lanes) of the budget (a mesh larger
- * than the share is still served, alone).  Requests queue per lane in
- * arrival order; a worker takes the oldest request and merges the waiting
- * requests with the same (mesh, Green, k) into one solve, up to
- * max_batch_rhs right-hand sides (continuous batching).  Every right-hand
- * side is solved exactly as bem_solve solves it with the same options, so
- * results do not depend on batching, lanes or arrival order.
+ * stay with one lane, which builds their device mesh and trees on first use
+ * and keeps them resident.  A mesh holds one tree per wavenumber bucket: with
+ * the wavenumber bound on (tree.kappa > 0, tree.k_hint = 0) a Helmholtz
+ * request of wavenumber k uses the tree whose lists hold for every k up to
+ * the bucket's top 2^(ceil(4 log2 k) / 4) (buckets 19% wide), Laplace
+ * requests a tree without the bound; otherwise one tree per mesh.
+ * Admission by device-memory budget: every lane's context is bounded by
+ * hbm_budget / lanes bytes (everything it holds: meshes, trees, their
+ * per-wavenumber caches, Krylov bases, staging and freed blocks kept for
+ * reuse), so the server never holds more than hbm_budget.  Before a batch a
+ * lane evicts its least recently used trees until the batch's estimate fits;
+ * an allocation that would still pass the bound makes the lane evict one more
+ * tree and run the batch again; a batch that does not fit even in an empty
+ * lane fails with BEM_ENOMEM.  Requests queue per lane in arrival order; a
+ * worker takes the oldest request and merges the waiting requests with the
+ * same (mesh, Green, k) into one solve, up to max_batch_rhs right-hand sides
+ * (continuous batching).  Every right-hand side is solved exactly as
+ * bem_solve solves it on the same tree with the same options, so results do
+ * not depend on batching, lanes, eviction or arrival order; the solve
+ * options' step and time budgets (max_iters, max_seconds) bound each batch.
  * Host buffers passed to the server are copied at the call; results are
  * copied out by bem_server_poll.  The server calls are thread-safe. */
 typedef struct bem_server bem_server;
@@ -316,19 +340,22 @@ typedef struct bem_server bem_server;
 typedef struct {
     int device;              /* HIP device */
     int lanes;               /* concurrent workers; 0 -> 4 */
-    int64_t hbm_budget;      /* device bytes for resident meshes, trees and solves; 0 -> 32 GiB */
+    int64_t hbm_budget;      /* device bytes the server may hold in total; 0 -> 32 GiB */
     int max_batch_rhs;       /* most right-hand sides merged into one solve; 0 -> 32 */
     bem_tree_opts tree;      /* tree options of every mesh (zero fields -> defaults).  With
-                                kappa > 0 and k_hint = 0, each Helmholtz batch is solved on a
-                                tree of its own k (built for the batch and freed after it);
-                                with k_hint > 0, the mesh's one tree serves every k (its lists
-                                then hold for every k <= k_hint) */
+                                kappa > 0 and k_hint = 0, Helmholtz requests use trees per
+                                wavenumber bucket (above); with k_hint > 0 every mesh has one
+                                tree, whose lists hold for every k <= k_hint, and requests
+                                with a larger k are refused */
     bem_solve_opts solve;    /* solve options of every request (zero fields -> defaults) */
 } bem_server_opts;
 
 typedef struct {
     int64_t submitted, completed, batches, rhs_solved, evictions, trees_built;
-    int64_t resident_bytes;  /* device bytes held by the lanes now */
+    int64_t resident_bytes;  /* device bytes held by the lanes now (live and kept for reuse) */
+    int64_t resident_peak;   /* sum over the lanes of the most each has held at once (>= the
+                                largest resident_bytes; at most hbm_budget) */
+    int64_t rejected;        /* requests that failed with BEM_ENOMEM (larger than a lane's share) */
 } bem_server_stats;
 
 /* Starts the workers.  Errors: BEM_EINVAL for bad options, BEM_EDEVICE. */
@@ -342,15 +369,17 @@ int bem_server_add_mesh(bem_server *s, const double *node_xyz, int64_t n_nodes, 
 int bem_server_mesh_dofs(bem_server *s, int32_t mesh_id, int32_t *elem_dofs, double *dof_xyz, double *dof_normal);
 /* Queues a solve of c.phi - K phi = -S chi for nrhs right-hand sides; chi_host
  * is [nrhs][n_dof] float64 (Laplace) or interleaved complex128 (Helmholtz),
- * copied here.  Returns a ticket.  Errors: BEM_EINVAL (unknown mesh, nrhs < 1,
- * k <= 0 for Helmholtz). */
+ * copied here.  Returns a ticket.  Errors: BEM_EINVAL (unknown mesh, nrhs < 1
+ * or above max_batch_rhs, k <= 0 for Helmholtz, a Helmholtz k above the
+ * server's fixed tree.k_hint when tree.kappa > 0). */
 int bem_server_submit(bem_server *s, int32_t mesh_id, bem_green g, double k, int nrhs, const void *chi_host,
                       int64_t *ticket);
 /* Result of a ticket: with wait != 0 blocks until it completes.  When done,
  * copies phi ([nrhs][n_dof], may be NULL) and info ([nrhs], may be NULL),
  * sets *latency_s (may be NULL) to the time from submission to completion,
  * releases the ticket and returns the solve's status (BEM_OK or
- * BEM_ENOCONV, or the error that stopped it).  Returns BEM_EAGAIN if not
+ * BEM_ENOCONV, or the error that stopped it, e.g. BEM_ENOMEM for a request
+ * larger than a lane's share of the budget).  Returns BEM_EAGAIN if not
  * done and wait == 0, BEM_EINVAL for an unknown ticket. */
 int bem_server_poll(bem_server *s, int64_t ticket, int wait, void *phi_host, bem_solve_info *info,
                     double *latency_s);

@@ -30,7 +30,8 @@ BEM_KRYLOV_GMRES, BEM_KRYLOV_BICGSTAB = 0, 1
 
 EXPORTED = [
     "bem_ctx_create", "bem_ctx_destroy", "bem_ctx_timing", "bem_ctx_device_bytes", "bem_last_error", "bem_mesh_load", "bem_mesh_dofs", "bem_mesh_free",
-    "bem_tree_build", "bem_tree_export", "bem_tree_free", "bem_tree_stats_get", "bem_matvec", "bem_solve", "bem_field",
+    "bem_tree_build", "bem_tree_export", "bem_tree_free", "bem_tree_stats_get", "bem_matvec", "bem_solve",
+    "bem_field",
     "bem_server_create", "bem_server_add_mesh", "bem_server_mesh_dofs", "bem_server_submit", "bem_server_poll",
     "bem_server_stats_get",
     "bem_server_destroy",
@@ -77,8 +78,8 @@ class _TreeStats(ctypes.Structure):
 
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_restarts", ctypes.c_int),
-                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
-                ("method", ctypes.c_int), ("krylov", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_iters", ctypes.c_int),
+                ("method", ctypes.c_int), ("krylov", ctypes.c_int), ("max_seconds", ctypes.c_double)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -88,11 +89,11 @@ class _ServerOpts(ctypes.Structure):
 
 class _ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "batches", "rhs_solved", "evictions",
-                                              "trees_built", "resident_bytes")]
+                                              "trees_built", "resident_bytes", "resident_peak", "rejected")]
 
 
 class _SolveInfo(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int), ("refinements", ctypes.c_int), ("matvecs", ctypes.c_int),
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("matvecs", ctypes.c_int),
                 ("residual", ctypes.c_double), ("status", ctypes.c_int)]
 
 
@@ -281,7 +282,7 @@ class Mesh:
 
 
 class Tree:
-    def __init__(self, ctx: Context, mesh: Mesh, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21, k_hint=0.0,
+    def __init__(self, ctx: Context, mesh: Mesh, B=32, order=8, theta=0.5, kappa=0.0, max_depth=21, k_hint=0.0,
                  order_min=0, attach_radii=False):
         self.ctx, self.mesh = ctx, mesh
         opts = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min, int(attach_radii))
@@ -360,13 +361,16 @@ def bem_matvec(ctx: Context, tree: Tree, green: int, k: float, op: int, method: 
 
 
 def bem_solve(ctx: Context, tree: Tree, green: int, k: float, chi, phi, tol=1e-8, restart=50, max_restarts=100,
-              precision=BEM_PREC_FP64, inner_tol=0.0, max_refine=0, method=BEM_FMM, raise_on_noconv=False,
-              krylov=BEM_KRYLOV_GMRES):
-    """Solves c.phi - K phi = -S chi; returns a list of per-rhs info dicts."""
+              precision=BEM_PREC_FP64, inner_tol=0.0, max_iters=0, method=BEM_FMM, raise_on_noconv=False,
+              krylov=BEM_KRYLOV_GMRES, max_seconds=0.0):
+    """Solves c.phi - K phi = -S chi; returns a list of per-rhs info dicts.
+    max_iters / max_seconds: step budget per right-hand side and wall-time
+    budget of the call (0: none); a right-hand side that runs out reports
+    BEM_ENOCONV with its last iterate."""
     nrhs = _check_vec(chi, tree.n_dof, green)
     if _check_vec(phi, tree.n_dof, green) != nrhs:
         raise ValueError("chi and phi differ in shape")
-    opts = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method, krylov)
+    opts = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_iters, method, krylov, max_seconds)
     info = (_SolveInfo * nrhs)()
     rc = ctx.L.bem_solve(ctx.h, tree.h, green, float(k), nrhs, ctypes.c_void_p(chi.data_ptr()),
                          ctypes.c_void_p(phi.data_ptr()), ctypes.byref(opts), info)
@@ -405,9 +409,9 @@ class Server:
     request is pending and wait is False."""
 
     def __init__(self, device=0, lanes=4, hbm_budget=32 << 30, max_batch_rhs=32, tol=1e-8, restart=50,
-                 max_restarts=100, precision=BEM_PREC_FP64, inner_tol=0.0, max_refine=0, method=BEM_FMM,
-                 krylov=BEM_KRYLOV_GMRES, B=32, order=8, theta=0.6, kappa=0.0, max_depth=21, order_min=0,
-                 k_hint=0.0, attach_radii=0):
+                 max_restarts=100, precision=BEM_PREC_FP64, inner_tol=0.0, max_iters=0, method=BEM_FMM,
+                 krylov=BEM_KRYLOV_GMRES, B=32, order=8, theta=0.5, kappa=0.0, max_depth=21, order_min=0,
+                 k_hint=0.0, attach_radii=0, max_seconds=0.0):
         self.L = load_library()
         import torch
 
@@ -418,7 +422,7 @@ class Server:
         # kappa > 0 with k_hint = 0: every Helmholtz batch gets a tree of its own k;
         # with k_hint > 0 the mesh's one tree serves every k up to k_hint
         o.tree = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min, int(attach_radii))
-        o.solve = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_refine, method, krylov)
+        o.solve = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_iters, method, krylov, max_seconds)
         h = ctypes.c_void_p()
         rc = self.L.bem_server_create(ctypes.byref(o), ctypes.byref(h))
         if rc != 0:

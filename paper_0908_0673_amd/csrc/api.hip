@@ -34,6 +34,19 @@ int guard(Ctx *c, F &&f) {
 
 thread_local std::string g_err;
 
+// A tree built with the wavenumber bound k (r1 + r2) <= kappa on its lists
+// (Section 3.6's separation test with the Helmholtz bound) keeps the
+// truncation error of the Taylor expansions in check only for the k it was
+// built for (k_hint) and smaller ones.
+void check_wavenumber(const bem_tree &t, int g, double k) {
+    if (g != BEM_HELMHOLTZ || !(t.kappa > 0.0) || !std::isfinite(t.kappa)) return;
+    BEM_REQUIRE(t.k_hint > 0.0, BEM_EINVAL,
+                "this tree has the wavenumber bound (kappa > 0) but no k_hint: its lists hold no bound for "
+                "any Helmholtz k; build it with k_hint >= k");
+    BEM_REQUIRE(k <= t.k_hint, BEM_EINVAL,
+                "Helmholtz k above the k_hint this tree's lists were built for (kappa bound)");
+}
+
 }  // namespace
 
 extern "C" {
@@ -275,6 +288,7 @@ int bem_matvec(bem_ctx *ctx, const bem_tree *tc, bem_green g, double k, bem_op o
         BEM_REQUIRE(op >= BEM_OP_S && op <= BEM_OP_RHS, BEM_EINVAL, "unknown operator");
         BEM_REQUIRE(m == BEM_DIRECT || m == BEM_FMM, BEM_EINVAL, "unknown method");
         BEM_REQUIRE(p == BEM_PREC_FP64 || p == BEM_PREC_MIXED, BEM_EINVAL, "unknown precision");
+        check_wavenumber(*t, g, k);
         bem::matvec(*t, g, g == BEM_HELMHOLTZ ? k : 0.0, op, m, p, nrhs, x_dev, y_dev);
     });
 }
@@ -301,6 +315,8 @@ int bem_solve(bem_ctx *ctx, const bem_tree *tc, bem_green g, double k, int nrhs,
                     "unknown Krylov method");
         BEM_REQUIRE(o.krylov != BEM_KRYLOV_GMRES || o.restart <= 90, BEM_EINVAL, "GMRES restart must be <= 90");
         BEM_REQUIRE(o.method == BEM_FMM || o.method == BEM_DIRECT, BEM_EINVAL, "unknown method");
+        BEM_REQUIRE(o.max_iters >= 0 && o.max_seconds >= 0.0, BEM_EINVAL, "max_iters and max_seconds must be >= 0");
+        check_wavenumber(*t, g, k);
         status = bem::solve(*t, g, g == BEM_HELMHOLTZ ? k : 0.0, nrhs, chi_dev, phi_dev, o, info);
     });
     if (rc != BEM_OK) return rc;
@@ -321,6 +337,7 @@ int bem_field(bem_ctx *ctx, const bem_tree *tc, bem_green g, double k, double th
         BEM_REQUIRE(g == BEM_LAPLACE || g == BEM_HELMHOLTZ, BEM_EINVAL, "unknown Green's function");
         BEM_REQUIRE(g != BEM_HELMHOLTZ || (k > 0.0 && std::isfinite(k)), BEM_EINVAL, "Helmholtz needs k > 0");
         BEM_REQUIRE(!(theta > 1.0) && !std::isnan(theta), BEM_EINVAL, "theta must be at most 1");
+        check_wavenumber(*t, g, k);
         bem::field(*t, g, g == BEM_HELMHOLTZ ? k : 0.0, theta, nrhs, phi_dev, chi_dev, n_pts, pts_dev, u_dev);
     });
 }

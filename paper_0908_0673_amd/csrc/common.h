@@ -167,6 +167,12 @@ struct Ctx {
     std::atomic<size_t> bytes_peak{0};  // largest bytes_live since creation or the last reset
     std::atomic<size_t> cached{0};
     size_t cache_limit = (size_t)1 << 30;
+    // Hard bound on the device bytes this context holds (live plus cached;
+    // 0: none): an allocation that would pass it first returns the cached
+    // blocks, then fails with BEM_ENOMEM (a serving lane's share of the
+    // budget).
+    size_t limit = 0;
+    std::atomic<size_t> held_peak{0};  // largest bytes_live + cached so far
     std::unordered_map<void *, size_t> sizes;
     std::multimap<size_t, void *> cache;
     static size_t size_class(size_t bytes) {
@@ -178,6 +184,16 @@ struct Ctx {
     void *dmalloc(size_t bytes) {
         if (bytes == 0) bytes = 256;
         void *p = nullptr;
+        if (limit) {
+            // handing out a cached block of the size class leaves live + cached as it is
+            const size_t want = has_alloc ? bytes : size_class(bytes);
+            if (has_alloc || cache.find(want) == cache.end()) {
+                if (bytes_live + cached + want > limit) trim_cache();
+                if (bytes_live + cached + want > limit)
+                    fail(BEM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes would pass the " +
+                                         std::to_string(limit) + "-byte bound of this context");
+            }
+        }
         if (has_alloc) {
             p = alloc.alloc(alloc.user, bytes, (void *)stream);
             if (!p) fail(BEM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
@@ -202,6 +218,7 @@ struct Ctx {
         sizes[p] = bytes;
         const size_t live = bytes_live += bytes;
         if (live > bytes_peak) bytes_peak = live;
+        if (live + cached > held_peak) held_peak = live + cached;
         return p;
     }
     void dfree(void *p) {

@@ -32,8 +32,30 @@ namespace bem {
 struct Corr {
     int green = -1;
     double k = 0.0;
+    uint64_t last_use = 0;  // tree's use counter at the last lookup (least recently used goes first)
     DBuf<double> S, K;  // [n_pairs][6] (x2 interleaved when complex): accurate - 7-point
 };
+
+// Helmholtz wavenumbers whose corrections and M2L plans a tree keeps at once;
+// looking up another one drops the least recently used (Laplace ones stay).
+constexpr int MAX_K_CACHED = 3;
+
+// Drops the least recently used Helmholtz entry of `v` (entries with fields
+// green and last_use) while it holds MAX_K_CACHED or more of them.
+template <class T>
+void evict_wavenumbers(std::vector<std::unique_ptr<T>> &v) {
+    for (;;) {
+        int n = 0;
+        size_t lru = v.size();
+        for (size_t i = 0; i < v.size(); i++) {
+            if (v[i]->green != BEM_HELMHOLTZ) continue;
+            n++;
+            if (lru == v.size() || v[i]->last_use < v[lru]->last_use) lru = i;
+        }
+        if (n < MAX_K_CACHED) return;
+        v.erase(v.begin() + (std::ptrdiff_t)lru);
+    }
+}
 
 // Expansion operator tables for one order p.
 struct FmmTables {
@@ -69,6 +91,7 @@ struct M2lTasks {
 struct M2lPlan {
     int green = -1;
     double k = 0.0;
+    uint64_t last_use = 0;
     int64_t n_class = 0, n_pairs = 0;
     DBuf<double> D64;                 // [n_class][P2] (x2 interleaved when complex), canonical separations
     DBuf<int32_t> cls_delta;          // level difference of the class
@@ -126,7 +149,7 @@ struct bem_tree {
     int order_min = 0;  // level-dependent order when > 0 (see level_p)
     bool attach = false;  // leaf radii over the elements attached to the leaf's target nodes
     bool literal = false; // the paper's tree read literally: DOF sources, B counting DOFs (attach too)
-    double theta = 0.6, kappa = 0.0, k_hint = 0.0;
+    double theta = 0.5, kappa = 0.0, k_hint = 0.0;
     int64_t n_box = 0, n_leaf = 0, n_near = 0, n_inter = 0, n_el = 0, n_tgt = 0, n_q = 0;
     int max_level = 0;
     double corner[3] = {0, 0, 0}, side = 0;
@@ -195,6 +218,7 @@ struct bem_tree {
 
     std::vector<std::unique_ptr<bem::Corr>> corr;
     std::vector<std::unique_ptr<bem::M2lPlan>> m2l;
+    uint64_t k_uses = 0;  // lookups of corr / m2l (orders their least recent use)
     std::vector<uint64_t> h_prefix;
     bem::DBuf<double> free_term;  // [n_dof], DOF order
     bool has_free_term = false;

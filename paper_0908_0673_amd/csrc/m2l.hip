@@ -424,8 +424,12 @@ void symmetry_tables(const std::vector<int8_t> &ex, int P, std::vector<int32_t> 
 M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     if (green == BEM_LAPLACE) k = 0.0;
     for (auto &p : t.m2l)
-        if (p->green == green && p->k == k) return *p;
+        if (p->green == green && p->k == k) {
+            p->last_use = ++t.k_uses;
+            return *p;
+        }
     Ctx &c = *t.ctx;
+    if (green == BEM_HELMHOLTZ) evict_wavenumbers(t.m2l);
     fmm_tables(t);
     plan_fmm(t);
     FmmTables &T = *t.tables;
@@ -435,6 +439,7 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     auto pl = std::make_unique<M2lPlan>();
     pl->green = green;
     pl->k = k;
+    pl->last_use = ++t.k_uses;
     if (t.h_prefix.empty()) t.h_prefix = t.prefix.download(t.n_box);
     // canonical classes of the interaction pairs of boxes with targets
     std::unordered_map<ClassKey, int32_t, ClassKeyHash> id;

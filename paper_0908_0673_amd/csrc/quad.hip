@@ -344,12 +344,17 @@ void build_pairs(bem_tree &t) {
 Corr &get_corr(bem_tree &t, int green, double k) {
     if (green == BEM_LAPLACE) k = 0.0;
     for (auto &p : t.corr)
-        if (p->green == green && p->k == k) return *p;
+        if (p->green == green && p->k == k) {
+            p->last_use = ++t.k_uses;
+            return *p;
+        }
     build_pairs(t);
     Ctx &c = *t.ctx;
+    if (green == BEM_HELMHOLTZ) evict_wavenumbers(t.corr);
     auto cr = std::make_unique<Corr>();
     cr->green = green;
     cr->k = k;
+    cr->last_use = ++t.k_uses;
     const int cw = green == BEM_HELMHOLTZ ? 2 : 1;
     cr->S.alloc(&c, (size_t)6 * cw * t.n_pairs);
     cr->K.alloc(&c, (size_t)6 * cw * t.n_pairs);

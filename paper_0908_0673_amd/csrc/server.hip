@@ -1,11 +1,13 @@
 // Serving layer: concurrent and batched solves of many independent problems
 // on one GPU (declared in include/bem.h).  Host code only: worker threads,
-// per-lane contexts (each with its own stream), a mesh registry with lane
-// affinity and least-recently-used eviction under a device-memory budget,
-// and per-lane request queues from which a worker merges the waiting
-// requests of one (mesh, Green, k) into a single multi-right-hand-side solve.
-// Every right-hand side goes through bem_solve with the server's options, so
-// its result is the one bem_solve gives for it alone.
+// per-lane contexts (each with its own stream and a hard bound on the device
+// bytes it holds), a mesh registry with lane affinity, trees per
+// (mesh, wavenumber bucket) kept resident under least-recently-used
+// eviction, and per-lane request queues from which a worker merges the
+// waiting requests of one (mesh, Green, k) into a single
+// multi-right-hand-side solve.  Every right-hand side goes through bem_solve
+// with the server's options on the tree its request maps to, so its result
+// is the one bem_solve gives for it alone on such a tree.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -36,6 +38,14 @@ struct Request {
     clk::time_point t_submit, t_done;
 };
 
+// A resident tree of a mesh, for the wavenumbers up to k_hint (0: the tree
+// without the wavenumber bound on its lists).
+struct TreeEntry {
+    double k_hint = 0.0;
+    bem_tree *tree = nullptr;
+    uint64_t last_use = 0;
+};
+
 struct MeshEntry {
     std::vector<double> xyz;
     std::vector<int32_t> elem;
@@ -45,18 +55,13 @@ struct MeshEntry {
     int64_t n_nodes = 0, n_elem = 0, n_dof = 0;
     int lane = 0;
     bem_mesh *mesh = nullptr;  // resident objects, owned by the lane's context
-    bem_tree *tree = nullptr;
-    size_t bytes = 0;          // device bytes of mesh + tree + caches when last measured
-    uint64_t last_use = 0;
+    std::vector<TreeEntry> trees;
 };
 
 struct Lane {
     bem_ctx *ctx = nullptr;
     std::thread th;
     std::deque<Request *> q;
-    size_t pending_rhs = 0;
-    void *dchi = nullptr, *dphi = nullptr;  // device staging of the right-hand sides
-    size_t dbytes = 0;
 };
 
 }  // namespace
@@ -71,7 +76,7 @@ struct bem_server {
     bool stop = false;
     int64_t next_ticket = 1;
     uint64_t use_clock = 0;
-    double bytes_per_elem = 4.0e4;  // running estimate of a resident mesh's device bytes per element
+    double bytes_per_elem = 4.0e4;  // running estimate of a resident tree's device bytes per element
     bem_server_stats st{};
 };
 
@@ -79,37 +84,122 @@ namespace {
 
 size_t value_bytes(int green) { return green == BEM_HELMHOLTZ ? 16 : 8; }
 
-// Evicts the lane's least recently used idle meshes until `need` more bytes
-// fit its share of the budget.  Called by the lane's worker (the only user of
-// its context) with the server lock held.
-void make_room(bem_server *s, int lane, size_t need, int32_t keep) {
-    Lane &L = *s->lanes[lane];
-    const size_t share = (size_t)(s->o.hbm_budget / s->o.lanes);
-    if (L.ctx->c.bytes_live + L.ctx->c.cached + need > share) L.ctx->c.trim_cache();
-    while (L.ctx->c.bytes_live + need > share) {
-        MeshEntry *victim = nullptr;
-        int32_t vid = -1;
-        for (size_t i = 0; i < s->meshes.size(); i++) {
-            MeshEntry *m = s->meshes[i].get();
-            if (m->lane != lane || !m->mesh || (int32_t)i == keep) continue;
-            if (!victim || m->last_use < victim->last_use) {
-                victim = m;
-                vid = (int32_t)i;
+// Top of the wavenumber bucket of k: 2^(ceil(4 log2 k) / 4), so that the
+// wavenumbers of one bucket differ by at most 19% and share a tree whose
+// lists carry the bound k (r1 + r2) <= kappa for the bucket's top.
+double bucket_top(double k) { return std::exp2(std::ceil(4.0 * std::log2(k) - 1e-12) / 4.0); }
+
+// k_hint of the tree a request of (green, k) is solved on.
+double tree_key(const bem_server *s, int green, double k) {
+    const bem_tree_opts &to = s->o.tree;
+    if (!(to.kappa > 0.0) || !std::isfinite(to.kappa)) return 0.0;  // no wavenumber bound: one tree
+    if (to.k_hint > 0.0) return to.k_hint;                          // fixed: one tree for k <= k_hint
+    return green == BEM_HELMHOLTZ ? bucket_top(k) : 0.0;
+}
+
+// Bytes a solve of nrhs right-hand sides needs beyond its resident tree
+// (whose per-product work buffers stay with it): Krylov bases and vectors,
+// right-hand-side and staging buffers, the strengths and expansions of nrhs
+// at once (a coarse upper estimate; the lane's bound is the hard limit).
+size_t solve_bytes(const bem_server *s, int green, int64_t n_dof, int64_t n_elem, int nrhs) {
+    const int m = s->o.solve.restart > 0 ? s->o.solve.restart : 50;
+    const size_t vb = value_bytes(green);
+    return (size_t)nrhs * (size_t)n_dof * vb * (size_t)(m + 12) + (size_t)nrhs * (size_t)n_elem * 7 * vb * 3 +
+           ((size_t)4 << 20);
+}
+
+// Detaches the lane's least recently used tree other than (keep_mesh,
+// keep_key) under the server lock; the caller frees it outside the lock (the
+// lane's own thread: the only user of its context).  A mesh whose last tree
+// goes is detached with it.  Returns false when nothing is left to evict.
+bool detach_lru(bem_server *s, int lane, int32_t keep_mesh, double keep_key, bem_tree **tree, bem_mesh **mesh) {
+    *tree = nullptr;
+    *mesh = nullptr;
+    MeshEntry *vm = nullptr;
+    size_t vt = 0;
+    for (size_t i = 0; i < s->meshes.size(); i++) {
+        MeshEntry *m = s->meshes[i].get();
+        if (m->lane != lane) continue;
+        for (size_t j = 0; j < m->trees.size(); j++) {
+            if ((int32_t)i == keep_mesh && m->trees[j].k_hint == keep_key) continue;
+            if (!vm || m->trees[j].last_use < vm->trees[vt].last_use) {
+                vm = m;
+                vt = j;
             }
         }
-        if (!victim) break;  // nothing left to evict: a mesh larger than the share is served alone
-        (void)vid;
-        bem_tree_free(victim->tree);
-        bem_mesh_free(victim->mesh);
-        victim->tree = nullptr;
-        victim->mesh = nullptr;
-        s->st.evictions++;
     }
+    if (!vm) {  // meshes left without trees (other than the one in use)
+        for (size_t i = 0; i < s->meshes.size(); i++) {
+            MeshEntry *m = s->meshes[i].get();
+            if (m->lane == lane && m->mesh && m->trees.empty() && (int32_t)i != keep_mesh) {
+                *mesh = m->mesh;
+                m->mesh = nullptr;
+                s->st.evictions++;
+                return true;
+            }
+        }
+        return false;
+    }
+    *tree = vm->trees[vt].tree;
+    vm->trees.erase(vm->trees.begin() + (std::ptrdiff_t)vt);
+    if (vm->trees.empty() && vm != s->meshes[keep_mesh].get()) {
+        *mesh = vm->mesh;
+        vm->mesh = nullptr;
+    }
+    s->st.evictions++;
+    return true;
+}
+
+// One batch on the lane's context: the mesh and tree built if missing, the
+// right-hand sides staged through buffers of the context, the solve, the
+// results copied back.  Throws nothing; returns a bem_status.
+int run_batch(bem_server *s, Lane &L, MeshEntry &me, TreeEntry &te, double key, int green, double k, int nrhs,
+              const std::vector<char> &chi, std::vector<char> &phi, std::vector<bem_solve_info> &info) {
+    bem_ctx *ctx = L.ctx;
+    bem::Ctx &c = ctx->c;
+    int rc = BEM_OK;
+    if (!me.mesh) rc = bem_mesh_load(ctx, me.xyz.data(), me.n_nodes, me.elem.data(), me.n_elem, &me.mopts, &me.mesh);
+    if (rc != BEM_OK) return rc;
+    const bool fresh = !te.tree;
+    const size_t before = c.bytes_live;
+    if (fresh) {
+        bem_tree_opts to = s->o.tree;
+        to.k_hint = key;
+        rc = bem_tree_build(ctx, me.mesh, &to, &te.tree);
+        if (rc != BEM_OK) return rc;
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->st.trees_built++;
+    }
+    const size_t vb = value_bytes(green), bytes = (size_t)nrhs * (size_t)me.n_dof * vb;
+    try {
+        bem::DBuf<char> dchi, dphi;
+        dchi.alloc(&c, bytes);
+        dphi.alloc(&c, bytes);
+        BEM_HIP(hipMemcpyAsync(dchi.p, chi.data(), bytes, hipMemcpyHostToDevice, c.stream));
+        rc = bem_solve(ctx, te.tree, (bem_green)green, k, nrhs, dchi.p, dphi.p, &s->o.solve, info.data());
+        if (rc == BEM_OK || rc == BEM_ENOCONV) {
+            BEM_HIP(hipMemcpyAsync(phi.data(), dphi.p, bytes, hipMemcpyDeviceToHost, c.stream));
+            BEM_HIP(hipStreamSynchronize(c.stream));
+        }
+    } catch (const bem::Error &e) {
+        return e.code;
+    } catch (...) {
+        return BEM_ENOMEM;
+    }
+    if (fresh && (rc == BEM_OK || rc == BEM_ENOCONV)) {
+        // a resident tree's bytes per element (tree, corrections, plans,
+        // operators; the solve's own buffers are freed by now)
+        std::lock_guard<std::mutex> lk(s->mu);
+        const double per = (double)(c.bytes_live > before ? c.bytes_live - before : 0) / (double)me.n_elem;
+        s->bytes_per_elem = std::max(s->bytes_per_elem * 0.9, per);
+    }
+    return rc;
 }
 
 void worker(bem_server *s, int lane) {
     Lane &L = *s->lanes[lane];
     (void)hipSetDevice(s->o.device);
+    const size_t limit = L.ctx->c.limit;
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         s->cv_work.wait(lk, [&] { return s->stop || !L.q.empty(); });
@@ -132,17 +222,21 @@ void worker(bem_server *s, int lane) {
                 ++it;
             }
         }
-        L.pending_rhs -= nrhs;
-        MeshEntry &me = *s->meshes[batch[0]->mesh];
-        me.last_use = ++s->use_clock;
+        const int32_t mid = batch[0]->mesh;
+        MeshEntry &me = *s->meshes[mid];
         const int green = batch[0]->green;
         const double k = batch[0]->k;
+        const double key = tree_key(s, green, k);
+        // the batch's tree entry (looked up again after every eviction: erasing
+        // another entry of this mesh moves it)
+        auto entry = [&]() -> TreeEntry * {
+            for (auto &t : me.trees)
+                if (t.k_hint == key) return &t;
+            me.trees.push_back(TreeEntry{key, nullptr, 0});
+            return &me.trees.back();
+        };
+        entry()->last_use = ++s->use_clock;
         const size_t vb = value_bytes(green), n = (size_t)me.n_dof;
-        int rc = BEM_OK;
-        if (!me.mesh) {
-            make_room(s, lane, (size_t)(s->bytes_per_elem * me.n_elem), batch[0]->mesh);
-            s->st.trees_built++;
-        }
         std::vector<char> chi(nrhs * n * vb), phi(nrhs * n * vb);
         size_t off = 0;
         for (Request *r : batch) {
@@ -150,62 +244,55 @@ void worker(bem_server *s, int lane) {
             off += r->chi.size();
         }
         std::vector<bem_solve_info> info(nrhs);
-        lk.unlock();
-        // device work of this lane, outside the lock
-        bem_ctx *ctx = L.ctx;
-        if (!me.mesh) {
-            const size_t before = ctx->c.bytes_live;
-            rc = bem_mesh_load(ctx, me.xyz.data(), me.n_nodes, me.elem.data(), me.n_elem, &me.mopts, &me.mesh);
-            if (rc == BEM_OK) rc = bem_tree_build(ctx, me.mesh, &s->o.tree, &me.tree);
-            if (rc == BEM_OK) {
-                me.bytes = ctx->c.bytes_live - before;
-            } else {
-                // leave the mesh unbuilt; a later request retries
-                if (me.tree) bem_tree_free(me.tree);
-                if (me.mesh) bem_mesh_free(me.mesh);
-                me.tree = nullptr;
-                me.mesh = nullptr;
+        // admission: make room for the batch's estimate by evicting the
+        // lane's least recently used trees (the bound itself is enforced by
+        // the context's allocator)
+        const size_t need = (entry()->tree ? 0 : (size_t)(s->bytes_per_elem * me.n_elem)) +
+                            solve_bytes(s, green, me.n_dof, me.n_elem, nrhs);
+        int rc = BEM_OK;
+        for (;;) {
+            std::vector<std::pair<bem_tree *, bem_mesh *>> gone;
+            while (L.ctx->c.bytes_live + L.ctx->c.cached + need > limit) {
+                bem_tree *t = nullptr;
+                bem_mesh *m = nullptr;
+                if (!detach_lru(s, lane, mid, key, &t, &m)) break;
+                gone.emplace_back(t, m);
             }
-        }
-        const size_t need = 2 * nrhs * n * vb;
-        if (rc == BEM_OK && L.dbytes < need) {
-            if (L.dchi) (void)hipFree(L.dchi);
-            if (L.dphi) (void)hipFree(L.dphi);
-            L.dchi = L.dphi = nullptr;
-            L.dbytes = 0;
-            if (hipMalloc(&L.dchi, need / 2) != hipSuccess || hipMalloc(&L.dphi, need / 2) != hipSuccess)
-                rc = BEM_ENOMEM;
-            else
-                L.dbytes = need;
-        }
-        hipStream_t st = ctx->c.stream;
-        if (rc == BEM_OK && (hipMemcpyAsync(L.dchi, chi.data(), nrhs * n * vb, hipMemcpyHostToDevice, st) != hipSuccess ||
-                             hipStreamSynchronize(st) != hipSuccess))
-            rc = BEM_EDEVICE;
-        // Helmholtz with the wavenumber bound on the lists (tree.kappa > 0) and
-        // no fixed k_hint: the batch gets a tree of its own k, freed after it
-        bem_tree *own = nullptr;
-        if (rc == BEM_OK && green == BEM_HELMHOLTZ && s->o.tree.kappa > 0.0 && s->o.tree.k_hint == 0.0) {
-            bem_tree_opts to = s->o.tree;
-            to.k_hint = k;
-            rc = bem_tree_build(ctx, me.mesh, &to, &own);
-        }
-        if (rc == BEM_OK) {
-            const size_t before = ctx->c.bytes_live;
-            rc = bem_solve(ctx, own ? own : me.tree, (bem_green)green, k, nrhs, L.dchi, L.dphi, &s->o.solve,
-                           info.data());
-            // the first solve of a (Green, k) caches its corrections on the tree
-            if (!own) me.bytes += ctx->c.bytes_live > before ? ctx->c.bytes_live - before : 0;
-            if (rc == BEM_OK || rc == BEM_ENOCONV) {
-                if (hipMemcpyAsync(phi.data(), L.dphi, nrhs * n * vb, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                    hipStreamSynchronize(st) != hipSuccess)
-                    rc = BEM_EDEVICE;
+            lk.unlock();
+            for (auto &g : gone) {  // device frees outside the lock
+                if (g.first) bem_tree_free(g.first);
+                if (g.second) bem_mesh_free(g.second);
             }
+            if (L.ctx->c.bytes_live + L.ctx->c.cached + need > limit) L.ctx->c.trim_cache();
+            lk.lock();
+            TreeEntry *te = entry();
+            lk.unlock();
+            rc = run_batch(s, L, me, *te, key, green, k, nrhs, chi, phi, info);
+            lk.lock();
+            if (rc != BEM_ENOMEM) break;
+            // past the lane's bound: one more tree goes and the batch runs again
+            bem_tree *t = nullptr;
+            bem_mesh *m = nullptr;
+            if (!detach_lru(s, lane, mid, key, &t, &m)) break;  // nothing left: the batch does not fit
+            lk.unlock();
+            if (t) bem_tree_free(t);
+            if (m) bem_mesh_free(m);
+            L.ctx->c.trim_cache();
+            lk.lock();
         }
-        if (own) bem_tree_free(own);
-        lk.lock();
-        if (me.bytes && me.n_elem)
-            s->bytes_per_elem = std::max(s->bytes_per_elem * 0.5, (double)me.bytes / (double)me.n_elem);
+        if (rc == BEM_ENOMEM) {  // keep nothing of a batch that does not fit
+            for (size_t j = 0; j < me.trees.size(); j++)
+                if (me.trees[j].k_hint == key) {
+                    bem_tree *t = me.trees[j].tree;
+                    me.trees.erase(me.trees.begin() + (std::ptrdiff_t)j);
+                    lk.unlock();
+                    if (t) bem_tree_free(t);
+                    L.ctx->c.trim_cache();
+                    lk.lock();
+                    break;
+                }
+            s->st.rejected += (int64_t)batch.size();
+        }
         const auto now = clk::now();
         off = 0;
         int ri = 0;
@@ -251,6 +338,7 @@ int bem_server_create(const bem_server_opts *opts, bem_server **out) {
     if (o.hbm_budget == 0) o.hbm_budget = (int64_t)32 << 30;
     if (o.max_batch_rhs == 0) o.max_batch_rhs = 32;
     if (o.lanes < 1 || o.lanes > 64 || o.hbm_budget < 0 || o.max_batch_rhs < 1) return BEM_EINVAL;
+    if (o.solve.max_iters < 0 || o.solve.max_seconds < 0.0) return BEM_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) return BEM_EDEVICE;
     if (hipSetDevice(o.device) != hipSuccess) return BEM_EDEVICE;
@@ -273,6 +361,8 @@ int bem_server_create(const bem_server_opts *opts, bem_server **out) {
             (void)hipStreamDestroy(st);
             return unwind(rc);
         }
+        L->ctx->c.limit = (size_t)(o.hbm_budget / o.lanes);  // the lane's share: a hard bound
+        L->ctx->c.cache_limit = std::min(L->ctx->c.cache_limit, L->ctx->c.limit / 4);
         s->lanes.push_back(std::move(L));
     }
     bem_server *raw = s.release();
@@ -334,6 +424,9 @@ int bem_server_submit(bem_server *s, int32_t mesh_id, bem_green g, double k, int
     if (!s || !chi_host || !ticket || nrhs < 1) return BEM_EINVAL;
     if (g != BEM_LAPLACE && g != BEM_HELMHOLTZ) return BEM_EINVAL;
     if (g == BEM_HELMHOLTZ && !(k > 0.0 && std::isfinite(k))) return BEM_EINVAL;
+    const bem_tree_opts &to = s->o.tree;
+    if (g == BEM_HELMHOLTZ && to.kappa > 0.0 && std::isfinite(to.kappa) && to.k_hint > 0.0 && k > to.k_hint)
+        return BEM_EINVAL;  // the fixed tree's lists hold the bound only up to k_hint
     std::lock_guard<std::mutex> lk(s->mu);
     if (mesh_id < 0 || mesh_id >= (int32_t)s->meshes.size()) return BEM_EINVAL;
     MeshEntry &me = *s->meshes[mesh_id];
@@ -349,7 +442,6 @@ int bem_server_submit(bem_server *s, int32_t mesh_id, bem_green g, double k, int
     r->t_submit = clk::now();
     Lane &L = *s->lanes[me.lane];
     L.q.push_back(r.get());
-    L.pending_rhs += nrhs;
     *ticket = r->ticket;
     s->reqs[r->ticket] = std::move(r);
     s->st.submitted++;
@@ -381,9 +473,13 @@ int bem_server_stats_get(bem_server *s, bem_server_stats *st) {
     if (!s || !st) return BEM_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
     *st = s->st;
-    int64_t b = 0;
-    for (auto &l : s->lanes) b += (int64_t)(l->ctx->c.bytes_live + l->ctx->c.cached) + (int64_t)l->dbytes;
+    int64_t b = 0, peak = 0;
+    for (auto &l : s->lanes) {
+        b += (int64_t)(l->ctx->c.bytes_live + l->ctx->c.cached);
+        peak += (int64_t)l->ctx->c.held_peak;
+    }
     st->resident_bytes = b;
+    st->resident_peak = peak;
     return BEM_OK;
 }
 
@@ -406,12 +502,11 @@ void bem_server_destroy(bem_server *s) {
         if (l->th.joinable()) l->th.join();
     (void)hipSetDevice(s->o.device);
     for (auto &m : s->meshes) {
-        if (m->tree) bem_tree_free(m->tree);
+        for (auto &t : m->trees)
+            if (t.tree) bem_tree_free(t.tree);
         if (m->mesh) bem_mesh_free(m->mesh);
     }
     for (auto &l : s->lanes) {
-        if (l->dchi) (void)hipFree(l->dchi);
-        if (l->dphi) (void)hipFree(l->dphi);
         hipStream_t st = l->ctx->c.stream;
         bem_ctx_destroy(l->ctx);
         (void)hipStreamDestroy(st);

@@ -15,6 +15,8 @@
 //          product once the residual is small enough for its error not to
 //          matter (relaxed inexact Krylov); the residual that decides
 //          convergence is always formed with the FP64 product.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <memory>
 
@@ -25,6 +27,20 @@ namespace bem {
 namespace {
 
 constexpr int RBS = 256;
+
+// Budget of a solve: Krylov steps per right-hand side (0: none) and the wall
+// time of the whole call (0: none), checked on the host after every step.
+struct Budget {
+    int max_iters;
+    double max_seconds;
+    std::chrono::steady_clock::time_point t0;
+    Budget(int it, double sec) : max_iters(it), max_seconds(sec), t0(std::chrono::steady_clock::now()) {}
+    bool out_of_steps(int iters) const { return max_iters > 0 && iters >= max_iters; }
+    bool out_of_time() const {
+        return max_seconds > 0.0 &&
+               std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() >= max_seconds;
+    }
+};
 
 __device__ inline double cj(double v) { return v; }
 __device__ inline cx<double> cj(cx<double> v) { return conj(v); }
@@ -380,8 +396,8 @@ std::vector<double> norms(std::vector<Krylov<V> *> &K, const std::vector<const V
 // restarts from there (counted in restarts[r]).
 template <class V, class F>
 void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, const std::vector<const V *> &b,
-           const std::vector<V *> &x, double tol, int max_cycles, double mixed_below, int *iters, int *matvecs,
-           int *restarts, double *relres, int *status, bool zero_x0) {
+           const std::vector<V *> &x, double tol, int max_cycles, double mixed_below, const Budget &bud, int *iters,
+           int *matvecs, int *restarts, double *relres, int *status, bool zero_x0) {
     const size_t nr = K.size();
     if (!nr) return;
     Ctx &c = K[0]->c;
@@ -422,6 +438,7 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
             act.push_back(r);
         }
     }
+    std::vector<size_t> spent;  // right-hand sides out of steps or time: stopped where they are
     for (int cycle = 0; cycle < max_cycles && !act.empty(); cycle++) {
         // r0 = b - A x into V0
         if (zero_x0 && cycle == 0) {
@@ -505,13 +522,19 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
             }
             c.sync();
             std::vector<size_t> next;
+            const bool late = bud.out_of_time();
             for (size_t i = 0; i < live.size(); i++) {
                 const size_t r = live[i];
                 iters[r]++;
                 jdone[r] = j + 1;
                 relres[r] = K[r]->h_out[0] / bnorm[r];
                 const bool breakdown = K[r]->h_out[1] != 0.0;
-                if (!(relres[r] <= tol || breakdown)) next.push_back(r);
+                if (relres[r] <= tol || breakdown) continue;
+                if (late || bud.out_of_steps(iters[r])) {
+                    spent.push_back(r);  // leaves the cycle; its iterate is formed below
+                    continue;
+                }
+                next.push_back(r);
             }
             live = next;
         }
@@ -522,7 +545,20 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
             k_lincomb<V><<<nb, RBS, 0, c.stream>>>(Kr.basis.p, n, Kr.y.p, jdone[r], x[r], n);
             BEM_LAUNCH_CHECK();
         }
+        // a right-hand side that has spent its budget starts no further cycle
+        if (!spent.empty()) {
+            std::vector<size_t> keep;
+            for (size_t r : act)
+                if (std::find(spent.begin(), spent.end(), r) == spent.end()) keep.push_back(r);
+            act = keep;
+        }
+        if (bud.out_of_time()) {  // every right-hand side stops where it is
+            spent.insert(spent.end(), act.begin(), act.end());
+            act.clear();
+        }
     }
+    act.insert(act.end(), spent.begin(), spent.end());
+    std::sort(act.begin(), act.end());
     // final explicit residual of those that did not stop at a cycle start
     if (!act.empty()) {
         std::vector<const V *> in;
@@ -559,7 +595,7 @@ void gmres(std::vector<Krylov<V> *> &K, F &&apply, V *stage_in, V *stage_out, co
 // once per step.
 template <class V, class F>
 void bicgstab(Krylov<V> &K, F &&apply, const V *b, V *x, double tol, int max_cycles, int steps, double mixed_below,
-              int *iters, int *matvecs, int *restarts, double *relres, int *status) {
+              const Budget &bud, int *iters, int *matvecs, int *restarts, double *relres, int *status) {
     Ctx &c = K.c;
     const int64_t n = K.n;
     const unsigned nb = nblocks(n, RBS);
@@ -575,6 +611,7 @@ void bicgstab(Krylov<V> &K, F &&apply, const V *b, V *x, double tol, int max_cyc
         *status = BEM_OK;
         return;
     }
+    bool spent = bud.out_of_time();  // out of steps or time: the FP64 residual of x, then stop
     for (int cycle = 0;; cycle++) {
         // r = b - A x in FP64 (b itself while x = 0)
         if (cycle == 0) {
@@ -598,7 +635,7 @@ void bicgstab(Krylov<V> &K, F &&apply, const V *b, V *x, double tol, int max_cyc
             *status = BEM_OK;
             return;
         }
-        if (cycle >= max_cycles || !(rel == rel)) return;  // out of cycles, or the iterate is not finite
+        if (cycle >= max_cycles || spent || !(rel == rel)) return;  // out of budget, or the iterate is not finite
         if (cycle > 0) (*restarts)++;
         for (int it = 0; it < steps; it++) {
             const int prec = rel <= mixed_below ? BEM_PREC_MIXED : BEM_PREC_FP64;
@@ -619,6 +656,10 @@ void bicgstab(Krylov<V> &K, F &&apply, const V *b, V *x, double tol, int max_cyc
             (*iters)++;
             rel = std::sqrt(K.h_out[2]) / bnorm;
             if (!(rel == rel) || rel <= tol) break;  // converged, or broke down (x kept): FP64 residual, restart
+            if (bud.out_of_steps(*iters) || bud.out_of_time()) {
+                spent = true;
+                break;
+            }
         }
     }
 }
@@ -626,6 +667,7 @@ void bicgstab(Krylov<V> &K, F &&apply, const V *b, V *x, double tol, int max_cyc
 template <class V>
 int solve_t(bem_tree &t, int green, double k, int nrhs, const V *chi, V *phi, const bem_solve_opts &o,
             bem_solve_info *info) {
+    const Budget bud(o.max_iters, o.max_seconds);
     Ctx &c = *t.ctx;
     const int64_t n = t.mesh->n_dof;
     const int m = o.restart;
@@ -666,17 +708,17 @@ int solve_t(bem_tree &t, int green, double k, int nrhs, const V *chi, V *phi, co
         // one right-hand side after the other, each with its own vectors
         for (int r = 0; r < nrhs; r++) {
             Krylov<V> Kb(c, n, 6);
-            bicgstab(Kb, A, bv[r], xv[r], o.tol, o.max_restarts, o.restart, mixed_below, &iters[r], &mv[r], &rs[r],
-                     &res[r], &st[r]);
+            bicgstab(Kb, A, bv[r], xv[r], o.tol, o.max_restarts, o.restart, mixed_below, bud, &iters[r], &mv[r],
+                     &rs[r], &res[r], &st[r]);
         }
     } else {
-        gmres(K, A, sin.p, sout.p, bv, xv, o.tol, o.max_restarts, mixed_below, iters.data(), mv.data(), rs.data(),
-              res.data(), st.data(), true);
+        gmres(K, A, sin.p, sout.p, bv, xv, o.tol, o.max_restarts, mixed_below, bud, iters.data(), mv.data(),
+              rs.data(), res.data(), st.data(), true);
     }
     for (int r = 0; r < nrhs; r++) {
         inf[r].iterations += iters[r];
         inf[r].matvecs += mv[r];
-        inf[r].refinements = mixed ? rs[r] : 0;
+        inf[r].restarts = rs[r];
         inf[r].residual = res[r];
         inf[r].status = st[r];
     }
