@@ -234,6 +234,26 @@ int bem_tree_stats_get(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k
 int bem_matvec(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, bem_op op, bem_method m,
                bem_precision p, int nrhs, const void *x_dev, void *y_dev);
 
+/* bem_matvec without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, stream ordering and results (bit
+ * for bit) as bem_matvec.  The product's work space (strengths, expansions,
+ * near-field partial sums, multipole-to-local buffers) comes from one fixed
+ * array of BEM_NOALLOC_SCRATCH_BYTES per device, which the library holds from
+ * the moment its code is loaded on the device until the process ends; the
+ * call makes no hipMalloc / hipFree and no allocator callback.  All calls on
+ * one device share that array and it keeps the last call's contents: calls
+ * that overlap on one GPU (other contexts, streams or threads) race, so
+ * callers serialise them.
+ * Errors: those of bem_matvec; BEM_ESTATE while the tree's tables for this
+ * (g, k, op, m, p) are not built (one bem_matvec call with the same
+ * arguments builds them) or while phase timing is on; BEM_EINVAL when the
+ * product needs more work space than the array holds (the message gives
+ * both sizes). */
+#define BEM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int bem_matvec_noalloc(bem_ctx *ctx, const bem_tree *tree, bem_green g, double k, bem_op op, bem_method m,
+                       bem_precision p, int nrhs, const void *x_dev, void *y_dev);
+
 /* ------------------------------------------------------------------ solve */
 typedef struct {
     double tol;          /* relative residual |b - A x| / |b| to reach; 0 -> 1e-8 */

@@ -30,8 +30,8 @@ BEM_KRYLOV_GMRES, BEM_KRYLOV_BICGSTAB = 0, 1
 
 EXPORTED = [
     "bem_ctx_create", "bem_ctx_destroy", "bem_ctx_timing", "bem_ctx_device_bytes", "bem_last_error", "bem_mesh_load", "bem_mesh_dofs", "bem_mesh_free",
-    "bem_tree_build", "bem_tree_export", "bem_tree_free", "bem_tree_stats_get", "bem_matvec", "bem_solve",
-    "bem_field",
+    "bem_tree_build", "bem_tree_export", "bem_tree_free", "bem_tree_stats_get", "bem_matvec", "bem_matvec_noalloc",
+    "bem_solve", "bem_field",
     "bem_server_create", "bem_server_add_mesh", "bem_server_mesh_dofs", "bem_server_submit", "bem_server_poll",
     "bem_server_stats_get",
     "bem_server_destroy",
@@ -149,6 +149,7 @@ def load_library(path: str = LIB_PATH):
     L.bem_tree_free.restype = None
     L.bem_tree_stats_get.argtypes = [vp, vp, i32, dbl, ctypes.POINTER(_TreeStats)]
     L.bem_matvec.argtypes = [vp, vp, i32, dbl, i32, i32, i32, i32, vp, vp]
+    L.bem_matvec_noalloc.argtypes = [vp, vp, i32, dbl, i32, i32, i32, i32, vp, vp]
     L.bem_solve.argtypes = [vp, vp, i32, dbl, i32, vp, vp, ctypes.POINTER(_SolveOpts), ctypes.POINTER(_SolveInfo)]
     L.bem_field.argtypes = [vp, vp, i32, dbl, dbl, i32, vp, vp, i64, vp, vp]
     L.bem_server_create.argtypes = [ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]
@@ -358,6 +359,19 @@ def bem_matvec(ctx: Context, tree: Tree, green: int, k: float, op: int, method: 
         raise ValueError("x and y differ in shape")
     ctx.check(ctx.L.bem_matvec(ctx.h, tree.h, green, float(k), op, method, precision, nrhs,
                                ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())), "bem_matvec")
+
+
+def bem_matvec_noalloc(ctx: Context, tree: Tree, green: int, k: float, op: int, method: int, precision: int, x,
+                       y) -> None:
+    """bem_matvec with its work space in the library's fixed per-device
+    scratch (no device allocation); the tree's tables must exist (one
+    bem_matvec call with the same arguments builds them)."""
+    nrhs = _check_vec(x, tree.n_dof, green)
+    if _check_vec(y, tree.n_dof, green) != nrhs:
+        raise ValueError("x and y differ in shape")
+    ctx.check(ctx.L.bem_matvec_noalloc(ctx.h, tree.h, green, float(k), op, method, precision, nrhs,
+                                       ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())),
+              "bem_matvec_noalloc")
 
 
 def bem_solve(ctx: Context, tree: Tree, green: int, k: float, chi, phi, tol=1e-8, restart=50, max_restarts=100,

@@ -2,6 +2,8 @@
 // error capture, and the calls into the tree, quadrature, product and solver
 // units.  No exception crosses this file's functions.
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <new>
 
 #include "kernels.h"
@@ -33,6 +35,33 @@ int guard(Ctx *c, F &&f) {
 }
 
 thread_local std::string g_err;
+
+// Work space of bem_matvec_noalloc: one array per device, holding the
+// per-product buffers (strengths, expansions, near-field partial sums, the
+// multipole-to-local moments and results) of every such call on that device.
+// It is held from the moment the library's code is loaded on a device until
+// the process ends.  Host code never passes the array's name to a kernel: it
+// stands for the host-side shadow, not a device address; each device's copy
+// is reached through the address hipGetSymbolAddress returns for it.
+constexpr size_t SCRATCH_BYTES = BEM_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch;  // device -> its copy of scratch
+
+// Resolves the device address of `scratch` on the current device (once per
+// device; called by bem_ctx_create with its device current).
+char *scratch_on_current_device(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(device);
+    if (it != g_scratch.end()) return it->second;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        bem::fail(BEM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[device] = (char *)ptr;
+    return (char *)ptr;
+}
 
 // A tree built with the wavenumber bound k (r1 + r2) <= kappa on its lists
 // (Section 3.6's separation test with the Helmholtz bound) keeps the
@@ -66,6 +95,7 @@ int bem_ctx_create(int device, void *hip_stream, const bem_allocator *alloc, bem
         int n = 0;
         BEM_HIP(hipGetDeviceCount(&n));
         BEM_REQUIRE(device >= 0 && device < n, BEM_EINVAL, "no such device");
+        (void)scratch_on_current_device(device);  // the device is current here (guard)
     });
     if (rc != BEM_OK) {
         g_err = ctx->c.err;
@@ -290,6 +320,49 @@ int bem_matvec(bem_ctx *ctx, const bem_tree *tc, bem_green g, double k, bem_op o
         BEM_REQUIRE(p == BEM_PREC_FP64 || p == BEM_PREC_MIXED, BEM_EINVAL, "unknown precision");
         check_wavenumber(*t, g, k);
         bem::matvec(*t, g, g == BEM_HELMHOLTZ ? k : 0.0, op, m, p, nrhs, x_dev, y_dev);
+    });
+}
+
+int bem_matvec_noalloc(bem_ctx *ctx, const bem_tree *tc, bem_green g, double k, bem_op op, bem_method m,
+                       bem_precision p, int nrhs, const void *x_dev, void *y_dev) {
+    if (!ctx || !tc) return BEM_EINVAL;
+    bem_tree *t = const_cast<bem_tree *>(tc);
+    Ctx &c = ctx->c;
+    return guard(&c, [&] {
+        BEM_REQUIRE(t->ctx == &c, BEM_ESTATE, "tree belongs to another context");
+        BEM_REQUIRE(nrhs >= 1 && nrhs <= 65535, BEM_EINVAL, "nrhs must be in 1..65535");
+        BEM_REQUIRE(x_dev && y_dev && x_dev != y_dev, BEM_EINVAL, "x and y must be distinct device buffers");
+        BEM_REQUIRE(g == BEM_LAPLACE || g == BEM_HELMHOLTZ, BEM_EINVAL, "unknown Green's function");
+        BEM_REQUIRE(g != BEM_HELMHOLTZ || (k > 0.0 && std::isfinite(k)), BEM_EINVAL, "Helmholtz needs k > 0");
+        BEM_REQUIRE(op >= BEM_OP_S && op <= BEM_OP_RHS, BEM_EINVAL, "unknown operator");
+        BEM_REQUIRE(m == BEM_DIRECT || m == BEM_FMM, BEM_EINVAL, "unknown method");
+        BEM_REQUIRE(p == BEM_PREC_FP64 || p == BEM_PREC_MIXED, BEM_EINVAL, "unknown precision");
+        check_wavenumber(*t, g, k);
+        const double kk = g == BEM_HELMHOLTZ ? k : 0.0;
+        BEM_REQUIRE(c.timing == 0, BEM_ESTATE, "bem_matvec_noalloc runs with phase timing off");
+        BEM_REQUIRE(bem::product_ready(*t, g, kk, op, m, p), BEM_ESTATE,
+                    "the tree's tables for this product are not built: call bem_matvec once with the same "
+                    "green, k, op, method and precision first");
+        char *base = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_scratch_mu);
+            auto it = g_scratch.find(c.device);
+            BEM_REQUIRE(it != g_scratch.end(), BEM_ESTATE, "no scratch resolved for this device");
+            base = it->second;
+        }
+        struct ArenaScope {  // the arena holds for this product only, whatever happens in it
+            Ctx &c;
+            ArenaScope(Ctx &c_, char *b) : c(c_) {
+                c.arena = b;
+                c.arena_size = SCRATCH_BYTES;
+                c.arena_used = 0;
+            }
+            ~ArenaScope() {
+                c.arena = nullptr;
+                c.arena_size = c.arena_used = 0;
+            }
+        } scope(c, base);
+        bem::matvec(*t, g, kk, op, m, p, nrhs, x_dev, y_dev);
     });
 }
 

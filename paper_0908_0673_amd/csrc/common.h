@@ -156,6 +156,12 @@ struct Ctx {
     bool has_alloc = false;
     std::string err;
 
+    // Work arena: while set (bem_matvec_noalloc), the per-product work
+    // buffers are carved from this device region in order instead of being
+    // allocated; a product that needs more than arena_size fails.
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
+
     // Device bytes in use by the library through this context (bytes_live)
     // and freed blocks kept for reuse (cached).  Without a caller allocator,
     // freed blocks up to cache_limit bytes in total are kept by size class

@@ -799,10 +799,8 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
     const R *q = std::is_same<R, float>::value ? (const R *)t.q32.p : (const R *)t.q64.p;
     const R *tg = std::is_same<R, float>::value ? (const R *)t.t32.p : (const R *)t.t64.p;
     // work buffers
-    t.work.strength.ensure(&c, sizeof(V) * nq * nrhs);
-    if (method == BEM_DIRECT) t.work.yacc.ensure(&c, sizeof(V) * nt * nrhs);
-    V *s = (V *)t.work.strength.p;
-    V *yacc = (V *)t.work.yacc.p;
+    V *s = (V *)work_buf(c, t.work.strength, sizeof(V) * nq * nrhs);
+    V *yacc = method == BEM_DIRECT ? (V *)work_buf(c, t.work.yacc, sizeof(V) * nt * nrhs) : nullptr;
     rule_shapes(t);
     if (method == BEM_FMM) {
         fmm_tables(t);
@@ -812,11 +810,11 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
     }
     // moments and locals of the fast product in one buffer, cleared by the strength launch
     V *mom = nullptr, *loc = nullptr;
+    void *p2p_part = nullptr;  // near-field partial sums of the fast product
     size_t nexp = 0;
     if (method == BEM_FMM) {
         nexp = (size_t)t.n_box * t.tables->P * nrhs;
-        t.work.mom.ensure(&c, 2 * sizeof(V) * nexp);
-        mom = (V *)t.work.mom.p;
+        mom = (V *)work_buf(c, t.work.mom, 2 * sizeof(V) * nexp);
         loc = mom + nexp;
     }
     c.mark(9);
@@ -840,8 +838,8 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         using PD = typename std::conditional<HELM, cx<double>, double>::type;
         PD *part = nullptr;
         if (t.n_p2p_items) {
-            t.work.p2p_part.ensure(&c, sizeof(PD) * 64 * (size_t)t.n_p2p_units * nrhs);
-            part = (PD *)t.work.p2p_part.p;
+            part = (PD *)work_buf(c, t.work.p2p_part, sizeof(PD) * 64 * (size_t)t.n_p2p_units * nrhs);
+            p2p_part = part;
         }
         // While it runs beside the far field, the near-field kernel asks for
         // enough LDS that at most P2P_PER_CU of its blocks share a CU, which
@@ -919,7 +917,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
     // near-field sums, corrections and combination in FP64
     using VD = typename std::conditional<HELM, cx<double>, double>::type;
     const XV *corr = (const XV *)(dbl ? cr.K.p : cr.S.p);
-    const VD *part = method == BEM_FMM && t.n_p2p_items ? (const VD *)t.work.p2p_part.p : nullptr;
+    const VD *part = (const VD *)p2p_part;
     dim3 g(nblocks(8 * nt, 256), nrhs);
     const bool fmm = method == BEM_FMM;
     k_combine<XV, V, R, VD, !HELM><<<g, 256, 0, c.stream>>>(
@@ -932,6 +930,20 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
 }
 
 }  // namespace
+
+bool product_ready(const bem_tree &t, int green, double k, int op, int method, int prec) {
+    if (green == BEM_LAPLACE) k = 0.0;
+    bool corr = false;
+    for (auto &p : t.corr) corr = corr || (p->green == green && p->k == k);
+    if (!corr || !t.L7.p || (op == BEM_OP_A && !t.has_free_term)) return false;
+    if (method == BEM_DIRECT) return true;
+    if (!t.tables || t.tables->p != t.order || !t.planned || !t.pass.built) return false;
+    // the near field runs on the context's second stream, created by the first product
+    if (t.n_p2p_items && !t.ctx->side) return false;
+    for (auto &pl : t.m2l)
+        if (pl->green == green && pl->k == k) return m2l_ready(*pl, prec);
+    return false;
+}
 
 void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int nrhs, const void *x, void *y) {
     Ctx &c = *t.ctx;

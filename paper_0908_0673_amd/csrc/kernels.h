@@ -140,6 +140,23 @@ struct Work {
     DBuf<char> strength, mom, loc, yacc, m2l_out, m2l_mom, p2p_part;
 };
 
+// Device work space of `bytes` for one product: the next 256-byte aligned
+// piece of the context's arena when one is set (nothing is allocated; a
+// product that does not fit fails with BEM_EINVAL), else the tree's buffer
+// `buf`, grown on demand.
+inline void *work_buf(Ctx &c, DBuf<char> &buf, size_t bytes) {
+    if (c.arena) {
+        const size_t at = (c.arena_used + 255) & ~(size_t)255;
+        BEM_REQUIRE(at + bytes <= c.arena_size, BEM_EINVAL,
+                    "the product needs more work space than the no-allocation scratch holds (" +
+                        std::to_string(at + bytes) + " > " + std::to_string(c.arena_size) + " bytes)");
+        c.arena_used = at + bytes;
+        return c.arena + at;
+    }
+    buf.ensure(&c, bytes);
+    return buf.p;
+}
+
 }  // namespace bem
 
 struct bem_tree {
@@ -258,6 +275,10 @@ void fmm_tables(bem_tree &t);
 void plan_fmm(bem_tree &t);
 LevelP level_p(const bem_tree &t);  // coefficients per level: min(order, order_min + max_level - l)
 void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int nrhs, const void *x, void *y);
+// whether every table such a product reads exists already (an earlier
+// product with the same arguments built them), so that it allocates nothing
+// beyond its work space
+bool product_ready(const bem_tree &t, int green, double k, int op, int method, int prec);
 
 // passes.hip
 void build_pass_tables(bem_tree &t);
@@ -272,6 +293,7 @@ void l2l_apply(bem_tree &t, int nrhs, V *loc);
 M2lPlan &get_m2l_plan(bem_tree &t, int green, double k);
 template <class V, class R>
 void m2l_prepare(bem_tree &t, M2lPlan &pl);
+bool m2l_ready(const M2lPlan &pl, int prec);  // operators and tasks of precision prec exist
 template <class V, class R>
 void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc);
 

@@ -688,6 +688,16 @@ constexpr int m2l_cols() {
 
 }  // namespace
 
+bool m2l_ready(const M2lPlan &pl, int prec) {
+    const bool helm = pl.green == BEM_HELMHOLTZ, f32 = prec == BEM_PREC_MIXED;
+    if (pl.n_class && !(f32 ? (const void *)pl.T32.p : (const void *)pl.T64.p)) return false;
+    const int cols = helm ? (f32 ? m2l_cols<cx<float>, float>() : m2l_cols<cx<double>, double>())
+                          : (f32 ? m2l_cols<float, float>() : m2l_cols<double, double>());
+    for (auto &tk : pl.tasks)
+        if (tk->cols == cols) return true;
+    return false;
+}
+
 template <class V, class R>
 void m2l_prepare(bem_tree &t, M2lPlan &pl) {
     expanded<R>(t, pl);
@@ -704,13 +714,11 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc) {
         c.mark(3);
         return;
     }
-    t.work.m2l_out.ensure(&c, sizeof(V) * (size_t)std::max<int64_t>(1, t.n_inter) * OUT_LD);
-    V *out = (V *)t.work.m2l_out.p;
+    V *out = (V *)work_buf(c, t.work.m2l_out, sizeof(V) * (size_t)std::max<int64_t>(1, t.n_inter) * OUT_LD);
     M2lArgs a{tk.task_class.p, tk.task_first.p, tk.task_count.p, pl.pair_slot.p, pl.pair_src.p, pl.pair_mom.p,
               t.level.p, tk.task_kt.p, tk.task_mt.p, t.side, P};
     const LevelP lp = level_p(t);
-    t.work.m2l_mom.ensure(&c, sizeof(V) * (size_t)std::max<int64_t>(1, pl.n_u) * KIN);
-    V *Mc = (V *)t.work.m2l_mom.p;
+    V *Mc = (V *)work_buf(c, t.work.m2l_mom, sizeof(V) * (size_t)std::max<int64_t>(1, pl.n_u) * KIN);
     const R *Tx = expanded<R>(t, pl);
     for (int rhs = 0; rhs < nrhs; rhs++) {
         const V *m = mom + (int64_t)rhs * t.n_box * P;
