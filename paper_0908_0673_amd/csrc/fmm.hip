@@ -87,33 +87,13 @@ __device__ inline double inv_sqrt(double v) {
     return y;
 }
 
-// sin and cos of x for the near field's phases k r: Cody-Waite reduction by
+// sin and cos of x for the FP64 near field's phases k r: Cody-Waite reduction by
 // the nearest multiple q of pi/2 (pi/2 split in three parts, each product
 // q * part formed exactly inside an fma), Taylor polynomials of sin and cos
 // on the reduced argument |r| <= pi/4 (the first omitted term is below half
 // an ulp there) and the quadrant q mod 4.  No range branch; the reduction
-// stays accurate while |x| < 2^20 in single and 2^40 in double precision,
-// far beyond k times any near-field distance.
-__device__ inline void sincos_near(float x, float *s, float *c) {
-    const float q = rintf(x * 0.63661977f);
-    float r = fmaf(-q, 1.5707963705062866f, x);
-    r = fmaf(-q, -4.371138828673793e-08f, r);
-    r = fmaf(-q, -1.7151245100058819e-15f, r);
-    const float r2 = r * r;
-    float ps = fmaf(r2, 2.7557319e-6f, -1.9841270e-4f);  // 1/9!, -1/7!
-    ps = fmaf(r2, ps, 8.3333333e-3f);                    // 1/5!
-    ps = fmaf(r2, ps, -1.6666667e-1f);                   // -1/3!
-    const float sr = fmaf(r * r2, ps, r);
-    float pc = fmaf(r2, -2.7557319e-7f, 2.4801587e-5f);  // -1/10!, 1/8!
-    pc = fmaf(r2, pc, -1.3888889e-3f);                   // -1/6!
-    pc = fmaf(r2, pc, 4.1666667e-2f);                    // 1/4!
-    pc = fmaf(r2, pc, -0.5f);
-    const float cr = fmaf(r2, pc, 1.0f);
-    const int n = (int)q;  // two's complement: n & 3 is q mod 4 for negative q too
-    const float u = (n & 1) ? cr : sr, v = (n & 1) ? sr : cr;
-    *s = (n & 2) ? -u : u;
-    *c = ((n + 1) & 2) ? -v : v;
-}
+// stays accurate while |x| < 2^40, far beyond k times any near-field
+// distance.
 __device__ inline void sincos_near(double x, double *s, double *c) {
     const double q = rint(x * 0.6366197723675814);
     double r = fma(-q, 1.5707963267948966, x);
@@ -142,6 +122,19 @@ __device__ inline void sincos_near(double x, double *s, double *c) {
     *c = ((n + 1) & 2) ? -v : v;
 }
 
+// sin and cos of x in single precision from the matrix-core generation's
+// transcendental unit: x in revolutions (x / 2 pi), its fractional part, then
+// the hardware sine and cosine of a fraction of a turn.  The near field's
+// phases k r stay within a few turns, where the reduction to [0, 1) is exact
+// and the hardware functions keep the products within the stated tolerance
+// (checked against the oracle with the rest of the mixed-precision path).
+__device__ inline void sincos_turns(float x, float *s, float *c) {
+    const float f = __builtin_amdgcn_fractf(x * 0.159154943f);  // 1 / (2 pi)
+    *s = __builtin_amdgcn_sinf(f);
+    *c = __builtin_amdgcn_cosf(f);
+}
+__device__ inline void sincos_turns(double x, double *s, double *c) { sincos_near(x, s, c); }
+
 template <class R> struct r4;
 template <> struct r4<float> { using type = float4; };
 template <> struct r4<double> { using type = double4; };
@@ -160,7 +153,7 @@ __device__ inline V p2p_term(double x0, double x1, double x2, double2 sxy, doubl
         if (DBL) g = g * (d0 * ns.x + d1 * ns.y + d2 * ns.z) * ir * ir;
         const R kr = k * r2 * ir;
         R sn, cs;
-        sincos_near(kr, &sn, &cs);
+        sincos_turns(kr, &sn, &cs);
         cx<R> kv = DBL ? cx<R>(g * (cs + kr * sn), g * (sn - kr * cs)) : cx<R>(g * cs, g * sn);
         return kv * cx<R>(ns.w, si);
     } else {
