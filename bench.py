@@ -238,8 +238,6 @@ def main():
     ap.add_argument("--no-cpu-fmm", action="store_true", help="skip timing the oracle's fast product")
     ap.add_argument("--no-phases", action="store_true", help="skip the serialized per-phase timing pass")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--serve-full", action="store_true",
-                    help="serving measurement on the longer stream (200 requests, 2000-40000 triangles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (for HBM counter calibration)")
     ap.add_argument("--batched", action="store_true",
@@ -248,8 +246,17 @@ def main():
     ap.add_argument("--batched-kappa", type=float, default=2.2,
                     help="wavenumber bound k (r1 + r2) <= kappa on the lists of the Helmholtz trees")
     ap.add_argument("--batched-ka-max", type=float, default=20.0, help="largest ka of the batched set")
-    ap.add_argument("--serve-ka-max", type=float, default=25.0,
-                    help="largest ka of the --serve-full stream (see --batched-ka-max)")
+    ap.add_argument("--serve-c5", action="store_true",
+                    help="run only the serving stream of the C5 shape: Poisson arrivals, 2000-80000 triangles "
+                         "log-uniform, Laplace/Helmholtz 50/50, ka 1-25, 1-32 right-hand sides, rate swept over "
+                         "fractions of the saturation rate")
+    ap.add_argument("--c5-count", type=int, default=1000, help="counted requests of --serve-c5")
+    ap.add_argument("--c5-warmup", type=int, default=50, help="warm-up requests of --serve-c5")
+    ap.add_argument("--c5-fracs", default="0.25,0.5,0.8,1.0", help="rates of --serve-c5 as fractions of saturation")
+    ap.add_argument("--c5-baseline", type=int, default=0,
+                    help="plain FP64 service times on the first this many counted requests (0: all)")
+    ap.add_argument("--lanes", type=int, default=4, help="serving lanes")
+    ap.add_argument("--max-seconds", type=float, default=60.0, help="time budget per served batch")
     ap.add_argument("--protocol", action="store_true",
                     help="run only the paper's own test protocol (Tables 1-8 shapes, level-dependent order, "
                          "BiCGSTAB, three trees)")
@@ -266,10 +273,19 @@ def main():
     if args.protocol:
         paper_protocol()
         return
-    if args.batched:
-        print(json.dumps({"batched": serving(64, 20090909, (1000, 40000), (1.0, args.batched_ka_max), 16, 4,
-                                             96 << 30, uniform_size=True, nrhs_fixed=16,
-                                             kappa=args.batched_kappa)}), flush=True)
+    if args.batched:  # C4: 64 instances, 1000-40000 triangles, ka 1-20, 16 plane waves each, all at once
+        print(json.dumps({"batched": serving(64, 20090909, (1000, 40000), (1.0, args.batched_ka_max), 16,
+                                             args.lanes, 96 << 30, rate_fracs=(), uniform_size=True, nrhs_fixed=16,
+                                             kappa=args.batched_kappa, max_seconds=args.max_seconds,
+                                             label="batched")}), flush=True)
+        return
+    if args.serve_c5:  # C5: Poisson stream, 2000-80000 triangles, ka 1-25, 1-32 right-hand sides
+        fr = tuple(float(f) for f in args.c5_fracs.split(","))
+        print(json.dumps({"serving_c5": serving(args.c5_count, 20090910, (2000, 80000), (1.0, 25.0), 32,
+                                                args.lanes, 96 << 30, rate_fracs=fr, kappa=2.2,
+                                                max_seconds=args.max_seconds, warmup=args.c5_warmup,
+                                                baseline_count=args.c5_baseline or None, label="c5")}),
+              flush=True)
         return
 
     import torch
@@ -350,12 +366,11 @@ def main():
     if not args.no_solve:
         out["solve"] = solves(bem, ctx, wls)
 
-    if not args.no_serve:
-        if args.serve_full:
-            out["serving"] = serving(200, 20090908, (2000, 40000), (1.0, args.serve_ka_max), 32, 4, 96 << 30,
-                                     kappa=2.2)
-        else:
-            out["serving"] = serving(24, 20090908, (1000, 6000), (1.0, 5.0), 8, 4, 32 << 30, kappa=2.2)
+    if not args.no_serve:  # a bounded slice of the C5 stream's shape
+        out["serving"] = serving(32, 20090908, (2000, 20000), (1.0, 25.0), 8, 4, 32 << 30, rate_fracs=(0.5,),
+                                 kappa=2.2, max_seconds=10.0, warmup=4, label="serving")
+        out["serving"]["slice"] = ("the C5 shape bounded for the default run: 32 requests after 4 warm-up, "
+                                   "2000-20000 triangles, 1-8 right-hand sides, 32 GiB budget")
 
     if not args.no_cpu and "c2_sphere" in wls:
         w = wls["c2_sphere"]
@@ -539,114 +554,203 @@ def _boundary_data(dofs, req):
     return np.array(rows)
 
 
-def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_frac=0.5, uniform_size=False, nrhs_fixed=0,
-            kappa=2.2, max_iters=1500):
+def _bucket_top(k):
+    """Top of the server's wavenumber bucket of k: 2^(ceil(4 log2 k) / 4)."""
+    return float(2.0 ** (np.ceil(4.0 * np.log2(k) - 1e-12) / 4.0))
+
+
+_JN_ZEROS = None
+
+
+def _jn_zero_distance(ka):
+    """Distance of ka to the nearest zero of a spherical Bessel function j_n
+    (n <= 60): the exterior Neumann equation without a Burton-Miller
+    correction is singular there on the unit sphere."""
+    global _JN_ZEROS
+    if _JN_ZEROS is None:
+        from scipy.optimize import brentq
+        from scipy.special import spherical_jn
+
+        zs = []
+        x = np.linspace(0.05, 45.0, 45001)
+        for n in range(61):
+            v = spherical_jn(n, x)
+            for i in np.nonzero(np.sign(v[:-1]) * np.sign(v[1:]) < 0)[0]:
+                zs.append(brentq(lambda t: spherical_jn(n, t), x[i], x[i + 1]))
+        _JN_ZEROS = np.sort(np.array(zs))
+    return float(np.abs(_JN_ZEROS - ka).min())
+
+
+def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_fracs=(0.5,), uniform_size=False, nrhs_fixed=0,
+            kappa=2.2, max_iters=1000, max_seconds=60.0, warmup=0, baseline_count=None, label="serving"):
     """Served, mixed-precision solves (bem_server_*: concurrent lanes, request
-    merging, right-hand sides in lock step) against plain FP64 solves of one
-    right-hand side at a time on one context, on the same seeded request
-    stream; trees are cached per mesh on both sides.
-    Throughput: all requests offered at once.  Latency: a second pass with
-    Poisson arrivals at rate_frac times the measured request throughput
-    (warm caches), submission to completion."""
+    merging, right-hand sides in lock step, trees kept per mesh and
+    wavenumber bucket under the device-memory budget) against plain FP64
+    solves of one request and one right-hand side at a time on one context,
+    on the same seeded request stream and the same trees.
+
+    The first `warmup` requests are served and not counted.  Throughput: the
+    next `count` requests offered at once (the saturation rate).  Latency:
+    for each fraction f of rate_fracs, the same requests again as a Poisson
+    stream at f times the saturation rate (open loop, submission to
+    completion).  Baseline: the FP64 service time of every counted request
+    (or of the first baseline_count), its throughput, and its latency under
+    the same arrivals as a single first-come-first-served server (completion
+    = max(arrival, previous completion) + service time), so the two latency
+    figures are measured against the same arrival process.  Every solve has
+    the step budget max_iters per right-hand side and the time budget
+    max_seconds per batch (non-converged counts reported on both sides), and
+    for Helmholtz requests on spheres the distance of ka to the nearest zero
+    of a spherical Bessel function is reported (irregular frequencies)."""
     import torch
 
     import paper_0908_0673_amd as bem
     from bem_inputs.requests import mesh_of, request_stream
 
-    reqs = request_stream(count, seed, n_tri=n_tri, ka=ka, nrhs_max=nrhs_max, uniform_size=uniform_size,
-                          nrhs_fixed=nrhs_fixed)
+    reqs_all = request_stream(count + warmup, seed, n_tri=n_tri, ka=ka, nrhs_max=nrhs_max, uniform_size=uniform_size,
+                              nrhs_fixed=nrhs_fixed)
+    t0 = time.perf_counter()
     meshes = {}
-    for r in reqs:
+    for r in reqs_all:
         if r["key"] not in meshes:
             meshes[r["key"]] = mesh_of(r)
+    warm, reqs = reqs_all[:warmup], reqs_all[warmup:]
     total_rhs = sum(r["nrhs"] for r in reqs)
-    print(f"serving: {len(meshes)} meshes generated, {total_rhs} right-hand sides", file=sys.stderr, flush=True)
-    out = {"requests": count, "rhs": total_rhs, "distinct_meshes": len(meshes), "kappa": kappa,
-           "elements": [int(min(m.n_elem for m in meshes.values())), int(max(m.n_elem for m in meshes.values()))],
-           "lanes": lanes, "hbm_budget_gb": budget / 2 ** 30, "seed": seed,
+    print(f"{label}: {len(meshes)} meshes generated in {time.perf_counter() - t0:.1f} s, {len(reqs)} requests "
+          f"({total_rhs} right-hand sides) after {warmup} warm-up", file=sys.stderr, flush=True)
+    sizes = [meshes[r["key"]].n_elem for r in reqs]
+    out = {"requests": count, "warmup_requests": warmup, "rhs": total_rhs, "distinct_meshes": len(meshes),
+           "kappa": kappa, "elements": [int(min(sizes)), int(max(sizes))], "mean_elements": float(np.mean(sizes)),
+           "lanes": lanes, "hbm_budget_gb": budget / 2 ** 30, "seed": seed, "max_iters": max_iters,
+           "max_seconds_per_batch": max_seconds,
            "stream": f"n_tri {'uniform' if uniform_size else 'log-uniform'} {list(n_tri)}, sphere/cube/ellipsoid, "
-                     f"Laplace/Helmholtz 50/50, ka U{list(ka)}, "
+                     f"Laplace/Helmholtz 50/50, ka U{list(ka)} (k = ka / circumradius), "
                      + (f"nrhs {nrhs_fixed}" if nrhs_fixed else f"nrhs U[1,{nrhs_max}]")}
-    # served
-    # kappa > 0: the wavenumber bound on the lists; the server then solves every
-    # Helmholtz batch on a tree of its own k, and so does the baseline below
+    sph = [r for r in reqs if r["green"] and r["shape"] == "sphere"]
+    if sph:
+        d = np.array([_jn_zero_distance(r["ka"]) for r in sph])
+        out["sphere_helmholtz_jn_zero_distance"] = {"requests": len(sph), "min": float(d.min()),
+                                                    "median": float(np.median(d)),
+                                                    "below_0.05": int((d < 0.05).sum())}
+
+    def summary(results):
+        infos = [i for r in results for i in r[2]]
+        it = np.array([i["iterations"] for i in infos]) if infos else np.zeros(1)
+        return {"not_converged": sum(1 for i in infos if i["status"] != 0),
+                "failed_requests": sum(1 for r in results if r[0] not in (0, bem.BEM_ENOCONV)),
+                "iterations": {"median": float(np.median(it)), "max": int(it.max()), "mean": float(it.mean())}}
+
     srv = bem.Server(lanes=lanes, hbm_budget=budget, max_batch_rhs=32, precision=bem.BEM_PREC_MIXED, kappa=kappa,
-                     max_iters=max_iters)
+                     max_iters=max_iters, max_seconds=max_seconds)
     try:
         ids = {key: srv.add_mesh(m.xyz, m.elem)[0] for key, m in meshes.items()}
-        chis = [_boundary_data(srv.mesh_dofs(ids[r["key"]]), r) for r in reqs]
+        dofs = {key: srv.mesh_dofs(i) for key, i in ids.items()}
+
+        def submit(r):
+            return srv.submit(ids[r["key"]], r["green"], r["k"], _boundary_data(dofs[r["key"]], r))
+
+        if warm:
+            for t in [submit(r) for r in warm]:
+                srv.poll(t)
+            print(f"{label}: warm-up served", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        tickets = [srv.submit(ids[r["key"]], r["green"], r["k"], c) for r, c in zip(reqs, chis)]
+        tickets = [submit(r) for r in reqs]
         res = []
         for i, t in enumerate(tickets):
-            res.append(srv.poll(t))
-            if (i + 1) % 8 == 0:
-                print(f"serving: {i + 1} of {count} requests served", file=sys.stderr, flush=True)
+            rc, phi, info, lat = srv.poll(t)
+            res.append((rc, None, info, lat))
+            if (i + 1) % max(8, len(reqs) // 10) == 0:
+                print(f"{label}: {i + 1} of {len(reqs)} requests served", file=sys.stderr, flush=True)
         dt = time.perf_counter() - t0
+        sat = len(reqs) / dt
         out["served_solves_per_s"] = total_rhs / dt
-        out["served_requests_per_s"] = count / dt
-        out["served_not_converged"] = sum(1 for r in res for i in r[2] if i["status"] != 0)
-        rate = rate_frac * count / dt
-        t0 = time.perf_counter()
-        tickets = []
-        for r, c in zip(reqs, chis):
-            wait = r["t"] / rate - (time.perf_counter() - t0)
-            if wait > 0:
-                time.sleep(wait)
-            tickets.append(srv.submit(ids[r["key"]], r["green"], r["k"], c))
-        lat = np.array([srv.poll(t)[3] for t in tickets])
-        out["open_loop_rate_requests_per_s"] = rate
-        out["latency_ms"] = {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)}
+        out["served_requests_per_s"] = sat
+        out["served"] = summary(res)
+        out["open_loop"] = []
+        arrivals = np.array([r["t"] for r in reqs])
+        arrivals = arrivals - arrivals[0]
+        for f in rate_fracs:
+            rate = f * sat
+            t0 = time.perf_counter()
+            tickets = []
+            for r, a_ in zip(reqs, arrivals):
+                wait = a_ / rate - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+                tickets.append(submit(r))
+            lat = np.array([srv.poll(t)[3] for t in tickets])
+            out["open_loop"].append({"rate_fraction_of_saturation": f, "rate_requests_per_s": rate,
+                                     "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                                                    "p99": float(np.percentile(lat, 99) * 1e3)}})
+            print(f"{label}: open loop at {f} x saturation done", file=sys.stderr, flush=True)
         out["server_stats"] = srv.stats()
     finally:
         srv.close()
-    print(f"serving: served pass done ({out.get('served_solves_per_s', 0):.1f} solves/s)", file=sys.stderr, flush=True)
+    print(f"{label}: served ({out.get('served_solves_per_s', 0):.1f} solves/s)", file=sys.stderr, flush=True)
     # plain FP64, one request at a time, one right-hand side at a time, on the
     # trees the server uses (per mesh and, with the wavenumber bound, per
-    # wavenumber bucket), cached on first use
+    # wavenumber bucket), cached on first use (least recently used dropped
+    # beyond the budget's worth of meshes)
     ctx = bem.Context(0)
     meshes_dev, trees = {}, {}
-    t0 = time.perf_counter()
-    lat_base = []
-    nconv = 0
-    for r, c in zip(reqs, chis):
+    base = reqs if baseline_count is None else reqs[:baseline_count]
+    service = []
+    bres = []
+    for r in base:
         t1 = time.perf_counter()
         if r["key"] not in meshes_dev:
             m = meshes[r["key"]]
             meshes_dev[r["key"]] = bem.bem_mesh_load(ctx, m.xyz, m.elem)
         kh = _bucket_top(r["k"]) if (kappa > 0.0 and r["green"] == 1) else 0.0
-        if (r["key"], kh) not in trees:
-            trees[(r["key"], kh)] = bem.bem_tree_build(ctx, meshes_dev[r["key"]], B=32, order=8, theta=0.5,
-                                                       kappa=kappa, k_hint=kh)
-        tree = trees[(r["key"], kh)]
+        tk = (r["key"], kh)
+        if tk not in trees:
+            while trees and ctx.device_bytes()[0] > budget // 2:  # keep the baseline's residency bounded too
+                old = next(iter(trees))
+                trees.pop(old).close()
+            trees[tk] = bem.bem_tree_build(ctx, meshes_dev[r["key"]], B=32, order=8, theta=0.5, kappa=kappa,
+                                           k_hint=kh)
+        else:
+            trees[tk] = trees.pop(tk)  # most recently used last
+        tree = trees[tk]
+        c = _boundary_data(dofs[r["key"]], r)
         cplx = r["green"] == 1
         chid = torch.tensor(c if cplx else c.real, dtype=torch.complex128 if cplx else torch.float64, device="cuda:0")
         phid = torch.empty_like(chid)
+        infos = []
+        t_b = time.perf_counter()
         for j in range(chid.shape[0]):
-            info = bem.bem_solve(ctx, tree, r["green"], r["k"], chid[j:j + 1], phid[j:j + 1],
-                                 precision=bem.BEM_PREC_FP64, max_iters=max_iters)
-            nconv += sum(1 for i in info if i["status"] != 0)
+            infos += bem.bem_solve(ctx, tree, r["green"], r["k"], chid[j:j + 1], phid[j:j + 1],
+                                   precision=bem.BEM_PREC_FP64, max_iters=max_iters,
+                                   max_seconds=max(1e-3, max_seconds - (time.perf_counter() - t_b)))
         torch.cuda.synchronize()
-        lat_base.append(time.perf_counter() - t1)
-        if len(lat_base) % 8 == 0:
-            print(f"serving: {len(lat_base)} of {count} requests solved one at a time", file=sys.stderr, flush=True)
-    dtb = time.perf_counter() - t0
-    out["baseline_fp64_solves_per_s"] = total_rhs / dtb
-    out["baseline_not_converged"] = nconv
-    out["baseline_latency_ms"] = {"p50": float(np.percentile(lat_base, 50) * 1e3),
-                                  "p99": float(np.percentile(lat_base, 99) * 1e3),
-                                  "note": "back to back, no queue: service time per request"}
+        service.append(time.perf_counter() - t1)
+        bres.append((0, None, infos, 0.0))
+        if len(service) % max(8, len(base) // 10) == 0:
+            print(f"{label}: {len(service)} of {len(base)} requests solved one at a time", file=sys.stderr,
+                  flush=True)
+    service = np.array(service)
+    brhs = sum(r["nrhs"] for r in base)
+    out["baseline_requests"] = len(base)
+    out["baseline_fp64_solves_per_s"] = brhs / service.sum()
+    out["baseline"] = summary(bres)
+    out["baseline_service_ms"] = {"p50": float(np.percentile(service, 50) * 1e3),
+                                  "p99": float(np.percentile(service, 99) * 1e3)}
+    for ol in out["open_loop"]:
+        arr = arrivals[:len(base)] / ol["rate_requests_per_s"]
+        done, lat = 0.0, []
+        for a_, s_ in zip(arr, service):
+            done = max(a_, done) + s_
+            lat.append(done - a_)
+        ol["baseline_latency_ms"] = {"p50": float(np.percentile(lat, 50) * 1e3),
+                                     "p99": float(np.percentile(lat, 99) * 1e3),
+                                     "note": "FP64 service times, first come first served, same arrivals"}
+    # throughput over the same requests on both sides when the baseline covers them all
     out["speedup_solves_per_s"] = out["served_solves_per_s"] / out["baseline_fp64_solves_per_s"]
     for tr in trees.values():
         tr.close()
     for m in meshes_dev.values():
         m.close()
     return out
-
-
-def _bucket_top(k):
-    """Top of the server's wavenumber bucket of k: 2^(ceil(4 log2 k) / 4)."""
-    return float(2.0 ** (np.ceil(4.0 * np.log2(k) - 1e-12) / 4.0))
 
 
 def cpu_baseline(m, x_np, seconds, fmm=True, B=48, theta=0.5):

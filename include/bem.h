@@ -123,6 +123,20 @@ const char *bem_last_error(const bem_ctx *ctx);
 #define BEM_NPHASE 11
 int bem_ctx_timing(bem_ctx *ctx, int enable, double *ms, int64_t *launches);
 
+/* Autotuning of the fast product's launch choices (tile shapes that change
+ * its speed but not its results, bit for bit: the near field's blocks per CU
+ * while the far field runs beside it, the waves per multipole-to-local
+ * block).  With enable = 1 (the default) the first product of a shape class
+ * (Green's function, precision, layer, and the near-field pair and
+ * interaction counts on a grid of factors sqrt(2)) times the candidates on
+ * its own input and keeps the fastest in a table of the process shared by
+ * all contexts; enable = 0 uses the tuned choice where one exists and the
+ * defaults otherwise, without tuning; enable = 2 empties the process's table
+ * (every shape class is tuned again) and turns tuning on.  *classes (may be
+ * NULL) receives the number of shape classes tuned so far.  BEM_EINVAL for
+ * other values. */
+int bem_ctx_autotune(bem_ctx *ctx, int enable, int64_t *classes);
+
 /* Device bytes the library holds through this context for meshes, trees and
  * work buffers (live), and the largest such figure since the context was
  * created or since the last call with reset_peak = 1 (peak: the memory a
@@ -183,6 +197,10 @@ typedef struct {
                                element fields of bem_tree_export then describe element pieces
                                (the part of an element in one leaf's basis functions).
                                0: owned elements and targets only */
+    int m2l_slab_slots;     /* interaction-list slots whose multipole-to-local results a product
+                               holds at once: the translations run slab by slab over runs of
+                               target boxes, which bounds the product's work space (176 values
+                               per slot); 0 -> 2^20 */
 } bem_tree_opts;
 
 /* Builds the octree over the mesh on the device (Section 3.1): element keys

@@ -29,7 +29,8 @@ BEM_PREC_FP64, BEM_PREC_MIXED = 0, 1
 BEM_KRYLOV_GMRES, BEM_KRYLOV_BICGSTAB = 0, 1
 
 EXPORTED = [
-    "bem_ctx_create", "bem_ctx_destroy", "bem_ctx_timing", "bem_ctx_device_bytes", "bem_last_error", "bem_mesh_load", "bem_mesh_dofs", "bem_mesh_free",
+    "bem_ctx_create", "bem_ctx_destroy", "bem_ctx_timing", "bem_ctx_autotune", "bem_ctx_device_bytes", "bem_last_error",
+    "bem_mesh_load", "bem_mesh_dofs", "bem_mesh_free",
     "bem_tree_build", "bem_tree_export", "bem_tree_free", "bem_tree_stats_get", "bem_matvec", "bem_matvec_noalloc",
     "bem_solve", "bem_field",
     "bem_server_create", "bem_server_add_mesh", "bem_server_mesh_dofs", "bem_server_submit", "bem_server_poll",
@@ -59,7 +60,7 @@ class _MeshOpts(ctypes.Structure):
 class _TreeOpts(ctypes.Structure):
     _fields_ = [("max_elems_per_leaf", ctypes.c_int), ("order", ctypes.c_int), ("theta", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("max_depth", ctypes.c_int), ("k_hint", ctypes.c_double),
-                ("order_min", ctypes.c_int), ("attach_radii", ctypes.c_int)]
+                ("order_min", ctypes.c_int), ("attach_radii", ctypes.c_int), ("m2l_slab_slots", ctypes.c_int)]
 
 
 class _TreeView(ctypes.Structure):
@@ -137,6 +138,7 @@ def load_library(path: str = LIB_PATH):
     L.bem_ctx_destroy.restype = None
     L.bem_ctx_timing.argtypes = [vp, i32, vp, vp]
     L.bem_ctx_device_bytes.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.bem_ctx_autotune.argtypes = [vp, i32, ctypes.POINTER(i64)]
     L.bem_last_error.argtypes = [vp]
     L.bem_last_error.restype = ctypes.c_char_p
     L.bem_mesh_load.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(_MeshOpts), ctypes.POINTER(vp)]
@@ -222,6 +224,15 @@ class Context:
         self.check(self.L.bem_ctx_timing(self.h, int(mode), _np_ptr(ms), _np_ptr(n)), "bem_ctx_timing")
         return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(self.PHASES)}
 
+    def autotune(self, enable=True, forget=False):
+        """Turns the launch-choice autotuner on or off for this context
+        (forget: first empty the process's table of tuned shape classes, and
+        turn it on); returns the number of shape classes tuned so far."""
+        n = ctypes.c_int64()
+        mode = 2 if forget else int(bool(enable))
+        self.check(self.L.bem_ctx_autotune(self.h, mode, ctypes.byref(n)), "bem_ctx_autotune")
+        return n.value
+
     def device_bytes(self, reset_peak=False):
         """(live, peak) device bytes held by the library through this context."""
         live, peak = ctypes.c_int64(), ctypes.c_int64()
@@ -284,9 +295,9 @@ class Mesh:
 
 class Tree:
     def __init__(self, ctx: Context, mesh: Mesh, B=32, order=8, theta=0.5, kappa=0.0, max_depth=21, k_hint=0.0,
-                 order_min=0, attach_radii=False):
+                 order_min=0, attach_radii=False, m2l_slab_slots=0):
         self.ctx, self.mesh = ctx, mesh
-        opts = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min, int(attach_radii))
+        opts = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min, int(attach_radii), int(m2l_slab_slots))
         h = ctypes.c_void_p()
         ctx.check(ctx.L.bem_tree_build(ctx.h, mesh.h, ctypes.byref(opts), ctypes.byref(h)), "bem_tree_build")
         self.h = h

@@ -131,6 +131,14 @@ int bem_ctx_timing(bem_ctx *ctx, int enable, double *ms, int64_t *launches) {
     return BEM_OK;
 }
 
+int bem_ctx_autotune(bem_ctx *ctx, int enable, int64_t *classes) {
+    if (!ctx || enable < 0 || enable > 2) return BEM_EINVAL;
+    if (enable == 2) bem::forget_tuned_classes();
+    ctx->c.autotune = enable != 0;
+    if (classes) *classes = bem::tuned_classes();
+    return BEM_OK;
+}
+
 int bem_ctx_device_bytes(bem_ctx *ctx, int reset_peak, int64_t *live, int64_t *peak) {
     if (!ctx) return BEM_EINVAL;
     Ctx &c = ctx->c;
@@ -220,6 +228,8 @@ int bem_tree_build(bem_ctx *ctx, const bem_mesh *mesh, const bem_tree_opts *opts
             BEM_REQUIRE(opts->attach_radii >= 0 && opts->attach_radii <= 2, BEM_EINVAL, "attach_radii must be 0, 1 or 2");
             t->attach = opts->attach_radii != 0;
             t->literal = opts->attach_radii == 2;
+            BEM_REQUIRE(opts->m2l_slab_slots >= 0, BEM_EINVAL, "m2l_slab_slots must be >= 0");
+            if (opts->m2l_slab_slots > 0) t->m2l_slab = opts->m2l_slab_slots;
         }
         BEM_REQUIRE(t->order_min >= 0, BEM_EINVAL, "order_min must be >= 0");
         if (t->order_min >= t->order) t->order_min = 0;

@@ -53,6 +53,7 @@ struct Ctx {
     // sequence number of its product.
     int timing = 0;
     int64_t prod_seq = 0;  // products started on this context
+    bool autotune = true;  // tune the launch choices of an untuned shape class on its first product
     double phase_ms[BEM_NPHASE] = {0};
     int64_t phase_n[BEM_NPHASE] = {0};
     std::vector<hipEvent_t> events;

@@ -23,7 +23,11 @@
 //   L2P        local expansion at each target of each leaf
 //   P2P        7-point sums over the near-list boxes' points, tiles in LDS
 //   correction sparse (accurate - 7-point) terms, free term, combination (FP64)
+#include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <unordered_map>
 
@@ -70,7 +74,6 @@ __global__ void k_strength(const XV *x, int64_t n_dof, const int32_t *se_dofs, c
 constexpr int P2P_BS = 256;
 constexpr int P2P_TILE = 256;
 constexpr int P2P_CH = 256;  // near-list entries per chunk
-constexpr int P2P_PER_CU = 4;  // near-field blocks per CU while the far field runs beside it
 #ifndef P2P_TPL
 #define P2P_TPL 4  // targets per lane
 #endif
@@ -782,7 +785,7 @@ void direct_regular_unit_double_layer(bem_tree &t, double *out) {
 namespace {
 
 template <class V, class R, class XV, bool HELM>
-void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x, XV *y) {
+void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x, XV *y, const LaunchChoice &lc) {
     Ctx &c = *t.ctx;
     const bool dbl = (op == BEM_OP_K || op == BEM_OP_A);
     const int64_t nq = t.n_q, nt = t.n_tgt;
@@ -799,7 +802,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         fmm_tables(t);
         plan_fmm(t);
         build_pass_tables(t);
-        m2l_prepare<V, R>(t, *pl);
+        m2l_prepare<V, R>(t, *pl, lc.m2l_waves);
     }
     // moments and locals of the fast product in one buffer, cleared by the strength launch
     V *mom = nullptr, *loc = nullptr;
@@ -835,21 +838,22 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
             p2p_part = part;
         }
         // While it runs beside the far field, the near-field kernel asks for
-        // enough LDS that at most P2P_PER_CU of its blocks share a CU, which
-        // leaves registers and wave slots for the far-field kernels (their
-        // matrix-core and latency-bound work then overlaps its VALU work).
+        // enough LDS that at most lc.p2p_per_cu of its blocks share a CU,
+        // which leaves registers and wave slots for the far-field kernels
+        // (their matrix-core and latency-bound work then overlaps its VALU
+        // work); 0 asks for no more than the kernel's own LDS.
         auto near_lds = [&](const void *fn) -> unsigned {
-            static thread_local std::unordered_map<const void *, unsigned> memo;  // per kernel (one device model)
-            auto it = memo.find(fn);
+            if (lc.p2p_per_cu <= 0) return 0u;
+            static thread_local std::map<std::pair<const void *, int>, unsigned> memo;  // per kernel (one device model)
+            const auto key = std::make_pair(fn, lc.p2p_per_cu);
+            auto it = memo.find(key);
             if (it != memo.end()) return it->second;
             hipFuncAttributes fa;
             BEM_HIP(hipFuncGetAttributes(&fa, fn));
             int lds = 0;
             BEM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c.device));
-            // (three for the complex kernels, whose blocks are heavier: measured)
-            const long per_cu = HELM ? P2P_PER_CU - 1 : P2P_PER_CU;
-            const long pad = (long)lds / per_cu - (long)fa.sharedSizeBytes - 256;
-            return memo[fn] = pad > 0 ? (unsigned)pad : 0u;
+            const long pad = (long)lds / lc.p2p_per_cu - (long)fa.sharedSizeBytes - 256;
+            return memo[key] = pad > 0 ? (unsigned)pad : 0u;
         };
         auto near_field = [&](hipStream_t st) {
             dim3 g((unsigned)t.n_p2p_units, nrhs);
@@ -896,7 +900,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
             c.fork();
             near_field(side);
         }
-        m2l_apply<V, R>(t, *pl, nrhs, mom, loc);
+        m2l_apply<V, R>(t, *pl, nrhs, mom, loc, lc.m2l_waves);
         // downward pass
         l2l_apply<V, R>(t, nrhs, loc);
         c.mark(4);
@@ -924,6 +928,52 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
 
 }  // namespace
 
+// ---------------------------------------------------------------- launch choices
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::array<int64_t, 5>, LaunchChoice> g_tuned;  // shape class -> fastest launch choice
+
+// Shape class of a fast product: Green's function, precision, layer, and the
+// near-field pair and interaction-slot counts on a grid of factors sqrt(2).
+std::array<int64_t, 5> shape_class(const bem_tree &t, int green, int prec, int op) {
+    auto b = [](int64_t v) { return (int64_t)std::lround(2.0 * std::log2((double)std::max<int64_t>(1, v))); };
+    const bool dbl = op == BEM_OP_K || op == BEM_OP_A;
+    return {green, prec == BEM_PREC_MIXED ? 1 : 0, dbl ? 1 : 0, b(t.n_p2p_pairs), b(t.n_inter)};
+}
+
+LaunchChoice default_choice(int green, int prec) {
+    LaunchChoice lc;
+    // complex near-field blocks are heavier: three per CU (measured)
+    if (green == BEM_HELMHOLTZ) lc.p2p_per_cu = 3;
+    (void)prec;
+    return lc;
+}
+
+template <class V, class R, class XV, bool HELM>
+void run_with(bem_tree &t, double k, int op, int method, int nrhs, const void *x, void *y, const LaunchChoice &lc) {
+    run_matvec<V, R, XV, HELM>(t, k, op, method, nrhs, (const XV *)x, (XV *)y, lc);
+}
+
+}  // namespace
+
+int64_t tuned_classes() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return (int64_t)g_tuned.size();
+}
+
+void forget_tuned_classes() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+}
+
+LaunchChoice launch_choice(const bem_tree &t, int green, int prec, int op, bool *tuned) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(shape_class(t, green, prec, op));
+    if (tuned) *tuned = it != g_tuned.end();
+    return it != g_tuned.end() ? it->second : default_choice(green, prec);
+}
+
 bool product_ready(const bem_tree &t, int green, double k, int op, int method, int prec) {
     if (green == BEM_LAPLACE) k = 0.0;
     bool corr = false;
@@ -933,8 +983,9 @@ bool product_ready(const bem_tree &t, int green, double k, int op, int method, i
     if (!t.tables || t.tables->p != t.order || !t.planned || !t.pass.built) return false;
     // the near field runs on the context's second stream, created by the first product
     if (t.n_p2p_items && !t.ctx->side) return false;
+    const LaunchChoice lc = launch_choice(t, green, prec, op, nullptr);
     for (auto &pl : t.m2l)
-        if (pl->green == green && pl->k == k) return m2l_ready(*pl, prec);
+        if (pl->green == green && pl->k == k) return m2l_ready(*pl, prec, lc.m2l_waves);
     return false;
 }
 
@@ -945,18 +996,71 @@ void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int 
         c.sync();
         c.collect();
     }
-    if (green == BEM_HELMHOLTZ) {
-        using XV = cx<double>;
-        if (prec == BEM_PREC_FP64 || method == BEM_DIRECT)
-            run_matvec<cx<double>, double, XV, true>(t, k, op, method, nrhs, (const XV *)x, (XV *)y);
-        else
-            run_matvec<cx<float>, float, XV, true>(t, k, op, method, nrhs, (const XV *)x, (XV *)y);
-    } else {
-        if (prec == BEM_PREC_FP64 || method == BEM_DIRECT)
-            run_matvec<double, double, double, false>(t, 0.0, op, method, nrhs, (const double *)x, (double *)y);
-        else
-            run_matvec<float, float, double, false>(t, 0.0, op, method, nrhs, (const double *)x, (double *)y);
+    using CD = cx<double>;
+    using CF = cx<float>;
+    const bool f64 = prec == BEM_PREC_FP64 || method == BEM_DIRECT;
+    auto run = [&](const LaunchChoice &lc) {
+        if (green == BEM_HELMHOLTZ) {
+            if (f64) run_with<CD, double, CD, true>(t, k, op, method, nrhs, x, y, lc);
+            else run_with<CF, float, CD, true>(t, k, op, method, nrhs, x, y, lc);
+        } else {
+            if (f64) run_with<double, double, double, false>(t, 0.0, op, method, nrhs, x, y, lc);
+            else run_with<float, float, double, false>(t, 0.0, op, method, nrhs, x, y, lc);
+        }
+    };
+    bool tuned = false;
+    if (method == BEM_FMM) plan_fmm(t);  // the shape class reads the plan's pair counts
+    LaunchChoice lc = method == BEM_FMM ? launch_choice(t, green, prec, op, &tuned) : LaunchChoice{};
+    if (method == BEM_FMM && !tuned && c.autotune && !c.arena && !c.timing && t.n_p2p_items) {
+        // Autotuner: the first product of an untuned shape class sets up
+        // everything with the default choice, then times candidates (event
+        // pairs on the context's stream around whole products, which end on
+        // that stream after the near field's stream has joined it; best of
+        // two each): the M2L waves per block first, then the near field's
+        // blocks per CU with the best of those.  The products write y; the
+        // product proper follows with the fastest choice.
+        run(lc);
+        hipEvent_t e0, e1;
+        BEM_HIP(hipEventCreate(&e0));
+        BEM_HIP(hipEventCreate(&e1));
+        auto time_of = [&](const LaunchChoice &cand) {
+            float best = 1e30f;
+            for (int rep = 0; rep < 2; rep++) {
+                BEM_HIP(hipEventRecord(e0, c.stream));
+                run(cand);
+                BEM_HIP(hipEventRecord(e1, c.stream));
+                BEM_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                best = std::min(best, ms);
+            }
+            return best;
+        };
+        LaunchChoice best = lc;
+        float tbest = time_of(lc);
+        for (int w : {2, 8}) {
+            LaunchChoice cand = best;
+            cand.m2l_waves = w;
+            const float tm = time_of(cand);
+            if (tm < tbest) { tbest = tm; best = cand; }
+        }
+        const LaunchChoice base = best;
+        for (int pc : {2, 3, 4, 6, 0}) {
+            if (pc == base.p2p_per_cu) continue;
+            LaunchChoice cand = base;
+            cand.p2p_per_cu = pc;
+            const float tm = time_of(cand);
+            if (tm < tbest) { tbest = tm; best = cand; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned.emplace(shape_class(t, green, prec, op), best);  // a concurrent tuner's entry stays
+            lc = g_tuned[shape_class(t, green, prec, op)];
+        }
     }
+    run(lc);
 }
 
 }  // namespace bem

@@ -36,6 +36,11 @@ struct Corr {
     DBuf<double> S, K;  // [n_pairs][6] (x2 interleaved when complex): accurate - 7-point
 };
 
+// Interaction slots whose multipole-to-local results are held at once (a slab
+// of target boxes), unless the tree's options set another bound: 2^20 slots
+// of 176 complex FP64 values are 2.9 GB.
+constexpr int64_t M2L_SLAB_SLOTS = (int64_t)1 << 20;
+
 // Helmholtz wavenumbers whose corrections and M2L plans a tree keeps at once;
 // looking up another one drops the least recently used (Laplace ones stay).
 constexpr int MAX_K_CACHED = 3;
@@ -75,10 +80,12 @@ struct FmmTables {
     int nnz_m2m = 0, nnz_l2l = 0;
 };
 
-// Tasks of one wave each over the pairs of an M2L plan, for one column width.
+// Tasks of one wave each over the pairs of an M2L plan, for one column width;
+// the tasks of slab s are [slab_task0[s], slab_task0[s + 1]).
 struct M2lTasks {
     int cols = 0;
     int64_t n_task = 0;
+    std::vector<int64_t> slab_task0;
     DBuf<int32_t> task_class, task_first, task_count;
     // level-dependent order only: contraction steps of 4 and row tiles of 16
     // that cover the largest source and target orders of each task's pairs
@@ -100,7 +107,15 @@ struct M2lPlan {
     DBuf<int32_t> pair_mom;           // canonical moment vector (source box, symmetry) of each pair
     int64_t n_u = 0;                  // used (source box, symmetry) combinations
     DBuf<int32_t> u_src, u_sym;
-    std::vector<int32_t> h_class_order, h_class_first, h_class_count;  // classes, largest first
+    // Pairs grouped by slab (a run of target boxes whose interaction slots
+    // fit M2L_SLAB_SLOTS, so that the per-pair results of one slab at a time
+    // bound the work space), then by class, largest first: group i is class
+    // h_class_order[i] of slab h_group_slab[i], pairs [first, first + count)
+    std::vector<int32_t> h_class_order, h_class_first, h_class_count, h_group_slab;
+    // slab s: interaction slots [slab_slot0[s], slab_slot0[s + 1]) and target
+    // boxes m2l_boxes[slab_box0[s] .. slab_box0[s + 1])
+    std::vector<int64_t> slab_slot0, slab_box0;
+    int64_t slab_max_slots = 0;
     bool var = false;                 // level-dependent order: per-pair steps and row tiles below
     std::vector<int32_t> h_pair_kt, h_pair_mt;
     std::vector<std::unique_ptr<M2lTasks>> tasks;
@@ -135,6 +150,17 @@ struct LevelP {
     int32_t P[MAXLEV + 1];
 };
 
+// Launch choices of the fast product that change its speed but not its
+// arithmetic (every sum runs over the same terms in the same order whatever
+// they are): the near field's blocks per CU while it runs beside the far
+// field (0: as many as fit) and the waves per M2L block.  The autotuner times
+// candidates on the first product of each shape class and keeps the fastest
+// (one table per process, shared by all contexts and trees).
+struct LaunchChoice {
+    int p2p_per_cu = 4;
+    int m2l_waves = 4;
+};
+
 // Per-matvec work buffers, grown on demand and kept on the tree.
 struct Work {
     DBuf<char> strength, mom, loc, yacc, m2l_out, m2l_mom, p2p_part;
@@ -167,6 +193,7 @@ struct bem_tree {
     bool attach = false;  // leaf radii over the elements attached to the leaf's target nodes
     bool literal = false; // the paper's tree read literally: DOF sources, B counting DOFs (attach too)
     double theta = 0.5, kappa = 0.0, k_hint = 0.0;
+    int64_t m2l_slab = bem::M2L_SLAB_SLOTS;  // interaction slots whose M2L results are held at once
     int64_t n_box = 0, n_leaf = 0, n_near = 0, n_inter = 0, n_el = 0, n_tgt = 0, n_q = 0;
     int max_level = 0;
     double corner[3] = {0, 0, 0}, side = 0;
@@ -279,6 +306,11 @@ void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int 
 // product with the same arguments built them), so that it allocates nothing
 // beyond its work space
 bool product_ready(const bem_tree &t, int green, double k, int op, int method, int prec);
+// the launch choice of a fast product of this tree (tuned or default), and
+// the number of shape classes tuned so far in this process
+LaunchChoice launch_choice(const bem_tree &t, int green, int prec, int op, bool *tuned);
+int64_t tuned_classes();
+void forget_tuned_classes();
 
 // passes.hip
 void build_pass_tables(bem_tree &t);
@@ -292,10 +324,10 @@ void l2l_apply(bem_tree &t, int nrhs, V *loc);
 // m2l.hip
 M2lPlan &get_m2l_plan(bem_tree &t, int green, double k);
 template <class V, class R>
-void m2l_prepare(bem_tree &t, M2lPlan &pl);
-bool m2l_ready(const M2lPlan &pl, int prec);  // operators and tasks of precision prec exist
+void m2l_prepare(bem_tree &t, M2lPlan &pl, int waves);
+bool m2l_ready(const M2lPlan &pl, int prec, int waves);  // operators and tasks of precision prec exist
 template <class V, class R>
-void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc);
+void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int waves);
 
 // field.hip
 void field(bem_tree &t, int green, double k, double theta, int nrhs, const void *phi, const void *chi, int64_t n_pts,

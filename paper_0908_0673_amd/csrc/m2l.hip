@@ -41,6 +41,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <type_traits>
 #include <unordered_map>
 
 #include "greens.h"
@@ -145,6 +146,7 @@ struct M2lArgs {
 
     double side;
     int P;
+    int64_t slot0;  // first interaction slot of the slab: results go to out[slot - slot0]
 };
 
 // Moments in the canonical frame of each used (source box, symmetry)
@@ -176,14 +178,15 @@ __global__ void k_m2l_canonical_moments(int64_t n_u, const int32_t *u_src, const
     }
 }
 
-// Blocks of M2L_WAVES waves share one class: the class's expanded operator
+// Blocks of W waves share one class: the class's expanded operator
 // streams through a double-buffered LDS ring in chunks of KC contraction
 // steps (coalesced 16-byte loads, one chunk ahead, one barrier per chunk), and
 // every wave reads its A operands from there for its own 16 pair columns, so
 // each operator byte is fetched once per block rather than once per wave.
 // The B operands (the columns' canonical moments) stream per wave through a
-// register ring NB steps ahead.
-constexpr int M2L_WAVES = 4;
+// register ring NB steps ahead.  W (2, 4 or 8 waves per block) is a launch
+// choice the product's autotuner makes per shape class; it does not change the
+// arithmetic (each column's sums run over the same steps in the same order).
 constexpr int M2L_NB = 8;
 
 // Row split: with MS = 2 the block's waves pair up, each computing half of
@@ -194,13 +197,13 @@ constexpr int m2l_ms() {
     return sizeof(R) * NA >= 8 ? 2 : 1;
 }
 
-template <class R, int NA>
+template <class R, int NA, int W>
 struct M2lChunk {
     static constexpr int KC = sizeof(R) * NA == 4 ? 6 : (sizeof(R) * NA == 8 ? 3 : 2);
     static constexpr int NCH = KT / KC;
     static constexpr int CE = KC * MT * 64;                     // values per chunk and plane
     static constexpr int U4 = CE * NA * (int)sizeof(R) / 16;    // 16-byte pieces per chunk
-    static constexpr int PER = (U4 + 64 * M2L_WAVES - 1) / (64 * M2L_WAVES);
+    static constexpr int PER = (U4 + 64 * W - 1) / (64 * W);
     static_assert(KT % KC == 0, "chunks must tile the contraction");
 };
 
@@ -212,11 +215,11 @@ struct M2lChunk {
 // sources' coefficients (the moments past them are zero, so the skipped
 // products add nothing) and computes and stores only the row tiles that
 // cover its targets' coefficients (the reduction reads no other row).
-template <class R, int NA, bool VAR>
-__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, const R *Mc, R *out) {
+template <class R, int NA, bool VAR, int W>
+__global__ void __launch_bounds__(64 * W) k_m2l(M2lArgs a, const R *T, const R *Mc, R *out) {
     far_field_priority();
     using V4 = typename vec4<R>::type;
-    using CK = M2lChunk<R, NA>;
+    using CK = M2lChunk<R, NA, W>;
     constexpr int KC = CK::KC, NCH = CK::NCH, CE = CK::CE, U4 = CK::U4, PER = CK::PER, NB = M2L_NB;
     constexpr int MS = m2l_ms<R, NA>(), MTH = (MT + MS - 1) / MS;
     __shared__ __align__(16) R As[2][NA * CE];
@@ -238,14 +241,14 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, c
     auto fetch = [&](int ch, uint4 (&r)[PER]) {
 #pragma unroll
         for (int i = 0; i < PER; i++) {
-            const int x = min(tid + 64 * M2L_WAVES * i, U4 - 1);
+            const int x = min(tid + 64 * W * i, U4 - 1);
             const int q = x / (U4 / NA), off = x % (U4 / NA);
             r[i] = Tg[(int64_t)q * (TSZ * (int)sizeof(R) / 16) + (int64_t)ch * (U4 / NA) + off];
         }
     };
     auto stash = [&](int buf, const uint4 (&r)[PER]) {
 #pragma unroll
-        for (int i = 0; i < PER; i++) ((uint4 *)As[buf])[min(tid + 64 * M2L_WAVES * i, U4 - 1)] = r[i];
+        for (int i = 0; i < PER; i++) ((uint4 *)As[buf])[min(tid + 64 * W * i, U4 - 1)] = r[i];
     };
     uint4 r[PER];
     fetch(0, r);
@@ -284,7 +287,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, c
     const R scale = (R)ldexp(1.0 / a.side, a.level[p < cnt ? a.pair_src[first + p] : 0]);  // 1 / rho_s
     if constexpr (NA == 1) {
         if (p < cnt) {
-            R *o = out + (int64_t)a.pair_slot[first + p] * OUT_LD;
+            R *o = out + ((int64_t)a.pair_slot[first + p] - a.slot0) * OUT_LD;
 #pragma unroll
             for (int j = 0; j < MTH; j++)
                 if ((MS == 1 || mt0 + j < MT) && (!VAR || mt0 + j < mtn))
@@ -294,7 +297,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l(M2lArgs a, const R *T, c
     } else {
         // lane with column < 8 holds Tr.Mr and Ti.Mr of its pair; lane ^ 8 holds Tr.Mi and Ti.Mi
         const bool store = col < 8 && p < cnt;
-        cx<R> *o = (cx<R> *)out + (int64_t)(store ? a.pair_slot[first + p] : 0) * OUT_LD;
+        cx<R> *o = (cx<R> *)out + (store ? (int64_t)a.pair_slot[first + p] - a.slot0 : 0) * OUT_LD;
 #pragma unroll
         for (int j = 0; j < MTH; j++)
             if ((MS == 1 || mt0 + j < MT) && (!VAR || mt0 + j < mtn))
@@ -323,7 +326,7 @@ constexpr int RED_RU = 6;    // slots per wave in flight
 template <class V>
 __global__ void __launch_bounds__(256) k_m2l_reduce(const int32_t *boxes, const int64_t *iptr, const int32_t *slot_sym,
                                                     const int16_t *sym_red, int P, const int32_t *level, LevelP lp,
-                                                    const V *out, V *loc) {
+                                                    int64_t slot0, const V *out, V *loc) {
     far_field_priority();
     __shared__ __align__(16) int16_t tab[NSYM * OUT_LD];
     __shared__ int32_t ssym[RED_CH];
@@ -351,7 +354,7 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(const int32_t *boxes, const 
                     const int i = lane + 64 * r;
                     const int e = (j < ns && i < Pt) ? tab[g * OUT_LD + i] : 0;
                     sg[k][r] = (j < ns && i < Pt) ? ((e & 0x100) ? -1 : 1) : 0;
-                    v[k][r] = out[(cb + min(j, ns - 1)) * OUT_LD + (e & 0xff)];
+                    v[k][r] = out[(cb + min(j, ns - 1) - slot0) * OUT_LD + (e & 0xff)];
                 }
             }
 #pragma unroll
@@ -510,26 +513,63 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
             msym[cl].swap(s2);
             mlev[cl].swap(l2);
         }
-    // pairs grouped by class, largest class first
+    // slabs: runs of consecutive target boxes (the reduction's boxes) whose
+    // interaction slots fit t.m2l_slab (a box with more forms a slab alone)
+    std::vector<int32_t> box_slab(t.n_box, -1);
+    {
+        int64_t s0 = -1, nb = 0;
+        for (int64_t b = 0; b < t.n_box; b++) {
+            if (t.h_te[b] == t.h_tb[b] || t.h_inter_ptr[b + 1] == t.h_inter_ptr[b]) continue;
+            if (s0 < 0 || t.h_inter_ptr[b + 1] - s0 > t.m2l_slab) {
+                s0 = t.h_inter_ptr[b];
+                pl->slab_slot0.push_back(s0);
+                pl->slab_box0.push_back(nb);
+            }
+            box_slab[b] = (int32_t)pl->slab_slot0.size() - 1;
+            nb++;
+        }
+        pl->slab_slot0.push_back(t.n_inter);
+        pl->slab_box0.push_back(nb);
+        if (pl->slab_slot0.size() == 1) pl->slab_slot0.insert(pl->slab_slot0.begin(), 0);  // no pairs: one empty slab
+        if (pl->slab_box0.size() == 1) pl->slab_box0.insert(pl->slab_box0.begin(), 0);
+        for (size_t sl = 0; sl + 1 < pl->slab_slot0.size(); sl++) {
+            // the slab's slots end where its last box's list ends
+            int64_t end = pl->slab_slot0[sl];
+            for (int64_t b = 0; b < t.n_box; b++)
+                if (box_slab[b] == (int32_t)sl) end = t.h_inter_ptr[b + 1];
+            pl->slab_max_slots = std::max(pl->slab_max_slots, end - pl->slab_slot0[sl]);
+        }
+    }
+    const int n_slab = (int)pl->slab_slot0.size() - 1;
+    // slot -> target box (for the slab of each pair)
+    std::vector<int32_t> slot_box(std::max<int64_t>(1, t.n_inter), -1);
+    for (int64_t b = 0; b < t.n_box; b++)
+        for (int64_t j = t.h_inter_ptr[b]; j < t.h_inter_ptr[b + 1]; j++) slot_box[j] = (int32_t)b;
+    // pairs grouped by slab, then by class, largest class first
     std::vector<int32_t> order(members.size());
     for (size_t i = 0; i < order.size(); i++) order[i] = (int32_t)i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t x, int32_t y) { return members[x].size() > members[y].size(); });
     std::vector<int32_t> slot, src, sym;
-    for (int32_t cl : order) {
-        pl->h_class_order.push_back(cl);
-        pl->h_class_first.push_back((int32_t)slot.size());
-        pl->h_class_count.push_back((int32_t)members[cl].size());
-        for (size_t i = 0; i < members[cl].size(); i++) {
-            slot.push_back(members[cl][i]);
-            src.push_back(t.h_inter_idx[members[cl][i]]);
-            sym.push_back(msym[cl][i]);
-            if (pl->var) {
-                pl->h_pair_kt.push_back((lp.P[t.h_level[src.back()]] + 3) / 4);
-                pl->h_pair_mt.push_back((lp.P[mlev[cl][i]] + 15) / 16);
+    for (int sl = 0; sl < n_slab; sl++)
+        for (int32_t cl : order) {
+            const int32_t first = (int32_t)slot.size();
+            for (size_t i = 0; i < members[cl].size(); i++) {
+                if (n_slab > 1 && box_slab[slot_box[members[cl][i]]] != sl) continue;
+                slot.push_back(members[cl][i]);
+                src.push_back(t.h_inter_idx[members[cl][i]]);
+                sym.push_back(msym[cl][i]);
+                if (pl->var) {
+                    pl->h_pair_kt.push_back((lp.P[t.h_level[src.back()]] + 3) / 4);
+                    pl->h_pair_mt.push_back((lp.P[mlev[cl][i]] + 15) / 16);
+                }
             }
+            if ((int32_t)slot.size() == first) continue;
+            pl->h_class_order.push_back(cl);
+            pl->h_class_first.push_back(first);
+            pl->h_class_count.push_back((int32_t)slot.size() - first);
+            pl->h_group_slab.push_back(sl);
         }
-    }
     pl->n_pairs = (int64_t)slot.size();
     auto up = [&](DBuf<int32_t> &d, const std::vector<int32_t> &v) {
         d.alloc(&c, std::max<size_t>(1, v.size()));
@@ -594,53 +634,70 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
 
 namespace {
 
-// Tasks of `cols` pairs: each class, largest first, goes to the least-loaded
-// of the 8 XCD queues, and the queues are interleaved so that block i runs
-// on XCD i mod 8.  Padding tasks have no pairs.
+// Tasks of `cols` pairs, slab by slab: within a slab each class, largest
+// first, goes to the least-loaded of the 8 XCD queues, and the queues are
+// interleaved so that block i of the slab's launch runs on XCD i mod 8.
+// Padding tasks have no pairs.
 M2lTasks &get_tasks(Ctx &c, M2lPlan &pl, int cols) {
     for (auto &tk : pl.tasks)
         if (tk->cols == cols) return *tk;
     constexpr int NXCD = 8;
-    std::vector<std::vector<int32_t>> qc(NXCD), qf(NXCD), qn(NXCD), qk(NXCD), qm(NXCD);
-    std::vector<int64_t> load(NXCD, 0);
-    for (size_t i = 0; i < pl.h_class_order.size(); i++) {
-        const int32_t cl = pl.h_class_order[i], f0 = pl.h_class_first[i], n = pl.h_class_count[i];
-        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        for (int32_t o = 0; o < n; o += cols) {
-            qc[x].push_back(cl);
-            qf[x].push_back(f0 + o);
-            qn[x].push_back(std::min(cols, n - o));
-            if (pl.var) {
-                int32_t kt = 0, mt = 0;
-                for (int32_t i = f0 + o; i < f0 + o + qn[x].back(); i++) {
-                    kt = std::max(kt, pl.h_pair_kt[i]);
-                    mt = std::max(mt, pl.h_pair_mt[i]);
-                }
-                qk[x].push_back(kt);
-                qm[x].push_back(mt);
-            }
-            load[x]++;
-        }
-    }
-    size_t qmax = 0;
-    for (int x = 0; x < NXCD; x++) qmax = std::max(qmax, qc[x].size());
-    std::vector<int32_t> tc(qmax * NXCD, 0), tf(qmax * NXCD, 0), tn(qmax * NXCD, 0), tkt, tmt;
-    if (pl.var) {
-        tkt.assign(qmax * NXCD, 0);
-        tmt.assign(qmax * NXCD, 0);
-    }
-    for (int x = 0; x < NXCD; x++)
-        for (size_t i = 0; i < qc[x].size(); i++) {
-            tc[i * NXCD + x] = qc[x][i];
-            tf[i * NXCD + x] = qf[x][i];
-            tn[i * NXCD + x] = qn[x][i];
-            if (pl.var) {
-                tkt[i * NXCD + x] = qk[x][i];
-                tmt[i * NXCD + x] = qm[x][i];
-            }
-        }
+    std::vector<int32_t> tc, tf, tn, tkt, tmt;
     auto tk = std::make_unique<M2lTasks>();
     tk->cols = cols;
+    // the tasks of groups [g0, g1) (one slab), appended in XCD-interleaved order
+    auto slab_tasks = [&](size_t g0, size_t g1) {
+        std::vector<std::vector<int32_t>> qc(NXCD), qf(NXCD), qn(NXCD), qk(NXCD), qm(NXCD);
+        std::vector<int64_t> load(NXCD, 0);
+        for (size_t i = g0; i < g1; i++) {
+            const int32_t cl = pl.h_class_order[i], f0 = pl.h_class_first[i], n = pl.h_class_count[i];
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            for (int32_t o = 0; o < n; o += cols) {
+                qc[x].push_back(cl);
+                qf[x].push_back(f0 + o);
+                qn[x].push_back(std::min(cols, n - o));
+                if (pl.var) {
+                    int32_t kt = 0, mt = 0;
+                    for (int32_t j = f0 + o; j < f0 + o + qn[x].back(); j++) {
+                        kt = std::max(kt, pl.h_pair_kt[j]);
+                        mt = std::max(mt, pl.h_pair_mt[j]);
+                    }
+                    qk[x].push_back(kt);
+                    qm[x].push_back(mt);
+                }
+                load[x]++;
+            }
+        }
+        size_t qmax = 0;
+        for (int x = 0; x < NXCD; x++) qmax = std::max(qmax, qc[x].size());
+        const size_t base = tc.size();
+        tc.resize(base + qmax * NXCD, 0);
+        tf.resize(base + qmax * NXCD, 0);
+        tn.resize(base + qmax * NXCD, 0);
+        if (pl.var) {
+            tkt.resize(base + qmax * NXCD, 0);
+            tmt.resize(base + qmax * NXCD, 0);
+        }
+        for (int x = 0; x < NXCD; x++)
+            for (size_t i = 0; i < qc[x].size(); i++) {
+                tc[base + i * NXCD + x] = qc[x][i];
+                tf[base + i * NXCD + x] = qf[x][i];
+                tn[base + i * NXCD + x] = qn[x][i];
+                if (pl.var) {
+                    tkt[base + i * NXCD + x] = qk[x][i];
+                    tmt[base + i * NXCD + x] = qm[x][i];
+                }
+            }
+    };
+    const int n_slab = (int)pl.slab_slot0.size() - 1;
+    size_t g = 0;  // groups are in slab order
+    for (int sl = 0; sl < n_slab; sl++) {
+        tk->slab_task0.push_back((int64_t)tc.size());
+        const size_t g0 = g;
+        while (g < pl.h_class_order.size() && pl.h_group_slab[g] == sl) g++;
+        slab_tasks(g0, g);
+    }
+    tk->slab_task0.push_back((int64_t)tc.size());
     tk->n_task = (int64_t)tc.size();
     auto up = [&](DBuf<int32_t> &d, const std::vector<int32_t> &v) {
         d.alloc(&c, std::max<size_t>(1, v.size()));
@@ -679,44 +736,42 @@ const R *expanded(bem_tree &t, M2lPlan &pl) {
     return buf.p;
 }
 
-// pairs per block: 16 real or 8 complex per column group
+// pairs per block of w waves: 16 real or 8 complex per column group
 template <class V, class R>
-constexpr int m2l_cols() {
+constexpr int m2l_cols(int w) {
     constexpr int NA = std::is_same<V, R>::value ? 1 : 2;
-    return (NA == 1 ? 16 : 8) * (M2L_WAVES / m2l_ms<R, NA>());
+    return (NA == 1 ? 16 : 8) * (w / m2l_ms<R, NA>());
 }
 
 }  // namespace
 
-bool m2l_ready(const M2lPlan &pl, int prec) {
+bool m2l_ready(const M2lPlan &pl, int prec, int waves) {
     const bool helm = pl.green == BEM_HELMHOLTZ, f32 = prec == BEM_PREC_MIXED;
     if (pl.n_class && !(f32 ? (const void *)pl.T32.p : (const void *)pl.T64.p)) return false;
-    const int cols = helm ? (f32 ? m2l_cols<cx<float>, float>() : m2l_cols<cx<double>, double>())
-                          : (f32 ? m2l_cols<float, float>() : m2l_cols<double, double>());
+    const int cols = helm ? (f32 ? m2l_cols<cx<float>, float>(waves) : m2l_cols<cx<double>, double>(waves))
+                          : (f32 ? m2l_cols<float, float>(waves) : m2l_cols<double, double>(waves));
     for (auto &tk : pl.tasks)
         if (tk->cols == cols) return true;
     return false;
 }
 
 template <class V, class R>
-void m2l_prepare(bem_tree &t, M2lPlan &pl) {
+void m2l_prepare(bem_tree &t, M2lPlan &pl, int waves) {
     expanded<R>(t, pl);
-    get_tasks(*t.ctx, pl, m2l_cols<V, R>());
+    get_tasks(*t.ctx, pl, m2l_cols<V, R>(waves));
 }
 
 template <class V, class R>
-void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc) {
+void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int waves) {
     Ctx &c = *t.ctx;
     FmmTables &T = *t.tables;
     const int P = T.P;
-    M2lTasks &tk = get_tasks(c, pl, m2l_cols<V, R>());
+    M2lTasks &tk = get_tasks(c, pl, m2l_cols<V, R>(waves));
     if (!tk.n_task || !pl.n_pairs) {
         c.mark(3);
         return;
     }
-    V *out = (V *)work_buf(c, t.work.m2l_out, sizeof(V) * (size_t)std::max<int64_t>(1, t.n_inter) * OUT_LD);
-    M2lArgs a{tk.task_class.p, tk.task_first.p, tk.task_count.p, pl.pair_slot.p, pl.pair_src.p, pl.pair_mom.p,
-              t.level.p, tk.task_kt.p, tk.task_mt.p, t.side, P};
+    V *out = (V *)work_buf(c, t.work.m2l_out, sizeof(V) * (size_t)std::max<int64_t>(1, pl.slab_max_slots) * OUT_LD);
     const LevelP lp = level_p(t);
     V *Mc = (V *)work_buf(c, t.work.m2l_mom, sizeof(V) * (size_t)std::max<int64_t>(1, pl.n_u) * KIN);
     const R *Tx = expanded<R>(t, pl);
@@ -728,28 +783,47 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc) {
         BEM_LAUNCH_CHECK();
         c.mark(10);
         constexpr int NA = std::is_same<V, R>::value ? 1 : 2;
-        c.kbegin(c.stream, 3);
-        if (pl.var)
-            k_m2l<R, NA, true><<<(unsigned)tk.n_task, 64 * M2L_WAVES, 0, c.stream>>>(a, Tx, (const R *)Mc, (R *)out);
-        else
-            k_m2l<R, NA, false><<<(unsigned)tk.n_task, 64 * M2L_WAVES, 0, c.stream>>>(a, Tx, (const R *)Mc, (R *)out);
-        BEM_LAUNCH_CHECK();
-        c.kend(c.stream);
-        c.mark(3);
-        k_m2l_reduce<V><<<(unsigned)t.n_m2l_boxes, 256, 0, c.stream>>>(t.m2l_boxes.p, t.inter_ptr.p, pl.slot_sym.p,
-                                                                       pl.sym_red.p, P, t.level.p, lp, out, l);
-        BEM_LAUNCH_CHECK();
-        c.mark(10);
+        // one slab of target boxes at a time: its pairs' results, then their sums
+        for (size_t sl = 0; sl + 1 < pl.slab_slot0.size(); sl++) {
+            const int64_t t0 = tk.slab_task0[sl], nt = tk.slab_task0[sl + 1] - t0;
+            const int64_t b0 = pl.slab_box0[sl], nb = pl.slab_box0[sl + 1] - b0;
+            M2lArgs a{tk.task_class.p + t0, tk.task_first.p + t0, tk.task_count.p + t0, pl.pair_slot.p,
+                      pl.pair_src.p, pl.pair_mom.p, t.level.p, pl.var ? tk.task_kt.p + t0 : nullptr,
+                      pl.var ? tk.task_mt.p + t0 : nullptr, t.side, P, pl.slab_slot0[sl]};
+            c.kbegin(c.stream, 3);
+            auto launch = [&](auto wv) {
+                constexpr int W = decltype(wv)::value;
+                if (pl.var)
+                    k_m2l<R, NA, true, W><<<(unsigned)nt, 64 * W, 0, c.stream>>>(a, Tx, (const R *)Mc, (R *)out);
+                else
+                    k_m2l<R, NA, false, W><<<(unsigned)nt, 64 * W, 0, c.stream>>>(a, Tx, (const R *)Mc, (R *)out);
+            };
+            if (nt > 0) {
+                if (waves == 2) launch(std::integral_constant<int, 2>());
+                else if (waves == 8) launch(std::integral_constant<int, 8>());
+                else launch(std::integral_constant<int, 4>());
+                BEM_LAUNCH_CHECK();
+            }
+            c.kend(c.stream);
+            c.mark(3);
+            if (nb > 0) {
+                k_m2l_reduce<V><<<(unsigned)nb, 256, 0, c.stream>>>(t.m2l_boxes.p + b0, t.inter_ptr.p, pl.slot_sym.p,
+                                                                    pl.sym_red.p, P, t.level.p, lp, pl.slab_slot0[sl],
+                                                                    out, l);
+                BEM_LAUNCH_CHECK();
+            }
+            c.mark(10);
+        }
     }
 }
 
-template void m2l_prepare<double, double>(bem_tree &, M2lPlan &);
-template void m2l_prepare<float, float>(bem_tree &, M2lPlan &);
-template void m2l_prepare<cx<double>, double>(bem_tree &, M2lPlan &);
-template void m2l_prepare<cx<float>, float>(bem_tree &, M2lPlan &);
-template void m2l_apply<double, double>(bem_tree &, M2lPlan &, int, const double *, double *);
-template void m2l_apply<float, float>(bem_tree &, M2lPlan &, int, const float *, float *);
-template void m2l_apply<cx<double>, double>(bem_tree &, M2lPlan &, int, const cx<double> *, cx<double> *);
-template void m2l_apply<cx<float>, float>(bem_tree &, M2lPlan &, int, const cx<float> *, cx<float> *);
+template void m2l_prepare<double, double>(bem_tree &, M2lPlan &, int);
+template void m2l_prepare<float, float>(bem_tree &, M2lPlan &, int);
+template void m2l_prepare<cx<double>, double>(bem_tree &, M2lPlan &, int);
+template void m2l_prepare<cx<float>, float>(bem_tree &, M2lPlan &, int);
+template void m2l_apply<double, double>(bem_tree &, M2lPlan &, int, const double *, double *, int);
+template void m2l_apply<float, float>(bem_tree &, M2lPlan &, int, const float *, float *, int);
+template void m2l_apply<cx<double>, double>(bem_tree &, M2lPlan &, int, const cx<double> *, cx<double> *, int);
+template void m2l_apply<cx<float>, float>(bem_tree &, M2lPlan &, int, const cx<float> *, cx<float> *, int);
 
 }  // namespace bem

@@ -810,3 +810,68 @@ def test_field_rejects_bad_arguments():
         bem.bem_field(ctx, tree, 0, 0.0, x, x, pts.float())
     u = bem.bem_field(ctx, tree, 0, 0.0, x, x, pts)  # zero densities: zero field
     assert torch.count_nonzero(u) == 0
+
+
+# ---------------------------------------------------------------- autotuned launch choices
+@pytest.mark.parametrize("green,k,prec", [(0, 0.0, 1), (0, 0.0, 0), (1, 2.0, 1)])
+def test_autotuned_products_equal_untuned_ones(green, k, prec):
+    """The autotuner picks launch choices that change the speed of the fast
+    product but not its arithmetic: on a shape class no product has tuned
+    yet, the default choice (autotuning off) and the tuned one (the first
+    product with autotuning on times every candidate) give the same bits."""
+    import paper_0908_0673_amd as bem
+
+    m = bem_inputs.icosphere(3)
+    rng = np.random.default_rng(71 + 3 * green + prec)
+    x = rng.standard_normal((2, 2562)) + (1j * rng.standard_normal((2, 2562)) if green else 0)
+    ref = None
+    for tune in (False, True):
+        ctx = bem.Context(0)
+        if not tune:
+            ctx.autotune(forget=True)  # every shape class untuned again
+        before = ctx.autotune(tune)
+        mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
+        tree = bem.bem_tree_build(ctx, mesh, B=32, order=8, theta=0.5)
+        xd = to_dev(x, green == 1)
+        yd = xd.clone()
+        bem.bem_matvec(ctx, tree, green, k, bem.BEM_OP_A, bem.BEM_FMM, prec, xd, yd)
+        after = ctx.autotune(tune)
+        y = yd.cpu().numpy()
+        say(f"  autotune={tune}: classes tuned {before} -> {after}")
+        if tune:
+            assert before == 0 and after == 1
+            assert np.array_equal(y, ref)
+        else:
+            assert before == 0 and after == 0
+            ref = y
+        tree.close()
+        mesh.close()
+        ctx.close()
+
+
+@pytest.mark.parametrize("green,k", [(0, 0.0), (1, 2.0)])
+def test_m2l_in_slabs_equals_one_slab(green, k):
+    """The multipole-to-local step runs slab by slab over runs of target boxes
+    whose interaction slots fit the tree's bound (the product's work space):
+    with many small slabs the products equal the one-slab products bit for
+    bit (each pair's translation and each box's sum are the same), and the
+    FP64 one equals the oracle's fast product."""
+    bem = _bem()
+    m, ctx, mesh, tree, om, ot = setup("sphere1280")
+    small = bem.bem_tree_build(ctx, mesh, B=32, order=8, theta=THETA, m2l_slab_slots=700)
+    cplx = green == 1
+    x = bem_inputs.random_vector(om.n_dof, 81, nrhs=2, complex_=cplx)
+    xd = to_dev(x, cplx)
+    y1, y2 = xd.clone(), xd.clone()
+    for op in (bem.BEM_OP_A, bem.BEM_OP_RHS):
+        for prec in (bem.BEM_PREC_FP64, bem.BEM_PREC_MIXED):
+            bem.bem_matvec(ctx, tree, green, k, op, bem.BEM_FMM, prec, xd, y1)
+            bem.bem_matvec(ctx, small, green, k, op, bem.BEM_FMM, prec, xd, y2)
+            assert np.array_equal(y1.cpu().numpy(), y2.cpu().numpy()), (op, prec)
+        ref = ot.fmm_matvec(x[0], op, green, k)
+        bem.bem_matvec(ctx, small, green, k, op, bem.BEM_FMM, bem.BEM_PREC_FP64, xd, y2)
+        check_product(y2.cpu().numpy()[0], ref if cplx else ref.real, 1e-11, f"slabs op={op} fp64 vs oracle fast")
+    with pytest.raises(bem.BemError) as e:
+        bem.bem_tree_build(ctx, mesh, m2l_slab_slots=-5)
+    assert e.value.code == bem.BEM_EINVAL
+    small.close()
