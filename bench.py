@@ -650,8 +650,9 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_fracs=(0.5,), 
             return srv.submit(ids[r["key"]], r["green"], r["k"], _boundary_data(dofs[r["key"]], r))
 
         if warm:
-            for t in [submit(r) for r in warm]:
+            for i, t in enumerate([submit(r) for r in warm]):
                 srv.poll(t)
+                print(f"{label}: warm-up {i + 1} of {len(warm)} served", file=sys.stderr, flush=True)
             print(f"{label}: warm-up served", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         tickets = [submit(r) for r in reqs]
@@ -659,8 +660,10 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_fracs=(0.5,), 
         for i, t in enumerate(tickets):
             rc, phi, info, lat = srv.poll(t)
             res.append((rc, None, info, lat))
-            if (i + 1) % max(8, len(reqs) // 10) == 0:
-                print(f"{label}: {i + 1} of {len(reqs)} requests served", file=sys.stderr, flush=True)
+            r = reqs[i]
+            print(f"{label}: {i + 1} of {len(reqs)} requests served at {time.perf_counter() - t0:.1f} s "
+                  f"({r['n_tri']} tri, green {r['green']}, ka {r['ka']:.2f}, nrhs {r['nrhs']}, rc {rc})",
+                  file=sys.stderr, flush=True)
         dt = time.perf_counter() - t0
         sat = len(reqs) / dt
         out["served_solves_per_s"] = total_rhs / dt
@@ -678,7 +681,13 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_fracs=(0.5,), 
                 if wait > 0:
                     time.sleep(wait)
                 tickets.append(submit(r))
-            lat = np.array([srv.poll(t)[3] for t in tickets])
+                print(f"{label}: open loop at {f}: {len(tickets)} of {len(reqs)} submitted", file=sys.stderr,
+                      flush=True)
+            lat = []
+            for i, t in enumerate(tickets):
+                lat.append(srv.poll(t)[3])
+                print(f"{label}: open loop at {f}: {i + 1} of {len(tickets)} done", file=sys.stderr, flush=True)
+            lat = np.array(lat)
             out["open_loop"].append({"rate_fraction_of_saturation": f, "rate_requests_per_s": rate,
                                      "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                                                     "p99": float(np.percentile(lat, 99) * 1e3)}})
@@ -725,9 +734,8 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_fracs=(0.5,), 
         torch.cuda.synchronize()
         service.append(time.perf_counter() - t1)
         bres.append((0, None, infos, 0.0))
-        if len(service) % max(8, len(base) // 10) == 0:
-            print(f"{label}: {len(service)} of {len(base)} requests solved one at a time", file=sys.stderr,
-                  flush=True)
+        print(f"{label}: {len(service)} of {len(base)} requests solved one at a time ({service[-1]:.2f} s)",
+              file=sys.stderr, flush=True)
     service = np.array(service)
     brhs = sum(r["nrhs"] for r in base)
     out["baseline_requests"] = len(base)
