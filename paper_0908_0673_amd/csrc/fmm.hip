@@ -142,40 +142,63 @@ template <class R> struct r4;
 template <> struct r4<float> { using type = float4; };
 template <> struct r4<double> { using type = double4; };
 
-// Kernel value times strength for one (target, source point) pair.  For
-// Laplace the source record holds (s n, s) and the 1/(4 pi) factor is applied
-// once per target by the caller; for Helmholtz it holds (n, Re s) plus Im s.
-template <class V, class R, bool DBL, bool HELM>
-__device__ inline V p2p_term(double x0, double x1, double x2, double2 sxy, double sz, typename r4<R>::type ns, R si,
-                             R k) {
-    const R d0 = (R)(x0 - sxy.x), d1 = (R)(x1 - sxy.y), d2 = (R)(x2 - sz);
+__device__ inline float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Adds the kernel value times the strength of one (target, source point)
+// pair to acc; d is the target minus the point, ns the point's record.
+// Laplace: the record holds (s n, s), so the double layer is (d . s n) / r^3
+// and the single layer s / r.  Helmholtz: the record holds (n, Re s) and Im s;
+// the value is a (u + j v) times s with a = 1/r, u + j v = e^{jkr} (single
+// layer) or a = (d . n) / r^3, u = cos kr + kr sin kr, v = sin kr - kr cos kr
+// (double layer: the normal derivative at the point of e^{jkr}/r), and the
+// complex product is accumulated by four fused multiply-adds.  The 1/(4 pi)
+// of G is applied once per target by the caller.
+template <bool DBL, bool HELM, class R, class A>
+__device__ inline void p2p_add(A &acc, R d0, R d1, R d2, typename r4<R>::type ns, R si, R k) {
     const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
     const R ir = inv_sqrt(r2);
     if constexpr (HELM) {
-        R g = (R)kInv4Pi * ir;
-        if (DBL) g = g * (d0 * ns.x + d1 * ns.y + d2 * ns.z) * ir * ir;
-        const R kr = k * r2 * ir;
+        const R kr = k * (r2 * ir);
         R sn, cs;
         sincos_turns(kr, &sn, &cs);
-        cx<R> kv = DBL ? cx<R>(g * (cs + kr * sn), g * (sn - kr * cs)) : cx<R>(g * cs, g * sn);
-        return kv * cx<R>(ns.w, si);
+        R a, u, v;
+        if (DBL) {
+            a = (d0 * ns.x + d1 * ns.y + d2 * ns.z) * (ir * ir) * ir;
+            u = fmar(kr, sn, cs);
+            v = fmar(-kr, cs, sn);
+        } else {
+            a = ir;
+            u = cs;
+            v = sn;
+        }
+        const R au = a * u, av = a * v;
+        acc.re = fmar(au, ns.w, acc.re);
+        acc.re = fmar(-av, si, acc.re);
+        acc.im = fmar(au, si, acc.im);
+        acc.im = fmar(av, ns.w, acc.im);
     } else {
-        if (DBL) return V((d0 * ns.x + d1 * ns.y + d2 * ns.z) * (ir * ir * ir));
-        return V(ns.w * ir);
+        if (DBL) acc += (d0 * ns.x + d1 * ns.y + d2 * ns.z) * (ir * ir * ir);
+        else acc += ns.w * ir;
     }
 }
 
 // One block per work item (a target leaf and up to 64 of its targets).  The
 // near-list boxes' points (contiguous runs in tree order) are split into four
 // equal shares, one per wave; each wave streams its share in batches of 64
-// points, one per lane, through its own LDS slot as packed records (FP64
-// position, normal and strength in R), loading the next batch into registers
-// while it computes the current one, so no block barrier sits inside the
-// loop.  Each lane holds TPL targets, so every LDS read serves TPL
-// interactions; lanes not needed for targets split a batch into sub-streams.
-// The target-source difference is formed in FP64 and only then rounded to R,
-// so close pairs keep their relative accuracy in the mixed path; per-batch
-// partial sums in R are added into an FP64 total.
+// points, one per lane, through its own LDS slot as packed records (position,
+// normal and strength), loading the next batch into registers while it
+// computes the current one, so no block barrier sits inside the loop.  Each
+// lane holds TPL targets, so every LDS read serves TPL interactions; lanes not
+// needed for targets split a batch into sub-streams.  The target-point
+// difference is formed in FP64 and only then rounded to R, so that close pairs
+// keep their relative accuracy in the mixed path: the double layer's
+// numerator n . d of two nearby points of a smooth surface is of the order of
+// |d|^2 / (radius of curvature), and a difference of FP32 coordinates taken
+// relative to a common origin a leaf side away (one subtraction instead of
+// two instructions per axis) puts errors of about 1e-5 into products of the
+// 20480-element sphere.  Per-batch partial sums in R are added into an FP64
+// total.
 template <class V, class R, bool DBL, bool HELM, int TPL>
 __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const int32_t *unit_item,
                                                 const int64_t *unit_f, int64_t n_unit, const int32_t *wi_box,
@@ -295,10 +318,11 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
                 const double2 cxy = sxy[wave][buf][kk];
                 const double cz = szz[wave][buf][kk];
                 const R4 cns = sns[wave][buf][kk];
-                const R csi = HELM ? ssi[wave][buf][kk] : (R)0;
+                const R csi = HELM ? ssi[wave][buf][HELM ? kk : 0] : (R)0;
 #pragma unroll
                 for (int q = 0; q < TPL; q++)
-                    acc[q] += p2p_term<V, R, DBL, HELM>(xt[q][0], xt[q][1], xt[q][2], cxy, cz, cns, csi, k);
+                    p2p_add<DBL, HELM>(acc[q], (R)(xt[q][0] - cxy.x), (R)(xt[q][1] - cxy.y), (R)(xt[q][2] - cz), cns,
+                                       csi, k);
             }
 #pragma unroll
             for (int q = 0; q < TPL; q++) tot[q] += vcast<VD>(acc[q]);
@@ -369,7 +393,7 @@ __global__ void __launch_bounds__(256) k_direct(const double *q, int64_t n_q, co
 
 // ---------------------------------------------------------------- correction + combine (FP64)
 // y(DOF of sorted target t) = the operator's combination of the far field,
-// the near-field partial sums of t's item (1/4pi applied for Laplace), the
+// the near-field partial sums of t's item (times 1/4pi), the
 // singular / near-singular corrections and, for A, the free term.  Eight
 // lanes per target share its correction pairs and meet by shuffles.  The far
 // field is either a finished value per target (yacc, direct product) or, for
@@ -379,7 +403,7 @@ __global__ void __launch_bounds__(256) k_direct(const double *q, int64_t n_q, co
 // components, which three lanes of the target form in FP64 and leave in LDS
 // in the expansion's precision; the target's eight lanes then take every
 // eighth coefficient, and the sum over lanes runs in FP64.
-template <class XV, class AV, class R, class VD, bool LAP>
+template <class XV, class AV, class R, class VD>
 __global__ void __launch_bounds__(256) k_combine(int64_t n_tgt, const int32_t *tperm, const AV *yacc,
                                                  const int32_t *tgt_leaf, const double *t64, const double *centre,
                                                  const int32_t *level, double side, const int8_t *exps, int order,
@@ -431,7 +455,7 @@ __global__ void __launch_bounds__(256) k_combine(int64_t n_tgt, const int32_t *t
             const int64_t o = t - wi_t0[w];
             VD v = VD(0.0);
             for (int32_t u = item_unit[w]; u < item_unit[w + 1]; u++) v += part[((int64_t)rhs * n_unit + u) * 64 + o];
-            if (LAP) v = v * kInv4Pi;
+            v = v * kInv4Pi;
             acc += vcast<XV>(v);
         }
         if (yacc && l8 == 0) acc += vcast<XV>(yacc[(int64_t)rhs * n_tgt + t]);
@@ -917,7 +941,7 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
     const VD *part = (const VD *)p2p_part;
     dim3 g(nblocks(8 * nt, 256), nrhs);
     const bool fmm = method == BEM_FMM;
-    k_combine<XV, V, R, VD, !HELM><<<g, 256, 0, c.stream>>>(
+    k_combine<XV, V, R, VD><<<g, 256, 0, c.stream>>>(
         nt, t.tperm.p, fmm ? nullptr : yacc, t.tgt_leaf.p, t.t64.p, t.centre.p, t.level.p, t.side,
         fmm ? t.tables->exps.p : nullptr, t.order, fmm ? loc : nullptr, fmm ? t.tables->P : 0, t.n_box,
         t.p2p_tgt_item.p, t.p2p_item_unit.p, t.p2p_t0.p, part, t.n_p2p_units, t.pair_ptr.p,

@@ -24,6 +24,18 @@ struct bem_mesh {
     bem::DBuf<int32_t> elem_dofs; // [n_el][6]
     bem::DBuf<int32_t> dof_node;  // [n_dof]
     bem::DBuf<double> dof_xyz;    // [n_dof][3]
+    // Free terms computed by trees of this mesh, one per tree hierarchy (leaf
+    // size, depth, tree kind).  Trees of one hierarchy find the same
+    // correction pairs in the same order and sum them the same way, so a
+    // later tree copies the stored one instead of repeating the all-points
+    // sum: the copy is bitwise what it would compute.  A cache (the mesh's
+    // geometry does not change), filled and read by the trees.
+    struct FreeTerm {
+        int B = 0, max_depth = 0;
+        bool attach = false, literal = false;
+        bem::DBuf<double> c;  // [n_dof], DOF order
+    };
+    mutable std::vector<std::unique_ptr<FreeTerm>> free_terms;
 };
 
 namespace bem {

@@ -381,6 +381,16 @@ Corr &get_corr(bem_tree &t, int green, double k) {
 void build_free_term(bem_tree &t) {
     if (t.has_free_term) return;
     Ctx &c = *t.ctx;
+    const bem_mesh &m = *t.mesh;
+    for (const auto &f : m.free_terms)
+        if (f->B == t.B && f->max_depth == t.max_depth && f->attach == t.attach && f->literal == t.literal) {
+            t.free_term.alloc(&c, t.n_tgt);
+            BEM_HIP(hipMemcpyAsync(t.free_term.p, f->c.p, sizeof(double) * t.n_tgt, hipMemcpyDeviceToDevice,
+                                   c.stream));
+            c.sync();
+            t.has_free_term = true;
+            return;
+        }
     Corr &lap = get_corr(t, BEM_LAPLACE, 0.0);
     DBuf<double> reg;
     reg.alloc(&c, t.n_tgt);
@@ -390,7 +400,15 @@ void build_free_term(bem_tree &t) {
     k_free_term<<<nblocks(t.n_tgt, 256), 256, 0, c.stream>>>(t.n_tgt, t.tperm.p, reg.p, t.pair_ptr.p, lap.K.p,
                                                             t.free_term.p);
     BEM_LAUNCH_CHECK();
+    auto f = std::make_unique<bem_mesh::FreeTerm>();
+    f->B = t.B;
+    f->max_depth = t.max_depth;
+    f->attach = t.attach;
+    f->literal = t.literal;
+    f->c.alloc(m.ctx ? m.ctx : &c, t.n_tgt);
+    BEM_HIP(hipMemcpyAsync(f->c.p, t.free_term.p, sizeof(double) * t.n_tgt, hipMemcpyDeviceToDevice, c.stream));
     c.sync();
+    m.free_terms.push_back(std::move(f));
     t.has_free_term = true;
 }
 

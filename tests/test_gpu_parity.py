@@ -163,6 +163,34 @@ def test_direct_on_cube_with_sharp_edges():
     assert rel(yd.cpu().numpy()[0], (c * x - K @ x).real) < 1e-10
 
 
+def test_free_term_shared_by_trees_of_one_mesh():
+    """The free term is computed once per mesh and tree hierarchy (leaf size,
+    depth, kind) and copied by later trees of that hierarchy: a later tree
+    with another separation factor and wavenumber bound gives the first
+    tree's product A bitwise, a tree of another leaf size computes its own,
+    and all are within 1e-10 of the oracle's dense definition."""
+    bem = _bem()
+    m = mesh_by_name("cube4")
+    ctx = context()
+    mesh = bem.bem_mesh_load(ctx, m.xyz, m.elem)
+    om = oracle.OracleMesh(m.xyz, m.elem)
+    S, K, c = om.assemble()
+    x = bem_inputs.random_vector(om.n_dof, 23)[0]
+    xd = to_dev(x, False)
+    yd = xd.clone()
+    ys = []
+    for B, theta, kappa, k_hint in ((32, 0.5, 0.0, 0.0), (16, 0.5, 0.0, 0.0), (32, 0.6, 2.2, 3.0)):
+        tree = bem.bem_tree_build(ctx, mesh, B=B, order=8, theta=theta, kappa=kappa, k_hint=k_hint)
+        bem.bem_matvec(ctx, tree, 0, 0.0, bem.BEM_OP_A, bem.BEM_DIRECT, bem.BEM_PREC_FP64, xd, yd)
+        ys.append(yd.cpu().numpy()[0].copy())
+        tree.close()
+    mesh.close()
+    ref = (c * x - K @ x).real
+    for y in ys:
+        assert rel(y, ref) < 1e-10 and relmax(y, ref) < 1e-10
+    assert np.array_equal(ys[0], ys[2])
+
+
 # ---------------------------------------------------------------- fast product
 @pytest.mark.parametrize("name", ["sphere320", "sphere1280", "cube4", "perturbed", "sphere1280_p1", "cube4_p1",
                                   "perturbed_p1"])
