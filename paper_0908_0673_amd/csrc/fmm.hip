@@ -26,8 +26,11 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <unordered_map>
 
@@ -865,18 +868,23 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
         // enough LDS that at most lc.p2p_per_cu of its blocks share a CU,
         // which leaves registers and wave slots for the far-field kernels
         // (their matrix-core and latency-bound work then overlaps its VALU
-        // work); 0 asks for no more than the kernel's own LDS.
+        // work); with lc.m2l_room the blocks share what one M2L product block
+        // leaves of the CU's LDS, so that one such block fits beside them.
+        // 0 asks for no more than the kernel's own LDS.
+        const size_t m2l_lds = lc.m2l_room && pl ? m2l_block_lds(*pl, std::is_same<R, float>::value ? BEM_PREC_MIXED : BEM_PREC_FP64, lc.m2l_waves) : 0;
         auto near_lds = [&](const void *fn) -> unsigned {
             if (lc.p2p_per_cu <= 0) return 0u;
-            static thread_local std::map<std::pair<const void *, int>, unsigned> memo;  // per kernel (one device model)
-            const auto key = std::make_pair(fn, lc.p2p_per_cu);
+            // per kernel, blocks per CU and room (one device model)
+            static thread_local std::map<std::tuple<const void *, int, size_t>, unsigned> memo;
+            const auto key = std::make_tuple(fn, lc.p2p_per_cu, m2l_lds);
             auto it = memo.find(key);
             if (it != memo.end()) return it->second;
             hipFuncAttributes fa;
             BEM_HIP(hipFuncGetAttributes(&fa, fn));
             int lds = 0;
             BEM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c.device));
-            const long pad = (long)lds / lc.p2p_per_cu - (long)fa.sharedSizeBytes - 256;
+            const long avail = (long)lds - (m2l_lds ? (long)m2l_lds + 1024 : 0);
+            const long pad = avail / lc.p2p_per_cu - (long)fa.sharedSizeBytes - 256;
             return memo[key] = pad > 0 ? (unsigned)pad : 0u;
         };
         auto near_field = [&](hipStream_t st) {
@@ -1041,12 +1049,14 @@ void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int 
         // pairs on the context's stream around whole products, which end on
         // that stream after the near field's stream has joined it; best of
         // two each): the M2L waves per block first, then the near field's
-        // blocks per CU with the best of those.  The products write y; the
+        // blocks per CU (with or without LDS left for one M2L block) with the
+        // best of those, then the waves again.  The products write y; the
         // product proper follows with the fastest choice.
         run(lc);
         hipEvent_t e0, e1;
         BEM_HIP(hipEventCreate(&e0));
         BEM_HIP(hipEventCreate(&e1));
+        static const bool log = std::getenv("BEM_TUNE_LOG") != nullptr;  // candidates' times on stderr
         auto time_of = [&](const LaunchChoice &cand) {
             float best = 1e30f;
             for (int rep = 0; rep < 2; rep++) {
@@ -1058,6 +1068,10 @@ void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int 
                 BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
                 best = std::min(best, ms);
             }
+            if (log)
+                std::fprintf(stderr, "bem tune: n_tgt %lld green %d prec %d op %d: near blocks/CU %d%s, M2L waves %d: %.4f ms\n",
+                             (long long)t.n_tgt, green, prec, op, cand.p2p_per_cu, cand.m2l_room ? " + M2L room" : "",
+                             cand.m2l_waves, best);
             return best;
         };
         LaunchChoice best = lc;
@@ -1069,10 +1083,21 @@ void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int 
             if (tm < tbest) { tbest = tm; best = cand; }
         }
         const LaunchChoice base = best;
-        for (int pc : {2, 3, 4, 6, 0}) {
-            if (pc == base.p2p_per_cu) continue;
-            LaunchChoice cand = base;
-            cand.p2p_per_cu = pc;
+        for (int room = 0; room < 2; room++)
+            for (int pc : {1, 2, 3, 4, 6, 0}) {
+                if ((pc == base.p2p_per_cu && room == (int)base.m2l_room) || (room && (pc == 0 || pc > 3))) continue;
+                LaunchChoice cand = base;
+                cand.p2p_per_cu = pc;
+                cand.m2l_room = room;
+                const float tm = time_of(cand);
+                if (tm < tbest) { tbest = tm; best = cand; }
+            }
+        // the waves per M2L block once more, beside the chosen near field
+        const LaunchChoice fin = best;
+        for (int w : {2, 4, 8}) {
+            if (w == fin.m2l_waves) continue;
+            LaunchChoice cand = fin;
+            cand.m2l_waves = w;
             const float tm = time_of(cand);
             if (tm < tbest) { tbest = tm; best = cand; }
         }

@@ -137,6 +137,7 @@ struct M2lPlan {
     DBuf<int32_t> slot_sym;           // symmetry of each interaction-list slot
     DBuf<float> T32;                  // expanded operators, built on first use per precision
     DBuf<double> T64;
+    DBuf<uint16_t> T3;                // three-term bf16 splits (mixed path with one order)
     template <class R>
     DBuf<R> &expanded_buf();
 };
@@ -171,6 +172,7 @@ struct LevelP {
 struct LaunchChoice {
     int p2p_per_cu = 4;
     int m2l_waves = 4;
+    bool m2l_room = false;  // the near field's blocks leave LDS for one M2L block per CU
 };
 
 // Per-matvec work buffers, grown on demand and kept on the tree.
@@ -337,7 +339,10 @@ void l2l_apply(bem_tree &t, int nrhs, V *loc);
 M2lPlan &get_m2l_plan(bem_tree &t, int green, double k);
 template <class V, class R>
 void m2l_prepare(bem_tree &t, M2lPlan &pl, int waves);
-bool m2l_ready(const M2lPlan &pl, int prec, int waves);  // operators and tasks of precision prec exist
+bool m2l_ready(const M2lPlan &pl, int prec, int waves);
+// LDS of one block of the M2L product kernel a product of precision prec
+// with `waves` waves per block launches on this plan
+size_t m2l_block_lds(const M2lPlan &pl, int prec, int waves);  // operators and tasks of precision prec exist
 template <class V, class R>
 void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int waves);
 

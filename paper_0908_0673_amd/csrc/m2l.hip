@@ -41,6 +41,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <type_traits>
 #include <unordered_map>
 
@@ -309,6 +310,232 @@ __global__ void __launch_bounds__(64 * W) k_m2l(M2lArgs a, const R *T, const R *
                         o[16 * (mt0 + j) + crow(R(0), kq, r4)] =
                             cx<R>((acc[0][j][r4] - timi) * scale, (trmi + acc[1][j][r4]) * scale);
                 }
+    }
+}
+
+// ---------------------------------------------------------------- split-bf16 products
+// The mixed path runs the products on the bf16 matrix instruction
+// v_mfma_f32_16x16x32_bf16 (FP32 accumulation), whose rate on this chip is
+// about fifteen times that of the FP32 one (measured: 2.2 PFLOP/s against
+// 0.149).  Every operand x is carried as three bf16 terms, x1 = bf16(x),
+// x2 = bf16(x - x1), x3 = bf16(x - x1 - x2) (each term holds the next eight
+// significant bits, so together they hold x to about 2^-27 relative), and each
+// product keeps the six cross terms of combined order up to four,
+//     x y ~ x1 y1 + (x1 y2 + x2 y1) + (x1 y3 + x2 y2 + x3 y1),
+// the dropped ones being below 2^-27 relative: the accuracy of FP32 operands
+// (2^-24) at about 2.5 times the speed of the FP32 instruction for the same
+// work.  The smaller terms are accumulated first.  The contraction runs over
+// K3 = 192 >= P in blocks of 32; a chunk of the operator is one block of one
+// plane (the real or imaginary part): 11 row tiles x 3 terms x 1 KB, the A
+// operands of the instruction in lane order (lane l holds row l % 16,
+// columns 8 (l / 16) .. + 7 of its 16 x 32 tile).
+constexpr int KB = 6;                  // contraction blocks of 32
+constexpr int K3 = KB * 32;            // 192
+constexpr int TILE3 = 512;             // bf16 values of one A tile of one term
+constexpr int CH3 = MT * 3 * TILE3;    // bf16 values of one chunk (one block of one plane)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline floatx4 mfma3(uint4 a, uint4 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                   0, 0);
+}
+
+// three-term bf16 split (bit patterns) of an FP64 or FP32 value
+__device__ inline void split3(double x, uint16_t *t) {
+    const __bf16 h = (__bf16)(float)x;
+    const double r = x - (double)(float)h;
+    const __bf16 m = (__bf16)(float)r;
+    const __bf16 l = (__bf16)(float)(r - (double)(float)m);
+    t[0] = __builtin_bit_cast(uint16_t, h);
+    t[1] = __builtin_bit_cast(uint16_t, m);
+    t[2] = __builtin_bit_cast(uint16_t, l);
+}
+__device__ inline void split3(float x, uint16_t *t) {
+    const __bf16 h = (__bf16)x;
+    const float r = x - (float)h;  // exact: x and h agree in their leading bits
+    const __bf16 m = (__bf16)r;
+    const __bf16 l = (__bf16)(r - (float)m);
+    t[0] = __builtin_bit_cast(uint16_t, h);
+    t[1] = __builtin_bit_cast(uint16_t, m);
+    t[2] = __builtin_bit_cast(uint16_t, l);
+}
+
+// T_c of k_expand_T as three-term splits: T3[((c KB + kb) NA + q) CH3 +
+// (mt 3 + s) TILE3 + 8 lane + i] is term s of plane q of T_c[b][a] with
+// b = 16 mt + lane % 16, a = 32 kb + 8 (lane / 16) + i.
+template <bool HELM>
+__global__ void k_expand_T3(const double *D64, const int32_t *pk, const int32_t *cls_delta, const double *inv_fact,
+                            int P, int P2, uint16_t *T3) {
+    constexpr int NA = HELM ? 2 : 1;
+    const int c = blockIdx.x, kb = blockIdx.y / MT, mt = blockIdx.y % MT, lane = threadIdx.x;
+    const int b = 16 * mt + (lane & 15);
+    for (int i = 0; i < 8; i++) {
+        const int al = 32 * kb + 8 * (lane >> 4) + i;
+        double v[2] = {0.0, 0.0};
+        if (b < P && al < P) {
+            const int qa = pk[al], qb = pk[b];
+            const int na = (qa & 31) + ((qa >> 5) & 31) + (qa >> 10);
+            const int nb = (qb & 31) + ((qb >> 5) & 31) + (qb >> 10);
+            const double f = inv_fact[b] * ldexp(1.0, -cls_delta[c] * nb) * ((na & 1) ? -1.0 : 1.0);
+            const int ix = sum_index(qa + qb);
+            if (HELM) {
+                v[0] = f * D64[2 * ((int64_t)c * P2 + ix)];
+                v[1] = f * D64[2 * ((int64_t)c * P2 + ix) + 1];
+            } else {
+                v[0] = f * D64[(int64_t)c * P2 + ix];
+            }
+        }
+        for (int q = 0; q < NA; q++) {
+            uint16_t tt[3];
+            split3(v[q], tt);
+            const int64_t o = ((int64_t)(c * KB + kb) * NA + q) * CH3 + (int64_t)(mt * 3) * TILE3 + 8 * lane + i;
+            for (int s3 = 0; s3 < 3; s3++) T3[o + s3 * TILE3] = tt[s3];
+        }
+    }
+}
+
+// Canonical moments (as k_m2l_canonical_moments) as three-term splits:
+// Mc3[((u NA + part) 3 + s) K3 + a'], part 0 the real part, 1 the imaginary
+// part; zero past P.  One wave per combination.
+template <class V>
+__global__ void k_m2l_canonical_moments3(int64_t n_u, const int32_t *u_src, const int32_t *u_sym,
+                                         const int32_t *sym_in, int P, const V *mom, uint16_t *Mc3) {
+    far_field_priority();
+    constexpr int NA = std::is_same<V, float>::value ? 1 : 2;
+    const int64_t u = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    if (u >= n_u) return;
+    const int lane = threadIdx.x & 63;
+    const V *ms = mom + (int64_t)u_src[u] * P;
+    const int32_t *si = sym_in + u_sym[u] * KIN;
+#pragma unroll
+    for (int it = 0; it < K3 / 64; it++) {
+        const int a = lane + 64 * it;
+        V v = V(0.0f);
+        if (a < P) {
+            const int32_t e = si[a];
+            v = ms[e & 0xffff];
+            if (e & SYM_NEG) v = V(0.0f) - v;
+        }
+        float part[2];
+        if constexpr (NA == 1) {
+            part[0] = v;
+        } else {
+            part[0] = v.re;
+            part[1] = v.im;
+        }
+#pragma unroll
+        for (int q = 0; q < NA; q++) {
+            uint16_t tt[3];
+            split3(part[q], tt);
+#pragma unroll
+            for (int s3 = 0; s3 < 3; s3++) Mc3[((u * NA + q) * 3 + s3) * K3 + a] = tt[s3];
+        }
+    }
+}
+
+// The products of one task on the split operands (as k_m2l with FP32 values,
+// NA = 1 real or 2 complex, every contraction block and row tile): blocks of
+// W waves share the class's operator, streamed through a double-buffered LDS
+// ring one chunk ahead (one barrier per chunk), each wave owning 16 columns
+// whose B operands it loads from the split moments one contraction block
+// ahead.  The per-column arithmetic does not depend on W.
+template <int NA, int W>
+__global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, const uint4 *Mc3, float *out) {
+    far_field_priority();
+    constexpr int U4 = CH3 * 2 / 16;  // 16-byte pieces per chunk
+    constexpr int PER = (U4 + 64 * W - 1) / (64 * W);
+    constexpr int NCH = KB * NA;
+    constexpr int MROW = K3 / 8;      // 16-byte pieces per split moment row
+    __shared__ uint4 As[2][U4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, task = blockIdx.x;
+    const int cnt = a.task_count[task];
+    if (cnt == 0) return;  // the same for the whole block
+    const int c = a.task_class[task], first = a.task_first[task];
+    const int col = lane & 15, kq = lane >> 4;
+    const int p = NA == 1 ? 16 * w + col : 8 * w + (col & 7);
+    const int64_t u = p < cnt ? a.pair_mom[first + p] : 0;
+    // this lane's B rows: its column's moments (complex tasks: columns 8..15
+    // take the imaginary parts of the pairs of columns 0..7)
+    const uint4 *mb = Mc3 + (u * NA + (NA == 2 && col >= 8 ? 1 : 0)) * 3 * MROW + kq;
+    const uint4 *Tg = T3 + (int64_t)c * NCH * U4;
+    // pieces past the chunk are clamped to its last one: those threads load
+    // and store the same value as its owner, so no branch is needed
+    auto fetch = [&](int ch, uint4 (&r)[PER]) {
+#pragma unroll
+        for (int i = 0; i < PER; i++) r[i] = Tg[(int64_t)ch * U4 + min(tid + 64 * W * i, U4 - 1)];
+    };
+    auto stash = [&](int buf, const uint4 (&r)[PER]) {
+#pragma unroll
+        for (int i = 0; i < PER; i++) As[buf][min(tid + 64 * W * i, U4 - 1)] = r[i];
+    };
+    uint4 r[PER];
+    fetch(0, r);
+    uint4 B[3], Bn[3];
+#pragma unroll
+    for (int s3 = 0; s3 < 3; s3++) {
+        B[s3] = mb[s3 * MROW];
+        Bn[s3] = mb[s3 * MROW + 4];
+    }
+    floatx4 acc[NA][MT];
+#pragma unroll
+    for (int q = 0; q < NA; q++)
+#pragma unroll
+        for (int j = 0; j < MT; j++) acc[q][j] = floatx4{0, 0, 0, 0};
+    stash(0, r);
+    __syncthreads();
+    fetch(1, r);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ch++) {
+        const int kb = ch / NA, q = ch % NA;
+        if (q == 0 && kb > 0) {
+#pragma unroll
+            for (int s3 = 0; s3 < 3; s3++) {
+                B[s3] = Bn[s3];
+                if (kb + 1 < KB) Bn[s3] = mb[s3 * MROW + 4 * (kb + 1)];
+            }
+        }
+        const uint4 *Ab = As[ch & 1] + lane;
+#pragma unroll
+        for (int j = 0; j < MT; j++) {
+            const uint4 a0 = Ab[(3 * j) * 64], a1 = Ab[(3 * j + 1) * 64], a2 = Ab[(3 * j + 2) * 64];
+            floatx4 x = acc[q][j];
+            x = mfma3(a2, B[0], x);
+            x = mfma3(a0, B[2], x);
+            x = mfma3(a1, B[1], x);
+            x = mfma3(a1, B[0], x);
+            x = mfma3(a0, B[1], x);
+            x = mfma3(a0, B[0], x);
+            acc[q][j] = x;
+        }
+        if (ch + 1 < NCH) {
+            stash((ch + 1) & 1, r);  // that buffer's last readers passed the previous barrier
+            __syncthreads();
+            if (ch + 2 < NCH) fetch(ch + 2, r);
+        }
+    }
+    const float scale = (float)ldexp(1.0 / a.side, a.level[p < cnt ? a.pair_src[first + p] : 0]);  // 1 / rho_s
+    if constexpr (NA == 1) {
+        if (p < cnt) {
+            float *o = out + ((int64_t)a.pair_slot[first + p] - a.slot0) * OUT_LD;
+#pragma unroll
+            for (int j = 0; j < MT; j++)
+#pragma unroll
+                for (int r4 = 0; r4 < 4; r4++) o[16 * j + 4 * kq + r4] = acc[0][j][r4] * scale;
+        }
+    } else {
+        // lane with column < 8 holds Tr.Mr and Ti.Mr of its pair; lane ^ 8 holds Tr.Mi and Ti.Mi
+        const bool store = col < 8 && p < cnt;
+        cx<float> *o = (cx<float> *)out + (store ? (int64_t)a.pair_slot[first + p] - a.slot0 : 0) * OUT_LD;
+#pragma unroll
+        for (int j = 0; j < MT; j++)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; r4++) {
+                const float trmi = __shfl_xor(acc[0][j][r4], 8, 64);
+                const float timi = __shfl_xor(acc[1][j][r4], 8, 64);
+                if (store)
+                    o[16 * j + 4 * kq + r4] = cx<float>((acc[0][j][r4] - timi) * scale, (trmi + acc[1][j][r4]) * scale);
+            }
     }
 }
 
@@ -736,29 +963,89 @@ const R *expanded(bem_tree &t, M2lPlan &pl) {
     return buf.p;
 }
 
-// pairs per block of w waves: 16 real or 8 complex per column group
+// split operators of the plan (built on first use)
+const uint16_t *expanded3(bem_tree &t, M2lPlan &pl) {
+    Ctx &c = *t.ctx;
+    FmmTables &T = *t.tables;
+    if (!pl.T3.p && pl.n_class) {
+        const bool helm = pl.green == BEM_HELMHOLTZ;
+        pl.T3.alloc(&c, (size_t)(helm ? 2 : 1) * KB * CH3 * pl.n_class);
+        dim3 g((unsigned)pl.n_class, KB * MT);
+        if (helm)
+            k_expand_T3<true><<<g, 64, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p, T.inv_fact64.p, T.P, T.P2,
+                                                      pl.T3.p);
+        else
+            k_expand_T3<false><<<g, 64, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p, T.inv_fact64.p, T.P, T.P2,
+                                                       pl.T3.p);
+        BEM_LAUNCH_CHECK();
+        c.sync();
+    }
+    return pl.T3.p;
+}
+
+// whether a product of precision R on this plan runs on the split operands
+// (mixed precision with one order for all levels)
+template <class R>
+bool split_path(const M2lPlan &pl) {
+    return std::is_same<R, float>::value && !pl.var;
+}
+
+// pairs per block of w waves: 16 real or 8 complex per column group (the
+// FP32 and FP64 kernels with rows split over two waves have w / 2 groups)
 template <class V, class R>
-constexpr int m2l_cols(int w) {
+int m2l_cols(const M2lPlan &pl, int w) {
     constexpr int NA = std::is_same<V, R>::value ? 1 : 2;
-    return (NA == 1 ? 16 : 8) * (w / m2l_ms<R, NA>());
+    return (NA == 1 ? 16 : 8) * (split_path<R>(pl) ? w : w / m2l_ms<R, NA>());
 }
 
 }  // namespace
 
 bool m2l_ready(const M2lPlan &pl, int prec, int waves) {
     const bool helm = pl.green == BEM_HELMHOLTZ, f32 = prec == BEM_PREC_MIXED;
-    if (pl.n_class && !(f32 ? (const void *)pl.T32.p : (const void *)pl.T64.p)) return false;
-    const int cols = helm ? (f32 ? m2l_cols<cx<float>, float>(waves) : m2l_cols<cx<double>, double>(waves))
-                          : (f32 ? m2l_cols<float, float>(waves) : m2l_cols<double, double>(waves));
+    const void *ops = f32 ? (split_path<float>(pl) ? (const void *)pl.T3.p : (const void *)pl.T32.p)
+                          : (const void *)pl.T64.p;
+    if (pl.n_class && !ops) return false;
+    const int cols = helm ? (f32 ? m2l_cols<cx<float>, float>(pl, waves) : m2l_cols<cx<double>, double>(pl, waves))
+                          : (f32 ? m2l_cols<float, float>(pl, waves) : m2l_cols<double, double>(pl, waves));
     for (auto &tk : pl.tasks)
         if (tk->cols == cols) return true;
     return false;
 }
 
+namespace {
+
+template <int W>
+const void *m2l_kernel(const M2lPlan &pl, bool f32, bool helm) {
+    if (f32 && !pl.var) return helm ? (const void *)k_m2l_x3<2, W> : (const void *)k_m2l_x3<1, W>;
+    if (f32) return helm ? (const void *)k_m2l<float, 2, true, W> : (const void *)k_m2l<float, 1, true, W>;
+    if (pl.var) return helm ? (const void *)k_m2l<double, 2, true, W> : (const void *)k_m2l<double, 1, true, W>;
+    return helm ? (const void *)k_m2l<double, 2, false, W> : (const void *)k_m2l<double, 1, false, W>;
+}
+
+}  // namespace
+
+size_t m2l_block_lds(const M2lPlan &pl, int prec, int waves) {
+    const bool f32 = prec == BEM_PREC_MIXED, helm = pl.green == BEM_HELMHOLTZ;
+    const void *fn = waves == 2   ? m2l_kernel<2>(pl, f32, helm)
+                     : waves == 8 ? m2l_kernel<8>(pl, f32, helm)
+                                  : m2l_kernel<4>(pl, f32, helm);
+    static std::mutex mu;
+    static std::map<const void *, size_t> memo;  // one device model
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = memo.find(fn);
+    if (it != memo.end()) return it->second;
+    hipFuncAttributes fa;
+    BEM_HIP(hipFuncGetAttributes(&fa, fn));
+    return memo[fn] = fa.sharedSizeBytes;
+}
+
 template <class V, class R>
 void m2l_prepare(bem_tree &t, M2lPlan &pl, int waves) {
-    expanded<R>(t, pl);
-    get_tasks(*t.ctx, pl, m2l_cols<V, R>(waves));
+    if (split_path<R>(pl))
+        expanded3(t, pl);
+    else
+        expanded<R>(t, pl);
+    get_tasks(*t.ctx, pl, m2l_cols<V, R>(pl, waves));
 }
 
 template <class V, class R>
@@ -766,23 +1053,35 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
     Ctx &c = *t.ctx;
     FmmTables &T = *t.tables;
     const int P = T.P;
-    M2lTasks &tk = get_tasks(c, pl, m2l_cols<V, R>(waves));
+    M2lTasks &tk = get_tasks(c, pl, m2l_cols<V, R>(pl, waves));
     if (!tk.n_task || !pl.n_pairs) {
         c.mark(3);
         return;
     }
+    constexpr int NA = std::is_same<V, R>::value ? 1 : 2;
+    const bool split = split_path<R>(pl);
     V *out = (V *)work_buf(c, t.work.m2l_out, sizeof(V) * (size_t)std::max<int64_t>(1, pl.slab_max_slots) * OUT_LD);
     const LevelP lp = level_p(t);
-    V *Mc = (V *)work_buf(c, t.work.m2l_mom, sizeof(V) * (size_t)std::max<int64_t>(1, pl.n_u) * KIN);
-    const R *Tx = expanded<R>(t, pl);
+    const size_t mc_bytes = split ? sizeof(uint16_t) * 3 * NA * K3 : sizeof(V) * KIN;
+    void *Mc = work_buf(c, t.work.m2l_mom, mc_bytes * (size_t)std::max<int64_t>(1, pl.n_u));
+    const R *Tx = split ? nullptr : expanded<R>(t, pl);
+    const uint4 *T3 = split ? (const uint4 *)expanded3(t, pl) : nullptr;
     for (int rhs = 0; rhs < nrhs; rhs++) {
         const V *m = mom + (int64_t)rhs * t.n_box * P;
         V *l = loc + (int64_t)rhs * t.n_box * P;
-        k_m2l_canonical_moments<V><<<(unsigned)((pl.n_u + 3) / 4), 256, 0, c.stream>>>(pl.n_u, pl.u_src.p, pl.u_sym.p,
-                                                                                     pl.sym_in.p, P, m, Mc);
+        bool done = false;
+        if constexpr (std::is_same<R, float>::value) {
+            if (split) {
+                k_m2l_canonical_moments3<V><<<(unsigned)((pl.n_u + 3) / 4), 256, 0, c.stream>>>(
+                    pl.n_u, pl.u_src.p, pl.u_sym.p, pl.sym_in.p, P, m, (uint16_t *)Mc);
+                done = true;
+            }
+        }
+        if (!done)
+            k_m2l_canonical_moments<V><<<(unsigned)((pl.n_u + 3) / 4), 256, 0, c.stream>>>(
+                pl.n_u, pl.u_src.p, pl.u_sym.p, pl.sym_in.p, P, m, (V *)Mc);
         BEM_LAUNCH_CHECK();
         c.mark(10);
-        constexpr int NA = std::is_same<V, R>::value ? 1 : 2;
         // one slab of target boxes at a time: its pairs' results, then their sums
         for (size_t sl = 0; sl + 1 < pl.slab_slot0.size(); sl++) {
             const int64_t t0 = tk.slab_task0[sl], nt = tk.slab_task0[sl + 1] - t0;
@@ -793,6 +1092,12 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
             c.kbegin(c.stream, 3);
             auto launch = [&](auto wv) {
                 constexpr int W = decltype(wv)::value;
+                if constexpr (std::is_same<R, float>::value) {
+                    if (split) {
+                        k_m2l_x3<NA, W><<<(unsigned)nt, 64 * W, 0, c.stream>>>(a, T3, (const uint4 *)Mc, (float *)out);
+                        return;
+                    }
+                }
                 if (pl.var)
                     k_m2l<R, NA, true, W><<<(unsigned)nt, 64 * W, 0, c.stream>>>(a, Tx, (const R *)Mc, (R *)out);
                 else
