@@ -138,6 +138,15 @@ struct M2lPlan {
     DBuf<float> T32;                  // expanded operators, built on first use per precision
     DBuf<double> T64;
     DBuf<uint16_t> T3;                // three-term bf16 splits (mixed path with one order)
+    std::vector<int32_t> h_pair_slot, h_pair_sym;
+    // Mixed path with one order: partial slots of the per-target sums the
+    // product kernel forms itself (built on first use for `parts_g` pairs
+    // per pass): pair -> partial slot, the pairs' symmetries, and the slots
+    // of each M2L target box (m2l_boxes order), contiguous, box by box.
+    int parts_g = 0;
+    DBuf<int32_t> pair_part, pair_sym;
+    DBuf<int64_t> part_ptr;           // [n_m2l_boxes + 1]
+    std::vector<int64_t> h_part_ptr;
     template <class R>
     DBuf<R> &expanded_buf();
 };

@@ -148,6 +148,10 @@ struct M2lArgs {
     double side;
     int P;
     int64_t slot0;  // first interaction slot of the slab: results go to out[slot - slot0]
+    // split path: partial slot and symmetry of each pair, the symmetry
+    // table back to the pairs' frames; slot0 is then the slab's first partial
+    const int32_t *pair_part, *pair_sym;
+    const int16_t *sym_red;
 };
 
 // Moments in the canonical frame of each used (source box, symmetry)
@@ -514,28 +518,100 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, c
             if (ch + 2 < NCH) fetch(ch + 2, r);
         }
     }
+    // Each pair's canonical result, scaled, is taken back to its own frame
+    // (row i is the canonical row sym_red[sym][i], signed) and summed with the
+    // pairs that follow it in the wave and share its target box (runs of
+    // consecutive pairs, which share a partial slot), in passes of G pairs
+    // staged in the LDS ring beside a copy of the symmetry table; each run's
+    // sum is written once, to its slot.
     const float scale = (float)ldexp(1.0 / a.side, a.level[p < cnt ? a.pair_src[first + p] : 0]);  // 1 / rho_s
-    if constexpr (NA == 1) {
-        if (p < cnt) {
-            float *o = out + ((int64_t)a.pair_slot[first + p] - a.slot0) * OUT_LD;
+    using VO = typename std::conditional<NA == 1, float, cx<float>>::type;
+    constexpr int G = 8;                          // pairs per pass: 5.5 (real) or 11 KB of staging per wave
+    constexpr int PW = NA == 1 ? 16 : 8;          // pairs per wave
+    constexpr int SB = W * G * OUT_LD * (int)sizeof(VO);  // staging bytes of the block
+    static_assert(SB % 16 == 0 && SB + NSYM * OUT_LD * 2 <= 2 * U4 * 16, "staging exceeds the LDS ring");
+    VO *S = (VO *)&As[0][0] + w * G * OUT_LD;
+    const int16_t *tab = (const int16_t *)((const char *)&As[0][0] + SB);
+    VO *o = (VO *)out;
+    __syncthreads();  // every wave is past its last operator reads
+    for (int x = tid; x < NSYM * OUT_LD / 8; x += 64 * W)
+        ((uint4 *)((char *)&As[0][0] + SB))[x] = ((const uint4 *)a.sym_red)[x];
+    __syncthreads();
 #pragma unroll
-            for (int j = 0; j < MT; j++)
+    for (int h = 0; h < PW / G; h++) {
+        const int c0 = h * G;        // first column (pair) of the pass
+        const int pb = PW * w + c0;  // the pass's first pair in the task
+        int part[G], sym[G];
 #pragma unroll
-                for (int r4 = 0; r4 < 4; r4++) o[16 * j + 4 * kq + r4] = acc[0][j][r4] * scale;
+        for (int cc = 0; cc < G; cc++) {
+            const bool ok = pb + cc < cnt;
+            part[cc] = ok ? a.pair_part[first + pb + cc] : -1;
+            sym[cc] = ok ? a.pair_sym[first + pb + cc] : 0;
         }
-    } else {
-        // lane with column < 8 holds Tr.Mr and Ti.Mr of its pair; lane ^ 8 holds Tr.Mi and Ti.Mi
-        const bool store = col < 8 && p < cnt;
-        cx<float> *o = (cx<float> *)out + (store ? (int64_t)a.pair_slot[first + p] - a.slot0 : 0) * OUT_LD;
 #pragma unroll
         for (int j = 0; j < MT; j++)
 #pragma unroll
             for (int r4 = 0; r4 < 4; r4++) {
-                const float trmi = __shfl_xor(acc[0][j][r4], 8, 64);
-                const float timi = __shfl_xor(acc[1][j][r4], 8, 64);
-                if (store)
-                    o[16 * j + 4 * kq + r4] = cx<float>((acc[0][j][r4] - timi) * scale, (trmi + acc[1][j][r4]) * scale);
+                if constexpr (NA == 1) {
+                    if (col >= c0 && col < c0 + G) S[(col - c0) * OUT_LD + 16 * j + 4 * kq + r4] = acc[0][j][r4] * scale;
+                } else {
+                    // lane with column < 8 holds Tr.Mr and Ti.Mr of its pair; lane ^ 8 holds Tr.Mi and Ti.Mi
+                    const float trmi = __shfl_xor(acc[0][j][r4], 8, 64);
+                    const float timi = __shfl_xor(acc[1][j][r4], 8, 64);
+                    if (col >= c0 && col < c0 + G)
+                        S[(col - c0) * OUT_LD + 16 * j + 4 * kq + r4] =
+                            cx<float>((acc[0][j][r4] - timi) * scale, (trmi + acc[1][j][r4]) * scale);
+                }
             }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            const int i = lane + 64 * r;
+            const bool row = i < a.P;
+            VO x[G];
+#pragma unroll
+            for (int cc = 0; cc < G; cc++) {
+                const int e = row ? tab[sym[cc] * OUT_LD + i] : 0;
+                const VO v = S[cc * OUT_LD + (e & 0xff)];
+                x[cc] = (e & 0x100) ? VO(0.0f) - v : v;
+            }
+            VO v = x[0];
+#pragma unroll
+            for (int cc = 1; cc <= G; cc++) {
+                const bool end = cc == G || part[cc] != part[cc - 1];  // the same for the whole wave
+                if (end) {
+                    if (row && part[cc - 1] >= 0) o[(int64_t)(part[cc - 1] - a.slot0) * OUT_LD + i] = v;
+                    if (cc < G) v = x[cc];
+                } else {
+                    v += x[cc];
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // the next pass overwrites the staging
+    }
+}
+
+// The split path's M2L sums: each target box's locals are the sum of its
+// partial slots (contiguous, in plan order).  One block per box of the slab.
+template <class V>
+__global__ void __launch_bounds__(256) k_m2l_sum_parts(const int32_t *boxes, const int64_t *part_ptr, int64_t part0,
+                                                       int P, const V *parts, V *loc) {
+    far_field_priority();
+    const int b = boxes[blockIdx.x];
+    const int64_t k0 = part_ptr[blockIdx.x] - part0, k1 = part_ptr[blockIdx.x + 1] - part0;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        V v = V(0.0f);
+        int64_t k = k0;
+        for (; k + 4 <= k1; k += 4) {  // four loads in flight, added in order
+            const V x0 = parts[k * OUT_LD + i], x1 = parts[(k + 1) * OUT_LD + i];
+            const V x2 = parts[(k + 2) * OUT_LD + i], x3 = parts[(k + 3) * OUT_LD + i];
+            v += x0;
+            v += x1;
+            v += x2;
+            v += x3;
+        }
+        for (; k < k1; k++) v += parts[k * OUT_LD + i];
+        loc[(int64_t)b * P + i] = v;
     }
 }
 
@@ -798,6 +874,8 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
             pl->h_group_slab.push_back(sl);
         }
     pl->n_pairs = (int64_t)slot.size();
+    pl->h_pair_slot = slot;
+    pl->h_pair_sym = sym;
     auto up = [&](DBuf<int32_t> &d, const std::vector<int32_t> &v) {
         d.alloc(&c, std::max<size_t>(1, v.size()));
         if (!v.empty()) d.upload(v.data(), v.size());
@@ -983,6 +1061,56 @@ const uint16_t *expanded3(bem_tree &t, M2lPlan &pl) {
     return pl.T3.p;
 }
 
+// Partial slots of the split path's per-target sums: within each (slab,
+// class) group of pairs, passes of G = 8 pairs from its first pair (the
+// product kernel's waves take 16 real or 8 complex pairs from there); a run of consecutive pairs of one pass with the same target box
+// shares a slot.  Slots are numbered box by box in m2l_boxes order (a slab's
+// slots are then contiguous), within a box in pair order, so that a box's sum
+// runs over one contiguous range in a fixed order.
+void build_parts(bem_tree &t, M2lPlan &pl) {
+    constexpr int G = 8;  // as the product kernel
+    if (pl.parts_g == G) return;
+    Ctx &c = *t.ctx;
+    std::vector<int32_t> slot_box(std::max<int64_t>(1, t.n_inter), -1), box_x(t.n_box, -1);
+    int32_t nx = 0;
+    for (int64_t b = 0; b < t.n_box; b++) {
+        for (int64_t j = t.h_inter_ptr[b]; j < t.h_inter_ptr[b + 1]; j++) slot_box[j] = (int32_t)b;
+        if (t.h_te[b] > t.h_tb[b] && t.h_inter_ptr[b + 1] > t.h_inter_ptr[b]) box_x[b] = nx++;  // as plan_fmm
+    }
+    const size_t np = pl.h_pair_slot.size();
+    std::vector<int32_t> run(np, 0), run_x;  // run of each pair; m2l-box index of each run
+    for (size_t g = 0; g < pl.h_class_first.size(); g++) {
+        const int64_t f0 = pl.h_class_first[g], f1 = f0 + pl.h_class_count[g];
+        for (int64_t i = f0; i < f1; i++) {
+            const int32_t x = box_x[slot_box[pl.h_pair_slot[i]]];
+            const bool fresh = i == f0 || (i - f0) % G == 0 || run_x.back() != x;
+            if (fresh) run_x.push_back(x);
+            run[i] = (int32_t)run_x.size() - 1;
+        }
+    }
+    // number the runs box by box (stable: pair order within a box)
+    std::vector<int64_t> ptr((size_t)nx + 1, 0);
+    for (int32_t x : run_x) ptr[(size_t)x + 1]++;
+    for (int32_t x = 0; x < nx; x++) ptr[(size_t)x + 1] += ptr[(size_t)x];
+    std::vector<int64_t> next(ptr.begin(), ptr.end() - 1);
+    std::vector<int32_t> slot_of(run_x.size());
+    for (size_t r = 0; r < run_x.size(); r++) slot_of[r] = (int32_t)next[(size_t)run_x[r]]++;
+    std::vector<int32_t> part(np);
+    for (size_t i = 0; i < np; i++) part[i] = slot_of[(size_t)run[i]];
+    pl.pair_part.alloc(&c, std::max<size_t>(1, np));
+    if (np) pl.pair_part.upload(part.data(), np);
+    pl.pair_sym.alloc(&c, std::max<size_t>(1, np));
+    if (np) pl.pair_sym.upload(pl.h_pair_sym.data(), np);
+    pl.part_ptr.alloc(&c, ptr.size());
+    pl.part_ptr.upload(ptr.data(), ptr.size());
+    pl.h_part_ptr = ptr;
+    pl.parts_g = G;
+}
+
+// waves per block of the split kernel: the complex one stages 11 KB per wave
+// beside the symmetry table in its LDS ring, which holds four
+int split_waves(int na, int w) { return na == 2 && w > 4 ? 4 : w; }
+
 // whether a product of precision R on this plan runs on the split operands
 // (mixed precision with one order for all levels)
 template <class R>
@@ -995,7 +1123,7 @@ bool split_path(const M2lPlan &pl) {
 template <class V, class R>
 int m2l_cols(const M2lPlan &pl, int w) {
     constexpr int NA = std::is_same<V, R>::value ? 1 : 2;
-    return (NA == 1 ? 16 : 8) * (split_path<R>(pl) ? w : w / m2l_ms<R, NA>());
+    return (NA == 1 ? 16 : 8) * (split_path<R>(pl) ? split_waves(NA, w) : w / m2l_ms<R, NA>());
 }
 
 }  // namespace
@@ -1005,6 +1133,7 @@ bool m2l_ready(const M2lPlan &pl, int prec, int waves) {
     const void *ops = f32 ? (split_path<float>(pl) ? (const void *)pl.T3.p : (const void *)pl.T32.p)
                           : (const void *)pl.T64.p;
     if (pl.n_class && !ops) return false;
+    if (f32 && split_path<float>(pl) && pl.parts_g != 8) return false;
     const int cols = helm ? (f32 ? m2l_cols<cx<float>, float>(pl, waves) : m2l_cols<cx<double>, double>(pl, waves))
                           : (f32 ? m2l_cols<float, float>(pl, waves) : m2l_cols<double, double>(pl, waves));
     for (auto &tk : pl.tasks)
@@ -1016,7 +1145,7 @@ namespace {
 
 template <int W>
 const void *m2l_kernel(const M2lPlan &pl, bool f32, bool helm) {
-    if (f32 && !pl.var) return helm ? (const void *)k_m2l_x3<2, W> : (const void *)k_m2l_x3<1, W>;
+    if (f32 && !pl.var) return helm ? (const void *)k_m2l_x3<2, (W > 4 ? 4 : W)> : (const void *)k_m2l_x3<1, W>;
     if (f32) return helm ? (const void *)k_m2l<float, 2, true, W> : (const void *)k_m2l<float, 1, true, W>;
     if (pl.var) return helm ? (const void *)k_m2l<double, 2, true, W> : (const void *)k_m2l<double, 1, true, W>;
     return helm ? (const void *)k_m2l<double, 2, false, W> : (const void *)k_m2l<double, 1, false, W>;
@@ -1041,9 +1170,10 @@ size_t m2l_block_lds(const M2lPlan &pl, int prec, int waves) {
 
 template <class V, class R>
 void m2l_prepare(bem_tree &t, M2lPlan &pl, int waves) {
-    if (split_path<R>(pl))
+    if (split_path<R>(pl)) {
         expanded3(t, pl);
-    else
+        build_parts(t, pl);
+    } else
         expanded<R>(t, pl);
     get_tasks(*t.ctx, pl, m2l_cols<V, R>(pl, waves));
 }
@@ -1066,6 +1196,7 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
     void *Mc = work_buf(c, t.work.m2l_mom, mc_bytes * (size_t)std::max<int64_t>(1, pl.n_u));
     const R *Tx = split ? nullptr : expanded<R>(t, pl);
     const uint4 *T3 = split ? (const uint4 *)expanded3(t, pl) : nullptr;
+    if (split) build_parts(t, pl);
     for (int rhs = 0; rhs < nrhs; rhs++) {
         const V *m = mom + (int64_t)rhs * t.n_box * P;
         V *l = loc + (int64_t)rhs * t.n_box * P;
@@ -1086,15 +1217,19 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
         for (size_t sl = 0; sl + 1 < pl.slab_slot0.size(); sl++) {
             const int64_t t0 = tk.slab_task0[sl], nt = tk.slab_task0[sl + 1] - t0;
             const int64_t b0 = pl.slab_box0[sl], nb = pl.slab_box0[sl + 1] - b0;
+            // split path: results go to the slab's partial slots, from its first box's
+            const int64_t part0 = split ? pl.h_part_ptr[(size_t)b0] : 0;
             M2lArgs a{tk.task_class.p + t0, tk.task_first.p + t0, tk.task_count.p + t0, pl.pair_slot.p,
                       pl.pair_src.p, pl.pair_mom.p, t.level.p, pl.var ? tk.task_kt.p + t0 : nullptr,
-                      pl.var ? tk.task_mt.p + t0 : nullptr, t.side, P, pl.slab_slot0[sl]};
+                      pl.var ? tk.task_mt.p + t0 : nullptr, t.side, P, split ? part0 : pl.slab_slot0[sl],
+                      split ? pl.pair_part.p : nullptr, split ? pl.pair_sym.p : nullptr, pl.sym_red.p};
             c.kbegin(c.stream, 3);
             auto launch = [&](auto wv) {
                 constexpr int W = decltype(wv)::value;
                 if constexpr (std::is_same<R, float>::value) {
                     if (split) {
-                        k_m2l_x3<NA, W><<<(unsigned)nt, 64 * W, 0, c.stream>>>(a, T3, (const uint4 *)Mc, (float *)out);
+                        constexpr int WS = NA == 2 && W > 4 ? 4 : W;  // as split_waves
+                        k_m2l_x3<NA, WS><<<(unsigned)nt, 64 * WS, 0, c.stream>>>(a, T3, (const uint4 *)Mc, (float *)out);
                         return;
                     }
                 }
@@ -1111,7 +1246,11 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
             }
             c.kend(c.stream);
             c.mark(3);
-            if (nb > 0) {
+            if (nb > 0 && split) {
+                k_m2l_sum_parts<V><<<(unsigned)nb, 256, 0, c.stream>>>(t.m2l_boxes.p + b0, pl.part_ptr.p + b0, part0,
+                                                                       P, out, l);
+                BEM_LAUNCH_CHECK();
+            } else if (nb > 0) {
                 k_m2l_reduce<V><<<(unsigned)nb, 256, 0, c.stream>>>(t.m2l_boxes.p + b0, t.inter_ptr.p, pl.slot_sym.p,
                                                                     pl.sym_red.p, P, t.level.p, lp, pl.slab_slot0[sl],
                                                                     out, l);

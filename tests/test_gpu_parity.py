@@ -881,9 +881,11 @@ def test_autotuned_products_equal_untuned_ones(green, k, prec):
 def test_m2l_in_slabs_equals_one_slab(green, k):
     """The multipole-to-local step runs slab by slab over runs of target boxes
     whose interaction slots fit the tree's bound (the product's work space):
-    with many small slabs the products equal the one-slab products bit for
-    bit (each pair's translation and each box's sum are the same), and the
-    FP64 one equals the oracle's fast product."""
+    with many small slabs the FP64 products equal the one-slab products bit
+    for bit (each pair's translation and each box's sum are the same) and the
+    oracle's fast product; the mixed ones, whose per-box sums the product
+    kernel starts over runs of pairs that the slabs cut differently, agree to
+    FP32 rounding."""
     bem = _bem()
     m, ctx, mesh, tree, om, ot = setup("sphere1280")
     small = bem.bem_tree_build(ctx, mesh, B=32, order=8, theta=THETA, m2l_slab_slots=700)
@@ -895,7 +897,10 @@ def test_m2l_in_slabs_equals_one_slab(green, k):
         for prec in (bem.BEM_PREC_FP64, bem.BEM_PREC_MIXED):
             bem.bem_matvec(ctx, tree, green, k, op, bem.BEM_FMM, prec, xd, y1)
             bem.bem_matvec(ctx, small, green, k, op, bem.BEM_FMM, prec, xd, y2)
-            assert np.array_equal(y1.cpu().numpy(), y2.cpu().numpy()), (op, prec)
+            if prec == bem.BEM_PREC_FP64:
+                assert np.array_equal(y1.cpu().numpy(), y2.cpu().numpy()), (op, prec)
+            else:
+                check_product(y2.cpu().numpy(), y1.cpu().numpy(), 1e-6, f"slabs op={op} mixed vs one slab")
         ref = ot.fmm_matvec(x[0], op, green, k)
         bem.bem_matvec(ctx, small, green, k, op, bem.BEM_FMM, bem.BEM_PREC_FP64, xd, y2)
         check_product(y2.cpu().numpy()[0], ref if cplx else ref.real, 1e-11, f"slabs op={op} fp64 vs oracle fast")
