@@ -144,6 +144,7 @@ struct M2lPlan {
     // per pass): pair -> partial slot, the pairs' symmetries, and the slots
     // of each M2L target box (m2l_boxes order), contiguous, box by box.
     int parts_g = 0;
+    int64_t parts_max = 0;            // largest number of partial slots of one slab
     DBuf<int32_t> pair_part, pair_sym;
     DBuf<int64_t> part_ptr;           // [n_m2l_boxes + 1]
     std::vector<int64_t> h_part_ptr;

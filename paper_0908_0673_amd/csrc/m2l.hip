@@ -1104,6 +1104,9 @@ void build_parts(bem_tree &t, M2lPlan &pl) {
     pl.part_ptr.alloc(&c, ptr.size());
     pl.part_ptr.upload(ptr.data(), ptr.size());
     pl.h_part_ptr = ptr;
+    pl.parts_max = 0;
+    for (size_t sl = 0; sl + 1 < pl.slab_box0.size(); sl++)
+        pl.parts_max = std::max(pl.parts_max, ptr[(size_t)pl.slab_box0[sl + 1]] - ptr[(size_t)pl.slab_box0[sl]]);
     pl.parts_g = G;
 }
 
@@ -1190,13 +1193,15 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
     }
     constexpr int NA = std::is_same<V, R>::value ? 1 : 2;
     const bool split = split_path<R>(pl);
-    V *out = (V *)work_buf(c, t.work.m2l_out, sizeof(V) * (size_t)std::max<int64_t>(1, pl.slab_max_slots) * OUT_LD);
+    if (split) build_parts(t, pl);
+    // per-pair results of a slab, or its partial slots on the split path
+    const int64_t out_rows = split ? pl.parts_max : pl.slab_max_slots;
+    V *out = (V *)work_buf(c, t.work.m2l_out, sizeof(V) * (size_t)std::max<int64_t>(1, out_rows) * OUT_LD);
     const LevelP lp = level_p(t);
     const size_t mc_bytes = split ? sizeof(uint16_t) * 3 * NA * K3 : sizeof(V) * KIN;
     void *Mc = work_buf(c, t.work.m2l_mom, mc_bytes * (size_t)std::max<int64_t>(1, pl.n_u));
     const R *Tx = split ? nullptr : expanded<R>(t, pl);
     const uint4 *T3 = split ? (const uint4 *)expanded3(t, pl) : nullptr;
-    if (split) build_parts(t, pl);
     for (int rhs = 0; rhs < nrhs; rhs++) {
         const V *m = mom + (int64_t)rhs * t.n_box * P;
         V *l = loc + (int64_t)rhs * t.n_box * P;
