@@ -43,6 +43,7 @@ FP32_VEC_PEAK = 157.3  # TFLOP/s, MI355X vector FP32 (256 CUs x 2.4 GHz; counts 
 FP32_VEC_UNPACKED = 78.6  # TFLOP/s: the same without packed FP32, which this build does not emit
 FP32_MFMA_PEAK = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 FP64_VEC_PEAK = 78.6
+BF16_MFMA_PEAK = 2500.0  # TFLOP/s: dense bf16 matrix peak (the split M2L's instruction)
 KERNEL_PEAKS = {"m2l": ("mfma", FP32_MFMA_PEAK), "p2p": ("alu", FP32_VEC_PEAK)}
 # source file of each timed kernel (the HBM traffic figures hold for one version of it)
 KERNEL_SOURCES = {"m2l": "m2l.hip", "p2p": "fmm.hip"}
@@ -99,13 +100,15 @@ def algorithmic_flops(stats, P, helm):
     """Per-product algorithmic flop counts of the two heavy phases (operator A,
     double layer).
 
-    near field, per (target, source point) pair, as the kernel evaluates it:
+    near field, per (target, source point) pair, as the mixed-precision kernel
+    evaluates it (a transcendental instruction counted as one):
       Laplace:   3 (difference) + 5 (r^2) + 1 (1/r) + 5 (r.n) + 3 (r^-3) + 2 (accumulate) = 19
-      Helmholtz: 3 + 5 + 1 + 5 (r.n) + 4 (G, r.n / r^3) + 2 (k r) + 31 (sin and cos of k r by
-                 reduction and polynomials) + 6 (dG/dn) + 8 (complex strength and accumulate) = 65
+      Helmholtz: 3 + 5 + 1 + 2 (k r) + 4 (turns, fraction, sin, cos) + 5 (r.n) + 3 (r.n / r^3)
+                 + 4 (cos + kr sin, sin - kr cos) + 2 (scaling) + 8 (complex strength and
+                 accumulate) = 37
     M2L: per (target box, source box) pair a P x P product, 2 P^2 real, 8 P^2 complex.
     """
-    return {"p2p": (65.0 if helm else 19.0) * stats["n_p2p"],
+    return {"p2p": (37.0 if helm else 19.0) * stats["n_p2p"],
             "m2l": (8.0 if helm else 2.0) * P * P * stats["n_m2l"]}
 
 
@@ -223,6 +226,14 @@ def roofline(dom, flops, ms_launch, launches, traffic):
     if dom == "p2p":  # the attainable VALU peak of a build without packed FP32
         r["peak_unpacked"] = FP32_VEC_UNPACKED
         r["frac_unpacked"] = achieved / FP32_VEC_UNPACKED
+    if dom == "m2l":
+        # the mixed-precision products run on the bf16 matrix instruction with
+        # three-term operand splits: six products per FP32-equivalent one, on
+        # a 176 x 192 padded tile per P x P block
+        ex = achieved * 6 * (176 * 192) / (165 * 165)
+        r["bf16_executed_tflops"] = ex
+        r["bf16_peak"] = BF16_MFMA_PEAK
+        r["bf16_frac"] = ex / BF16_MFMA_PEAK
     return r
 
 
