@@ -57,6 +57,17 @@ WORKLOADS = {
 HEADLINE = ("c2_sphere", "c2_cube")
 
 
+def code_sha256(path):
+    """Hash of a source file's code: comments, blank lines and the
+    indentation of lines removed (a change of comments only keeps it)."""
+    import re
+
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = [re.sub(r"//.*$", "", ln).strip() for ln in text.splitlines()]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln).encode()).hexdigest()
+
+
 def hbm_traffic(kernel, mesh, B, theta, kappa):
     """HBM bytes per launch of the mixed-precision kernel on this tree, from
     the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, scaled by the
@@ -71,8 +82,7 @@ def hbm_traffic(kernel, mesh, B, theta, kappa):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     src = os.path.join(ROOT, "paper_0908_0673_amd", "csrc", KERNEL_SOURCES[kernel])
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if kv.get("source_sha256") != sha or "hbm_bytes_per_launch" not in kv:
+    if kv.get("code_sha256") != code_sha256(src) or "hbm_bytes_per_launch" not in kv:
         return None
     try:
         same = (int(kv.get("B", -1)) == B and abs(float(kv.get("theta", "nan")) - theta) < 1e-12

@@ -33,11 +33,16 @@
 // real columns); its B operands are the pairs' moments in the canonical
 // frame, which a small kernel first writes once per used (source box,
 // symmetry) combination so that the product reads them contiguously, and it
-// stores each pair's canonical result whole (the stores are contiguous).  Tasks are ordered so that every wave of a class is dispatched
-// to the same XCD (blocks go round-robin over the 8 XCDs), whose L2 then
-// holds that class's operator.  Each pair's result goes to its slot in the
-// interaction list; a second kernel sums every target box's slots in list
-// order, so the result does not depend on scheduling (no float atomics).
+// stores each pair's canonical result whole (the stores are contiguous).
+// Tasks are ordered so that every wave of a class is dispatched to the same
+// XCD (blocks go round-robin over the 8 XCDs), whose L2 then holds that
+// class's operator.  FP64 path: each pair's result goes to its slot in the
+// interaction list, and a second kernel sums every target box's slots in
+// list order.  Mixed path (one order for all levels): the products run on
+// the bf16 instruction with split operands, and each wave sums its pairs of
+// one target box in the box's frame before writing (see k_m2l_x3); a second
+// kernel adds a box's partial sums in plan order.  Either way the result does
+// not depend on scheduling (no float atomics).
 #include <algorithm>
 #include <cmath>
 #include <map>
