@@ -690,6 +690,7 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_fracs=(0.5,), 
         out["served_solves_per_s"] = total_rhs / dt
         out["served_requests_per_s"] = sat
         out["served"] = summary(res)
+        print(f"{label}: partial {json.dumps(out)}", file=sys.stderr, flush=True)
         out["open_loop"] = []
         arrivals = np.array([r["t"] for r in reqs])
         arrivals = arrivals - arrivals[0]
@@ -712,7 +713,8 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_fracs=(0.5,), 
             out["open_loop"].append({"rate_fraction_of_saturation": f, "rate_requests_per_s": rate,
                                      "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                                                     "p99": float(np.percentile(lat, 99) * 1e3)}})
-            print(f"{label}: open loop at {f} x saturation done", file=sys.stderr, flush=True)
+            print(f"{label}: open loop at {f} x saturation done: {json.dumps(out['open_loop'][-1])}", file=sys.stderr,
+                  flush=True)
         out["server_stats"] = srv.stats()
     finally:
         srv.close()

@@ -1031,28 +1031,32 @@ void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int 
     using CD = cx<double>;
     using CF = cx<float>;
     const bool f64 = prec == BEM_PREC_FP64 || method == BEM_DIRECT;
-    auto run = [&](const LaunchChoice &lc) {
+    auto run_n = [&](const LaunchChoice &lc, int n) {
         if (green == BEM_HELMHOLTZ) {
-            if (f64) run_with<CD, double, CD, true>(t, k, op, method, nrhs, x, y, lc);
-            else run_with<CF, float, CD, true>(t, k, op, method, nrhs, x, y, lc);
+            if (f64) run_with<CD, double, CD, true>(t, k, op, method, n, x, y, lc);
+            else run_with<CF, float, CD, true>(t, k, op, method, n, x, y, lc);
         } else {
-            if (f64) run_with<double, double, double, false>(t, 0.0, op, method, nrhs, x, y, lc);
-            else run_with<float, float, double, false>(t, 0.0, op, method, nrhs, x, y, lc);
+            if (f64) run_with<double, double, double, false>(t, 0.0, op, method, n, x, y, lc);
+            else run_with<float, float, double, false>(t, 0.0, op, method, n, x, y, lc);
         }
     };
+    auto run = [&](const LaunchChoice &lc) { run_n(lc, nrhs); };
+    auto run1 = [&](const LaunchChoice &lc) { run_n(lc, 1); };  // the first right-hand side alone
     bool tuned = false;
     if (method == BEM_FMM) plan_fmm(t);  // the shape class reads the plan's pair counts
     LaunchChoice lc = method == BEM_FMM ? launch_choice(t, green, prec, op, &tuned) : LaunchChoice{};
     if (method == BEM_FMM && !tuned && c.autotune && !c.arena && !c.timing && t.n_p2p_items) {
         // Autotuner: the first product of an untuned shape class sets up
-        // everything with the default choice, then times candidates (event
-        // pairs on the context's stream around whole products, which end on
-        // that stream after the near field's stream has joined it; best of
-        // two each): the M2L waves per block first, then the near field's
-        // blocks per CU (with or without LDS left for one M2L block) with the
-        // best of those, then the waves again.  The products write y; the
-        // product proper follows with the fastest choice.
-        run(lc);
+        // everything with the default choice, then times candidates on the
+        // first right-hand side alone (event pairs on the context's stream
+        // around whole products, which end on that stream after the near
+        // field's stream has joined it; best of two each): the M2L waves per
+        // block (4 or 8) first, then the near field's blocks per CU (with or
+        // without LDS left for one M2L block) with the best of those, then
+        // the waves again.  (One block per CU and two-wave M2L blocks, never
+        // competitive where measured, are not tried.)  The products write y;
+        // the product proper follows with the fastest choice.
+        run1(lc);
         hipEvent_t e0, e1;
         BEM_HIP(hipEventCreate(&e0));
         BEM_HIP(hipEventCreate(&e1));
@@ -1061,7 +1065,7 @@ void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int 
             float best = 1e30f;
             for (int rep = 0; rep < 2; rep++) {
                 BEM_HIP(hipEventRecord(e0, c.stream));
-                run(cand);
+                run1(cand);
                 BEM_HIP(hipEventRecord(e1, c.stream));
                 BEM_HIP(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -1076,15 +1080,17 @@ void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int 
         };
         LaunchChoice best = lc;
         float tbest = time_of(lc);
-        for (int w : {2, 8}) {
+        // complex mixed products run at most four M2L waves per block
+        const bool w8 = !(green == BEM_HELMHOLTZ && !f64);
+        if (w8) {
             LaunchChoice cand = best;
-            cand.m2l_waves = w;
+            cand.m2l_waves = 8;
             const float tm = time_of(cand);
             if (tm < tbest) { tbest = tm; best = cand; }
         }
         const LaunchChoice base = best;
         for (int room = 0; room < 2; room++)
-            for (int pc : {1, 2, 3, 4, 6, 0}) {
+            for (int pc : {2, 3, 4, 6, 0}) {
                 if ((pc == base.p2p_per_cu && room == (int)base.m2l_room) || (room && (pc == 0 || pc > 3))) continue;
                 LaunchChoice cand = base;
                 cand.p2p_per_cu = pc;
@@ -1094,8 +1100,8 @@ void matvec(bem_tree &t, int green, double k, int op, int method, int prec, int 
             }
         // the waves per M2L block once more, beside the chosen near field
         const LaunchChoice fin = best;
-        for (int w : {2, 4, 8}) {
-            if (w == fin.m2l_waves) continue;
+        for (int w : {4, 8}) {
+            if (w == fin.m2l_waves || (w == 8 && !w8)) continue;
             LaunchChoice cand = fin;
             cand.m2l_waves = w;
             const float tm = time_of(cand);

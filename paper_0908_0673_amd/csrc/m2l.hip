@@ -404,43 +404,40 @@ __global__ void k_expand_T3(const double *D64, const int32_t *pk, const int32_t 
     }
 }
 
-// Canonical moments (as k_m2l_canonical_moments) as three-term splits:
-// Mc3[((u NA + part) 3 + s) K3 + a'], part 0 the real part, 1 the imaginary
-// part; zero past P.  One wave per combination.
-template <class V>
-__global__ void k_m2l_canonical_moments3(int64_t n_u, const int32_t *u_src, const int32_t *u_sym,
-                                         const int32_t *sym_in, int P, const V *mom, uint16_t *Mc3) {
-    far_field_priority();
-    constexpr int NA = std::is_same<V, float>::value ? 1 : 2;
-    const int64_t u = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-    if (u >= n_u) return;
-    const int lane = threadIdx.x & 63;
-    const V *ms = mom + (int64_t)u_src[u] * P;
-    const int32_t *si = sym_in + u_sym[u] * KIN;
+// The lane's eight B values of contraction block kb: moments a = 32 kb +
+// 8 (lane / 16) + i of its column (real, or for complex tasks the real or
+// imaginary part), zero past the stored KIN; FP32 as the canonical moments
+// kernel writes them, split into bf16 terms only in registers.
+template <int NA>
+__device__ inline void load_b(const float *mr, int kb, int kq, bool imag, float (&v)[8]) {
+    const int a0 = 32 * kb + 8 * kq;
+    if (a0 >= KIN) {  // KIN is a multiple of 8
 #pragma unroll
-    for (int it = 0; it < K3 / 64; it++) {
-        const int a = lane + 64 * it;
-        V v = V(0.0f);
-        if (a < P) {
-            const int32_t e = si[a];
-            v = ms[e & 0xffff];
-            if (e & SYM_NEG) v = V(0.0f) - v;
-        }
-        float part[2];
-        if constexpr (NA == 1) {
-            part[0] = v;
-        } else {
-            part[0] = v.re;
-            part[1] = v.im;
-        }
+        for (int i = 0; i < 8; i++) v[i] = 0.0f;
+        return;
+    }
+    if constexpr (NA == 1) {
+        const float4 x0 = *(const float4 *)(mr + a0), x1 = *(const float4 *)(mr + a0 + 4);
+        v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
+        v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+    } else {  // interleaved (re, im)
+        const float4 *pp = (const float4 *)(mr + 2 * a0);
 #pragma unroll
-        for (int q = 0; q < NA; q++) {
-            uint16_t tt[3];
-            split3(part[q], tt);
-#pragma unroll
-            for (int s3 = 0; s3 < 3; s3++) Mc3[((u * NA + q) * 3 + s3) * K3 + a] = tt[s3];
+        for (int h = 0; h < 4; h++) {
+            const float4 y = pp[h];
+            v[2 * h] = imag ? y.y : y.x;
+            v[2 * h + 1] = imag ? y.w : y.z;
         }
     }
+}
+__device__ inline void split_b(const float (&v)[8], uint4 (&B)[3]) {
+    uint16_t t[8][3];
+#pragma unroll
+    for (int i = 0; i < 8; i++) split3(v[i], t[i]);
+#pragma unroll
+    for (int s3 = 0; s3 < 3; s3++)
+        B[s3] = make_uint4(t[0][s3] | (uint32_t)t[1][s3] << 16, t[2][s3] | (uint32_t)t[3][s3] << 16,
+                           t[4][s3] | (uint32_t)t[5][s3] << 16, t[6][s3] | (uint32_t)t[7][s3] << 16);
 }
 
 // The products of one task on the split operands (as k_m2l with FP32 values,
@@ -450,12 +447,11 @@ __global__ void k_m2l_canonical_moments3(int64_t n_u, const int32_t *u_src, cons
 // whose B operands it loads from the split moments one contraction block
 // ahead.  The per-column arithmetic does not depend on W.
 template <int NA, int W>
-__global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, const uint4 *Mc3, float *out) {
+__global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, const float *Mc, float *out) {
     far_field_priority();
     constexpr int U4 = CH3 * 2 / 16;  // 16-byte pieces per chunk
     constexpr int PER = (U4 + 64 * W - 1) / (64 * W);
     constexpr int NCH = KB * NA;
-    constexpr int MROW = K3 / 8;      // 16-byte pieces per split moment row
     __shared__ uint4 As[2][U4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, task = blockIdx.x;
     const int cnt = a.task_count[task];
@@ -464,9 +460,10 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, c
     const int col = lane & 15, kq = lane >> 4;
     const int p = NA == 1 ? 16 * w + col : 8 * w + (col & 7);
     const int64_t u = p < cnt ? a.pair_mom[first + p] : 0;
-    // this lane's B rows: its column's moments (complex tasks: columns 8..15
+    // this lane's B values: its column's moments (complex tasks: columns 8..15
     // take the imaginary parts of the pairs of columns 0..7)
-    const uint4 *mb = Mc3 + (u * NA + (NA == 2 && col >= 8 ? 1 : 0)) * 3 * MROW + kq;
+    const float *mr = Mc + u * KIN * NA;
+    const bool imag = NA == 2 && col >= 8;
     const uint4 *Tg = T3 + (int64_t)c * NCH * U4;
     // pieces past the chunk are clamped to its last one: those threads load
     // and store the same value as its owner, so no branch is needed
@@ -480,12 +477,11 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, c
     };
     uint4 r[PER];
     fetch(0, r);
-    uint4 B[3], Bn[3];
-#pragma unroll
-    for (int s3 = 0; s3 < 3; s3++) {
-        B[s3] = mb[s3 * MROW];
-        Bn[s3] = mb[s3 * MROW + 4];
-    }
+    uint4 B[3];
+    float bn[8];  // the next block's values, in flight
+    load_b<NA>(mr, 0, kq, imag, bn);
+    split_b(bn, B);
+    load_b<NA>(mr, 1, kq, imag, bn);
     floatx4 acc[NA][MT];
 #pragma unroll
     for (int q = 0; q < NA; q++)
@@ -498,11 +494,8 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, c
     for (int ch = 0; ch < NCH; ch++) {
         const int kb = ch / NA, q = ch % NA;
         if (q == 0 && kb > 0) {
-#pragma unroll
-            for (int s3 = 0; s3 < 3; s3++) {
-                B[s3] = Bn[s3];
-                if (kb + 1 < KB) Bn[s3] = mb[s3 * MROW + 4 * (kb + 1)];
-            }
+            split_b(bn, B);
+            if (kb + 1 < KB) load_b<NA>(mr, kb + 1, kq, imag, bn);
         }
         const uint4 *Ab = As[ch & 1] + lane;
 #pragma unroll
@@ -1203,24 +1196,14 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
     const int64_t out_rows = split ? pl.parts_max : pl.slab_max_slots;
     V *out = (V *)work_buf(c, t.work.m2l_out, sizeof(V) * (size_t)std::max<int64_t>(1, out_rows) * OUT_LD);
     const LevelP lp = level_p(t);
-    const size_t mc_bytes = split ? sizeof(uint16_t) * 3 * NA * K3 : sizeof(V) * KIN;
-    void *Mc = work_buf(c, t.work.m2l_mom, mc_bytes * (size_t)std::max<int64_t>(1, pl.n_u));
+    void *Mc = work_buf(c, t.work.m2l_mom, sizeof(V) * KIN * (size_t)std::max<int64_t>(1, pl.n_u));
     const R *Tx = split ? nullptr : expanded<R>(t, pl);
     const uint4 *T3 = split ? (const uint4 *)expanded3(t, pl) : nullptr;
     for (int rhs = 0; rhs < nrhs; rhs++) {
         const V *m = mom + (int64_t)rhs * t.n_box * P;
         V *l = loc + (int64_t)rhs * t.n_box * P;
-        bool done = false;
-        if constexpr (std::is_same<R, float>::value) {
-            if (split) {
-                k_m2l_canonical_moments3<V><<<(unsigned)((pl.n_u + 3) / 4), 256, 0, c.stream>>>(
-                    pl.n_u, pl.u_src.p, pl.u_sym.p, pl.sym_in.p, P, m, (uint16_t *)Mc);
-                done = true;
-            }
-        }
-        if (!done)
-            k_m2l_canonical_moments<V><<<(unsigned)((pl.n_u + 3) / 4), 256, 0, c.stream>>>(
-                pl.n_u, pl.u_src.p, pl.u_sym.p, pl.sym_in.p, P, m, (V *)Mc);
+        k_m2l_canonical_moments<V><<<(unsigned)((pl.n_u + 3) / 4), 256, 0, c.stream>>>(
+            pl.n_u, pl.u_src.p, pl.u_sym.p, pl.sym_in.p, P, m, (V *)Mc);
         BEM_LAUNCH_CHECK();
         c.mark(10);
         // one slab of target boxes at a time: its pairs' results, then their sums
@@ -1239,7 +1222,7 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
                 if constexpr (std::is_same<R, float>::value) {
                     if (split) {
                         constexpr int WS = NA == 2 && W > 4 ? 4 : W;  // as split_waves
-                        k_m2l_x3<NA, WS><<<(unsigned)nt, 64 * WS, 0, c.stream>>>(a, T3, (const uint4 *)Mc, (float *)out);
+                        k_m2l_x3<NA, WS><<<(unsigned)nt, 64 * WS, 0, c.stream>>>(a, T3, (const float *)Mc, (float *)out);
                         return;
                     }
                 }
