@@ -213,8 +213,10 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
     using VD = typename std::conditional<HELM, cx<double>, double>::type;
     using R4 = typename r4<R>::type;
     constexpr int NW = P2P_BS / 64;
-    __shared__ int64_t pref[P2P_CH + 1];
-    __shared__ int64_t qbeg[P2P_CH];
+    // positions within the item's near-point sequence and point indices fit
+    // 32 bits (the planner checks the point count)
+    __shared__ int32_t pref[P2P_CH + 1];
+    __shared__ int32_t qbeg[P2P_CH];
     __shared__ double2 sxy[NW][2][64];
     __shared__ double szz[NW][2][64];
     __shared__ R4 sns[NW][2][64];
@@ -223,7 +225,7 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
     __shared__ VD subs[NW][64];
     const int u = unit_order[blockIdx.x], rhs = blockIdx.y;
     const int w = unit_item[u];
-    const int64_t u0 = unit_f[2 * u], u1 = unit_f[2 * u + 1];  // the unit's share of the item's near points
+    const int32_t u0 = (int32_t)unit_f[2 * u], u1 = (int32_t)unit_f[2 * u + 1];  // the unit's share of the item's near points
     const int b = wi_box[w], t0 = wi_t0[w], nt = wi_nt[w];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // tpw lanes hold the item's targets, TPL each (the last one repeated to
@@ -239,27 +241,29 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
         xt[q][2] = t64[2 * n_tgt + ti];
     }
     const V *sr = s + (int64_t)rhs * n_q;
+    const double *qx = q64, *qy = q64 + n_q, *qz = q64 + 2 * n_q;
+    const R *qnx = q + 4 * n_q, *qny = q + 5 * n_q, *qnz = q + 6 * n_q;
     VD tot[TPL];
 #pragma unroll
     for (int q = 0; q < TPL; q++) tot[q] = VD(0.0);
     const int64_t j0 = nptr[b], j1 = nptr[b + 1];
-    int64_t base = 0;  // position of the chunk's first point in the item's near-point sequence
+    int32_t base = 0;  // position of the chunk's first point in the item's near-point sequence
     for (int64_t cb = j0; cb < j1 && base < u1; cb += P2P_CH) {
         const int nc = (int)min<int64_t>(P2P_CH, j1 - cb);
         // run lengths of the chunk's near-list boxes, scanned by the first wave
         if (tid < 64) {
-            int64_t carry = 0;
+            int32_t carry = 0;
             for (int base = 0; base < nc; base += 64) {
                 const int i = base + lane;
-                int64_t len = 0;
+                int32_t len = 0;
                 if (i < nc) {
                     const int32_t nb_ = nidx[cb + i];
-                    qbeg[i] = 7 * eb[nb_];
-                    len = 7 * (ee[nb_] - eb[nb_]);
+                    qbeg[i] = (int32_t)(7 * eb[nb_]);
+                    len = (int32_t)(7 * (ee[nb_] - eb[nb_]));
                 }
-                int64_t incl = len;
+                int32_t incl = len;
                 for (int o = 1; o < 64; o <<= 1) {
-                    const int64_t u = __shfl_up(incl, o, 64);
+                    const int32_t u = __shfl_up(incl, o, 64);
                     if (lane >= o) incl += u;
                 }
                 if (i < nc) pref[i + 1] = carry + incl;
@@ -268,11 +272,11 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
             if (lane == 0) pref[0] = 0;
         }
         __syncthreads();
-        const int64_t total = pref[nc];
+        const int32_t total = pref[nc];
         // this wave's share of the unit's points in the chunk
-        const int64_t g0 = max<int64_t>(0, u0 - base), g1 = min<int64_t>(total, u1 - base);
-        const int64_t gn = max<int64_t>(0, g1 - g0), per = (gn + NW - 1) / NW;
-        const int64_t f0 = g0 + min(gn, per * wave), f1 = g0 + min(gn, per * wave + per);
+        const int32_t g0 = max(0, u0 - base), g1 = min(total, u1 - base);
+        const int32_t gn = max(0, g1 - g0), per = (gn + NW - 1) / NW;
+        const int32_t f0 = g0 + min(gn, per * wave), f1 = g0 + min(gn, per * wave + per);
         base += total;
         int e = 0;  // run holding this lane's current point
         // raw point records are loaded a batch ahead and only combined (strength
@@ -280,24 +284,24 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
         double rx = 0.0, ry = 0.0, rz = 0.0;
         R rnx = 0, rny = 0, rnz = 0;
         V rs = V(0.0);
-        auto fetch = [&](int64_t f) {
+        auto fetch = [&](int32_t f) {
             if (f < f1) {
                 while (pref[e + 1] <= f) e++;
-                const int64_t qi = qbeg[e] + (f - pref[e]);
-                rx = q64[qi];
-                ry = q64[n_q + qi];
-                rz = q64[2 * n_q + qi];
+                const uint32_t qi = (uint32_t)(qbeg[e] + (f - pref[e]));
+                rx = qx[qi];
+                ry = qy[qi];
+                rz = qz[qi];
                 rs = sr[qi];
                 if (DBL) {
-                    rnx = q[4 * n_q + qi];
-                    rny = q[5 * n_q + qi];
-                    rnz = q[6 * n_q + qi];
+                    rnx = qnx[qi];
+                    rny = qny[qi];
+                    rnz = qnz[qi];
                 }
             }
         };
         fetch(f0 + lane);
         int buf = 0;
-        for (int64_t fb = f0; fb < f1; fb += 64) {
+        for (int32_t fb = f0; fb < f1; fb += 64) {
             {
                 R4 ns;
                 ns.w = re_part(rs);
@@ -312,7 +316,7 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
             }
             __builtin_amdgcn_wave_barrier();
             fetch(fb + 64 + lane);  // next batch in flight while this one is computed
-            const int nin = (int)min<int64_t>(64, f1 - fb);
+            const int nin = min(64, f1 - fb);
             V acc[TPL];
 #pragma unroll
             for (int q = 0; q < TPL; q++) acc[q] = V(0.0);
@@ -668,6 +672,7 @@ void plan_fmm(bem_tree &t) {
             for (int32_t k = 0; k < wnt[i]; k++) titem[wt0[i] + k] = (int32_t)i;
         t.p2p_tgt_item = upload_i32(c, titem);
     }
+    BEM_REQUIRE(t.n_q < ((int64_t)1 << 31), BEM_EUNSUPPORTED, "more quadrature points than the near-field kernel indexes");
     // near-field pair count: targets x source points
     t.n_p2p_pairs = 0;
     for (int64_t b = 0; b < t.n_box; b++) {
