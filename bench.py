@@ -45,6 +45,9 @@ FP32_MFMA_PEAK = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 FP64_VEC_PEAK = 78.6
 BF16_MFMA_PEAK = 2500.0  # TFLOP/s: dense bf16 matrix peak (the split M2L's instruction)
 KERNEL_PEAKS = {"m2l": ("mfma", FP32_MFMA_PEAK), "p2p": ("alu", FP32_VEC_PEAK)}
+# leaf sizes of the served trees: Laplace, and Helmholtz per wavenumber bucket
+# (the C3 sweep: B = 64 is 5.6 times faster than B = 32 at ka = 10)
+SERVE_B, SERVE_B_HELMHOLTZ = 48, 64
 # source file of each timed kernel (the HBM traffic figures hold for one version of it)
 KERNEL_SOURCES = {"m2l": "m2l.hip", "p2p": "fmm.hip"}
 
@@ -662,7 +665,7 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_fracs=(0.5,), 
                 "iterations": {"median": float(np.median(it)), "max": int(it.max()), "mean": float(it.mean())}}
 
     srv = bem.Server(lanes=lanes, hbm_budget=budget, max_batch_rhs=32, precision=bem.BEM_PREC_MIXED, kappa=kappa,
-                     max_iters=max_iters, max_seconds=max_seconds)
+                     max_iters=max_iters, max_seconds=max_seconds, B=SERVE_B, helmholtz_B=SERVE_B_HELMHOLTZ)
     try:
         ids = {key: srv.add_mesh(m.xyz, m.elem)[0] for key, m in meshes.items()}
         dofs = {key: srv.mesh_dofs(i) for key, i in ids.items()}
@@ -739,8 +742,8 @@ def serving(count, seed, n_tri, ka, nrhs_max, lanes, budget, rate_fracs=(0.5,), 
             while trees and ctx.device_bytes()[0] > budget // 2:  # keep the baseline's residency bounded too
                 old = next(iter(trees))
                 trees.pop(old).close()
-            trees[tk] = bem.bem_tree_build(ctx, meshes_dev[r["key"]], B=32, order=8, theta=0.5, kappa=kappa,
-                                           k_hint=kh)
+            trees[tk] = bem.bem_tree_build(ctx, meshes_dev[r["key"]], B=SERVE_B_HELMHOLTZ if kh > 0 else SERVE_B,
+                                           order=8, theta=0.5, kappa=kappa, k_hint=kh)
         else:
             trees[tk] = trees.pop(tk)  # most recently used last
         tree = trees[tk]

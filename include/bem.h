@@ -386,6 +386,9 @@ typedef struct {
                                 tree, whose lists hold for every k <= k_hint, and requests
                                 with a larger k are refused */
     bem_solve_opts solve;    /* solve options of every request (zero fields -> defaults) */
+    int helmholtz_B;         /* leaf size of the per-wavenumber-bucket Helmholtz trees (kappa > 0,
+                                k_hint = 0); 0 -> tree.B.  High wavenumbers favour larger leaves:
+                                the bound leaves few boxes small enough to interact */
 } bem_server_opts;
 
 typedef struct {

@@ -85,7 +85,8 @@ class _SolveOpts(ctypes.Structure):
 
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("lanes", ctypes.c_int), ("hbm_budget", ctypes.c_int64),
-                ("max_batch_rhs", ctypes.c_int), ("tree", _TreeOpts), ("solve", _SolveOpts)]
+                ("max_batch_rhs", ctypes.c_int), ("tree", _TreeOpts), ("solve", _SolveOpts),
+                ("helmholtz_B", ctypes.c_int)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -436,7 +437,7 @@ class Server:
     def __init__(self, device=0, lanes=4, hbm_budget=32 << 30, max_batch_rhs=32, tol=1e-8, restart=50,
                  max_restarts=100, precision=BEM_PREC_FP64, inner_tol=0.0, max_iters=0, method=BEM_FMM,
                  krylov=BEM_KRYLOV_GMRES, B=32, order=8, theta=0.5, kappa=0.0, max_depth=21, order_min=0,
-                 k_hint=0.0, attach_radii=0, max_seconds=0.0):
+                 k_hint=0.0, attach_radii=0, max_seconds=0.0, helmholtz_B=0):
         self.L = load_library()
         import torch
 
@@ -444,9 +445,11 @@ class Server:
             raise RuntimeError("no GPU visible: the library runs on gfx950 only")
         o = _ServerOpts()
         o.device, o.lanes, o.hbm_budget, o.max_batch_rhs = device, lanes, int(hbm_budget), max_batch_rhs
-        # kappa > 0 with k_hint = 0: every Helmholtz batch gets a tree of its own k;
-        # with k_hint > 0 the mesh's one tree serves every k up to k_hint
+        # kappa > 0 with k_hint = 0: Helmholtz requests use a tree per wavenumber
+        # bucket (leaf size helmholtz_B, or B when 0); with k_hint > 0 the mesh's
+        # one tree serves every k up to k_hint
         o.tree = _TreeOpts(B, order, theta, kappa, max_depth, k_hint, order_min, int(attach_radii))
+        o.helmholtz_B = int(helmholtz_B)
         o.solve = _SolveOpts(tol, restart, max_restarts, precision, inner_tol, max_iters, method, krylov, max_seconds)
         h = ctypes.c_void_p()
         rc = self.L.bem_server_create(ctypes.byref(o), ctypes.byref(h))

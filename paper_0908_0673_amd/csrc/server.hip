@@ -165,6 +165,7 @@ int run_batch(bem_server *s, Lane &L, MeshEntry &me, TreeEntry &te, double key, 
     if (fresh) {
         bem_tree_opts to = s->o.tree;
         to.k_hint = key;
+        if (key > 0.0 && s->o.helmholtz_B > 0) to.max_elems_per_leaf = s->o.helmholtz_B;  // a per-wavenumber tree
         rc = bem_tree_build(ctx, me.mesh, &to, &te.tree);
         if (rc != BEM_OK) return rc;
         std::lock_guard<std::mutex> lk(s->mu);
@@ -338,7 +339,7 @@ int bem_server_create(const bem_server_opts *opts, bem_server **out) {
     if (o.hbm_budget == 0) o.hbm_budget = (int64_t)32 << 30;
     if (o.max_batch_rhs == 0) o.max_batch_rhs = 32;
     if (o.lanes < 1 || o.lanes > 64 || o.hbm_budget < 0 || o.max_batch_rhs < 1) return BEM_EINVAL;
-    if (o.solve.max_iters < 0 || o.solve.max_seconds < 0.0) return BEM_EINVAL;
+    if (o.solve.max_iters < 0 || o.solve.max_seconds < 0.0 || o.helmholtz_B < 0) return BEM_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) return BEM_EDEVICE;
     if (hipSetDevice(o.device) != hipSuccess) return BEM_EDEVICE;

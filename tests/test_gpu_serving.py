@@ -242,16 +242,17 @@ def _bucket_top(k):
     return 2.0 ** (np.ceil(4.0 * np.log2(k) - 1e-12) / 4.0)
 
 
-def test_server_helmholtz_trees_per_wavenumber_bucket():
+@pytest.mark.parametrize("helmholtz_B", [0, 48])
+def test_server_helmholtz_trees_per_wavenumber_bucket(helmholtz_B):
     """With the wavenumber bound on the lists (kappa > 0, no fixed k_hint),
     Helmholtz batches are solved on the mesh's resident tree for their
-    wavenumber bucket (lists built for the bucket's top): results equal
-    bem_solve's on such a tree, bit for bit, and wavenumbers of one bucket
-    share one tree."""
+    wavenumber bucket (lists built for the bucket's top, leaf size
+    helmholtz_B when set): results equal bem_solve's on such a tree, bit for
+    bit, and wavenumbers of one bucket share one tree."""
     bem = _bem()
     mesh = bem_inputs.icosphere(3)
     rng = np.random.default_rng(17)
-    srv = bem.Server(lanes=1, max_batch_rhs=4, precision=1, kappa=2.2, **TREE)
+    srv = bem.Server(lanes=1, max_batch_rhs=4, precision=1, kappa=2.2, helmholtz_B=helmholtz_B, **TREE)
     ks = (4.0, 7.5, 7.1)  # 7.5 and 7.1 share the bucket whose top is 8
     try:
         mid, nd = srv.add_mesh(mesh.xyz, mesh.elem)
@@ -265,7 +266,8 @@ def test_server_helmholtz_trees_per_wavenumber_bucket():
     m = bem.bem_mesh_load(ctx, mesh.xyz, mesh.elem)
     for k, chi, (rc, phi, info, lat) in zip(ks, chis, res):
         assert rc == 0 and all(i["status"] == 0 for i in info)
-        t = bem.bem_tree_build(ctx, m, kappa=2.2, k_hint=_bucket_top(k), **TREE)
+        topts = dict(TREE, B=helmholtz_B) if helmholtz_B else TREE
+        t = bem.bem_tree_build(ctx, m, kappa=2.2, k_hint=_bucket_top(k), **topts)
         for r in range(2):
             d = to_dev(chi[r][None], True)
             p = d.clone()

@@ -70,6 +70,9 @@ def test_server_options_are_checked_before_any_device_work():
     assert L.bem_server_create(ctypes.byref(o), ctypes.byref(h)) == bem.BEM_EINVAL
     o.lanes, o.max_batch_rhs = 1, -3
     assert L.bem_server_create(ctypes.byref(o), ctypes.byref(h)) == bem.BEM_EINVAL
+    o.max_batch_rhs, o.helmholtz_B = 1, -1
+    assert L.bem_server_create(ctypes.byref(o), ctypes.byref(h)) == bem.BEM_EINVAL
+    o.helmholtz_B = 0
     o.max_batch_rhs, o.device = 1, 1 << 20  # no such device
     assert L.bem_server_create(ctypes.byref(o), ctypes.byref(h)) == bem.BEM_EDEVICE
     assert not h.value
