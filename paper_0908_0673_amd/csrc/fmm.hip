@@ -148,17 +148,24 @@ template <> struct r4<double> { using type = double4; };
 __device__ inline float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Adds the kernel value times the strength of one (target, source point)
-// pair to acc; d is the target minus the point, ns the point's record.
-// Laplace: the record holds (s n, s), so the double layer is (d . s n) / r^3
-// and the single layer s / r.  Helmholtz: the record holds (n, Re s) and Im s;
-// the value is a (u + j v) times s with a = 1/r, u + j v = e^{jkr} (single
-// layer) or a = (d . n) / r^3, u = cos kr + kr sin kr, v = sin kr - kr cos kr
-// (double layer: the normal derivative at the point of e^{jkr}/r), and the
-// complex product is accumulated by four fused multiply-adds.  The 1/(4 pi)
-// of G is applied once per target by the caller.
-template <bool DBL, bool HELM, class R, class A>
-__device__ inline void p2p_add(A &acc, R d0, R d1, R d2, typename r4<R>::type ns, R si, R k) {
+// One (target, source point) pair; d is the target minus the point, ns the
+// point's record for one right-hand side.  Laplace: the record holds
+// (s n, s), so the double layer is (d . s n) / r^3 and the single layer s / r.
+// Helmholtz: the record holds (n, Re s) and Im s; the value is a (u + j v)
+// times s with a = 1/r, u + j v = e^{jkr} (single layer) or a = (d . n) / r^3,
+// u = cos kr + kr sin kr, v = sin kr - kr cos kr (double layer: the normal
+// derivative at the point of e^{jkr}/r), and the complex product is
+// accumulated by four fused multiply-adds.  The 1/(4 pi) of G is applied
+// once per target by the caller.  p2p_pair forms what every right-hand side
+// shares (Laplace: 1/r and 1/r^3; Helmholtz: a u and a v), p2p_acc adds one
+// right-hand side's term, by the same operations whatever the number of
+// right-hand sides the kernel serves at once.
+template <class R>
+struct PairTerm {
+    R x, y;
+};
+template <bool DBL, bool HELM, class R>
+__device__ inline PairTerm<R> p2p_pair(R d0, R d1, R d2, typename r4<R>::type ns, R k) {
     const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
     const R ir = inv_sqrt(r2);
     if constexpr (HELM) {
@@ -167,7 +174,10 @@ __device__ inline void p2p_add(A &acc, R d0, R d1, R d2, typename r4<R>::type ns
         sincos_turns(kr, &sn, &cs);
         R a, u, v;
         if (DBL) {
-            a = (d0 * ns.x + d1 * ns.y + d2 * ns.z) * (ir * ir) * ir;
+            R t = d1 * ns.y;
+            t = fmar(d0, ns.x, t);
+            t = fmar(d2, ns.z, t);
+            a = t * (ir * ir) * ir;
             u = fmar(kr, sn, cs);
             v = fmar(-kr, cs, sn);
         } else {
@@ -175,14 +185,25 @@ __device__ inline void p2p_add(A &acc, R d0, R d1, R d2, typename r4<R>::type ns
             u = cs;
             v = sn;
         }
-        const R au = a * u, av = a * v;
-        acc.re = fmar(au, ns.w, acc.re);
-        acc.re = fmar(-av, si, acc.re);
-        acc.im = fmar(au, si, acc.im);
-        acc.im = fmar(av, ns.w, acc.im);
+        return {a * u, a * v};
     } else {
-        if (DBL) acc += (d0 * ns.x + d1 * ns.y + d2 * ns.z) * (ir * ir * ir);
-        else acc += ns.w * ir;
+        return {ir, (ir * ir) * ir};
+    }
+}
+template <bool DBL, bool HELM, class R, class A>
+__device__ inline void p2p_acc(A &acc, const PairTerm<R> &pt, R d0, R d1, R d2, typename r4<R>::type ns, R si) {
+    if constexpr (HELM) {
+        acc.re = fmar(pt.x, ns.w, acc.re);
+        acc.re = fmar(-pt.y, si, acc.re);
+        acc.im = fmar(pt.x, si, acc.im);
+        acc.im = fmar(pt.y, ns.w, acc.im);
+    } else if constexpr (DBL) {
+        R t = d1 * ns.y;
+        t = fmar(d0, ns.x, t);
+        t = fmar(d2, ns.z, t);
+        acc = fmar(t, pt.y, acc);
+    } else {
+        acc = fmar(ns.w, pt.x, acc);
     }
 }
 
@@ -201,14 +222,17 @@ __device__ inline void p2p_add(A &acc, R d0, R d1, R d2, typename r4<R>::type ns
 // relative to a common origin a leaf side away (one subtraction instead of
 // two instructions per axis) puts errors of about 1e-5 into products of the
 // 20480-element sphere.  Per-batch partial sums in R are added into an FP64
-// total.
-template <class V, class R, bool DBL, bool HELM, int TPL>
+// total.  A block serves NR right-hand sides (grid y: groups of NR): each
+// pair's geometry is formed once and its terms added per right-hand side,
+// every right-hand side's sums running exactly as with NR = 1 (bitwise the
+// same results).
+template <class V, class R, bool DBL, bool HELM, int TPL, int NR>
 __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const int32_t *unit_item,
                                                 const int64_t *unit_f, int64_t n_unit, const int32_t *wi_box,
                                                 const int32_t *wi_t0, const int32_t *wi_nt, const int64_t *nptr,
                                                 const int32_t *nidx, const int64_t *eb, const int64_t *ee,
                                                 const double *q64, const R *q, int64_t n_q, const V *s,
-                                                const double *t64, int64_t n_tgt, R k,
+                                                const double *t64, int64_t n_tgt, R k, int nrhs,
                                                 typename std::conditional<HELM, cx<double>, double>::type *part) {
     using VD = typename std::conditional<HELM, cx<double>, double>::type;
     using R4 = typename r4<R>::type;
@@ -219,11 +243,11 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
     __shared__ int32_t qbeg[P2P_CH];
     __shared__ double2 sxy[NW][2][64];
     __shared__ double szz[NW][2][64];
-    __shared__ R4 sns[NW][2][64];
-    __shared__ R ssi[NW][2][HELM ? 64 : 1];
+    __shared__ R4 sns[NW][2][64][NR];
+    __shared__ R ssi[NW][2][HELM ? 64 : 1][NR];
     __shared__ VD red[NW][64];
     __shared__ VD subs[NW][64];
-    const int u = unit_order[blockIdx.x], rhs = blockIdx.y;
+    const int u = unit_order[blockIdx.x], rhs0 = blockIdx.y * NR;  // the block's first right-hand side
     const int w = unit_item[u];
     const int32_t u0 = (int32_t)unit_f[2 * u], u1 = (int32_t)unit_f[2 * u + 1];  // the unit's share of the item's near points
     const int b = wi_box[w], t0 = wi_t0[w], nt = wi_nt[w];
@@ -240,12 +264,16 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
         xt[q][1] = t64[n_tgt + ti];
         xt[q][2] = t64[2 * n_tgt + ti];
     }
-    const V *sr = s + (int64_t)rhs * n_q;
+    const V *sr[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) sr[r] = s + (int64_t)min(rhs0 + r, nrhs - 1) * n_q;
     const double *qx = q64, *qy = q64 + n_q, *qz = q64 + 2 * n_q;
     const R *qnx = q + 4 * n_q, *qny = q + 5 * n_q, *qnz = q + 6 * n_q;
-    VD tot[TPL];
+    VD tot[TPL][NR];
 #pragma unroll
-    for (int q = 0; q < TPL; q++) tot[q] = VD(0.0);
+    for (int q = 0; q < TPL; q++)
+#pragma unroll
+        for (int r = 0; r < NR; r++) tot[q][r] = VD(0.0);
     const int64_t j0 = nptr[b], j1 = nptr[b + 1];
     int32_t base = 0;  // position of the chunk's first point in the item's near-point sequence
     for (int64_t cb = j0; cb < j1 && base < u1; cb += P2P_CH) {
@@ -283,7 +311,9 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
         // into the normal) when stored, so the loads stay in flight meanwhile
         double rx = 0.0, ry = 0.0, rz = 0.0;
         R rnx = 0, rny = 0, rnz = 0;
-        V rs = V(0.0);
+        V rs[NR];
+#pragma unroll
+        for (int r = 0; r < NR; r++) rs[r] = V(0.0);
         auto fetch = [&](int32_t f) {
             if (f < f1) {
                 while (pref[e + 1] <= f) e++;
@@ -291,7 +321,8 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
                 rx = qx[qi];
                 ry = qy[qi];
                 rz = qz[qi];
-                rs = sr[qi];
+#pragma unroll
+                for (int r = 0; r < NR; r++) rs[r] = sr[r][qi];
                 if (DBL) {
                     rnx = qnx[qi];
                     rny = qny[qi];
@@ -303,57 +334,77 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
         int buf = 0;
         for (int32_t fb = f0; fb < f1; fb += 64) {
             {
-                R4 ns;
-                ns.w = re_part(rs);
-                const R sc = HELM ? (R)1 : ns.w;  // Laplace: strength folded into the normal
-                ns.x = rnx * sc;
-                ns.y = rny * sc;
-                ns.z = rnz * sc;
                 sxy[wave][buf][lane] = make_double2(rx, ry);
                 szz[wave][buf][lane] = rz;
-                sns[wave][buf][lane] = ns;
-                if constexpr (HELM) ssi[wave][buf][lane] = rs.im;
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    R4 ns;
+                    ns.w = re_part(rs[r]);
+                    const R sc = HELM ? (R)1 : ns.w;  // Laplace: strength folded into the normal
+                    ns.x = rnx * sc;
+                    ns.y = rny * sc;
+                    ns.z = rnz * sc;
+                    sns[wave][buf][lane][r] = ns;
+                    if constexpr (HELM) ssi[wave][buf][lane][r] = rs[r].im;
+                }
             }
             __builtin_amdgcn_wave_barrier();
             fetch(fb + 64 + lane);  // next batch in flight while this one is computed
             const int nin = min(64, f1 - fb);
-            V acc[TPL];
+            V acc[TPL][NR];
 #pragma unroll
-            for (int q = 0; q < TPL; q++) acc[q] = V(0.0);
+            for (int q = 0; q < TPL; q++)
+#pragma unroll
+                for (int r = 0; r < NR; r++) acc[q][r] = V(0.0);
 #pragma unroll(8 / TPL)
             for (int kk = sub < nsub ? sub : nin; kk < nin; kk += nsub) {
                 const double2 cxy = sxy[wave][buf][kk];
                 const double cz = szz[wave][buf][kk];
-                const R4 cns = sns[wave][buf][kk];
-                const R csi = HELM ? ssi[wave][buf][HELM ? kk : 0] : (R)0;
+                R4 cns[NR];
+                R csi[NR];
 #pragma unroll
-                for (int q = 0; q < TPL; q++)
-                    p2p_add<DBL, HELM>(acc[q], (R)(xt[q][0] - cxy.x), (R)(xt[q][1] - cxy.y), (R)(xt[q][2] - cz), cns,
-                                       csi, k);
+                for (int r = 0; r < NR; r++) {
+                    cns[r] = sns[wave][buf][kk][r];
+                    csi[r] = HELM ? ssi[wave][buf][HELM ? kk : 0][r] : (R)0;
+                }
+#pragma unroll
+                for (int q = 0; q < TPL; q++) {
+                    const R d0 = (R)(xt[q][0] - cxy.x), d1 = (R)(xt[q][1] - cxy.y), d2 = (R)(xt[q][2] - cz);
+                    const PairTerm<R> pt = p2p_pair<DBL, HELM>(d0, d1, d2, cns[0], k);
+#pragma unroll
+                    for (int r = 0; r < NR; r++) p2p_acc<DBL, HELM>(acc[q][r], pt, d0, d1, d2, cns[r], csi[r]);
+                }
             }
 #pragma unroll
-            for (int q = 0; q < TPL; q++) tot[q] += vcast<VD>(acc[q]);
+            for (int q = 0; q < TPL; q++)
+#pragma unroll
+                for (int r = 0; r < NR; r++) tot[q][r] += vcast<VD>(acc[q][r]);
             buf ^= 1;
         }
         __syncthreads();  // pref / qbeg are rewritten by the next chunk
     }
-    // reduce over the wave's groups (lanes tl, tl + tpw, ...), in group order
+    // per right-hand side: reduce over the wave's groups (lanes tl, tl + tpw,
+    // ...), in group order, then over the waves in wave order
 #pragma unroll
-    for (int q = 0; q < TPL; q++) {
-        subs[wave][lane] = tot[q];
-        __builtin_amdgcn_wave_barrier();
-        if (sub == 0) {
-            VD v = tot[q];
-            for (int k = 1; k < nsub; k++) v += subs[wave][tl + k * tpw];
-            if (TPL * tl + q < 64) red[wave][TPL * tl + q] = v;
+    for (int r = 0; r < NR; r++) {
+#pragma unroll
+        for (int q = 0; q < TPL; q++) {
+            subs[wave][lane] = tot[q][r];
+            __builtin_amdgcn_wave_barrier();
+            if (sub == 0) {
+                VD v = tot[q][r];
+                for (int k = 1; k < nsub; k++) v += subs[wave][tl + k * tpw];
+                if (TPL * tl + q < 64) red[wave][TPL * tl + q] = v;
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
-    }
-    __syncthreads();
-    if (tid < nt) {
-        VD v = red[0][tid];
-        for (int wv = 1; wv < NW; wv++) v += red[wv][tid];
-        part[((int64_t)rhs * n_unit + u) * 64 + tid] = v;
+        __syncthreads();
+        if (tid < nt && rhs0 + r < nrhs) {
+            VD v = red[0][tid];
+            for (int wv = 1; wv < NW; wv++) v += red[wv][tid];
+            part[((int64_t)(rhs0 + r) * n_unit + u) * 64 + tid] = v;
+        }
+        if (NR > 1) __syncthreads();  // red is rewritten for the next right-hand side
     }
 }
 
@@ -892,21 +943,32 @@ void run_matvec(bem_tree &t, double k, int op, int method, int nrhs, const XV *x
             const long pad = avail / lc.p2p_per_cu - (long)fa.sharedSizeBytes - 256;
             return memo[key] = pad > 0 ? (unsigned)pad : 0u;
         };
+        // Several right-hand sides: two per block, sharing each pair's geometry.
         auto near_field = [&](hipStream_t st) {
-            dim3 g((unsigned)t.n_p2p_units, nrhs);
             const bool beside = st != c.stream;
             c.kbegin(st, 6);
             constexpr int TPL = P2P_TPL;
-            if (dbl)
-                k_p2p<V, R, true, HELM, TPL><<<g, P2P_BS,
-                                               beside ? near_lds((const void *)k_p2p<V, R, true, HELM, TPL>) : 0, st>>>(
+            auto launch = [&](auto nr, auto dl) {
+                constexpr int NR = decltype(nr)::value;
+                constexpr bool DL = decltype(dl)::value;
+                const void *fn = (const void *)k_p2p<V, R, DL, HELM, TPL, NR>;
+                dim3 g((unsigned)t.n_p2p_units, (unsigned)((nrhs + NR - 1) / NR));
+                k_p2p<V, R, DL, HELM, TPL, NR><<<g, P2P_BS, beside ? near_lds(fn) : 0, st>>>(
                     t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
-                    t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
-            else
-                k_p2p<V, R, false, HELM, TPL><<<g, P2P_BS,
-                                                beside ? near_lds((const void *)k_p2p<V, R, false, HELM, TPL>) : 0, st>>>(
-                    t.p2p_unit_order.p, t.p2p_unit_item.p, t.p2p_unit_f.p, t.n_p2p_units, t.p2p_box.p, t.p2p_t0.p,
-                    t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, part);
+                    t.p2p_nt.p, t.near_ptr.p, t.near_idx.p, t.eb.p, t.ee.p, t.q64.p, q, nq, s, t.t64.p, nt, (R)k, nrhs,
+                    part);
+            };
+            using one = std::integral_constant<int, 1>;
+            using two = std::integral_constant<int, 2>;
+            using yes = std::true_type;
+            using no = std::false_type;
+            if (nrhs > 1) {
+                if (dbl) launch(two(), yes());
+                else launch(two(), no());
+            } else {
+                if (dbl) launch(one(), yes());
+                else launch(one(), no());
+            }
             BEM_LAUNCH_CHECK();
             c.kend(st);
         };
