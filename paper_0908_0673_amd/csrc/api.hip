@@ -236,8 +236,14 @@ int bem_tree_build(bem_ctx *ctx, const bem_mesh *mesh, const bem_tree_opts *opts
         BEM_REQUIRE(t->order >= 1 && t->order <= 8, BEM_EUNSUPPORTED, "expansion order must be 1..8");
         BEM_REQUIRE(t->max_depth <= bem::MAXLEV, BEM_EINVAL, "max_depth must be <= 21");
         BEM_REQUIRE(t->theta > 0.0 && t->theta <= 1.0, BEM_EINVAL, "theta must be in (0, 1]");
-        bem::build_tree(*t);
-        bem::build_geometry(*t);
+        {
+            bem::SetupTimer st_(ctx->c, "tree and lists");
+            bem::build_tree(*t);
+        }
+        {
+            bem::SetupTimer st_(ctx->c, "geometry in tree order");
+            bem::build_geometry(*t);
+        }
         ctx->c.sync();
     });
     if (rc != BEM_OK) {

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <stdexcept>
@@ -296,6 +299,25 @@ struct Ctx {
 // Zeroes `bytes` bytes at device address p on the context's stream with a
 // fill kernel (no memset node, so the call can sit in a captured graph).
 void zero_fill(Ctx &c, void *p, size_t bytes);
+
+// With BEM_SETUP_LOG set in the environment, the wall time of a set-up step
+// (its device work synchronised first) goes to stderr when the scope ends.
+struct SetupTimer {
+    Ctx *c;
+    const char *what;
+    std::chrono::steady_clock::time_point t0;
+    bool on;
+    SetupTimer(Ctx &ctx, const char *w) : c(&ctx), what(w), t0(std::chrono::steady_clock::now()) {
+        static const bool log = std::getenv("BEM_SETUP_LOG") != nullptr;
+        on = log;
+    }
+    ~SetupTimer() {
+        if (!on) return;
+        (void)hipStreamSynchronize(c->stream);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        std::fprintf(stderr, "bem setup: %s %.2f ms\n", what, ms);
+    }
+};
 
 // Device array owned by the library, released through the context's allocator.
 template <class T>

@@ -635,6 +635,7 @@ static DBuf<int32_t> upload_i32(Ctx &c, const std::vector<int32_t> &v) {
 
 void plan_fmm(bem_tree &t) {
     if (t.planned) return;
+    SetupTimer st_(*t.ctx, "near and far plans");
     Ctx &c = *t.ctx;
     std::vector<int32_t> src_leaves, tgt_leaves, m2l, wb, wt0, wnt;
     for (int64_t b = 0; b < t.n_box; b++) {

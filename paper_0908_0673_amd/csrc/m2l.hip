@@ -736,6 +736,7 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     if (green == BEM_HELMHOLTZ) evict_wavenumbers(t.m2l);
     fmm_tables(t);
     plan_fmm(t);
+    SetupTimer st_(c, "M2L plan (classes, pairs, slabs, derivative tables)");
     FmmTables &T = *t.tables;
     const int p = t.order, P = T.P, P2 = T.P2, H = 2 * p;
     BEM_REQUIRE(P <= MT * 16 && P <= KIN && P <= 3 * 64, BEM_EUNSUPPORTED, "expansion order too high for the M2L tiles");
@@ -1044,6 +1045,7 @@ const uint16_t *expanded3(bem_tree &t, M2lPlan &pl) {
     Ctx &c = *t.ctx;
     FmmTables &T = *t.tables;
     if (!pl.T3.p && pl.n_class) {
+        SetupTimer st_(c, "M2L split operators");
         const bool helm = pl.green == BEM_HELMHOLTZ;
         pl.T3.alloc(&c, (size_t)(helm ? 2 : 1) * KB * CH3 * pl.n_class);
         dim3 g((unsigned)pl.n_class, KB * MT);
@@ -1069,6 +1071,7 @@ void build_parts(bem_tree &t, M2lPlan &pl) {
     constexpr int G = 8;  // as the product kernel
     if (pl.parts_g == G) return;
     Ctx &c = *t.ctx;
+    SetupTimer st_(c, "M2L partial slots");
     std::vector<int32_t> slot_box(std::max<int64_t>(1, t.n_inter), -1), box_x(t.n_box, -1);
     int32_t nx = 0;
     for (int64_t b = 0; b < t.n_box; b++) {

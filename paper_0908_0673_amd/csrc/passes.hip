@@ -328,6 +328,7 @@ void build_pass_tables(bem_tree &t) {
     Ctx &c = *t.ctx;
     fmm_tables(t);
     plan_fmm(t);
+    SetupTimer st_(c, "P2M weights and L2P monomials");
     FmmTables &T = *t.tables;
     const int p = t.order, P = T.P;
     // DOF slots of each source leaf

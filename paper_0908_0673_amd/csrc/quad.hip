@@ -311,6 +311,7 @@ __global__ void k_free_term(int64_t n_tgt, const int32_t *tperm, const double *r
 void build_pairs(bem_tree &t) {
     if (t.has_pairs) return;
     Ctx &c = *t.ctx;
+    SetupTimer st_(c, "correction pair search");
     const bem_mesh &m = *t.mesh;
     DBuf<int64_t> cnt;
     cnt.alloc(&c, t.n_tgt);
@@ -350,6 +351,7 @@ Corr &get_corr(bem_tree &t, int green, double k) {
         }
     build_pairs(t);
     Ctx &c = *t.ctx;
+    SetupTimer st_(c, "corrections");
     if (green == BEM_HELMHOLTZ) evict_wavenumbers(t.corr);
     auto cr = std::make_unique<Corr>();
     cr->green = green;
@@ -381,6 +383,7 @@ Corr &get_corr(bem_tree &t, int green, double k) {
 void build_free_term(bem_tree &t) {
     if (t.has_free_term) return;
     Ctx &c = *t.ctx;
+    SetupTimer st_(c, "free term");
     const bem_mesh &m = *t.mesh;
     for (const auto &f : m.free_terms)
         if (f->B == t.B && f->max_depth == t.max_depth && f->attach == t.attach && f->literal == t.literal) {
