@@ -317,6 +317,16 @@ struct SetupTimer {
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         std::fprintf(stderr, "bem setup: %s %.2f ms\n", what, ms);
     }
+    // the time since construction or the previous lap, as a sub-step
+    void lap(const char *part) {
+        if (!on) return;
+        (void)hipStreamSynchronize(c->stream);
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "bem setup:   %s: %s %.2f ms\n", what, part,
+                     std::chrono::duration<double, std::milli>(now - (tl.time_since_epoch().count() ? tl : t0)).count());
+        tl = now;
+    }
+    std::chrono::steady_clock::time_point tl{};
 };
 
 // Device array owned by the library, released through the context's allocator.

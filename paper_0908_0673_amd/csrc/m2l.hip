@@ -45,10 +45,10 @@
 // not depend on scheduling (no float atomics).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <type_traits>
-#include <unordered_map>
 
 #include "greens.h"
 #include "kernels.h"
@@ -688,6 +688,32 @@ struct ClassKeyHash {
     }
 };
 
+// Class ids by key in order of first appearance (open addressing, linear
+// probing; the table is kept at most half full).
+struct ClassIds {
+    std::vector<ClassKey> keys;
+    std::vector<int32_t> tab = std::vector<int32_t>(1024, -1);
+    int32_t get(const ClassKey &k, bool &added) {
+        size_t m = tab.size() - 1, h = ClassKeyHash()(k) & m;
+        for (; tab[h] >= 0; h = (h + 1) & m)
+            if (keys[tab[h]] == k) return tab[h];
+        added = true;
+        const int32_t id = (int32_t)keys.size();
+        keys.push_back(k);
+        tab[h] = id;
+        if (2 * keys.size() > tab.size()) {
+            tab.assign(2 * tab.size(), -1);
+            m = tab.size() - 1;
+            for (int32_t i = 0; i < (int32_t)keys.size(); i++) {
+                size_t x = ClassKeyHash()(keys[i]) & m;
+                while (tab[x] >= 0) x = (x + 1) & m;
+                tab[x] = i;
+            }
+        }
+        return id;
+    }
+};
+
 uint64_t compact3h(uint64_t v) {
     uint64_t r = 0;
     for (int b = 0; b < 21; b++) r |= ((v >> (3 * b)) & 1u) << b;
@@ -746,21 +772,23 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     pl->k = k;
     pl->last_use = ++t.k_uses;
     if (t.h_prefix.empty()) t.h_prefix = t.prefix.download(t.n_box);
-    // canonical classes of the interaction pairs of boxes with targets
-    std::unordered_map<ClassKey, int32_t, ClassKeyHash> id;
-    std::vector<std::vector<int32_t>> members;  // slots
-    std::vector<std::vector<int32_t>> msym, mlev;  // symmetry and target level of each member
-    std::vector<int32_t> cdelta;
+    // integer centre coordinates of every box, in half-widths of its own level
+    std::vector<int64_t> bxyz((size_t)3 * t.n_box);
+    for (int64_t b = 0; b < t.n_box; b++)
+        for (int e = 0; e < 3; e++) bxyz[3 * b + e] = (int64_t)compact3h(t.h_prefix[b] >> (2 - e));
+    // canonical classes of the interaction pairs of boxes with targets, ids in
+    // order of first appearance; class and symmetry of every slot
+    ClassIds id;
+    std::vector<int32_t> cdelta, csize;
     std::vector<double> rbar, kbar;
+    std::vector<int32_t> pcls(std::max<int64_t>(1, t.n_inter), -1), psym(std::max<int64_t>(1, t.n_inter), 0);
     for (int64_t b = 0; b < t.n_box; b++) {
         if (t.h_te[b] == t.h_tb[b]) continue;
-        const uint64_t pb = t.h_prefix[b];
-        const int64_t ib[3] = {(int64_t)compact3h(pb >> 2), (int64_t)compact3h(pb >> 1), (int64_t)compact3h(pb)};
+        const int64_t *ib = &bxyz[3 * b];
         for (int64_t j = t.h_inter_ptr[b]; j < t.h_inter_ptr[b + 1]; j++) {
             const int32_t s = t.h_inter_idx[j];
             const int d = t.h_level[b] - t.h_level[s];
-            const uint64_t ps = t.h_prefix[s];
-            const int64_t is[3] = {(int64_t)compact3h(ps >> 2), (int64_t)compact3h(ps >> 1), (int64_t)compact3h(ps)};
+            const int64_t *is = &bxyz[3 * (int64_t)s];
             int64_t q[3], u[3];
             int flips = 0;
             for (int e = 0; e < 3; e++) {
@@ -775,46 +803,25 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
                 if (u[sg[0]] <= u[sg[1]] && u[sg[1]] <= u[sg[2]]) break;
             }
             const int *sg = PERMS[perm];
-            ClassKey key{d, (int32_t)u[sg[0]], (int32_t)u[sg[1]], (int32_t)u[sg[2]], helm ? t.h_level[s] : -1};
-            auto it = id.find(key);
-            int32_t cid;
-            if (it == id.end()) {
-                cid = (int32_t)members.size();
-                id.emplace(key, cid);
-                members.emplace_back();
-                msym.emplace_back();
-                mlev.emplace_back();
+            const ClassKey key{d, (int32_t)u[sg[0]], (int32_t)u[sg[1]], (int32_t)u[sg[2]], helm ? t.h_level[s] : -1};
+            bool added = false;
+            const int32_t cid = id.get(key, added);
+            if (added) {
                 cdelta.push_back(d);
+                csize.push_back(0);
                 for (int e = 0; e < 3; e++) rbar.push_back(std::ldexp((double)u[sg[e]], -(d + 1)));
                 kbar.push_back(k * std::ldexp(t.side, -t.h_level[s]));
-            } else {
-                cid = it->second;
             }
-            members[cid].push_back((int32_t)j);
-            msym[cid].push_back(8 * perm + flips);
-            mlev[cid].push_back(t.h_level[b]);
+            csize[cid]++;
+            pcls[j] = cid;
+            psym[j] = 8 * perm + flips;
         }
     }
-    pl->n_class = (int64_t)members.size();
-    // level-dependent order: a class's pairs in target-level order, so that
-    // the pairs of a task mostly share their orders
+    pl->n_class = (int64_t)csize.size();
+    st_.lap("classes");
+    if (st_.on) std::fprintf(stderr, "bem setup:   %lld classes, %lld interaction pairs\n", (long long)pl->n_class, (long long)t.n_inter);
     const LevelP lp = level_p(t);
     pl->var = t.order_min > 0 && t.order_min < t.order;
-    if (pl->var)
-        for (size_t cl = 0; cl < members.size(); cl++) {
-            std::vector<size_t> ix(members[cl].size());
-            for (size_t i = 0; i < ix.size(); i++) ix[i] = i;
-            std::stable_sort(ix.begin(), ix.end(), [&](size_t x, size_t y) { return mlev[cl][x] < mlev[cl][y]; });
-            std::vector<int32_t> m2(ix.size()), s2(ix.size()), l2(ix.size());
-            for (size_t i = 0; i < ix.size(); i++) {
-                m2[i] = members[cl][ix[i]];
-                s2[i] = msym[cl][ix[i]];
-                l2[i] = mlev[cl][ix[i]];
-            }
-            members[cl].swap(m2);
-            msym[cl].swap(s2);
-            mlev[cl].swap(l2);
-        }
     // slabs: runs of consecutive target boxes (the reduction's boxes) whose
     // interaction slots fit t.m2l_slab (a box with more forms a slab alone)
     std::vector<int32_t> box_slab(t.n_box, -1);
@@ -843,36 +850,64 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
         }
     }
     const int n_slab = (int)pl->slab_slot0.size() - 1;
+    st_.lap("slabs");
     // slot -> target box (for the slab of each pair)
     std::vector<int32_t> slot_box(std::max<int64_t>(1, t.n_inter), -1);
     for (int64_t b = 0; b < t.n_box; b++)
         for (int64_t j = t.h_inter_ptr[b]; j < t.h_inter_ptr[b + 1]; j++) slot_box[j] = (int32_t)b;
-    // pairs grouped by slab, then by class, largest class first
-    std::vector<int32_t> order(members.size());
-    for (size_t i = 0; i < order.size(); i++) order[i] = (int32_t)i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t x, int32_t y) { return members[x].size() > members[y].size(); });
-    std::vector<int32_t> slot, src, sym;
-    for (int sl = 0; sl < n_slab; sl++)
-        for (int32_t cl : order) {
-            const int32_t first = (int32_t)slot.size();
-            for (size_t i = 0; i < members[cl].size(); i++) {
-                if (n_slab > 1 && box_slab[slot_box[members[cl][i]]] != sl) continue;
-                slot.push_back(members[cl][i]);
-                src.push_back(t.h_inter_idx[members[cl][i]]);
-                sym.push_back(msym[cl][i]);
-                if (pl->var) {
-                    pl->h_pair_kt.push_back((lp.P[t.h_level[src.back()]] + 3) / 4);
-                    pl->h_pair_mt.push_back((lp.P[mlev[cl][i]] + 15) / 16);
-                }
-            }
-            if ((int32_t)slot.size() == first) continue;
-            pl->h_class_order.push_back(cl);
-            pl->h_class_first.push_back(first);
-            pl->h_class_count.push_back((int32_t)slot.size() - first);
-            pl->h_group_slab.push_back(sl);
+    // pairs grouped by slab, then by class, largest class first; within a
+    // class in target-level order when the order depends on the level (so that
+    // the pairs of a task mostly share their orders), else in slot order.
+    // Two stable counting sorts: by target level, then by (slab, class rank).
+    const int32_t ncl = (int32_t)pl->n_class;
+    std::vector<int32_t> order(ncl), rank(ncl);
+    for (int32_t i = 0; i < ncl; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return csize[x] > csize[y]; });
+    for (int32_t i = 0; i < ncl; i++) rank[order[i]] = i;
+    std::vector<int32_t> seq;
+    seq.reserve(t.n_inter);
+    if (pl->var) {
+        std::vector<int64_t> lc(66, 0);
+        for (int64_t j = 0; j < t.n_inter; j++)
+            if (pcls[j] >= 0) lc[t.h_level[slot_box[j]] + 1]++;
+        for (size_t l = 1; l < lc.size(); l++) lc[l] += lc[l - 1];
+        seq.resize(lc.back());
+        for (int64_t j = 0; j < t.n_inter; j++)
+            if (pcls[j] >= 0) seq[lc[t.h_level[slot_box[j]]]++] = (int32_t)j;
+    } else {
+        for (int64_t j = 0; j < t.n_inter; j++)
+            if (pcls[j] >= 0) seq.push_back((int32_t)j);
+    }
+    auto bucket = [&](int32_t j) { return (int64_t)box_slab[slot_box[j]] * ncl + rank[pcls[j]]; };
+    std::vector<int64_t> bp((size_t)n_slab * ncl + 1, 0);
+    for (int32_t j : seq) bp[bucket(j) + 1]++;
+    for (size_t i = 1; i < bp.size(); i++) bp[i] += bp[i - 1];
+    std::vector<int32_t> slot(seq.size()), src(seq.size()), sym(seq.size());
+    {
+        std::vector<int64_t> at(bp.begin(), bp.end() - 1);
+        for (int32_t j : seq) slot[at[bucket(j)]++] = j;
+    }
+    for (size_t i = 0; i < slot.size(); i++) {
+        src[i] = t.h_inter_idx[slot[i]];
+        sym[i] = psym[slot[i]];
+    }
+    if (pl->var) {
+        pl->h_pair_kt.resize(slot.size());
+        pl->h_pair_mt.resize(slot.size());
+        for (size_t i = 0; i < slot.size(); i++) {
+            pl->h_pair_kt[i] = (lp.P[t.h_level[src[i]]] + 3) / 4;
+            pl->h_pair_mt[i] = (lp.P[t.h_level[slot_box[slot[i]]]] + 15) / 16;
         }
+    }
+    for (size_t g = 0; g + 1 < bp.size(); g++) {
+        if (bp[g + 1] == bp[g]) continue;
+        pl->h_class_order.push_back(order[g % ncl]);
+        pl->h_class_first.push_back((int32_t)bp[g]);
+        pl->h_class_count.push_back((int32_t)(bp[g + 1] - bp[g]));
+        pl->h_group_slab.push_back((int32_t)(g / ncl));
+    }
     pl->n_pairs = (int64_t)slot.size();
+    st_.lap("pairs by slab and class");
     pl->h_pair_slot = slot;
     pl->h_pair_sym = sym;
     auto up = [&](DBuf<int32_t> &d, const std::vector<int32_t> &v) {
@@ -883,23 +918,23 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     up(pl->pair_src, src);
     // used (source box, symmetry) combinations: one canonical moment vector each
     {
-        std::unordered_map<int64_t, int32_t> uid;
+        std::vector<int32_t> uid((size_t)t.n_box * NSYM, -1);
         std::vector<int32_t> pmom(slot.size()), usrc, usym;
         for (size_t i = 0; i < slot.size(); i++) {
-            const int64_t key = (int64_t)src[i] * NSYM + sym[i];
-            auto it = uid.find(key);
-            if (it == uid.end()) {
-                it = uid.emplace(key, (int32_t)usrc.size()).first;
+            int32_t &u = uid[(size_t)src[i] * NSYM + sym[i]];
+            if (u < 0) {
+                u = (int32_t)usrc.size();
                 usrc.push_back(src[i]);
                 usym.push_back(sym[i]);
             }
-            pmom[i] = it->second;
+            pmom[i] = u;
         }
         pl->n_u = (int64_t)usrc.size();
         up(pl->pair_mom, pmom);
         up(pl->u_src, usrc);
         up(pl->u_sym, usym);
     }
+    st_.lap("moment vectors");
     up(pl->cls_delta, cdelta);
     // packed multi-indices of the rows and contraction indices
     std::vector<int32_t> pk(KIN, 0);
@@ -915,6 +950,7 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     std::vector<int32_t> ssym(std::max<int64_t>(1, t.n_inter), 0);
     for (size_t i = 0; i < slot.size(); i++) ssym[slot[i]] = sym[i];
     up(pl->slot_sym, ssym);
+    st_.lap("tables");
     // class derivative tables at the canonical separations
     const int cw = helm ? 2 : 1;
     pl->D64.alloc(&c, (size_t)cw * P2 * std::max<int64_t>(1, pl->n_class));
