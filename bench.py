@@ -43,7 +43,7 @@ FP32_VEC_PEAK = 157.3  # TFLOP/s, MI355X vector FP32 (256 CUs x 2.4 GHz; counts 
 FP32_VEC_UNPACKED = 78.6  # TFLOP/s: the same without packed FP32, which this build does not emit
 FP32_MFMA_PEAK = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 FP64_VEC_PEAK = 78.6
-BF16_MFMA_PEAK = 2500.0  # TFLOP/s: dense bf16 matrix peak (the split M2L's instruction)
+FP16_MFMA_PEAK = 2500.0  # TFLOP/s: dense fp16 matrix peak (the split M2L's instruction)
 KERNEL_PEAKS = {"m2l": ("mfma", FP32_MFMA_PEAK), "p2p": ("alu", FP32_VEC_PEAK)}
 # leaf sizes of the served trees: Laplace, and Helmholtz per wavenumber bucket
 # (the C3 sweep: B = 64 is 5.6 times faster than B = 32 at ka = 10)
@@ -240,13 +240,13 @@ def roofline(dom, flops, ms_launch, launches, traffic):
         r["peak_unpacked"] = FP32_VEC_UNPACKED
         r["frac_unpacked"] = achieved / FP32_VEC_UNPACKED
     if dom == "m2l":
-        # the mixed-precision products run on the bf16 matrix instruction with
-        # three-term operand splits: six products per FP32-equivalent one, on
+        # the mixed-precision products run on the fp16 matrix instruction with
+        # two-term operand splits: three products per FP32-equivalent one, on
         # a 176 x 192 padded tile per P x P block
-        ex = achieved * 6 * (176 * 192) / (165 * 165)
-        r["bf16_executed_tflops"] = ex
-        r["bf16_peak"] = BF16_MFMA_PEAK
-        r["bf16_frac"] = ex / BF16_MFMA_PEAK
+        ex = achieved * 3 * (176 * 192) / (165 * 165)
+        r["fp16_executed_tflops"] = ex
+        r["fp16_peak"] = FP16_MFMA_PEAK
+        r["fp16_frac"] = ex / FP16_MFMA_PEAK
     return r
 
 

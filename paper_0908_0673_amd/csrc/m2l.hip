@@ -39,8 +39,8 @@
 // class's operator.  FP64 path: each pair's result goes to its slot in the
 // interaction list, and a second kernel sums every target box's slots in
 // list order.  Mixed path (one order for all levels): the products run on
-// the bf16 instruction with split operands, and each wave sums its pairs of
-// one target box in the box's frame before writing (see k_m2l_x3); a second
+// the fp16 instruction with split operands, and each wave sums its pairs of
+// one target box in the box's frame before writing (see k_m2l_x2); a second
 // kernel adds a box's partial sums in plan order.  Either way the result does
 // not depend on scheduling (no float atomics).
 #include <algorithm>
@@ -157,14 +157,25 @@ struct M2lArgs {
     // table back to the pairs' frames; slot0 is then the slab's first partial
     const int32_t *pair_part, *pair_sym;
     const int16_t *sym_red;
+    // split path: power-of-two exponent of each canonical moment vector and
+    // 2^-exponent of each operator row (class, row), undone on the results
+    const int32_t *u_exp;
+    const float *row_scale;
 };
+
+__device__ inline float abs_max(float x) { return fabsf(x); }
+__device__ inline float abs_max(cx<float> x) { return fmaxf(fabsf(x.re), fabsf(x.im)); }
+__device__ inline float scaled(float x, int e) { return ldexpf(x, e); }
+__device__ inline cx<float> scaled(cx<float> x, int e) { return cx<float>(ldexpf(x.re, e), ldexpf(x.im, e)); }
 
 // Moments in the canonical frame of each used (source box, symmetry)
 // combination u: Mc[u][a'] = sign * M_src[index], (index, sign) = sym_in[sym][a'],
-// zero past P.  One wave per combination.
+// zero past P.  One wave per combination.  With u_exp (FP32 values, the split
+// path) each vector is scaled by 2^e, e = u_exp[u], so that its largest
+// component lies in [2^14, 2^15) (e = 0 for a zero vector).
 template <class V>
 __global__ void k_m2l_canonical_moments(int64_t n_u, const int32_t *u_src, const int32_t *u_sym,
-                                        const int32_t *sym_in, int P, const V *mom, V *Mc) {
+                                        const int32_t *sym_in, int P, const V *mom, V *Mc, int32_t *u_exp) {
     far_field_priority();
     const int64_t u = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     if (u >= n_u) return;
@@ -181,6 +192,19 @@ __global__ void k_m2l_canonical_moments(int64_t n_u, const int32_t *u_src, const
     }
 #pragma unroll
     for (int it = 0; it < NIT; it++) v[it] = e[it] >= 0 ? ms[e[it] & 0xffff] : V(0.0);
+    if constexpr (std::is_same<V, float>::value || std::is_same<V, cx<float>>::value) {
+        if (u_exp) {  // the same for the whole wave
+            float m = 0.0f;
+#pragma unroll
+            for (int it = 0; it < NIT; it++) m = fmaxf(m, abs_max(v[it]));
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+            const int ex = m > 0.0f ? 14 - ilogbf(m) : 0;
+#pragma unroll
+            for (int it = 0; it < NIT; it++) v[it] = scaled(v[it], ex);
+            if (lane == 0) u_exp[u] = ex;
+        }
+    }
 #pragma unroll
     for (int it = 0; it < NIT; it++) {
         const int a = lane + 64 * it;
@@ -322,60 +346,82 @@ __global__ void __launch_bounds__(64 * W) k_m2l(M2lArgs a, const R *T, const R *
     }
 }
 
-// ---------------------------------------------------------------- split-bf16 products
-// The mixed path runs the products on the bf16 matrix instruction
-// v_mfma_f32_16x16x32_bf16 (FP32 accumulation), whose rate on this chip is
-// about fifteen times that of the FP32 one (measured: 2.2 PFLOP/s against
-// 0.149).  Every operand x is carried as three bf16 terms, x1 = bf16(x),
-// x2 = bf16(x - x1), x3 = bf16(x - x1 - x2) (each term holds the next eight
-// significant bits, so together they hold x to about 2^-27 relative), and each
-// product keeps the six cross terms of combined order up to four,
-//     x y ~ x1 y1 + (x1 y2 + x2 y1) + (x1 y3 + x2 y2 + x3 y1),
-// the dropped ones being below 2^-27 relative: the accuracy of FP32 operands
-// (2^-24) at about 2.5 times the speed of the FP32 instruction for the same
-// work.  The smaller terms are accumulated first.  The contraction runs over
-// K3 = 192 >= P in blocks of 32; a chunk of the operator is one block of one
-// plane (the real or imaginary part): 11 row tiles x 3 terms x 1 KB, the A
-// operands of the instruction in lane order (lane l holds row l % 16,
-// columns 8 (l / 16) .. + 7 of its 16 x 32 tile).
+// ---------------------------------------------------------------- split-fp16 products
+// The mixed path runs the products on the fp16 matrix instruction
+// v_mfma_f32_16x16x32_f16 (FP32 accumulation), whose rate on this chip is
+// about fifteen times that of the FP32 one.  Every operand x is carried as two
+// fp16 terms, x1 = fp16(x) and x2 = fp16(x - x1) (eleven significant bits
+// each, together x to about 2^-22 relative), and each product keeps the three
+// cross terms of combined order up to three,
+//     x y ~ x1 y1 + (x1 y2 + x2 y1),
+// the dropped x2 y2 being below 2^-22 relative; the smaller terms are
+// accumulated first.  fp16's exponent range is narrow, so both operands are
+// first scaled by powers of two (exact): every operator row (class, row) and
+// every canonical moment vector so that its largest entry lies in
+// [2^14, 2^15).  Entries far below their row's or vector's largest lose
+// relative precision to fp16's subnormal range, but never more than 2^-38 of
+// that largest entry in absolute terms.  The scales are undone on the
+// results.  The contraction runs over K3 = 192 >= P in blocks of 32; a chunk
+// of the operator is one block of one plane (the real or imaginary part):
+// 11 row tiles x 2 terms x 1 KB, the A operands of the instruction in lane
+// order (lane l holds row l % 16, columns 8 (l / 16) .. + 7 of its 16 x 32
+// tile).
 constexpr int KB = 6;                  // contraction blocks of 32
 constexpr int K3 = KB * 32;            // 192
-constexpr int TILE3 = 512;             // bf16 values of one A tile of one term
-constexpr int CH3 = MT * 3 * TILE3;    // bf16 values of one chunk (one block of one plane)
+constexpr int TILE2 = 512;             // fp16 values of one A tile of one term
+constexpr int CH2 = MT * 2 * TILE2;    // fp16 values of one chunk (one block of one plane)
+constexpr int SPLIT_TOP = 14;          // scaled operands' largest entries lie in [2^14, 2^15)
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
-__device__ inline floatx4 mfma3(uint4 a, uint4 b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
-                                                   0, 0);
+__device__ inline floatx4 mfma_h(uint4 a, uint4 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, a), __builtin_bit_cast(halfx8, b), c, 0,
+                                                  0, 0);
 }
 
-// three-term bf16 split (bit patterns) of an FP64 or FP32 value
-__device__ inline void split3(double x, uint16_t *t) {
-    const __bf16 h = (__bf16)(float)x;
-    const double r = x - (double)(float)h;
-    const __bf16 m = (__bf16)(float)r;
-    const __bf16 l = (__bf16)(float)(r - (double)(float)m);
+// two-term fp16 split (bit patterns) of an FP64 or FP32 value
+__device__ inline void split2(double x, uint16_t *t) {
+    const _Float16 h = (_Float16)(float)x;
+    const _Float16 l = (_Float16)(float)(x - (double)h);
     t[0] = __builtin_bit_cast(uint16_t, h);
-    t[1] = __builtin_bit_cast(uint16_t, m);
-    t[2] = __builtin_bit_cast(uint16_t, l);
+    t[1] = __builtin_bit_cast(uint16_t, l);
 }
-__device__ inline void split3(float x, uint16_t *t) {
-    const __bf16 h = (__bf16)x;
-    const float r = x - (float)h;  // exact: x and h agree in their leading bits
-    const __bf16 m = (__bf16)r;
-    const __bf16 l = (__bf16)(r - (float)m);
+__device__ inline void split2(float x, uint16_t *t) {
+    const _Float16 h = (_Float16)x;
+    const _Float16 l = (_Float16)(x - (float)h);  // x - h is exact in FP32
     t[0] = __builtin_bit_cast(uint16_t, h);
-    t[1] = __builtin_bit_cast(uint16_t, m);
-    t[2] = __builtin_bit_cast(uint16_t, l);
+    t[1] = __builtin_bit_cast(uint16_t, l);
 }
 
-// T_c of k_expand_T as three-term splits: T3[((c KB + kb) NA + q) CH3 +
-// (mt 3 + s) TILE3 + 8 lane + i] is term s of plane q of T_c[b][a] with
-// b = 16 mt + lane % 16, a = 32 kb + 8 (lane / 16) + i.
+// Row scales of the split operators: row_scale[c][b] = 2^(ilogb(m) - 14),
+// m = max_a |T_c[b][a]| over both planes (1 for a zero or padding row), so
+// that T_c[b][a] / row_scale[c][b] has its largest entry in [2^14, 2^15).
+// One thread per row.
 template <bool HELM>
-__global__ void k_expand_T3(const double *D64, const int32_t *pk, const int32_t *cls_delta, const double *inv_fact,
-                            int P, int P2, uint16_t *T3) {
+__global__ void k_row_scale(const double *D64, const int32_t *pk, const int32_t *cls_delta, const double *inv_fact,
+                            int P, int P2, float *row_scale) {
+    const int c = blockIdx.x, b = threadIdx.x;
+    if (b >= OUT_LD) return;
+    double m = 0.0;
+    if (b < P) {
+        const int qb = pk[b];
+        const int nb = (qb & 31) + ((qb >> 5) & 31) + (qb >> 10);
+        for (int al = 0; al < P; al++) {
+            const int64_t ix = (int64_t)c * P2 + sum_index(pk[al] + qb);
+            m = HELM ? fmax(m, fmax(fabs(D64[2 * ix]), fabs(D64[2 * ix + 1]))) : fmax(m, fabs(D64[ix]));
+        }
+        m *= inv_fact[b] * ldexp(1.0, -cls_delta[c] * nb);
+    }
+    row_scale[(int64_t)c * OUT_LD + b] = m > 0.0 ? ldexpf(1.0f, ilogb(m) - SPLIT_TOP) : 1.0f;
+}
+
+// T_c of k_expand_T as two-term splits of its scaled rows:
+// T2[((c KB + kb) NA + q) CH2 + (mt 2 + s) TILE2 + 8 lane + i] is term s of
+// plane q of T_c[b][a] / row_scale[c][b] with b = 16 mt + lane % 16,
+// a = 32 kb + 8 (lane / 16) + i.
+template <bool HELM>
+__global__ void k_expand_T2(const double *D64, const int32_t *pk, const int32_t *cls_delta, const double *inv_fact,
+                            int P, int P2, const float *row_scale, uint16_t *T2) {
     constexpr int NA = HELM ? 2 : 1;
     const int c = blockIdx.x, kb = blockIdx.y / MT, mt = blockIdx.y % MT, lane = threadIdx.x;
     const int b = 16 * mt + (lane & 15);
@@ -386,7 +432,8 @@ __global__ void k_expand_T3(const double *D64, const int32_t *pk, const int32_t 
             const int qa = pk[al], qb = pk[b];
             const int na = (qa & 31) + ((qa >> 5) & 31) + (qa >> 10);
             const int nb = (qb & 31) + ((qb >> 5) & 31) + (qb >> 10);
-            const double f = inv_fact[b] * ldexp(1.0, -cls_delta[c] * nb) * ((na & 1) ? -1.0 : 1.0);
+            const double f = inv_fact[b] * ldexp(1.0, -cls_delta[c] * nb) * ((na & 1) ? -1.0 : 1.0) /
+                             (double)row_scale[(int64_t)c * OUT_LD + b];
             const int ix = sum_index(qa + qb);
             if (HELM) {
                 v[0] = f * D64[2 * ((int64_t)c * P2 + ix)];
@@ -396,10 +443,10 @@ __global__ void k_expand_T3(const double *D64, const int32_t *pk, const int32_t 
             }
         }
         for (int q = 0; q < NA; q++) {
-            uint16_t tt[3];
-            split3(v[q], tt);
-            const int64_t o = ((int64_t)(c * KB + kb) * NA + q) * CH3 + (int64_t)(mt * 3) * TILE3 + 8 * lane + i;
-            for (int s3 = 0; s3 < 3; s3++) T3[o + s3 * TILE3] = tt[s3];
+            uint16_t tt[2];
+            split2(v[q], tt);
+            const int64_t o = ((int64_t)(c * KB + kb) * NA + q) * CH2 + (int64_t)(mt * 2) * TILE2 + 8 * lane + i;
+            for (int s2 = 0; s2 < 2; s2++) T2[o + s2 * TILE2] = tt[s2];
         }
     }
 }
@@ -407,7 +454,7 @@ __global__ void k_expand_T3(const double *D64, const int32_t *pk, const int32_t 
 // The lane's eight B values of contraction block kb: moments a = 32 kb +
 // 8 (lane / 16) + i of its column (real, or for complex tasks the real or
 // imaginary part), zero past the stored KIN; FP32 as the canonical moments
-// kernel writes them, split into bf16 terms only in registers.
+// kernel writes them (scaled), split into fp16 terms only in registers.
 template <int NA>
 __device__ inline void load_b(const float *mr, int kb, int kq, bool imag, float (&v)[8]) {
     const int a0 = 32 * kb + 8 * kq;
@@ -430,14 +477,14 @@ __device__ inline void load_b(const float *mr, int kb, int kq, bool imag, float 
         }
     }
 }
-__device__ inline void split_b(const float (&v)[8], uint4 (&B)[3]) {
-    uint16_t t[8][3];
+__device__ inline void split_b(const float (&v)[8], uint4 (&B)[2]) {
+    uint16_t t[8][2];
 #pragma unroll
-    for (int i = 0; i < 8; i++) split3(v[i], t[i]);
+    for (int i = 0; i < 8; i++) split2(v[i], t[i]);
 #pragma unroll
-    for (int s3 = 0; s3 < 3; s3++)
-        B[s3] = make_uint4(t[0][s3] | (uint32_t)t[1][s3] << 16, t[2][s3] | (uint32_t)t[3][s3] << 16,
-                           t[4][s3] | (uint32_t)t[5][s3] << 16, t[6][s3] | (uint32_t)t[7][s3] << 16);
+    for (int s2 = 0; s2 < 2; s2++)
+        B[s2] = make_uint4(t[0][s2] | (uint32_t)t[1][s2] << 16, t[2][s2] | (uint32_t)t[3][s2] << 16,
+                           t[4][s2] | (uint32_t)t[5][s2] << 16, t[6][s2] | (uint32_t)t[7][s2] << 16);
 }
 
 // The products of one task on the split operands (as k_m2l with FP32 values,
@@ -447,9 +494,9 @@ __device__ inline void split_b(const float (&v)[8], uint4 (&B)[3]) {
 // whose B operands it loads from the split moments one contraction block
 // ahead.  The per-column arithmetic does not depend on W.
 template <int NA, int W>
-__global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, const float *Mc, float *out) {
+__global__ void __launch_bounds__(64 * W) k_m2l_x2(M2lArgs a, const uint4 *T2, const float *Mc, float *out) {
     far_field_priority();
-    constexpr int U4 = CH3 * 2 / 16;  // 16-byte pieces per chunk
+    constexpr int U4 = CH2 * 2 / 16;  // 16-byte pieces per chunk
     constexpr int PER = (U4 + 64 * W - 1) / (64 * W);
     constexpr int NCH = KB * NA;
     __shared__ uint4 As[2][U4];
@@ -464,7 +511,7 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, c
     // take the imaginary parts of the pairs of columns 0..7)
     const float *mr = Mc + u * KIN * NA;
     const bool imag = NA == 2 && col >= 8;
-    const uint4 *Tg = T3 + (int64_t)c * NCH * U4;
+    const uint4 *Tg = T2 + (int64_t)c * NCH * U4;
     // pieces past the chunk are clamped to its last one: those threads load
     // and store the same value as its owner, so no branch is needed
     auto fetch = [&](int ch, uint4 (&r)[PER]) {
@@ -477,7 +524,7 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, c
     };
     uint4 r[PER];
     fetch(0, r);
-    uint4 B[3];
+    uint4 B[2];
     float bn[8];  // the next block's values, in flight
     load_b<NA>(mr, 0, kq, imag, bn);
     split_b(bn, B);
@@ -500,14 +547,11 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, c
         const uint4 *Ab = As[ch & 1] + lane;
 #pragma unroll
         for (int j = 0; j < MT; j++) {
-            const uint4 a0 = Ab[(3 * j) * 64], a1 = Ab[(3 * j + 1) * 64], a2 = Ab[(3 * j + 2) * 64];
+            const uint4 a0 = Ab[(2 * j) * 64], a1 = Ab[(2 * j + 1) * 64];
             floatx4 x = acc[q][j];
-            x = mfma3(a2, B[0], x);
-            x = mfma3(a0, B[2], x);
-            x = mfma3(a1, B[1], x);
-            x = mfma3(a1, B[0], x);
-            x = mfma3(a0, B[1], x);
-            x = mfma3(a0, B[0], x);
+            x = mfma_h(a1, B[0], x);
+            x = mfma_h(a0, B[1], x);
+            x = mfma_h(a0, B[0], x);
             acc[q][j] = x;
         }
         if (ch + 1 < NCH) {
@@ -516,24 +560,28 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, c
             if (ch + 2 < NCH) fetch(ch + 2, r);
         }
     }
-    // Each pair's canonical result, scaled, is taken back to its own frame
+    // Each pair's canonical result, unscaled, is taken back to its own frame
     // (row i is the canonical row sym_red[sym][i], signed) and summed with the
     // pairs that follow it in the wave and share its target box (runs of
     // consecutive pairs, which share a partial slot), in passes of G pairs
-    // staged in the LDS ring beside a copy of the symmetry table; each run's
-    // sum is written once, to its slot.
-    const float scale = (float)ldexp(1.0 / a.side, a.level[p < cnt ? a.pair_src[first + p] : 0]);  // 1 / rho_s
+    // staged in the LDS ring beside copies of the symmetry table and the
+    // class's row scales; each run's sum is written once, to its slot.  The
+    // column's scale (1 / rho_s and the moment vector's exponent) is applied
+    // when staging, the row's when gathering; both are powers of two.
+    const float scale = (float)ldexp(1.0 / a.side, a.level[p < cnt ? a.pair_src[first + p] : 0] - a.u_exp[u]);
     using VO = typename std::conditional<NA == 1, float, cx<float>>::type;
-    constexpr int G = 8;                          // pairs per pass: 5.5 (real) or 11 KB of staging per wave
+    constexpr int G = 4;                          // pairs per pass: 2.8 (real) or 5.5 KB of staging per wave
     constexpr int PW = NA == 1 ? 16 : 8;          // pairs per wave
     constexpr int SB = W * G * OUT_LD * (int)sizeof(VO);  // staging bytes of the block
-    static_assert(SB % 16 == 0 && SB + NSYM * OUT_LD * 2 <= 2 * U4 * 16, "staging exceeds the LDS ring");
+    constexpr int TB = NSYM * OUT_LD * 2;                  // symmetry table bytes
+    static_assert(SB % 16 == 0 && SB + TB + OUT_LD * 4 <= 2 * U4 * 16, "staging exceeds the LDS ring");
     VO *S = (VO *)&As[0][0] + w * G * OUT_LD;
     const int16_t *tab = (const int16_t *)((const char *)&As[0][0] + SB);
+    float *rs = (float *)((char *)&As[0][0] + SB + TB);
     VO *o = (VO *)out;
     __syncthreads();  // every wave is past its last operator reads
-    for (int x = tid; x < NSYM * OUT_LD / 8; x += 64 * W)
-        ((uint4 *)((char *)&As[0][0] + SB))[x] = ((const uint4 *)a.sym_red)[x];
+    for (int x = tid; x < TB / 16; x += 64 * W) ((uint4 *)((char *)&As[0][0] + SB))[x] = ((const uint4 *)a.sym_red)[x];
+    for (int x = tid; x < OUT_LD; x += 64 * W) rs[x] = a.row_scale[(int64_t)c * OUT_LD + x];
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < PW / G; h++) {
@@ -570,7 +618,8 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x3(M2lArgs a, const uint4 *T3, c
 #pragma unroll
             for (int cc = 0; cc < G; cc++) {
                 const int e = row ? tab[sym[cc] * OUT_LD + i] : 0;
-                const VO v = S[cc * OUT_LD + (e & 0xff)];
+                VO v = S[cc * OUT_LD + (e & 0xff)];
+                v *= rs[e & 0xff];
                 x[cc] = (e & 0x100) ? VO(0.0f) - v : v;
             }
             VO v = x[0];
@@ -1076,35 +1125,44 @@ const R *expanded(bem_tree &t, M2lPlan &pl) {
     return buf.p;
 }
 
-// split operators of the plan (built on first use)
-const uint16_t *expanded3(bem_tree &t, M2lPlan &pl) {
+// split operators of the plan and their row scales (built on first use)
+const uint16_t *expanded2(bem_tree &t, M2lPlan &pl) {
     Ctx &c = *t.ctx;
     FmmTables &T = *t.tables;
-    if (!pl.T3.p && pl.n_class) {
+    if (!pl.T2.p && pl.n_class) {
         SetupTimer st_(c, "M2L split operators");
         const bool helm = pl.green == BEM_HELMHOLTZ;
-        pl.T3.alloc(&c, (size_t)(helm ? 2 : 1) * KB * CH3 * pl.n_class);
+        pl.row_scale.alloc(&c, (size_t)OUT_LD * pl.n_class);
+        pl.T2.alloc(&c, (size_t)(helm ? 2 : 1) * KB * CH2 * pl.n_class);
+        static_assert(OUT_LD <= 256, "one thread per row");
         dim3 g((unsigned)pl.n_class, KB * MT);
-        if (helm)
-            k_expand_T3<true><<<g, 64, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p, T.inv_fact64.p, T.P, T.P2,
-                                                      pl.T3.p);
-        else
-            k_expand_T3<false><<<g, 64, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p, T.inv_fact64.p, T.P, T.P2,
-                                                       pl.T3.p);
+        if (helm) {
+            k_row_scale<true><<<(unsigned)pl.n_class, 256, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p,
+                                                                          T.inv_fact64.p, T.P, T.P2, pl.row_scale.p);
+            BEM_LAUNCH_CHECK();
+            k_expand_T2<true><<<g, 64, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p, T.inv_fact64.p, T.P, T.P2,
+                                                      pl.row_scale.p, pl.T2.p);
+        } else {
+            k_row_scale<false><<<(unsigned)pl.n_class, 256, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p,
+                                                                           T.inv_fact64.p, T.P, T.P2, pl.row_scale.p);
+            BEM_LAUNCH_CHECK();
+            k_expand_T2<false><<<g, 64, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p, T.inv_fact64.p, T.P, T.P2,
+                                                       pl.row_scale.p, pl.T2.p);
+        }
         BEM_LAUNCH_CHECK();
         c.sync();
     }
-    return pl.T3.p;
+    return pl.T2.p;
 }
 
 // Partial slots of the split path's per-target sums: within each (slab,
-// class) group of pairs, passes of G = 8 pairs from its first pair (the
+// class) group of pairs, passes of G = 4 pairs from its first pair (the
 // product kernel's waves take 16 real or 8 complex pairs from there); a run of consecutive pairs of one pass with the same target box
 // shares a slot.  Slots are numbered box by box in m2l_boxes order (a slab's
 // slots are then contiguous), within a box in pair order, so that a box's sum
 // runs over one contiguous range in a fixed order.
 void build_parts(bem_tree &t, M2lPlan &pl) {
-    constexpr int G = 8;  // as the product kernel
+    constexpr int G = 4;  // as the product kernel
     if (pl.parts_g == G) return;
     Ctx &c = *t.ctx;
     SetupTimer st_(c, "M2L partial slots");
@@ -1147,8 +1205,9 @@ void build_parts(bem_tree &t, M2lPlan &pl) {
     pl.parts_g = G;
 }
 
-// waves per block of the split kernel: the complex one stages 11 KB per wave
-// beside the symmetry table in its LDS ring, which holds four
+// waves per block of the split kernel: the complex one stages 5.5 KB per wave
+// beside the symmetry and row-scale tables in its 44 KB LDS ring, which holds
+// four
 int split_waves(int na, int w) { return na == 2 && w > 4 ? 4 : w; }
 
 // whether a product of precision R on this plan runs on the split operands
@@ -1170,10 +1229,10 @@ int m2l_cols(const M2lPlan &pl, int w) {
 
 bool m2l_ready(const M2lPlan &pl, int prec, int waves) {
     const bool helm = pl.green == BEM_HELMHOLTZ, f32 = prec == BEM_PREC_MIXED;
-    const void *ops = f32 ? (split_path<float>(pl) ? (const void *)pl.T3.p : (const void *)pl.T32.p)
+    const void *ops = f32 ? (split_path<float>(pl) ? (const void *)pl.T2.p : (const void *)pl.T32.p)
                           : (const void *)pl.T64.p;
     if (pl.n_class && !ops) return false;
-    if (f32 && split_path<float>(pl) && pl.parts_g != 8) return false;
+    if (f32 && split_path<float>(pl) && pl.parts_g != 4) return false;
     const int cols = helm ? (f32 ? m2l_cols<cx<float>, float>(pl, waves) : m2l_cols<cx<double>, double>(pl, waves))
                           : (f32 ? m2l_cols<float, float>(pl, waves) : m2l_cols<double, double>(pl, waves));
     for (auto &tk : pl.tasks)
@@ -1185,7 +1244,7 @@ namespace {
 
 template <int W>
 const void *m2l_kernel(const M2lPlan &pl, bool f32, bool helm) {
-    if (f32 && !pl.var) return helm ? (const void *)k_m2l_x3<2, (W > 4 ? 4 : W)> : (const void *)k_m2l_x3<1, W>;
+    if (f32 && !pl.var) return helm ? (const void *)k_m2l_x2<2, (W > 4 ? 4 : W)> : (const void *)k_m2l_x2<1, W>;
     if (f32) return helm ? (const void *)k_m2l<float, 2, true, W> : (const void *)k_m2l<float, 1, true, W>;
     if (pl.var) return helm ? (const void *)k_m2l<double, 2, true, W> : (const void *)k_m2l<double, 1, true, W>;
     return helm ? (const void *)k_m2l<double, 2, false, W> : (const void *)k_m2l<double, 1, false, W>;
@@ -1211,7 +1270,7 @@ size_t m2l_block_lds(const M2lPlan &pl, int prec, int waves) {
 template <class V, class R>
 void m2l_prepare(bem_tree &t, M2lPlan &pl, int waves) {
     if (split_path<R>(pl)) {
-        expanded3(t, pl);
+        expanded2(t, pl);
         build_parts(t, pl);
     } else
         expanded<R>(t, pl);
@@ -1235,14 +1294,17 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
     const int64_t out_rows = split ? pl.parts_max : pl.slab_max_slots;
     V *out = (V *)work_buf(c, t.work.m2l_out, sizeof(V) * (size_t)std::max<int64_t>(1, out_rows) * OUT_LD);
     const LevelP lp = level_p(t);
-    void *Mc = work_buf(c, t.work.m2l_mom, sizeof(V) * KIN * (size_t)std::max<int64_t>(1, pl.n_u));
+    // canonical moments, then (split path) their exponents
+    const size_t mc_bytes = sizeof(V) * KIN * (size_t)std::max<int64_t>(1, pl.n_u);
+    void *Mc = work_buf(c, t.work.m2l_mom, mc_bytes + (split ? sizeof(int32_t) * (size_t)std::max<int64_t>(1, pl.n_u) : 0));
+    int32_t *u_exp = split ? (int32_t *)((char *)Mc + mc_bytes) : nullptr;
     const R *Tx = split ? nullptr : expanded<R>(t, pl);
-    const uint4 *T3 = split ? (const uint4 *)expanded3(t, pl) : nullptr;
+    const uint4 *T2 = split ? (const uint4 *)expanded2(t, pl) : nullptr;
     for (int rhs = 0; rhs < nrhs; rhs++) {
         const V *m = mom + (int64_t)rhs * t.n_box * P;
         V *l = loc + (int64_t)rhs * t.n_box * P;
         k_m2l_canonical_moments<V><<<(unsigned)((pl.n_u + 3) / 4), 256, 0, c.stream>>>(
-            pl.n_u, pl.u_src.p, pl.u_sym.p, pl.sym_in.p, P, m, (V *)Mc);
+            pl.n_u, pl.u_src.p, pl.u_sym.p, pl.sym_in.p, P, m, (V *)Mc, u_exp);
         BEM_LAUNCH_CHECK();
         c.mark(10);
         // one slab of target boxes at a time: its pairs' results, then their sums
@@ -1254,14 +1316,15 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
             M2lArgs a{tk.task_class.p + t0, tk.task_first.p + t0, tk.task_count.p + t0, pl.pair_slot.p,
                       pl.pair_src.p, pl.pair_mom.p, t.level.p, pl.var ? tk.task_kt.p + t0 : nullptr,
                       pl.var ? tk.task_mt.p + t0 : nullptr, t.side, P, split ? part0 : pl.slab_slot0[sl],
-                      split ? pl.pair_part.p : nullptr, split ? pl.pair_sym.p : nullptr, pl.sym_red.p};
+                      split ? pl.pair_part.p : nullptr, split ? pl.pair_sym.p : nullptr, pl.sym_red.p,
+                      u_exp, split ? pl.row_scale.p : nullptr};
             c.kbegin(c.stream, 3);
             auto launch = [&](auto wv) {
                 constexpr int W = decltype(wv)::value;
                 if constexpr (std::is_same<R, float>::value) {
                     if (split) {
                         constexpr int WS = NA == 2 && W > 4 ? 4 : W;  // as split_waves
-                        k_m2l_x3<NA, WS><<<(unsigned)nt, 64 * WS, 0, c.stream>>>(a, T3, (const float *)Mc, (float *)out);
+                        k_m2l_x2<NA, WS><<<(unsigned)nt, 64 * WS, 0, c.stream>>>(a, T2, (const float *)Mc, (float *)out);
                         return;
                     }
                 }

@@ -322,6 +322,30 @@ def test_fmm_mixed_error_against_oracle(name, green, k):
                       dref[2] if op == 1 else None)
 
 
+@pytest.mark.parametrize("green,k", [(0, 0.0), (1, 2.0)])
+def test_mixed_product_scales_exactly(green, k):
+    """The mixed product of 2^s x is 2^s times that of x, bit for bit, for
+    s = -40 and 40: every step is linear and a power-of-two factor commutes
+    with rounding, so this holds while nothing overflows or underflows.  The
+    matrix-instruction products carry their operands as fp16 terms (largest
+    finite value 65504), so it holds only because each moment vector and
+    each operator row is brought into range by its own power-of-two scale."""
+    bem = _bem()
+    m, ctx, mesh, tree, om, ot = setup("sphere1280")
+    cplx = green == 1
+    x = bem_inputs.random_vector(om.n_dof, 31, complex_=cplx)[0]
+    y1 = to_dev(x, cplx)
+    bem.bem_matvec(ctx, tree, green, k, 2, bem.BEM_FMM, bem.BEM_PREC_MIXED, to_dev(x, cplx), y1)
+    base = y1.cpu().numpy()[0]
+    for s in (-40, 40):
+        xs = to_dev(x * 2.0 ** s, cplx)
+        ys = xs.clone()
+        bem.bem_matvec(ctx, tree, green, k, 2, bem.BEM_FMM, bem.BEM_PREC_MIXED, xs, ys)
+        got = ys.cpu().numpy()[0] * 2.0 ** -s
+        say(f"    green={green} s={s}: largest difference {np.abs(got - base).max():.3e}")
+        assert np.array_equal(got, base), (green, s)
+
+
 def test_multiple_rhs_equal_single_calls():
     bem = _bem()
     m, ctx, mesh, tree, om, ot = setup("sphere320")
