@@ -137,8 +137,8 @@ struct M2lPlan {
     DBuf<int32_t> slot_sym;           // symmetry of each interaction-list slot
     DBuf<float> T32;                  // expanded operators, built on first use per precision
     DBuf<double> T64;
-    DBuf<uint16_t> T2;                // two-term fp16 splits of the scaled rows (mixed path with one order)
-    DBuf<float> row_scale;            // [class][OUT_LD] power-of-two scale of each split operator row
+    DBuf<uint16_t> T2;                // two-term fp16 splits of the scaled operators (mixed path with one order)
+    DBuf<float> cls_scale;            // [class] power-of-two scale of each split operator
     std::vector<int32_t> h_pair_slot, h_pair_sym;
     // Mixed path with one order: partial slots of the per-target sums the
     // product kernel forms itself (built on first use for `parts_g` pairs

@@ -158,9 +158,9 @@ struct M2lArgs {
     const int32_t *pair_part, *pair_sym;
     const int16_t *sym_red;
     // split path: power-of-two exponent of each canonical moment vector and
-    // 2^-exponent of each operator row (class, row), undone on the results
+    // 2^-exponent of each class's operator, undone on the results
     const int32_t *u_exp;
-    const float *row_scale;
+    const float *cls_scale;
 };
 
 __device__ inline float abs_max(float x) { return fabsf(x); }
@@ -356,12 +356,12 @@ __global__ void __launch_bounds__(64 * W) k_m2l(M2lArgs a, const R *T, const R *
 //     x y ~ x1 y1 + (x1 y2 + x2 y1),
 // the dropped x2 y2 being below 2^-22 relative; the smaller terms are
 // accumulated first.  fp16's exponent range is narrow, so both operands are
-// first scaled by powers of two (exact): every operator row (class, row) and
-// every canonical moment vector so that its largest entry lies in
-// [2^14, 2^15).  Entries far below their row's or vector's largest lose
-// relative precision to fp16's subnormal range, but never more than 2^-38 of
-// that largest entry in absolute terms.  The scales are undone on the
-// results.  The contraction runs over K3 = 192 >= P in blocks of 32; a chunk
+// first scaled by powers of two (exact): every class's operator and every
+// canonical moment vector so that its largest entry lies in [2^14, 2^15).
+// Entries far below that largest lose relative precision to fp16's subnormal
+// range, but never more than 2^-38 of it in absolute terms (in the scaled
+// units every entry contributes in proportion to its size).  The scales are
+// undone on the results.  The contraction runs over K3 = 192 >= P in blocks of 32; a chunk
 // of the operator is one block of one plane (the real or imaginary part):
 // 11 row tiles x 2 terms x 1 KB, the A operands of the instruction in lane
 // order (lane l holds row l % 16, columns 8 (l / 16) .. + 7 of its 16 x 32
@@ -393,15 +393,15 @@ __device__ inline void split2(float x, uint16_t *t) {
     t[1] = __builtin_bit_cast(uint16_t, l);
 }
 
-// Row scales of the split operators: row_scale[c][b] = 2^(ilogb(m) - 14),
-// m = max_a |T_c[b][a]| over both planes (1 for a zero or padding row), so
-// that T_c[b][a] / row_scale[c][b] has its largest entry in [2^14, 2^15).
-// One thread per row.
+// Scales of the split operators: cls_scale[c] = 2^(ilogb(m) - 14),
+// m = max |T_c[b][a]| over both planes (1 for a zero operator), so that
+// T_c / cls_scale[c] has its largest entry in [2^14, 2^15).  One block of 256
+// threads per class, a thread per row.
 template <bool HELM>
-__global__ void k_row_scale(const double *D64, const int32_t *pk, const int32_t *cls_delta, const double *inv_fact,
-                            int P, int P2, float *row_scale) {
+__global__ void __launch_bounds__(256) k_cls_scale(const double *D64, const int32_t *pk, const int32_t *cls_delta,
+                                                   const double *inv_fact, int P, int P2, float *cls_scale) {
+    __shared__ double red[256];
     const int c = blockIdx.x, b = threadIdx.x;
-    if (b >= OUT_LD) return;
     double m = 0.0;
     if (b < P) {
         const int qb = pk[b];
@@ -412,16 +412,22 @@ __global__ void k_row_scale(const double *D64, const int32_t *pk, const int32_t 
         }
         m *= inv_fact[b] * ldexp(1.0, -cls_delta[c] * nb);
     }
-    row_scale[(int64_t)c * OUT_LD + b] = m > 0.0 ? ldexpf(1.0f, ilogb(m) - SPLIT_TOP) : 1.0f;
+    red[b] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (b < h) red[b] = fmax(red[b], red[b + h]);
+        __syncthreads();
+    }
+    if (b == 0) cls_scale[c] = red[0] > 0.0 ? ldexpf(1.0f, ilogb(red[0]) - SPLIT_TOP) : 1.0f;
 }
 
-// T_c of k_expand_T as two-term splits of its scaled rows:
+// T_c of k_expand_T as two-term splits of its scaled values:
 // T2[((c KB + kb) NA + q) CH2 + (mt 2 + s) TILE2 + 8 lane + i] is term s of
-// plane q of T_c[b][a] / row_scale[c][b] with b = 16 mt + lane % 16,
+// plane q of T_c[b][a] / cls_scale[c] with b = 16 mt + lane % 16,
 // a = 32 kb + 8 (lane / 16) + i.
 template <bool HELM>
 __global__ void k_expand_T2(const double *D64, const int32_t *pk, const int32_t *cls_delta, const double *inv_fact,
-                            int P, int P2, const float *row_scale, uint16_t *T2) {
+                            int P, int P2, const float *cls_scale, uint16_t *T2) {
     constexpr int NA = HELM ? 2 : 1;
     const int c = blockIdx.x, kb = blockIdx.y / MT, mt = blockIdx.y % MT, lane = threadIdx.x;
     const int b = 16 * mt + (lane & 15);
@@ -433,7 +439,7 @@ __global__ void k_expand_T2(const double *D64, const int32_t *pk, const int32_t 
             const int na = (qa & 31) + ((qa >> 5) & 31) + (qa >> 10);
             const int nb = (qb & 31) + ((qb >> 5) & 31) + (qb >> 10);
             const double f = inv_fact[b] * ldexp(1.0, -cls_delta[c] * nb) * ((na & 1) ? -1.0 : 1.0) /
-                             (double)row_scale[(int64_t)c * OUT_LD + b];
+                             (double)cls_scale[c];
             const int ix = sum_index(qa + qb);
             if (HELM) {
                 v[0] = f * D64[2 * ((int64_t)c * P2 + ix)];
@@ -560,28 +566,26 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x2(M2lArgs a, const uint4 *T2, c
             if (ch + 2 < NCH) fetch(ch + 2, r);
         }
     }
-    // Each pair's canonical result, unscaled, is taken back to its own frame
+    // Each pair's canonical result, unscaled (1 / rho_s, the moment vector's
+    // and the operator's power-of-two scales), is taken back to its own frame
     // (row i is the canonical row sym_red[sym][i], signed) and summed with the
     // pairs that follow it in the wave and share its target box (runs of
     // consecutive pairs, which share a partial slot), in passes of G pairs
-    // staged in the LDS ring beside copies of the symmetry table and the
-    // class's row scales; each run's sum is written once, to its slot.  The
-    // column's scale (1 / rho_s and the moment vector's exponent) is applied
-    // when staging, the row's when gathering; both are powers of two.
-    const float scale = (float)ldexp(1.0 / a.side, a.level[p < cnt ? a.pair_src[first + p] : 0] - a.u_exp[u]);
+    // staged in the LDS ring beside a copy of the symmetry table; each run's
+    // sum is written once, to its slot.
+    const float scale =
+        (float)(ldexp(1.0 / a.side, a.level[p < cnt ? a.pair_src[first + p] : 0] - a.u_exp[u]) * a.cls_scale[c]);
     using VO = typename std::conditional<NA == 1, float, cx<float>>::type;
     constexpr int G = 4;                          // pairs per pass: 2.8 (real) or 5.5 KB of staging per wave
     constexpr int PW = NA == 1 ? 16 : 8;          // pairs per wave
     constexpr int SB = W * G * OUT_LD * (int)sizeof(VO);  // staging bytes of the block
     constexpr int TB = NSYM * OUT_LD * 2;                  // symmetry table bytes
-    static_assert(SB % 16 == 0 && SB + TB + OUT_LD * 4 <= 2 * U4 * 16, "staging exceeds the LDS ring");
+    static_assert(SB % 16 == 0 && SB + TB <= 2 * U4 * 16, "staging exceeds the LDS ring");
     VO *S = (VO *)&As[0][0] + w * G * OUT_LD;
     const int16_t *tab = (const int16_t *)((const char *)&As[0][0] + SB);
-    float *rs = (float *)((char *)&As[0][0] + SB + TB);
     VO *o = (VO *)out;
     __syncthreads();  // every wave is past its last operator reads
     for (int x = tid; x < TB / 16; x += 64 * W) ((uint4 *)((char *)&As[0][0] + SB))[x] = ((const uint4 *)a.sym_red)[x];
-    for (int x = tid; x < OUT_LD; x += 64 * W) rs[x] = a.row_scale[(int64_t)c * OUT_LD + x];
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < PW / G; h++) {
@@ -595,20 +599,28 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x2(M2lArgs a, const uint4 *T2, c
             sym[cc] = ok ? a.pair_sym[first + pb + cc] : 0;
         }
 #pragma unroll
-        for (int j = 0; j < MT; j++)
+        for (int j = 0; j < MT; j++) {
+            VO *d = S + (col - c0) * OUT_LD + 16 * j + 4 * kq;  // 16-byte aligned
+            if constexpr (NA == 1) {
+                if (col >= c0 && col < c0 + G)
+                    *(float4 *)d = make_float4(acc[0][j][0] * scale, acc[0][j][1] * scale, acc[0][j][2] * scale,
+                                               acc[0][j][3] * scale);
+            } else {
+                // lane with column < 8 holds Tr.Mr and Ti.Mr of its pair; lane ^ 8 holds Tr.Mi and Ti.Mi
+                float re[4], im[4];
 #pragma unroll
-            for (int r4 = 0; r4 < 4; r4++) {
-                if constexpr (NA == 1) {
-                    if (col >= c0 && col < c0 + G) S[(col - c0) * OUT_LD + 16 * j + 4 * kq + r4] = acc[0][j][r4] * scale;
-                } else {
-                    // lane with column < 8 holds Tr.Mr and Ti.Mr of its pair; lane ^ 8 holds Tr.Mi and Ti.Mi
+                for (int r4 = 0; r4 < 4; r4++) {
                     const float trmi = __shfl_xor(acc[0][j][r4], 8, 64);
                     const float timi = __shfl_xor(acc[1][j][r4], 8, 64);
-                    if (col >= c0 && col < c0 + G)
-                        S[(col - c0) * OUT_LD + 16 * j + 4 * kq + r4] =
-                            cx<float>((acc[0][j][r4] - timi) * scale, (trmi + acc[1][j][r4]) * scale);
+                    re[r4] = (acc[0][j][r4] - timi) * scale;
+                    im[r4] = (trmi + acc[1][j][r4]) * scale;
+                }
+                if (col >= c0 && col < c0 + G) {
+                    ((float4 *)d)[0] = make_float4(re[0], im[0], re[1], im[1]);
+                    ((float4 *)d)[1] = make_float4(re[2], im[2], re[3], im[3]);
                 }
             }
+        }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int r = 0; r < 3; r++) {
@@ -618,8 +630,7 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x2(M2lArgs a, const uint4 *T2, c
 #pragma unroll
             for (int cc = 0; cc < G; cc++) {
                 const int e = row ? tab[sym[cc] * OUT_LD + i] : 0;
-                VO v = S[cc * OUT_LD + (e & 0xff)];
-                v *= rs[e & 0xff];
+                const VO v = S[cc * OUT_LD + (e & 0xff)];
                 x[cc] = (e & 0x100) ? VO(0.0f) - v : v;
             }
             VO v = x[0];
@@ -1125,29 +1136,29 @@ const R *expanded(bem_tree &t, M2lPlan &pl) {
     return buf.p;
 }
 
-// split operators of the plan and their row scales (built on first use)
+// split operators of the plan and their scales (built on first use)
 const uint16_t *expanded2(bem_tree &t, M2lPlan &pl) {
     Ctx &c = *t.ctx;
     FmmTables &T = *t.tables;
     if (!pl.T2.p && pl.n_class) {
         SetupTimer st_(c, "M2L split operators");
         const bool helm = pl.green == BEM_HELMHOLTZ;
-        pl.row_scale.alloc(&c, (size_t)OUT_LD * pl.n_class);
+        pl.cls_scale.alloc(&c, (size_t)pl.n_class);
         pl.T2.alloc(&c, (size_t)(helm ? 2 : 1) * KB * CH2 * pl.n_class);
-        static_assert(OUT_LD <= 256, "one thread per row");
+        static_assert(OUT_LD <= 256, "one thread per operator row");
         dim3 g((unsigned)pl.n_class, KB * MT);
         if (helm) {
-            k_row_scale<true><<<(unsigned)pl.n_class, 256, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p,
-                                                                          T.inv_fact64.p, T.P, T.P2, pl.row_scale.p);
+            k_cls_scale<true><<<(unsigned)pl.n_class, 256, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p,
+                                                                          T.inv_fact64.p, T.P, T.P2, pl.cls_scale.p);
             BEM_LAUNCH_CHECK();
             k_expand_T2<true><<<g, 64, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p, T.inv_fact64.p, T.P, T.P2,
-                                                      pl.row_scale.p, pl.T2.p);
+                                                      pl.cls_scale.p, pl.T2.p);
         } else {
-            k_row_scale<false><<<(unsigned)pl.n_class, 256, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p,
-                                                                           T.inv_fact64.p, T.P, T.P2, pl.row_scale.p);
+            k_cls_scale<false><<<(unsigned)pl.n_class, 256, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p,
+                                                                           T.inv_fact64.p, T.P, T.P2, pl.cls_scale.p);
             BEM_LAUNCH_CHECK();
             k_expand_T2<false><<<g, 64, 0, c.stream>>>(pl.D64.p, pl.pk.p, pl.cls_delta.p, T.inv_fact64.p, T.P, T.P2,
-                                                       pl.row_scale.p, pl.T2.p);
+                                                       pl.cls_scale.p, pl.T2.p);
         }
         BEM_LAUNCH_CHECK();
         c.sync();
@@ -1317,7 +1328,7 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
                       pl.pair_src.p, pl.pair_mom.p, t.level.p, pl.var ? tk.task_kt.p + t0 : nullptr,
                       pl.var ? tk.task_mt.p + t0 : nullptr, t.side, P, split ? part0 : pl.slab_slot0[sl],
                       split ? pl.pair_part.p : nullptr, split ? pl.pair_sym.p : nullptr, pl.sym_red.p,
-                      u_exp, split ? pl.row_scale.p : nullptr};
+                      u_exp, split ? pl.cls_scale.p : nullptr};
             c.kbegin(c.stream, 3);
             auto launch = [&](auto wv) {
                 constexpr int W = decltype(wv)::value;
