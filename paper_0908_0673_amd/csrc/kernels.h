@@ -139,6 +139,7 @@ struct M2lPlan {
     DBuf<double> T64;
     DBuf<uint16_t> T2;                // two-term fp16 splits of the scaled operators (mixed path with one order)
     DBuf<float> cls_scale;            // [class] power-of-two scale of each split operator
+    DBuf<uint8_t> sym_perm;           // [7][OUT_LD] compact symmetry table of the split kernel
     std::vector<int32_t> h_pair_slot, h_pair_sym;
     // Mixed path with one order: partial slots of the per-target sums the
     // product kernel forms itself (built on first use for `parts_g` pairs

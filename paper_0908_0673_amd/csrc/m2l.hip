@@ -161,6 +161,11 @@ struct M2lArgs {
     // 2^-exponent of each class's operator, undone on the results
     const int32_t *u_exp;
     const float *cls_scale;
+    // split path: the symmetry table in compact form, sym_perm[o][i] = the
+    // canonical row of row i under axis ordering o (o = sym / 8), then
+    // sym_perm[6][i] = the axes along which row i's multi-index is odd (the
+    // result is negated when an odd number of them are flipped, sym % 8)
+    const uint8_t *sym_perm;
 };
 
 __device__ inline float abs_max(float x) { return fabsf(x); }
@@ -505,7 +510,10 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x2(M2lArgs a, const uint4 *T2, c
     constexpr int U4 = CH2 * 2 / 16;  // 16-byte pieces per chunk
     constexpr int PER = (U4 + 64 * W - 1) / (64 * W);
     constexpr int NCH = KB * NA;
+    constexpr int TB = 7 * OUT_LD;  // bytes of the compact symmetry table
+    static_assert(TB % 16 == 0, "whole 16-byte pieces");
     __shared__ uint4 As[2][U4];
+    __shared__ uint4 Ts[TB / 16];  // copy of the compact symmetry table back to the pairs' frames
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, task = blockIdx.x;
     const int cnt = a.task_count[task];
     if (cnt == 0) return;  // the same for the whole block
@@ -530,6 +538,9 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x2(M2lArgs a, const uint4 *T2, c
     };
     uint4 r[PER];
     fetch(0, r);
+    // the table is read only after the products, so its copy is taken while
+    // the first chunk is on its way (visible after the first barrier)
+    for (int x = tid; x < TB / 16; x += 64 * W) Ts[x] = ((const uint4 *)a.sym_perm)[x];
     uint4 B[2];
     float bn[8];  // the next block's values, in flight
     load_b<NA>(mr, 0, kq, imag, bn);
@@ -568,25 +579,22 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x2(M2lArgs a, const uint4 *T2, c
     }
     // Each pair's canonical result, unscaled (1 / rho_s, the moment vector's
     // and the operator's power-of-two scales), is taken back to its own frame
-    // (row i is the canonical row sym_red[sym][i], signed) and summed with the
+    // (row i is the canonical row sym_perm[sym / 8][i], negated when an odd
+    // number of the flipped axes sym % 8 are odd in row i) and summed with the
     // pairs that follow it in the wave and share its target box (runs of
     // consecutive pairs, which share a partial slot), in passes of G pairs
-    // staged in the LDS ring beside a copy of the symmetry table; each run's
-    // sum is written once, to its slot.
+    // staged in the LDS ring; each run's sum is written once, to its slot.
     const float scale =
         (float)(ldexp(1.0 / a.side, a.level[p < cnt ? a.pair_src[first + p] : 0] - a.u_exp[u]) * a.cls_scale[c]);
     using VO = typename std::conditional<NA == 1, float, cx<float>>::type;
-    constexpr int G = 4;                          // pairs per pass: 2.8 (real) or 5.5 KB of staging per wave
+    constexpr int G = 8;                          // pairs per pass: 5.5 (real) or 11 KB of staging per wave
     constexpr int PW = NA == 1 ? 16 : 8;          // pairs per wave
     constexpr int SB = W * G * OUT_LD * (int)sizeof(VO);  // staging bytes of the block
-    constexpr int TB = NSYM * OUT_LD * 2;                  // symmetry table bytes
-    static_assert(SB % 16 == 0 && SB + TB <= 2 * U4 * 16, "staging exceeds the LDS ring");
+    static_assert(SB % 16 == 0 && SB <= 2 * U4 * 16, "staging exceeds the LDS ring");
     VO *S = (VO *)&As[0][0] + w * G * OUT_LD;
-    const int16_t *tab = (const int16_t *)((const char *)&As[0][0] + SB);
+    const uint8_t *perm = (const uint8_t *)Ts, *odd = perm + 6 * OUT_LD;
     VO *o = (VO *)out;
     __syncthreads();  // every wave is past its last operator reads
-    for (int x = tid; x < TB / 16; x += 64 * W) ((uint4 *)((char *)&As[0][0] + SB))[x] = ((const uint4 *)a.sym_red)[x];
-    __syncthreads();
 #pragma unroll
     for (int h = 0; h < PW / G; h++) {
         const int c0 = h * G;        // first column (pair) of the pass
@@ -626,12 +634,13 @@ __global__ void __launch_bounds__(64 * W) k_m2l_x2(M2lArgs a, const uint4 *T2, c
         for (int r = 0; r < 3; r++) {
             const int i = lane + 64 * r;
             const bool row = i < a.P;
+            const int od = row ? odd[i] : 0;
             VO x[G];
 #pragma unroll
             for (int cc = 0; cc < G; cc++) {
-                const int e = row ? tab[sym[cc] * OUT_LD + i] : 0;
-                const VO v = S[cc * OUT_LD + (e & 0xff)];
-                x[cc] = (e & 0x100) ? VO(0.0f) - v : v;
+                const int e = row ? perm[(sym[cc] >> 3) * OUT_LD + i] : 0;
+                const VO v = S[cc * OUT_LD + e];
+                x[cc] = (__popc(sym[cc] & od) & 1) ? VO(0.0f) - v : v;
             }
             VO v = x[0];
 #pragma unroll
@@ -1006,6 +1015,22 @@ M2lPlan &get_m2l_plan(bem_tree &t, int green, double k) {
     up(pl->sym_in, sin);
     pl->sym_red.alloc(&c, sred.size());
     pl->sym_red.upload(sred.data(), sred.size());
+    {  // the compact form of sym_red that the split kernel reads
+        std::vector<uint8_t> po((size_t)7 * OUT_LD, 0);
+        for (int i = 0; i < P; i++) {
+            for (int o = 0; o < 6; o++) po[(size_t)o * OUT_LD + i] = (uint8_t)(sred[(size_t)8 * o * OUT_LD + i] & 0xff);
+            po[(size_t)6 * OUT_LD + i] =
+                (uint8_t)((T.h_exps[3 * i] & 1) | (T.h_exps[3 * i + 1] & 1) << 1 | (T.h_exps[3 * i + 2] & 1) << 2);
+        }
+        for (int g = 0; g < NSYM; g++)
+            for (int i = 0; i < P; i++) {
+                const int neg = __builtin_popcount((g & 7) & po[(size_t)6 * OUT_LD + i]) & 1;
+                BEM_REQUIRE(sred[(size_t)g * OUT_LD + i] == (po[(size_t)(g / 8) * OUT_LD + i] | (neg ? 0x100 : 0)),
+                            BEM_EUNSUPPORTED, "compact symmetry table disagrees with the full one");
+            }
+        pl->sym_perm.alloc(&c, po.size());
+        pl->sym_perm.upload(po.data(), po.size());
+    }
     // symmetry of every interaction-list slot (slots outside the plan stay 0)
     std::vector<int32_t> ssym(std::max<int64_t>(1, t.n_inter), 0);
     for (size_t i = 0; i < slot.size(); i++) ssym[slot[i]] = sym[i];
@@ -1167,13 +1192,13 @@ const uint16_t *expanded2(bem_tree &t, M2lPlan &pl) {
 }
 
 // Partial slots of the split path's per-target sums: within each (slab,
-// class) group of pairs, passes of G = 4 pairs from its first pair (the
+// class) group of pairs, passes of G = 8 pairs from its first pair (the
 // product kernel's waves take 16 real or 8 complex pairs from there); a run of consecutive pairs of one pass with the same target box
 // shares a slot.  Slots are numbered box by box in m2l_boxes order (a slab's
 // slots are then contiguous), within a box in pair order, so that a box's sum
 // runs over one contiguous range in a fixed order.
 void build_parts(bem_tree &t, M2lPlan &pl) {
-    constexpr int G = 4;  // as the product kernel
+    constexpr int G = 8;  // as the product kernel
     if (pl.parts_g == G) return;
     Ctx &c = *t.ctx;
     SetupTimer st_(c, "M2L partial slots");
@@ -1216,9 +1241,8 @@ void build_parts(bem_tree &t, M2lPlan &pl) {
     pl.parts_g = G;
 }
 
-// waves per block of the split kernel: the complex one stages 5.5 KB per wave
-// beside the symmetry and row-scale tables in its 44 KB LDS ring, which holds
-// four
+// waves per block of the split kernel: the complex one stages 11 KB per wave
+// in its 44 KB LDS ring, which holds four
 int split_waves(int na, int w) { return na == 2 && w > 4 ? 4 : w; }
 
 // whether a product of precision R on this plan runs on the split operands
@@ -1243,7 +1267,7 @@ bool m2l_ready(const M2lPlan &pl, int prec, int waves) {
     const void *ops = f32 ? (split_path<float>(pl) ? (const void *)pl.T2.p : (const void *)pl.T32.p)
                           : (const void *)pl.T64.p;
     if (pl.n_class && !ops) return false;
-    if (f32 && split_path<float>(pl) && pl.parts_g != 4) return false;
+    if (f32 && split_path<float>(pl) && pl.parts_g != 8) return false;
     const int cols = helm ? (f32 ? m2l_cols<cx<float>, float>(pl, waves) : m2l_cols<cx<double>, double>(pl, waves))
                           : (f32 ? m2l_cols<float, float>(pl, waves) : m2l_cols<double, double>(pl, waves));
     for (auto &tk : pl.tasks)
@@ -1328,7 +1352,7 @@ void m2l_apply(bem_tree &t, M2lPlan &pl, int nrhs, const V *mom, V *loc, int wav
                       pl.pair_src.p, pl.pair_mom.p, t.level.p, pl.var ? tk.task_kt.p + t0 : nullptr,
                       pl.var ? tk.task_mt.p + t0 : nullptr, t.side, P, split ? part0 : pl.slab_slot0[sl],
                       split ? pl.pair_part.p : nullptr, split ? pl.pair_sym.p : nullptr, pl.sym_red.p,
-                      u_exp, split ? pl.cls_scale.p : nullptr};
+                      u_exp, split ? pl.cls_scale.p : nullptr, pl.sym_perm.p};
             c.kbegin(c.stream, 3);
             auto launch = [&](auto wv) {
                 constexpr int W = decltype(wv)::value;
