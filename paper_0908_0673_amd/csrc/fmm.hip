@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(P2P_BS) k_p2p(const int32_t *unit_order, const
             for (int q = 0; q < TPL; q++)
 #pragma unroll
                 for (int r = 0; r < NR; r++) acc[q][r] = V(0.0);
-#pragma unroll(8 / TPL)
+#pragma unroll 1
             for (int kk = sub < nsub ? sub : nin; kk < nin; kk += nsub) {
                 const double2 cxy = sxy[wave][buf][kk];
                 const double cz = szz[wave][buf][kk];
