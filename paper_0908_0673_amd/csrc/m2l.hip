@@ -25,7 +25,9 @@
 //     OUT[b', j] = sum_a' T_c[b', a'] M'[a', j],
 //     T_c[b', a'] = rs_c[b'] (-1)^|a'| D'_c[a' + b'],  rs_c[b'] = 2^(-dl |b'|) / b'!
 //
-// run on the matrix cores (v_mfma 16x16x4, FP32 or FP64).  T_c is expanded
+// run on the matrix cores (v_mfma 16x16x4 in FP64, or FP32 for mixed products
+// with level-dependent orders; 16x16x32 fp16 on split operands for the other
+// mixed products, below).  T_c is expanded
 // once per tree into the A-operand order of the instruction, so a wave
 // streams it with one coalesced 256-byte load per product; the canonical
 // operators of a tree take a few MB and stay resident in the L2 caches.  One
