@@ -425,7 +425,9 @@ __global__ void __launch_bounds__(256) k_cls_scale(const double *D64, const int3
         if (b < h) red[b] = fmax(red[b], red[b + h]);
         __syncthreads();
     }
-    if (b == 0) cls_scale[c] = red[0] > 0.0 ? ldexpf(1.0f, ilogb(red[0]) - SPLIT_TOP) : 1.0f;
+    // (the exponent is kept within FP32's normal range: operators of any
+    // physical class are many orders of magnitude inside it)
+    if (b == 0) cls_scale[c] = red[0] > 0.0 ? ldexpf(1.0f, max(-120, min(120, ilogb(red[0]) - SPLIT_TOP))) : 1.0f;
 }
 
 // T_c of k_expand_T as two-term splits of its scaled values:
