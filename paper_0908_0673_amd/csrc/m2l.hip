@@ -355,8 +355,9 @@ __global__ void __launch_bounds__(64 * W) k_m2l(M2lArgs a, const R *T, const R *
 
 // ---------------------------------------------------------------- split-fp16 products
 // The mixed path runs the products on the fp16 matrix instruction
-// v_mfma_f32_16x16x32_f16 (FP32 accumulation), whose rate on this chip is
-// about fifteen times that of the FP32 one.  Every operand x is carried as two
+// v_mfma_f32_16x16x32_f16 (FP32 accumulation), whose dense rate on this chip
+// (that of the bf16 one, measured at about fifteen times the FP32
+// instruction's) far exceeds the FP32 one.  Every operand x is carried as two
 // fp16 terms, x1 = fp16(x) and x2 = fp16(x - x1) (eleven significant bits
 // each, together x to about 2^-22 relative), and each product keeps the three
 // cross terms of combined order up to three,
@@ -368,8 +369,9 @@ __global__ void __launch_bounds__(64 * W) k_m2l(M2lArgs a, const R *T, const R *
 // Entries far below that largest lose relative precision to fp16's subnormal
 // range, but never more than 2^-38 of it in absolute terms (in the scaled
 // units every entry contributes in proportion to its size).  The scales are
-// undone on the results.  The contraction runs over K3 = 192 >= P in blocks of 32; a chunk
-// of the operator is one block of one plane (the real or imaginary part):
+// undone on the results (SPLIT_TOP below; the canonical-moments kernel above
+// uses the same 14).  The contraction runs over K3 = 192 >= P in blocks of 32;
+// a chunk of the operator is one block of one plane (the real or imaginary part):
 // 11 row tiles x 2 terms x 1 KB, the A operands of the instruction in lane
 // order (lane l holds row l % 16, columns 8 (l / 16) .. + 7 of its 16 x 32
 // tile).
